@@ -1,0 +1,149 @@
+"""FP64 oracle for the SS-FNO / NAF pipeline and the perturbative correction.
+
+TEST INFRASTRUCTURE ONLY.
+
+Steps (Sec. "Computational Details", steps 2-4f):
+  2   canonical MP2 amplitudes and the MP2 virtual density D^MP2;
+  3   canonical EA-ADC(2) roots (Davidson);
+  4a  D^EA-ADC(2)(k) from the zeroth-order ISR of ADC(2) eigenvector k (eq 17);
+  4b  D^SS(k) = D^MP2 + D^EA-ADC(2)(k) (eq 17);
+  4c  natural orbitals D V = V eta (eq 9), sorted by occupation;
+  4d  keep eta > threshold (eqs 10-11), recanonicalise the kept block
+      (eqs 12-13) and map the DF factor to the new virtuals (eqs 14-16);
+  4e  natural auxiliary functions from W = J_vv J_vv^T (eqs 27-29);
+      EA-ADC(2) and EA-ADC(3) in the truncated basis;
+  4f  omega_corr = omega_FNO-ADC(3) + omega_can-ADC(2) - omega_FNO-ADC(2) (eq 30).
+
+Readings where the paper is silent (each listed in the design notes):
+* D^MP2_ab (per spin) = sum_klc (2T^ac_kl - T^ca_kl) T^bc_kl.
+* D^EA(k) is the virtual block of the density of the state
+  r1 c+_a Phi0 + (2p1h determinants), spin averaged:
+  D^EA_ab = 1/2 [r1_a r1_b + sum_ci (x_aci x_bci + y_aci y_bci + x_cai x_cbi)].
+* FNO keeps eta > thr; NAF keeps w >= thr; thr <= 0 disables the step.
+* Eigenvector signs: largest-magnitude component positive.
+* Root k of the truncated problems is their k-th lowest root (index matching), so
+  that with nothing truncated the corrected root k is canonical ADC(3) root k.
+"""
+import numpy as np
+
+from .adc_cs import Problem, z_to_x
+from .davidson import davidson
+
+
+def fix_signs(V):
+    """Make the largest-|.| entry of every column positive (first one on ties)."""
+    idx = np.argmax(np.abs(V), axis=0)
+    s = np.sign(V[idx, np.arange(V.shape[1])])
+    s[s == 0] = 1.0
+    return V * s
+
+
+def ea_density(P, vec):
+    """Spin-averaged virtual density of the ADC(2) state vec (1p + z 2p1h), eq 17 reading."""
+    r1, z = P.split(vec)
+    x = z_to_x(z)
+    y = x - x.transpose(0, 2, 1)
+    rho = np.outer(r1, r1)
+    rho += np.einsum("iac,ibc->ab", x, x) + np.einsum("iac,ibc->ab", y, y) + np.einsum("ica,icb->ab", x, x)
+    return 0.5 * rho
+
+
+def natural_orbitals(D, eps_vir, thresh):
+    """Eqs 9-14: returns (U [v, vk], eps_new [vk], eta [v] descending, kept count)."""
+    eta, V = np.linalg.eigh(D)
+    order = np.argsort(-eta, kind="stable")
+    eta, V = eta[order], fix_signs(V[:, order])
+    keep = eta > thresh if thresh > 0 else np.ones(eta.size, bool)
+    Vt = V[:, keep]
+    F = Vt.T @ np.diag(eps_vir) @ Vt
+    F = 0.5 * (F + F.T)
+    e_new, Z = np.linalg.eigh(F)
+    U = fix_signs(Vt @ Z)
+    return U, e_new, eta, int(keep.sum())
+
+
+def transform_B(B, nocc, U):
+    """DF factor in the new virtual basis: Boo kept, Bov -> Bov U, Bvv -> U^T Bvv U (eqs 14-16)."""
+    o = nocc
+    v2 = U.shape[1]
+    X = B.shape[0]
+    out = np.zeros((X, o + v2, o + v2))
+    out[:, :o, :o] = B[:, :o, :o]
+    ov = B[:, :o, o:] @ U
+    out[:, :o, o:] = ov
+    out[:, o:, :o] = ov.transpose(0, 2, 1)
+    out[:, o:, o:] = np.einsum("pa,Qpq,qb->Qab", U, B[:, o:, o:], U, optimize=True)
+    return out
+
+
+def naf(B, nocc, thresh):
+    """Eqs 27-29: W = J_vv J_vv^T over all (a,b); keep eigenvalues w >= thresh.
+
+    Returns (B_naf [Xk, n, n], w descending, kept count)."""
+    o = nocc
+    X = B.shape[0]
+    Jvv = B[:, o:, o:].reshape(X, -1)
+    W = Jvv @ Jvv.T
+    w, N = np.linalg.eigh(0.5 * (W + W.T))
+    order = np.argsort(-w, kind="stable")
+    w, N = w[order], fix_signs(N[:, order])
+    keep = w >= thresh if thresh > 0 else np.ones(w.size, bool)
+    Nk = N[:, keep]
+    Bn = np.einsum("PQ,Pmn->Qmn", Nk, B, optimize=True)
+    return Bn, w, int(keep.sum())
+
+
+def solve_roots(P, level, nroots, conv, dense_limit=4000):
+    """Lowest nroots eigenpairs of ADC(level): dense eigh for small spaces, Davidson otherwise."""
+    n = P.dim()
+    if n <= dense_limit:
+        M = P.dense(level)
+        M = 0.5 * (M + M.T)
+        w, Y = np.linalg.eigh(M)
+        return w[:nroots], Y[:, :nroots].T, True
+    w, X, rn, it, ok = davidson(lambda V: P.sigma(V, level), P.diagonal(level), nroots, conv=conv)
+    return w, X, ok
+
+
+def carry_vector(vec, o, v, U):
+    """Express a canonical-basis state in the truncated virtual basis (projection by U)."""
+    r1 = vec[:v] @ U
+    z = vec[v:].reshape(o, v, v)
+    z2 = np.einsum("pa,ipq,qb->iab", U, z, U, optimize=True)
+    return np.concatenate([r1, z2.reshape(-1)])
+
+
+def run(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, dense_limit=4000):
+    """The whole method.  Returns a dict with the corrected roots and per-root details."""
+    o, v = eps_occ.size, eps_vir.size
+    P0 = Problem(eps_occ, eps_vir, B)
+    out = {"nocc": o, "nvir": v, "naux": B.shape[0]}
+    if fno_thresh <= 0 and naf_thresh <= 0:
+        w3, Y3, ok = solve_roots(P0, 3, nroots, conv, dense_limit)
+        out.update(roots=w3, omega_uncorr=w3, converged=ok, nvir_kept=[v] * nroots, naux_kept=[B.shape[0]] * nroots)
+        return out
+    w2, Y2, ok2 = solve_roots(P0, 2, nroots, conv, dense_limit)
+    Dmp2 = P0.mp2_density_vv()
+    out.update(omega_adc2_can=w2, e_mp2=P0.mp2_energy(), d_mp2=Dmp2)
+    roots, unc, a2f, nk, xk, eta_all = [], [], [], [], [], []
+    for k in range(nroots):
+        Dss = Dmp2 + ea_density(P0, Y2[k])
+        U, e_new, eta, nkeep = natural_orbitals(Dss, eps_vir, fno_thresh)
+        Bt = transform_B(B, o, U)
+        if naf_thresh > 0:
+            Bt, wnaf, xkeep = naf(Bt, o, naf_thresh)
+        else:
+            xkeep = B.shape[0]
+        Pk = Problem(eps_occ, e_new, Bt)
+        w2k, Y2k, _ = solve_roots(Pk, 2, nroots, conv, dense_limit)
+        w3k, Y3k, _ = solve_roots(Pk, 3, nroots, conv, dense_limit)
+        m2 = m3 = k
+        unc.append(w3k[m3])
+        a2f.append(w2k[m2])
+        roots.append(w3k[m3] + w2[k] - w2k[m2])
+        nk.append(nkeep)
+        xk.append(xkeep)
+        eta_all.append(eta)
+    out.update(roots=np.array(roots), omega_uncorr=np.array(unc), omega_adc2_fno=np.array(a2f),
+               nvir_kept=nk, naux_kept=xk, eta=eta_all, converged=ok2)
+    return out
