@@ -1,0 +1,153 @@
+/*
+ * adc3ea.h -- C ABI of the MI355X (gfx950) DF-SS-FNO-EA-ADC(3) library.
+ *
+ * The method: density-fitted third-order algebraic diagrammatic construction for
+ * electron attachment (non-Dyson EA-ADC, Sec. "Algebraic Diagrammatic
+ * Construction (ADC) Theory", eqs 1-6) with state-specific frozen natural
+ * orbitals (Sec. "State-Specific Frozen Natural Orbitals (SS-FNO)", eqs 9-17),
+ * natural auxiliary functions (Sec. "Natural Auxiliary Functions (NAF)",
+ * eqs 27-29) and the perturbative truncation correction (eq 30), following the
+ * steps of Sec. "Computational Details".
+ *
+ * Conventions shared by every entry point
+ *   - Energies in Hartree.  A root omega is an eigenvalue of the secular matrix
+ *     M (eq 6): omega = E(N+1) - E(N); the electron affinity is -omega.
+ *   - Inputs describe a closed-shell reference in its canonical orbitals:
+ *     eps_occ[nocc], eps_vir[nvir] (ascending; every occupied energy below every
+ *     virtual one) and the DF factor B[naux][n][n], n = nocc + nvir, row-major,
+ *     occupied orbitals first, symmetric in its two orbital indices, such that
+ *     (pq|rs) = sum_Q B[Q][p][q] B[Q][r][s] (eqs 25-26).
+ *   - Vector space: N = nvir + nocc*nvir*nvir.  A vector is [r1[nvir], z[nocc][nvir][nvir]]:
+ *     r1 the 1p amplitudes, z orthonormal doublet coordinates of the 2p1h space
+ *     (x = z_S + z_A/sqrt(3) on c+_{a alpha} c+_{b beta} c_{i beta}|0>).
+ *   - Pointers named *_dev are device pointers (HBM); others are host pointers.
+ *     The caller owns every buffer.  Device work is ordered on `stream`; calls that
+ *     return host results synchronise that stream before returning.
+ *   - Errors: every call returns an adc3_status; nothing is thrown across the
+ *     ABI.  adc3_last_error() returns a message for the last failing call on the
+ *     calling thread.  Arguments are validated before any launch.
+ *   - Workspace: device memory is taken only from the caller's workspace
+ *     (size from the matching *_workspace_bytes query); too small a workspace
+ *     returns ADC3_ENOMEM before any launch.
+ */
+#ifndef ADC3EA_H
+#define ADC3EA_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ADC3_OK = 0,
+    ADC3_WNOCONV = 1,     /* outputs valid, Davidson not converged within max_iter */
+    ADC3_EINVAL = -1,     /* invalid argument (message says which) */
+    ADC3_ENOMEM = -2,     /* workspace too small */
+    ADC3_EHIP = -3,       /* HIP runtime error */
+    ADC3_ENUMERIC = -4,   /* non-finite value met */
+    ADC3_EUNSUP = -5      /* unsupported option */
+} adc3_status;
+
+/* Options.  adc3_default_opts() fills the defaults listed here. */
+typedef struct {
+    int level;            /* 2 or 3: ADC order of the final roots (default 3) */
+    int max_iter;         /* Davidson iterations per solve (default 200) */
+    int max_subspace;     /* Davidson subspace limit; 0 = max(8*nroots, 40) */
+    int fno_correction;   /* 1: add omega_can-ADC(2) - omega_FNO-ADC(2) (eq 30); default 1 */
+    int precision;        /* 0: FP64 everywhere (only value supported) */
+    int precond;          /* 0: Jacobi (diagonal) preconditioner */
+} adc3_opts;
+
+/* Per-root report of adc3_ea_solve. */
+typedef struct {
+    double omega;          /* reported root (corrected when SS-FNO/NAF is active) */
+    double omega_uncorr;   /* ADC(3) root k in the truncated basis */
+    double omega_adc2_can; /* canonical ADC(2) root k (0 when no truncation ran) */
+    double omega_adc2_fno; /* ADC(2) root k in the truncated basis */
+    double resnorm;        /* final residual 2-norm of the ADC(3) root */
+    int nvir_kept;         /* virtuals kept by SS-FNO (eq 11) */
+    int naux_kept;         /* auxiliary functions kept by NAF (eq 29) */
+    int iters;             /* Davidson iterations of the ADC(3) solve */
+    int sigma_builds;      /* sigma vectors built for this root (all solves) */
+} adc3_root_report;
+
+void adc3_default_opts(adc3_opts* opts);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* adc3_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Full method (Sec. "Computational Details", steps 2-4f).
+ *   fno_thresh > 0: per root k, build D^SS(k) = D^MP2 + D^EA-ADC(2)(k) (eq 17),
+ *     keep natural orbitals with occupation > fno_thresh (eqs 9-11),
+ *     recanonicalise (eqs 12-16);
+ *   naf_thresh > 0: keep natural auxiliary functions with W-eigenvalue >= naf_thresh
+ *     (eqs 27-29, W from the vv block of the root's truncated factor);
+ *   both <= 0: plain canonical EA-ADC(level) roots.
+ *   Root k of a truncated problem is its k-th lowest root.  roots_out[k] =
+ *   omega_FNO-ADC(3)(k) + omega_can-ADC(2)(k) - omega_FNO-ADC(2)(k) (eq 30).
+ * Inputs eps_occ_dev, eps_vir_dev, B_dev are device pointers and are not modified.
+ * roots_out[nroots] and reports[nroots] (nullable) are host arrays.
+ * conv: a root is converged when its residual 2-norm and eigenvalue change are <= conv.
+ * Returns ADC3_WNOCONV (outputs valid) if any solve hit max_iter.
+ * ------------------------------------------------------------------------- */
+size_t adc3_ea_solve_workspace_bytes(int nocc, int nvir, int naux, int nroots, const adc3_opts* opts);
+
+int adc3_ea_solve(const double* eps_occ_dev, const double* eps_vir_dev, const double* B_dev,
+                  int nocc, int nvir, int naux, int nroots,
+                  double fno_thresh, double naf_thresh, double conv,
+                  const adc3_opts* opts, double* roots_out, adc3_root_report* reports,
+                  void* workspace_dev, size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Secular-matrix context: integrals and intermediates of EA-ADC(level) for one
+ * instance (eqs 3-5 truncated at `level`), kept in the caller's workspace.
+ * The handle (host memory) is freed by adc3_ctx_destroy, which frees no device
+ * memory; the workspace must stay alive while the context is used.
+ * ------------------------------------------------------------------------- */
+typedef struct adc3_ctx adc3_ctx;
+
+/* Workspace for adc3_ea_setup plus everything later calls on the context take from
+ * it: sigma builds, the dense-matrix hook and (nroots > 0) adc3_ea_davidson with up to
+ * nroots roots and the default subspace.  Returns 0 for invalid arguments. */
+size_t adc3_ea_setup_workspace_bytes(int nocc, int nvir, int naux, int level, int nroots);
+
+int adc3_ea_setup(const double* eps_occ_dev, const double* eps_vir_dev, const double* B_dev,
+                  int nocc, int nvir, int naux, int level,
+                  void* workspace_dev, size_t workspace_bytes, hipStream_t stream,
+                  adc3_ctx** ctx_out);
+
+void adc3_ctx_destroy(adc3_ctx* ctx);
+
+/* Dimension N of the context's vector space. */
+long long adc3_ea_dim(const adc3_ctx* ctx);
+
+/* sigma = M r for nvec vectors (Sec. ADC theory, Davidson sigma vectors):
+ * r_dev[nvec][N], sigma_dev[nvec][N] device, row-major, must not overlap. */
+int adc3_ea_sigma(adc3_ctx* ctx, const double* r_dev, double* sigma_dev, int nvec, hipStream_t stream);
+
+/* Diagonal of M: diag_dev[N] device. */
+int adc3_ea_diagonal(adc3_ctx* ctx, double* diag_dev, hipStream_t stream);
+
+/* Lowest nroots eigenpairs of M by block Davidson (FP64).  omega[nroots] host;
+ * vectors_dev[nroots][N] device (nullable); resnorm[nroots] host (nullable);
+ * iters (host, nullable) receives the iteration count. */
+int adc3_ea_davidson(adc3_ctx* ctx, int nroots, double conv, int max_iter, int max_subspace,
+                     double* omega, double* vectors_dev, double* resnorm, int* iters,
+                     hipStream_t stream);
+
+/* Test hook: dense M (N <= 20000) into M_dev[N][ldm] device. */
+int adc3_ea_dense_matrix(adc3_ctx* ctx, double* M_dev, int ldm, hipStream_t stream);
+
+/* Test hook: copy an intermediate to a device buffer.  which: 0 = M11 [nvir][nvir],
+ * 1 = U_z [nvir][nocc*nvir*nvir] (1p-2p1h block in z coordinates),
+ * 2 = T [nocc][nocc][nvir][nvir] first-order amplitudes, 3 = MP2 virtual density
+ * [nvir][nvir] (per spin).  count receives the element count when out_dev is NULL. */
+int adc3_ea_intermediate(adc3_ctx* ctx, int which, double* out_dev, long long* count, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADC3EA_H */

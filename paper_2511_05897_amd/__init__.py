@@ -1,0 +1,214 @@
+"""MI355X (gfx950) DF-SS-FNO-EA-ADC(3): thin Python binding of the C ABI in include/adc3ea.h.
+
+Every step of the method runs in the HIP library libadc3ea.so; this module only
+marshals arguments.  Device buffers are torch tensors (float64, contiguous, on the
+current HIP device); work runs on torch's current stream.  The library must be
+built (``python -m paper_2511_05897_amd.build``); importing the binding without it
+raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadc3ea.so")
+
+ADC3_OK, ADC3_WNOCONV = 0, 1
+ADC3_EINVAL, ADC3_ENOMEM, ADC3_EHIP, ADC3_ENUMERIC, ADC3_EUNSUP = -1, -2, -3, -4, -5
+
+# every symbol declared in include/adc3ea.h
+EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_bytes", "adc3_ea_solve",
+           "adc3_ea_setup_workspace_bytes", "adc3_ea_setup", "adc3_ctx_destroy", "adc3_ea_dim",
+           "adc3_ea_sigma", "adc3_ea_diagonal", "adc3_ea_davidson", "adc3_ea_dense_matrix",
+           "adc3_ea_intermediate"]
+
+
+class adc3_opts(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int), ("max_iter", ctypes.c_int), ("max_subspace", ctypes.c_int),
+                ("fno_correction", ctypes.c_int), ("precision", ctypes.c_int), ("precond", ctypes.c_int)]
+
+
+class adc3_root_report(ctypes.Structure):
+    _fields_ = [("omega", ctypes.c_double), ("omega_uncorr", ctypes.c_double),
+                ("omega_adc2_can", ctypes.c_double), ("omega_adc2_fno", ctypes.c_double),
+                ("resnorm", ctypes.c_double), ("nvir_kept", ctypes.c_int), ("naux_kept", ctypes.c_int),
+                ("iters", ctypes.c_int), ("sigma_builds", ctypes.c_int)]
+
+
+class ADCError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("adc3 status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load libadc3ea.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError("libadc3ea.so not built: run python -m paper_2511_05897_amd.build")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, S, LL = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t, ctypes.c_longlong
+    lib.adc3_default_opts.argtypes = [ctypes.POINTER(adc3_opts)]
+    lib.adc3_default_opts.restype = None
+    lib.adc3_last_error.restype = ctypes.c_char_p
+    lib.adc3_ea_solve_workspace_bytes.argtypes = [I, I, I, I, ctypes.POINTER(adc3_opts)]
+    lib.adc3_ea_solve_workspace_bytes.restype = S
+    lib.adc3_ea_solve.argtypes = [P, P, P, I, I, I, I, D, D, D, ctypes.POINTER(adc3_opts),
+                                  ctypes.POINTER(D), ctypes.POINTER(adc3_root_report), P, S, P]
+    lib.adc3_ea_solve.restype = I
+    lib.adc3_ea_setup_workspace_bytes.argtypes = [I, I, I, I, I]
+    lib.adc3_ea_setup_workspace_bytes.restype = S
+    lib.adc3_ea_setup.argtypes = [P, P, P, I, I, I, I, P, S, P, ctypes.POINTER(P)]
+    lib.adc3_ea_setup.restype = I
+    lib.adc3_ctx_destroy.argtypes = [P]
+    lib.adc3_ctx_destroy.restype = None
+    lib.adc3_ea_dim.argtypes = [P]
+    lib.adc3_ea_dim.restype = LL
+    lib.adc3_ea_sigma.argtypes = [P, P, P, I, P]
+    lib.adc3_ea_sigma.restype = I
+    lib.adc3_ea_diagonal.argtypes = [P, P, P]
+    lib.adc3_ea_diagonal.restype = I
+    lib.adc3_ea_davidson.argtypes = [P, I, D, I, I, ctypes.POINTER(D), P, ctypes.POINTER(D),
+                                     ctypes.POINTER(I), P]
+    lib.adc3_ea_davidson.restype = I
+    lib.adc3_ea_dense_matrix.argtypes = [P, P, I, P]
+    lib.adc3_ea_dense_matrix.restype = I
+    lib.adc3_ea_intermediate.argtypes = [P, I, P, ctypes.POINTER(LL), P]
+    lib.adc3_ea_intermediate.restype = I
+    _lib = lib
+    return lib
+
+
+def _check(status, allow_noconv=False):
+    if status == ADC3_OK or (allow_noconv and status == ADC3_WNOCONV):
+        return status
+    raise ADCError(status, load().adc3_last_error().decode())
+
+
+def _ptr(t):
+    import torch
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _workspace(nbytes):
+    import torch
+    if nbytes == 0:
+        raise ADCError(ADC3_EINVAL, "workspace size query failed (invalid arguments)")
+    return torch.empty(int(nbytes), dtype=torch.uint8, device="cuda")
+
+
+def adc3_default_opts():
+    o = adc3_opts()
+    load().adc3_default_opts(ctypes.byref(o))
+    return o
+
+
+def adc3_ea_solve_workspace_bytes(nocc, nvir, naux, nroots, opts=None):
+    o = opts if opts is not None else adc3_default_opts()
+    return load().adc3_ea_solve_workspace_bytes(nocc, nvir, naux, nroots, ctypes.byref(o))
+
+
+def adc3_ea_solve(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, opts=None, workspace=None):
+    """Full SS-FNO/NAF EA-ADC solve on device tensors.  Returns (roots[nroots], reports, status)."""
+    lib = load()
+    o = opts if opts is not None else adc3_default_opts()
+    nocc, nvir, naux = int(eps_occ.numel()), int(eps_vir.numel()), int(B.shape[0])
+    if workspace is None:
+        workspace = _workspace(adc3_ea_solve_workspace_bytes(nocc, nvir, naux, nroots, o))
+    roots = (ctypes.c_double * nroots)()
+    reps = (adc3_root_report * nroots)()
+    st = lib.adc3_ea_solve(_ptr(eps_occ), _ptr(eps_vir), _ptr(B), nocc, nvir, naux, nroots,
+                           float(fno_thresh), float(naf_thresh), float(conv), ctypes.byref(o), roots, reps,
+                           ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream())
+    _check(st, allow_noconv=True)
+    reports = [{f: getattr(r, f) for f, _ in adc3_root_report._fields_} for r in reps]
+    return np.array(roots[:]), reports, st
+
+
+def adc3_ea_setup_workspace_bytes(nocc, nvir, naux, level, nroots=0):
+    return load().adc3_ea_setup_workspace_bytes(nocc, nvir, naux, level, nroots)
+
+
+class Context:
+    """Secular-matrix context (adc3_ea_setup ... adc3_ctx_destroy)."""
+
+    def __init__(self, eps_occ, eps_vir, B, level, nroots=8):
+        lib = load()
+        self.nocc, self.nvir, self.naux = int(eps_occ.numel()), int(eps_vir.numel()), int(B.shape[0])
+        self.level = level
+        self.workspace = _workspace(adc3_ea_setup_workspace_bytes(self.nocc, self.nvir, self.naux, level, nroots))
+        h = ctypes.c_void_p()
+        _check(lib.adc3_ea_setup(_ptr(eps_occ), _ptr(eps_vir), _ptr(B), self.nocc, self.nvir, self.naux, level,
+                                 ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(), _stream(),
+                                 ctypes.byref(h)))
+        self.handle = h
+        self.N = lib.adc3_ea_dim(h)
+
+    def close(self):
+        if self.handle:
+            load().adc3_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sigma(self, r, out=None):
+        import torch
+        r = r.contiguous()
+        nvec = 1 if r.dim() == 1 else r.shape[0]
+        if out is None:
+            out = torch.empty_like(r)
+        _check(load().adc3_ea_sigma(self.handle, _ptr(r), _ptr(out), nvec, _stream()))
+        return out
+
+    def diagonal(self):
+        import torch
+        d = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(load().adc3_ea_diagonal(self.handle, _ptr(d), _stream()))
+        return d
+
+    def davidson(self, nroots, conv, max_iter=200, max_subspace=0, want_vectors=False):
+        import torch
+        w = (ctypes.c_double * nroots)()
+        rn = (ctypes.c_double * nroots)()
+        it = ctypes.c_int()
+        vec = torch.empty((nroots, self.N), dtype=torch.float64, device="cuda") if want_vectors else None
+        st = load().adc3_ea_davidson(self.handle, nroots, conv, max_iter, max_subspace, w,
+                                     _ptr(vec) if vec is not None else None, rn, ctypes.byref(it), _stream())
+        _check(st, allow_noconv=True)
+        return np.array(w[:]), vec, np.array(rn[:]), it.value, st
+
+    def dense(self):
+        import torch
+        M = torch.empty((self.N, self.N), dtype=torch.float64, device="cuda")
+        _check(load().adc3_ea_dense_matrix(self.handle, _ptr(M), self.N, _stream()))
+        return M
+
+    def intermediate(self, which):
+        import torch
+        n = ctypes.c_longlong()
+        _check(load().adc3_ea_intermediate(self.handle, which, None, ctypes.byref(n), _stream()))
+        out = torch.empty(n.value, dtype=torch.float64, device="cuda")
+        _check(load().adc3_ea_intermediate(self.handle, which, _ptr(out), None, _stream()))
+        return out
+
+
+adc3_ea_setup = Context

@@ -1,0 +1,956 @@
+// EA-ADC(2)/ADC(3) secular matrix, sigma build, Davidson and the SS-FNO/NAF pipeline.
+//
+// Closed-shell, density-fitted (eq 25): integrals with at most two virtual indices
+// are formed once ((ia|jb), (ij|ab)); three-virtual integrals only enter the
+// one-time 1p/2p1h coupling build; the four-virtual integrals (ac|bd) are assembled
+// once per basis from the DF factor on the matrix cores and kept in HBM as the
+// ladder matrix G[(ab),(cd)] (v^4 doubles: 12.8 GB at v = 200, one of the design
+// choices HBM capacity allows), so every ladder application in the Davidson loop
+// is one GEMM.
+//
+// Vector layout: r = [r1[v], z[o][v][v]], z orthonormal doublet coordinates;
+// x = z_S + z_A/sqrt(3) are the alpha-beta determinant coefficients and
+// sigma_z = S(sigma_D) + sqrt(3) A(sigma_D).
+//
+// Secular matrix blocks (Sec. "Algebraic Diagrammatic Construction (ADC) Theory",
+// eq 5 truncated; closed forms derived from the intermediate-state definition):
+//   M11 = diag(e_v) - sym(P[T])                                  (through 2nd order)
+//        + static self-energy of the 2nd-order density - sym(P[U2])
+//        - sym(sum T (2L - L~)) - sym(ring)                       (3rd order, ADC(3))
+//   U_D[a,b,c,i] = (ab|ic) + (2nd-order terms, ADC(3))
+//   K  = e_a + e_b - e_i + (ladder + particle-hole terms, ADC(3))
+// with T the first-order amplitudes T^ab_ij = (ia|jb)/(e_i+e_j-e_a-e_b),
+// P[A]_ab = sum_klc (2A^ac_kl - A^ca_kl)(kb|lc), L^ab_ij = sum_cd (ac|bd) T^cd_ij.
+#include "internal.h"
+#include "tensor.h"
+#include "../../include/adc3ea.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace adc3 {
+
+namespace {
+thread_local std::string g_msg;
+}
+
+void set_error(const std::string& msg) { g_msg = msg; }
+[[noreturn]] void fail(int status, const std::string& msg) { throw Error{status, msg}; }
+
+static void d2h(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (g_dry) {
+        std::memset(dst, 0, bytes);
+        return;
+    }
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+static void h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    if (g_dry) return;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+constexpr int NVMAX = 16;  // vectors per sigma pass
+
+struct Ctx {
+    int o = 0, v = 0, X = 0, level = 2;
+    long long N = 0;
+    Arena ws;
+    double *eo = nullptr, *ev = nullptr, *Boo = nullptr, *Bov = nullptr, *Bvv = nullptr;
+    double *ovov = nullptr, *oovv = nullptr, *T = nullptr, *M11 = nullptr, *Uz = nullptr, *diag = nullptr;
+    double *Dmp2 = nullptr;
+    double *G = nullptr;      // ladder (ac|bd) as [(ab),(cd)], level 3
+    double *P1 = nullptr;     // (ij|bd) as [i][b][j][d], level 3
+    double *P2 = nullptr;     // (ij|ad) as [i][a][j][d], level 3
+    double *zb = nullptr, *xb = nullptr, *xtb = nullptr, *sdb = nullptr, *sb = nullptr;
+    long long sigma_count = 0;
+};
+
+static double* take(Arena& ws, long long n) { return ws.take<double>((size_t)std::max<long long>(n, 1)); }
+
+// symmetric part, scaled: M += a * (P + P^T)/2, P destroyed
+static void add_sym(double* M, double* P, int v, double a, hipStream_t s) {
+    k_symmetrize(P, v, s);
+    k_axpby(M, P, (long long)v * v, a, 1.0, s);
+}
+
+// Build the context from DF blocks (copied in).  Temporaries are released on return.
+static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const double* Boo_in, const double* Bov_in,
+                      const double* Bvv_in, int o, int v, int X, int level, hipStream_t s) {
+    Ctx* c = new Ctx();
+    c->o = o; c->v = v; c->X = X; c->level = level;
+    c->N = v + (long long)o * v * v;
+    const long long oo = (long long)o * o, ov = (long long)o * v, vv = (long long)v * v;
+    c->eo = take(ws, o); c->ev = take(ws, v);
+    k_copy(c->eo, eo_in, o, s);
+    k_copy(c->ev, ev_in, v, s);
+    c->Boo = take(ws, X * oo); c->Bov = take(ws, X * ov); c->Bvv = take(ws, X * vv);
+    k_copy(c->Boo, Boo_in, X * oo, s);
+    k_copy(c->Bov, Bov_in, X * ov, s);
+    k_copy(c->Bvv, Bvv_in, X * vv, s);
+    const double *Boo = c->Boo, *Bov = c->Bov, *Bvv = c->Bvv, *eo = c->eo, *ev = c->ev;
+
+    c->ovov = take(ws, ov * ov);
+    ein(ws, "Qia,Qjb->iajb", 1.0, TV(Bov, {X, o, v}), TV(Bov, {X, o, v}), 0.0, c->ovov, s);
+    c->oovv = take(ws, oo * vv);
+    ein(ws, "Qij,Qab->ijab", 1.0, TV(Boo, {X, o, o}), TV(Bvv, {X, v, v}), 0.0, c->oovv, s);
+    c->T = take(ws, oo * vv);
+    k_amp_t(c->ovov, eo, ev, o, v, c->T, s);
+    const double* T = c->T;
+    c->M11 = take(ws, vv);
+    c->Dmp2 = take(ws, vv);
+    c->diag = take(ws, c->N);
+    c->Uz = take(ws, v * (long long)o * vv);
+    if (level >= 3) {
+        c->G = take(ws, vv * vv);
+        c->P1 = take(ws, oo * vv);
+        c->P2 = take(ws, oo * vv);
+    }
+    c->zb = take(ws, NVMAX * (long long)o * vv);
+    c->xb = take(ws, NVMAX * (long long)o * vv);
+    c->xtb = take(ws, NVMAX * (long long)o * vv);
+    c->sdb = take(ws, NVMAX * (long long)o * vv);
+    c->sb = take(ws, NVMAX * (long long)o * vv);
+    // ---- everything below is temporary ----
+    const size_t mark = ws.mark();
+    double* Tt2 = take(ws, oo * vv);  // 2T - T~
+    k_comb_t(Tt2, T, oo, v, 2.0, -1.0, s);
+    // MP2 virtual density (per spin): sum_klc (2T^ce_kl - T^ec_kl) T^cd_kl
+    ein(ws, "klce,klcd->ed", 1.0, TV(Tt2, {o, o, v, v}), TV(T, {o, o, v, v}), 0.0, c->Dmp2, s);
+    // M11 through second order
+    double* P = take(ws, vv);
+    ein(ws, "klac,kblc->ab", 1.0, TV(Tt2, {o, o, v, v}), TV(c->ovov, {o, v, o, v}), 0.0, P, s);
+    k_fill(c->M11, vv, 0.0, s);
+    add_sym(c->M11, P, v, -1.0, s);
+    k_add_diag(c->M11, ev, v, s);
+    // coupling U_D[a][b][c][i], first order (ab|ic)
+    double* Ud = take(ws, vv * ov);
+    ein(ws, "Qab,Qic->abci", 1.0, TV(Bvv, {X, v, v}), TV(Bov, {X, o, v}), 0.0, Ud, s);
+
+    if (level >= 3) {
+        // ladder matrix G[(ab),(cd)] = (ac|bd) = sum_Q B^Q_ac B^Q_bd: batch over (a,b)
+        {
+            Gemm g;
+            g.M = v; g.N = v; g.K = X;
+            g.A = Bvv; g.sAm = 1; g.sAk = vv;  // A(c,Q) = Bvv[Q][a][c], batch offset a*v
+            g.B = Bvv; g.sBk = vv; g.sBn = 1;  // B(Q,d) = Bvv[Q][b][d], batch offset b*v
+            g.C = c->G; g.sCm = v; g.sCn = 1;  // C[a][b][c][d]
+            g.nb0 = v; g.bA0 = 0; g.bB0 = v; g.bC0 = vv;          // b0 = b
+            for (int a0 = 0; a0 < v; a0 += std::max(1, 65535 / v)) {
+                int na = std::min(v - a0, std::max(1, 65535 / v));
+                Gemm h = g;
+                h.A = Bvv + (long long)a0 * v;
+                h.C = c->G + (long long)a0 * v * vv;
+                h.nb1 = na; h.bA1 = v; h.bB1 = 0; h.bC1 = v * vv;  // b1 = a - a0
+                gemm(h, s);
+            }
+        }
+        double* oooo = take(ws, oo * oo);
+        ein(ws, "Qij,Qkl->ijkl", 1.0, TV(Boo, {X, o, o}), TV(Boo, {X, o, o}), 0.0, oooo, s);
+        double* ooov = take(ws, oo * ov);
+        ein(ws, "Qij,Qka->ijka", 1.0, TV(Boo, {X, o, o}), TV(Bov, {X, o, v}), 0.0, ooov, s);
+        // second-order doubles residual Y (alpha-beta block)
+        double* L = take(ws, oo * vv);
+        gemm_rm((int)oo, (int)vv, (int)vv, 1.0, T, vv, false, c->G, vv, false, 0.0, L, vv, s);
+        double* Y = take(ws, oo * vv);
+        k_copy(Y, L, oo * vv, s);
+        TV tT(T, {o, o, v, v}), tT2(Tt2, {o, o, v, v}), tovov(c->ovov, {o, v, o, v}), toovv(c->oovv, {o, o, v, v});
+        ein(ws, "klab,kilj->ijab", 1.0, tT, TV(oooo, {o, o, o, o}), 1.0, Y, s);
+        ein(ws, "ikac,jbkc->ijab", 1.0, tT2, tovov, 1.0, Y, s);
+        ein(ws, "ikac,kjbc->ijab", -1.0, tT, toovv, 1.0, Y, s);
+        ein(ws, "kjac,kibc->ijab", -1.0, tT, toovv, 1.0, Y, s);
+        ein(ws, "ikcb,kjac->ijab", -1.0, tT, toovv, 1.0, Y, s);
+        ein(ws, "jkbc,iakc->ijab", 1.0, tT2, tovov, 1.0, Y, s);
+        ein(ws, "jkbc,kiac->ijab", -1.0, tT, toovv, 1.0, Y, s);
+        double* U2 = Y;  // in place: U2 = Y / D
+        k_div_d2(U2, eo, ev, o, v, s);
+        // second-order singles u1[i][a]
+        double* W = take(ws, X * ov);
+        ein(ws, "Qkd,ikcd->Qic", 1.0, TV(Bov, {X, o, v}), tT2, 0.0, W, s);
+        double* u1 = take(ws, ov);
+        ein(ws, "Qac,Qic->ia", 1.0, TV(Bvv, {X, v, v}), TV(W, {X, o, v}), 0.0, u1, s);
+        ein(ws, "klac,kilc->ia", -1.0, tT2, TV(ooov, {o, o, o, v}), 1.0, u1, s);
+        k_div_d1(u1, eo, ev, o, v, s);
+        // second-order densities (per spin)
+        double* roo = take(ws, oo);
+        ein(ws, "mkcd,lkcd->ml", -1.0, tT2, tT, 0.0, roo, s);
+        const double* rvv = c->Dmp2;
+        // static self-energy  sum_pq <ap||bq> rho_pq
+        double* J = take(ws, X);
+        gemm_rm(X, 1, (int)oo, 1.0, Boo, oo, false, roo, 1, false, 0.0, J, 1, s);
+        gemm_rm(X, 1, (int)vv, 1.0, Bvv, vv, false, rvv, 1, false, 1.0, J, 1, s);
+        gemm_rm(X, 1, (int)ov, 2.0, Bov, ov, false, u1, 1, false, 1.0, J, 1, s);
+        gemm_rm((int)vv, 1, X, 2.0, Bvv, vv, true, J, 1, false, 1.0, c->M11, 1, s);
+        double* Z1 = take(ws, X * ov);
+        ein(ws, "ml,Qlb->Qmb", 1.0, TV(roo, {o, o}), TV(Bov, {X, o, v}), 0.0, Z1, s);
+        ein(ws, "Qma,Qmb->ab", -1.0, TV(Bov, {X, o, v}), TV(Z1, {X, o, v}), 1.0, c->M11, s);
+        double* Z2 = take(ws, X * vv);
+        ein(ws, "Qad,ed->Qae", 1.0, TV(Bvv, {X, v, v}), TV(rvv, {v, v}), 0.0, Z2, s);
+        ein(ws, "Qae,Qeb->ab", -1.0, TV(Z2, {X, v, v}), TV(Bvv, {X, v, v}), 1.0, c->M11, s);
+        double* Z3 = Z1;
+        ein(ws, "Qbc,kc->Qkb", 1.0, TV(Bvv, {X, v, v}), TV(u1, {o, v}), 0.0, Z3, s);
+        ein(ws, "Qka,Qkb->ab", -1.0, TV(Bov, {X, o, v}), TV(Z3, {X, o, v}), 1.0, c->M11, s);
+        ein(ws, "Qkb,Qka->ab", -1.0, TV(Bov, {X, o, v}), TV(Z3, {X, o, v}), 1.0, c->M11, s);
+        // second-order form with second-order amplitudes
+        double* U2t2 = take(ws, oo * vv);
+        k_comb_t(U2t2, U2, oo, v, 2.0, -1.0, s);
+        ein(ws, "klac,kblc->ab", 1.0, TV(U2t2, {o, o, v, v}), tovov, 0.0, P, s);
+        add_sym(c->M11, P, v, -1.0, s);
+        // ladder part: - sym( sum_ekl T^ae_kl (2 L^be_kl - L^eb_kl) )
+        double* Lt2 = U2t2;
+        k_comb_t(Lt2, L, oo, v, 2.0, -1.0, s);
+        ein(ws, "klae,klbe->ab", 1.0, tT, TV(Lt2, {o, o, v, v}), 0.0, P, s);
+        add_sym(c->M11, P, v, -1.0, s);
+        // ring part
+        double* g1 = take(ws, oo * vv);   // [d][l][b][m] = (db|ml) - (dl|mb)
+        double* g2 = take(ws, oo * vv);   // [d][l][b][m] = (dl|mb)
+        double* g3 = take(ws, oo * vv);   // [d][l][b][m] = (db|ml)
+        {
+            int d_oovv[4] = {o, o, v, v}, p_oovv[4] = {2, 1, 3, 0};  // oovv[m][l][d][b] -> [d][l][b][m]
+            int d_ovov[4] = {o, v, o, v}, p_ovov[4] = {1, 0, 3, 2};  // ovov[l][d][m][b] -> [d][l][b][m]
+            k_permute4(g3, c->oovv, d_oovv, p_oovv, 1.0, 0.0, s);
+            k_permute4(g2, c->ovov, d_ovov, p_ovov, 1.0, 0.0, s);
+            k_copy(g1, g3, oo * vv, s);
+            k_axpby(g1, g2, oo * vv, -1.0, 1.0, s);
+        }
+        double* TmT = Lt2;  // T - T~
+        k_comb_t(TmT, T, oo, v, 1.0, -1.0, s);
+        TV tg1(g1, {v, o, v, o}), tg2(g2, {v, o, v, o}), tg3(g3, {v, o, v, o}), tTm(TmT, {o, o, v, v});
+        double* RA = take(ws, oo * vv);
+        double* RB = take(ws, oo * vv);
+        double* RC = take(ws, oo * vv);
+        ein(ws, "klcd,dlbm->ckbm", 1.0, tTm, tg1, 0.0, RA, s);
+        ein(ws, "klcd,dlbm->ckbm", -1.0, tT, tg2, 1.0, RA, s);
+        ein(ws, "klcd,dlbm->ckbm", 1.0, tT, tg1, 0.0, RB, s);
+        ein(ws, "klcd,dlbm->ckbm", -1.0, tTm, tg2, 1.0, RB, s);
+        ein(ws, "kldc,dlbm->ckbm", -1.0, tT, tg3, 0.0, RC, s);
+        TV tRA(RA, {v, o, v, o}), tRB(RB, {v, o, v, o}), tRC(RC, {v, o, v, o});
+        ein(ws, "kmac,ckbm->ab", 1.0, tTm, tRA, 0.0, P, s);
+        ein(ws, "mkac,ckbm->ab", -1.0, tT, tRB, 1.0, P, s);
+        ein(ws, "kmac,ckbm->ab", 1.0, tT, tRC, 1.0, P, s);
+        add_sym(c->M11, P, v, -1.0, s);
+        // coupling, second order
+        ein(ws, "klbc,ilka->abci", 1.0, tT, TV(ooov, {o, o, o, v}), 1.0, Ud, s);
+        double* ovvv = take(ws, ov * vv);
+        ein(ws, "Qka,Qcd->kacd", 1.0, TV(Bov, {X, o, v}), TV(Bvv, {X, v, v}), 0.0, ovvv, s);
+        TV tovvv(ovvv, {o, v, v, v});
+        ein(ws, "kibd,kacd->abci", -1.0, tT, tovvv, 1.0, Ud, s);
+        ein(ws, "ikcd,kdab->abci", 1.0, tT2, tovvv, 1.0, Ud, s);
+        ein(ws, "ikcd,kabd->abci", -1.0, tT, tovvv, 1.0, Ud, s);
+        // permuted integrals for the particle-hole sigma terms
+        {
+            int d_oovv[4] = {o, o, v, v};
+            int p1[4] = {0, 2, 1, 3};  // [i][j][b][d] -> [i][b][j][d]
+            k_permute4(c->P1, c->oovv, d_oovv, p1, 1.0, 0.0, s);
+            k_permute4(c->P2, c->oovv, d_oovv, p1, 1.0, 0.0, s);  // same layout, read as [i][a][j][d]
+        }
+    }
+    // U_z[a][i][b][c] = S + sqrt3 A over (b,c) of U_D[a][b][c][i]
+    {
+        double* Up = take(ws, vv * ov);
+        int d[4] = {v, v, v, o}, p[4] = {0, 3, 1, 2};
+        k_permute4(Up, Ud, d, p, 1.0, 0.0, s);
+        k_fill(c->Uz, vv * ov, 0.0, s);
+        k_d_to_z_add(c->Uz, Up, (long long)v * o, v, s);
+    }
+    k_diag_adc(c->diag, c->M11, eo, ev, Bvv, c->oovv, c->ovov, o, v, X, level, s);
+    ws.release(mark);
+    c->ws = ws;  // snapshot (base/cap/used) for sigma temporaries
+    return c;
+}
+
+// sigma = M r for nvec vectors
+static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nvec, hipStream_t s) {
+    const int o = c->o, v = c->v;
+    const long long N = c->N, vv = (long long)v * v, ovv = (long long)o * vv;
+    for (int n0 = 0; n0 < nvec; n0 += NVMAX) {
+        const int nv = std::min(NVMAX, nvec - n0);
+        const double* rr = r + (long long)n0 * N;
+        double* ss = sg + (long long)n0 * N;
+        // 1p: M11 r1 + U_z z
+        gemm_rm(nv, v, v, 1.0, rr, N, false, c->M11, v, true, 0.0, ss, N, s);
+        gemm_rm(nv, v, (int)ovv, 1.0, rr + v, N, false, c->Uz, ovv, true, 1.0, ss, N, s);
+        // 2p1h: U_z^T r1 + K0 z
+        gemm_rm(nv, (int)ovv, v, 1.0, rr, N, false, c->Uz, ovv, false, 0.0, ss + v, N, s);
+        k_k0_add(ss + v, rr + v, c->eo, c->ev, o, v, nv, N, s);
+        if (c->level >= 3) {
+            Arena& ws = wsin;
+            double* zb = c->zb;
+            k_copy2d(zb, ovv, rr + v, N, nv, ovv, 1.0, 0.0, s);
+            // ladder: sum_cd (ac|bd) z_cd  (G symmetric)
+            gemm_rm(nv * o, (int)vv, (int)vv, 1.0, zb, vv, false, c->G, vv, false, 0.0, c->sb, vv, s);
+            // particle-hole terms on the alpha-beta determinants
+            k_z_to_x(zb, c->xb, c->xtb, (long long)nv * o, v, s);
+            TV tx(c->xb, {nv, o, v, v}), txt(c->xtb, {nv, o, v, v});
+            ein(ws, "ibjd,njad->niab", 1.0, TV(c->ovov, {o, v, o, v}), txt, 0.0, c->sdb, s);
+            ein(ws, "ibjd,njad->niab", -1.0, TV(c->P1, {o, v, o, v}), tx, 1.0, c->sdb, s);
+            ein(ws, "iajd,njdb->niab", -1.0, TV(c->P2, {o, v, o, v}), tx, 1.0, c->sdb, s);
+            k_d_to_z_add(c->sb, c->sdb, (long long)nv * o, v, s);
+            k_copy2d(ss + v, N, c->sb, ovv, nv, ovv, 1.0, 1.0, s);
+        }
+    }
+    c->sigma_count += nvec;
+}
+
+// ---------------------------------------------------------------------------
+// Davidson (FP64, device-resident subspace)
+// ---------------------------------------------------------------------------
+struct DavResult {
+    std::vector<double> w, rn;
+    int iters = 0;
+    bool converged = false;
+};
+
+static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int max_iter, int max_sub,
+                               double* vec_out, hipStream_t s) {
+    const long long N = c->N;
+    if (nroots < 1 || nroots > N) fail(-1, "davidson: nroots out of range");
+    if (nroots > 40) fail(-1, "davidson: at most 40 roots per solve");
+    int mmax = max_sub > 0 ? max_sub : std::max(8 * nroots, 40);
+    mmax = std::max(mmax, 2 * nroots + 1);
+    mmax = (int)std::min<long long>(std::min(mmax, 96), N);
+    const int nguess = (int)std::min<long long>(N, std::min(nroots + 4, mmax));
+    const size_t mark = ws.mark();
+    double* V = take(ws, (long long)mmax * N);
+    double* S = take(ws, (long long)mmax * N);
+    double* Xr = take(ws, (long long)nroots * N);
+    double* AX = take(ws, (long long)nroots * N);
+    double* R = take(ws, (long long)nroots * N);
+    double* Gm = take(ws, (long long)mmax * mmax);
+    double* Gw = take(ws, (long long)mmax * mmax + mmax);
+    double* ev = take(ws, mmax);
+    double* Y = take(ws, (long long)mmax * mmax);
+    double* th = take(ws, nroots);
+    double* coef = take(ws, (long long)mmax * nroots);
+    double* small = take(ws, 16);
+    double* part = take(ws, (long long)dots_partial_elems(mmax, mmax, N));
+    DavResult res;
+    res.w.assign(nroots, 0.0);
+    res.rn.assign(nroots, 0.0);
+    if (g_dry) {
+        sigma_impl(c, ws, V, S, std::min(NVMAX, nguess), s);  // count the sigma temporaries too
+        ws.release(mark);
+        return res;
+    }
+    // guesses: unit vectors on the lowest diagonal entries (ties by index)
+    std::vector<double> hd(N);
+    d2h(hd.data(), c->diag, N * sizeof(double), s);
+    std::vector<long long> idx(N);
+    for (long long i = 0; i < N; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](long long a, long long b) { return hd[a] < hd[b]; });
+    k_fill(V, (long long)nguess * N, 0.0, s);
+    std::vector<double> one(1, 1.0);
+    for (int k = 0; k < nguess; ++k) h2d(V + (long long)k * N + idx[k], one.data(), sizeof(double), s);
+    int m = nguess;
+    sigma_impl(c, ws, V, S, m, s);
+    std::vector<double> thold(nroots, INFINITY), hw(mmax), hrn(nroots * nroots);
+    std::vector<double> hY;
+    int it = 0;
+    for (;;) {
+        ++it;
+        // Rayleigh-Ritz
+        k_dots(V, N, m, S, N, m, N, Gm, m, part, s);
+        k_symmetrize(Gm, m, s);
+        eig_small(Gm, m, ev, Y, s);
+        k_sort_eig(ev, Y, m, 0, Gw, Gw + m, s);  // ascending, deterministic signs
+        d2h(hw.data(), ev, m * sizeof(double), s);
+        for (int k = 0; k < nroots; ++k) res.w[k] = hw[k];
+        // Ritz vectors X = Y^T V, AX = Y^T S (first nroots columns of Y)
+        k_copy2d(coef, nroots, Y, m, m, nroots, 1.0, 0.0, s);
+        k_lincomb(Xr, N, nroots, V, N, m, coef, nroots, N, 1.0, 0.0, s);
+        k_lincomb(AX, N, nroots, S, N, m, coef, nroots, N, 1.0, 0.0, s);
+        k_copy(th, ev, nroots, s);
+        k_residual(R, AX, Xr, th, nroots, N, s);
+        k_dots(R, N, nroots, R, N, nroots, N, Gw, nroots, part, s);
+        d2h(hrn.data(), Gw, (size_t)nroots * nroots * sizeof(double), s);
+        std::vector<int> todo;
+        bool finite = true;
+        for (int k = 0; k < nroots; ++k) {
+            res.rn[k] = std::sqrt(std::max(0.0, hrn[k * nroots + k]));
+            if (!std::isfinite(res.w[k]) || !std::isfinite(res.rn[k])) finite = false;
+            bool ok = res.rn[k] <= conv && std::fabs(res.w[k] - thold[k]) <= conv;
+            if (!ok) todo.push_back(k);
+        }
+        if (!finite) fail(-4, "davidson: non-finite Ritz value or residual");
+        res.iters = it;
+        if (todo.empty() || it >= max_iter) {
+            res.converged = todo.empty();
+            break;
+        }
+        for (int k = 0; k < nroots; ++k) thold[k] = res.w[k];
+        int nn = (int)todo.size();
+        // collapse when the new block does not fit
+        if (m + nn > mmax) {
+            k_copy(V, Xr, (long long)nroots * N, s);
+            k_copy(S, AX, (long long)nroots * N, s);
+            m = nroots;
+        }
+        nn = std::min(nn, mmax - m);
+        if (nn <= 0) {
+            res.converged = false;
+            break;
+        }
+        // preconditioned residuals of the unconverged roots -> V[m .. m+nn)
+        double* Tn = V + (long long)m * N;
+        for (int j = 0; j < nn; ++j) {
+            int k = todo[j];
+            k_precond(Tn + (long long)j * N, R + (long long)k * N, c->diag, th + k, 1, N, s);
+        }
+        // two passes of classical Gram-Schmidt against V[0..m)
+        for (int pass = 0; pass < 2; ++pass) {
+            k_dots(V, N, m, Tn, N, nn, N, coef, nn, part, s);
+            k_lincomb(Tn, N, nn, V, N, m, coef, nn, N, -1.0, 1.0, s);
+        }
+        // orthonormalise the new block among itself; drop vectors with tiny norm
+        int acc = 0;
+        for (int j = 0; j < nn; ++j) {
+            double* tj = Tn + (long long)j * N;
+            for (int pass = 0; pass < 2; ++pass) {
+                int cur = m + acc;
+                k_dots(V, N, cur, tj, N, 1, N, coef, 1, part, s);
+                k_lincomb(tj, N, 1, V, N, cur, coef, 1, N, -1.0, 1.0, s);
+            }
+            double nrm2;
+            k_dots(tj, N, 1, tj, N, 1, N, small, 1, part, s);
+            d2h(&nrm2, small, sizeof(double), s);
+            double nrm = std::sqrt(std::max(0.0, nrm2));
+            if (!(nrm > 1e-10)) continue;
+            double inv = 1.0 / nrm;
+            h2d(small + 1, &inv, sizeof(double), s);
+            double* dst = V + (long long)(m + acc) * N;
+            if (dst != tj) k_copy(dst, tj, N, s);
+            k_scale_vec(dst, N, small + 1, s);
+            ++acc;
+        }
+        if (acc == 0) {
+            res.converged = false;
+            break;
+        }
+        sigma_impl(c, ws, V + (long long)m * N, S + (long long)m * N, acc, s);
+        m += acc;
+    }
+    if (vec_out) k_copy(vec_out, Xr, (long long)nroots * N, s);
+    HIPCHK(hipStreamSynchronize(s));
+    ws.release(mark);
+    return res;
+}
+
+// ---------------------------------------------------------------------------
+// SS-FNO / NAF pipeline (Sec. "Computational Details", steps 2-4f)
+// ---------------------------------------------------------------------------
+struct Blocks {
+    double *Boo, *Bov, *Bvv;
+    int X, o, v;
+};
+
+// D^EA(k) (eq 17, zeroth-order ISR of the ADC(2) eigenvector), spin averaged:
+// 1/2 [r1 r1^T + sum_ci (x_aci x_bci + y_aci y_bci + x_cai x_cbi)],  y = x - x^T
+static void ea_density(Arena& ws, const Ctx* c, const double* vec, double* D, hipStream_t s) {
+    const int o = c->o, v = c->v;
+    const long long vv = (long long)v * v, ovv = o * vv;
+    const size_t mark = ws.mark();
+    double* x = take(ws, ovv);
+    double* y = take(ws, ovv);
+    k_z_to_x(vec + v, x, nullptr, o, v, s);
+    k_comb_t(y, x, o, v, 1.0, -1.0, s);
+    gemm_rm(v, v, 1, 0.5, vec, 1, false, vec, v, false, 0.0, D, v, s);
+    TV tx(x, {o, v, v}), ty(y, {o, v, v});
+    ein(ws, "iac,ibc->ab", 0.5, tx, tx, 1.0, D, s);
+    ein(ws, "iac,ibc->ab", 0.5, ty, ty, 1.0, D, s);
+    ein(ws, "ica,icb->ab", 0.5, tx, tx, 1.0, D, s);
+    ws.release(mark);
+}
+
+// Natural orbitals of D (eq 9), kept eta > thr (eqs 10-11; thr <= 0 keeps all),
+// recanonicalised (eqs 12-13); returns kept count, writes U[v][vk] (eq 14) and e_new[vk].
+static int natural_orbitals(Arena& ws, const double* D, const double* ev, int v, double thr, double* U,
+                            double* e_new, hipStream_t s) {
+    const long long vv = (long long)v * v;
+    const size_t mark = ws.mark();
+    double* A = take(ws, vv);
+    double* w = take(ws, v);
+    double* V = take(ws, vv);
+    double* wt = take(ws, v);
+    double* Vt = take(ws, vv);
+    double* scr = take(ws, (long long)eig_large_scratch(v));
+    k_copy(A, D, vv, s);
+    k_symmetrize(A, v, s);
+    eig_large(A, v, w, V, scr, s);
+    k_sort_eig(w, V, v, 1, wt, Vt, s);  // descending occupation
+    std::vector<double> hw(v);
+    d2h(hw.data(), w, v * sizeof(double), s);
+    int vk = 0;
+    if (g_dry || !(thr > 0)) vk = v;
+    else
+        for (int a = 0; a < v; ++a) vk += hw[a] > thr;
+    if (vk > 0) {
+        // F~ = V~^T diag(e) V~ (V~ = first vk columns of V)
+        double* EV = take(ws, (long long)v * vk);
+        k_copy2d(EV, vk, V, v, v, vk, 1.0, 0.0, s);
+        double* EVs = take(ws, (long long)v * vk);
+        k_scale_rows(EVs, EV, ev, v, vk, s);
+        double* F = take(ws, (long long)vk * vk);
+        gemm_rm(vk, vk, v, 1.0, EV, vk, true, EVs, vk, false, 0.0, F, vk, s);
+        k_symmetrize(F, vk, s);
+        double* Z = take(ws, (long long)vk * vk);
+        double* zt = take(ws, (long long)vk * vk);
+        double* scr2 = take(ws, (long long)eig_large_scratch(vk));
+        eig_large(F, vk, e_new, Z, scr2, s);
+        k_sort_eig(e_new, Z, vk, 0, wt, zt, s);
+        gemm_rm(v, vk, vk, 1.0, EV, vk, false, Z, vk, false, 0.0, U, vk, s);
+        k_colsign(U, vk, v, vk, s);
+    }
+    ws.release(mark);
+    return vk;
+}
+
+// New factor blocks in the truncated virtual basis: Bov U, U^T Bvv U (eqs 14-16).
+static void transform_blocks(const Blocks& in, const double* U, int vk, Blocks& out, Arena& ws, hipStream_t s) {
+    const int X = in.X, o = in.o, v = in.v;
+    out.X = X; out.o = o; out.v = vk;
+    out.Boo = in.Boo;
+    out.Bov = take(ws, (long long)X * o * vk);
+    out.Bvv = take(ws, (long long)X * vk * vk);
+    gemm_rm(X * o, vk, v, 1.0, in.Bov, v, false, U, vk, false, 0.0, out.Bov, vk, s);
+    const size_t mark = ws.mark();
+    double* tmp = take(ws, (long long)X * v * vk);
+    gemm_rm(X * v, vk, v, 1.0, in.Bvv, v, false, U, vk, false, 0.0, tmp, vk, s);
+    Gemm g;
+    g.M = vk; g.N = vk; g.K = v;
+    g.A = U; g.sAm = 1; g.sAk = vk;
+    g.B = tmp; g.sBk = vk; g.sBn = 1; g.bB0 = (long long)v * vk;
+    g.C = out.Bvv; g.sCm = vk; g.sCn = 1; g.bC0 = (long long)vk * vk;
+    for (int q0 = 0; q0 < X; q0 += 65535) {
+        Gemm h = g;
+        h.nb0 = std::min(65535, X - q0);
+        h.B = tmp + (long long)q0 * v * vk;
+        h.C = out.Bvv + (long long)q0 * vk * vk;
+        gemm(h, s);
+    }
+    ws.release(mark);
+}
+
+// Natural auxiliary functions (eqs 27-29): W = J_vv J_vv^T, keep w >= thr (thr <= 0 keeps all).
+static int naf_blocks(const Blocks& in, double thr, Blocks& out, Arena& ws, hipStream_t s) {
+    const int X = in.X, o = in.o, v = in.v;
+    const long long vv = (long long)v * v;
+    double* W = take(ws, (long long)X * X);
+    double* w = take(ws, X);
+    double* N = take(ws, (long long)X * X);
+    {
+        const size_t mark = ws.mark();
+        double* wt = take(ws, X);
+        double* Nt = take(ws, (long long)X * X);
+        double* scr = take(ws, (long long)eig_large_scratch(X));
+        gemm_rm(X, X, (int)vv, 1.0, in.Bvv, vv, false, in.Bvv, vv, true, 0.0, W, X, s);
+        k_symmetrize(W, X, s);
+        eig_large(W, X, w, N, scr, s);
+        k_sort_eig(w, N, X, 1, wt, Nt, s);
+        ws.release(mark);
+    }
+    std::vector<double> hw(std::max(X, 1));
+    d2h(hw.data(), w, X * sizeof(double), s);
+    int xk = 0;
+    if (g_dry || !(thr > 0)) xk = X;
+    else
+        for (int q = 0; q < X; ++q) xk += hw[q] >= thr;
+    out.X = xk; out.o = o; out.v = v;
+    out.Boo = take(ws, (long long)xk * o * o);
+    out.Bov = take(ws, (long long)xk * o * v);
+    out.Bvv = take(ws, (long long)xk * vv);
+    if (xk > 0) {
+        gemm_rm(xk, o * o, X, 1.0, N, X, true, in.Boo, (long long)o * o, false, 0.0, out.Boo, (long long)o * o, s);
+        gemm_rm(xk, o * v, X, 1.0, N, X, true, in.Bov, (long long)o * v, false, 0.0, out.Bov, (long long)o * v, s);
+        gemm_rm(xk, (int)vv, X, 1.0, N, X, true, in.Bvv, vv, false, 0.0, out.Bvv, vv, s);
+    }
+    return xk;
+}
+
+struct SolveOut {
+    std::vector<adc3_root_report> rep;
+    bool all_conv = true;
+};
+
+static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const Blocks& B0, int nroots, double fno,
+                           double naf, double conv, const adc3_opts& op, hipStream_t s) {
+    const int o = B0.o, v = B0.v, X = B0.X;
+    SolveOut out;
+    out.rep.assign(nroots, adc3_root_report{});
+    const int level = op.level;
+    if (!(fno > 0) && !(naf > 0)) {
+        const size_t mark = ws.mark();
+        Ctx* c = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, level, s);
+        DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s);
+        for (int k = 0; k < nroots; ++k) {
+            auto& R = out.rep[k];
+            R.omega = R.omega_uncorr = r.w[k];
+            R.resnorm = r.rn[k];
+            R.nvir_kept = v;
+            R.naux_kept = X;
+            R.iters = r.iters;
+            R.sigma_builds = (int)c->sigma_count;
+        }
+        out.all_conv = r.converged;
+        delete c;
+        ws.release(mark);
+        return out;
+    }
+    // steps 2-3: canonical MP2 density and canonical ADC(2) roots
+    const size_t mark0 = ws.mark();
+    Ctx* c0 = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, 2, s);
+    double* Y2 = take(ws, (long long)nroots * c0->N);
+    DavResult r2 = davidson_impl(c0, ws, nroots, conv, op.max_iter, op.max_subspace, Y2, s);
+    out.all_conv = out.all_conv && r2.converged;
+    const int sig0 = (int)c0->sigma_count;
+    // step 4: per root
+    for (int k = 0; k < nroots; ++k) {
+        const size_t mark = ws.mark();
+        auto& R = out.rep[k];
+        R.omega_adc2_can = r2.w[k];
+        double* D = take(ws, (long long)v * v);
+        ea_density(ws, c0, Y2 + (long long)k * c0->N, D, s);          // 4a
+        k_axpby(D, c0->Dmp2, (long long)v * v, 1.0, 1.0, s);          // 4b
+        double* U = take(ws, (long long)v * v);
+        double* enew = take(ws, v);
+        int vk = natural_orbitals(ws, D, ev, v, fno, U, enew, s);     // 4c-4d
+        if (vk < 1) fail(ADC3_EINVAL, "SS-FNO threshold removes every virtual orbital");
+        Blocks Bt;
+        transform_blocks(B0, U, vk, Bt, ws, s);
+        Blocks Bn = Bt;
+        int xk = X;
+        if (naf > 0) xk = naf_blocks(Bt, naf, Bn, ws, s);           // 4e
+        const long long Nk = vk + (long long)o * vk * vk;
+        if (nroots > Nk) fail(ADC3_EINVAL, "truncated space smaller than nroots");
+        int sig = 0;
+        {
+            const size_t m2 = ws.mark();
+            Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s);
+            DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s);
+            R.omega_adc2_fno = a2.w[k];
+            out.all_conv = out.all_conv && a2.converged;
+            sig += (int)c2->sigma_count;
+            delete c2;
+            ws.release(m2);
+        }
+        {
+            const size_t m3 = ws.mark();
+            Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s);
+            DavResult a3 = davidson_impl(c3, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s);
+            R.omega_uncorr = a3.w[k];
+            R.resnorm = a3.rn[k];
+            R.iters = a3.iters;
+            out.all_conv = out.all_conv && a3.converged;
+            sig += (int)c3->sigma_count;
+            delete c3;
+            ws.release(m3);
+        }
+        R.nvir_kept = vk;
+        R.naux_kept = xk;
+        R.sigma_builds = sig + (k == 0 ? sig0 : 0);
+        R.omega = R.omega_uncorr + (op.fno_correction ? (R.omega_adc2_can - R.omega_adc2_fno) : 0.0);  // eq 30
+        ws.release(mark);
+    }
+    delete c0;
+    ws.release(mark0);
+    return out;
+}
+
+}  // namespace adc3
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+using namespace adc3;
+
+struct adc3_ctx {
+    Ctx* c;
+};
+
+#define API_BEGIN try {
+#define API_END                                   \
+    }                                             \
+    catch (const Error& e) {                      \
+        g_dry = false;                            \
+        set_error(e.msg);                         \
+        return e.status;                          \
+    }                                             \
+    catch (const std::exception& e) {             \
+        g_dry = false;                            \
+        set_error(e.what());                      \
+        return ADC3_EINVAL;                       \
+    }
+
+extern "C" {
+
+void adc3_default_opts(adc3_opts* o) {
+    if (!o) return;
+    o->level = 3;
+    o->max_iter = 200;
+    o->max_subspace = 0;
+    o->fno_correction = 1;
+    o->precision = 0;
+    o->precond = 0;
+}
+
+const char* adc3_last_error(void) { return g_msg.c_str(); }
+
+static void check_dims(int nocc, int nvir, int naux) {
+    if (nocc <= 0 || nvir <= 0 || naux < 0) fail(ADC3_EINVAL, "nocc and nvir must be > 0 and naux >= 0");
+    if ((long long)nvir * nvir * nvir * nvir > (1LL << 40)) fail(ADC3_EINVAL, "nvir too large for the stored ladder");
+}
+
+size_t adc3_ea_setup_workspace_bytes(int nocc, int nvir, int naux, int level, int nroots) {
+    try {
+        check_dims(nocc, nvir, naux);
+        if (level != 2 && level != 3) return 0;
+        Arena ws;
+        g_dry = true;
+        const long long n = nocc + nvir;
+        take(ws, (long long)naux * n * n);  // split blocks of the public setup
+        Ctx* c = build_ctx(ws, nullptr, nullptr, nullptr, nullptr, nullptr, nocc, nvir, naux, level, nullptr);
+        {
+            Arena w2 = ws;
+            take(w2, 2LL * NVMAX * c->N);  // dense-matrix hook
+            sigma_impl(c, w2, nullptr, nullptr, NVMAX, nullptr);
+            ws.peak = std::max(ws.peak, w2.peak);
+        }
+        if (nroots > 0) {
+            Arena w3 = ws;
+            davidson_impl(c, w3, (int)std::min<long long>(nroots, c->N), 1.0, 1, 0, nullptr, nullptr);
+            ws.peak = std::max(ws.peak, w3.peak);
+        }
+        delete c;
+        g_dry = false;
+        return ws.peak + (1 << 20);
+    } catch (...) {
+        g_dry = false;
+        return 0;
+    }
+}
+
+int adc3_ea_setup(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir, int naux,
+                  int level, void* workspace, size_t ws_bytes, hipStream_t stream, adc3_ctx** ctx_out) {
+    API_BEGIN
+    if (!ctx_out) fail(ADC3_EINVAL, "ctx_out is NULL");
+    *ctx_out = nullptr;
+    check_dims(nocc, nvir, naux);
+    if (level != 2 && level != 3) fail(ADC3_EINVAL, "level must be 2 or 3");
+    if (!eps_occ || !eps_vir || (!B && naux > 0) || !workspace) fail(ADC3_EINVAL, "NULL pointer argument");
+    Arena ws;
+    ws.base = (char*)workspace;
+    ws.cap = ws_bytes;
+    const long long n = nocc + nvir;
+    // split the factor into blocks (temporary, at the top of the workspace)
+    const size_t mark0 = ws.mark();
+    double* Boo = take(ws, (long long)naux * nocc * nocc);
+    double* Bov = take(ws, (long long)naux * nocc * nvir);
+    double* Bvv = take(ws, (long long)naux * nvir * nvir);
+    k_split_B(B, naux, nocc, nvir, Boo, Bov, Bvv, stream);
+    (void)n;
+    Ctx* c = build_ctx(ws, eps_occ, eps_vir, Boo, Bov, Bvv, nocc, nvir, naux, level, stream);
+    (void)mark0;
+    HIPCHK(hipStreamSynchronize(stream));
+    adc3_ctx* h = new adc3_ctx{c};
+    *ctx_out = h;
+    return ADC3_OK;
+    API_END
+}
+
+void adc3_ctx_destroy(adc3_ctx* ctx) {
+    if (!ctx) return;
+    delete ctx->c;
+    delete ctx;
+}
+
+long long adc3_ea_dim(const adc3_ctx* ctx) { return ctx ? ctx->c->N : 0; }
+
+int adc3_ea_sigma(adc3_ctx* ctx, const double* r, double* sigma, int nvec, hipStream_t stream) {
+    API_BEGIN
+    if (!ctx || !r || !sigma) fail(ADC3_EINVAL, "NULL argument");
+    if (nvec < 0) fail(ADC3_EINVAL, "nvec < 0");
+    Arena ws = ctx->c->ws;
+    sigma_impl(ctx->c, ws, r, sigma, nvec, stream);
+    return ADC3_OK;
+    API_END
+}
+
+int adc3_ea_diagonal(adc3_ctx* ctx, double* diag, hipStream_t stream) {
+    API_BEGIN
+    if (!ctx || !diag) fail(ADC3_EINVAL, "NULL argument");
+    k_copy(diag, ctx->c->diag, ctx->c->N, stream);
+    return ADC3_OK;
+    API_END
+}
+
+int adc3_ea_davidson(adc3_ctx* ctx, int nroots, double conv, int max_iter, int max_subspace, double* omega,
+                     double* vectors, double* resnorm, int* iters, hipStream_t stream) {
+    API_BEGIN
+    if (!ctx || !omega) fail(ADC3_EINVAL, "NULL argument");
+    if (!(conv > 0)) fail(ADC3_EINVAL, "conv must be > 0");
+    if (nroots < 1 || nroots > ctx->c->N) fail(ADC3_EINVAL, "nroots out of range");
+    if (max_iter < 1) fail(ADC3_EINVAL, "max_iter must be >= 1");
+    Arena ws = ctx->c->ws;
+    DavResult r = davidson_impl(ctx->c, ws, nroots, conv, max_iter, max_subspace, vectors, stream);
+    for (int k = 0; k < nroots; ++k) {
+        omega[k] = r.w[k];
+        if (resnorm) resnorm[k] = r.rn[k];
+    }
+    if (iters) *iters = r.iters;
+    return r.converged ? ADC3_OK : ADC3_WNOCONV;
+    API_END
+}
+
+int adc3_ea_dense_matrix(adc3_ctx* ctx, double* M, int ldm, hipStream_t stream) {
+    API_BEGIN
+    if (!ctx || !M) fail(ADC3_EINVAL, "NULL argument");
+    const long long N = ctx->c->N;
+    if (N > 20000) fail(ADC3_EINVAL, "dense matrix only for N <= 20000");
+    if (ldm < N) fail(ADC3_EINVAL, "ldm < N");
+    Arena ws = ctx->c->ws;
+    double* E = take(ws, NVMAX * N);
+    double* Sg = take(ws, NVMAX * N);
+    std::vector<double> one(1, 1.0);
+    for (long long j0 = 0; j0 < N; j0 += NVMAX) {
+        int nb = (int)std::min<long long>(NVMAX, N - j0);
+        k_fill(E, nb * N, 0.0, stream);
+        for (int j = 0; j < nb; ++j) h2d(E + j * N + j0 + j, one.data(), sizeof(double), stream);
+        sigma_impl(ctx->c, ws, E, Sg, nb, stream);
+        // columns j0..j0+nb of M = rows of Sg (M symmetric)
+        k_copy2d(M + j0 * ldm, ldm, Sg, N, nb, N, 1.0, 0.0, stream);
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+    return ADC3_OK;
+    API_END
+}
+
+int adc3_ea_intermediate(adc3_ctx* ctx, int which, double* out, long long* count, hipStream_t stream) {
+    API_BEGIN
+    if (!ctx) fail(ADC3_EINVAL, "NULL ctx");
+    Ctx* c = ctx->c;
+    const long long vv = (long long)c->v * c->v;
+    const double* src = nullptr;
+    long long n = 0;
+    switch (which) {
+        case 0: src = c->M11; n = vv; break;
+        case 1: src = c->Uz; n = vv * c->v * c->o; break;
+        case 2: src = c->T; n = vv * c->o * c->o; break;
+        case 3: src = c->Dmp2; n = vv; break;
+        default: fail(ADC3_EINVAL, "unknown intermediate");
+    }
+    if (count) *count = n;
+    if (out) k_copy(out, src, n, stream);
+    return ADC3_OK;
+    API_END
+}
+
+}  // extern "C"
+
+static void validate_inputs(const double* eo, const double* ev, const double* B, int o, int v, int X, hipStream_t s,
+                            Arena& ws) {
+    std::vector<double> ho(o), hv(v);
+    d2h(ho.data(), eo, o * sizeof(double), s);
+    d2h(hv.data(), ev, v * sizeof(double), s);
+    if (g_dry) return;
+    for (int i = 0; i < o; ++i)
+        if (!std::isfinite(ho[i]) || (i && ho[i] < ho[i - 1])) fail(ADC3_EINVAL, "eps_occ must be finite and ascending");
+    for (int a = 0; a < v; ++a)
+        if (!std::isfinite(hv[a]) || (a && hv[a] < hv[a - 1])) fail(ADC3_EINVAL, "eps_vir must be finite and ascending");
+    if (!(ho[o - 1] < hv[0])) fail(ADC3_EINVAL, "every occupied energy must lie below every virtual energy");
+    if (X > 0) {
+        const size_t mark = ws.mark();
+        double* f = take(ws, 4);
+        k_check_B(B, X, o + v, f, s);
+        unsigned long long hf[3];
+        d2h(hf, f, sizeof(hf), s);
+        double asym, mabs;
+        std::memcpy(&asym, &hf[1], 8);
+        std::memcpy(&mabs, &hf[2], 8);
+        if (hf[0]) fail(ADC3_EINVAL, "B contains non-finite values");
+        if (asym > 1e-12 * std::max(mabs, 1e-300)) fail(ADC3_EINVAL, "B must be symmetric in its orbital indices");
+        ws.release(mark);
+    }
+}
+
+static adc3_opts resolve_opts(const adc3_opts* opts) {
+    adc3_opts o;
+    adc3_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.level != 2 && o.level != 3) fail(ADC3_EINVAL, "opts.level must be 2 or 3");
+    if (o.max_iter < 1) fail(ADC3_EINVAL, "opts.max_iter must be >= 1");
+    if (o.precision != 0) fail(ADC3_EUNSUP, "only FP64 (precision 0) is supported");
+    if (o.precond != 0) fail(ADC3_EUNSUP, "only the Jacobi preconditioner (precond 0) is supported");
+    return o;
+}
+
+static void plan_solve(int nocc, int nvir, int naux, int nroots, const adc3_opts& op, Arena& ws) {
+    g_dry = true;
+    const long long n = nocc + nvir;
+    Blocks B0;
+    B0.X = naux; B0.o = nocc; B0.v = nvir;
+    B0.Boo = take(ws, (long long)naux * nocc * nocc);
+    B0.Bov = take(ws, (long long)naux * nocc * nvir);
+    B0.Bvv = take(ws, (long long)naux * nvir * nvir);
+    (void)n;
+    solve_impl(ws, nullptr, nullptr, B0, nroots, 1.0, 1.0, 1.0, op, nullptr);   // truncation path
+    Arena ws2;
+    ws2.used = 0;
+    solve_impl(ws2, nullptr, nullptr, B0, nroots, 0.0, 0.0, 1.0, op, nullptr); // canonical path
+    ws.peak = std::max(ws.peak, ws2.peak + (size_t)(3 * naux * n * n * sizeof(double)));
+    g_dry = false;
+}
+
+extern "C" size_t adc3_ea_solve_workspace_bytes(int nocc, int nvir, int naux, int nroots, const adc3_opts* opts) {
+    try {
+        check_dims(nocc, nvir, naux);
+        adc3_opts op = resolve_opts(opts);
+        Arena ws;
+        plan_solve(nocc, nvir, naux, nroots, op, ws);
+        return ws.peak + (1 << 20);
+    } catch (...) {
+        g_dry = false;
+        return 0;
+    }
+}
+
+extern "C" int adc3_ea_solve(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir,
+                             int naux, int nroots, double fno_thresh, double naf_thresh, double conv,
+                             const adc3_opts* opts, double* roots_out, adc3_root_report* reports, void* workspace,
+                             size_t ws_bytes, hipStream_t stream) {
+    API_BEGIN
+    check_dims(nocc, nvir, naux);
+    adc3_opts op = resolve_opts(opts);
+    if (!eps_occ || !eps_vir || (!B && naux > 0) || !roots_out || !workspace) fail(ADC3_EINVAL, "NULL pointer argument");
+    const long long N = nvir + (long long)nocc * nvir * nvir;
+    if (nroots < 1 || nroots > N) fail(ADC3_EINVAL, "nroots must be in [1, N]");
+    if (!(conv > 0) || !std::isfinite(conv)) fail(ADC3_EINVAL, "conv must be a positive number");
+    if (std::isnan(fno_thresh) || std::isnan(naf_thresh)) fail(ADC3_EINVAL, "thresholds must not be NaN");
+    Arena ws;
+    ws.base = (char*)workspace;
+    ws.cap = ws_bytes;
+    {
+        Arena plan;
+        plan_solve(nocc, nvir, naux, nroots, op, plan);
+        if (plan.peak > ws_bytes) fail(ADC3_ENOMEM, "workspace too small: need " + std::to_string(plan.peak) + " bytes");
+    }
+    validate_inputs(eps_occ, eps_vir, B, nocc, nvir, naux, stream, ws);
+    Blocks B0;
+    B0.X = naux; B0.o = nocc; B0.v = nvir;
+    B0.Boo = take(ws, (long long)naux * nocc * nocc);
+    B0.Bov = take(ws, (long long)naux * nocc * nvir);
+    B0.Bvv = take(ws, (long long)naux * nvir * nvir);
+    k_split_B(B, naux, nocc, nvir, B0.Boo, B0.Bov, B0.Bvv, stream);
+    SolveOut r = solve_impl(ws, eps_occ, eps_vir, B0, nroots, fno_thresh, naf_thresh, conv, op, stream);
+    HIPCHK(hipStreamSynchronize(stream));
+    for (int k = 0; k < nroots; ++k) {
+        roots_out[k] = r.rep[k].omega;
+        if (reports) reports[k] = r.rep[k];
+    }
+    return r.all_conv ? ADC3_OK : ADC3_WNOCONV;
+    API_END
+}

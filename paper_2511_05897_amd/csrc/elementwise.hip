@@ -1,0 +1,405 @@
+// Elementwise and data-movement kernels (HBM-bound; grid-stride, coalesced writes).
+#include "internal.h"
+
+namespace adc3 {
+
+namespace {
+constexpr int NT = 256;
+inline unsigned nblocks(long long n) {
+    long long b = (n + NT - 1) / NT;
+    if (b > 8192) b = 8192;
+    return (unsigned)(b < 1 ? 1 : b);
+}
+#define GRID_STRIDE(i, n) for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
+
+__global__ void fill_kernel(double* x, long long n, double v) { GRID_STRIDE(i, n) x[i] = v; }
+__global__ void copy_kernel(double* d, const double* s, long long n) { GRID_STRIDE(i, n) d[i] = s[i]; }
+__global__ void axpby_kernel(double* y, const double* x, long long n, double a, double b) {
+    GRID_STRIDE(i, n) y[i] = a * x[i] + (b == 0.0 ? 0.0 : b * y[i]);
+}
+
+struct P4 { int d[4]; int perm[4]; };
+__global__ void permute4_kernel(double* out, const double* in, P4 p, double alpha, double beta) {
+    // output dims
+    long long od[4], is[4];
+    long long st[4];
+    st[3] = 1; st[2] = p.d[3]; st[1] = (long long)p.d[3] * p.d[2]; st[0] = st[1] * p.d[1];
+    for (int k = 0; k < 4; ++k) { od[k] = p.d[p.perm[k]]; is[k] = st[p.perm[k]]; }
+    long long n = od[0] * od[1] * od[2] * od[3];
+    GRID_STRIDE(t, n) {
+        long long r = t;
+        long long i3 = r % od[3]; r /= od[3];
+        long long i2 = r % od[2]; r /= od[2];
+        long long i1 = r % od[1]; r /= od[1];
+        long long i0 = r;
+        double v = alpha * in[i0 * is[0] + i1 * is[1] + i2 * is[2] + i3 * is[3]];
+        out[t] = (beta == 0.0) ? v : v + beta * out[t];
+    }
+}
+
+__global__ void split_B_kernel(const double* B, int X, int o, int v, double* Boo, double* Bov, double* Bvv) {
+    const int n = o + v;
+    long long tot = (long long)X * n * n;
+    GRID_STRIDE(t, tot) {
+        long long Q = t / ((long long)n * n);
+        int r = (int)(t % ((long long)n * n));
+        int p = r / n, q = r % n;
+        double x = B[t];
+        if (p < o && q < o) Boo[(Q * o + p) * o + q] = x;
+        else if (p < o && q >= o) Bov[(Q * o + p) * v + (q - o)] = x;
+        else if (p >= o && q >= o) Bvv[(Q * v + (p - o)) * v + (q - o)] = x;
+    }
+}
+
+__global__ void amp_t_kernel(const double* ovov, const double* eo, const double* ev, int o, int v, double* T) {
+    long long tot = (long long)o * o * v * v;
+    GRID_STRIDE(t, tot) {
+        int b = (int)(t % v); long long r = t / v;
+        int a = (int)(r % v); r /= v;
+        int j = (int)(r % o); int i = (int)(r / o);
+        double g = ovov[(((long long)i * v + a) * o + j) * v + b];
+        T[t] = g / (eo[i] + eo[j] - ev[a] - ev[b]);
+    }
+}
+
+__global__ void div_d2_kernel(double* Y, const double* eo, const double* ev, int o, int v) {
+    long long tot = (long long)o * o * v * v;
+    GRID_STRIDE(t, tot) {
+        int b = (int)(t % v); long long r = t / v;
+        int a = (int)(r % v); r /= v;
+        int j = (int)(r % o); int i = (int)(r / o);
+        Y[t] /= (eo[i] + eo[j] - ev[a] - ev[b]);
+    }
+}
+
+__global__ void div_d1_kernel(double* y, const double* eo, const double* ev, int o, int v) {
+    long long tot = (long long)o * v;
+    GRID_STRIDE(t, tot) {
+        int a = (int)(t % v), i = (int)(t / v);
+        y[t] /= (eo[i] - ev[a]);
+    }
+}
+
+__global__ void comb_t_kernel(double* out, const double* T, long long nblk, int v, double ca, double cb) {
+    long long vv = (long long)v * v, tot = nblk * vv;
+    GRID_STRIDE(t, tot) {
+        long long blk = t / vv;
+        int r = (int)(t % vv), a = r / v, b = r % v;
+        out[t] = ca * T[t] + cb * T[blk * vv + (long long)b * v + a];
+    }
+}
+
+__global__ void copy2d_kernel(double* dst, long long ldd, const double* src, long long lds, long long rows,
+                              long long cols, double a, double b) {
+    long long tot = rows * cols;
+    GRID_STRIDE(t, tot) {
+        long long r = t / cols, c = t % cols;
+        double v = a * src[r * lds + c];
+        dst[r * ldd + c] = (b == 0.0) ? v : v + b * dst[r * ldd + c];
+    }
+}
+
+__global__ void scale_rows_kernel(double* out, const double* in, const double* d, long long rows, long long cols) {
+    long long tot = rows * cols;
+    GRID_STRIDE(t, tot) out[t] = in[t] * d[t / cols];
+}
+
+__global__ void colsign_kernel(double* A, long long lda, int rows, int cols) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    double best = -1.0, sg = 1.0;
+    for (int r = 0; r < rows; ++r) {
+        double x = A[r * lda + c];
+        if (fabs(x) > best) { best = fabs(x); sg = x < 0 ? -1.0 : 1.0; }
+    }
+    if (sg < 0)
+        for (int r = 0; r < rows; ++r) A[r * lda + c] = -A[r * lda + c];
+}
+
+__global__ void residual_kernel(double* R, const double* AX, const double* X, const double* th, int nk, long long n) {
+    long long tot = (long long)nk * n;
+    GRID_STRIDE(t, tot) R[t] = AX[t] - th[t / n] * X[t];
+}
+
+__global__ void precond_kernel(double* T, const double* R, const double* D, const double* th, int nk, long long n) {
+    long long tot = (long long)nk * n;
+    GRID_STRIDE(t, tot) {
+        double den = D[t % n] - th[t / n];
+        if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+        T[t] = R[t] / den;
+    }
+}
+
+__global__ void scale_vec_kernel(double* x, long long n, const double* f) {
+    double a = f[0];
+    GRID_STRIDE(t, n) x[t] *= a;
+}
+
+__global__ void check_B_kernel(const double* B, int X, int n, unsigned long long* out) {
+    // out[0]: nonfinite flag, out[1]: max asym bits, out[2]: max |B| bits (non-negative doubles order as ints)
+    long long tot = (long long)X * n * n;
+    double masym = 0.0, mabs = 0.0;
+    unsigned long long bad = 0;
+    GRID_STRIDE(t, tot) {
+        long long Q = t / ((long long)n * n);
+        int r = (int)(t % ((long long)n * n)), p = r / n, q = r % n;
+        double x = B[t];
+        if (!isfinite(x)) bad = 1;
+        mabs = fmax(mabs, fabs(x));
+        if (p < q) masym = fmax(masym, fabs(x - B[Q * n * n + (long long)q * n + p]));
+    }
+    if (bad) atomicOr(&out[0], 1ull);
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(masym));
+    atomicMax(&out[2], (unsigned long long)__double_as_longlong(mabs));
+}
+
+__global__ void z_to_x_kernel(const double* z, double* x, double* xt, long long nblk, int v) {
+    const double is3 = 0.57735026918962576451;  // 1/sqrt(3)
+    long long vv = (long long)v * v, tot = nblk * vv;
+    GRID_STRIDE(t, tot) {
+        long long blk = t / vv;
+        int r = (int)(t % vv), a = r / v, b = r % v;
+        double zab = z[t], zba = z[blk * vv + (long long)b * v + a];
+        double s = 0.5 * (zab + zba), an = 0.5 * (zab - zba);
+        double xab = s + an * is3, xba = s - an * is3;
+        if (x) x[t] = xab;
+        if (xt) xt[t] = 2.0 * xab - xba;
+    }
+}
+
+__global__ void d_to_z_add_kernel(double* acc, const double* d, long long nblk, int v) {
+    const double s3 = 1.73205080756887729353;
+    long long vv = (long long)v * v, tot = nblk * vv;
+    GRID_STRIDE(t, tot) {
+        long long blk = t / vv;
+        int r = (int)(t % vv), a = r / v, b = r % v;
+        double dab = d[t], dba = d[blk * vv + (long long)b * v + a];
+        acc[t] += 0.5 * (dab + dba) + s3 * 0.5 * (dab - dba);
+    }
+}
+
+__global__ void k0_add_kernel(double* s2, const double* z, const double* eo, const double* ev, int o, int v,
+                              int nvec, long long ld) {
+    long long per = (long long)o * v * v, tot = per * nvec;
+    GRID_STRIDE(t, tot) {
+        long long vec = t / per, r = t % per;
+        int b = (int)(r % v); long long q = r / v;
+        int a = (int)(q % v); int i = (int)(q / v);
+        s2[vec * ld + r] += (ev[a] + ev[b] - eo[i]) * z[vec * ld + r];
+    }
+}
+
+__global__ void symmetrize_kernel(double* A, int n) {
+    long long tot = (long long)n * n;
+    GRID_STRIDE(t, tot) {
+        int i = (int)(t / n), j = (int)(t % n);
+        if (i < j) {
+            double m = 0.5 * (A[t] + A[(long long)j * n + i]);
+            A[t] = m;
+            A[(long long)j * n + i] = m;
+        }
+    }
+}
+
+__global__ void add_diag_kernel(double* A, const double* d, int n) {
+    GRID_STRIDE(i, n) A[(long long)i * n + i] += d[i];
+}
+
+// diag[0..v) = diag(M11); diag[v + (i*v + a)*v + b] = K0 + (level>=3) K1 diagonal in z coordinates
+__global__ void diag_adc_kernel(double* diag, const double* M11, const double* eo, const double* ev,
+                                const double* Bvv, const double* oovv, const double* ovov, int o, int v,
+                                int X, int level) {
+    const double s3 = 1.73205080756887729353;
+    long long vv = (long long)v * v;
+    GRID_STRIDE(t, vv) {
+        int a = (int)(t / v), b = (int)(t % v);
+        if (b == 0) diag[a] = M11[(long long)a * v + a];
+        double aabb = 0.0, abab = 0.0;
+        if (level >= 3) {
+            for (int Q = 0; Q < X; ++Q) {
+                const double* BQ = Bvv + (long long)Q * vv;
+                aabb += BQ[(long long)a * v + a] * BQ[(long long)b * v + b];
+                double x = BQ[(long long)a * v + b];
+                abab += x * x;
+            }
+        }
+        const double al = 0.5 + 0.5 * s3, be = 0.5 - 0.5 * s3;
+        const double ga = 0.5 + 0.5 / s3, de = 0.5 - 0.5 / s3;
+        for (int i = 0; i < o; ++i) {
+            double d = ev[a] + ev[b] - eo[i];
+            if (level >= 3) {
+                double aaii = oovv[(((long long)i * o + i) * v + a) * v + a];
+                double bbii = oovv[(((long long)i * o + i) * v + b) * v + b];
+                double aiia = ovov[(((long long)i * v + a) * o + i) * v + a];
+                double biib = ovov[(((long long)i * v + b) * o + i) * v + b];
+                if (a == b) {
+                    d += aabb - 2.0 * aaii + aiia;
+                } else {
+                    double kabab = aabb - bbii - aaii + 2.0 * biib;
+                    double kbaba = aabb - aaii - bbii + 2.0 * aiia;
+                    double kabba = abab - biib;
+                    double kbaab = abab - aiia;
+                    d += al * ga * kabab + al * de * kabba + be * ga * kbaab + be * de * kbaba;
+                }
+            }
+            diag[v + ((long long)i * v + a) * v + b] = d;
+        }
+    }
+}
+}  // namespace
+
+void k_fill(double* x, long long n, double v, hipStream_t s) {
+    if (g_dry) return;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(fill_kernel, dim3(nblocks(n)), dim3(NT), 0, s, x, n, v);
+    LAUNCHCHK();
+}
+void k_copy(double* d, const double* src, long long n, hipStream_t s) {
+    if (g_dry) return;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(copy_kernel, dim3(nblocks(n)), dim3(NT), 0, s, d, src, n);
+    LAUNCHCHK();
+}
+void k_axpby(double* y, const double* x, long long n, double a, double b, hipStream_t s) {
+    if (g_dry) return;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(axpby_kernel, dim3(nblocks(n)), dim3(NT), 0, s, y, x, n, a, b);
+    LAUNCHCHK();
+}
+void k_permute4(double* out, const double* in, const int din[4], const int perm[4], double alpha, double beta,
+                hipStream_t s) {
+    if (g_dry) return;
+    P4 p;
+    long long n = 1;
+    for (int k = 0; k < 4; ++k) { p.d[k] = din[k]; p.perm[k] = perm[k]; n *= din[k]; }
+    if (n <= 0) return;
+    hipLaunchKernelGGL(permute4_kernel, dim3(nblocks(n)), dim3(NT), 0, s, out, in, p, alpha, beta);
+    LAUNCHCHK();
+}
+void k_split_B(const double* B, int X, int o, int v, double* Boo, double* Bov, double* Bvv, hipStream_t s) {
+    if (g_dry) return;
+    long long n = (long long)X * (o + v) * (o + v);
+    if (n <= 0) return;
+    hipLaunchKernelGGL(split_B_kernel, dim3(nblocks(n)), dim3(NT), 0, s, B, X, o, v, Boo, Bov, Bvv);
+    LAUNCHCHK();
+}
+void k_amp_t(const double* ovov, const double* eo, const double* ev, int o, int v, double* T, hipStream_t s) {
+    if (g_dry) return;
+    long long n = (long long)o * o * v * v;
+    hipLaunchKernelGGL(amp_t_kernel, dim3(nblocks(n)), dim3(NT), 0, s, ovov, eo, ev, o, v, T);
+    LAUNCHCHK();
+}
+void k_div_d2(double* Y, const double* eo, const double* ev, int o, int v, hipStream_t s) {
+    if (g_dry) return;
+    long long n = (long long)o * o * v * v;
+    hipLaunchKernelGGL(div_d2_kernel, dim3(nblocks(n)), dim3(NT), 0, s, Y, eo, ev, o, v);
+    LAUNCHCHK();
+}
+void k_div_d1(double* y, const double* eo, const double* ev, int o, int v, hipStream_t s) {
+    if (g_dry) return;
+    long long n = (long long)o * v;
+    hipLaunchKernelGGL(div_d1_kernel, dim3(nblocks(n)), dim3(NT), 0, s, y, eo, ev, o, v);
+    LAUNCHCHK();
+}
+void k_comb_t(double* out, const double* T, long long nblk, int v, double a, double b, hipStream_t s) {
+    if (g_dry) return;
+    long long n = nblk * v * v;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(comb_t_kernel, dim3(nblocks(n)), dim3(NT), 0, s, out, T, nblk, v, a, b);
+    LAUNCHCHK();
+}
+void k_copy2d(double* dst, long long ldd, const double* src, long long lds, long long rows, long long cols,
+              double a, double b, hipStream_t s) {
+    if (g_dry) return;
+    long long n = rows * cols;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(copy2d_kernel, dim3(nblocks(n)), dim3(NT), 0, s, dst, ldd, src, lds, rows, cols, a, b);
+    LAUNCHCHK();
+}
+void k_scale_rows(double* out, const double* in, const double* d, long long rows, long long cols, hipStream_t s) {
+    if (g_dry) return;
+    long long n = rows * cols;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(scale_rows_kernel, dim3(nblocks(n)), dim3(NT), 0, s, out, in, d, rows, cols);
+    LAUNCHCHK();
+}
+void k_colsign(double* A, long long lda, int rows, int cols, hipStream_t s) {
+    if (g_dry) return;
+    if (rows <= 0 || cols <= 0) return;
+    hipLaunchKernelGGL(colsign_kernel, dim3((cols + 255) / 256), dim3(256), 0, s, A, lda, rows, cols);
+    LAUNCHCHK();
+}
+void k_residual(double* R, const double* AX, const double* X, const double* th, int nk, long long n, hipStream_t s) {
+    if (g_dry) return;
+    long long t = (long long)nk * n;
+    if (t <= 0) return;
+    hipLaunchKernelGGL(residual_kernel, dim3(nblocks(t)), dim3(NT), 0, s, R, AX, X, th, nk, n);
+    LAUNCHCHK();
+}
+void k_precond(double* T, const double* R, const double* D, const double* th, int nk, long long n, hipStream_t s) {
+    if (g_dry) return;
+    long long t = (long long)nk * n;
+    if (t <= 0) return;
+    hipLaunchKernelGGL(precond_kernel, dim3(nblocks(t)), dim3(NT), 0, s, T, R, D, th, nk, n);
+    LAUNCHCHK();
+}
+void k_scale_vec(double* x, long long n, const double* f, hipStream_t s) {
+    if (g_dry) return;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(scale_vec_kernel, dim3(nblocks(n)), dim3(NT), 0, s, x, n, f);
+    LAUNCHCHK();
+}
+void k_check_B(const double* B, int X, int n, double* flags, hipStream_t s) {
+    if (g_dry) return;
+    HIPCHK(hipMemsetAsync(flags, 0, 3 * sizeof(double), s));
+    long long t = (long long)X * n * n;
+    if (t <= 0) return;
+    hipLaunchKernelGGL(check_B_kernel, dim3(nblocks(t)), dim3(NT), 0, s, B, X, n, (unsigned long long*)flags);
+    LAUNCHCHK();
+}
+void k_z_to_x(const double* z, double* x, double* xt, long long nblk, int v, hipStream_t s) {
+    if (g_dry) return;
+    long long n = nblk * v * v;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(z_to_x_kernel, dim3(nblocks(n)), dim3(NT), 0, s, z, x, xt, nblk, v);
+    LAUNCHCHK();
+}
+void k_d_to_z_add(double* acc, const double* d, long long nblk, int v, hipStream_t s) {
+    if (g_dry) return;
+    long long n = nblk * v * v;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(d_to_z_add_kernel, dim3(nblocks(n)), dim3(NT), 0, s, acc, d, nblk, v);
+    LAUNCHCHK();
+}
+void k_k0_add(double* s2, const double* z, const double* eo, const double* ev, int o, int v, int nvec,
+              long long ld, hipStream_t s) {
+    if (g_dry) return;
+    long long n = (long long)o * v * v * nvec;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k0_add_kernel, dim3(nblocks(n)), dim3(NT), 0, s, s2, z, eo, ev, o, v, nvec, ld);
+    LAUNCHCHK();
+}
+void k_symmetrize(double* A, int n, hipStream_t s) {
+    if (g_dry) return;
+    long long nn = (long long)n * n;
+    if (nn <= 0) return;
+    hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks(nn)), dim3(NT), 0, s, A, n);
+    LAUNCHCHK();
+}
+void k_add_diag(double* A, const double* d, int n, hipStream_t s) {
+    if (g_dry) return;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(add_diag_kernel, dim3(nblocks(n)), dim3(NT), 0, s, A, d, n);
+    LAUNCHCHK();
+}
+void k_diag_adc(double* diag, const double* M11, const double* eo, const double* ev, const double* Bvv,
+                const double* oovv, const double* ovov, int o, int v, int X, int level, hipStream_t s) {
+    if (g_dry) return;
+    long long n = (long long)v * v;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(diag_adc_kernel, dim3(nblocks(n)), dim3(NT), 0, s, diag, M11, eo, ev, Bvv, oovv, ovov, o,
+                       v, X, level);
+    LAUNCHCHK();
+}
+
+}  // namespace adc3

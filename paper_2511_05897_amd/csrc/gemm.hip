@@ -1,0 +1,133 @@
+// FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4f64), strided and batched.
+//
+// One workgroup (4 wave64) computes a 64x64 tile of C; each wave a 32x32 quarter as
+// 2x2 MFMA 16x16 blocks.  A and B tiles (64x16, 16x64) are staged through LDS,
+// double buffered: the next K-slab is fetched into registers while the current one
+// feeds the matrix cores.  Global loads are coalesced along whichever operand
+// dimension is contiguous.
+//
+// MFMA f64 16x16x4 operand layout (lane l of a wave64):
+//   A frag: A[row = l%16][k = l/16]   B frag: B[k = l/16][col = l%16]
+//   D     : D[row = l/16 + 4*r][col = l%16] in accumulator element r = 0..3
+#include "internal.h"
+
+namespace adc3 {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+namespace {
+constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
+constexpr int PER = BM * BK / NT;  // 4 elements of A (and of B) per thread per slab
+
+__global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
+    __shared__ double As[2][BM][BK + 1];
+    __shared__ double Bs[2][BK][BN + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int bz = blockIdx.z;
+    const int b0 = bz % g.nb0, b1 = bz / g.nb0;
+    const double* __restrict__ A = g.A + b0 * g.bA0 + b1 * g.bA1;
+    const double* __restrict__ B = g.B + b0 * g.bB0 + b1 * g.bB1;
+    double* __restrict__ C = g.C + b0 * g.bC0 + b1 * g.bC1;
+    const long long m0 = (long long)blockIdx.y * BM, n0 = (long long)blockIdx.x * BN;
+    const int wr = wave >> 1, wc = wave & 1;
+    const bool a_kc = (g.sAk == 1), b_nc = (g.sBn == 1);
+
+    // per-thread slab coordinates (fixed for the whole K loop)
+    int ar[PER], ak[PER], bk[PER], bn[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        int idx = tid + NT * p;
+        if (a_kc) { ar[p] = idx / BK; ak[p] = idx % BK; } else { ar[p] = idx % BM; ak[p] = idx / BM; }
+        if (b_nc) { bn[p] = idx % BN; bk[p] = idx / BN; } else { bk[p] = idx % BK; bn[p] = idx / BK; }
+    }
+    double ra[PER], rb[PER];
+    auto fetch = [&](long long k0) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            long long m = m0 + ar[p], k = k0 + ak[p];
+            ra[p] = (m < g.M && k < g.K) ? A[m * g.sAm + k * g.sAk] : 0.0;
+            long long kb = k0 + bk[p], n = n0 + bn[p];
+            rb[p] = (kb < g.K && n < g.N) ? B[kb * g.sBk + n * g.sBn] : 0.0;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            As[buf][ar[p]][ak[p]] = ra[p];
+            Bs[buf][bk[p]][bn[p]] = rb[p];
+        }
+    };
+
+    d4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    const int nslab = (g.K + BK - 1) / BK;
+    if (nslab > 0) {
+        fetch(0);
+        stash(0);
+    }
+    __syncthreads();
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int s = 0; s < nslab; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nslab) fetch((long long)(s + 1) * BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            double a0 = As[buf][wr * 32 + lr][kk + lk];
+            double a1 = As[buf][wr * 32 + 16 + lr][kk + lk];
+            double c0 = Bs[buf][kk + lk][wc * 32 + lr];
+            double c1 = Bs[buf][kk + lk][wc * 32 + 16 + lr];
+            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, c0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, c1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, c0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, c1, acc[1][1], 0, 0, 0);
+        }
+        if (s + 1 < nslab) stash(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                long long row = m0 + wr * 32 + i * 16 + lk + 4 * r;
+                long long col = n0 + wc * 32 + j * 16 + lr;
+                if (row < g.M && col < g.N) {
+                    double* c = C + row * g.sCm + col * g.sCn;
+                    double v = g.alpha * acc[i][j][r];
+                    *c = (g.beta == 0.0) ? v : v + g.beta * (*c);
+                }
+            }
+}
+}  // namespace
+
+void gemm(const Gemm& g, hipStream_t s) {
+    if (g_dry) return;
+    if (g.M <= 0 || g.N <= 0) return;
+    long long nb = (long long)g.nb0 * g.nb1;
+    if (nb <= 0) return;
+    // K <= 0 is valid: the kernel then writes C = beta*C.
+    if (nb > 65535) fail(-1, "gemm: too many batches");
+    dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, (unsigned)nb);
+    if (grid.y > 65535) fail(-1, "gemm: M too large");
+    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(NT), 0, s, g);
+    LAUNCHCHK();
+}
+
+void gemm_rm(int M, int N, int K, double alpha, const double* A, long long lda, bool transA,
+             const double* B, long long ldb, bool transB, double beta, double* C, long long ldc,
+             hipStream_t s) {
+    Gemm g;
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.sAm = transA ? 1 : lda; g.sAk = transA ? lda : 1;
+    g.B = B; g.sBk = transB ? 1 : ldb; g.sBn = transB ? ldb : 1;
+    g.C = C; g.sCm = ldc; g.sCn = 1;
+    g.alpha = alpha; g.beta = beta;
+    gemm(g, s);
+}
+
+}  // namespace adc3

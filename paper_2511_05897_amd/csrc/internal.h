@@ -1,0 +1,138 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace adc3 {
+
+// dry run: allocations are counted, no device work is issued (workspace planning)
+extern thread_local bool g_dry;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error {
+    int status;
+    std::string msg;
+};
+void set_error(const std::string& msg);
+[[noreturn]] void fail(int status, const std::string& msg);
+
+#define HIPCHK(call)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            ::adc3::fail(-3, std::string(#call) + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+#define LAUNCHCHK() HIPCHK(hipGetLastError())
+
+// ---------------------------------------------------------------------------
+// bump allocator over the caller's workspace; base == nullptr only counts bytes
+// ---------------------------------------------------------------------------
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    size_t peak = 0;
+    template <class T>
+    T* take(size_t count) {
+        size_t off = (used + 255) & ~size_t(255);
+        size_t bytes = count * sizeof(T);
+        used = off + bytes;
+        if (used > peak) peak = used;
+        if (base == nullptr) return nullptr;
+        if (used > cap) fail(-2, "workspace too small: need at least " + std::to_string(used) + " bytes");
+        return reinterpret_cast<T*>(base + off);
+    }
+    size_t mark() const { return used; }
+    void release(size_t m) { used = m; }
+};
+
+// ---------------------------------------------------------------------------
+// GEMM:  C(m,n) = alpha * sum_k A(m,k) B(k,n) + beta * C(m,n)
+// A(m,k) = A[bA0*b0 + bA1*b1 + m*sAm + k*sAk], likewise B, C; batch index
+// b = b0 + nb0*b1 over nbatch = nb0*nb1.
+// ---------------------------------------------------------------------------
+struct Gemm {
+    int M = 0, N = 0, K = 0;
+    const double* A = nullptr; long long sAm = 0, sAk = 0, bA0 = 0, bA1 = 0;
+    const double* B = nullptr; long long sBk = 0, sBn = 0, bB0 = 0, bB1 = 0;
+    double* C = nullptr; long long sCm = 0, sCn = 0, bC0 = 0, bC1 = 0;
+    int nb0 = 1, nb1 = 1;
+    double alpha = 1.0, beta = 0.0;
+};
+void gemm(const Gemm& g, hipStream_t s);
+// row-major helpers: C[M,N] (ldc) = alpha*op(A)op(B) + beta*C
+void gemm_rm(int M, int N, int K, double alpha, const double* A, long long lda, bool transA,
+             const double* B, long long ldb, bool transB, double beta, double* C, long long ldc,
+             hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// elementwise / data movement
+// ---------------------------------------------------------------------------
+void k_fill(double* x, long long n, double v, hipStream_t s);
+void k_copy(double* dst, const double* src, long long n, hipStream_t s);
+void k_axpby(double* y, const double* x, long long n, double a, double b, hipStream_t s);  // y = a*x + b*y
+// out[d0][d1][d2][d3] with out index permutation: out[i0][i1][i2][i3] = alpha*in[...] + beta*out
+// perm[k] = which input axis becomes output axis k; in dims din[4]
+void k_permute4(double* out, const double* in, const int din[4], const int perm[4], double alpha,
+                double beta, hipStream_t s);
+void k_split_B(const double* B, int X, int o, int v, double* Boo, double* Bov, double* Bvv, hipStream_t s);
+// T[i][j][a][b] = ovov[i][a][j][b] / (eo_i + eo_j - ev_a - ev_b)
+void k_amp_t(const double* ovov, const double* eo, const double* ev, int o, int v, double* T, hipStream_t s);
+// Y[i][j][a][b] /= (eo_i + eo_j - ev_a - ev_b)
+void k_div_d2(double* Y, const double* eo, const double* ev, int o, int v, hipStream_t s);
+void k_div_d1(double* y, const double* eo, const double* ev, int o, int v, hipStream_t s);
+// out = a*T + b*T^(ab swapped), T[n][v][v] blocks
+void k_comb_t(double* out, const double* T, long long nblk, int v, double a, double b, hipStream_t s);
+// dst[r*ldd + c] = a*src[r*lds + c] + b*dst[r*ldd + c]
+void k_copy2d(double* dst, long long ldd, const double* src, long long lds, long long rows, long long cols,
+              double a, double b, hipStream_t s);
+void k_scale_rows(double* out, const double* in, const double* d, long long rows, long long cols, hipStream_t s);
+// make the largest-|.| entry of each column of A[rows][cols] (row stride lda) positive
+void k_colsign(double* A, long long lda, int rows, int cols, hipStream_t s);
+// R[k][i] = AX[k][i] - theta[k] X[k][i]
+void k_residual(double* R, const double* AX, const double* X, const double* theta, int nk, long long n, hipStream_t s);
+// T[k][i] = R[k][i] / (D[i] - theta[k]) with |D - theta| >= floor
+void k_precond(double* T, const double* R, const double* D, const double* theta, int nk, long long n, hipStream_t s);
+void k_scale_vec(double* x, long long n, const double* factor_dev, hipStream_t s);   // x *= factor[0]
+// flags[0] = 1 if any non-finite; flags[1] = max |B_Qpq - B_Qqp|; flags[2] = max |B|
+void k_check_B(const double* B, int X, int n, double* flags, hipStream_t s);
+// z -> x = z_S + z_A/sqrt3 and xt = 2x - x^T  (blocks of v*v)
+void k_z_to_x(const double* z, double* x, double* xt, long long nblk, int v, hipStream_t s);
+// acc += S(d) + sqrt3*A(d)
+void k_d_to_z_add(double* acc, const double* d, long long nblk, int v, hipStream_t s);
+// sigma2 += K0 * z, K0[i][a][b] = ev_a + ev_b - eo_i;  z/sigma2 with vector stride ld
+void k_k0_add(double* s2, const double* z, const double* eo, const double* ev, int o, int v, int nvec,
+              long long ld, hipStream_t s);
+void k_symmetrize(double* A, int n, hipStream_t s);   // A = (A + A^T)/2
+void k_add_diag(double* A, const double* d, int n, hipStream_t s);
+void k_diag_adc(double* diag, const double* M11, const double* eo, const double* ev, const double* Bvv,
+                const double* oovv, const double* ovov, int o, int v, int X, int level, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// reductions (deterministic, FP64)
+// ---------------------------------------------------------------------------
+// G[p][q] = sum_i X[p*ldx + i] * Y[q*ldy + i], p < np, q < nq  (G row stride ldg)
+void k_dots(const double* X, long long ldx, int np, const double* Y, long long ldy, int nq, long long n,
+            double* G, int ldg, double* partial, hipStream_t s);
+size_t dots_partial_elems(int np, int nq, long long n);
+// Y[q][i] = beta*Y[q][i] + alpha * sum_p C[p*ldc + q] * X[p][i]    (linear combination of rows)
+void k_lincomb(double* Y, long long ldy, int nq, const double* X, long long ldx, int np, const double* C,
+               int ldc, long long n, double alpha, double beta, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// symmetric eigensolvers (Jacobi, FP64)
+// ---------------------------------------------------------------------------
+// A[n][n] (destroyed) -> w[n] ascending, V[n][n] columns eigenvectors (row-major V[i*n+k])
+void eig_small(double* A, int n, double* w, double* V, hipStream_t s);   // n <= 128, one workgroup
+void eig_large(double* A, int n, double* w, double* V, double* scratch, hipStream_t s);
+size_t eig_large_scratch(int n);
+// reorder eigenpairs descending (desc=1) or ascending and fix signs (largest |.| positive)
+void k_sort_eig(double* w, double* V, int n, int desc, double* wtmp, double* Vtmp, hipStream_t s);
+
+}  // namespace adc3

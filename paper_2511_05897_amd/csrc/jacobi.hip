@@ -1,0 +1,279 @@
+// Symmetric eigensolvers in FP64: cyclic two-sided Jacobi with the round-robin
+// ("circle method") ordering, so that every round rotates n/2 disjoint index pairs
+// in parallel.  Used for the Rayleigh-Ritz subspace matrix (small, one workgroup,
+// LDS resident), the natural-orbital and recanonicalisation matrices and the
+// natural-auxiliary-function matrix (large, one launch pair per round).
+#include "internal.h"
+#include <cmath>
+
+namespace adc3 {
+
+namespace {
+
+__device__ inline void pair_of(int r, int k, int np, int& p, int& q) {
+    // players 0..np-1 (np even); player 0 fixed, others rotate by r
+    auto pos = [&](int i) { return i == 0 ? 0 : 1 + (i - 1 + r) % (np - 1); };
+    p = pos(k);
+    q = pos(np - 1 - k);
+    if (p > q) { int t = p; p = q; q = t; }
+}
+
+__device__ inline void rot_of(double app, double aqq, double apq, double& c, double& s) {
+    if (apq == 0.0) { c = 1.0; s = 0.0; return; }
+    double th = (aqq - app) / (2.0 * apq);
+    double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+    c = 1.0 / sqrt(t * t + 1.0);
+    s = t * c;
+}
+
+// ---------------- small: one workgroup, matrix and vectors in LDS ----------------
+constexpr int SMALL_MAX = 96;
+constexpr int SNT = 1024;
+
+__global__ __launch_bounds__(SNT) void jacobi_small_kernel(double* Ag, int n, double* w, double* Vg) {
+    extern __shared__ double sm[];
+    const int ld = n + 1;
+    double* A = sm;
+    double* V = sm + (size_t)n * ld;
+    __shared__ double cs[SMALL_MAX / 2 + 1], sn[SMALL_MAX / 2 + 1];
+    __shared__ int pp[SMALL_MAX / 2 + 1], qq[SMALL_MAX / 2 + 1];
+    __shared__ double red[SNT / 64];
+    __shared__ double red2[SNT / 64];
+    const int tid = threadIdx.x;
+    for (int t = tid; t < n * n; t += SNT) {
+        int i = t / n, j = t % n;
+        A[i * ld + j] = Ag[t];
+        V[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int np = n + (n & 1);
+    const int npair = np / 2;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int t = tid; t < n * n; t += SNT) {
+            int i = t / n, j = t % n;
+            double a = A[i * ld + j];
+            tot += a * a;
+            if (i != j) off += a * a;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_down(off, o, 64);
+            tot += __shfl_down(tot, o, 64);
+        }
+        if ((tid & 63) == 0) { red[tid >> 6] = off; red2[tid >> 6] = tot; }
+        __syncthreads();
+        double offs = 0.0, tots = 0.0;
+        for (int k = 0; k < SNT / 64; ++k) { offs += red[k]; tots += red2[k]; }
+        __syncthreads();
+        if (offs <= 1e-30 * tots || offs == 0.0) break;
+        for (int r = 0; r < np - 1; ++r) {
+            if (tid < npair) {
+                int p, q;
+                pair_of(r, tid, np, p, q);
+                double c = 1.0, s = 0.0;
+                if (q < n) rot_of(A[p * ld + p], A[q * ld + q], A[p * ld + q], c, s);
+                pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
+            }
+            __syncthreads();
+            for (int t = tid; t < npair * n; t += SNT) {
+                int k = t / n, j = t % n;
+                int p = pp[k], q = qq[k];
+                if (q >= n) continue;
+                double c = cs[k], s = sn[k];
+                double apj = A[p * ld + j], aqj = A[q * ld + j];
+                A[p * ld + j] = c * apj - s * aqj;
+                A[q * ld + j] = s * apj + c * aqj;
+            }
+            __syncthreads();
+            for (int t = tid; t < npair * n; t += SNT) {
+                int k = t / n, i = t % n;
+                int p = pp[k], q = qq[k];
+                if (q >= n) continue;
+                double c = cs[k], s = sn[k];
+                double aip = A[i * ld + p], aiq = A[i * ld + q];
+                A[i * ld + p] = c * aip - s * aiq;
+                A[i * ld + q] = s * aip + c * aiq;
+                double vip = V[i * ld + p], viq = V[i * ld + q];
+                V[i * ld + p] = c * vip - s * viq;
+                V[i * ld + q] = s * vip + c * viq;
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = tid; t < n * n; t += SNT) {
+        int i = t / n, j = t % n;
+        Vg[t] = V[i * ld + j];
+    }
+    for (int i = tid; i < n; i += SNT) w[i] = A[i * ld + i];
+}
+
+// ---------------- large: global memory, one launch pair per round ----------------
+__global__ void jacobi_angles_kernel(const double* A, int n, int np, int r, double* cs) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np / 2) return;
+    int p, q;
+    pair_of(r, k, np, p, q);
+    double c = 1.0, s = 0.0;
+    if (q < n) rot_of(A[(long long)p * n + p], A[(long long)q * n + q], A[(long long)p * n + q], c, s);
+    cs[2 * k] = c;
+    cs[2 * k + 1] = s;
+}
+
+// block-pair update A[P,P'] <- J_P^T A[P,P'] J_P'  and  V[:,P] <- V[:,P] J_P
+__global__ void jacobi_rotate_kernel(double* A, double* V, int n, int np, int r, const double* cs) {
+    const int npair = np / 2;
+    long long nblk = (long long)npair * npair;
+    long long nv = (long long)n * npair;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nblk + nv;
+         t += (long long)gridDim.x * blockDim.x) {
+        if (t < nblk) {
+            int k1 = (int)(t / npair), k2 = (int)(t % npair);
+            int p1, q1, p2, q2;
+            pair_of(r, k1, np, p1, q1);
+            pair_of(r, k2, np, p2, q2);
+            double c1 = cs[2 * k1], s1 = cs[2 * k1 + 1], c2 = cs[2 * k2], s2 = cs[2 * k2 + 1];
+            bool v1 = q1 < n, v2 = q2 < n;
+            // rows p1 (and q1 if valid), columns p2 (and q2 if valid)
+            double a = A[(long long)p1 * n + p2];
+            double b = v2 ? A[(long long)p1 * n + q2] : 0.0;
+            double c = v1 ? A[(long long)q1 * n + p2] : 0.0;
+            double d = (v1 && v2) ? A[(long long)q1 * n + q2] : 0.0;
+            // rows: [p;q] <- [c1 -s1; s1 c1] [p;q]
+            double ra = c1 * a - s1 * c, rb = c1 * b - s1 * d;
+            double rc = s1 * a + c1 * c, rd = s1 * b + c1 * d;
+            // cols: [p q] <- [p q] [c2 s2; -s2 c2]
+            double na = c2 * ra - s2 * rb, nb = s2 * ra + c2 * rb;
+            double nc = c2 * rc - s2 * rd, nd = s2 * rc + c2 * rd;
+            A[(long long)p1 * n + p2] = na;
+            if (v2) A[(long long)p1 * n + q2] = nb;
+            if (v1) A[(long long)q1 * n + p2] = nc;
+            if (v1 && v2) A[(long long)q1 * n + q2] = nd;
+        } else {
+            long long u = t - nblk;
+            int k = (int)(u / n), i = (int)(u % n);
+            int p, q;
+            pair_of(r, k, np, p, q);
+            if (q >= n) continue;
+            double c = cs[2 * k], s = cs[2 * k + 1];
+            double vip = V[(long long)i * n + p], viq = V[(long long)i * n + q];
+            V[(long long)i * n + p] = c * vip - s * viq;
+            V[(long long)i * n + q] = s * vip + c * viq;
+        }
+    }
+}
+
+__global__ void offnorm_kernel(const double* A, int n, double* out) {
+    __shared__ double r1[16], r2[16];
+    double off = 0.0, tot = 0.0;
+    long long nn = (long long)n * n;
+    for (long long t = threadIdx.x; t < nn; t += blockDim.x) {
+        double a = A[t];
+        tot += a * a;
+        if (t / n != t % n) off += a * a;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        off += __shfl_down(off, o, 64);
+        tot += __shfl_down(tot, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) { r1[threadIdx.x >> 6] = off; r2[threadIdx.x >> 6] = tot; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { a += r1[k]; b += r2[k]; }
+        out[0] = a;
+        out[1] = b;
+    }
+}
+
+__global__ void eye_kernel(double* V, int n) {
+    long long nn = (long long)n * n;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nn; t += (long long)gridDim.x * blockDim.x)
+        V[t] = (t / n == t % n) ? 1.0 : 0.0;
+}
+
+__global__ void diag_out_kernel(const double* A, int n, double* w) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w[i] = A[(long long)i * n + i];
+}
+
+// ascending (desc=0) or descending (desc=1) order; ties by index; sign: largest |.| of
+// each column positive (first index on ties)
+__global__ void sort_eig_kernel(double* w, double* V, int n, int desc, double* wtmp, double* Vtmp) {
+    // rank
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double wi = w[i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            double wj = w[j];
+            bool before = desc ? (wj > wi || (wj == wi && j < i)) : (wj < wi || (wj == wi && j < i));
+            rank += before;
+        }
+        wtmp[rank] = wi;
+        // copy column i to column rank with sign fix
+        double best = -1.0, sgn = 1.0;
+        for (int r = 0; r < n; ++r) {
+            double x = V[(long long)r * n + i];
+            if (fabs(x) > best) { best = fabs(x); sgn = x < 0 ? -1.0 : 1.0; }
+        }
+        for (int r = 0; r < n; ++r) Vtmp[(long long)r * n + rank] = sgn * V[(long long)r * n + i];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = wtmp[i];
+    for (long long t = threadIdx.x; t < (long long)n * n; t += blockDim.x) V[t] = Vtmp[t];
+}
+}  // namespace
+
+void eig_small(double* A, int n, double* w, double* V, hipStream_t s) {
+    if (g_dry) return;
+    if (n <= 0) return;
+    if (n > SMALL_MAX) fail(-1, "eig_small: n too large");
+    size_t lds = 2 * (size_t)n * (n + 1) * sizeof(double);
+    static bool attr_set = false;
+    if (!attr_set) {
+        HIPCHK(hipFuncSetAttribute((const void*)jacobi_small_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(2 * SMALL_MAX * (SMALL_MAX + 1) * sizeof(double))));
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(jacobi_small_kernel, dim3(1), dim3(SNT), lds, s, A, n, w, V);
+    LAUNCHCHK();
+}
+
+size_t eig_large_scratch(int n) { return (size_t)(n + 2) + 4; }
+
+void eig_large(double* A, int n, double* w, double* V, double* scratch, hipStream_t s) {
+    if (g_dry) return;
+    if (n <= 0) return;
+    if (n <= SMALL_MAX) { eig_small(A, n, w, V, s); return; }
+    const int np = n + (n & 1);
+    double* cs = scratch;            // np doubles
+    double* nrm = scratch + np;      // 2 doubles
+    hipLaunchKernelGGL(eye_kernel, dim3(256), dim3(256), 0, s, V, n);
+    LAUNCHCHK();
+    long long work = (long long)(np / 2) * (np / 2) + (long long)n * (np / 2);
+    unsigned gb = (unsigned)std::min<long long>((work + 255) / 256, 4096);
+    double hn[2];
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        hipLaunchKernelGGL(offnorm_kernel, dim3(1), dim3(1024), 0, s, A, n, nrm);
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(hn, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (!std::isfinite(hn[0]) || !std::isfinite(hn[1])) fail(-4, "eigensolver: non-finite matrix");
+        if (hn[0] <= 1e-30 * hn[1] || hn[0] == 0.0) break;
+        for (int r = 0; r < np - 1; ++r) {
+            hipLaunchKernelGGL(jacobi_angles_kernel, dim3((np / 2 + 255) / 256), dim3(256), 0, s, A, n, np, r, cs);
+            hipLaunchKernelGGL(jacobi_rotate_kernel, dim3(gb), dim3(256), 0, s, A, V, n, np, r, cs);
+        }
+        LAUNCHCHK();
+    }
+    hipLaunchKernelGGL(diag_out_kernel, dim3((n + 255) / 256), dim3(256), 0, s, A, n, w);
+    LAUNCHCHK();
+}
+
+void k_sort_eig(double* w, double* V, int n, int desc, double* wtmp, double* Vtmp, hipStream_t s) {
+    if (g_dry) return;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(sort_eig_kernel, dim3(1), dim3(1024), 0, s, w, V, n, desc, wtmp, Vtmp);
+    LAUNCHCHK();
+}
+
+}  // namespace adc3

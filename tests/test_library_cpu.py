@@ -1,0 +1,64 @@
+"""Host-side checks of the C-ABI library (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2511_05897_amd as adc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    txt = open(os.path.join(ROOT, "include", "adc3ea.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(adc3_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(adc.LIB_PATH):
+        pytest.skip("library not built")
+    return adc.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    syms = _header_symbols()
+    assert set(syms) == set(adc.EXPORTS)
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_default_opts(lib):
+    o = adc.adc3_default_opts()
+    assert (o.level, o.max_iter, o.max_subspace, o.fno_correction, o.precision, o.precond) == (3, 200, 0, 1, 0, 0)
+
+
+def test_workspace_planning(lib):
+    small = adc.adc3_ea_setup_workspace_bytes(4, 20, 60, 3, 3)
+    big = adc.adc3_ea_setup_workspace_bytes(20, 200, 600, 3, 5)
+    assert 0 < small < big
+    # the stored ladder alone is v^4 doubles
+    assert big > 200 ** 4 * 8
+    assert adc.adc3_ea_solve_workspace_bytes(20, 200, 600, 5) >= big
+    assert adc.adc3_ea_setup_workspace_bytes(0, 20, 60, 3, 3) == 0
+    assert adc.adc3_ea_setup_workspace_bytes(4, 20, 60, 4, 3) == 0
+    o = adc.adc3_default_opts()
+    o.precision = 2
+    assert adc.adc3_ea_solve_workspace_bytes(4, 20, 60, 3, o) == 0
+
+
+def test_error_paths_without_device(lib):
+    """Arguments are validated before any launch: NULL inputs are rejected with EINVAL."""
+    o = adc.adc3_default_opts()
+    roots = (ctypes.c_double * 3)()
+    st = lib.adc3_ea_solve(None, None, None, 4, 20, 60, 3, 0.0, 0.0, 1e-6, ctypes.byref(o), roots, None,
+                           None, 0, None)
+    assert st == adc.ADC3_EINVAL
+    assert b"NULL" in lib.adc3_last_error()
+    h = ctypes.c_void_p()
+    st = lib.adc3_ea_setup(None, None, None, 4, 20, 60, 5, None, 0, None, ctypes.byref(h))
+    assert st == adc.ADC3_EINVAL
+    st = lib.adc3_ea_setup(None, None, None, -1, 20, 60, 3, None, 0, None, ctypes.byref(h))
+    assert st == adc.ADC3_EINVAL
