@@ -1,0 +1,189 @@
+"""Benchmark: sigma-builds/s and time-to-roots of the full DF-SS-FNO-EA-ADC(3) solve on one MI355X.
+
+One step = one call of adc3_ea_solve on the named workload (default: o=20, v=200,
+X=600, seed 1, 5 roots, SS-FNO threshold 10^-4.5, NAF threshold 1e-2, Davidson
+conv 1e-6 Eh, perturbative correction on): canonical MP2 + EA-ADC(2), then per
+root D^SS, natural orbitals, recanonicalisation, NAF, EA-ADC(2) and EA-ADC(3) in
+the truncated basis and the correction.  Inputs are resident in HBM before the
+timed region.
+
+value  = sigma vectors built during the timed solves / timed wall time
+ms_per_step = time to all roots (one full solve)
+
+Usage: python bench.py [--steps K] [--warmup W] [--workload NAME] [--scale s]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="ssfno-o20v200x600")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sigma-reps", type=int, default=10)
+    ap.add_argument("--variant-scale", type=float, default=0.018,
+                    help="also time one solve with B scaled by this factor (weak correlation, FNO truncates); 0 = skip")
+    return ap.parse_args()
+
+
+def cpu_baseline(shape, nvec):
+    """The FP64 oracle's sigma build on the host: nvec ADC(3) sigma vectors on a
+    synthetic instance of the truncated-basis shape (one-time intermediates not timed)."""
+    import numpy as np
+
+    import synth
+    from oracle.adc_cs import Problem
+    o, v, X = shape
+    eo, ev, B = synth.make_instance(o, v, X, 1)
+    P = Problem(eo, ev, B)
+    P.m11(3)
+    P.coupling_z(3)
+    r = np.random.default_rng(0).standard_normal((nvec, P.dim()))
+    t0 = time.perf_counter()
+    P.sigma(r, 3)
+    dt = time.perf_counter() - t0
+    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    return {"value": nvec / dt, "unit": "sigma-builds/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d ADC(3) sigma vectors, o=%d v=%d X=%d (the SS-FNO/NAF basis shape of the workload), "
+                      "NumPy FP64; intermediates built once, untimed; %.2f s" % (nvec, o, v, X, dt)}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2511_05897_amd as adc
+    import synth
+
+    p, eo, ev, B = synth.preset(a.workload, scale=a.scale)
+    d = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")  # noqa: E731
+    teo, tev, tB = d(eo), d(ev), d(B)
+    del B
+    nroots = p["nroots"]
+    opts = adc.adc3_default_opts()
+    ws = torch.empty(adc.adc3_ea_solve_workspace_bytes(p["nocc"], p["nvir"], p["naux"], nroots, opts),
+                     dtype=torch.uint8, device="cuda")
+    run = lambda: adc.adc3_ea_solve(teo, tev, tB, nroots, p["fno_thresh"], p["naf_thresh"], p["conv"],  # noqa: E731
+                                    opts, workspace=ws)
+    for w in range(a.warmup):
+        roots, reps, st = run()
+        print("warmup %d done: roots %s status %d" % (w, np.array2string(roots, precision=8), st),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    adc.adc3_profile_enable(True)
+    nsig = 0
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        roots, reps, st = run()
+        nsig += sum(r["sigma_builds"] for r in reps)
+        print("step %d done" % k, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lad_ms, lad_n, lad_f, lad_b = adc.adc3_profile_query(adc.PROF_LADDER)
+    sig_ms, sig_n, _, _ = adc.adc3_profile_query(adc.PROF_SIGMA)
+    setup_ms, setup_n, _, _ = adc.adc3_profile_query(adc.PROF_SETUP)
+    dav_ms, _, _, _ = adc.adc3_profile_query(adc.PROF_DAVIDSON)
+    eig_ms, eig_n, _, _ = adc.adc3_profile_query(adc.PROF_EIG)
+    adc.adc3_profile_enable(False)
+    vk, xk = reps[0]["nvir_kept"], reps[0]["naux_kept"]
+
+    # isolated ADC(3) sigma builds (blocks of nroots vectors) in a basis of the truncated shape
+    iso = None
+    try:
+        e2, v2, B2 = synth.make_instance(p["nocc"], vk, xk, 1, scale=a.scale)
+        ctx = adc.Context(d(e2), d(v2), d(B2), 3, nroots=0)
+        r = torch.randn((nroots, ctx.N), dtype=torch.float64, device="cuda")
+        out = torch.empty_like(r)
+        ctx.sigma(r, out)
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        for _ in range(a.sigma_reps):
+            ctx.sigma(r, out)
+        torch.cuda.synchronize()
+        sdt = time.perf_counter() - s0
+        iso = {"value": a.sigma_reps * nroots / sdt, "unit": "sigma-builds/s", "nvec_per_call": nroots,
+               "shape": {"nocc": p["nocc"], "nvir": vk, "naux": xk}}
+        ctx.close()
+        del ctx
+    except Exception as e:  # reported, never silent
+        iso = {"error": str(e)}
+
+    # the same workload with B scaled into the weakly correlated regime (SS-FNO then truncates)
+    variant = None
+    if a.variant_scale > 0:
+        try:
+            pv, eov, evv, Bv = synth.preset(a.workload, scale=a.variant_scale)
+            tBv = d(Bv)
+            adc.adc3_ea_solve(d(eov), d(evv), tBv, nroots, pv["fno_thresh"], pv["naf_thresh"], pv["conv"],
+                              opts, workspace=ws)
+            torch.cuda.synchronize()
+            v0 = time.perf_counter()
+            rv, repv, stv = adc.adc3_ea_solve(d(eov), d(evv), tBv, nroots, pv["fno_thresh"], pv["naf_thresh"],
+                                              pv["conv"], opts, workspace=ws)
+            torch.cuda.synchronize()
+            vdt = time.perf_counter() - v0
+            variant = {"scale": a.variant_scale, "time_to_roots_s": vdt,
+                       "sigma_builds_per_s": sum(r["sigma_builds"] for r in repv) / vdt,
+                       "roots": [float(x) for x in rv], "status": stv,
+                       "nvir_kept": [r["nvir_kept"] for r in repv], "naux_kept": [r["naux_kept"] for r in repv]}
+            del tBv
+        except Exception as e:
+            variant = {"error": str(e)}
+
+    achieved = lad_f / (lad_ms * 1e-3) / 1e12 if lad_ms > 0 else 0.0
+    line = {
+        "metric": "sigma-builds/s (whole SS-FNO-EA-ADC(3) solve) + time-to-5-roots, FP64, 1 GPU",
+        "value": nsig / dt,
+        "unit": "sigma-builds/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt / a.steps * 1e3,
+        "time_to_roots_s": dt / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded DF factor and orbital energies)",
+        "config": {"workload": a.workload, "nocc": p["nocc"], "nvir": p["nvir"], "naux": p["naux"],
+                   "seed": p["seed"], "nroots": nroots, "fno_thresh": p["fno_thresh"],
+                   "naf_thresh": p["naf_thresh"], "conv": p["conv"], "scale": a.scale,
+                   "nvir_kept": [r["nvir_kept"] for r in reps], "naux_kept": [r["naux_kept"] for r in reps]},
+        "roots": [float(x) for x in roots],
+        "status": st,
+        "roofline": {"kernel": "sigma ladder GEMM (gemm_f64_kernel<1>)", "bound": "mfma",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "launches": lad_n, "avg_launch_ms": lad_ms / max(lad_n, 1),
+                     "flops_per_launch": lad_f / max(lad_n, 1)},
+        "phases_ms_per_step": {"setup": setup_ms / a.steps, "davidson": dav_ms / a.steps,
+                               "sigma": sig_ms / a.steps, "ladder": lad_ms / a.steps,
+                               "large_eig": eig_ms / a.steps},
+        "sigma_adc3_isolated": iso,
+        "variant_weak_correlation": variant,
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline((p["nocc"], vk, xk), nroots)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

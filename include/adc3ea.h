@@ -53,7 +53,7 @@ typedef enum {
 /* Options.  adc3_default_opts() fills the defaults listed here. */
 typedef struct {
     int level;            /* 2 or 3: ADC order of the final roots (default 3) */
-    int max_iter;         /* Davidson iterations per solve (default 200) */
+    int max_iter;         /* Davidson iterations per solve (default 500) */
     int max_subspace;     /* Davidson subspace limit; 0 = max(8*nroots, 40) */
     int fno_correction;   /* 1: add omega_can-ADC(2) - omega_FNO-ADC(2) (eq 30); default 1 */
     int precision;        /* 0: FP64 everywhere (only value supported) */
@@ -146,6 +146,18 @@ int adc3_ea_dense_matrix(adc3_ctx* ctx, double* M_dev, int ldm, hipStream_t stre
  * 2 = T [nocc][nocc][nvir][nvir] first-order amplitudes, 3 = MP2 virtual density
  * [nvir][nvir] (per spin).  count receives the element count when out_dev is NULL. */
 int adc3_ea_intermediate(adc3_ctx* ctx, int which, double* out_dev, long long* count, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Timing (tracing aid, not part of the method).  When enabled, HIP events are
+ * recorded on the launching stream around: 0 = each sigma-ladder GEMM launch
+ * (with its algorithmic flops 2*(nvec*nocc)*nvir^4 and bytes), 1 = each sigma
+ * build, 2 = each secular-matrix setup, 3 = each Davidson solve, 4 = each large
+ * eigensolve.  adc3_profile_enable(1) resets and starts; (0) stops.
+ * adc3_profile_query synchronises the recorded events and returns the summed
+ * milliseconds, the number of timed launches, and the summed flops and bytes.
+ * ------------------------------------------------------------------------- */
+void adc3_profile_enable(int on);
+int adc3_profile_query(int kernel, double* total_ms, long long* count, double* flops, double* bytes);
 
 #ifdef __cplusplus
 }

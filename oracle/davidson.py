@@ -12,12 +12,13 @@ subspace is full.
 Readings where the paper is silent: guesses are unit vectors on the
 nroots + 4 lowest diagonal entries (ties broken by index); a root is converged
 when its residual 2-norm and its eigenvalue change since the previous
-iteration are both <= conv.
+iteration are both <= conv.  When the subspace is full it restarts from the
+lowest min(2*nroots + 2, max_space/2) Ritz vectors (thick restart).
 """
 import numpy as np
 
 
-def davidson(sigma, diag, nroots, conv=1e-6, max_iter=200, max_space=None, guess=None, verbose=False):
+def davidson(sigma, diag, nroots, conv=1e-6, max_iter=1000, max_space=None, guess=None, verbose=False):
     n = diag.size
     nguess = min(n, nroots + 4)
     if max_space is None:
@@ -36,8 +37,8 @@ def davidson(sigma, diag, nroots, conv=1e-6, max_iter=200, max_space=None, guess
         it += 1
         G = V @ S.T
         G = 0.5 * (G + G.T)
-        w, y = np.linalg.eigh(G)
-        w, y = w[:nroots], y[:, :nroots]
+        wall, yall = np.linalg.eigh(G)
+        w, y = wall[:nroots], yall[:, :nroots]
         X = y.T @ V
         R = y.T @ S - w[:, None] * X
         rn = np.linalg.norm(R, axis=1)
@@ -53,8 +54,12 @@ def davidson(sigma, diag, nroots, conv=1e-6, max_iter=200, max_space=None, guess
             den = np.where(np.abs(den) < 1e-8, np.copysign(1e-8, den), den)
             new.append(R[k] / den)
         new = np.array(new)
+        # scale each correction to unit length first, so that the drop test below is relative
+        new = new / np.maximum(np.linalg.norm(new, axis=1), 1e-300)[:, None]
         if V.shape[0] + new.shape[0] > max_space:
-            V, S = X.copy(), (y.T @ S)
+            nkeep = min(V.shape[0] - 1, max(nroots, min(2 * nroots + 2, max_space // 2)))
+            yk = yall[:, :nkeep]
+            V, S = yk.T @ V, yk.T @ S
         for _ in range(2):
             new = new - (new @ V.T) @ V
         keep = []
@@ -65,7 +70,7 @@ def davidson(sigma, diag, nroots, conv=1e-6, max_iter=200, max_space=None, guess
             for j in keep:
                 vk = vk - (vk @ j) * j
             nk = np.linalg.norm(vk)
-            if nk > 1e-10:
+            if nk > 1e-8:
                 keep.append(vk / nk)
         if not keep:
             return w, X, rn, it, False

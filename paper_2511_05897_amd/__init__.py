@@ -21,7 +21,7 @@ ADC3_EINVAL, ADC3_ENOMEM, ADC3_EHIP, ADC3_ENUMERIC, ADC3_EUNSUP = -1, -2, -3, -4
 EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_bytes", "adc3_ea_solve",
            "adc3_ea_setup_workspace_bytes", "adc3_ea_setup", "adc3_ctx_destroy", "adc3_ea_dim",
            "adc3_ea_sigma", "adc3_ea_diagonal", "adc3_ea_davidson", "adc3_ea_dense_matrix",
-           "adc3_ea_intermediate"]
+           "adc3_ea_intermediate", "adc3_profile_enable", "adc3_profile_query"]
 
 
 class adc3_opts(ctypes.Structure):
@@ -81,6 +81,10 @@ def load():
     lib.adc3_ea_dense_matrix.restype = I
     lib.adc3_ea_intermediate.argtypes = [P, I, P, ctypes.POINTER(LL), P]
     lib.adc3_ea_intermediate.restype = I
+    lib.adc3_profile_enable.argtypes = [I]
+    lib.adc3_profile_enable.restype = None
+    lib.adc3_profile_query.argtypes = [I, ctypes.POINTER(D), ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]
+    lib.adc3_profile_query.restype = I
     _lib = lib
     return lib
 
@@ -212,3 +216,17 @@ class Context:
 
 
 adc3_ea_setup = Context
+
+
+PROF_LADDER, PROF_SIGMA, PROF_SETUP, PROF_DAVIDSON, PROF_EIG = range(5)
+
+
+def adc3_profile_enable(on=True):
+    load().adc3_profile_enable(1 if on else 0)
+
+
+def adc3_profile_query(kernel):
+    """(total_ms, launches, flops, bytes) recorded for a timing id since the last enable."""
+    ms, n, f, b = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+    _check(load().adc3_profile_query(kernel, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(f), ctypes.byref(b)))
+    return ms.value, n.value, f.value, b.value

@@ -27,6 +27,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -38,6 +40,25 @@ thread_local std::string g_msg;
 
 void set_error(const std::string& msg) { g_msg = msg; }
 [[noreturn]] void fail(int status, const std::string& msg) { throw Error{status, msg}; }
+
+// ADC3_VERBOSE=1 in the environment prints one line per pipeline phase to stderr
+static int verbosity() {
+    static int v = -1;
+    if (v < 0) {
+        const char* e = std::getenv("ADC3_VERBOSE");
+        v = (e && e[0] >= '1' && e[0] <= '9') ? e[0] - '0' : 0;
+    }
+    return g_dry ? 0 : v;
+}
+static bool verbose() { return verbosity() >= 1; }
+#define VLOG(...)                                 \
+    do {                                          \
+        if (verbose()) {                          \
+            std::fprintf(stderr, "[adc3] " __VA_ARGS__); \
+            std::fprintf(stderr, "\n");           \
+            std::fflush(stderr);                  \
+        }                                         \
+    } while (0)
 
 static void d2h(void* dst, const void* src, size_t bytes, hipStream_t s) {
     if (g_dry) {
@@ -83,6 +104,7 @@ static void add_sym(double* M, double* P, int v, double a, hipStream_t s) {
 // Build the context from DF blocks (copied in).  Temporaries are released on return.
 static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const double* Boo_in, const double* Bov_in,
                       const double* Bvv_in, int o, int v, int X, int level, hipStream_t s) {
+    ProfScope prof(PROF_SETUP, s, 0.0, 0.0);
     Ctx* c = new Ctx();
     c->o = o; c->v = v; c->X = X; c->level = level;
     c->N = v + (long long)o * v * v;
@@ -119,6 +141,7 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     c->sb = take(ws, NVMAX * (long long)o * vv);
     // ---- everything below is temporary ----
     const size_t mark = ws.mark();
+    GemmScratch gscr(ws, GEMM_SCRATCH);
     double* Tt2 = take(ws, oo * vv);  // 2T - T~
     k_comb_t(Tt2, T, oo, v, 2.0, -1.0, s);
     // MP2 virtual density (per spin): sum_klc (2T^ce_kl - T^ec_kl) T^cd_kl
@@ -267,6 +290,9 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
 
 // sigma = M r for nvec vectors
 static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nvec, hipStream_t s) {
+    ProfScope prof(PROF_SIGMA, s, 0.0, 0.0);
+    const size_t smark = wsin.mark();
+    GemmScratch gscr(wsin, GEMM_SCRATCH);
     const int o = c->o, v = c->v;
     const long long N = c->N, vv = (long long)v * v, ovv = (long long)o * vv;
     for (int n0 = 0; n0 < nvec; n0 += NVMAX) {
@@ -284,7 +310,11 @@ static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nve
             double* zb = c->zb;
             k_copy2d(zb, ovv, rr + v, N, nv, ovv, 1.0, 0.0, s);
             // ladder: sum_cd (ac|bd) z_cd  (G symmetric)
-            gemm_rm(nv * o, (int)vv, (int)vv, 1.0, zb, vv, false, c->G, vv, false, 0.0, c->sb, vv, s);
+            {
+                ProfScope p(PROF_LADDER, s, 2.0 * nv * o * (double)vv * vv,
+                            8.0 * ((double)vv * vv + 2.0 * nv * o * vv));
+                gemm_rm(nv * o, (int)vv, (int)vv, 1.0, zb, vv, false, c->G, vv, false, 0.0, c->sb, vv, s, 1);
+            }
             // particle-hole terms on the alpha-beta determinants
             k_z_to_x(zb, c->xb, c->xtb, (long long)nv * o, v, s);
             TV tx(c->xb, {nv, o, v, v}), txt(c->xtb, {nv, o, v, v});
@@ -296,6 +326,7 @@ static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nve
         }
     }
     c->sigma_count += nvec;
+    wsin.release(smark);
 }
 
 // ---------------------------------------------------------------------------
@@ -309,6 +340,7 @@ struct DavResult {
 
 static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int max_iter, int max_sub,
                                double* vec_out, hipStream_t s) {
+    ProfScope prof(PROF_DAVIDSON, s, 0.0, 0.0);
     const long long N = c->N;
     if (nroots < 1 || nroots > N) fail(-1, "davidson: nroots out of range");
     if (nroots > 40) fail(-1, "davidson: at most 40 roots per solve");
@@ -321,13 +353,16 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     double* S = take(ws, (long long)mmax * N);
     double* Xr = take(ws, (long long)nroots * N);
     double* AX = take(ws, (long long)nroots * N);
-    double* R = take(ws, (long long)nroots * N);
+    double* R = take(ws, (long long)std::max(nroots, 1) * N);
     double* Gm = take(ws, (long long)mmax * mmax);
     double* Gw = take(ws, (long long)mmax * mmax + mmax);
     double* ev = take(ws, mmax);
     double* Y = take(ws, (long long)mmax * mmax);
     double* th = take(ws, nroots);
-    double* coef = take(ws, (long long)mmax * nroots);
+    double* coef = take(ws, (long long)mmax * mmax);
+    const int nkeep_max = std::max(nroots, std::min(2 * nroots + 2, mmax / 2));
+    double* Vk = take(ws, (long long)nkeep_max * N);
+    double* Sk = take(ws, (long long)nkeep_max * N);
     double* small = take(ws, 16);
     double* part = take(ws, (long long)dots_partial_elems(mmax, mmax, N));
     DavResult res;
@@ -378,6 +413,11 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
             if (!ok) todo.push_back(k);
         }
         if (!finite) fail(-4, "davidson: non-finite Ritz value or residual");
+        if (verbosity() >= 2) {
+            std::fprintf(stderr, "[adc3]   it %3d m %2d", it, m);
+            for (int k = 0; k < nroots; ++k) std::fprintf(stderr, "  %.10f (%.1e)", res.w[k], res.rn[k]);
+            std::fprintf(stderr, "\n");
+        }
         res.iters = it;
         if (todo.empty() || it >= max_iter) {
             res.converged = todo.empty();
@@ -385,11 +425,15 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
         }
         for (int k = 0; k < nroots; ++k) thold[k] = res.w[k];
         int nn = (int)todo.size();
-        // collapse when the new block does not fit
+        // collapse when the new block does not fit: keep the lowest nkeep Ritz vectors
         if (m + nn > mmax) {
-            k_copy(V, Xr, (long long)nroots * N, s);
-            k_copy(S, AX, (long long)nroots * N, s);
-            m = nroots;
+            const int nkeep = std::min(m - 1, nkeep_max);
+            k_copy2d(coef, nkeep, Y, m, m, nkeep, 1.0, 0.0, s);
+            k_lincomb(Vk, N, nkeep, V, N, m, coef, nkeep, N, 1.0, 0.0, s);
+            k_lincomb(Sk, N, nkeep, S, N, m, coef, nkeep, N, 1.0, 0.0, s);
+            k_copy(V, Vk, (long long)nkeep * N, s);
+            k_copy(S, Sk, (long long)nkeep * N, s);
+            m = nkeep;
         }
         nn = std::min(nn, mmax - m);
         if (nn <= 0) {
@@ -402,31 +446,29 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
             int k = todo[j];
             k_precond(Tn + (long long)j * N, R + (long long)k * N, c->diag, th + k, 1, N, s);
         }
-        // two passes of classical Gram-Schmidt against V[0..m)
-        for (int pass = 0; pass < 2; ++pass) {
-            k_dots(V, N, m, Tn, N, nn, N, coef, nn, part, s);
-            k_lincomb(Tn, N, nn, V, N, m, coef, nn, N, -1.0, 1.0, s);
-        }
-        // orthonormalise the new block among itself; drop vectors with tiny norm
-        int acc = 0;
-        for (int j = 0; j < nn; ++j) {
-            double* tj = Tn + (long long)j * N;
+        // unit rows, then block orthonormalisation against V and within the block, twice
+        k_dots(Tn, N, nn, Tn, N, nn, N, Gw, nn, part, s);
+        k_rscale_rows(Tn, nn, N, Gw, nn, s);
+        int acc = nn;
+        for (int round = 0; round < 2 && acc > 0; ++round) {
             for (int pass = 0; pass < 2; ++pass) {
-                int cur = m + acc;
-                k_dots(V, N, cur, tj, N, 1, N, coef, 1, part, s);
-                k_lincomb(tj, N, 1, V, N, cur, coef, 1, N, -1.0, 1.0, s);
+                k_dots(V, N, m, Tn, N, acc, N, coef, acc, part, s);
+                k_lincomb(Tn, N, acc, V, N, m, coef, acc, N, -1.0, 1.0, s);
             }
-            double nrm2;
-            k_dots(tj, N, 1, tj, N, 1, N, small, 1, part, s);
-            d2h(&nrm2, small, sizeof(double), s);
-            double nrm = std::sqrt(std::max(0.0, nrm2));
-            if (!(nrm > 1e-10)) continue;
-            double inv = 1.0 / nrm;
-            h2d(small + 1, &inv, sizeof(double), s);
-            double* dst = V + (long long)(m + acc) * N;
-            if (dst != tj) k_copy(dst, tj, N, s);
-            k_scale_vec(dst, N, small + 1, s);
-            ++acc;
+            // Loewdin within the block: T' = (U w^-1/2)^T T over the kept directions
+            k_dots(Tn, N, acc, Tn, N, acc, N, Gm, acc, part, s);
+            k_symmetrize(Gm, acc, s);
+            eig_small(Gm, acc, ev, Y, s);
+            k_sort_eig(ev, Y, acc, 1, Gw, Gw + acc, s);
+            std::vector<double> hq(acc);
+            d2h(hq.data(), ev, acc * sizeof(double), s);
+            int keep = 0;
+            for (int q = 0; q < acc; ++q) keep += (hq[q] > 1e-14 && std::isfinite(hq[q]));
+            if (keep == 0) { acc = 0; break; }
+            k_lowdin_coef(coef, Y, ev, acc, keep, s);
+            k_lincomb(R, N, keep, Tn, N, acc, coef, keep, N, 1.0, 0.0, s);
+            k_copy(Tn, R, (long long)keep * N, s);
+            acc = keep;
         }
         if (acc == 0) {
             res.converged = false;
@@ -607,11 +649,13 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     double* Y2 = take(ws, (long long)nroots * c0->N);
     DavResult r2 = davidson_impl(c0, ws, nroots, conv, op.max_iter, op.max_subspace, Y2, s);
     out.all_conv = out.all_conv && r2.converged;
+    VLOG("canonical ADC(2): %d roots, %d iterations, lowest %.10f", nroots, r2.iters, r2.w[0]);
     const int sig0 = (int)c0->sigma_count;
     // step 4: per root
     for (int k = 0; k < nroots; ++k) {
         const size_t mark = ws.mark();
         auto& R = out.rep[k];
+        GemmScratch gscr(ws, GEMM_SCRATCH);
         R.omega_adc2_can = r2.w[k];
         double* D = take(ws, (long long)v * v);
         ea_density(ws, c0, Y2 + (long long)k * c0->N, D, s);          // 4a
@@ -625,6 +669,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         Blocks Bn = Bt;
         int xk = X;
         if (naf > 0) xk = naf_blocks(Bt, naf, Bn, ws, s);           // 4e
+        VLOG("root %d: kept %d virtuals, %d auxiliary functions", k, vk, xk);
         const long long Nk = vk + (long long)o * vk * vk;
         if (nroots > Nk) fail(ADC3_EINVAL, "truncated space smaller than nroots");
         int sig = 0;
@@ -633,6 +678,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s);
             DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s);
             R.omega_adc2_fno = a2.w[k];
+            VLOG("root %d: truncated ADC(2) %d iterations", k, a2.iters);
             out.all_conv = out.all_conv && a2.converged;
             sig += (int)c2->sigma_count;
             delete c2;
@@ -643,6 +689,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s);
             DavResult a3 = davidson_impl(c3, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s);
             R.omega_uncorr = a3.w[k];
+            VLOG("root %d: truncated ADC(3) %d iterations, omega %.10f, |r| %.2e", k, a3.iters, a3.w[k], a3.rn[k]);
             R.resnorm = a3.rn[k];
             R.iters = a3.iters;
             out.all_conv = out.all_conv && a3.converged;
@@ -691,7 +738,7 @@ extern "C" {
 void adc3_default_opts(adc3_opts* o) {
     if (!o) return;
     o->level = 3;
-    o->max_iter = 200;
+    o->max_iter = 500;
     o->max_subspace = 0;
     o->fno_correction = 1;
     o->precision = 0;

@@ -130,6 +130,22 @@ __global__ void precond_kernel(double* T, const double* R, const double* D, cons
     }
 }
 
+__global__ void rscale_rows_kernel(double* T, int nn, long long n, const double* G, int ldg) {
+    long long tot = (long long)nn * n;
+    GRID_STRIDE(t, tot) {
+        int j = (int)(t / n);
+        double g = G[(long long)j * ldg + j];
+        T[t] = (g > 0.0) ? T[t] / sqrt(g) : 0.0;
+    }
+}
+
+__global__ void lowdin_coef_kernel(double* coef, const double* U, const double* w, int acc, int keep) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= acc * keep) return;
+    int j = t / keep, q = t % keep;
+    coef[t] = U[j * acc + q] / sqrt(w[q]);
+}
+
 __global__ void scale_vec_kernel(double* x, long long n, const double* f) {
     double a = f[0];
     GRID_STRIDE(t, n) x[t] *= a;
@@ -347,6 +363,19 @@ void k_scale_vec(double* x, long long n, const double* f, hipStream_t s) {
     if (g_dry) return;
     if (n <= 0) return;
     hipLaunchKernelGGL(scale_vec_kernel, dim3(nblocks(n)), dim3(NT), 0, s, x, n, f);
+    LAUNCHCHK();
+}
+void k_rscale_rows(double* T, int nn, long long n, const double* G, int ldg, hipStream_t s) {
+    if (g_dry) return;
+    long long t = (long long)nn * n;
+    if (t <= 0) return;
+    hipLaunchKernelGGL(rscale_rows_kernel, dim3(nblocks(t)), dim3(NT), 0, s, T, nn, n, G, ldg);
+    LAUNCHCHK();
+}
+void k_lowdin_coef(double* coef, const double* U, const double* w, int acc, int keep, hipStream_t s) {
+    if (g_dry) return;
+    if (acc <= 0 || keep <= 0) return;
+    hipLaunchKernelGGL(lowdin_coef_kernel, dim3((acc * keep + 255) / 256), dim3(256), 0, s, coef, U, w, acc, keep);
     LAUNCHCHK();
 }
 void k_check_B(const double* B, int X, int n, double* flags, hipStream_t s) {

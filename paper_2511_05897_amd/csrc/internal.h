@@ -65,11 +65,32 @@ struct Gemm {
     int nb0 = 1, nb1 = 1;
     double alpha = 1.0, beta = 0.0;
 };
-void gemm(const Gemm& g, hipStream_t s);
+void gemm(const Gemm& g, hipStream_t s, int tag = 0);
+// scratch for split-K GEMMs issued by this thread while the guard lives
+struct GemmScratch {
+    double* prev;
+    long long prev_n;
+    GemmScratch(Arena& ws, long long n);
+    ~GemmScratch();
+};
+constexpr long long GEMM_SCRATCH = 4LL << 20;  // doubles
 // row-major helpers: C[M,N] (ldc) = alpha*op(A)op(B) + beta*C
 void gemm_rm(int M, int N, int K, double alpha, const double* A, long long lda, bool transA,
              const double* B, long long ldb, bool transB, double beta, double* C, long long ldc,
-             hipStream_t s);
+             hipStream_t s, int tag = 0);
+
+// ---------------------------------------------------------------------------
+// profiling: HIP events around selected launches, on the launching stream
+// ---------------------------------------------------------------------------
+enum ProfKernel { PROF_LADDER = 0, PROF_SIGMA = 1, PROF_SETUP = 2, PROF_DAVIDSON = 3, PROF_EIG = 4, PROF_N = 5 };
+struct ProfScope {
+    int k;
+    hipStream_t s;
+    double flops, bytes;
+    void* ev0 = nullptr;
+    ProfScope(int kernel, hipStream_t stream, double flops, double bytes);
+    ~ProfScope();
+};
 
 // ---------------------------------------------------------------------------
 // elementwise / data movement
@@ -100,6 +121,10 @@ void k_residual(double* R, const double* AX, const double* X, const double* thet
 // T[k][i] = R[k][i] / (D[i] - theta[k]) with |D - theta| >= floor
 void k_precond(double* T, const double* R, const double* D, const double* theta, int nk, long long n, hipStream_t s);
 void k_scale_vec(double* x, long long n, const double* factor_dev, hipStream_t s);   // x *= factor[0]
+// row j of T[nn][n] *= 1/sqrt(G[j*ldg + j])  (rows with G <= 0 are zeroed)
+void k_rscale_rows(double* T, int nn, long long n, const double* G, int ldg, hipStream_t s);
+// coef[j*keep + q] = U[j*acc + q] / sqrt(w[q]),  j < acc, q < keep
+void k_lowdin_coef(double* coef, const double* U, const double* w, int acc, int keep, hipStream_t s);
 // flags[0] = 1 if any non-finite; flags[1] = max |B_Qpq - B_Qqp|; flags[2] = max |B|
 void k_check_B(const double* B, int X, int n, double* flags, hipStream_t s);
 // z -> x = z_S + z_A/sqrt3 and xt = 2x - x^T  (blocks of v*v)

@@ -242,6 +242,7 @@ size_t eig_large_scratch(int n) { return (size_t)(n + 2) + 4; }
 
 void eig_large(double* A, int n, double* w, double* V, double* scratch, hipStream_t s) {
     if (g_dry) return;
+    ProfScope prof(PROF_EIG, s, 0.0, 0.0);
     if (n <= 0) return;
     if (n <= SMALL_MAX) { eig_small(A, n, w, V, s); return; }
     const int np = n + (n & 1);

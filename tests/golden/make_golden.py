@@ -1,0 +1,41 @@
+"""Write the stored expected values of the full-size workloads.  Calls only oracle/ and synth.
+
+    python tests/golden/make_golden.py ssfno-o20v200x600 [scale]
+
+Writes tests/golden/<workload>[_s<scale>].json with the corrected roots, the
+uncorrected ADC(3) roots, the canonical and truncated ADC(2) roots and the kept
+virtual/auxiliary counts of the SS-FNO/NAF pipeline (Sec. "Computational
+Details", steps 2-4f), computed by the FP64 oracle with Davidson conv 1e-8.
+"""
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import synth  # noqa: E402
+from oracle import ssfno  # noqa: E402
+
+
+def main():
+    name = sys.argv[1]
+    scale = float(sys.argv[2]) if len(sys.argv) > 2 else 1.0
+    p, eo, ev, B = synth.preset(name, scale=scale)
+    t0 = time.time()
+    r = ssfno.run(eo, ev, B, p["nroots"], p["fno_thresh"], p["naf_thresh"], 1e-8)
+    out = {"workload": name, "scale": scale, "oracle_conv": 1e-8, "seconds": time.time() - t0,
+           "roots": [float(x) for x in r["roots"]],
+           "omega_uncorr": [float(x) for x in r["omega_uncorr"]],
+           "omega_adc2_can": [float(x) for x in r.get("omega_adc2_can", [])],
+           "omega_adc2_fno": [float(x) for x in r.get("omega_adc2_fno", [])],
+           "nvir_kept": [int(x) for x in r["nvir_kept"]], "naux_kept": [int(x) for x in r["naux_kept"]]}
+    tag = name if scale == 1.0 else "%s_s%g" % (name, scale)
+    with open(os.path.join(HERE, tag + ".json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
