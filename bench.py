@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sigma-reps", type=int, default=10)
+    ap.add_argument("--sigma-only", action="store_true",
+                    help="profiling mode: only the isolated ADC(3) sigma builds plus a 2 GiB copy (counter calibration)")
     ap.add_argument("--variant-scale", type=float, default=0.018,
                     help="also time one solve with B scaled by this factor (weak correlation, FNO truncates); 0 = skip")
     return ap.parse_args()
@@ -73,8 +75,25 @@ def main():
     import paper_2511_05897_amd as adc
     import synth
 
-    p, eo, ev, B = synth.preset(a.workload, scale=a.scale)
     d = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")  # noqa: E731
+    if a.sigma_only:
+        # ADC(3) sigma builds in the SS-FNO/NAF basis shape of the default workload
+        e2, v2, B2 = synth.make_instance(20, 200, 128, 1)
+        ctx = adc.Context(d(e2), d(v2), d(B2), 3, nroots=0)
+        r = torch.randn((5, ctx.N), dtype=torch.float64, device="cuda")
+        out = torch.empty_like(r)
+        for _ in range(a.sigma_reps):
+            ctx.sigma(r, out)
+        torch.cuda.synchronize()
+        # plain copy of known size: 2 GiB read + 2 GiB written
+        x = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "sigma-only", "sigma_calls": a.sigma_reps, "nvec": 5,
+                          "ladder_flops_per_launch": 2.0 * 100 * 200 ** 4, "copy_bytes_each_way": 8 << 28}))
+        return
+    p, eo, ev, B = synth.preset(a.workload, scale=a.scale)
     teo, tev, tB = d(eo), d(ev), d(B)
     del B
     nroots = p["nroots"]
