@@ -63,7 +63,7 @@ typedef struct {
 /* Per-root report of adc3_ea_solve. */
 typedef struct {
     double omega;          /* reported root (corrected when SS-FNO/NAF is active) */
-    double omega_uncorr;   /* ADC(3) root k in the truncated basis */
+    double omega_uncorr;   /* ADC(3) root matched to k in the truncated basis */
     double omega_adc2_can; /* canonical ADC(2) root k (0 when no truncation ran) */
     double omega_adc2_fno; /* ADC(2) root k in the truncated basis */
     double resnorm;        /* final residual 2-norm of the ADC(3) root */
@@ -86,8 +86,10 @@ const char* adc3_last_error(void);
  *   naf_thresh > 0: keep natural auxiliary functions with W-eigenvalue >= naf_thresh
  *     (eqs 27-29, W from the vv block of the root's truncated factor);
  *   both <= 0: plain canonical EA-ADC(level) roots.
- *   Root k of a truncated problem is its k-th lowest root.  roots_out[k] =
- *   omega_FNO-ADC(3)(k) + omega_can-ADC(2)(k) - omega_FNO-ADC(2)(k) (eq 30).
+ *   Root k of a truncated problem: the truncated ADC(2) root m whose eigenvector has
+ *   the largest overlap with canonical ADC(2) eigenvector k projected into the kept
+ *   orbitals (lowest m on ties), and the truncated ADC(3) root of the same index m.
+ *   roots_out[k] = omega_FNO-ADC(3)(k) + omega_can-ADC(2)(k) - omega_FNO-ADC(2)(k) (eq 30).
  * Inputs eps_occ_dev, eps_vir_dev, B_dev are device pointers and are not modified.
  * roots_out[nroots] and reports[nroots] (nullable) are host arrays.
  * conv: a root is converged when its residual 2-norm and eigenvalue change are <= conv.

@@ -21,8 +21,11 @@ Readings where the paper is silent (each listed in the design notes):
   D^EA_ab = 1/2 [r1_a r1_b + sum_ci (x_aci x_bci + y_aci y_bci + x_cai x_cbi)].
 * FNO keeps eta > thr; NAF keeps w >= thr; thr <= 0 disables the step.
 * Eigenvector signs: largest-magnitude component positive.
-* Root k of the truncated problems is their k-th lowest root (index matching), so
-  that with nothing truncated the corrected root k is canonical ADC(3) root k.
+* Root k of the truncated problems: the truncated ADC(2) root m whose eigenvector
+  has the largest overlap with canonical ADC(2) eigenvector k carried into the
+  truncated basis (first one on ties), and the truncated ADC(3) root with the same
+  index m.  With nothing truncated m = k, so corrected root k is canonical ADC(3)
+  root k.
 """
 import numpy as np
 
@@ -137,7 +140,9 @@ def run(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, dense_limit=4
         Pk = Problem(eps_occ, e_new, Bt)
         w2k, Y2k, _ = solve_roots(Pk, 2, nroots, conv, dense_limit)
         w3k, Y3k, _ = solve_roots(Pk, 3, nroots, conv, dense_limit)
-        m2 = m3 = k
+        ref = carry_vector(Y2[k], o, v, U)
+        ov = np.abs(Y2k @ ref)
+        m2 = m3 = int(np.argmax(ov))
         unc.append(w3k[m3])
         a2f.append(w2k[m2])
         roots.append(w3k[m3] + w2[k] - w2k[m2])

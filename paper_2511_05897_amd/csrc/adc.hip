@@ -355,6 +355,7 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     double* AX = take(ws, (long long)nroots * N);
     double* R = take(ws, (long long)std::max(nroots, 1) * N);
     double* Gm = take(ws, (long long)mmax * mmax);
+    double* Gf = take(ws, (long long)mmax * mmax);  // Gram V S^T, kept incrementally (row stride mmax)
     double* Gw = take(ws, (long long)mmax * mmax + mmax);
     double* ev = take(ws, mmax);
     double* Y = take(ws, (long long)mmax * mmax);
@@ -384,13 +385,14 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     for (int k = 0; k < nguess; ++k) h2d(V + (long long)k * N + idx[k], one.data(), sizeof(double), s);
     int m = nguess;
     sigma_impl(c, ws, V, S, m, s);
+    k_dots(V, N, m, S, N, m, N, Gf, mmax, part, s);
     std::vector<double> thold(nroots, INFINITY), hw(mmax), hrn(nroots * nroots);
     std::vector<double> hY;
     int it = 0;
     for (;;) {
         ++it;
-        // Rayleigh-Ritz
-        k_dots(V, N, m, S, N, m, N, Gm, m, part, s);
+        // Rayleigh-Ritz on the (incrementally kept) Gram matrix
+        k_copy2d(Gm, m, Gf, mmax, m, m, 1.0, 0.0, s);
         k_symmetrize(Gm, m, s);
         eig_small(Gm, m, ev, Y, s);
         k_sort_eig(ev, Y, m, 0, Gw, Gw + m, s);  // ascending, deterministic signs
@@ -433,6 +435,8 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
             k_lincomb(Sk, N, nkeep, S, N, m, coef, nkeep, N, 1.0, 0.0, s);
             k_copy(V, Vk, (long long)nkeep * N, s);
             k_copy(S, Sk, (long long)nkeep * N, s);
+            // the Gram of the Ritz basis is diag(theta)
+            k_dots(V, N, nkeep, S, N, nkeep, N, Gf, mmax, part, s);
             m = nkeep;
         }
         nn = std::min(nn, mmax - m);
@@ -450,7 +454,8 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
         k_dots(Tn, N, nn, Tn, N, nn, N, Gw, nn, part, s);
         k_rscale_rows(Tn, nn, N, Gw, nn, s);
         int acc = nn;
-        for (int round = 0; round < 2 && acc > 0; ++round) {
+        bool again = true;
+        for (int round = 0; round < 2 && acc > 0 && again; ++round) {
             for (int pass = 0; pass < 2; ++pass) {
                 k_dots(V, N, m, Tn, N, acc, N, coef, acc, part, s);
                 k_lincomb(Tn, N, acc, V, N, m, coef, acc, N, -1.0, 1.0, s);
@@ -465,6 +470,7 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
             int keep = 0;
             for (int q = 0; q < acc; ++q) keep += (hq[q] > 1e-14 && std::isfinite(hq[q]));
             if (keep == 0) { acc = 0; break; }
+            again = hq[keep - 1] < 0.5;  // strong cancellation: orthonormalise once more
             k_lowdin_coef(coef, Y, ev, acc, keep, s);
             k_lincomb(R, N, keep, Tn, N, acc, coef, keep, N, 1.0, 0.0, s);
             k_copy(Tn, R, (long long)keep * N, s);
@@ -475,6 +481,9 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
             break;
         }
         sigma_impl(c, ws, V + (long long)m * N, S + (long long)m * N, acc, s);
+        // new Gram columns V[0..m+acc) . S[m..m+acc), mirrored into the new rows
+        k_dots(V, N, m + acc, S + (long long)m * N, N, acc, N, Gf + m, mmax, part, s);
+        k_mirror_cols(Gf, mmax, m, acc, s);
         m += acc;
     }
     if (vec_out) k_copy(vec_out, Xr, (long long)nroots * N, s);
@@ -673,12 +682,42 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         const long long Nk = vk + (long long)o * vk * vk;
         if (nroots > Nk) fail(ADC3_EINVAL, "truncated space smaller than nroots");
         int sig = 0;
+        int match = k;
         {
+            // canonical ADC(2) vector k carried into the truncated basis: r1 U, U^T z_i U
+            double* ref = take(ws, Nk);
+            double* Y2k = take(ws, (long long)nroots * Nk);
+            double* ovl = take(ws, 64);
+            double* part = take(ws, (long long)dots_partial_elems(nroots, 1, Nk));
+            {
+                const size_t mt = ws.mark();
+                const double* yk = Y2 + (long long)k * c0->N;
+                gemm_rm(1, vk, v, 1.0, yk, v, false, U, vk, false, 0.0, ref, vk, s);
+                double* tmp = take(ws, (long long)o * v * vk);
+                gemm_rm(o * v, vk, v, 1.0, yk + v, v, false, U, vk, false, 0.0, tmp, vk, s);
+                Gemm g;
+                g.M = vk; g.N = vk; g.K = v;
+                g.A = U; g.sAm = 1; g.sAk = vk;
+                g.B = tmp; g.sBk = vk; g.sBn = 1; g.bB0 = (long long)v * vk;
+                g.C = ref + vk; g.sCm = vk; g.sCn = 1; g.bC0 = (long long)vk * vk;
+                g.nb0 = o;
+                gemm(g, s);
+                ws.release(mt);
+            }
             const size_t m2 = ws.mark();
             Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s);
-            DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s);
-            R.omega_adc2_fno = a2.w[k];
-            VLOG("root %d: truncated ADC(2) %d iterations", k, a2.iters);
+            DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s);
+            k_dots(Y2k, Nk, nroots, ref, Nk, 1, Nk, ovl, 1, part, s);
+            std::vector<double> hov(nroots);
+            d2h(hov.data(), ovl, nroots * sizeof(double), s);
+            if (!g_dry) {
+                match = 0;
+                for (int q = 1; q < nroots; ++q)
+                    if (std::fabs(hov[q]) > std::fabs(hov[match])) match = q;
+            }
+            R.omega_adc2_fno = a2.w[match];
+            VLOG("root %d: truncated ADC(2) %d iterations, matched root %d (overlap %.4f)", k, a2.iters, match,
+                 std::fabs(hov[match]));
             out.all_conv = out.all_conv && a2.converged;
             sig += (int)c2->sigma_count;
             delete c2;
@@ -688,9 +727,10 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             const size_t m3 = ws.mark();
             Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s);
             DavResult a3 = davidson_impl(c3, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s);
-            R.omega_uncorr = a3.w[k];
-            VLOG("root %d: truncated ADC(3) %d iterations, omega %.10f, |r| %.2e", k, a3.iters, a3.w[k], a3.rn[k]);
-            R.resnorm = a3.rn[k];
+            R.omega_uncorr = a3.w[match];
+            VLOG("root %d: truncated ADC(3) %d iterations, omega %.10f, |r| %.2e", k, a3.iters, a3.w[match],
+                 a3.rn[match]);
+            R.resnorm = a3.rn[match];
             R.iters = a3.iters;
             out.all_conv = out.all_conv && a3.converged;
             sig += (int)c3->sigma_count;

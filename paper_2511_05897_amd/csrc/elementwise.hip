@@ -217,6 +217,15 @@ __global__ void symmetrize_kernel(double* A, int n) {
     }
 }
 
+__global__ void mirror_cols_kernel(double* G, int ld, int m0, int nc) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int rows = m0 + nc;
+    if (t >= rows * nc) return;
+    int i = t / nc, j = t % nc;
+    if (i >= m0 && i - m0 >= j) return;  // new-new block: keep the upper copy, mirror below
+    G[(long long)(m0 + j) * ld + i] = G[(long long)i * ld + m0 + j];
+}
+
 __global__ void add_diag_kernel(double* A, const double* d, int n) {
     GRID_STRIDE(i, n) A[(long long)i * n + i] += d[i];
 }
@@ -413,6 +422,13 @@ void k_symmetrize(double* A, int n, hipStream_t s) {
     long long nn = (long long)n * n;
     if (nn <= 0) return;
     hipLaunchKernelGGL(symmetrize_kernel, dim3(nblocks(nn)), dim3(NT), 0, s, A, n);
+    LAUNCHCHK();
+}
+void k_mirror_cols(double* G, int ld, int m0, int nc, hipStream_t s) {
+    if (g_dry) return;
+    int n = (m0 + nc) * nc;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(mirror_cols_kernel, dim3((n + 255) / 256), dim3(256), 0, s, G, ld, m0, nc);
     LAUNCHCHK();
 }
 void k_add_diag(double* A, const double* d, int n, hipStream_t s) {

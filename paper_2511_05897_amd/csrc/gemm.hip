@@ -1,10 +1,19 @@
 // FP64 GEMM on CDNA4 matrix cores (v_mfma_f64_16x16x4f64), strided and batched.
 //
-// One workgroup (4 wave64) computes a 64x64 tile of C; each wave a 32x32 quarter as
-// 2x2 MFMA 16x16 blocks.  A and B tiles (64x16, 16x64) are staged through LDS,
-// double buffered: the next K-slab is fetched into registers while the current one
-// feeds the matrix cores.  Global loads are coalesced along whichever operand
-// dimension is contiguous.
+// One workgroup = 4 wave64.  A BM x BN tile of C is split over the waves as a
+// WM x WN grid; each wave accumulates (BM/WM) x (BN/WN) as 16x16 MFMA blocks.  A and
+// B slabs (BM x 16, 16 x BN) are staged through LDS, double buffered: the next slab
+// is fetched into registers while the current one feeds the matrix cores.  Global
+// loads are coalesced along whichever operand dimension is contiguous.
+//
+// Tile shapes:
+//   64x64   (2x2 waves)  general
+//   16x256  (1x4 waves)  skinny: M <= 16 (Davidson linear combinations, 1p<->2p1h)
+//   16x64   (1x4 waves)  M <= 16 and N <= 64 (K-chunked Gram blocks of the Davidson)
+//   128x80  (4x1 waves)  sigma ladder: all (vector, occupied) rows in one tile, so the
+//                        v^4 ladder matrix streams from HBM exactly once; 80 columns
+//                        give 500 workgroups at v = 200 (2 per CU, one round)
+//   128x128 (2x2 waves)  large square setup contractions
 //
 // MFMA f64 16x16x4 operand layout (lane l of a wave64):
 //   A frag: A[row = l%16][k = l/16]   B frag: B[k = l/16][col = l%16]
@@ -17,11 +26,14 @@ namespace adc3 {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 namespace {
-constexpr int BM = 64, BN = 64, BK = 16, NT = 256;
-constexpr int PER = BM * BK / NT;  // 4 elements of A (and of B) per thread per slab
+constexpr int BK = 16, NT = 256;
 
-template <int TAG>
+template <int BM, int BN, int WM, int WN, int TAG>
 __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
+    static_assert(WM * WN == 4, "four waves");
+    constexpr int TM = BM / WM / 16, TN = BN / WN / 16;  // MFMA blocks per wave
+    static_assert(TM >= 1 && TN >= 1 && (BM / WM) % 16 == 0 && (BN / WN) % 16 == 0, "tile");
+    constexpr int PA = (BM * BK + NT - 1) / NT, PB = (BN * BK + NT - 1) / NT;
     __shared__ double As[2][BM][BK + 1];
     __shared__ double Bs[2][BK][BN + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -31,73 +43,86 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
     const double* __restrict__ B = g.B + b0 * g.bB0 + b1 * g.bB1;
     double* __restrict__ C = g.C + b0 * g.bC0 + b1 * g.bC1;
     const long long m0 = (long long)blockIdx.y * BM, n0 = (long long)blockIdx.x * BN;
-    const int wr = wave >> 1, wc = wave & 1;
+    const int wr = wave / WN, wc = wave % WN;
     const bool a_kc = (g.sAk == 1), b_nc = (g.sBn == 1);
+    const int K = (g.Klast >= 0 && b0 == g.nb0 - 1) ? g.Klast : g.K;
 
-    // per-thread slab coordinates (fixed for the whole K loop)
-    int ar[PER], ak[PER], bk[PER], bn[PER];
+    int ar[PA], ak[PA], bk[PB], bn[PB];
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
+    for (int p = 0; p < PA; ++p) {
         int idx = tid + NT * p;
+        if (idx >= BM * BK) { ar[p] = -1; ak[p] = 0; continue; }
         if (a_kc) { ar[p] = idx / BK; ak[p] = idx % BK; } else { ar[p] = idx % BM; ak[p] = idx / BM; }
+    }
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        int idx = tid + NT * p;
+        if (idx >= BN * BK) { bn[p] = -1; bk[p] = 0; continue; }
         if (b_nc) { bn[p] = idx % BN; bk[p] = idx / BN; } else { bk[p] = idx % BK; bn[p] = idx / BK; }
     }
-    double ra[PER], rb[PER];
+    double ra[PA], rb[PB];
     auto fetch = [&](long long k0) {
 #pragma unroll
-        for (int p = 0; p < PER; ++p) {
+        for (int p = 0; p < PA; ++p) {
             long long m = m0 + ar[p], k = k0 + ak[p];
-            ra[p] = (m < g.M && k < g.K) ? A[m * g.sAm + k * g.sAk] : 0.0;
+            ra[p] = (ar[p] >= 0 && m < g.M && k < K) ? A[m * g.sAm + k * g.sAk] : 0.0;
+        }
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
             long long kb = k0 + bk[p], n = n0 + bn[p];
-            rb[p] = (kb < g.K && n < g.N) ? B[kb * g.sBk + n * g.sBn] : 0.0;
+            rb[p] = (bn[p] >= 0 && kb < K && n < g.N) ? B[kb * g.sBk + n * g.sBn] : 0.0;
         }
     };
     auto stash = [&](int buf) {
 #pragma unroll
-        for (int p = 0; p < PER; ++p) {
-            As[buf][ar[p]][ak[p]] = ra[p];
-            Bs[buf][bk[p]][bn[p]] = rb[p];
-        }
+        for (int p = 0; p < PA; ++p)
+            if (ar[p] >= 0) As[buf][ar[p]][ak[p]] = ra[p];
+#pragma unroll
+        for (int p = 0; p < PB; ++p)
+            if (bn[p] >= 0) Bs[buf][bk[p]][bn[p]] = rb[p];
     };
 
-    d4 acc[2][2];
+    d4 acc[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-    const int nslab = (g.K + BK - 1) / BK;
+    const int nslab = (K + BK - 1) / BK;
     if (nslab > 0) {
         fetch(0);
         stash(0);
     }
     __syncthreads();
     const int lr = lane & 15, lk = lane >> 4;
+    const int rowbase = wr * (BM / WM), colbase = wc * (BN / WN);
     for (int s = 0; s < nslab; ++s) {
         const int buf = s & 1;
         if (s + 1 < nslab) fetch((long long)(s + 1) * BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
-            double a0 = As[buf][wr * 32 + lr][kk + lk];
-            double a1 = As[buf][wr * 32 + 16 + lr][kk + lk];
-            double c0 = Bs[buf][kk + lk][wc * 32 + lr];
-            double c1 = Bs[buf][kk + lk][wc * 32 + 16 + lr];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, c0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, c1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, c0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, c1, acc[1][1], 0, 0, 0);
+            double af[TM], bf[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) af[i] = As[buf][rowbase + i * 16 + lr][kk + lk];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) bf[j] = Bs[buf][kk + lk][colbase + j * 16 + lr];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
         }
         if (s + 1 < nslab) stash(buf ^ 1);
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                long long row = m0 + wr * 32 + i * 16 + lk + 4 * r;
-                long long col = n0 + wc * 32 + j * 16 + lr;
+                long long row = m0 + rowbase + i * 16 + lk + 4 * r;
+                long long col = n0 + colbase + j * 16 + lr;
                 if (row < g.M && col < g.N) {
                     double* c = C + row * g.sCm + col * g.sCn;
                     double v = g.alpha * acc[i][j][r];
@@ -105,6 +130,7 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
                 }
             }
 }
+
 __global__ void splitk_reduce_kernel(const double* part, int nchunk, int M, int N, double alpha, double beta,
                                      double* C, long long sCm, long long sCn) {
     long long MN = (long long)M * N;
@@ -116,6 +142,47 @@ __global__ void splitk_reduce_kernel(const double* part, int nchunk, int M, int 
         double v = alpha * acc;
         *cp = (beta == 0.0) ? v : v + beta * (*cp);
     }
+}
+
+enum Shape { SH_64x64 = 0, SH_16x256 = 1, SH_128x80 = 2, SH_128x128 = 3, SH_16x64 = 4 };
+inline int tile_m(int sh) { return sh == SH_64x64 ? 64 : (sh == SH_16x256 || sh == SH_16x64) ? 16 : 128; }
+inline int tile_n(int sh) {
+    return sh == SH_64x64 ? 64 : sh == SH_16x256 ? 256 : sh == SH_128x80 ? 80 : sh == SH_16x64 ? 64 : 128;
+}
+
+int pick_shape(const Gemm& g, int tag) {
+    if (tag == 1) return SH_128x80;
+    if (g.M <= 16 && g.N <= 64) return SH_16x64;
+    if (g.M <= 16) return SH_16x256;
+    long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128);
+    if (g.M >= 128 && g.N >= 128 && t128 * g.nb0 * g.nb1 >= 512) return SH_128x128;
+    return SH_64x64;
+}
+
+void launch_tiles(const Gemm& g, hipStream_t s, int tag, long long nb, int sh) {
+    const int bm = tile_m(sh), bn = tile_n(sh);
+    dim3 grid((unsigned)((g.N + bn - 1) / bn), (unsigned)((g.M + bm - 1) / bm), (unsigned)nb);
+    if (grid.y > 65535) fail(-1, "gemm: M too large");
+    switch (sh) {
+        case SH_16x256:
+            hipLaunchKernelGGL((gemm_f64_kernel<16, 256, 1, 4, 0>), grid, dim3(NT), 0, s, g);
+            break;
+        case SH_16x64:
+            hipLaunchKernelGGL((gemm_f64_kernel<16, 64, 1, 4, 0>), grid, dim3(NT), 0, s, g);
+            break;
+        case SH_128x80:
+            if (tag == 1)  // sigma ladder: own symbol for profiling
+                hipLaunchKernelGGL((gemm_f64_kernel<128, 80, 4, 1, 1>), grid, dim3(NT), 0, s, g);
+            else
+                hipLaunchKernelGGL((gemm_f64_kernel<128, 80, 4, 1, 0>), grid, dim3(NT), 0, s, g);
+            break;
+        case SH_128x128:
+            hipLaunchKernelGGL((gemm_f64_kernel<128, 128, 2, 2, 0>), grid, dim3(NT), 0, s, g);
+            break;
+        default:
+            hipLaunchKernelGGL((gemm_f64_kernel<64, 64, 2, 2, 0>), grid, dim3(NT), 0, s, g);
+    }
+    LAUNCHCHK();
 }
 }  // namespace
 
@@ -132,16 +199,6 @@ GemmScratch::~GemmScratch() {
     g_gemm_scratch_n = prev_n;
 }
 
-static void launch_tiles(const Gemm& g, hipStream_t s, int tag, long long nb) {
-    dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, (unsigned)nb);
-    if (grid.y > 65535) fail(-1, "gemm: M too large");
-    if (tag == 1)
-        hipLaunchKernelGGL(gemm_f64_kernel<1>, grid, dim3(NT), 0, s, g);  // sigma ladder (own symbol for profiling)
-    else
-        hipLaunchKernelGGL(gemm_f64_kernel<0>, grid, dim3(NT), 0, s, g);
-    LAUNCHCHK();
-}
-
 void gemm(const Gemm& g, hipStream_t s, int tag) {
     if (g_dry) return;
     if (g.M <= 0 || g.N <= 0) return;
@@ -149,42 +206,35 @@ void gemm(const Gemm& g, hipStream_t s, int tag) {
     if (nb <= 0) return;
     // K <= 0 is valid: the kernel then writes C = beta*C.
     if (nb > 65535) fail(-1, "gemm: too many batches");
-    const long long tiles = (long long)((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM);
+    const int sh = pick_shape(g, tag);
+    const long long tiles = (long long)((g.N + tile_n(sh) - 1) / tile_n(sh)) * ((g.M + tile_m(sh) - 1) / tile_m(sh));
     const long long MN = (long long)g.M * g.N;
     // few output tiles and a long K: cut K into chunks (one batch each), then sum the
     // partial tiles in a fixed order (deterministic)
-    if (nb == 1 && tiles < 256 && g.K >= 8192 && g_gemm_scratch) {
-        long long nchunk = std::min<long long>((g.K + 2047) / 2048, (1024 + tiles - 1) / tiles);
+    if (nb == 1 && tiles < 256 && g.K >= 4096 && g_gemm_scratch) {
+        long long nchunk = std::min<long long>((g.K + 255) / 256, (2048 + tiles - 1) / tiles);
         nchunk = std::min<long long>(nchunk, g_gemm_scratch_n / std::max<long long>(MN, 1));
         nchunk = std::min<long long>(nchunk, 65535);
         if (nchunk >= 2) {
             const long long kc = (g.K + nchunk - 1) / nchunk;
-            const long long nfull = g.K / kc, rem = g.K - nfull * kc;
+            const long long nc = (g.K + kc - 1) / kc;
+            const long long last = g.K - (nc - 1) * kc;
             Gemm h = g;
             h.K = (int)kc;
+            h.Klast = (int)last;
             h.alpha = 1.0; h.beta = 0.0;
             h.bA0 = kc * g.sAk; h.bB0 = kc * g.sBk;
             h.C = g_gemm_scratch; h.sCm = g.N; h.sCn = 1; h.bC0 = MN;
-            h.nb0 = (int)nfull; h.nb1 = 1;
-            launch_tiles(h, s, tag, nfull);
-            if (rem) {
-                Gemm t = h;
-                t.K = (int)rem;
-                t.A = g.A + nfull * kc * g.sAk;
-                t.B = g.B + nfull * kc * g.sBk;
-                t.C = g_gemm_scratch + nfull * MN;
-                t.nb0 = 1;
-                launch_tiles(t, s, tag, 1);
-            }
-            const int nc = (int)(nfull + (rem ? 1 : 0));
+            h.nb0 = (int)nc; h.nb1 = 1;
+            launch_tiles(h, s, tag, nc, sh);
             unsigned gb = (unsigned)std::min<long long>((MN + 255) / 256, 4096);
-            hipLaunchKernelGGL(splitk_reduce_kernel, dim3(gb), dim3(256), 0, s, (const double*)g_gemm_scratch, nc, g.M,
-                               g.N, g.alpha, g.beta, g.C, g.sCm, g.sCn);
+            hipLaunchKernelGGL(splitk_reduce_kernel, dim3(gb), dim3(256), 0, s, (const double*)g_gemm_scratch, (int)nc,
+                               g.M, g.N, g.alpha, g.beta, g.C, g.sCm, g.sCn);
             LAUNCHCHK();
             return;
         }
     }
-    launch_tiles(g, s, tag, nb);
+    launch_tiles(g, s, tag, nb, sh);
 }
 
 void gemm_rm(int M, int N, int K, double alpha, const double* A, long long lda, bool transA,

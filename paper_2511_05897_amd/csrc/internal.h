@@ -64,6 +64,7 @@ struct Gemm {
     double* C = nullptr; long long sCm = 0, sCn = 0, bC0 = 0, bC1 = 0;
     int nb0 = 1, nb1 = 1;
     double alpha = 1.0, beta = 0.0;
+    int Klast = -1;  // if >= 0: K of the batches with b0 == nb0-1 (ragged last K chunk)
 };
 void gemm(const Gemm& g, hipStream_t s, int tag = 0);
 // scratch for split-K GEMMs issued by this thread while the guard lives
@@ -135,6 +136,8 @@ void k_d_to_z_add(double* acc, const double* d, long long nblk, int v, hipStream
 void k_k0_add(double* s2, const double* z, const double* eo, const double* ev, int o, int v, int nvec,
               long long ld, hipStream_t s);
 void k_symmetrize(double* A, int n, hipStream_t s);   // A = (A + A^T)/2
+// G[(m0+j)*ld + i] = G[i*ld + m0 + j] for i < m0 + nc, j < nc  (new columns mirrored into rows)
+void k_mirror_cols(double* G, int ld, int m0, int nc, hipStream_t s);
 void k_add_diag(double* A, const double* d, int n, hipStream_t s);
 void k_diag_adc(double* diag, const double* M11, const double* eo, const double* ev, const double* Bvv,
                 const double* oovv, const double* ovov, int o, int v, int X, int level, hipStream_t s);

@@ -2,60 +2,70 @@
 //
 // Inner products G = X Y^T of a few long vectors are a GEMM with a huge K: the K
 // axis is cut into fixed chunks, each chunk is one batch of the matrix-core GEMM
-// (so every vector element is read once), and the per-chunk partial Gram blocks
-// are summed in a fixed order -- the result does not depend on scheduling.
+// (every vector element is read once; ~n/1024 workgroups keep the chip busy), and
+// the per-chunk partial Gram blocks are summed by one workgroup per output element
+// in a fixed order -- the result does not depend on scheduling.
 #include "internal.h"
+#include <algorithm>
 
 namespace adc3 {
 
 namespace {
-constexpr long long CHUNK = 4096;
+inline long long chunk_of(long long n) { return std::max<long long>(256, (n + 8191) / 8192); }
 
-__global__ void sum_partials_kernel(const double* partial, long long nchunk, int np, int nq, double* G, int ldg) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= np * nq) return;
-    int p = t / nq, q = t % nq;
+// G[p*ldg + q] = sum_c partial[c][r][s] with (r,s) = (p,q) or (q,p) when swapped
+__global__ void sum_partials_kernel(const double* partial, long long nchunk, int M, int N, int swapped, double* G,
+                                    int ldg) {
+    const int t = blockIdx.x;  // output element of the partial [M][N] block
+    const long long MN = (long long)M * N;
     double acc = 0.0;
-    for (long long c = 0; c < nchunk; ++c) acc += partial[c * np * nq + t];
-    G[p * ldg + q] = acc;
+    for (long long c = threadIdx.x; c < nchunk; c += blockDim.x) acc += partial[c * MN + t];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    __shared__ double red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = red[0] + red[1] + red[2] + red[3];
+        int r = t / N, q = t % N;
+        if (swapped) G[(long long)q * ldg + r] = s;
+        else G[(long long)r * ldg + q] = s;
+    }
 }
 }  // namespace
 
-size_t dots_partial_elems(int np, int nq, long long n) { return (size_t)(n / CHUNK + 2) * np * nq; }
+size_t dots_partial_elems(int np, int nq, long long n) {
+    return (size_t)(n / chunk_of(n) + 2) * np * nq;
+}
 
 void k_dots(const double* X, long long ldx, int np, const double* Y, long long ldy, int nq, long long n, double* G,
             int ldg, double* partial, hipStream_t s) {
     if (g_dry) return;
     if (np <= 0 || nq <= 0) return;
-    long long nfull = n / CHUNK, rem = n % CHUNK;
-    long long nchunk = nfull + (rem ? 1 : 0);
+    // rows of the GEMM = the smaller set (skinny tiles when it is <= 16)
+    const bool swapped = nq < np;
+    const double* A = swapped ? Y : X;
+    const double* B = swapped ? X : Y;
+    const long long lda = swapped ? ldy : ldx, ldb = swapped ? ldx : ldy;
+    const int M = swapped ? nq : np, N = swapped ? np : nq;
+    const long long MN = (long long)M * N;
+    const long long CH = chunk_of(n);
+    long long nchunk = (n + CH - 1) / CH;
     if (nchunk == 0) {
-        // empty vectors: G = 0
-        k_fill(partial, (long long)np * nq, 0.0, s);
+        k_fill(partial, MN, 0.0, s);
         nchunk = 1;
-    }
-    const long long pq = (long long)np * nq;
-    // partial buffer holds nchunk * np * nq doubles (caller sizes it with dots_partial_elems)
-    for (long long c0 = 0; c0 < nfull; c0 += 65535) {
-        long long nb = std::min<long long>(65535, nfull - c0);
+    } else {
+        if (nchunk > 65535) fail(-1, "k_dots: vectors too long");
         Gemm g;
-        g.M = np; g.N = nq; g.K = (int)CHUNK;
-        g.A = X + c0 * CHUNK; g.sAm = ldx; g.sAk = 1; g.bA0 = CHUNK;
-        g.B = Y + c0 * CHUNK; g.sBk = 1; g.sBn = ldy; g.bB0 = CHUNK;
-        g.C = partial + c0 * pq; g.sCm = nq; g.sCn = 1; g.bC0 = pq;
-        g.nb0 = (int)nb;
+        g.M = M; g.N = N; g.K = (int)CH;
+        g.Klast = (int)(n - (nchunk - 1) * CH);
+        g.A = A; g.sAm = lda; g.sAk = 1; g.bA0 = CH;
+        g.B = B; g.sBk = 1; g.sBn = ldb; g.bB0 = CH;
+        g.C = partial; g.sCm = N; g.sCn = 1; g.bC0 = MN;
+        g.nb0 = (int)nchunk;
         gemm(g, s);
     }
-    if (rem) {
-        Gemm g;
-        g.M = np; g.N = nq; g.K = (int)rem;
-        g.A = X + nfull * CHUNK; g.sAm = ldx; g.sAk = 1;
-        g.B = Y + nfull * CHUNK; g.sBk = 1; g.sBn = ldy;
-        g.C = partial + nfull * pq; g.sCm = nq; g.sCn = 1;
-        gemm(g, s);
-    }
-    hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)((pq + 255) / 256)), dim3(256), 0, s, partial, nchunk,
-                       np, nq, G, ldg);
+    hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)MN), dim3(256), 0, s, partial, nchunk, M, N,
+                       swapped ? 1 : 0, G, ldg);
     LAUNCHCHK();
 }
 
