@@ -33,6 +33,7 @@ def parse():
     ap.add_argument("--workload", default="ssfno-o20v200x600")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 mixed-precision solves")
     ap.add_argument("--sigma-reps", type=int, default=10)
     ap.add_argument("--sigma-only", action="store_true",
                     help="profiling mode: only the isolated ADC(3) sigma builds plus a 2 GiB copy (counter calibration)")
@@ -145,6 +146,35 @@ def main():
     except Exception as e:  # reported, never silent
         iso = {"error": str(e)}
 
+    # the same solve with reduced-precision sigma (FP64 residual correction), vs the FP64 roots
+    mixed = {}
+    if not a.no_mixed:
+        for prec, tag, peak in ((1, "fp32", 157.3), (2, "bf16", 2500.0)):
+            try:
+                om = adc.adc3_default_opts()
+                om.precision = prec
+                wsm = torch.empty(adc.adc3_ea_solve_workspace_bytes(p["nocc"], p["nvir"], p["naux"], nroots, om),
+                                  dtype=torch.uint8, device="cuda")
+                torch.cuda.synchronize()
+                adc.adc3_profile_enable(True)
+                m0 = time.perf_counter()
+                rm, repm, stm = adc.adc3_ea_solve(teo, tev, tB, nroots, p["fno_thresh"], p["naf_thresh"], p["conv"],
+                                                  om, workspace=wsm)
+                torch.cuda.synchronize()
+                mdt = time.perf_counter() - m0
+                lms, ln, lf, lb = adc.adc3_profile_query(adc.PROF_LADDER_LP)
+                adc.adc3_profile_enable(False)
+                del wsm
+                ach = lf / (lms * 1e-3) / 1e12 if lms > 0 else 0.0
+                mixed[tag] = {"time_to_roots_s": mdt, "speedup_vs_fp64": (dt / a.steps) / mdt, "status": stm,
+                              "max_abs_root_diff_vs_fp64_Eh": float(np.abs(rm - roots).max()),
+                              "root_diff_vs_fp64_Eh": [float(x) for x in (rm - roots)],
+                              "lowp_phase_root_error_Eh": [float(r["omega_lowp"] - r["omega_uncorr"]) for r in repm],
+                              "ladder": {"launches": ln, "avg_launch_ms": lms / max(ln, 1),
+                                         "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak}}
+            except Exception as e:
+                mixed[tag] = {"error": str(e)}
+
     # the same workload with B scaled into the weakly correlated regime (SS-FNO then truncates)
     variant = None
     if a.variant_scale > 0:
@@ -197,6 +227,7 @@ def main():
                                "sigma": sig_ms / a.steps, "ladder": lad_ms / a.steps,
                                "large_eig": eig_ms / a.steps},
         "sigma_adc3_isolated": iso,
+        "mixed_precision": mixed,
         "variant_weak_correlation": variant,
     }
     if not a.no_cpu_baseline:

@@ -56,7 +56,13 @@ typedef struct {
     int max_iter;         /* Davidson iterations per solve (default 500) */
     int max_subspace;     /* Davidson subspace limit; 0 = max(8*nroots, 40) */
     int fno_correction;   /* 1: add omega_can-ADC(2) - omega_FNO-ADC(2) (eq 30); default 1 */
-    int precision;        /* 0: FP64 everywhere (only value supported) */
+    int precision;        /* sigma arithmetic: 0 FP64; 1 FP32 ladder and 1p/2p1h coupling (FP32 matrix
+                             cores, FP32 accumulation); 2 BF16 ladder (BF16 matrix cores, FP32
+                             accumulation) and FP32 coupling.  For 1 and 2 each Davidson runs the
+                             reduced-precision sigma until its noise floor, then restarts from the
+                             Ritz vectors with FP64 sigma (FP64 residual correction) down to conv;
+                             orthogonalisation, Rayleigh-Ritz, residual norms and every
+                             eigendecomposition stay FP64.  Default 0. */
     int precond;          /* 0: Jacobi (diagonal) preconditioner */
 } adc3_opts;
 
@@ -71,6 +77,8 @@ typedef struct {
     int naux_kept;         /* auxiliary functions kept by NAF (eq 29) */
     int iters;             /* Davidson iterations of the ADC(3) solve */
     int sigma_builds;      /* sigma vectors built for this root (all solves) */
+    double omega_lowp;     /* precision 1/2: root k when the reduced-precision phase ended */
+    int iters_lowp;        /* precision 1/2: Davidson iterations in the reduced-precision phase */
 } adc3_root_report;
 
 void adc3_default_opts(adc3_opts* opts);
@@ -114,10 +122,12 @@ typedef struct adc3_ctx adc3_ctx;
 /* Workspace for adc3_ea_setup plus everything later calls on the context take from
  * it: sigma builds, the dense-matrix hook and (nroots > 0) adc3_ea_davidson with up to
  * nroots roots and the default subspace.  Returns 0 for invalid arguments. */
-size_t adc3_ea_setup_workspace_bytes(int nocc, int nvir, int naux, int level, int nroots);
+size_t adc3_ea_setup_workspace_bytes(int nocc, int nvir, int naux, int level, int nroots, int precision);
 
+/* precision 1 or 2 also keeps the reduced-precision copies (see adc3_opts.precision)
+ * so that adc3_ea_sigma / adc3_ea_davidson may use them. */
 int adc3_ea_setup(const double* eps_occ_dev, const double* eps_vir_dev, const double* B_dev,
-                  int nocc, int nvir, int naux, int level,
+                  int nocc, int nvir, int naux, int level, int precision,
                   void* workspace_dev, size_t workspace_bytes, hipStream_t stream,
                   adc3_ctx** ctx_out);
 
@@ -127,8 +137,10 @@ void adc3_ctx_destroy(adc3_ctx* ctx);
 long long adc3_ea_dim(const adc3_ctx* ctx);
 
 /* sigma = M r for nvec vectors (Sec. ADC theory, Davidson sigma vectors):
- * r_dev[nvec][N], sigma_dev[nvec][N] device, row-major, must not overlap. */
-int adc3_ea_sigma(adc3_ctx* ctx, const double* r_dev, double* sigma_dev, int nvec, hipStream_t stream);
+ * r_dev[nvec][N], sigma_dev[nvec][N] device, row-major, must not overlap.
+ * precision as in adc3_opts (at most the context's setup precision). */
+int adc3_ea_sigma(adc3_ctx* ctx, const double* r_dev, double* sigma_dev, int nvec, int precision,
+                  hipStream_t stream);
 
 /* Diagonal of M: diag_dev[N] device. */
 int adc3_ea_diagonal(adc3_ctx* ctx, double* diag_dev, hipStream_t stream);
@@ -137,7 +149,7 @@ int adc3_ea_diagonal(adc3_ctx* ctx, double* diag_dev, hipStream_t stream);
  * vectors_dev[nroots][N] device (nullable); resnorm[nroots] host (nullable);
  * iters (host, nullable) receives the iteration count. */
 int adc3_ea_davidson(adc3_ctx* ctx, int nroots, double conv, int max_iter, int max_subspace,
-                     double* omega, double* vectors_dev, double* resnorm, int* iters,
+                     int precision, double* omega, double* vectors_dev, double* resnorm, int* iters,
                      hipStream_t stream);
 
 /* Test hook: dense M (N <= 20000) into M_dev[N][ldm] device. */
@@ -154,7 +166,7 @@ int adc3_ea_intermediate(adc3_ctx* ctx, int which, double* out_dev, long long* c
  * recorded on the launching stream around: 0 = each sigma-ladder GEMM launch
  * (with its algorithmic flops 2*(nvec*nocc)*nvir^4 and bytes), 1 = each sigma
  * build, 2 = each secular-matrix setup, 3 = each Davidson solve, 4 = each large
- * eigensolve.  adc3_profile_enable(1) resets and starts; (0) stops.
+ * eigensolve, 5 = each reduced-precision sigma-ladder launch.  adc3_profile_enable(1) resets and starts; (0) stops.
  * adc3_profile_query synchronises the recorded events and returns the summed
  * milliseconds, the number of timed launches, and the summed flops and bytes.
  * ------------------------------------------------------------------------- */

@@ -33,7 +33,8 @@ class adc3_root_report(ctypes.Structure):
     _fields_ = [("omega", ctypes.c_double), ("omega_uncorr", ctypes.c_double),
                 ("omega_adc2_can", ctypes.c_double), ("omega_adc2_fno", ctypes.c_double),
                 ("resnorm", ctypes.c_double), ("nvir_kept", ctypes.c_int), ("naux_kept", ctypes.c_int),
-                ("iters", ctypes.c_int), ("sigma_builds", ctypes.c_int)]
+                ("iters", ctypes.c_int), ("sigma_builds", ctypes.c_int), ("omega_lowp", ctypes.c_double),
+                ("iters_lowp", ctypes.c_int)]
 
 
 class ADCError(RuntimeError):
@@ -62,19 +63,19 @@ def load():
     lib.adc3_ea_solve.argtypes = [P, P, P, I, I, I, I, D, D, D, ctypes.POINTER(adc3_opts),
                                   ctypes.POINTER(D), ctypes.POINTER(adc3_root_report), P, S, P]
     lib.adc3_ea_solve.restype = I
-    lib.adc3_ea_setup_workspace_bytes.argtypes = [I, I, I, I, I]
+    lib.adc3_ea_setup_workspace_bytes.argtypes = [I, I, I, I, I, I]
     lib.adc3_ea_setup_workspace_bytes.restype = S
-    lib.adc3_ea_setup.argtypes = [P, P, P, I, I, I, I, P, S, P, ctypes.POINTER(P)]
+    lib.adc3_ea_setup.argtypes = [P, P, P, I, I, I, I, I, P, S, P, ctypes.POINTER(P)]
     lib.adc3_ea_setup.restype = I
     lib.adc3_ctx_destroy.argtypes = [P]
     lib.adc3_ctx_destroy.restype = None
     lib.adc3_ea_dim.argtypes = [P]
     lib.adc3_ea_dim.restype = LL
-    lib.adc3_ea_sigma.argtypes = [P, P, P, I, P]
+    lib.adc3_ea_sigma.argtypes = [P, P, P, I, I, P]
     lib.adc3_ea_sigma.restype = I
     lib.adc3_ea_diagonal.argtypes = [P, P, P]
     lib.adc3_ea_diagonal.restype = I
-    lib.adc3_ea_davidson.argtypes = [P, I, D, I, I, ctypes.POINTER(D), P, ctypes.POINTER(D),
+    lib.adc3_ea_davidson.argtypes = [P, I, D, I, I, I, ctypes.POINTER(D), P, ctypes.POINTER(D),
                                      ctypes.POINTER(I), P]
     lib.adc3_ea_davidson.restype = I
     lib.adc3_ea_dense_matrix.argtypes = [P, P, I, P]
@@ -144,20 +145,23 @@ def adc3_ea_solve(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, opt
     return np.array(roots[:]), reports, st
 
 
-def adc3_ea_setup_workspace_bytes(nocc, nvir, naux, level, nroots=0):
-    return load().adc3_ea_setup_workspace_bytes(nocc, nvir, naux, level, nroots)
+def adc3_ea_setup_workspace_bytes(nocc, nvir, naux, level, nroots=0, precision=0):
+    return load().adc3_ea_setup_workspace_bytes(nocc, nvir, naux, level, nroots, precision)
 
 
 class Context:
     """Secular-matrix context (adc3_ea_setup ... adc3_ctx_destroy)."""
 
-    def __init__(self, eps_occ, eps_vir, B, level, nroots=8):
+    def __init__(self, eps_occ, eps_vir, B, level, nroots=8, precision=0):
         lib = load()
         self.nocc, self.nvir, self.naux = int(eps_occ.numel()), int(eps_vir.numel()), int(B.shape[0])
         self.level = level
-        self.workspace = _workspace(adc3_ea_setup_workspace_bytes(self.nocc, self.nvir, self.naux, level, nroots))
+        self.precision = precision
+        self.workspace = _workspace(adc3_ea_setup_workspace_bytes(self.nocc, self.nvir, self.naux, level, nroots,
+                                                                  precision))
         h = ctypes.c_void_p()
         _check(lib.adc3_ea_setup(_ptr(eps_occ), _ptr(eps_vir), _ptr(B), self.nocc, self.nvir, self.naux, level,
+                                 precision,
                                  ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(), _stream(),
                                  ctypes.byref(h)))
         self.handle = h
@@ -174,13 +178,13 @@ class Context:
         except Exception:
             pass
 
-    def sigma(self, r, out=None):
+    def sigma(self, r, out=None, precision=0):
         import torch
         r = r.contiguous()
         nvec = 1 if r.dim() == 1 else r.shape[0]
         if out is None:
             out = torch.empty_like(r)
-        _check(load().adc3_ea_sigma(self.handle, _ptr(r), _ptr(out), nvec, _stream()))
+        _check(load().adc3_ea_sigma(self.handle, _ptr(r), _ptr(out), nvec, precision, _stream()))
         return out
 
     def diagonal(self):
@@ -189,13 +193,13 @@ class Context:
         _check(load().adc3_ea_diagonal(self.handle, _ptr(d), _stream()))
         return d
 
-    def davidson(self, nroots, conv, max_iter=200, max_subspace=0, want_vectors=False):
+    def davidson(self, nroots, conv, max_iter=500, max_subspace=0, want_vectors=False, precision=0):
         import torch
         w = (ctypes.c_double * nroots)()
         rn = (ctypes.c_double * nroots)()
         it = ctypes.c_int()
         vec = torch.empty((nroots, self.N), dtype=torch.float64, device="cuda") if want_vectors else None
-        st = load().adc3_ea_davidson(self.handle, nroots, conv, max_iter, max_subspace, w,
+        st = load().adc3_ea_davidson(self.handle, nroots, conv, max_iter, max_subspace, precision, w,
                                      _ptr(vec) if vec is not None else None, rn, ctypes.byref(it), _stream())
         _check(st, allow_noconv=True)
         return np.array(w[:]), vec, np.array(rn[:]), it.value, st
@@ -218,7 +222,7 @@ class Context:
 adc3_ea_setup = Context
 
 
-PROF_LADDER, PROF_SIGMA, PROF_SETUP, PROF_DAVIDSON, PROF_EIG = range(5)
+PROF_LADDER, PROF_SIGMA, PROF_SETUP, PROF_DAVIDSON, PROF_EIG, PROF_LADDER_LP = range(6)
 
 
 def adc3_profile_enable(on=True):

@@ -91,6 +91,10 @@ struct Ctx {
     double *P2 = nullptr;     // (ij|ad) as [i][a][j][d], level 3
     double *zb = nullptr, *xb = nullptr, *xtb = nullptr, *sdb = nullptr, *sb = nullptr;
     long long sigma_count = 0;
+    // reduced-precision copies (precision 1: FP32 ladder and coupling; 2: BF16 ladder, FP32 coupling)
+    int prec = 0;
+    void* Glo = nullptr;
+    float* Uz32 = nullptr;
 };
 
 static double* take(Arena& ws, long long n) { return ws.take<double>((size_t)std::max<long long>(n, 1)); }
@@ -103,10 +107,10 @@ static void add_sym(double* M, double* P, int v, double a, hipStream_t s) {
 
 // Build the context from DF blocks (copied in).  Temporaries are released on return.
 static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const double* Boo_in, const double* Bov_in,
-                      const double* Bvv_in, int o, int v, int X, int level, hipStream_t s) {
+                      const double* Bvv_in, int o, int v, int X, int level, hipStream_t s, int prec = 0) {
     ProfScope prof(PROF_SETUP, s, 0.0, 0.0);
     Ctx* c = new Ctx();
-    c->o = o; c->v = v; c->X = X; c->level = level;
+    c->o = o; c->v = v; c->X = X; c->level = level; c->prec = prec;
     c->N = v + (long long)o * v * v;
     const long long oo = (long long)o * o, ov = (long long)o * v, vv = (long long)v * v;
     c->eo = take(ws, o); c->ev = take(ws, v);
@@ -133,6 +137,13 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
         c->G = take(ws, vv * vv);
         c->P1 = take(ws, oo * vv);
         c->P2 = take(ws, oo * vv);
+    }
+    if (prec > 0) {
+        c->Uz32 = ws.take<float>((size_t)std::max<long long>(v * (long long)o * vv, 1));
+        if (level >= 3) {
+            if (prec == 1) c->Glo = ws.take<float>((size_t)(vv * vv));
+            else c->Glo = ws.take<unsigned short>((size_t)(vv * vv));
+        }
     }
     c->zb = take(ws, NVMAX * (long long)o * vv);
     c->xb = take(ws, NVMAX * (long long)o * vv);
@@ -283,13 +294,18 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
         k_d_to_z_add(c->Uz, Up, (long long)v * o, v, s);
     }
     k_diag_adc(c->diag, c->M11, eo, ev, Bvv, c->oovv, c->ovov, o, v, X, level, s);
+    if (prec > 0) {
+        k_to_lowp(c->Uz32, c->Uz, v * (long long)o * vv, 1, s);
+        if (level >= 3) k_to_lowp(c->Glo, c->G, vv * vv, prec, s);
+    }
     ws.release(mark);
     c->ws = ws;  // snapshot (base/cap/used) for sigma temporaries
     return c;
 }
 
 // sigma = M r for nvec vectors
-static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nvec, hipStream_t s) {
+static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nvec, hipStream_t s, int prec = 0) {
+    if (prec > c->prec) prec = c->prec;
     ProfScope prof(PROF_SIGMA, s, 0.0, 0.0);
     const size_t smark = wsin.mark();
     GemmScratch gscr(wsin, GEMM_SCRATCH);
@@ -301,16 +317,40 @@ static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nve
         double* ss = sg + (long long)n0 * N;
         // 1p: M11 r1 + U_z z
         gemm_rm(nv, v, v, 1.0, rr, N, false, c->M11, v, true, 0.0, ss, N, s);
-        gemm_rm(nv, v, (int)ovv, 1.0, rr + v, N, false, c->Uz, ovv, true, 1.0, ss, N, s);
-        // 2p1h: U_z^T r1 + K0 z
-        gemm_rm(nv, (int)ovv, v, 1.0, rr, N, false, c->Uz, ovv, false, 0.0, ss + v, N, s);
+        if (prec > 0) {
+            GemmLP g;
+            g.M = nv; g.N = v; g.K = (int)ovv;
+            g.A = rr + v; g.sAm = N; g.sAk = 1;
+            g.B = c->Uz32; g.sBk = 1; g.sBn = ovv;
+            g.C = ss; g.sCm = N; g.sCn = 1; g.beta = 1.0;
+            gemm_lp(g, 1, s);
+            GemmLP h;
+            h.M = nv; h.N = (int)ovv; h.K = v;
+            h.A = rr; h.sAm = N; h.sAk = 1;
+            h.B = c->Uz32; h.sBk = ovv; h.sBn = 1;
+            h.C = ss + v; h.sCm = N; h.sCn = 1;
+            gemm_lp(h, 1, s);
+        } else {
+            gemm_rm(nv, v, (int)ovv, 1.0, rr + v, N, false, c->Uz, ovv, true, 1.0, ss, N, s);
+            // 2p1h: U_z^T r1
+            gemm_rm(nv, (int)ovv, v, 1.0, rr, N, false, c->Uz, ovv, false, 0.0, ss + v, N, s);
+        }
         k_k0_add(ss + v, rr + v, c->eo, c->ev, o, v, nv, N, s);
         if (c->level >= 3) {
             Arena& ws = wsin;
             double* zb = c->zb;
             k_copy2d(zb, ovv, rr + v, N, nv, ovv, 1.0, 0.0, s);
             // ladder: sum_cd (ac|bd) z_cd  (G symmetric)
-            {
+            if (prec > 0) {
+                ProfScope p(PROF_LADDER_LP, s, 2.0 * nv * o * (double)vv * vv,
+                            (prec == 1 ? 4.0 : 2.0) * (double)vv * vv + 16.0 * nv * o * vv);
+                GemmLP g;
+                g.M = nv * o; g.N = (int)vv; g.K = (int)vv;
+                g.A = zb; g.sAm = vv; g.sAk = 1;
+                g.B = c->Glo; g.sBk = vv; g.sBn = 1;
+                g.C = c->sb; g.sCm = vv; g.sCn = 1;
+                gemm_lp(g, prec, s, 1);
+            } else {
                 ProfScope p(PROF_LADDER, s, 2.0 * nv * o * (double)vv * vv,
                             8.0 * ((double)vv * vv + 2.0 * nv * o * vv));
                 gemm_rm(nv * o, (int)vv, (int)vv, 1.0, zb, vv, false, c->G, vv, false, 0.0, c->sb, vv, s, 1);
@@ -334,12 +374,14 @@ static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nve
 // ---------------------------------------------------------------------------
 struct DavResult {
     std::vector<double> w, rn;
-    int iters = 0;
+    std::vector<double> w_lowp;  // Ritz values when the reduced-precision phase ended
+    int iters = 0, iters_lowp = 0;
     bool converged = false;
 };
 
 static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int max_iter, int max_sub,
-                               double* vec_out, hipStream_t s) {
+                               double* vec_out, hipStream_t s, int prec = 0) {
+    if (prec > c->prec) prec = c->prec;
     ProfScope prof(PROF_DAVIDSON, s, 0.0, 0.0);
     const long long N = c->N;
     if (nroots < 1 || nroots > N) fail(-1, "davidson: nroots out of range");
@@ -370,7 +412,7 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     res.w.assign(nroots, 0.0);
     res.rn.assign(nroots, 0.0);
     if (g_dry) {
-        sigma_impl(c, ws, V, S, std::min(NVMAX, nguess), s);  // count the sigma temporaries too
+        sigma_impl(c, ws, V, S, std::min(NVMAX, nguess), s, prec);  // count the sigma temporaries too
         ws.release(mark);
         return res;
     }
@@ -384,7 +426,10 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     std::vector<double> one(1, 1.0);
     for (int k = 0; k < nguess; ++k) h2d(V + (long long)k * N + idx[k], one.data(), sizeof(double), s);
     int m = nguess;
-    sigma_impl(c, ws, V, S, m, s);
+    int phase = prec;  // > 0: reduced-precision sigma until its noise floor, then FP64 correction
+    double best_lp = INFINITY;
+    int stall = 0, it_lp = 0;
+    sigma_impl(c, ws, V, S, m, s, phase);
     k_dots(V, N, m, S, N, m, N, Gf, mmax, part, s);
     std::vector<double> thold(nroots, INFINITY), hw(mmax), hrn(nroots * nroots);
     std::vector<double> hY;
@@ -415,6 +460,31 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
             if (!ok) todo.push_back(k);
         }
         if (!finite) fail(-4, "davidson: non-finite Ritz value or residual");
+        if (phase > 0) {
+            // reduced-precision phase: stop at a tolerance set by the precision, or when it stalls
+            ++it_lp;
+            double scale = 1.0, rmax = 0.0;
+            for (int k = 0; k < nroots; ++k) {
+                scale = std::max(scale, std::fabs(res.w[k]));
+                rmax = std::max(rmax, res.rn[k]);
+            }
+            const double tau = std::max(conv, (phase == 1 ? 1e-6 : 3e-3) * scale);
+            if (rmax < 0.9 * best_lp) { best_lp = rmax; stall = 0; } else ++stall;
+            if (rmax <= tau || stall >= 4 || it >= max_iter) {
+                // FP64 residual correction: restart from the Ritz vectors with FP64 sigma
+                const int nkeep = std::min(m, nkeep_max);
+                k_copy2d(coef, nkeep, Y, m, m, nkeep, 1.0, 0.0, s);
+                k_lincomb(Vk, N, nkeep, V, N, m, coef, nkeep, N, 1.0, 0.0, s);
+                k_copy(V, Vk, (long long)nkeep * N, s);
+                m = nkeep;
+                phase = 0;
+                res.iters_lowp = it_lp;
+                sigma_impl(c, ws, V, S, m, s, 0);
+                k_dots(V, N, m, S, N, m, N, Gf, mmax, part, s);
+                for (int k = 0; k < nroots; ++k) { res.w_lowp.push_back(res.w[k]); thold[k] = INFINITY; }
+                continue;
+            }
+        }
         if (verbosity() >= 2) {
             std::fprintf(stderr, "[adc3]   it %3d m %2d", it, m);
             for (int k = 0; k < nroots; ++k) std::fprintf(stderr, "  %.10f (%.1e)", res.w[k], res.rn[k]);
@@ -480,7 +550,7 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
             res.converged = false;
             break;
         }
-        sigma_impl(c, ws, V + (long long)m * N, S + (long long)m * N, acc, s);
+        sigma_impl(c, ws, V + (long long)m * N, S + (long long)m * N, acc, s, phase);
         // new Gram columns V[0..m+acc) . S[m..m+acc), mirrored into the new rows
         k_dots(V, N, m + acc, S + (long long)m * N, N, acc, N, Gf + m, mmax, part, s);
         k_mirror_cols(Gf, mmax, m, acc, s);
@@ -636,11 +706,13 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     const int level = op.level;
     if (!(fno > 0) && !(naf > 0)) {
         const size_t mark = ws.mark();
-        Ctx* c = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, level, s);
-        DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s);
+        Ctx* c = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, level, s, op.precision);
+        DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision);
         for (int k = 0; k < nroots; ++k) {
             auto& R = out.rep[k];
             R.omega = R.omega_uncorr = r.w[k];
+            R.omega_lowp = r.w_lowp.empty() ? r.w[k] : r.w_lowp[k];
+            R.iters_lowp = r.iters_lowp;
             R.resnorm = r.rn[k];
             R.nvir_kept = v;
             R.naux_kept = X;
@@ -654,9 +726,9 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     }
     // steps 2-3: canonical MP2 density and canonical ADC(2) roots
     const size_t mark0 = ws.mark();
-    Ctx* c0 = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, 2, s);
+    Ctx* c0 = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, 2, s, op.precision);
     double* Y2 = take(ws, (long long)nroots * c0->N);
-    DavResult r2 = davidson_impl(c0, ws, nroots, conv, op.max_iter, op.max_subspace, Y2, s);
+    DavResult r2 = davidson_impl(c0, ws, nroots, conv, op.max_iter, op.max_subspace, Y2, s, op.precision);
     out.all_conv = out.all_conv && r2.converged;
     VLOG("canonical ADC(2): %d roots, %d iterations, lowest %.10f", nroots, r2.iters, r2.w[0]);
     const int sig0 = (int)c0->sigma_count;
@@ -705,8 +777,8 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
                 ws.release(mt);
             }
             const size_t m2 = ws.mark();
-            Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s);
-            DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s);
+            Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s, op.precision);
+            DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s, op.precision);
             k_dots(Y2k, Nk, nroots, ref, Nk, 1, Nk, ovl, 1, part, s);
             std::vector<double> hov(nroots);
             d2h(hov.data(), ovl, nroots * sizeof(double), s);
@@ -725,9 +797,11 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         }
         {
             const size_t m3 = ws.mark();
-            Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s);
-            DavResult a3 = davidson_impl(c3, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s);
+            Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s, op.precision);
+            DavResult a3 = davidson_impl(c3, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision);
             R.omega_uncorr = a3.w[match];
+            R.omega_lowp = a3.w_lowp.empty() ? a3.w[match] : a3.w_lowp[match];
+            R.iters_lowp = a3.iters_lowp;
             VLOG("root %d: truncated ADC(3) %d iterations, omega %.10f, |r| %.2e", k, a3.iters, a3.w[match],
                  a3.rn[match]);
             R.resnorm = a3.rn[match];
@@ -792,24 +866,25 @@ static void check_dims(int nocc, int nvir, int naux) {
     if ((long long)nvir * nvir * nvir * nvir > (1LL << 40)) fail(ADC3_EINVAL, "nvir too large for the stored ladder");
 }
 
-size_t adc3_ea_setup_workspace_bytes(int nocc, int nvir, int naux, int level, int nroots) {
+size_t adc3_ea_setup_workspace_bytes(int nocc, int nvir, int naux, int level, int nroots, int precision) {
     try {
         check_dims(nocc, nvir, naux);
         if (level != 2 && level != 3) return 0;
+        if (precision < 0 || precision > 2) return 0;
         Arena ws;
         g_dry = true;
         const long long n = nocc + nvir;
         take(ws, (long long)naux * n * n);  // split blocks of the public setup
-        Ctx* c = build_ctx(ws, nullptr, nullptr, nullptr, nullptr, nullptr, nocc, nvir, naux, level, nullptr);
+        Ctx* c = build_ctx(ws, nullptr, nullptr, nullptr, nullptr, nullptr, nocc, nvir, naux, level, nullptr, precision);
         {
             Arena w2 = ws;
             take(w2, 2LL * NVMAX * c->N);  // dense-matrix hook
-            sigma_impl(c, w2, nullptr, nullptr, NVMAX, nullptr);
+            sigma_impl(c, w2, nullptr, nullptr, NVMAX, nullptr, precision);
             ws.peak = std::max(ws.peak, w2.peak);
         }
         if (nroots > 0) {
             Arena w3 = ws;
-            davidson_impl(c, w3, (int)std::min<long long>(nroots, c->N), 1.0, 1, 0, nullptr, nullptr);
+            davidson_impl(c, w3, (int)std::min<long long>(nroots, c->N), 1.0, 1, 0, nullptr, nullptr, precision);
             ws.peak = std::max(ws.peak, w3.peak);
         }
         delete c;
@@ -822,12 +897,13 @@ size_t adc3_ea_setup_workspace_bytes(int nocc, int nvir, int naux, int level, in
 }
 
 int adc3_ea_setup(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir, int naux,
-                  int level, void* workspace, size_t ws_bytes, hipStream_t stream, adc3_ctx** ctx_out) {
+                  int level, int precision, void* workspace, size_t ws_bytes, hipStream_t stream, adc3_ctx** ctx_out) {
     API_BEGIN
     if (!ctx_out) fail(ADC3_EINVAL, "ctx_out is NULL");
     *ctx_out = nullptr;
     check_dims(nocc, nvir, naux);
     if (level != 2 && level != 3) fail(ADC3_EINVAL, "level must be 2 or 3");
+    if (precision < 0 || precision > 2) fail(ADC3_EINVAL, "precision must be 0, 1 or 2");
     if (!eps_occ || !eps_vir || (!B && naux > 0) || !workspace) fail(ADC3_EINVAL, "NULL pointer argument");
     Arena ws;
     ws.base = (char*)workspace;
@@ -840,7 +916,7 @@ int adc3_ea_setup(const double* eps_occ, const double* eps_vir, const double* B,
     double* Bvv = take(ws, (long long)naux * nvir * nvir);
     k_split_B(B, naux, nocc, nvir, Boo, Bov, Bvv, stream);
     (void)n;
-    Ctx* c = build_ctx(ws, eps_occ, eps_vir, Boo, Bov, Bvv, nocc, nvir, naux, level, stream);
+    Ctx* c = build_ctx(ws, eps_occ, eps_vir, Boo, Bov, Bvv, nocc, nvir, naux, level, stream, precision);
     (void)mark0;
     HIPCHK(hipStreamSynchronize(stream));
     adc3_ctx* h = new adc3_ctx{c};
@@ -857,12 +933,14 @@ void adc3_ctx_destroy(adc3_ctx* ctx) {
 
 long long adc3_ea_dim(const adc3_ctx* ctx) { return ctx ? ctx->c->N : 0; }
 
-int adc3_ea_sigma(adc3_ctx* ctx, const double* r, double* sigma, int nvec, hipStream_t stream) {
+int adc3_ea_sigma(adc3_ctx* ctx, const double* r, double* sigma, int nvec, int precision, hipStream_t stream) {
     API_BEGIN
     if (!ctx || !r || !sigma) fail(ADC3_EINVAL, "NULL argument");
     if (nvec < 0) fail(ADC3_EINVAL, "nvec < 0");
+    if (precision < 0 || precision > ctx->c->prec)
+        fail(ADC3_EINVAL, "precision not available in this context (set it at setup)");
     Arena ws = ctx->c->ws;
-    sigma_impl(ctx->c, ws, r, sigma, nvec, stream);
+    sigma_impl(ctx->c, ws, r, sigma, nvec, stream, precision);
     return ADC3_OK;
     API_END
 }
@@ -875,15 +953,17 @@ int adc3_ea_diagonal(adc3_ctx* ctx, double* diag, hipStream_t stream) {
     API_END
 }
 
-int adc3_ea_davidson(adc3_ctx* ctx, int nroots, double conv, int max_iter, int max_subspace, double* omega,
-                     double* vectors, double* resnorm, int* iters, hipStream_t stream) {
+int adc3_ea_davidson(adc3_ctx* ctx, int nroots, double conv, int max_iter, int max_subspace, int precision,
+                     double* omega, double* vectors, double* resnorm, int* iters, hipStream_t stream) {
     API_BEGIN
     if (!ctx || !omega) fail(ADC3_EINVAL, "NULL argument");
     if (!(conv > 0)) fail(ADC3_EINVAL, "conv must be > 0");
     if (nroots < 1 || nroots > ctx->c->N) fail(ADC3_EINVAL, "nroots out of range");
     if (max_iter < 1) fail(ADC3_EINVAL, "max_iter must be >= 1");
+    if (precision < 0 || precision > ctx->c->prec)
+        fail(ADC3_EINVAL, "precision not available in this context (set it at setup)");
     Arena ws = ctx->c->ws;
-    DavResult r = davidson_impl(ctx->c, ws, nroots, conv, max_iter, max_subspace, vectors, stream);
+    DavResult r = davidson_impl(ctx->c, ws, nroots, conv, max_iter, max_subspace, vectors, stream, precision);
     for (int k = 0; k < nroots; ++k) {
         omega[k] = r.w[k];
         if (resnorm) resnorm[k] = r.rn[k];
@@ -970,7 +1050,7 @@ static adc3_opts resolve_opts(const adc3_opts* opts) {
     if (opts) o = *opts;
     if (o.level != 2 && o.level != 3) fail(ADC3_EINVAL, "opts.level must be 2 or 3");
     if (o.max_iter < 1) fail(ADC3_EINVAL, "opts.max_iter must be >= 1");
-    if (o.precision != 0) fail(ADC3_EUNSUP, "only FP64 (precision 0) is supported");
+    if (o.precision < 0 || o.precision > 2) fail(ADC3_EUNSUP, "opts.precision must be 0 (FP64), 1 (FP32) or 2 (BF16)");
     if (o.precond != 0) fail(ADC3_EUNSUP, "only the Jacobi preconditioner (precond 0) is supported");
     return o;
 }

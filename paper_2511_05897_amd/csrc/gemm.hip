@@ -186,6 +186,14 @@ void launch_tiles(const Gemm& g, hipStream_t s, int tag, long long nb, int sh) {
 }
 }  // namespace
 
+void splitk_reduce(const double* part, int nchunk, int M, int N, double alpha, double beta, double* C,
+                   long long sCm, long long sCn, hipStream_t s) {
+    long long MN = (long long)M * N;
+    unsigned gb = (unsigned)std::min<long long>((MN + 255) / 256, 4096);
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(gb), dim3(256), 0, s, part, nchunk, M, N, alpha, beta, C, sCm, sCn);
+    LAUNCHCHK();
+}
+
 thread_local double* g_gemm_scratch = nullptr;
 thread_local long long g_gemm_scratch_n = 0;
 

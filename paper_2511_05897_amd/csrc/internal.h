@@ -67,6 +67,23 @@ struct Gemm {
     int Klast = -1;  // if >= 0: K of the batches with b0 == nb0-1 (ragged last K chunk)
 };
 void gemm(const Gemm& g, hipStream_t s, int tag = 0);
+// reduced-precision GEMM, FP32 accumulation, FP64 C (see gemm_lp.hip):
+// A FP64 (converted on load), B in the reduced type (prec 1: float, 2: bf16)
+struct GemmLP {
+    int M = 0, N = 0, K = 0;
+    const double* A = nullptr; long long sAm = 0, sAk = 0;
+    const void* B = nullptr; long long sBk = 0, sBn = 0;
+    double* C = nullptr; long long sCm = 0, sCn = 0;
+    double alpha = 1.0, beta = 0.0;
+    long long bA = 0, bB = 0, bC = 0;  // per-K-chunk offsets (blockIdx.z), in elements
+    int Klast = -1;                    // K of the last chunk if >= 0
+};
+void splitk_reduce(const double* part, int nchunk, int M, int N, double alpha, double beta, double* C,
+                   long long sCm, long long sCn, hipStream_t s);
+extern thread_local double* g_gemm_scratch;
+extern thread_local long long g_gemm_scratch_n;
+void gemm_lp(const GemmLP& g, int prec, hipStream_t s, int tag = 0);
+void k_to_lowp(void* dst, const double* src, long long n, int prec, hipStream_t s);
 // scratch for split-K GEMMs issued by this thread while the guard lives
 struct GemmScratch {
     double* prev;
@@ -83,7 +100,7 @@ void gemm_rm(int M, int N, int K, double alpha, const double* A, long long lda, 
 // ---------------------------------------------------------------------------
 // profiling: HIP events around selected launches, on the launching stream
 // ---------------------------------------------------------------------------
-enum ProfKernel { PROF_LADDER = 0, PROF_SIGMA = 1, PROF_SETUP = 2, PROF_DAVIDSON = 3, PROF_EIG = 4, PROF_N = 5 };
+enum ProfKernel { PROF_LADDER = 0, PROF_SIGMA = 1, PROF_SETUP = 2, PROF_DAVIDSON = 3, PROF_EIG = 4, PROF_LADDER_LP = 5, PROF_N = 6 };
 struct ProfScope {
     int k;
     hipStream_t s;

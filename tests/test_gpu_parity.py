@@ -148,3 +148,18 @@ def test_invalid_inputs_rejected():
     with pytest.raises(adc.ADCError) as e:
         adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 2, 0.0, 0.0, 1e-6, workspace=ws)
     assert e.value.status == adc.ADC3_ENOMEM
+
+
+def test_solve_weak_correlation_full_size_fp64():
+    """Workload o=20, v=200, X=600, seed 1, B x 0.018 (SS-FNO keeps ~40%): roots vs stored FP64 oracle roots."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                       "ssfno-o20v200x600_s0.018.json")))
+    p, eo, ev, B = synth.preset("ssfno-o20v200x600", scale=0.018)
+    roots, reps, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 5, p["fno_thresh"], p["naf_thresh"], 1e-6)
+    assert st == adc.ADC3_OK
+    assert [r["nvir_kept"] for r in reps] == gold["nvir_kept"]
+    assert [r["naux_kept"] for r in reps] == gold["naux_kept"]
+    assert np.abs(roots - np.array(gold["roots"])).max() < 1e-8
+    assert np.abs(np.array([r["omega_uncorr"] for r in reps]) - np.array(gold["omega_uncorr"])).max() < 1e-8

@@ -38,6 +38,10 @@ def test_default_opts(lib):
 def test_workspace_planning(lib):
     small = adc.adc3_ea_setup_workspace_bytes(4, 20, 60, 3, 3)
     big = adc.adc3_ea_setup_workspace_bytes(20, 200, 600, 3, 5)
+    # reduced-precision copies of the ladder (FP32 / BF16) and the coupling (FP32) add memory
+    assert adc.adc3_ea_setup_workspace_bytes(20, 200, 600, 3, 5, 1) > big + 200 ** 4 * 4
+    assert adc.adc3_ea_setup_workspace_bytes(20, 200, 600, 3, 5, 2) > big + 200 ** 4 * 2
+    assert adc.adc3_ea_setup_workspace_bytes(20, 200, 600, 3, 5, 3) == 0
     assert 0 < small < big
     # the stored ladder alone is v^4 doubles
     assert big > 200 ** 4 * 8
@@ -46,6 +50,8 @@ def test_workspace_planning(lib):
     assert adc.adc3_ea_setup_workspace_bytes(4, 20, 60, 4, 3) == 0
     o = adc.adc3_default_opts()
     o.precision = 2
+    assert adc.adc3_ea_solve_workspace_bytes(4, 20, 60, 3, o) > 0
+    o.precision = 7
     assert adc.adc3_ea_solve_workspace_bytes(4, 20, 60, 3, o) == 0
 
 
@@ -58,7 +64,7 @@ def test_error_paths_without_device(lib):
     assert st == adc.ADC3_EINVAL
     assert b"NULL" in lib.adc3_last_error()
     h = ctypes.c_void_p()
-    st = lib.adc3_ea_setup(None, None, None, 4, 20, 60, 5, None, 0, None, ctypes.byref(h))
+    st = lib.adc3_ea_setup(None, None, None, 4, 20, 60, 5, 0, None, 0, None, ctypes.byref(h))
     assert st == adc.ADC3_EINVAL
-    st = lib.adc3_ea_setup(None, None, None, -1, 20, 60, 3, None, 0, None, ctypes.byref(h))
+    st = lib.adc3_ea_setup(None, None, None, -1, 20, 60, 3, 0, None, 0, None, ctypes.byref(h))
     assert st == adc.ADC3_EINVAL
