@@ -63,7 +63,8 @@ typedef struct {
                              Ritz vectors with FP64 sigma (FP64 residual correction) down to conv;
                              orthogonalisation, Rayleigh-Ritz, residual norms and every
                              eigendecomposition stay FP64.  Default 0. */
-    int precond;          /* 0: Jacobi (diagonal) preconditioner */
+    int precond;          /* 0: Jacobi (diagonal) preconditioner; 1: learned (needs mlp_weights) */
+    const float* mlp_weights; /* device, adc3_mlp_nparams() floats (see adc3_mlp_train); NULL default */
 } adc3_opts;
 
 /* Per-root report of adc3_ea_solve. */
@@ -160,6 +161,67 @@ int adc3_ea_dense_matrix(adc3_ctx* ctx, double* M_dev, int ldm, hipStream_t stre
  * 2 = T [nocc][nocc][nvir][nvir] first-order amplitudes, 3 = MP2 virtual density
  * [nvir][nvir] (per spin).  count receives the element count when out_dev is NULL. */
 int adc3_ea_intermediate(adc3_ctx* ctx, int which, double* out_dev, long long* count, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned Davidson preconditioner (a build addition, not in the paper).
+ * For root theta and residual r the step is t_e = a0_e (1 + u_e), a0_e = r_e/(D_e - theta)
+ * the Jacobi step, u_e = MLP(features of element e): 6 -> 256 -> 256 -> 1 with GELU
+ * (tanh form).  Features: (D_e - theta)/(|theta|+1), r_e/rms(r), [e is 1p], e_a,
+ * e_b (0 for 1p), e_i (0 for 1p).  Weights: float[adc3_mlp_nparams()] laid out
+ * W1[6][256], b1[256], W2[256][256], b2[256], W3[256], b3[1]; W3 = b3 = 0 gives
+ * exactly the Jacobi step.  Inference: one fused kernel per residual (FP32 first
+ * layer, BF16 matrix-core second layer with FP32 accumulation, FP32 head).  A
+ * non-finite step or a residual that grows by more than 2x switches that root back
+ * to Jacobi for the rest of the solve.
+ * ------------------------------------------------------------------------- */
+int adc3_mlp_nparams(void);
+
+/* Use the learned preconditioner in adc3_ea_davidson on this context (NULL: Jacobi).
+ * weights_dev must stay valid while the context is used. */
+int adc3_ea_set_preconditioner(adc3_ctx* ctx, const float* weights_dev);
+
+/* Training data from a Jacobi-preconditioned Davidson solve on ctx.  The solve runs
+ * twice (it is deterministic): the first run gives the converged vectors xf, the
+ * replay records, at every iteration and for every unconverged root, one group of
+ * group_size elements sampled by a hash of (seed, group, index): the features, the
+ * Jacobi step a0 and the target, the part of xf outside the current subspace V,
+ * xf - V (V^T xf), i.e. what the new search direction should supply.  Outputs
+ * (device): feat[max_groups][group_size][6], a0[max_groups][group_size],
+ * target[max_groups][group_size]; *ngroups (host) groups were written.  The
+ * context must have been set up with at least nroots roots.  Returns ADC3_WNOCONV
+ * if the solve did not converge. */
+int adc3_mlp_collect(adc3_ctx* ctx, int nroots, double conv, int max_iter, int group_size, int max_groups,
+                     unsigned long long seed, double* feat_dev, double* a0_dev, double* target_dev, int* ngroups,
+                     hipStream_t stream);
+
+/* Workspace for adc3_mlp_train / adc3_mlp_loss_grad with batch_groups groups of group_size. */
+size_t adc3_mlp_workspace_bytes(int batch_groups, int group_size);
+
+/* Mean over groups of 1 - cos^2(a, d), a = a0 (1 + u), and (grad_dev non-NULL) its
+ * gradient with respect to the weights (FP64, adc3_mlp_nparams() entries).  loss: host. */
+int adc3_mlp_loss_grad(const float* weights_dev, const double* feat_dev, const double* a0_dev,
+                       const double* target_dev, int ngroups, int group_size, double* grad_dev, double* loss,
+                       void* workspace_dev, size_t workspace_bytes, hipStream_t stream);
+
+/* u_dev[n] = MLP(feat_dev[n][6]) as in training: FP32 matrix cores, FP32 accumulation.
+ * Workspace: adc3_mlp_workspace_bytes(1, n). */
+int adc3_mlp_forward(const float* weights_dev, const double* feat_dev, long long n, double* u_dev,
+                     void* workspace_dev, size_t workspace_bytes, hipStream_t stream);
+
+/* One preconditioning step t = P(theta) r on the context: the learned step (fused BF16
+ * inference, as used inside adc3_ea_davidson) if a preconditioner is set, else the
+ * Jacobi step r/(D - theta).  r_dev, t_dev: adc3_ea_dim() doubles on the device.
+ * *fallback (nullable) is set to 1 if a non-finite learned step fell back to Jacobi
+ * at some element. */
+int adc3_ea_precondition(adc3_ctx* ctx, double theta, const double* r_dev, double* t_dev, int* fallback,
+                         hipStream_t stream);
+
+/* Adam training on the GPU (lr, beta 0.9/0.999, eps 1e-8): epochs over the groups in a
+ * seeded shuffled order, batch_groups groups per step; weights_dev updated in place
+ * (FP32 master weights); loss_per_epoch (host, nullable) receives the mean batch loss. */
+int adc3_mlp_train(float* weights_dev, const double* feat_dev, const double* a0_dev, const double* target_dev,
+                   int ngroups, int group_size, int epochs, int batch_groups, double lr, unsigned long long seed,
+                   double* loss_per_epoch, void* workspace_dev, size_t workspace_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Timing (tracing aid, not part of the method).  When enabled, HIP events are

@@ -21,12 +21,15 @@ ADC3_EINVAL, ADC3_ENOMEM, ADC3_EHIP, ADC3_ENUMERIC, ADC3_EUNSUP = -1, -2, -3, -4
 EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_bytes", "adc3_ea_solve",
            "adc3_ea_setup_workspace_bytes", "adc3_ea_setup", "adc3_ctx_destroy", "adc3_ea_dim",
            "adc3_ea_sigma", "adc3_ea_diagonal", "adc3_ea_davidson", "adc3_ea_dense_matrix",
-           "adc3_ea_intermediate", "adc3_profile_enable", "adc3_profile_query"]
+           "adc3_ea_intermediate", "adc3_profile_enable", "adc3_profile_query", "adc3_mlp_nparams",
+           "adc3_ea_set_preconditioner", "adc3_mlp_collect", "adc3_mlp_workspace_bytes", "adc3_mlp_loss_grad",
+           "adc3_mlp_forward", "adc3_mlp_train", "adc3_ea_precondition"]
 
 
 class adc3_opts(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int), ("max_iter", ctypes.c_int), ("max_subspace", ctypes.c_int),
-                ("fno_correction", ctypes.c_int), ("precision", ctypes.c_int), ("precond", ctypes.c_int)]
+                ("fno_correction", ctypes.c_int), ("precision", ctypes.c_int), ("precond", ctypes.c_int),
+                ("mlp_weights", ctypes.c_void_p)]
 
 
 class adc3_root_report(ctypes.Structure):
@@ -86,6 +89,23 @@ def load():
     lib.adc3_profile_enable.restype = None
     lib.adc3_profile_query.argtypes = [I, ctypes.POINTER(D), ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.adc3_profile_query.restype = I
+    U64 = ctypes.c_ulonglong
+    lib.adc3_mlp_nparams.argtypes = []
+    lib.adc3_mlp_nparams.restype = I
+    lib.adc3_ea_set_preconditioner.argtypes = [P, P]
+    lib.adc3_ea_set_preconditioner.restype = I
+    lib.adc3_mlp_collect.argtypes = [P, I, D, I, I, I, U64, P, P, P, ctypes.POINTER(I), P]
+    lib.adc3_mlp_collect.restype = I
+    lib.adc3_mlp_workspace_bytes.argtypes = [I, I]
+    lib.adc3_mlp_workspace_bytes.restype = S
+    lib.adc3_mlp_loss_grad.argtypes = [P, P, P, P, I, I, P, ctypes.POINTER(D), P, S, P]
+    lib.adc3_mlp_loss_grad.restype = I
+    lib.adc3_mlp_forward.argtypes = [P, P, LL, P, P, S, P]
+    lib.adc3_mlp_forward.restype = I
+    lib.adc3_mlp_train.argtypes = [P, P, P, P, I, I, I, I, D, U64, P, P, S, P]
+    lib.adc3_mlp_train.restype = I
+    lib.adc3_ea_precondition.argtypes = [P, D, P, P, ctypes.POINTER(I), P]
+    lib.adc3_ea_precondition.restype = I
     _lib = lib
     return lib
 
@@ -102,6 +122,15 @@ def _ptr(t):
         return None
     if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise ValueError("expected a contiguous float64 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptrf(t):
+    import torch
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float32 tensor on the GPU")
     return ctypes.c_void_p(t.data_ptr())
 
 
@@ -204,6 +233,33 @@ class Context:
         _check(st, allow_noconv=True)
         return np.array(w[:]), vec, np.array(rn[:]), it.value, st
 
+    def set_preconditioner(self, weights):
+        """Learned preconditioner for davidson() (float32 device weights; None: Jacobi)."""
+        self._mlp_weights = weights
+        _check(load().adc3_ea_set_preconditioner(self.handle, _ptrf(weights)))
+
+    def precondition(self, theta, r):
+        """(t, fallback): one preconditioning step on residual r (learned if set, else Jacobi)."""
+        import torch
+        t = torch.empty_like(r)
+        fb = ctypes.c_int()
+        _check(load().adc3_ea_precondition(self.handle, float(theta), _ptr(r.contiguous()), _ptr(t),
+                                           ctypes.byref(fb), _stream()))
+        return t, bool(fb.value)
+
+    def mlp_collect(self, nroots, conv, group_size, max_groups, seed, max_iter=500):
+        """Training groups from a Jacobi Davidson solve: (feat[G,S,6], a0[G,S], target[G,S], status)."""
+        import torch
+        F = torch.zeros((max_groups, group_size, 6), dtype=torch.float64, device="cuda")
+        A = torch.zeros((max_groups, group_size), dtype=torch.float64, device="cuda")
+        T = torch.zeros((max_groups, group_size), dtype=torch.float64, device="cuda")
+        ng = ctypes.c_int()
+        st = load().adc3_mlp_collect(self.handle, nroots, conv, max_iter, group_size, max_groups, seed, _ptr(F),
+                                     _ptr(A), _ptr(T), ctypes.byref(ng), _stream())
+        _check(st, allow_noconv=True)
+        g = ng.value
+        return F[:g], A[:g], T[:g], st
+
     def dense(self):
         import torch
         M = torch.empty((self.N, self.N), dtype=torch.float64, device="cuda")
@@ -220,6 +276,50 @@ class Context:
 
 
 adc3_ea_setup = Context
+
+
+def adc3_mlp_nparams():
+    return load().adc3_mlp_nparams()
+
+
+def adc3_mlp_workspace_bytes(batch_groups, group_size):
+    return load().adc3_mlp_workspace_bytes(batch_groups, group_size)
+
+
+def adc3_mlp_loss_grad(weights, feat, a0, target, want_grad=True):
+    """(loss, grad[nparams] float64 device tensor or None) for groups feat[G,S,6], a0/target[G,S]."""
+    import torch
+    G, S = int(a0.shape[0]), int(a0.shape[1])
+    ws = _workspace(adc3_mlp_workspace_bytes(G, S))
+    grad = torch.empty(adc3_mlp_nparams(), dtype=torch.float64, device="cuda") if want_grad else None
+    loss = ctypes.c_double()
+    _check(load().adc3_mlp_loss_grad(_ptrf(weights), _ptr(feat.contiguous()), _ptr(a0.contiguous()),
+                                     _ptr(target.contiguous()), G, S, _ptr(grad), ctypes.byref(loss),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return loss.value, grad
+
+
+def adc3_mlp_forward(weights, feat):
+    """u[n] = MLP(feat[n,6]) as in training (FP32 matrix cores)."""
+    import torch
+    n = int(feat.shape[0])
+    ws = _workspace(adc3_mlp_workspace_bytes(1, n))
+    u = torch.empty(n, dtype=torch.float64, device="cuda")
+    _check(load().adc3_mlp_forward(_ptrf(weights), _ptr(feat.contiguous()), n, _ptr(u),
+                                   ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return u
+
+
+def adc3_mlp_train(weights, feat, a0, target, epochs, batch_groups, lr, seed):
+    """Adam training in place on float32 device weights; returns the mean loss of every epoch."""
+    G, S = int(a0.shape[0]), int(a0.shape[1])
+    b = min(batch_groups, G)
+    ws = _workspace(adc3_mlp_workspace_bytes(b, S))
+    losses = (ctypes.c_double * epochs)()
+    _check(load().adc3_mlp_train(_ptrf(weights), _ptr(feat.contiguous()), _ptr(a0.contiguous()),
+                                 _ptr(target.contiguous()), G, S, epochs, b, float(lr), seed, losses,
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return np.array(losses[:])
 
 
 PROF_LADDER, PROF_SIGMA, PROF_SETUP, PROF_DAVIDSON, PROF_EIG, PROF_LADDER_LP = range(6)

@@ -95,6 +95,9 @@ struct Ctx {
     int prec = 0;
     void* Glo = nullptr;
     float* Uz32 = nullptr;
+    // learned preconditioner: weights (caller's device memory) and the BF16 W2 copy
+    const float* mlp_w = nullptr;
+    unsigned short* mlp_wb = nullptr;
 };
 
 static double* take(Arena& ws, long long n) { return ws.take<double>((size_t)std::max<long long>(n, 1)); }
@@ -145,6 +148,7 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             else c->Glo = ws.take<unsigned short>((size_t)(vv * vv));
         }
     }
+    c->mlp_wb = ws.take<unsigned short>(256 * 256);
     c->zb = take(ws, NVMAX * (long long)o * vv);
     c->xb = take(ws, NVMAX * (long long)o * vv);
     c->xtb = take(ws, NVMAX * (long long)o * vv);
@@ -372,6 +376,14 @@ static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nve
 // ---------------------------------------------------------------------------
 // Davidson (FP64, device-resident subspace)
 // ---------------------------------------------------------------------------
+// Training-data recorder of a replayed Jacobi solve whose converged vectors xf are known.
+struct Recorder {
+    int S = 0, Gmax = 0, G = 0;
+    unsigned long long seed = 0;
+    const double* xf = nullptr;                        // converged vectors [nroots][N]
+    double *F = nullptr, *A0 = nullptr, *D = nullptr;  // caller buffers [Gmax][S][6], [Gmax][S], [Gmax][S]
+};
+
 struct DavResult {
     std::vector<double> w, rn;
     std::vector<double> w_lowp;  // Ritz values when the reduced-precision phase ended
@@ -380,7 +392,8 @@ struct DavResult {
 };
 
 static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int max_iter, int max_sub,
-                               double* vec_out, hipStream_t s, int prec = 0) {
+                               double* vec_out, hipStream_t s, int prec = 0, bool use_mlp = false,
+                               Recorder* rec = nullptr) {
     if (prec > c->prec) prec = c->prec;
     ProfScope prof(PROF_DAVIDSON, s, 0.0, 0.0);
     const long long N = c->N;
@@ -407,6 +420,7 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     double* Vk = take(ws, (long long)nkeep_max * N);
     double* Sk = take(ws, (long long)nkeep_max * N);
     double* small = take(ws, 16);
+    unsigned int* mflag = (unsigned int*)take(ws, 1);
     double* part = take(ws, (long long)dots_partial_elems(mmax, mmax, N));
     DavResult res;
     res.w.assign(nroots, 0.0);
@@ -431,7 +445,9 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     int stall = 0, it_lp = 0;
     sigma_impl(c, ws, V, S, m, s, phase);
     k_dots(V, N, m, S, N, m, N, Gf, mmax, part, s);
-    std::vector<double> thold(nroots, INFINITY), hw(mmax), hrn(nroots * nroots);
+    std::vector<double> thold(nroots, INFINITY), hw(mmax), hrn(nroots * nroots), prev_rn(nroots, INFINITY);
+    std::vector<char> mlp_on(nroots, (use_mlp && c->mlp_w) ? 1 : 0);
+    if (use_mlp && c->mlp_w) mlp_weights_bf16(c->mlp_w, c->mlp_wb, s);
     std::vector<double> hY;
     int it = 0;
     for (;;) {
@@ -514,12 +530,47 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
             res.converged = false;
             break;
         }
+        // training data: features and Jacobi step at sampled elements, with the target the part of the
+        // converged vector outside the current subspace, xf - V (V^T xf)
+        if (rec) {
+            for (int j = 0; j < nn && rec->G < rec->Gmax; ++j) {
+                const int k = todo[j];
+                const double rms = std::max(res.rn[k] / std::sqrt((double)N), 1e-300);
+                const long long off = (long long)rec->G * rec->S;
+                double* miss = Vk;  // free until the next collapse
+                k_copy(miss, rec->xf + (long long)k * N, N, s);
+                k_dots(V, N, m, miss, N, 1, N, Gw, 1, part, s);
+                k_lincomb(miss, N, 1, V, N, m, Gw, 1, N, -1.0, 1.0, s);
+                mlp_features_idx(R + (long long)k * N, c->diag, res.w[k], rms, c->eo, c->ev, c->o, c->v, rec->seed,
+                                 rec->G, rec->S, N, miss, rec->F + off * 6, rec->A0 + off, rec->D + off, s);
+                rec->G++;
+            }
+        }
         // preconditioned residuals of the unconverged roots -> V[m .. m+nn)
         double* Tn = V + (long long)m * N;
         for (int j = 0; j < nn; ++j) {
             int k = todo[j];
-            k_precond(Tn + (long long)j * N, R + (long long)k * N, c->diag, th + k, 1, N, s);
+            if (mlp_on[k] && it > 1 && res.rn[k] > 2.0 * prev_rn[k]) {
+                mlp_on[k] = 0;  // the learned step made the residual grow: Jacobi from here on
+                VLOG("root %d: learned preconditioner disabled (residual grew)", k);
+            }
+            bool done_mlp = false;
+            if (mlp_on[k]) {
+                const double rms = std::max(res.rn[k] / std::sqrt((double)N), 1e-300);
+                HIPCHK(hipMemsetAsync(mflag, 0, sizeof(unsigned int), s));
+                mlp_precondition(R + (long long)k * N, c->diag, res.w[k], rms, c->eo, c->ev, c->o, c->v, N, c->mlp_w,
+                                 c->mlp_wb, Tn + (long long)j * N, mflag, s);
+                unsigned int hf = 0;
+                d2h(&hf, mflag, sizeof(hf), s);
+                done_mlp = (hf == 0);
+                if (!done_mlp) {
+                    mlp_on[k] = 0;
+                    VLOG("root %d: learned preconditioner gave a non-finite step; Jacobi from here on", k);
+                }
+            }
+            if (!done_mlp) k_precond(Tn + (long long)j * N, R + (long long)k * N, c->diag, th + k, 1, N, s);
         }
+        for (int k = 0; k < nroots; ++k) prev_rn[k] = res.rn[k];
         // unit rows, then block orthonormalisation against V and within the block, twice
         k_dots(Tn, N, nn, Tn, N, nn, N, Gw, nn, part, s);
         k_rscale_rows(Tn, nn, N, Gw, nn, s);
@@ -707,7 +758,9 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     if (!(fno > 0) && !(naf > 0)) {
         const size_t mark = ws.mark();
         Ctx* c = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, level, s, op.precision);
-        DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision);
+        c->mlp_w = op.mlp_weights;
+        DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
+                                    op.precond == 1);
         for (int k = 0; k < nroots; ++k) {
             auto& R = out.rep[k];
             R.omega = R.omega_uncorr = r.w[k];
@@ -798,7 +851,9 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         {
             const size_t m3 = ws.mark();
             Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s, op.precision);
-            DavResult a3 = davidson_impl(c3, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision);
+            c3->mlp_w = op.mlp_weights;
+            DavResult a3 = davidson_impl(c3, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
+                                         op.precond == 1);
             R.omega_uncorr = a3.w[match];
             R.omega_lowp = a3.w_lowp.empty() ? a3.w[match] : a3.w_lowp[match];
             R.iters_lowp = a3.iters_lowp;
@@ -857,6 +912,7 @@ void adc3_default_opts(adc3_opts* o) {
     o->fno_correction = 1;
     o->precision = 0;
     o->precond = 0;
+    o->mlp_weights = nullptr;
 }
 
 const char* adc3_last_error(void) { return g_msg.c_str(); }
@@ -884,6 +940,7 @@ size_t adc3_ea_setup_workspace_bytes(int nocc, int nvir, int naux, int level, in
         }
         if (nroots > 0) {
             Arena w3 = ws;
+            take(w3, (long long)std::min<long long>(nroots, c->N) * c->N);  // converged vectors of adc3_mlp_collect
             davidson_impl(c, w3, (int)std::min<long long>(nroots, c->N), 1.0, 1, 0, nullptr, nullptr, precision);
             ws.peak = std::max(ws.peak, w3.peak);
         }
@@ -963,7 +1020,8 @@ int adc3_ea_davidson(adc3_ctx* ctx, int nroots, double conv, int max_iter, int m
     if (precision < 0 || precision > ctx->c->prec)
         fail(ADC3_EINVAL, "precision not available in this context (set it at setup)");
     Arena ws = ctx->c->ws;
-    DavResult r = davidson_impl(ctx->c, ws, nroots, conv, max_iter, max_subspace, vectors, stream, precision);
+    DavResult r = davidson_impl(ctx->c, ws, nroots, conv, max_iter, max_subspace, vectors, stream, precision,
+                                ctx->c->mlp_w != nullptr);
     for (int k = 0; k < nroots; ++k) {
         omega[k] = r.w[k];
         if (resnorm) resnorm[k] = r.rn[k];
@@ -1051,7 +1109,8 @@ static adc3_opts resolve_opts(const adc3_opts* opts) {
     if (o.level != 2 && o.level != 3) fail(ADC3_EINVAL, "opts.level must be 2 or 3");
     if (o.max_iter < 1) fail(ADC3_EINVAL, "opts.max_iter must be >= 1");
     if (o.precision < 0 || o.precision > 2) fail(ADC3_EUNSUP, "opts.precision must be 0 (FP64), 1 (FP32) or 2 (BF16)");
-    if (o.precond != 0) fail(ADC3_EUNSUP, "only the Jacobi preconditioner (precond 0) is supported");
+    if (o.precond != 0 && o.precond != 1) fail(ADC3_EUNSUP, "opts.precond must be 0 (Jacobi) or 1 (learned)");
+    if (o.precond == 1 && !o.mlp_weights) fail(ADC3_EINVAL, "opts.precond = 1 needs opts.mlp_weights");
     return o;
 }
 
@@ -1119,5 +1178,163 @@ extern "C" int adc3_ea_solve(const double* eps_occ, const double* eps_vir, const
         if (reports) reports[k] = r.rep[k];
     }
     return r.all_conv ? ADC3_OK : ADC3_WNOCONV;
+    API_END
+}
+
+extern "C" int adc3_mlp_nparams(void) { return mlp_nparam(); }
+
+extern "C" int adc3_ea_set_preconditioner(adc3_ctx* ctx, const float* weights) {
+    API_BEGIN
+    if (!ctx) fail(ADC3_EINVAL, "NULL ctx");
+    ctx->c->mlp_w = weights;
+    return ADC3_OK;
+    API_END
+}
+
+extern "C" int adc3_mlp_collect(adc3_ctx* ctx, int nroots, double conv, int max_iter, int group_size, int max_groups,
+                                unsigned long long seed, double* feat, double* a0, double* target, int* ngroups,
+                                hipStream_t stream) {
+    API_BEGIN
+    if (!ctx || !feat || !a0 || !target || !ngroups) fail(ADC3_EINVAL, "NULL argument");
+    if (group_size < 1 || max_groups < 0) fail(ADC3_EINVAL, "group_size must be >= 1 and max_groups >= 0");
+    if (!(conv > 0)) fail(ADC3_EINVAL, "conv must be > 0");
+    if (nroots < 1 || nroots > ctx->c->N) fail(ADC3_EINVAL, "nroots out of range");
+    Arena ws = ctx->c->ws;
+    double* xf = take(ws, (long long)nroots * ctx->c->N);
+    // pass 1: converged vectors; pass 2 replays the same (deterministic) solve and records
+    DavResult r = davidson_impl(ctx->c, ws, nroots, conv, max_iter, 0, xf, stream, 0, false, nullptr);
+    Recorder rec;
+    rec.S = group_size; rec.Gmax = max_groups; rec.seed = seed; rec.xf = xf;
+    rec.F = feat; rec.A0 = a0; rec.D = target;
+    davidson_impl(ctx->c, ws, nroots, conv, max_iter, 0, nullptr, stream, 0, false, &rec);
+    *ngroups = rec.G;
+    return r.converged ? ADC3_OK : ADC3_WNOCONV;
+    API_END
+}
+
+extern "C" size_t adc3_mlp_workspace_bytes(int batch_groups, int group_size) {
+    const long long n = (long long)batch_groups * group_size;
+    if (n <= 0) return 0;
+    return (mlp_scratch_elems(n) + 3 * (size_t)n + 6 * (size_t)n + 4 * (size_t)mlp_nparam() + GEMM_SCRATCH + 4096) *
+           sizeof(double) + (1 << 20);
+}
+
+extern "C" int adc3_mlp_loss_grad(const float* weights, const double* feat, const double* a0, const double* target,
+                                  int ngroups, int group_size, double* grad, double* loss, void* workspace,
+                                  size_t ws_bytes, hipStream_t stream) {
+    API_BEGIN
+    if (!weights || !feat || !a0 || !target || !loss || !workspace) fail(ADC3_EINVAL, "NULL argument");
+    if (ngroups < 1 || group_size < 1) fail(ADC3_EINVAL, "ngroups and group_size must be >= 1");
+    Arena ws;
+    ws.base = (char*)workspace;
+    ws.cap = ws_bytes;
+    const long long n = (long long)ngroups * group_size;
+    double* scr = take(ws, (long long)mlp_scratch_elems(n));
+    GemmScratch gscr(ws, GEMM_SCRATCH);
+    *loss = mlp_loss_grad(weights, feat, a0, target, ngroups, group_size, grad, scr, nullptr, stream);
+    return ADC3_OK;
+    API_END
+}
+
+extern "C" int adc3_mlp_forward(const float* weights, const double* feat, long long n, double* u, void* workspace,
+                                size_t ws_bytes, hipStream_t stream) {
+    API_BEGIN
+    if (!weights || !feat || !u || !workspace) fail(ADC3_EINVAL, "NULL argument");
+    if (n < 1) fail(ADC3_EINVAL, "n must be >= 1");
+    Arena ws;
+    ws.base = (char*)workspace;
+    ws.cap = ws_bytes;
+    double* H = take(ws, 4 * n * 256);
+    GemmScratch gscr(ws, GEMM_SCRATCH);
+    mlp_forward(weights, feat, n, u, H, H + n * 256, H + 2 * n * 256, H + 3 * n * 256, stream);
+    HIPCHK(hipStreamSynchronize(stream));
+    return ADC3_OK;
+    API_END
+}
+
+extern "C" int adc3_mlp_train(float* weights, const double* feat, const double* a0, const double* target, int ngroups,
+                              int group_size, int epochs, int batch_groups, double lr, unsigned long long seed,
+                              double* loss_per_epoch, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    API_BEGIN
+    if (!weights || !feat || !a0 || !target || !workspace) fail(ADC3_EINVAL, "NULL argument");
+    if (ngroups < 1 || group_size < 1 || epochs < 1 || batch_groups < 1) fail(ADC3_EINVAL, "sizes must be >= 1");
+    batch_groups = std::min(batch_groups, ngroups);
+    Arena ws;
+    ws.base = (char*)workspace;
+    ws.cap = ws_bytes;
+    const int S = group_size;
+    const long long n = (long long)batch_groups * S;
+    const int P = mlp_nparam();
+    double* scr = take(ws, (long long)mlp_scratch_elems(n));
+    double* bF = take(ws, n * 6);
+    double* bA = take(ws, n);
+    double* bD = take(ws, n);
+    double* grad = take(ws, P);
+    double* mom = take(ws, P);
+    double* var = take(ws, P);
+    GemmScratch gscr(ws, GEMM_SCRATCH);
+    k_fill(mom, P, 0.0, stream);
+    k_fill(var, P, 0.0, stream);
+    // deterministic shuffles (splitmix64 on the host)
+    unsigned long long st = seed;
+    auto next = [&]() {
+        unsigned long long z = (st += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    };
+    std::vector<int> order(ngroups);
+    int step = 0;
+    for (int ep = 0; ep < epochs; ++ep) {
+        for (int g = 0; g < ngroups; ++g) order[g] = g;
+        for (int g = ngroups - 1; g > 0; --g) std::swap(order[g], order[(int)(next() % (unsigned long long)(g + 1))]);
+        double lsum = 0.0;
+        int nb = 0;
+        for (int b0 = 0; b0 + batch_groups <= ngroups; b0 += batch_groups) {
+            for (int j = 0; j < batch_groups; ++j) {
+                const long long src = (long long)order[b0 + j] * S;
+                k_copy(bF + (long long)j * S * 6, feat + src * 6, (long long)S * 6, stream);
+                k_copy(bA + (long long)j * S, a0 + src, S, stream);
+                k_copy(bD + (long long)j * S, target + src, S, stream);
+            }
+            lsum += mlp_loss_grad(weights, bF, bA, bD, batch_groups, S, grad, scr, nullptr, stream);
+            mlp_adam(weights, grad, mom, var, lr, ++step, stream);
+            ++nb;
+        }
+        if (loss_per_epoch) loss_per_epoch[ep] = nb ? lsum / nb : 0.0;
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+    return ADC3_OK;
+    API_END
+}
+
+extern "C" int adc3_ea_precondition(adc3_ctx* ctx, double theta, const double* r, double* t, int* fallback,
+                                    hipStream_t stream) {
+    API_BEGIN
+    if (!ctx || !r || !t) fail(ADC3_EINVAL, "NULL argument");
+    Ctx* c = ctx->c;
+    Arena ws = c->ws;
+    unsigned int* flag = (unsigned int*)take(ws, 1);
+    double* th = take(ws, 1);
+    int fb = 0;
+    if (c->mlp_w) {
+        double* part = take(ws, (long long)dots_partial_elems(1, 1, c->N));
+        k_dots(r, c->N, 1, r, c->N, 1, c->N, th, 1, part, stream);
+        double nrm2 = 0;
+        d2h(&nrm2, th, sizeof(double), stream);
+        const double rms = std::max(std::sqrt(nrm2 / (double)c->N), 1e-300);
+        HIPCHK(hipMemsetAsync(flag, 0, sizeof(unsigned int), stream));
+        mlp_weights_bf16(c->mlp_w, c->mlp_wb, stream);
+        mlp_precondition(r, c->diag, theta, rms, c->eo, c->ev, c->o, c->v, c->N, c->mlp_w, c->mlp_wb, t, flag, stream);
+        unsigned int hf = 0;
+        d2h(&hf, flag, sizeof(hf), stream);
+        fb = hf != 0;
+    } else {
+        h2d(th, &theta, sizeof(double), stream);
+        k_precond(t, r, c->diag, th, 1, c->N, stream);
+    }
+    HIPCHK(hipStreamSynchronize(stream));
+    if (fallback) *fallback = fb;
+    return ADC3_OK;
     API_END
 }

@@ -27,6 +27,7 @@ __global__ __launch_bounds__(NT) void gemm_f32_kernel(GemmLP g) {
     const int cz = blockIdx.z;
     const float* __restrict__ Bf = (const float*)g.B + cz * g.bB;
     const double* __restrict__ Ag = g.A + cz * g.bA;
+    const float* __restrict__ Agf = g.Af ? g.Af + cz * g.bA : nullptr;
     double* __restrict__ Cg = g.C + cz * g.bC;
     const int K = (g.Klast >= 0 && cz == (int)gridDim.z - 1) ? g.Klast : g.K;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -51,7 +52,8 @@ __global__ __launch_bounds__(NT) void gemm_f32_kernel(GemmLP g) {
 #pragma unroll
         for (int p = 0; p < PA; ++p) {
             long long m = m0 + ar[p], k = k0 + ak[p];
-            ra[p] = (ar[p] >= 0 && m < g.M && k < K) ? (float)Ag[m * g.sAm + k * g.sAk] : 0.f;
+            ra[p] = (ar[p] >= 0 && m < g.M && k < K) ? (Agf ? Agf[m * g.sAm + k * g.sAk] : (float)Ag[m * g.sAm + k * g.sAk])
+                                                    : 0.f;
         }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {

@@ -72,6 +72,7 @@ void gemm(const Gemm& g, hipStream_t s, int tag = 0);
 struct GemmLP {
     int M = 0, N = 0, K = 0;
     const double* A = nullptr; long long sAm = 0, sAk = 0;
+    const float* Af = nullptr;  // if set (prec 1 only): A read as FP32 instead of A
     const void* B = nullptr; long long sBk = 0, sBn = 0;
     double* C = nullptr; long long sCm = 0, sCn = 0;
     double alpha = 1.0, beta = 0.0;
@@ -179,5 +180,21 @@ void eig_large(double* A, int n, double* w, double* V, double* scratch, hipStrea
 size_t eig_large_scratch(int n);
 // reorder eigenpairs descending (desc=1) or ascending and fix signs (largest |.| positive)
 void k_sort_eig(double* w, double* V, int n, int desc, double* wtmp, double* Vtmp, hipStream_t s);
+
+// learned preconditioner (mlp.hip)
+int mlp_nparam();
+size_t mlp_scratch_elems(long long n);
+void mlp_forward(const float* w, const double* X, long long n, double* u, double* Z1, double* H1, double* Z2,
+                 double* H2, hipStream_t s);
+double mlp_loss_grad(const float* w, const double* X, const double* a0, const double* d, int G, int S, double* grad,
+                     double* scratch, double* Lg_host, hipStream_t s);
+void mlp_adam(float* w, const double* grad, double* m, double* v, double lr, int step, hipStream_t s);
+void mlp_weights_bf16(const float* w, unsigned short* wt, hipStream_t s);
+void mlp_precondition(const double* r, const double* D, double theta, double rms, const double* eo, const double* ev,
+                      int o, int v, long long N, const float* w, const unsigned short* wt, double* T,
+                      unsigned int* flag, hipStream_t s);
+void mlp_features_idx(const double* r, const double* D, double theta, double rms, const double* eo, const double* ev,
+                      int o, int v, unsigned long long seed, int g, int S, long long N, const double* xk, double* F,
+                      double* a0, double* xs, hipStream_t s);
 
 }  // namespace adc3

@@ -18,7 +18,7 @@ natural-orbital truncation actually removes virtuals.
 """
 import numpy as np
 
-__all__ = ["make_instance", "preset", "batch_shapes", "PRESETS"]
+__all__ = ["make_instance", "preset", "batch_shapes", "PRESETS", "mlp_init", "mlp_features_draw"]
 
 
 def make_instance(nocc, nvir, naux, seed, scale=1.0, rng=None):
@@ -68,3 +68,36 @@ def preset(name, scale=1.0):
     p = dict(PRESETS[name])
     eo, ev, B = make_instance(p["nocc"], p["nvir"], p["naux"], p["seed"], scale=scale)
     return p, eo, ev, B
+
+
+# Learned-preconditioner network: 6 -> 256 -> 256 -> 1, flat float32 layout
+# W1[6][256], b1[256], W2[256][256], b2[256], W3[256], b3[1].
+MLP_SIZES = (6 * 256, 256, 256 * 256, 256, 256, 1)
+
+
+def mlp_init(seed, head_scale=0.0):
+    """Initial weights: W1 ~ N(0, 1/6), W2 ~ N(0, 1/256), zero biases, W3 ~ head_scale * N(0, 1/256), b3 = 0.
+
+    head_scale = 0 makes the initial network output zero everywhere."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal(6 * 256) / np.sqrt(6.0)
+    W2 = rng.standard_normal(256 * 256) / 16.0
+    W3 = head_scale * rng.standard_normal(256) / 16.0
+    w = np.concatenate([W1, np.zeros(256), W2, np.zeros(256), W3, np.zeros(1)])
+    return w.astype(np.float32)
+
+
+def mlp_features_draw(n_groups, group, seed):
+    """Random (features[G*S, 6], a0[G*S], target[G*S]) of feature-like magnitudes for kernel checks."""
+    rng = np.random.default_rng(seed)
+    n = n_groups * group
+    F = np.empty((n, 6))
+    F[:, 0] = rng.uniform(0.0, 4.0, n)
+    F[:, 1] = rng.standard_normal(n)
+    F[:, 2] = (rng.uniform(size=n) < 0.1).astype(np.float64)
+    F[:, 3] = rng.uniform(0.05, 3.0, n)
+    F[:, 4] = rng.uniform(0.05, 3.0, n) * (1 - F[:, 2])
+    F[:, 5] = rng.uniform(-1.5, -0.3, n) * (1 - F[:, 2])
+    a0 = rng.standard_normal(n) * 1e-3
+    d = a0 * (1.0 + 0.3 * rng.standard_normal(n)) + 1e-4 * rng.standard_normal(n)
+    return F, a0, d

@@ -1,0 +1,202 @@
+"""Learned Davidson preconditioner on the GPU: training forward and gradients against
+the FP64 NumPy reference, the fused BF16 inference kernel against the reference step,
+the Jacobi fallback, training, root agreement with the Jacobi solve, and a gain study on
+held-out seeds."""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp_ref
+from oracle.adc_cs import Problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2511_05897_amd as adc  # noqa: E402
+
+# BF16 keeps an 8-bit significand (unit roundoff 2^-9); the fused kernel rounds the
+# layer-1 activations and W2 to it, so z2 carries a relative error of a few 2^-9 and u
+# (a 256-term sum of GELU(z2) W3) the same relative to its magnitude.
+BF16_MAX, BF16_RMS = 3e-2, 1e-2
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def devf(w):
+    return torch.as_tensor(np.ascontiguousarray(w, dtype=np.float32), device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def weights(seed, head=1.0, b1=0.05):
+    w = synth.mlp_init(seed, head_scale=head)
+    w[6 * 256:6 * 256 + 256] = b1
+    return w
+
+
+def test_forward_fp32_matches_reference():
+    w = weights(3)
+    F, _, _ = synth.mlp_features_draw(1, 5003, 11)  # ragged against the 128-row tiles
+    uref, _ = mlp_ref.forward(w.astype(np.float64), F)
+    u = host(adc.adc3_mlp_forward(devf(w), dev(F)))
+    # FP32 operands, FP32 accumulation over 256 terms
+    assert np.abs(u - uref).max() <= 1e-5 * max(1.0, np.abs(uref).max())
+
+
+@pytest.mark.parametrize("G,S", [(8, 301), (1, 64), (33, 97)])
+def test_loss_and_gradient_match_reference(G, S):
+    w = weights(4)
+    F, a0, d = synth.mlp_features_draw(G, S, 12 + G)
+    wd = w.astype(np.float64)
+    lref = mlp_ref.loss(wd, F, a0, d, S)
+    gref = mlp_ref.grad(wd, F, a0, d, S)
+    loss, g = adc.adc3_mlp_loss_grad(devf(w), dev(F.reshape(G, S, 6)), dev(a0.reshape(G, S)),
+                                     dev(d.reshape(G, S)))
+    g = host(g)
+    assert abs(loss - lref) <= 1e-6 * abs(lref)
+    offs = np.cumsum([0] + list(synth.MLP_SIZES))
+    for b in range(6):
+        sl = slice(offs[b], offs[b + 1])
+        rel = np.linalg.norm(g[sl] - gref[sl]) / np.linalg.norm(gref[sl])
+        assert rel <= 1e-5, (b, rel)
+
+
+def _ctx(o, v, x, seed, scale, nroots=5, level=3):
+    eo, ev, B = synth.make_instance(o, v, x, seed, scale=scale)
+    return (eo, ev, B), adc.Context(dev(eo), dev(ev), dev(B), level, nroots=nroots)
+
+
+def test_fused_preconditioner_matches_reference():
+    (eo, ev, B), ctx = _ctx(4, 20, 60, 0, 0.3)
+    D = Problem(eo, ev, B).diagonal(3)
+    r = np.random.default_rng(21).standard_normal(ctx.N) * 1e-3
+    theta = 0.37
+    # Jacobi without weights
+    t, fb = ctx.precondition(theta, dev(r))
+    assert not fb
+    assert np.abs(host(t) - r / (D - theta)).max() <= 1e-12 * np.abs(r / (D - theta)).max()
+    # learned step
+    w = weights(3)
+    wt = devf(w)
+    ctx.set_preconditioner(wt)
+    t, fb = ctx.precondition(theta, dev(r))
+    assert not fb
+    a0 = r / (D - theta)
+    u, _ = mlp_ref.forward(w.astype(np.float64), mlp_ref.features(r, theta, D, eo, ev, 4, 20))
+    err = (host(t) - a0 * (1 + u)) / np.abs(a0)
+    scale = max(1.0, np.abs(u).max())
+    assert np.abs(err).max() <= BF16_MAX * scale
+    assert np.sqrt(np.mean(err ** 2)) <= BF16_RMS * scale
+
+
+def test_fused_preconditioner_nonfinite_falls_back():
+    (eo, ev, B), ctx = _ctx(3, 12, 30, 1, 0.3)
+    D = Problem(eo, ev, B).diagonal(3)
+    w = weights(5)
+    w[-1] = np.inf  # b3 = inf: every learned step is non-finite
+    wt = devf(w)
+    ctx.set_preconditioner(wt)
+    r = np.random.default_rng(2).standard_normal(ctx.N)
+    t, fb = ctx.precondition(0.1, dev(r))
+    assert fb
+    a0 = r / (D - 0.1)
+    assert np.abs(host(t) - a0).max() <= 1e-12 * np.abs(a0).max()
+
+
+def test_training_reduces_loss_on_learnable_target():
+    G, S = 256, 128
+    F, a0, _ = synth.mlp_features_draw(G, S, 30)
+    d = a0 * (1.0 + 0.5 * np.tanh(F[:, 0] - 2.0) - 0.3 * F[:, 2])  # a smooth function of the features
+    w = devf(synth.mlp_init(2))
+    args = (dev(F.reshape(G, S, 6)), dev(a0.reshape(G, S)), dev(d.reshape(G, S)))
+    l0, _ = adc.adc3_mlp_loss_grad(w, *args, want_grad=False)
+    losses = adc.adc3_mlp_train(w, *args, epochs=30, batch_groups=16, lr=2e-3, seed=9)
+    l1, _ = adc.adc3_mlp_loss_grad(w, *args, want_grad=False)
+    print("loss", l0, "->", l1, "epochs", losses[[0, 9, 29]])
+    assert l1 < 0.1 * l0
+    assert losses[-1] < losses[0]
+
+
+def test_learned_roots_equal_jacobi_and_oracle():
+    p, eo, ev, B = synth.preset("tiny-dense")
+    P = Problem(eo, ev, B)
+    wref = np.linalg.eigvalsh(P.dense(3))[:3]
+    ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, nroots=3)
+    wj, _, _, itj, stj = ctx.davidson(3, 1e-7)
+    wt = devf(weights(7, head=0.3))
+    ctx.set_preconditioner(wt)
+    wl, _, _, itl, stl = ctx.davidson(3, 1e-7)
+    assert stj == 0 and stl == 0
+    assert np.abs(wl - wj).max() < 1e-8
+    assert np.abs(wl - wref).max() < 1e-8
+    # the full solve with opts.precond = 1
+    o = adc.adc3_default_opts()
+    o.precond = 1
+    o.mlp_weights = wt.data_ptr()
+    roots, _, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-7, opts=o)
+    assert st == 0 and np.abs(roots - wref).max() < 1e-8
+
+
+def test_precond_option_requires_weights():
+    p, eo, ev, B = synth.preset("tiny-dense")
+    o = adc.adc3_default_opts()
+    o.precond = 1
+    with pytest.raises(adc.ADCError):
+        adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-7, opts=o)
+
+
+TRAIN_SEEDS, HELD_OUT = range(200, 240), range(240, 244)
+SHAPE, SCALE = (6, 40, 120), 0.3
+
+
+def train_learned(group=256, max_groups=50, epochs=60):
+    """Collect from Jacobi runs on the training seeds and train; returns (weights, loss history)."""
+    Fs, As, Ds = [], [], []
+    for seed in TRAIN_SEEDS:
+        _, ctx = _ctx(*SHAPE, seed, SCALE)
+        F, A, D, st = ctx.mlp_collect(5, 1e-6, group, max_groups, seed)
+        assert st == 0
+        Fs.append(F)
+        As.append(A)
+        Ds.append(D)
+        ctx.close()
+    F, A, D = torch.cat(Fs), torch.cat(As), torch.cat(Ds)
+    w = devf(synth.mlp_init(1))
+    losses = adc.adc3_mlp_train(w, F, A, D, epochs=epochs, batch_groups=32, lr=2e-3, seed=7)
+    return w, losses, int(F.shape[0])
+
+
+def test_learned_gain_on_held_out_seeds():
+    w, losses, ngroups = train_learned()
+    assert ngroups == 2000
+    assert losses[-1] < losses[0]
+    tot_j = tot_l = 0
+    tj_all = tl_all = 0.0
+    for seed in HELD_OUT:
+        _, ctx = _ctx(*SHAPE, seed, SCALE)
+        t0 = time.perf_counter()
+        wj, _, _, itj, stj = ctx.davidson(5, 1e-6)
+        tj = time.perf_counter() - t0
+        ctx.set_preconditioner(w)
+        t0 = time.perf_counter()
+        wl, _, _, itl, stl = ctx.davidson(5, 1e-6)
+        tl = time.perf_counter() - t0
+        print("seed %d  jacobi %d it %.1f ms  learned %d it %.1f ms  max|dw| %.1e"
+              % (seed, itj, 1e3 * tj, itl, 1e3 * tl, np.abs(wj - wl).max()))
+        assert stj == 0 and stl == 0
+        assert np.abs(wj - wl).max() < 1e-8
+        tot_j += itj
+        tot_l += itl
+        tj_all += tj
+        tl_all += tl
+        ctx.close()
+    print("total iterations jacobi %d learned %d; wall %.1f ms vs %.1f ms" % (tot_j, tot_l, 1e3 * tj_all,
+                                                                              1e3 * tl_all))
+    assert tot_l <= tot_j
