@@ -393,7 +393,7 @@ struct DavResult {
 
 static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int max_iter, int max_sub,
                                double* vec_out, hipStream_t s, int prec = 0, bool use_mlp = false,
-                               Recorder* rec = nullptr) {
+                               Recorder* rec = nullptr, const double* guess = nullptr, int nguess_in = 0) {
     if (prec > c->prec) prec = c->prec;
     ProfScope prof(PROF_DAVIDSON, s, 0.0, 0.0);
     const long long N = c->N;
@@ -430,16 +430,55 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
         ws.release(mark);
         return res;
     }
-    // guesses: unit vectors on the lowest diagonal entries (ties by index)
+    // Block orthonormalisation of the rows Tn[0..nn) against V[0..m) and within the block:
+    // unit rows, then (two CGS passes + Loewdin over the kept directions), repeated once when
+    // the block was strongly cancelled.  tmp holds nn rows.  Returns the number kept.
+    auto orthonormalise = [&](double* Tn, int nn, int m, double* tmp) -> int {
+        k_dots(Tn, N, nn, Tn, N, nn, N, Gw, nn, part, s);
+        k_rscale_rows(Tn, nn, N, Gw, nn, s);
+        int acc = nn;
+        bool again = true;
+        for (int round = 0; round < 2 && acc > 0 && again; ++round) {
+            if (m > 0)
+                for (int pass = 0; pass < 2; ++pass) {
+                    k_dots(V, N, m, Tn, N, acc, N, coef, acc, part, s);
+                    k_lincomb(Tn, N, acc, V, N, m, coef, acc, N, -1.0, 1.0, s);
+                }
+            // Loewdin within the block: T' = (U w^-1/2)^T T over the kept directions
+            k_dots(Tn, N, acc, Tn, N, acc, N, Gm, acc, part, s);
+            k_symmetrize(Gm, acc, s);
+            eig_small(Gm, acc, ev, Y, s);
+            k_sort_eig(ev, Y, acc, 1, Gw, Gw + acc, s);
+            std::vector<double> hq(acc);
+            d2h(hq.data(), ev, acc * sizeof(double), s);
+            int keep = 0;
+            for (int q = 0; q < acc; ++q) keep += (hq[q] > 1e-14 && std::isfinite(hq[q]));
+            if (keep == 0) return 0;
+            again = hq[keep - 1] < 0.5;  // strong cancellation: orthonormalise once more
+            k_lowdin_coef(coef, Y, ev, acc, keep, s);
+            k_lincomb(tmp, N, keep, Tn, N, acc, coef, keep, N, 1.0, 0.0, s);
+            k_copy(Tn, tmp, (long long)keep * N, s);
+            acc = keep;
+        }
+        return acc;
+    };
+    // guesses: the caller's vectors first (if any), then unit vectors on the lowest diagonal
+    // entries (ties by index)
+    const int ng = guess ? std::min(nguess_in, nguess) : 0;
     std::vector<double> hd(N);
     d2h(hd.data(), c->diag, N * sizeof(double), s);
     std::vector<long long> idx(N);
     for (long long i = 0; i < N; ++i) idx[i] = i;
     std::stable_sort(idx.begin(), idx.end(), [&](long long a, long long b) { return hd[a] < hd[b]; });
     k_fill(V, (long long)nguess * N, 0.0, s);
+    if (ng > 0) k_copy(V, guess, (long long)ng * N, s);
     std::vector<double> one(1, 1.0);
-    for (int k = 0; k < nguess; ++k) h2d(V + (long long)k * N + idx[k], one.data(), sizeof(double), s);
+    for (int k = 0; k < nguess - ng; ++k) h2d(V + (long long)(ng + k) * N + idx[k], one.data(), sizeof(double), s);
     int m = nguess;
+    if (ng > 0) {
+        m = orthonormalise(V, nguess, 0, S);
+        if (m < nroots) fail(-4, "davidson: initial guesses are linearly dependent");
+    }
     int phase = prec;  // > 0: reduced-precision sigma until its noise floor, then FP64 correction
     double best_lp = INFINITY;
     int stall = 0, it_lp = 0;
@@ -571,32 +610,7 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
             if (!done_mlp) k_precond(Tn + (long long)j * N, R + (long long)k * N, c->diag, th + k, 1, N, s);
         }
         for (int k = 0; k < nroots; ++k) prev_rn[k] = res.rn[k];
-        // unit rows, then block orthonormalisation against V and within the block, twice
-        k_dots(Tn, N, nn, Tn, N, nn, N, Gw, nn, part, s);
-        k_rscale_rows(Tn, nn, N, Gw, nn, s);
-        int acc = nn;
-        bool again = true;
-        for (int round = 0; round < 2 && acc > 0 && again; ++round) {
-            for (int pass = 0; pass < 2; ++pass) {
-                k_dots(V, N, m, Tn, N, acc, N, coef, acc, part, s);
-                k_lincomb(Tn, N, acc, V, N, m, coef, acc, N, -1.0, 1.0, s);
-            }
-            // Loewdin within the block: T' = (U w^-1/2)^T T over the kept directions
-            k_dots(Tn, N, acc, Tn, N, acc, N, Gm, acc, part, s);
-            k_symmetrize(Gm, acc, s);
-            eig_small(Gm, acc, ev, Y, s);
-            k_sort_eig(ev, Y, acc, 1, Gw, Gw + acc, s);
-            std::vector<double> hq(acc);
-            d2h(hq.data(), ev, acc * sizeof(double), s);
-            int keep = 0;
-            for (int q = 0; q < acc; ++q) keep += (hq[q] > 1e-14 && std::isfinite(hq[q]));
-            if (keep == 0) { acc = 0; break; }
-            again = hq[keep - 1] < 0.5;  // strong cancellation: orthonormalise once more
-            k_lowdin_coef(coef, Y, ev, acc, keep, s);
-            k_lincomb(R, N, keep, Tn, N, acc, coef, keep, N, 1.0, 0.0, s);
-            k_copy(Tn, R, (long long)keep * N, s);
-            acc = keep;
-        }
+        const int acc = orthonormalise(Tn, nn, m, R);
         if (acc == 0) {
             res.converged = false;
             break;
@@ -808,30 +822,37 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         if (nroots > Nk) fail(ADC3_EINVAL, "truncated space smaller than nroots");
         int sig = 0;
         int match = k;
+        // the canonical ADC(2) vectors carried into the truncated basis (r1 U, U^T z_i U): vector k is
+        // the reference for root matching, all of them start the truncated ADC(2) solve, whose vectors
+        // in turn start the truncated ADC(3) solve
+        double* carried = take(ws, (long long)nroots * Nk);
+        double* Y2k = take(ws, (long long)nroots * Nk);
         {
-            // canonical ADC(2) vector k carried into the truncated basis: r1 U, U^T z_i U
-            double* ref = take(ws, Nk);
-            double* Y2k = take(ws, (long long)nroots * Nk);
-            double* ovl = take(ws, 64);
-            double* part = take(ws, (long long)dots_partial_elems(nroots, 1, Nk));
-            {
-                const size_t mt = ws.mark();
-                const double* yk = Y2 + (long long)k * c0->N;
-                gemm_rm(1, vk, v, 1.0, yk, v, false, U, vk, false, 0.0, ref, vk, s);
-                double* tmp = take(ws, (long long)o * v * vk);
-                gemm_rm(o * v, vk, v, 1.0, yk + v, v, false, U, vk, false, 0.0, tmp, vk, s);
+            const size_t mt = ws.mark();
+            double* tmp = take(ws, (long long)o * v * vk);
+            for (int q = 0; q < nroots; ++q) {
+                const double* yq = Y2 + (long long)q * c0->N;
+                double* cq = carried + (long long)q * Nk;
+                gemm_rm(1, vk, v, 1.0, yq, v, false, U, vk, false, 0.0, cq, vk, s);
+                gemm_rm(o * v, vk, v, 1.0, yq + v, v, false, U, vk, false, 0.0, tmp, vk, s);
                 Gemm g;
                 g.M = vk; g.N = vk; g.K = v;
                 g.A = U; g.sAm = 1; g.sAk = vk;
                 g.B = tmp; g.sBk = vk; g.sBn = 1; g.bB0 = (long long)v * vk;
-                g.C = ref + vk; g.sCm = vk; g.sCn = 1; g.bC0 = (long long)vk * vk;
+                g.C = cq + vk; g.sCm = vk; g.sCn = 1; g.bC0 = (long long)vk * vk;
                 g.nb0 = o;
                 gemm(g, s);
-                ws.release(mt);
             }
+            ws.release(mt);
+        }
+        {
+            const double* ref = carried + (long long)k * Nk;
+            double* ovl = take(ws, 64);
+            double* part = take(ws, (long long)dots_partial_elems(nroots, 1, Nk));
             const size_t m2 = ws.mark();
             Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s, op.precision);
-            DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s, op.precision);
+            DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s, op.precision,
+                                         false, nullptr, carried, nroots);
             k_dots(Y2k, Nk, nroots, ref, Nk, 1, Nk, ovl, 1, part, s);
             std::vector<double> hov(nroots);
             d2h(hov.data(), ovl, nroots * sizeof(double), s);
@@ -853,7 +874,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s, op.precision);
             c3->mlp_w = op.mlp_weights;
             DavResult a3 = davidson_impl(c3, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
-                                         op.precond == 1);
+                                         op.precond == 1, nullptr, Y2k, nroots);
             R.omega_uncorr = a3.w[match];
             R.omega_lowp = a3.w_lowp.empty() ? a3.w[match] : a3.w_lowp[match];
             R.iters_lowp = a3.iters_lowp;
