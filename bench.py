@@ -218,7 +218,7 @@ def main():
                    "nvir_kept": [r["nvir_kept"] for r in reps], "naux_kept": [r["naux_kept"] for r in reps]},
         "roots": [float(x) for x in roots],
         "status": st,
-        "roofline": {"kernel": "sigma ladder GEMM (gemm_f64_kernel<1>)", "bound": "mfma",
+        "roofline": {"kernel": "sigma ladder (ladder_f64_kernel)", "bound": "mfma",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
                      "launches": lad_n, "avg_launch_ms": lad_ms / max(lad_n, 1),

@@ -150,9 +150,11 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     }
     c->mlp_wb = ws.take<unsigned short>(256 * 256);
     c->zb = take(ws, NVMAX * (long long)o * vv);
-    c->xb = take(ws, NVMAX * (long long)o * vv);
-    c->xtb = take(ws, NVMAX * (long long)o * vv);
-    c->sdb = take(ws, NVMAX * (long long)o * vv);
+    // xb, xtb, sdb are contiguous: before the particle-hole terms use them they hold the
+    // ladder's split-K partial sums
+    c->xb = take(ws, 3 * NVMAX * (long long)o * vv);
+    c->xtb = c->xb + NVMAX * (long long)o * vv;
+    c->sdb = c->xtb + NVMAX * (long long)o * vv;
     c->sb = take(ws, NVMAX * (long long)o * vv);
     // ---- everything below is temporary ----
     const size_t mark = ws.mark();
@@ -357,7 +359,14 @@ static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nve
             } else {
                 ProfScope p(PROF_LADDER, s, 2.0 * nv * o * (double)vv * vv,
                             8.0 * ((double)vv * vv + 2.0 * nv * o * vv));
-                gemm_rm(nv * o, (int)vv, (int)vv, 1.0, zb, vv, false, c->G, vv, false, 0.0, c->sb, vv, s, 1);
+                const int M = nv * o;
+                if (ladder_supported(M, (int)vv, (int)vv, zb, vv, c->G, vv, c->sb, vv)) {
+                    const long long pe = 3 * NVMAX * (long long)o * vv;
+                    const int nch = ladder_tuned_chunks(M, (int)vv, (int)vv, zb, vv, c->G, vv, c->sb, vv, c->xb, pe, s);
+                    ladder_gemm(M, (int)vv, (int)vv, 1.0, zb, vv, c->G, vv, 0.0, c->sb, vv, nch, c->xb, pe, s);
+                } else {
+                    gemm_rm(M, (int)vv, (int)vv, 1.0, zb, vv, false, c->G, vv, false, 0.0, c->sb, vv, s, 1);
+                }
             }
             // particle-hole terms on the alpha-beta determinants
             k_z_to_x(zb, c->xb, c->xtb, (long long)nv * o, v, s);

@@ -81,6 +81,17 @@ struct GemmLP {
 };
 void splitk_reduce(const double* part, int nchunk, int M, int N, double alpha, double beta, double* C,
                    long long sCm, long long sCn, hipStream_t s);
+// sigma ladder (dedicated FP64 kernel): C = alpha Z G + beta C, K split into nchunk chunks
+// whose partial sums go to partial[nchunk][M][N] (nchunk 1: direct)
+bool ladder_supported(int M, int N, int K, const double* Z, long long ldz, const double* G, long long ldg,
+                      const double* C, long long ldc);
+int ladder_chunk_len(int K, int nchunk);
+void ladder_rows(int M, int& tm, int& mtiles);
+void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long ldz, const double* G, long long ldg,
+                 double beta, double* C, long long ldc, int nchunk, double* partial, long long partial_elems,
+                 hipStream_t s);
+int ladder_tuned_chunks(int M, int N, int K, const double* Z, long long ldz, const double* G, long long ldg, double* C,
+                        long long ldc, double* partial, long long partial_elems, hipStream_t s);
 extern thread_local double* g_gemm_scratch;
 extern thread_local long long g_gemm_scratch_n;
 void gemm_lp(const GemmLP& g, int prec, hipStream_t s, int tag = 0);

@@ -1,0 +1,326 @@
+// The sigma ladder as a dedicated FP64 matrix-core kernel.
+//
+//   C[m][n] = alpha * sum_k Z[m][k] G[k][n] + beta * C[m][n]
+//
+// m runs over (vector, occupied) pairs (a few hundred at most), k and n over virtual
+// pairs (v^2 each), G[(cd)][(ab)] = (ac|bd) is the stored ladder matrix (symmetric).
+// The kernel is shaped by three facts of this contraction on CDNA4:
+//   * all m rows fit one tile (TM blocks of 16 rows), so G streams from HBM exactly once;
+//   * FP64 MFMA is the bound (2 flops per G element per row, >= 20 rows), so the tile
+//     keeps 2 workgroups per CU (<= 256 registers a lane) to hide load latency across
+//     workgroups rather than within one;
+//   * K is split into chunks (deterministic partial sums, reduced in a fixed order) to
+//     give >= 4 workgroups per CU slot; with a multiple of 8 chunks, the workgroups that
+//     one XCD runs together share one chunk of Z in that XCD's L2.
+// Operands are read with 16-byte loads (both are contiguous along their tile rows) and
+// staged through double-buffered LDS.
+//
+// MFMA f64 16x16x4 (lane l of a wave64): A frag A[l%16][l/16], B frag B[l/16][l%16],
+// accumulator element r holds D[l/16 + 4r][l%16].
+#include "internal.h"
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+namespace adc3 {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+namespace {
+constexpr int LBK = 16, LNT = 256, LTN = 2, LBN = 4 * 16 * LTN;  // 128 columns, 4 waves side by side
+constexpr int APAD = 1, BPAD = 2;
+
+struct LadderArgs {
+    const double* Z; long long ldz;
+    const double* G; long long ldg;
+    double* C; long long ldc;
+    double* P;  // partials [nchunk][M][N] when nchunk > 1
+    int M, N, K, Kc, ntn, nchunk;
+    double alpha, beta;
+};
+
+template <int TM>
+__global__ __launch_bounds__(LNT, 2) void ladder_f64_kernel(LadderArgs g) {
+    constexpr int BM = 16 * TM;
+    constexpr int PA = (BM * (LBK / 2) + LNT - 1) / LNT;  // 16-byte A loads per thread
+    constexpr int PB = (LBK * (LBN / 2)) / LNT;            // 16-byte B loads per thread
+    __shared__ __attribute__((aligned(16))) double As[2][BM][LBK + APAD];
+    __shared__ __attribute__((aligned(16))) double Bs[2][LBK][LBN + BPAD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    // block -> (chunk, column tile), XCD-grouped when the chunk count allows it
+    const int b = blockIdx.x;
+    int chunk, nt;
+    if ((g.nchunk & 7) == 0) {
+        const int q = b >> 3;
+        chunk = (q / g.ntn) * 8 + (b & 7);
+        nt = q % g.ntn;
+    } else {
+        chunk = b / g.ntn;
+        nt = b % g.ntn;
+    }
+    const long long m0 = (long long)blockIdx.y * BM, n0 = (long long)nt * LBN;
+    const int kb = chunk * g.Kc, ke = std::min(g.K, kb + g.Kc);
+    // per-thread load slots
+    int arow[PA], akq[PA], bkr[PB], bnq[PB];
+#pragma unroll
+    for (int p = 0; p < PA; ++p) {
+        const int idx = tid + LNT * p;
+        arow[p] = idx < BM * (LBK / 2) ? idx / (LBK / 2) : -1;
+        akq[p] = idx % (LBK / 2);
+    }
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        const int idx = tid + LNT * p;
+        bkr[p] = idx / (LBN / 2);
+        bnq[p] = idx % (LBN / 2);
+    }
+    d2v ra[PA], rb[PB];
+    const d2v z2 = {0.0, 0.0};
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p) {
+            const long long m = m0 + arow[p];
+            const int k = k0 + 2 * akq[p];
+            ra[p] = (arow[p] >= 0 && m < g.M && k < ke) ? *(const d2v*)(g.Z + m * g.ldz + k) : z2;
+        }
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
+            const int k = k0 + bkr[p];
+            const long long n = n0 + 2 * bnq[p];
+            rb[p] = (k < ke && n < g.N) ? *(const d2v*)(g.G + (long long)k * g.ldg + n) : z2;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p)
+            if (arow[p] >= 0) {
+                As[buf][arow[p]][2 * akq[p]] = ra[p].x;
+                As[buf][arow[p]][2 * akq[p] + 1] = ra[p].y;
+            }
+#pragma unroll
+        for (int p = 0; p < PB; ++p) *(d2v*)&Bs[buf][bkr[p]][2 * bnq[p]] = rb[p];
+    };
+    d4v acc[TM][LTN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < LTN; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int nslab = (ke - kb + LBK - 1) / LBK;
+    if (nslab > 0) {
+        fetch(kb);
+        stash(0);
+    }
+    __syncthreads();
+    const int cb = wave * (16 * LTN);
+    for (int s = 0; s < nslab; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nslab) fetch(kb + (s + 1) * LBK);
+#pragma unroll
+        for (int kk = 0; kk < LBK; kk += 4) {
+            double bf[LTN];
+#pragma unroll
+            for (int j = 0; j < LTN; ++j) bf[j] = Bs[buf][kk + lk][cb + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const double af = As[buf][16 * i + lr][kk + lk];
+#pragma unroll
+                for (int j = 0; j < LTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        if (s + 1 < nslab) stash(buf ^ 1);
+        __syncthreads();
+    }
+    // epilogue: partial sums, or the final alpha/beta update when K is not split
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < LTN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long row = m0 + 16 * i + lk + 4 * r;
+                const long long col = n0 + cb + 16 * j + lr;
+                if (row < g.M && col < g.N) {
+                    if (g.nchunk > 1) {
+                        g.P[((long long)chunk * g.M + row) * g.N + col] = acc[i][j][r];
+                    } else {
+                        double* c = g.C + row * g.ldc + col;
+                        const double v = g.alpha * acc[i][j][r];
+                        *c = (g.beta == 0.0) ? v : v + g.beta * (*c);
+                    }
+                }
+            }
+}
+
+template <int TM>
+void launch_tm(const LadderArgs& a, int mtiles, hipStream_t s) {
+    hipLaunchKernelGGL((ladder_f64_kernel<TM>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
+}
+
+void launch(const LadderArgs& a, int tm, int mtiles, hipStream_t s) {
+    switch (tm) {
+        case 1: launch_tm<1>(a, mtiles, s); break;
+        case 2: launch_tm<2>(a, mtiles, s); break;
+        case 3: launch_tm<3>(a, mtiles, s); break;
+        case 4: launch_tm<4>(a, mtiles, s); break;
+        case 5: launch_tm<5>(a, mtiles, s); break;
+        case 6: launch_tm<6>(a, mtiles, s); break;
+        case 7: launch_tm<7>(a, mtiles, s); break;
+        default: launch_tm<8>(a, mtiles, s); break;
+    }
+    LAUNCHCHK();
+}
+}  // namespace
+
+// Row tiling: as few tiles of <= 128 rows as possible (each tile streams G once), each
+// as short as those rows allow (padding rows cost matrix-core time).
+void ladder_rows(int M, int& tm, int& mtiles) {
+    mtiles = (M + 127) / 128;
+    tm = (M + 16 * mtiles - 1) / (16 * mtiles);
+}
+
+bool ladder_supported(int M, int N, int K, const double* Z, long long ldz, const double* G, long long ldg,
+                      const double* C, long long ldc) {
+    auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    return M > 0 && N > 0 && K > 0 && (N % 2 == 0) && (K % 2 == 0) && (ldz % 2 == 0) && (ldg % 2 == 0) &&
+           (ldc % 2 == 0) && al16(Z) && al16(G) && al16(C);
+}
+
+// Column tiles x chunks launched for a given chunk count (used by the planner and the tuner).
+int ladder_chunk_len(int K, int nchunk) {
+    const int kc = (K + nchunk - 1) / nchunk;
+    return (kc + LBK - 1) / LBK * LBK;
+}
+
+void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long ldz, const double* G, long long ldg,
+                 double beta, double* C, long long ldc, int nchunk, double* partial, long long partial_elems,
+                 hipStream_t s) {
+    if (g_dry || M <= 0 || N <= 0) return;
+    int tm, mtiles;
+    ladder_rows(M, tm, mtiles);
+    nchunk = std::max(1, std::min(nchunk, (K + 255) / 256));
+    if (nchunk > 1 && (!partial || (long long)nchunk * M * N > partial_elems)) nchunk = 1;
+    LadderArgs a;
+    a.Z = Z; a.ldz = ldz; a.G = G; a.ldg = ldg; a.C = C; a.ldc = ldc; a.P = partial;
+    a.M = M; a.N = N; a.K = K;
+    a.Kc = ladder_chunk_len(K, nchunk);
+    a.nchunk = (K + a.Kc - 1) / a.Kc;
+    a.ntn = (N + LBN - 1) / LBN;
+    a.alpha = alpha; a.beta = beta;
+    launch(a, tm, mtiles, s);
+    if (a.nchunk > 1) splitk_reduce(partial, a.nchunk, M, N, alpha, beta, C, ldc, 1, s);
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner for the chunk count.  The best split depends on M (rows per tile), the
+// column count and the chip's load balance, so it is measured: on the first call for a
+// (rows, N, K) shape each candidate runs twice after a warm-up, timed with HIP events on
+// the caller's stream, and the fastest is kept for the process.  ADC3_TUNE_CACHE names a
+// text file that keeps the choices across processes (one line per shape and device
+// architecture); ADC3_LADDER_CHUNKS fixes the count and disables tuning.  Different
+// chunk counts sum in a different order, so the last bits of sigma can differ between
+// choices, never between two calls that use the same choice.
+// ---------------------------------------------------------------------------
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string arch_name() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    hipDeviceProp_t pr;
+    if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
+    std::string a = pr.gcnArchName;
+    return a.substr(0, a.find(':'));
+}
+
+std::string tune_key(int M, int N, int K) {
+    int tm, mt;
+    ladder_rows(M, tm, mt);
+    return "ladder_f64 " + arch_name() + " " + std::to_string(tm) + " " + std::to_string(mt) + " " +
+           std::to_string(N) + " " + std::to_string(K);
+}
+
+void load_cache() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("ADC3_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        std::string l(line);
+        const size_t sp = l.find_last_of(' ');
+        if (sp == std::string::npos) continue;
+        const int v = std::atoi(l.c_str() + sp + 1);
+        if (v >= 1) g_tune[l.substr(0, sp)] = v;
+    }
+    std::fclose(f);
+}
+
+void store_cache(const std::string& key, int v) {
+    const char* path = std::getenv("ADC3_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d\n", key.c_str(), v);
+    std::fclose(f);
+}
+}  // namespace
+
+int ladder_tuned_chunks(int M, int N, int K, const double* Z, long long ldz, const double* G, long long ldg, double* C,
+                        long long ldc, double* partial, long long partial_elems, hipStream_t s) {
+    const char* fixed = std::getenv("ADC3_LADDER_CHUNKS");
+    if (fixed && *fixed) return std::max(1, std::atoi(fixed));
+    const int def = 8;
+    if (g_dry) return def;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return def;
+    const std::string key = tune_key(M, N, K);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_cache();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return it->second;
+    }
+    std::vector<int> cand;
+    for (int c : {1, 2, 4, 8, 16}) {
+        if (c > 1 && (long long)c * M * N > partial_elems) continue;
+        if (c > 1 && K / c < 256) continue;
+        cand.push_back(c);
+    }
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int best = cand.empty() ? 1 : cand[0];
+    float best_ms = 1e30f;
+    for (int c : cand) {
+        ladder_gemm(M, N, K, 1.0, Z, ldz, G, ldg, 0.0, C, ldc, c, partial, partial_elems, s);  // warm-up
+        HIPCHK(hipEventRecord(e0, s));
+        for (int rep = 0; rep < 2; ++rep) ladder_gemm(M, N, K, 1.0, Z, ldz, G, ldg, 0.0, C, ldc, c, partial,
+                                                      partial_elems, s);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best_ms) { best_ms = ms; best = c; }
+    }
+    HIPCHK(hipEventDestroy(e0));
+    HIPCHK(hipEventDestroy(e1));
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = best;
+        store_cache(key, best);
+    }
+    return best;
+}
+
+}  // namespace adc3
