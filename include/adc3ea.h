@@ -139,7 +139,7 @@ long long adc3_ea_dim(const adc3_ctx* ctx);
 
 /* sigma = M r for nvec vectors (Sec. ADC theory, Davidson sigma vectors):
  * r_dev[nvec][N], sigma_dev[nvec][N] device, row-major, must not overlap.
- * precision as in adc3_opts (at most the context's setup precision). */
+ * precision: 0 (FP64) or the context's setup precision (as in adc3_opts). */
 int adc3_ea_sigma(adc3_ctx* ctx, const double* r_dev, double* sigma_dev, int nvec, int precision,
                   hipStream_t stream);
 

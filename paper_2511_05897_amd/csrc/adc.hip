@@ -94,6 +94,7 @@ struct Ctx {
     // reduced-precision copies (precision 1: FP32 ladder and coupling; 2: BF16 ladder, FP32 coupling)
     int prec = 0;
     void* Glo = nullptr;
+    void* zlo = nullptr;  // reduced-precision copy of the ladder's input rows
     float* Uz32 = nullptr;
     // learned preconditioner: weights (caller's device memory) and the BF16 W2 copy
     const float* mlp_w = nullptr;
@@ -146,6 +147,7 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
         if (level >= 3) {
             if (prec == 1) c->Glo = ws.take<float>((size_t)(vv * vv));
             else c->Glo = ws.take<unsigned short>((size_t)(vv * vv));
+            c->zlo = ws.take<float>((size_t)(NVMAX * (long long)o * vv));
         }
     }
     c->mlp_wb = ws.take<unsigned short>(256 * 256);
@@ -350,19 +352,29 @@ static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nve
             if (prec > 0) {
                 ProfScope p(PROF_LADDER_LP, s, 2.0 * nv * o * (double)vv * vv,
                             (prec == 1 ? 4.0 : 2.0) * (double)vv * vv + 16.0 * nv * o * vv);
-                GemmLP g;
-                g.M = nv * o; g.N = (int)vv; g.K = (int)vv;
-                g.A = zb; g.sAm = vv; g.sAk = 1;
-                g.B = c->Glo; g.sBk = vv; g.sBn = 1;
-                g.C = c->sb; g.sCm = vv; g.sCn = 1;
-                gemm_lp(g, prec, s, 1);
+                const int M = nv * o;
+                k_to_lowp(c->zlo, zb, (long long)M * vv, prec, s);
+                if (ladder_lp_supported(prec, M, (int)vv, (int)vv, c->zlo, vv, c->Glo, vv, c->sb, vv)) {
+                    const long long pe = 3 * NVMAX * (long long)o * vv;
+                    const int nch =
+                        ladder_tuned_chunks(prec, M, (int)vv, (int)vv, c->zlo, vv, c->Glo, vv, c->sb, vv, c->xb, pe, s);
+                    ladder_gemm_lp(prec, M, (int)vv, (int)vv, 1.0, c->zlo, vv, c->Glo, vv, 0.0, c->sb, vv, nch, c->xb,
+                                   pe, s);
+                } else {
+                    GemmLP g;
+                    g.M = M; g.N = (int)vv; g.K = (int)vv;
+                    g.A = zb; g.sAm = vv; g.sAk = 1;
+                    g.B = c->Glo; g.sBk = vv; g.sBn = 1;
+                    g.C = c->sb; g.sCm = vv; g.sCn = 1;
+                    gemm_lp(g, prec, s, 1);
+                }
             } else {
                 ProfScope p(PROF_LADDER, s, 2.0 * nv * o * (double)vv * vv,
                             8.0 * ((double)vv * vv + 2.0 * nv * o * vv));
                 const int M = nv * o;
                 if (ladder_supported(M, (int)vv, (int)vv, zb, vv, c->G, vv, c->sb, vv)) {
                     const long long pe = 3 * NVMAX * (long long)o * vv;
-                    const int nch = ladder_tuned_chunks(M, (int)vv, (int)vv, zb, vv, c->G, vv, c->sb, vv, c->xb, pe, s);
+                    const int nch = ladder_tuned_chunks(0, M, (int)vv, (int)vv, zb, vv, c->G, vv, c->sb, vv, c->xb, pe, s);
                     ladder_gemm(M, (int)vv, (int)vv, 1.0, zb, vv, c->G, vv, 0.0, c->sb, vv, nch, c->xb, pe, s);
                 } else {
                     gemm_rm(M, (int)vv, (int)vv, 1.0, zb, vv, false, c->G, vv, false, 0.0, c->sb, vv, s, 1);
@@ -1024,8 +1036,8 @@ int adc3_ea_sigma(adc3_ctx* ctx, const double* r, double* sigma, int nvec, int p
     API_BEGIN
     if (!ctx || !r || !sigma) fail(ADC3_EINVAL, "NULL argument");
     if (nvec < 0) fail(ADC3_EINVAL, "nvec < 0");
-    if (precision < 0 || precision > ctx->c->prec)
-        fail(ADC3_EINVAL, "precision not available in this context (set it at setup)");
+    if (precision != 0 && precision != ctx->c->prec)
+        fail(ADC3_EINVAL, "precision must be 0 (FP64) or the context's setup precision");
     Arena ws = ctx->c->ws;
     sigma_impl(ctx->c, ws, r, sigma, nvec, stream, precision);
     return ADC3_OK;
@@ -1047,8 +1059,8 @@ int adc3_ea_davidson(adc3_ctx* ctx, int nroots, double conv, int max_iter, int m
     if (!(conv > 0)) fail(ADC3_EINVAL, "conv must be > 0");
     if (nroots < 1 || nroots > ctx->c->N) fail(ADC3_EINVAL, "nroots out of range");
     if (max_iter < 1) fail(ADC3_EINVAL, "max_iter must be >= 1");
-    if (precision < 0 || precision > ctx->c->prec)
-        fail(ADC3_EINVAL, "precision not available in this context (set it at setup)");
+    if (precision != 0 && precision != ctx->c->prec)
+        fail(ADC3_EINVAL, "precision must be 0 (FP64) or the context's setup precision");
     Arena ws = ctx->c->ws;
     DavResult r = davidson_impl(ctx->c, ws, nroots, conv, max_iter, max_subspace, vectors, stream, precision,
                                 ctx->c->mlp_w != nullptr);

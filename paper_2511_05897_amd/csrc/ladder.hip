@@ -158,6 +158,253 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f64_kernel(LadderArgs g) {
             }
 }
 
+// ---------------------------------------------------------------------------
+// Reduced-precision ladders (FP32 accumulation, FP64 partial sums / output).
+//   FP32: v_mfma_f32_16x16x4f32, Z32[m][k] and G32[k][n] staged through LDS (BK 32).
+//   BF16: v_mfma_f32_16x16x32_bf16.  G is symmetric, so column n of the B operand is
+//         row n of G: each lane loads its 8 consecutive k straight from HBM into
+//         registers (one slab ahead), and only the Z slab (shared by the 4 waves) goes
+//         through LDS.  This kernel is bound by the G stream (2 bytes per element).
+// FP32-output accumulator layout of both: element r holds D[4(l/16) + r][l%16].
+// ---------------------------------------------------------------------------
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+struct LadderLP {
+    const void* Z; long long ldz;
+    const void* G; long long ldg;
+    double* C; long long ldc;
+    double* P;
+    int M, N, K, Kc, ntn, nchunk;
+    double alpha, beta;
+};
+
+__device__ inline void block_tile(int nchunk, int ntn, int& chunk, int& nt) {
+    const int b = blockIdx.x;
+    if ((nchunk & 7) == 0) {
+        const int q = b >> 3;
+        chunk = (q / ntn) * 8 + (b & 7);
+        nt = q % ntn;
+    } else {
+        chunk = b / ntn;
+        nt = b % ntn;
+    }
+}
+
+template <int TM>
+__device__ inline void store_f32_tile(const LadderLP& g, f4v (&acc)[TM][LTN], long long m0, long long n0, int cb,
+                                      int chunk, int lr, int lk) {
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < LTN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long row = m0 + 16 * i + 4 * lk + r;
+                const long long col = n0 + cb + 16 * j + lr;
+                if (row < g.M && col < g.N) {
+                    if (g.nchunk > 1) {
+                        g.P[((long long)chunk * g.M + row) * g.N + col] = (double)acc[i][j][r];
+                    } else {
+                        double* c = g.C + row * g.ldc + col;
+                        const double v = g.alpha * (double)acc[i][j][r];
+                        *c = (g.beta == 0.0) ? v : v + g.beta * (*c);
+                    }
+                }
+            }
+}
+
+constexpr int FBK = 32;
+template <int TM>
+__global__ __launch_bounds__(LNT, 2) void ladder_f32_kernel(LadderLP g) {
+    constexpr int BM = 16 * TM;
+    constexpr int PA = (BM * (FBK / 4) + LNT - 1) / LNT;
+    constexpr int PB = (FBK * (LBN / 4)) / LNT;
+    __shared__ __attribute__((aligned(16))) float As[2][BM][FBK + 1];
+    __shared__ __attribute__((aligned(16))) float Bs[2][FBK][LBN + 4];
+    const float* __restrict__ Z = (const float*)g.Z;
+    const float* __restrict__ G = (const float*)g.G;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    int chunk, nt;
+    block_tile(g.nchunk, g.ntn, chunk, nt);
+    const long long m0 = (long long)blockIdx.y * BM, n0 = (long long)nt * LBN;
+    const int kb = chunk * g.Kc, ke = min(g.K, kb + g.Kc);
+    int arow[PA], akq[PA], bkr[PB], bnq[PB];
+#pragma unroll
+    for (int p = 0; p < PA; ++p) {
+        const int idx = tid + LNT * p;
+        arow[p] = idx < BM * (FBK / 4) ? idx / (FBK / 4) : -1;
+        akq[p] = idx % (FBK / 4);
+    }
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        const int idx = tid + LNT * p;
+        bkr[p] = idx / (LBN / 4);
+        bnq[p] = idx % (LBN / 4);
+    }
+    f4v ra[PA], rb[PB];
+    const f4v z4 = {0.f, 0.f, 0.f, 0.f};
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p) {
+            const long long m = m0 + arow[p];
+            const int k = k0 + 4 * akq[p];
+            ra[p] = (arow[p] >= 0 && m < g.M && k < ke) ? *(const f4v*)(Z + m * g.ldz + k) : z4;
+        }
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
+            const int k = k0 + bkr[p];
+            const long long n = n0 + 4 * bnq[p];
+            rb[p] = (k < ke && n < g.N) ? *(const f4v*)(G + (long long)k * g.ldg + n) : z4;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p)
+            if (arow[p] >= 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) As[buf][arow[p]][4 * akq[p] + q] = ra[p][q];
+            }
+#pragma unroll
+        for (int p = 0; p < PB; ++p) *(f4v*)&Bs[buf][bkr[p]][4 * bnq[p]] = rb[p];
+    };
+    f4v acc[TM][LTN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < LTN; ++j) acc[i][j] = z4;
+    const int nslab = (ke - kb + FBK - 1) / FBK;
+    if (nslab > 0) {
+        fetch(kb);
+        stash(0);
+    }
+    __syncthreads();
+    const int cb = wave * (16 * LTN);
+    for (int s = 0; s < nslab; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nslab) fetch(kb + (s + 1) * FBK);
+#pragma unroll
+        for (int kk = 0; kk < FBK; kk += 4) {
+            float bf[LTN];
+#pragma unroll
+            for (int j = 0; j < LTN; ++j) bf[j] = Bs[buf][kk + lk][cb + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const float af = As[buf][16 * i + lr][kk + lk];
+#pragma unroll
+                for (int j = 0; j < LTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        if (s + 1 < nslab) stash(buf ^ 1);
+        __syncthreads();
+    }
+    store_f32_tile<TM>(g, acc, m0, n0, cb, chunk, lr, lk);
+}
+
+constexpr int HBK = 64, HPAD = 8;
+template <int TM>
+__global__ __launch_bounds__(LNT, 2) void ladder_bf16_kernel(LadderLP g) {
+    constexpr int BM = 16 * TM;
+    constexpr int PA = (BM * (HBK / 8) + LNT - 1) / LNT;
+    __shared__ __attribute__((aligned(16))) __bf16 As[2][BM][HBK + HPAD];
+    const __bf16* __restrict__ Z = (const __bf16*)g.Z;
+    const __bf16* __restrict__ G = (const __bf16*)g.G;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    int chunk, nt;
+    block_tile(g.nchunk, g.ntn, chunk, nt);
+    const long long m0 = (long long)blockIdx.y * BM, n0 = (long long)nt * LBN;
+    const int kb = chunk * g.Kc, ke = min(g.K, kb + g.Kc);
+    const int cb = wave * (16 * LTN);
+    int arow[PA], akq[PA];
+#pragma unroll
+    for (int p = 0; p < PA; ++p) {
+        const int idx = tid + LNT * p;
+        arow[p] = idx < BM * (HBK / 8) ? idx / (HBK / 8) : -1;
+        akq[p] = idx % (HBK / 8);
+    }
+    bf8v ra[PA], rb[LTN][2];
+    bf8v zero8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) zero8[q] = (__bf16)0.f;
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p) {
+            const long long m = m0 + arow[p];
+            const int k = k0 + 8 * akq[p];
+            ra[p] = (arow[p] >= 0 && m < g.M && k < ke) ? *(const bf8v*)(Z + m * g.ldz + k) : zero8;
+        }
+#pragma unroll
+        for (int j = 0; j < LTN; ++j) {
+            const long long col = n0 + cb + 16 * j + lr;
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const int k = k0 + 32 * ks + 8 * lk;
+                rb[j][ks] = (col < g.N && k < ke) ? *(const bf8v*)(G + col * g.ldg + k) : zero8;
+            }
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p)
+            if (arow[p] >= 0) *(bf8v*)&As[buf][arow[p]][8 * akq[p]] = ra[p];
+    };
+    f4v acc[TM][LTN];
+    const f4v z4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < LTN; ++j) acc[i][j] = z4;
+    const int nslab = (ke - kb + HBK - 1) / HBK;
+    bf8v cbf[LTN][2];
+    if (nslab > 0) {
+        fetch(kb);
+        stash(0);
+    }
+    __syncthreads();
+    for (int s = 0; s < nslab; ++s) {
+        const int buf = s & 1;
+#pragma unroll
+        for (int j = 0; j < LTN; ++j)
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) cbf[j][ks] = rb[j][ks];
+        if (s + 1 < nslab) fetch(kb + (s + 1) * HBK);
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const bf8v af = *(const bf8v*)&As[buf][16 * i + lr][32 * ks + 8 * lk];
+#pragma unroll
+                for (int j = 0; j < LTN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, cbf[j][ks], acc[i][j], 0, 0, 0);
+            }
+        if (s + 1 < nslab) stash(buf ^ 1);
+        __syncthreads();
+    }
+    store_f32_tile<TM>(g, acc, m0, n0, cb, chunk, lr, lk);
+}
+
+template <int TM>
+void launch_lp_tm(const LadderLP& a, int prec, int mtiles, hipStream_t s) {
+    if (prec == 1) hipLaunchKernelGGL((ladder_f32_kernel<TM>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
+    else hipLaunchKernelGGL((ladder_bf16_kernel<TM>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
+}
+
+void launch_lp(const LadderLP& a, int prec, int tm, int mtiles, hipStream_t s) {
+    switch (tm) {
+        case 1: launch_lp_tm<1>(a, prec, mtiles, s); break;
+        case 2: launch_lp_tm<2>(a, prec, mtiles, s); break;
+        case 3: launch_lp_tm<3>(a, prec, mtiles, s); break;
+        case 4: launch_lp_tm<4>(a, prec, mtiles, s); break;
+        case 5: launch_lp_tm<5>(a, prec, mtiles, s); break;
+        case 6: launch_lp_tm<6>(a, prec, mtiles, s); break;
+        case 7: launch_lp_tm<7>(a, prec, mtiles, s); break;
+        default: launch_lp_tm<8>(a, prec, mtiles, s); break;
+    }
+    LAUNCHCHK();
+}
+
 template <int TM>
 void launch_tm(const LadderArgs& a, int mtiles, hipStream_t s) {
     hipLaunchKernelGGL((ladder_f64_kernel<TM>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
@@ -192,10 +439,38 @@ bool ladder_supported(int M, int N, int K, const double* Z, long long ldz, const
            (ldc % 2 == 0) && al16(Z) && al16(G) && al16(C);
 }
 
-// Column tiles x chunks launched for a given chunk count (used by the planner and the tuner).
+// K per chunk: a multiple of the slab depth of every ladder kernel (64)
 int ladder_chunk_len(int K, int nchunk) {
     const int kc = (K + nchunk - 1) / nchunk;
-    return (kc + LBK - 1) / LBK * LBK;
+    return (kc + 63) / 64 * 64;
+}
+
+bool ladder_lp_supported(int prec, int M, int N, int K, const void* Z, long long ldz, const void* G, long long ldg,
+                         const double* C, long long ldc) {
+    auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    if (!(M > 0 && N > 0 && K > 0 && al16(Z) && al16(G) && al16(C) && ldc % 2 == 0)) return false;
+    if (prec == 1) return N % 4 == 0 && K % 4 == 0 && ldz % 4 == 0 && ldg % 4 == 0;
+    if (prec == 2) return N == K && K % 8 == 0 && ldz % 8 == 0 && ldg % 8 == 0;  // B read through symmetry
+    return false;
+}
+
+void ladder_gemm_lp(int prec, int M, int N, int K, double alpha, const void* Z, long long ldz, const void* G,
+                    long long ldg, double beta, double* C, long long ldc, int nchunk, double* partial,
+                    long long partial_elems, hipStream_t s) {
+    if (g_dry || M <= 0 || N <= 0) return;
+    int tm, mtiles;
+    ladder_rows(M, tm, mtiles);
+    nchunk = std::max(1, std::min(nchunk, (K + 255) / 256));
+    if (nchunk > 1 && (!partial || (long long)nchunk * M * N > partial_elems)) nchunk = 1;
+    LadderLP a;
+    a.Z = Z; a.ldz = ldz; a.G = G; a.ldg = ldg; a.C = C; a.ldc = ldc; a.P = partial;
+    a.M = M; a.N = N; a.K = K;
+    a.Kc = ladder_chunk_len(K, nchunk);
+    a.nchunk = (K + a.Kc - 1) / a.Kc;
+    a.ntn = (N + LBN - 1) / LBN;
+    a.alpha = alpha; a.beta = beta;
+    launch_lp(a, prec, tm, mtiles, s);
+    if (a.nchunk > 1) splitk_reduce(partial, a.nchunk, M, N, alpha, beta, C, ldc, 1, s);
 }
 
 void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long ldz, const double* G, long long ldg,
@@ -241,10 +516,10 @@ std::string arch_name() {
     return a.substr(0, a.find(':'));
 }
 
-std::string tune_key(int M, int N, int K) {
+std::string tune_key(int prec, int M, int N, int K) {
     int tm, mt;
     ladder_rows(M, tm, mt);
-    return "ladder_f64 " + arch_name() + " " + std::to_string(tm) + " " + std::to_string(mt) + " " +
+    return std::string(prec == 0 ? "ladder_f64 " : prec == 1 ? "ladder_f32 " : "ladder_bf16 ") + arch_name() + " " + std::to_string(tm) + " " + std::to_string(mt) + " " +
            std::to_string(N) + " " + std::to_string(K);
 }
 
@@ -276,15 +551,23 @@ void store_cache(const std::string& key, int v) {
 }
 }  // namespace
 
-int ladder_tuned_chunks(int M, int N, int K, const double* Z, long long ldz, const double* G, long long ldg, double* C,
-                        long long ldc, double* partial, long long partial_elems, hipStream_t s) {
+static void ladder_run(int prec, int M, int N, int K, const void* Z, long long ldz, const void* G, long long ldg,
+                       double* C, long long ldc, int nchunk, double* partial, long long pe, hipStream_t s) {
+    if (prec == 0)
+        ladder_gemm(M, N, K, 1.0, (const double*)Z, ldz, (const double*)G, ldg, 0.0, C, ldc, nchunk, partial, pe, s);
+    else
+        ladder_gemm_lp(prec, M, N, K, 1.0, Z, ldz, G, ldg, 0.0, C, ldc, nchunk, partial, pe, s);
+}
+
+int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long ldz, const void* G, long long ldg,
+                        double* C, long long ldc, double* partial, long long partial_elems, hipStream_t s) {
     const char* fixed = std::getenv("ADC3_LADDER_CHUNKS");
     if (fixed && *fixed) return std::max(1, std::atoi(fixed));
     const int def = 8;
     if (g_dry) return def;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return def;
-    const std::string key = tune_key(M, N, K);
+    const std::string key = tune_key(prec, M, N, K);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         load_cache();
@@ -303,10 +586,9 @@ int ladder_tuned_chunks(int M, int N, int K, const double* Z, long long ldz, con
     int best = cand.empty() ? 1 : cand[0];
     float best_ms = 1e30f;
     for (int c : cand) {
-        ladder_gemm(M, N, K, 1.0, Z, ldz, G, ldg, 0.0, C, ldc, c, partial, partial_elems, s);  // warm-up
+        ladder_run(prec, M, N, K, Z, ldz, G, ldg, C, ldc, c, partial, partial_elems, s);  // warm-up
         HIPCHK(hipEventRecord(e0, s));
-        for (int rep = 0; rep < 2; ++rep) ladder_gemm(M, N, K, 1.0, Z, ldz, G, ldg, 0.0, C, ldc, c, partial,
-                                                      partial_elems, s);
+        for (int rep = 0; rep < 2; ++rep) ladder_run(prec, M, N, K, Z, ldz, G, ldg, C, ldc, c, partial, partial_elems, s);
         HIPCHK(hipEventRecord(e1, s));
         HIPCHK(hipEventSynchronize(e1));
         float ms = 0.f;
