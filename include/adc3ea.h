@@ -65,6 +65,8 @@ typedef struct {
                              eigendecomposition stay FP64.  Default 0. */
     int precond;          /* 0: Jacobi (diagonal) preconditioner; 1: learned (needs mlp_weights) */
     const float* mlp_weights; /* device, adc3_mlp_nparams() floats (see adc3_mlp_train); NULL default */
+    int sigma_graphs;     /* 1: each sigma pass shape is captured once into a HIP graph and replayed
+                             (needs a non-null stream; on the null stream sigma runs eagerly); default 0 */
 } adc3_opts;
 
 /* Per-root report of adc3_ea_solve. */
@@ -111,6 +113,34 @@ int adc3_ea_solve(const double* eps_occ_dev, const double* eps_vir_dev, const do
                   double fno_thresh, double naf_thresh, double conv,
                   const adc3_opts* opts, double* roots_out, adc3_root_report* reports,
                   void* workspace_dev, size_t workspace_bytes, hipStream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Ragged batches of independent instances (a build addition, not in the paper): every
+ * instance is an adc3_ea_solve with its own sizes, roots and thresholds, and one set of
+ * options.  The instances are spread over nstreams worker streams (<= 0: 4), each
+ * driven by a host thread of the library, longest estimated work first onto the least
+ * loaded worker; a worker solves its instances one after another in its own slice of
+ * the workspace.  The workers start after the work already queued on `stream` and
+ * `stream` waits for all of them; the call returns when every instance is done.
+ * roots_out and reports (nullable) hold the instances' roots in order, nroots per
+ * instance; status_out[ninst] (nullable) each instance's status.  The return value is
+ * the most severe status (adc3_last_error names the first failing instance).
+ * Results do not depend on nstreams.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    const double* eps_occ;  /* device [nocc] */
+    const double* eps_vir;  /* device [nvir] */
+    const double* B;        /* device [naux][nocc+nvir][nocc+nvir] */
+    int nocc, nvir, naux, nroots;
+    double fno_thresh, naf_thresh, conv;
+} adc3_instance;
+
+size_t adc3_ea_solve_batched_workspace_bytes(const adc3_instance* inst, int ninst, const adc3_opts* opts,
+                                             int nstreams);
+
+int adc3_ea_solve_batched(const adc3_instance* inst, int ninst, const adc3_opts* opts, int nstreams,
+                          double* roots_out, adc3_root_report* reports, int* status_out,
+                          void* workspace_dev, size_t workspace_bytes, hipStream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Secular-matrix context: integrals and intermediates of EA-ADC(level) for one
@@ -175,6 +205,9 @@ int adc3_ea_intermediate(adc3_ctx* ctx, int which, double* out_dev, long long* c
  * to Jacobi for the rest of the solve.
  * ------------------------------------------------------------------------- */
 int adc3_mlp_nparams(void);
+
+/* Replay sigma passes from captured HIP graphs on this context (see adc3_opts.sigma_graphs). */
+int adc3_ea_set_sigma_graphs(adc3_ctx* ctx, int on);
 
 /* Use the learned preconditioner in adc3_ea_davidson on this context (NULL: Jacobi).
  * weights_dev must stay valid while the context is used. */

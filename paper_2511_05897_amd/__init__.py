@@ -23,13 +23,20 @@ EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_byte
            "adc3_ea_sigma", "adc3_ea_diagonal", "adc3_ea_davidson", "adc3_ea_dense_matrix",
            "adc3_ea_intermediate", "adc3_profile_enable", "adc3_profile_query", "adc3_mlp_nparams",
            "adc3_ea_set_preconditioner", "adc3_mlp_collect", "adc3_mlp_workspace_bytes", "adc3_mlp_loss_grad",
-           "adc3_mlp_forward", "adc3_mlp_train", "adc3_ea_precondition"]
+           "adc3_mlp_forward", "adc3_mlp_train", "adc3_ea_precondition", "adc3_ea_solve_batched_workspace_bytes",
+           "adc3_ea_solve_batched", "adc3_ea_set_sigma_graphs"]
 
 
 class adc3_opts(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int), ("max_iter", ctypes.c_int), ("max_subspace", ctypes.c_int),
                 ("fno_correction", ctypes.c_int), ("precision", ctypes.c_int), ("precond", ctypes.c_int),
-                ("mlp_weights", ctypes.c_void_p)]
+                ("mlp_weights", ctypes.c_void_p), ("sigma_graphs", ctypes.c_int)]
+
+
+class adc3_instance(ctypes.Structure):
+    _fields_ = [("eps_occ", ctypes.c_void_p), ("eps_vir", ctypes.c_void_p), ("B", ctypes.c_void_p),
+                ("nocc", ctypes.c_int), ("nvir", ctypes.c_int), ("naux", ctypes.c_int), ("nroots", ctypes.c_int),
+                ("fno_thresh", ctypes.c_double), ("naf_thresh", ctypes.c_double), ("conv", ctypes.c_double)]
 
 
 class adc3_root_report(ctypes.Structure):
@@ -106,6 +113,15 @@ def load():
     lib.adc3_mlp_train.restype = I
     lib.adc3_ea_precondition.argtypes = [P, D, P, P, ctypes.POINTER(I), P]
     lib.adc3_ea_precondition.restype = I
+    lib.adc3_ea_solve_batched_workspace_bytes.argtypes = [ctypes.POINTER(adc3_instance), I,
+                                                          ctypes.POINTER(adc3_opts), I]
+    lib.adc3_ea_solve_batched_workspace_bytes.restype = S
+    lib.adc3_ea_solve_batched.argtypes = [ctypes.POINTER(adc3_instance), I, ctypes.POINTER(adc3_opts), I,
+                                          ctypes.POINTER(D), ctypes.POINTER(adc3_root_report), ctypes.POINTER(I),
+                                          P, S, P]
+    lib.adc3_ea_solve_batched.restype = I
+    lib.adc3_ea_set_sigma_graphs.argtypes = [P, I]
+    lib.adc3_ea_set_sigma_graphs.restype = I
     _lib = lib
     return lib
 
@@ -174,6 +190,47 @@ def adc3_ea_solve(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, opt
     return np.array(roots[:]), reports, st
 
 
+def _instances(instances):
+    arr = (adc3_instance * len(instances))()
+    for i, d in enumerate(instances):
+        eo, ev, B = d["eps_occ"], d["eps_vir"], d["B"]
+        arr[i] = adc3_instance(_ptr(eo).value, _ptr(ev).value, _ptr(B).value, int(eo.numel()), int(ev.numel()),
+                               int(B.shape[0]), int(d["nroots"]), float(d.get("fno_thresh", 0.0)),
+                               float(d.get("naf_thresh", 0.0)), float(d["conv"]))
+    return arr
+
+
+def adc3_ea_solve_batched_workspace_bytes(instances, opts=None, nstreams=0):
+    o = opts if opts is not None else adc3_default_opts()
+    arr = _instances(instances)
+    return load().adc3_ea_solve_batched_workspace_bytes(arr, len(instances), ctypes.byref(o), nstreams)
+
+
+def adc3_ea_solve_batched(instances, opts=None, nstreams=0, workspace=None):
+    """Solve a ragged list of instances (dicts: eps_occ, eps_vir, B device tensors, nroots, conv,
+    fno_thresh, naf_thresh).  Returns (list of root arrays, list of report lists, statuses, status)."""
+    lib = load()
+    o = opts if opts is not None else adc3_default_opts()
+    arr = _instances(instances)
+    n = len(instances)
+    if workspace is None:
+        workspace = _workspace(lib.adc3_ea_solve_batched_workspace_bytes(arr, n, ctypes.byref(o), nstreams))
+    tot = sum(int(d["nroots"]) for d in instances)
+    roots = (ctypes.c_double * tot)()
+    reps = (adc3_root_report * tot)()
+    sts = (ctypes.c_int * n)()
+    st = lib.adc3_ea_solve_batched(arr, n, ctypes.byref(o), nstreams, roots, reps, sts,
+                                   ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream())
+    _check(st, allow_noconv=True)
+    out_r, out_p, k = [], [], 0
+    for d in instances:
+        m = int(d["nroots"])
+        out_r.append(np.array(roots[k:k + m]))
+        out_p.append([{f: getattr(r, f) for f, _ in adc3_root_report._fields_} for r in reps[k:k + m]])
+        k += m
+    return out_r, out_p, list(sts), st
+
+
 def adc3_ea_setup_workspace_bytes(nocc, nvir, naux, level, nroots=0, precision=0):
     return load().adc3_ea_setup_workspace_bytes(nocc, nvir, naux, level, nroots, precision)
 
@@ -232,6 +289,10 @@ class Context:
                                      _ptr(vec) if vec is not None else None, rn, ctypes.byref(it), _stream())
         _check(st, allow_noconv=True)
         return np.array(w[:]), vec, np.array(rn[:]), it.value, st
+
+    def set_sigma_graphs(self, on=True):
+        """Replay sigma passes from captured HIP graphs (on a non-null stream)."""
+        _check(load().adc3_ea_set_sigma_graphs(self.handle, 1 if on else 0))
 
     def set_preconditioner(self, weights):
         """Learned preconditioner for davidson() (float32 device weights; None: Jacobi)."""

@@ -30,6 +30,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <string>
+#include <thread>
 #include <vector>
 
 namespace adc3 {
@@ -99,9 +102,21 @@ struct Ctx {
     // learned preconditioner: weights (caller's device memory) and the BF16 W2 copy
     const float* mlp_w = nullptr;
     unsigned short* mlp_wb = nullptr;
+    // sigma temporaries live in a region fixed for the context's lifetime, so a sigma pass
+    // captured into a HIP graph stays valid; gin/gout stage the vectors of a replayed pass
+    char* sig_base = nullptr;
+    size_t sig_bytes = 0;
+    double *gin = nullptr, *gout = nullptr;
+    bool graphs = false;
+    std::map<int, hipGraphExec_t> graph_exec;  // key: vectors * 4 + precision
+    ~Ctx() {
+        for (auto& kv : graph_exec) (void)hipGraphExecDestroy(kv.second);
+    }
 };
 
 static double* take(Arena& ws, long long n) { return ws.take<double>((size_t)std::max<long long>(n, 1)); }
+static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, hipStream_t s, int prec);
+static size_t sigma_region_bytes(Ctx* c);
 
 // symmetric part, scaled: M += a * (P + P^T)/2, P destroyed
 static void add_sym(double* M, double* P, int v, double a, hipStream_t s) {
@@ -158,6 +173,10 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     c->xtb = c->xb + NVMAX * (long long)o * vv;
     c->sdb = c->xtb + NVMAX * (long long)o * vv;
     c->sb = take(ws, NVMAX * (long long)o * vv);
+    c->gin = take(ws, NVMAX * c->N);
+    c->gout = take(ws, NVMAX * c->N);
+    c->sig_bytes = sigma_region_bytes(c);
+    c->sig_base = ws.take<char>(c->sig_bytes);
     // ---- everything below is temporary ----
     const size_t mark = ws.mark();
     GemmScratch gscr(ws, GEMM_SCRATCH);
@@ -312,17 +331,12 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
 }
 
 // sigma = M r for nvec vectors
-static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nvec, hipStream_t s, int prec = 0) {
-    if (prec > c->prec) prec = c->prec;
-    ProfScope prof(PROF_SIGMA, s, 0.0, 0.0);
-    const size_t smark = wsin.mark();
-    GemmScratch gscr(wsin, GEMM_SCRATCH);
+// One pass of at most NVMAX vectors: ss[nv][N] = M rr[nv][N], temporaries from ws.
+static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, hipStream_t s, int prec) {
+    GemmScratch gscr(ws, GEMM_SCRATCH);
     const int o = c->o, v = c->v;
     const long long N = c->N, vv = (long long)v * v, ovv = (long long)o * vv;
-    for (int n0 = 0; n0 < nvec; n0 += NVMAX) {
-        const int nv = std::min(NVMAX, nvec - n0);
-        const double* rr = r + (long long)n0 * N;
-        double* ss = sg + (long long)n0 * N;
+    {
         // 1p: M11 r1 + U_z z
         gemm_rm(nv, v, v, 1.0, rr, N, false, c->M11, v, true, 0.0, ss, N, s);
         if (prec > 0) {
@@ -345,7 +359,6 @@ static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nve
         }
         k_k0_add(ss + v, rr + v, c->eo, c->ev, o, v, nv, N, s);
         if (c->level >= 3) {
-            Arena& ws = wsin;
             double* zb = c->zb;
             k_copy2d(zb, ovv, rr + v, N, nv, ovv, 1.0, 0.0, s);
             // ladder: sum_cd (ac|bd) z_cd  (G symmetric)
@@ -390,8 +403,68 @@ static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nve
             k_copy2d(ss + v, N, c->sb, ovv, nv, ovv, 1.0, 1.0, s);
         }
     }
+}
+
+// Bytes of the fixed sigma region: the peak of a pass of NVMAX vectors at either precision.
+static size_t sigma_region_bytes(Ctx* c) {
+    const bool was = g_dry;
+    g_dry = true;
+    size_t peak = 0;
+    for (int p : {0, c->prec}) {
+        Arena count;
+        sigma_pass(c, count, nullptr, nullptr, NVMAX, nullptr, p);
+        peak = std::max(peak, count.peak);
+    }
+    g_dry = was;
+    return peak + 4096;
+}
+
+// The context's fixed sigma region as an arena.
+static Arena sigma_arena(const Ctx* c) {
+    Arena a;
+    a.base = c->sig_base;
+    a.cap = c->sig_bytes;
+    return a;
+}
+
+// sigma = M r for nvec vectors, in passes of NVMAX.  With graphs on (and a non-null
+// stream) each pass shape is captured once, after one eager pass that also settles the
+// ladder tuner, and replayed on staged copies of the vectors.
+static void sigma_impl(Ctx* c, Arena& wsin, const double* r, double* sg, int nvec, hipStream_t s, int prec = 0) {
+    (void)wsin;
+    if (prec > c->prec) prec = c->prec;
+    ProfScope prof(PROF_SIGMA, s, 0.0, 0.0);
+    const long long N = c->N;
+    const bool use_graph = c->graphs && s != nullptr && !g_dry;
+    for (int n0 = 0; n0 < nvec; n0 += NVMAX) {
+        const int nv = std::min(NVMAX, nvec - n0);
+        const double* rr = r + (long long)n0 * N;
+        double* ss = sg + (long long)n0 * N;
+        Arena sw = sigma_arena(c);
+        if (!use_graph) {
+            sigma_pass(c, sw, rr, ss, nv, s, prec);
+            continue;
+        }
+        const int key = nv * 4 + prec;
+        auto it = c->graph_exec.find(key);
+        if (it == c->graph_exec.end()) {
+            sigma_pass(c, sw, rr, ss, nv, s, prec);  // eager, and the tuner's first look at this shape
+            hipGraph_t gr = nullptr;
+            Arena sw2 = sigma_arena(c);
+            HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            sigma_pass(c, sw2, c->gin, c->gout, nv, s, prec);
+            HIPCHK(hipStreamEndCapture(s, &gr));
+            hipGraphExec_t ex = nullptr;
+            HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+            HIPCHK(hipGraphDestroy(gr));
+            c->graph_exec[key] = ex;
+            continue;
+        }
+        k_copy(c->gin, rr, (long long)nv * N, s);
+        HIPCHK(hipGraphLaunch(it->second, s));
+        k_copy(ss, c->gout, (long long)nv * N, s);
+    }
     c->sigma_count += nvec;
-    wsin.release(smark);
 }
 
 // ---------------------------------------------------------------------------
@@ -794,6 +867,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         const size_t mark = ws.mark();
         Ctx* c = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, level, s, op.precision);
         c->mlp_w = op.mlp_weights;
+        c->graphs = op.sigma_graphs != 0;
         DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
                                     op.precond == 1);
         for (int k = 0; k < nroots; ++k) {
@@ -815,6 +889,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     // steps 2-3: canonical MP2 density and canonical ADC(2) roots
     const size_t mark0 = ws.mark();
     Ctx* c0 = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, 2, s, op.precision);
+    c0->graphs = op.sigma_graphs != 0;
     double* Y2 = take(ws, (long long)nroots * c0->N);
     DavResult r2 = davidson_impl(c0, ws, nroots, conv, op.max_iter, op.max_subspace, Y2, s, op.precision);
     out.all_conv = out.all_conv && r2.converged;
@@ -872,6 +947,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             double* part = take(ws, (long long)dots_partial_elems(nroots, 1, Nk));
             const size_t m2 = ws.mark();
             Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s, op.precision);
+            c2->graphs = op.sigma_graphs != 0;
             DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s, op.precision,
                                          false, nullptr, carried, nroots);
             k_dots(Y2k, Nk, nroots, ref, Nk, 1, Nk, ovl, 1, part, s);
@@ -894,6 +970,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             const size_t m3 = ws.mark();
             Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s, op.precision);
             c3->mlp_w = op.mlp_weights;
+            c3->graphs = op.sigma_graphs != 0;
             DavResult a3 = davidson_impl(c3, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
                                          op.precond == 1, nullptr, Y2k, nroots);
             R.omega_uncorr = a3.w[match];
@@ -955,6 +1032,7 @@ void adc3_default_opts(adc3_opts* o) {
     o->precision = 0;
     o->precond = 0;
     o->mlp_weights = nullptr;
+    o->sigma_graphs = 0;
 }
 
 const char* adc3_last_error(void) { return g_msg.c_str(); }
@@ -1186,13 +1264,12 @@ extern "C" size_t adc3_ea_solve_workspace_bytes(int nocc, int nvir, int naux, in
     }
 }
 
-extern "C" int adc3_ea_solve(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir,
-                             int naux, int nroots, double fno_thresh, double naf_thresh, double conv,
-                             const adc3_opts* opts, double* roots_out, adc3_root_report* reports, void* workspace,
-                             size_t ws_bytes, hipStream_t stream) {
-    API_BEGIN
+// One instance: validate, split B, run the pipeline.  Throws Error; returns OK or WNOCONV.
+static int solve_one(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir, int naux,
+                     int nroots, double fno_thresh, double naf_thresh, double conv, const adc3_opts& op,
+                     double* roots_out, adc3_root_report* reports, void* workspace, size_t ws_bytes,
+                     hipStream_t stream) {
     check_dims(nocc, nvir, naux);
-    adc3_opts op = resolve_opts(opts);
     if (!eps_occ || !eps_vir || (!B && naux > 0) || !roots_out || !workspace) fail(ADC3_EINVAL, "NULL pointer argument");
     const long long N = nvir + (long long)nocc * nvir * nvir;
     if (nroots < 1 || nroots > N) fail(ADC3_EINVAL, "nroots must be in [1, N]");
@@ -1220,6 +1297,160 @@ extern "C" int adc3_ea_solve(const double* eps_occ, const double* eps_vir, const
         if (reports) reports[k] = r.rep[k];
     }
     return r.all_conv ? ADC3_OK : ADC3_WNOCONV;
+}
+
+extern "C" int adc3_ea_solve(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir,
+                             int naux, int nroots, double fno_thresh, double naf_thresh, double conv,
+                             const adc3_opts* opts, double* roots_out, adc3_root_report* reports, void* workspace,
+                             size_t ws_bytes, hipStream_t stream) {
+    API_BEGIN
+    adc3_opts op = resolve_opts(opts);
+    return solve_one(eps_occ, eps_vir, B, nocc, nvir, naux, nroots, fno_thresh, naf_thresh, conv, op, roots_out,
+                     reports, workspace, ws_bytes, stream);
+    API_END
+}
+
+// ---------------------------------------------------------------------------
+// Ragged batches.  Instances are spread over worker streams (one host thread each) by
+// longest-processing-time-first on an estimate of their work; a worker solves its
+// instances in turn in its own slice of the workspace (sized for the largest of them).
+// While one worker waits on a host synchronisation of its Davidson, the others keep
+// the GPU busy, so small launch-bound instances overlap with each other and with the
+// large ladder-bound ones.
+// ---------------------------------------------------------------------------
+namespace {
+struct BatchPlan {
+    std::vector<int> worker;        // per instance
+    std::vector<size_t> offset;     // per worker, bytes into the workspace
+    std::vector<size_t> bytes;      // per worker
+    size_t total = 0;
+};
+
+double instance_cost(const adc3_instance& in) {
+    const double o = in.nocc, v = in.nvir, X = in.naux, v4 = v * v * v * v;
+    return 2.0 * o * v4 * in.nroots * 20.0 + 2.0 * X * v4 + 2.0 * o * o * v4 + 5e9;
+}
+
+BatchPlan plan_batch(const adc3_instance* inst, int ninst, const adc3_opts& op, int nworkers) {
+    BatchPlan P;
+    P.worker.assign(ninst, 0);
+    std::vector<int> order(ninst);
+    for (int i = 0; i < ninst; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return instance_cost(inst[a]) > instance_cost(inst[b]); });
+    std::vector<double> load(nworkers, 0.0);
+    P.bytes.assign(nworkers, 0);
+    for (int i : order) {
+        const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        P.worker[i] = w;
+        load[w] += instance_cost(inst[i]);
+        check_dims(inst[i].nocc, inst[i].nvir, inst[i].naux);
+        Arena plan;
+        plan_solve(inst[i].nocc, inst[i].nvir, inst[i].naux, inst[i].nroots, op, plan);
+        P.bytes[w] = std::max(P.bytes[w], (plan.peak + (1 << 20) + 255) / 256 * 256);
+    }
+    P.offset.assign(nworkers, 0);
+    for (int w = 0; w < nworkers; ++w) {
+        P.offset[w] = P.total;
+        P.total += P.bytes[w];
+    }
+    return P;
+}
+
+int batch_workers(int nstreams, int ninst) { return std::max(1, std::min(nstreams > 0 ? nstreams : 4, ninst)); }
+}  // namespace
+
+extern "C" size_t adc3_ea_solve_batched_workspace_bytes(const adc3_instance* inst, int ninst, const adc3_opts* opts,
+                                                        int nstreams) {
+    try {
+        if (!inst || ninst < 1) return 0;
+        adc3_opts op = resolve_opts(opts);
+        return plan_batch(inst, ninst, op, batch_workers(nstreams, ninst)).total;
+    } catch (...) {
+        g_dry = false;
+        return 0;
+    }
+}
+
+extern "C" int adc3_ea_solve_batched(const adc3_instance* inst, int ninst, const adc3_opts* opts, int nstreams,
+                                     double* roots_out, adc3_root_report* reports, int* status_out, void* workspace,
+                                     size_t ws_bytes, hipStream_t stream) {
+    API_BEGIN
+    if (!inst || ninst < 1 || !roots_out || !workspace) fail(ADC3_EINVAL, "NULL argument or ninst < 1");
+    adc3_opts op = resolve_opts(opts);
+    const int nw = batch_workers(nstreams, ninst);
+    BatchPlan P = plan_batch(inst, ninst, op, nw);
+    if (P.total > ws_bytes) fail(ADC3_ENOMEM, "workspace too small: need " + std::to_string(P.total) + " bytes");
+    std::vector<long long> first(ninst + 1, 0);
+    for (int i = 0; i < ninst; ++i) first[i + 1] = first[i] + std::max(inst[i].nroots, 0);
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    hipEvent_t ready;
+    HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(ready, stream));
+    std::vector<int> st(ninst, ADC3_OK);
+    std::vector<std::string> msg(ninst);
+    std::vector<hipEvent_t> done(nw, nullptr);
+    std::vector<std::thread> th;
+    for (int w = 0; w < nw; ++w) {
+        th.emplace_back([&, w]() {
+            hipStream_t ws = nullptr;
+            try {
+                HIPCHK(hipSetDevice(dev));
+                HIPCHK(hipStreamCreateWithFlags(&ws, hipStreamNonBlocking));
+                HIPCHK(hipStreamWaitEvent(ws, ready, 0));
+                for (int i = 0; i < ninst; ++i) {
+                    if (P.worker[i] != w) continue;
+                    try {
+                        st[i] = solve_one(inst[i].eps_occ, inst[i].eps_vir, inst[i].B, inst[i].nocc, inst[i].nvir,
+                                          inst[i].naux, inst[i].nroots, inst[i].fno_thresh, inst[i].naf_thresh,
+                                          inst[i].conv, op, roots_out + first[i], reports ? reports + first[i] : nullptr,
+                                          (char*)workspace + P.offset[w], P.bytes[w], ws);
+                    } catch (const Error& e) {
+                        g_dry = false;
+                        st[i] = e.status;
+                        msg[i] = e.msg;
+                        if (e.status == ADC3_EHIP) break;  // the stream may be unusable
+                    }
+                }
+                HIPCHK(hipEventCreateWithFlags(&done[w], hipEventDisableTiming));
+                HIPCHK(hipEventRecord(done[w], ws));
+                HIPCHK(hipStreamSynchronize(ws));
+            } catch (const Error& e) {
+                for (int i = 0; i < ninst; ++i)
+                    if (P.worker[i] == w && st[i] == ADC3_OK) { st[i] = e.status; msg[i] = e.msg; }
+            }
+            if (ws) (void)hipStreamDestroy(ws);
+        });
+    }
+    for (auto& t : th) t.join();
+    for (int w = 0; w < nw; ++w)
+        if (done[w]) {
+            (void)hipStreamWaitEvent(stream, done[w], 0);
+            (void)hipEventDestroy(done[w]);
+        }
+    (void)hipEventDestroy(ready);
+    int worst = ADC3_OK;
+    std::string first_msg;
+    for (int i = 0; i < ninst; ++i) {
+        if (status_out) status_out[i] = st[i];
+        if (st[i] < 0 && (worst >= 0 || st[i] < worst)) {
+            if (first_msg.empty()) first_msg = "instance " + std::to_string(i) + ": " + msg[i];
+            worst = st[i];
+        } else if (st[i] == ADC3_WNOCONV && worst == ADC3_OK) {
+            worst = ADC3_WNOCONV;
+        }
+    }
+    if (worst < 0) set_error(first_msg);
+    return worst;
+    API_END
+}
+
+extern "C" int adc3_ea_set_sigma_graphs(adc3_ctx* ctx, int on) {
+    API_BEGIN
+    if (!ctx) fail(ADC3_EINVAL, "NULL ctx");
+    ctx->c->graphs = on != 0;
+    return ADC3_OK;
     API_END
 }
 

@@ -38,6 +38,8 @@ void drain() {
 
 ProfScope::ProfScope(int kernel, hipStream_t stream, double f, double b) : k(kernel), s(stream), flops(f), bytes(b) {
     if (!enabled || g_dry) return;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
     hipEvent_t e;
     if (hipEventCreate(&e) != hipSuccess) return;
     if (hipEventRecord(e, s) != hipSuccess) { (void)hipEventDestroy(e); return; }

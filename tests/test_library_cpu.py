@@ -33,6 +33,31 @@ def test_exports_every_declared_symbol(lib):
 def test_default_opts(lib):
     o = adc.adc3_default_opts()
     assert (o.level, o.max_iter, o.max_subspace, o.fno_correction, o.precision, o.precond) == (3, 500, 0, 1, 0, 0)
+    assert not o.mlp_weights and o.sigma_graphs == 0
+
+
+def _inst(shapes):
+    arr = (adc.adc3_instance * len(shapes))()
+    for i, (o, v, x, nr) in enumerate(shapes):
+        arr[i] = adc.adc3_instance(None, None, None, o, v, x, nr, 0.0, 0.0, 1e-6)
+    return arr
+
+
+def test_batched_workspace_planning(lib):
+    """Each worker's slice holds its largest instance; one worker needs the largest single solve."""
+    o = adc.adc3_default_opts()
+    shapes = [(4, 20, 60, 3), (6, 40, 120, 3), (3, 12, 36, 2), (5, 30, 90, 4)]
+    arr = _inst(shapes)
+    single = [adc.adc3_ea_solve_workspace_bytes(a, b, c, d, o) for a, b, c, d in shapes]
+    one = lib.adc3_ea_solve_batched_workspace_bytes(arr, 4, ctypes.byref(o), 1)
+    four = lib.adc3_ea_solve_batched_workspace_bytes(arr, 4, ctypes.byref(o), 4)
+    assert max(single) <= one < max(single) + (2 << 20)
+    assert sum(single) <= four < sum(single) + 4 * (2 << 20)
+    assert lib.adc3_ea_solve_batched_workspace_bytes(arr, 0, ctypes.byref(o), 2) == 0
+    assert lib.adc3_ea_solve_batched_workspace_bytes(_inst([(0, 20, 60, 3)]), 1, ctypes.byref(o), 2) == 0
+    roots = (ctypes.c_double * 12)()
+    st = lib.adc3_ea_solve_batched(arr, 4, ctypes.byref(o), 2, roots, None, None, None, 0, None)
+    assert st == adc.ADC3_EINVAL
 
 
 def test_workspace_planning(lib):
