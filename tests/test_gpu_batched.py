@@ -147,3 +147,32 @@ def test_ladder_tuner_cache_file(tmp_path):
         assert any(l.startswith("ladder_f64 gfx950 ") and l.split()[-1].isdigit() for l in lines)
     finally:
         del os.environ["ADC3_TUNE_CACHE"]
+
+
+# instances of the ragged batched workload (nocc~U{5..30}, nvir~U{50..300}, naux = 3 nvir,
+# literal scale, 8 roots) small enough for a quick test: the generator's seeds with nvir <= 100
+BATCH_SEEDS = (142, 126, 150, 113, 112, 149)
+
+
+def test_batched_workload_instances_mixed_precision():
+    from oracle.davidson import davidson
+    raw = [synth.batch_instance(s) for s in BATCH_SEEDS]
+    inst = _as_instances(raw, nroots=8, conv=1e-6)
+    o = adc.adc3_default_opts()
+    o.precision = 1
+    o.sigma_graphs = 1
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        roots, reps, sts, st = adc.adc3_ea_solve_batched(inst, opts=o, nstreams=3)
+        assert st == 0 and all(s == 0 for s in sts)
+        for d, r, rp in zip(inst, roots, reps):
+            assert np.all(np.diff(r) >= 0)
+            assert all(x["resnorm"] <= 1e-6 for x in rp)
+            single, _, s1 = adc.adc3_ea_solve(d["eps_occ"], d["eps_vir"], d["B"], 8, 0.0, 0.0, 1e-6, opts=o)
+            assert s1 == 0 and np.abs(r - single).max() <= 1e-12 * max(1.0, np.abs(r).max())
+    torch.cuda.synchronize()
+    # the smallest instance against the FP64 oracle (mixed-precision bar 1e-6 Eh)
+    eo, ev, B = raw[0]
+    P = Problem(eo, ev, B)
+    w, _ = davidson(lambda X: P.sigma(X, 3), P.diagonal(3), 8, conv=1e-8)[:2]
+    assert np.all(np.abs(roots[0] - w[:8]) <= 1e-6 + 1e-12 * np.abs(w[:8]))
