@@ -34,12 +34,86 @@ def parse():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 mixed-precision solves")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner study")
     ap.add_argument("--sigma-reps", type=int, default=10)
     ap.add_argument("--sigma-only", action="store_true",
                     help="profiling mode: only the isolated ADC(3) sigma builds plus a 2 GiB copy (counter calibration)")
     ap.add_argument("--variant-scale", type=float, default=0.018,
                     help="also time one solve with B scaled by this factor (weak correlation, FNO truncates); 0 = skip")
     return ap.parse_args()
+
+
+# HBM traffic of the ladder kernel per launch, from two rocprofv3 --pmc runs (FETCH_SIZE,
+# then WRITE_SIZE) of `bench.py --sigma-only`, each scaled by the same counter's reading
+# for a copy of known size.  Keyed by a hash of the kernel's source: a changed kernel
+# reports null until it is measured again.
+LADDER_TRAFFIC = {
+    "7a0b4ea01ddb2338": {
+        "bytes_per_launch": 13.43e9, "read_bytes": 13.17e9, "written_bytes": 0.256e9,
+        "fetch_scale": 2.0, "write_scale": 1.0,
+        "measured_on": "sigma ladder o=20 v=200 X=128, 5 vectors (M=100), 8 K-chunks",
+        "profile": "profiles/ladder_f64_o20v200x128_sigma_counters.md"},
+}
+
+
+def ladder_traffic():
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_05897_amd", "csrc", "ladder.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return h, LADDER_TRAFFIC.get(h)
+
+
+def learned_study(adc, d, torch, np):
+    """Learned preconditioner vs Jacobi (ADC(3), 5 roots, conv 1e-6, scale 0.3): for each shape,
+    collect 2000 groups from Jacobi solves of seeds 200-239, train on the GPU, then solve the
+    held-out seeds 240-243 both ways (iterations, wall time, root agreement)."""
+    import synth
+    scale, nroots, out = 0.3, 5, {}
+    for shape in ((6, 40, 120), (16, 120, 360)):
+        t0 = time.perf_counter()
+        Fs, As, Ds = [], [], []
+        for seed in range(200, 240):
+            eo, ev, B = synth.make_instance(*shape, seed, scale=scale)
+            ctx = adc.Context(d(eo), d(ev), d(B), 3, nroots=nroots)
+            F, A, D, _ = ctx.mlp_collect(nroots, 1e-6, 256, 50, seed)
+            Fs.append(F)
+            As.append(A)
+            Ds.append(D)
+            ctx.close()
+        F, A, D = torch.cat(Fs), torch.cat(As), torch.cat(Ds)
+        t_collect = time.perf_counter() - t0
+        w = torch.as_tensor(synth.mlp_init(1), device="cuda")
+        t0 = time.perf_counter()
+        losses = adc.adc3_mlp_train(w, F, A, D, epochs=60, batch_groups=32, lr=2e-3, seed=7)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        held = {"jacobi": {"iterations": 0, "wall_s": 0.0}, "learned": {"iterations": 0, "wall_s": 0.0}}
+        dmax, statuses = 0.0, []
+        for seed in range(240, 244):
+            eo, ev, B = synth.make_instance(*shape, seed, scale=scale)
+            ctx = adc.Context(d(eo), d(ev), d(B), 3, nroots=nroots)
+            ctx.davidson(nroots, 1e-6)  # warm-up (tuner, first launches)
+            roots = {}
+            for tag, weights in (("jacobi", None), ("learned", w)):
+                ctx.set_preconditioner(weights)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                wr, _, _, it, st = ctx.davidson(nroots, 1e-6)
+                torch.cuda.synchronize()
+                held[tag]["iterations"] += it
+                held[tag]["wall_s"] += time.perf_counter() - t1
+                roots[tag] = wr
+                statuses.append(st)
+            dmax = max(dmax, float(np.abs(roots["learned"] - roots["jacobi"]).max()))
+            ctx.close()
+        out["o%dv%dx%d" % shape] = {
+            "train": {"seeds": "200-239", "groups": int(F.shape[0]), "group_size": 256, "collect_s": t_collect,
+                      "train_s": t_train, "epochs": 60, "loss_first_last": [float(losses[0]), float(losses[-1])]},
+            "held_out": {"seeds": "240-243", **held, "statuses": statuses,
+                         "iteration_ratio": held["learned"]["iterations"] / max(held["jacobi"]["iterations"], 1),
+                         "wall_ratio": held["learned"]["wall_s"] / held["jacobi"]["wall_s"],
+                         "max_abs_root_diff_Eh": dmax}}
+    return {"scale": scale, "level": 3, "nroots": nroots, "conv": 1e-6, "shapes": out}
 
 
 def cpu_baseline(shape, nvec):
@@ -127,24 +201,25 @@ def main():
 
     # isolated ADC(3) sigma builds (blocks of nroots vectors) in a basis of the truncated shape
     iso = None
-    try:
-        e2, v2, B2 = synth.make_instance(p["nocc"], vk, xk, 1, scale=a.scale)
-        ctx = adc.Context(d(e2), d(v2), d(B2), 3, nroots=0)
-        r = torch.randn((nroots, ctx.N), dtype=torch.float64, device="cuda")
-        out = torch.empty_like(r)
-        ctx.sigma(r, out)
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        for _ in range(a.sigma_reps):
+    if a.sigma_reps > 0:
+        try:
+            e2, v2, B2 = synth.make_instance(p["nocc"], vk, xk, 1, scale=a.scale)
+            ctx = adc.Context(d(e2), d(v2), d(B2), 3, nroots=0)
+            r = torch.randn((nroots, ctx.N), dtype=torch.float64, device="cuda")
+            out = torch.empty_like(r)
             ctx.sigma(r, out)
-        torch.cuda.synchronize()
-        sdt = time.perf_counter() - s0
-        iso = {"value": a.sigma_reps * nroots / sdt, "unit": "sigma-builds/s", "nvec_per_call": nroots,
-               "shape": {"nocc": p["nocc"], "nvir": vk, "naux": xk}}
-        ctx.close()
-        del ctx
-    except Exception as e:  # reported, never silent
-        iso = {"error": str(e)}
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            for _ in range(a.sigma_reps):
+                ctx.sigma(r, out)
+            torch.cuda.synchronize()
+            sdt = time.perf_counter() - s0
+            iso = {"value": a.sigma_reps * nroots / sdt, "unit": "sigma-builds/s", "nvec_per_call": nroots,
+                   "shape": {"nocc": p["nocc"], "nvir": vk, "naux": xk}}
+            ctx.close()
+            del ctx
+        except Exception as e:  # reported, never silent
+            iso = {"error": str(e)}
 
     # the same solve with reduced-precision sigma (FP64 residual correction), vs the FP64 roots
     mixed = {}
@@ -198,6 +273,13 @@ def main():
             variant = {"error": str(e)}
 
     achieved = lad_f / (lad_ms * 1e-3) / 1e12 if lad_ms > 0 else 0.0
+    src_hash, traffic = ladder_traffic()
+    learned = None
+    if not a.no_learned:
+        try:
+            learned = learned_study(adc, d, torch, np)
+        except Exception as e:
+            learned = {"error": str(e)}
     line = {
         "metric": "sigma-builds/s (whole SS-FNO-EA-ADC(3) solve) + time-to-5-roots, FP64, 1 GPU",
         "value": nsig / dt,
@@ -220,7 +302,9 @@ def main():
         "status": st,
         "roofline": {"kernel": "sigma ladder (ladder_f64_kernel)", "bound": "mfma",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_detail": traffic, "kernel_source_hash": src_hash,
                      "launches": lad_n, "avg_launch_ms": lad_ms / max(lad_n, 1),
                      "flops_per_launch": lad_f / max(lad_n, 1)},
         "phases_ms_per_step": {"setup": setup_ms / a.steps, "davidson": dav_ms / a.steps,
@@ -229,6 +313,7 @@ def main():
         "sigma_adc3_isolated": iso,
         "mixed_precision": mixed,
         "variant_weak_correlation": variant,
+        "learned_preconditioner": learned,
     }
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline((p["nocc"], vk, xk), nroots)

@@ -201,7 +201,8 @@ int adc3_ea_intermediate(adc3_ctx* ctx, int which, double* out_dev, long long* c
  * W1[6][256], b1[256], W2[256][256], b2[256], W3[256], b3[1]; W3 = b3 = 0 gives
  * exactly the Jacobi step.  Inference: one fused kernel per residual (FP32 first
  * layer, BF16 matrix-core second layer with FP32 accumulation, FP32 head).  A
- * non-finite step or a residual that grows by more than 2x switches that root back
+ * non-finite step, a residual that grows by more than 2x in one iteration, or one that
+ * has not improved on its best value by 10% in 5 iterations switches that root back
  * to Jacobi for the rest of the solve.
  * ------------------------------------------------------------------------- */
 int adc3_mlp_nparams(void);

@@ -514,7 +514,7 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     double* Vk = take(ws, (long long)nkeep_max * N);
     double* Sk = take(ws, (long long)nkeep_max * N);
     double* small = take(ws, 16);
-    unsigned int* mflag = (unsigned int*)take(ws, 1);
+    unsigned int* mflag = (unsigned int*)take(ws, (mmax + 1) / 2);  // one flag word per new direction
     double* part = take(ws, (long long)dots_partial_elems(mmax, mmax, N));
     DavResult res;
     res.w.assign(nroots, 0.0);
@@ -580,6 +580,8 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     k_dots(V, N, m, S, N, m, N, Gf, mmax, part, s);
     std::vector<double> thold(nroots, INFINITY), hw(mmax), hrn(nroots * nroots), prev_rn(nroots, INFINITY);
     std::vector<char> mlp_on(nroots, (use_mlp && c->mlp_w) ? 1 : 0);
+    std::vector<double> mlp_best(nroots, INFINITY);
+    std::vector<int> mlp_stall(nroots, 0);
     if (use_mlp && c->mlp_w) mlp_weights_bf16(c->mlp_w, c->mlp_wb, s);
     std::vector<double> hY;
     int it = 0;
@@ -679,29 +681,51 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
                 rec->G++;
             }
         }
-        // preconditioned residuals of the unconverged roots -> V[m .. m+nn)
+        // preconditioned residuals of the unconverged roots -> V[m .. m+nn); learned steps for all
+        // roots first, one flag word each, read back once
         double* Tn = V + (long long)m * N;
+        bool any_mlp = false;
         for (int j = 0; j < nn; ++j) {
-            int k = todo[j];
-            if (mlp_on[k] && it > 1 && res.rn[k] > 2.0 * prev_rn[k]) {
-                mlp_on[k] = 0;  // the learned step made the residual grow: Jacobi from here on
-                VLOG("root %d: learned preconditioner disabled (residual grew)", k);
-            }
-            bool done_mlp = false;
+            const int k = todo[j];
             if (mlp_on[k]) {
-                const double rms = std::max(res.rn[k] / std::sqrt((double)N), 1e-300);
-                HIPCHK(hipMemsetAsync(mflag, 0, sizeof(unsigned int), s));
-                mlp_precondition(R + (long long)k * N, c->diag, res.w[k], rms, c->eo, c->ev, c->o, c->v, N, c->mlp_w,
-                                 c->mlp_wb, Tn + (long long)j * N, mflag, s);
-                unsigned int hf = 0;
-                d2h(&hf, mflag, sizeof(hf), s);
-                done_mlp = (hf == 0);
-                if (!done_mlp) {
+                // Jacobi from here on if the learned steps made the residual grow, or stopped
+                // reducing it (no 10% gain on its best value in 5 iterations)
+                if (res.rn[k] < 0.9 * mlp_best[k]) {
+                    mlp_best[k] = res.rn[k];
+                    mlp_stall[k] = 0;
+                } else {
+                    ++mlp_stall[k];
+                }
+                if ((it > 1 && res.rn[k] > 2.0 * prev_rn[k]) || mlp_stall[k] >= 5) {
                     mlp_on[k] = 0;
-                    VLOG("root %d: learned preconditioner gave a non-finite step; Jacobi from here on", k);
+                    VLOG("root %d: learned preconditioner disabled (residual %s)", k,
+                         mlp_stall[k] >= 5 ? "stalled" : "grew");
                 }
             }
-            if (!done_mlp) k_precond(Tn + (long long)j * N, R + (long long)k * N, c->diag, th + k, 1, N, s);
+            any_mlp = any_mlp || mlp_on[k];
+        }
+        if (any_mlp) k_fill((double*)mflag, (nn + 1) / 2, 0.0, s);
+        for (int j = 0; j < nn; ++j) {
+            const int k = todo[j];
+            if (mlp_on[k]) {
+                const double rms = std::max(res.rn[k] / std::sqrt((double)N), 1e-300);
+                mlp_precondition(R + (long long)k * N, c->diag, res.w[k], rms, c->eo, c->ev, c->o, c->v, N, c->mlp_w,
+                                 c->mlp_wb, Tn + (long long)j * N, mflag + j, s);
+            } else {
+                k_precond(Tn + (long long)j * N, R + (long long)k * N, c->diag, th + k, 1, N, s);
+            }
+        }
+        if (any_mlp) {
+            std::vector<unsigned int> hf(nn, 0);
+            d2h(hf.data(), mflag, nn * sizeof(unsigned int), s);
+            for (int j = 0; j < nn; ++j) {
+                const int k = todo[j];
+                if (mlp_on[k] && hf[j] != 0) {
+                    mlp_on[k] = 0;
+                    VLOG("root %d: learned preconditioner gave a non-finite step; Jacobi from here on", k);
+                    k_precond(Tn + (long long)j * N, R + (long long)k * N, c->diag, th + k, 1, N, s);
+                }
+            }
         }
         for (int k = 0; k < nroots; ++k) prev_rn[k] = res.rn[k];
         const int acc = orthonormalise(Tn, nn, m, R);

@@ -131,6 +131,27 @@ __global__ __launch_bounds__(NT) void gemm_f64_kernel(Gemm g) {
             }
 }
 
+// Deterministic: thread t sums chunks t, t+256, ... in order, then a fixed tree over threads.
+__global__ void splitk_reduce_tree_kernel(const double* part, int nchunk, int M, int N, double alpha, double beta,
+                                          double* C, long long sCm, long long sCn) {
+    const long long MN = (long long)M * N, t = blockIdx.x;
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < nchunk; c += blockDim.x) acc += part[(long long)c * MN + t];
+    __shared__ double red[256];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const long long m = t / N, n = t % N;
+        double* cp = C + m * sCm + n * sCn;
+        const double v = alpha * red[0];
+        *cp = (beta == 0.0) ? v : v + beta * (*cp);
+    }
+}
+
 __global__ void splitk_reduce_kernel(const double* part, int nchunk, int M, int N, double alpha, double beta,
                                      double* C, long long sCm, long long sCn) {
     long long MN = (long long)M * N;
@@ -189,8 +210,15 @@ void launch_tiles(const Gemm& g, hipStream_t s, int tag, long long nb, int sh) {
 void splitk_reduce(const double* part, int nchunk, int M, int N, double alpha, double beta, double* C,
                    long long sCm, long long sCn, hipStream_t s) {
     long long MN = (long long)M * N;
-    unsigned gb = (unsigned)std::min<long long>((MN + 255) / 256, 4096);
-    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(gb), dim3(256), 0, s, part, nchunk, M, N, alpha, beta, C, sCm, sCn);
+    if (MN <= 32768 && nchunk >= 64) {
+        // few outputs, many chunks: one block per output, chunks spread over its threads
+        hipLaunchKernelGGL(splitk_reduce_tree_kernel, dim3((unsigned)MN), dim3(256), 0, s, part, nchunk, M, N, alpha,
+                           beta, C, sCm, sCn);
+    } else {
+        unsigned gb = (unsigned)std::min<long long>((MN + 255) / 256, 4096);
+        hipLaunchKernelGGL(splitk_reduce_kernel, dim3(gb), dim3(256), 0, s, part, nchunk, M, N, alpha, beta, C, sCm,
+                           sCn);
+    }
     LAUNCHCHK();
 }
 
@@ -235,10 +263,7 @@ void gemm(const Gemm& g, hipStream_t s, int tag) {
             h.C = g_gemm_scratch; h.sCm = g.N; h.sCn = 1; h.bC0 = MN;
             h.nb0 = (int)nc; h.nb1 = 1;
             launch_tiles(h, s, tag, nc, sh);
-            unsigned gb = (unsigned)std::min<long long>((MN + 255) / 256, 4096);
-            hipLaunchKernelGGL(splitk_reduce_kernel, dim3(gb), dim3(256), 0, s, (const double*)g_gemm_scratch, (int)nc,
-                               g.M, g.N, g.alpha, g.beta, g.C, g.sCm, g.sCn);
-            LAUNCHCHK();
+            splitk_reduce(g_gemm_scratch, (int)nc, g.M, g.N, g.alpha, g.beta, g.C, g.sCm, g.sCn, s);
             return;
         }
     }

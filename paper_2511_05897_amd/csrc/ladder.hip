@@ -45,7 +45,8 @@ struct LadderArgs {
     double alpha, beta;
 };
 
-template <int TM>
+// TAG 1 marks the tuner's trial launches (a separate symbol for profilers).
+template <int TM, int TAG>
 __global__ __launch_bounds__(LNT, 2) void ladder_f64_kernel(LadderArgs g) {
     constexpr int BM = 16 * TM;
     constexpr int PA = (BM * (LBK / 2) + LNT - 1) / LNT;  // 16-byte A loads per thread
@@ -215,7 +216,7 @@ __device__ inline void store_f32_tile(const LadderLP& g, f4v (&acc)[TM][LTN], lo
 }
 
 constexpr int FBK = 32;
-template <int TM>
+template <int TM, int TAG>
 __global__ __launch_bounds__(LNT, 2) void ladder_f32_kernel(LadderLP g) {
     constexpr int BM = 16 * TM;
     constexpr int PA = (BM * (FBK / 4) + LNT - 1) / LNT;
@@ -303,7 +304,7 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f32_kernel(LadderLP g) {
 }
 
 constexpr int HBK = 64, HPAD = 8;
-template <int TM>
+template <int TM, int TAG>
 __global__ __launch_bounds__(LNT, 2) void ladder_bf16_kernel(LadderLP g) {
     constexpr int BM = 16 * TM;
     constexpr int PA = (BM * (HBK / 8) + LNT - 1) / LNT;
@@ -385,42 +386,54 @@ __global__ __launch_bounds__(LNT, 2) void ladder_bf16_kernel(LadderLP g) {
     store_f32_tile<TM>(g, acc, m0, n0, cb, chunk, lr, lk);
 }
 
-template <int TM>
+template <int TM, int TAG>
 void launch_lp_tm(const LadderLP& a, int prec, int mtiles, hipStream_t s) {
-    if (prec == 1) hipLaunchKernelGGL((ladder_f32_kernel<TM>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
-    else hipLaunchKernelGGL((ladder_bf16_kernel<TM>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
+    if (prec == 1) hipLaunchKernelGGL((ladder_f32_kernel<TM, TAG>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
+    else hipLaunchKernelGGL((ladder_bf16_kernel<TM, TAG>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
 }
 
-void launch_lp(const LadderLP& a, int prec, int tm, int mtiles, hipStream_t s) {
+template <int TAG>
+void launch_lp_tag(const LadderLP& a, int prec, int tm, int mtiles, hipStream_t s) {
     switch (tm) {
-        case 1: launch_lp_tm<1>(a, prec, mtiles, s); break;
-        case 2: launch_lp_tm<2>(a, prec, mtiles, s); break;
-        case 3: launch_lp_tm<3>(a, prec, mtiles, s); break;
-        case 4: launch_lp_tm<4>(a, prec, mtiles, s); break;
-        case 5: launch_lp_tm<5>(a, prec, mtiles, s); break;
-        case 6: launch_lp_tm<6>(a, prec, mtiles, s); break;
-        case 7: launch_lp_tm<7>(a, prec, mtiles, s); break;
-        default: launch_lp_tm<8>(a, prec, mtiles, s); break;
+        case 1: launch_lp_tm<1, TAG>(a, prec, mtiles, s); break;
+        case 2: launch_lp_tm<2, TAG>(a, prec, mtiles, s); break;
+        case 3: launch_lp_tm<3, TAG>(a, prec, mtiles, s); break;
+        case 4: launch_lp_tm<4, TAG>(a, prec, mtiles, s); break;
+        case 5: launch_lp_tm<5, TAG>(a, prec, mtiles, s); break;
+        case 6: launch_lp_tm<6, TAG>(a, prec, mtiles, s); break;
+        case 7: launch_lp_tm<7, TAG>(a, prec, mtiles, s); break;
+        default: launch_lp_tm<8, TAG>(a, prec, mtiles, s); break;
     }
+}
+
+void launch_lp(const LadderLP& a, int prec, int tm, int mtiles, bool trial, hipStream_t s) {
+    if (trial) launch_lp_tag<1>(a, prec, tm, mtiles, s);
+    else launch_lp_tag<0>(a, prec, tm, mtiles, s);
     LAUNCHCHK();
 }
 
-template <int TM>
+template <int TM, int TAG>
 void launch_tm(const LadderArgs& a, int mtiles, hipStream_t s) {
-    hipLaunchKernelGGL((ladder_f64_kernel<TM>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
+    hipLaunchKernelGGL((ladder_f64_kernel<TM, TAG>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
 }
 
-void launch(const LadderArgs& a, int tm, int mtiles, hipStream_t s) {
+template <int TAG>
+void launch_tag(const LadderArgs& a, int tm, int mtiles, hipStream_t s) {
     switch (tm) {
-        case 1: launch_tm<1>(a, mtiles, s); break;
-        case 2: launch_tm<2>(a, mtiles, s); break;
-        case 3: launch_tm<3>(a, mtiles, s); break;
-        case 4: launch_tm<4>(a, mtiles, s); break;
-        case 5: launch_tm<5>(a, mtiles, s); break;
-        case 6: launch_tm<6>(a, mtiles, s); break;
-        case 7: launch_tm<7>(a, mtiles, s); break;
-        default: launch_tm<8>(a, mtiles, s); break;
+        case 1: launch_tm<1, TAG>(a, mtiles, s); break;
+        case 2: launch_tm<2, TAG>(a, mtiles, s); break;
+        case 3: launch_tm<3, TAG>(a, mtiles, s); break;
+        case 4: launch_tm<4, TAG>(a, mtiles, s); break;
+        case 5: launch_tm<5, TAG>(a, mtiles, s); break;
+        case 6: launch_tm<6, TAG>(a, mtiles, s); break;
+        case 7: launch_tm<7, TAG>(a, mtiles, s); break;
+        default: launch_tm<8, TAG>(a, mtiles, s); break;
     }
+}
+
+void launch(const LadderArgs& a, int tm, int mtiles, bool trial, hipStream_t s) {
+    if (trial) launch_tag<1>(a, tm, mtiles, s);
+    else launch_tag<0>(a, tm, mtiles, s);
     LAUNCHCHK();
 }
 }  // namespace
@@ -456,7 +469,7 @@ bool ladder_lp_supported(int prec, int M, int N, int K, const void* Z, long long
 
 void ladder_gemm_lp(int prec, int M, int N, int K, double alpha, const void* Z, long long ldz, const void* G,
                     long long ldg, double beta, double* C, long long ldc, int nchunk, double* partial,
-                    long long partial_elems, hipStream_t s) {
+                    long long partial_elems, hipStream_t s, bool trial) {
     if (g_dry || M <= 0 || N <= 0) return;
     int tm, mtiles;
     ladder_rows(M, tm, mtiles);
@@ -469,13 +482,13 @@ void ladder_gemm_lp(int prec, int M, int N, int K, double alpha, const void* Z, 
     a.nchunk = (K + a.Kc - 1) / a.Kc;
     a.ntn = (N + LBN - 1) / LBN;
     a.alpha = alpha; a.beta = beta;
-    launch_lp(a, prec, tm, mtiles, s);
+    launch_lp(a, prec, tm, mtiles, trial, s);
     if (a.nchunk > 1) splitk_reduce(partial, a.nchunk, M, N, alpha, beta, C, ldc, 1, s);
 }
 
 void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long ldz, const double* G, long long ldg,
                  double beta, double* C, long long ldc, int nchunk, double* partial, long long partial_elems,
-                 hipStream_t s) {
+                 hipStream_t s, bool trial) {
     if (g_dry || M <= 0 || N <= 0) return;
     int tm, mtiles;
     ladder_rows(M, tm, mtiles);
@@ -488,7 +501,7 @@ void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long l
     a.nchunk = (K + a.Kc - 1) / a.Kc;
     a.ntn = (N + LBN - 1) / LBN;
     a.alpha = alpha; a.beta = beta;
-    launch(a, tm, mtiles, s);
+    launch(a, tm, mtiles, trial, s);
     if (a.nchunk > 1) splitk_reduce(partial, a.nchunk, M, N, alpha, beta, C, ldc, 1, s);
 }
 
@@ -554,9 +567,10 @@ void store_cache(const std::string& key, int v) {
 static void ladder_run(int prec, int M, int N, int K, const void* Z, long long ldz, const void* G, long long ldg,
                        double* C, long long ldc, int nchunk, double* partial, long long pe, hipStream_t s) {
     if (prec == 0)
-        ladder_gemm(M, N, K, 1.0, (const double*)Z, ldz, (const double*)G, ldg, 0.0, C, ldc, nchunk, partial, pe, s);
+        ladder_gemm(M, N, K, 1.0, (const double*)Z, ldz, (const double*)G, ldg, 0.0, C, ldc, nchunk, partial, pe, s,
+                    true);
     else
-        ladder_gemm_lp(prec, M, N, K, 1.0, Z, ldz, G, ldg, 0.0, C, ldc, nchunk, partial, pe, s);
+        ladder_gemm_lp(prec, M, N, K, 1.0, Z, ldz, G, ldg, 0.0, C, ldc, nchunk, partial, pe, s, true);
 }
 
 int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long ldz, const void* G, long long ldg,

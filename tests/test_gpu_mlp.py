@@ -200,3 +200,17 @@ def test_learned_gain_on_held_out_seeds():
     print("total iterations jacobi %d learned %d; wall %.1f ms vs %.1f ms" % (tot_j, tot_l, 1e3 * tj_all,
                                                                               1e3 * tl_all))
     assert tot_l <= tot_j
+
+
+def test_bad_weights_fall_back_to_jacobi():
+    # u = -1 + noise: the learned step is nearly orthogonal to anything useful; the stall and
+    # growth checks must hand every root back to Jacobi and the solve must still converge
+    p, eo, ev, B = synth.preset("tiny-dense")
+    ref = np.linalg.eigvalsh(Problem(eo, ev, B).dense(3))[:3]
+    w = weights(9, head=20.0)
+    w[-1] = -1.0
+    ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, nroots=3)
+    ctx.set_preconditioner(devf(w))
+    wl, _, _, it, st = ctx.davidson(3, 1e-7)
+    assert st == 0
+    assert np.abs(wl - ref).max() < 1e-8
