@@ -63,7 +63,9 @@ typedef struct {
                              Ritz vectors with FP64 sigma (FP64 residual correction) down to conv;
                              orthogonalisation, Rayleigh-Ritz, residual norms and every
                              eigendecomposition stay FP64.  Default 0. */
-    int precond;          /* 0: Jacobi (diagonal) preconditioner; 1: learned (needs mlp_weights) */
+    int precond;          /* 0: Jacobi (diagonal) preconditioner; 1: learned (needs mlp_weights), in the
+                             ADC(3) solves (ADC(2) stays Jacobi); 2: Olsen, t = (D-theta)^-1 (r - eps x) with
+                             eps making t orthogonal to the Ritz vector x in the D-theta metric */
     const float* mlp_weights; /* device, adc3_mlp_nparams() floats (see adc3_mlp_train); NULL default */
     int sigma_graphs;     /* 1: each sigma pass shape is captured once into a HIP graph and replayed
                              (needs a non-null stream; on the null stream sigma runs eagerly); default 0 */

@@ -487,7 +487,8 @@ struct DavResult {
 
 static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int max_iter, int max_sub,
                                double* vec_out, hipStream_t s, int prec = 0, bool use_mlp = false,
-                               Recorder* rec = nullptr, const double* guess = nullptr, int nguess_in = 0) {
+                               Recorder* rec = nullptr, const double* guess = nullptr, int nguess_in = 0,
+                               bool olsen = false) {
     if (prec > c->prec) prec = c->prec;
     ProfScope prof(PROF_DAVIDSON, s, 0.0, 0.0);
     const long long N = c->N;
@@ -713,6 +714,14 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
                                  c->mlp_wb, Tn + (long long)j * N, mflag + j, s);
             } else {
                 k_precond(Tn + (long long)j * N, R + (long long)k * N, c->diag, th + k, 1, N, s);
+                if (olsen) {
+                    // Olsen: t = (D-theta)^-1 (r - eps x), eps = x.(D-theta)^-1 r / x.(D-theta)^-1 x
+                    double* bx = Vk;  // free until the next collapse
+                    k_precond(bx, Xr + (long long)k * N, c->diag, th + k, 1, N, s);
+                    k_dots(Xr + (long long)k * N, N, 1, Tn + (long long)j * N, N, 1, N, small, 1, part, s);
+                    k_dots(Xr + (long long)k * N, N, 1, bx, N, 1, N, small + 1, 1, part, s);
+                    k_olsen(Tn + (long long)j * N, bx, small, N, s);
+                }
             }
         }
         if (any_mlp) {
@@ -893,7 +902,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         c->mlp_w = op.mlp_weights;
         c->graphs = op.sigma_graphs != 0;
         DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
-                                    op.precond == 1);
+                                    op.precond == 1, nullptr, nullptr, 0, op.precond == 2);
         for (int k = 0; k < nroots; ++k) {
             auto& R = out.rep[k];
             R.omega = R.omega_uncorr = r.w[k];
@@ -915,7 +924,8 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     Ctx* c0 = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, 2, s, op.precision);
     c0->graphs = op.sigma_graphs != 0;
     double* Y2 = take(ws, (long long)nroots * c0->N);
-    DavResult r2 = davidson_impl(c0, ws, nroots, conv, op.max_iter, op.max_subspace, Y2, s, op.precision);
+    DavResult r2 = davidson_impl(c0, ws, nroots, conv, op.max_iter, op.max_subspace, Y2, s, op.precision, false,
+                                 nullptr, nullptr, 0, op.precond == 2);
     out.all_conv = out.all_conv && r2.converged;
     VLOG("canonical ADC(2): %d roots, %d iterations, lowest %.10f", nroots, r2.iters, r2.w[0]);
     const int sig0 = (int)c0->sigma_count;
@@ -973,7 +983,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s, op.precision);
             c2->graphs = op.sigma_graphs != 0;
             DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s, op.precision,
-                                         false, nullptr, carried, nroots);
+                                         false, nullptr, carried, nroots, op.precond == 2);
             k_dots(Y2k, Nk, nroots, ref, Nk, 1, Nk, ovl, 1, part, s);
             std::vector<double> hov(nroots);
             d2h(hov.data(), ovl, nroots * sizeof(double), s);
@@ -996,7 +1006,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             c3->mlp_w = op.mlp_weights;
             c3->graphs = op.sigma_graphs != 0;
             DavResult a3 = davidson_impl(c3, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
-                                         op.precond == 1, nullptr, Y2k, nroots);
+                                         op.precond == 1, nullptr, Y2k, nroots, op.precond == 2);
             R.omega_uncorr = a3.w[match];
             R.omega_lowp = a3.w_lowp.empty() ? a3.w[match] : a3.w_lowp[match];
             R.iters_lowp = a3.iters_lowp;
@@ -1253,7 +1263,7 @@ static adc3_opts resolve_opts(const adc3_opts* opts) {
     if (o.level != 2 && o.level != 3) fail(ADC3_EINVAL, "opts.level must be 2 or 3");
     if (o.max_iter < 1) fail(ADC3_EINVAL, "opts.max_iter must be >= 1");
     if (o.precision < 0 || o.precision > 2) fail(ADC3_EUNSUP, "opts.precision must be 0 (FP64), 1 (FP32) or 2 (BF16)");
-    if (o.precond != 0 && o.precond != 1) fail(ADC3_EUNSUP, "opts.precond must be 0 (Jacobi) or 1 (learned)");
+    if (o.precond < 0 || o.precond > 2) fail(ADC3_EUNSUP, "opts.precond must be 0 (Jacobi), 1 (learned) or 2 (Olsen)");
     if (o.precond == 1 && !o.mlp_weights) fail(ADC3_EINVAL, "opts.precond = 1 needs opts.mlp_weights");
     return o;
 }

@@ -361,6 +361,19 @@ void k_residual(double* R, const double* AX, const double* X, const double* th, 
     hipLaunchKernelGGL(residual_kernel, dim3(nblocks(t)), dim3(NT), 0, s, R, AX, X, th, nk, n);
     LAUNCHCHK();
 }
+// T -= (s[0]/s[1]) B  (s[1] == 0: T unchanged)
+__global__ void olsen_kernel(double* T, const double* B, const double* sc, long long n) {
+    const double d = sc[1];
+    const double e = d != 0.0 ? sc[0] / d : 0.0;
+    GRID_STRIDE(t, n) T[t] -= e * B[t];
+}
+
+void k_olsen(double* T, const double* B, const double* sc, long long n, hipStream_t s) {
+    if (g_dry || n <= 0) return;
+    hipLaunchKernelGGL(olsen_kernel, dim3(nblocks(n)), dim3(NT), 0, s, T, B, sc, n);
+    LAUNCHCHK();
+}
+
 void k_precond(double* T, const double* R, const double* D, const double* th, int nk, long long n, hipStream_t s) {
     if (g_dry) return;
     long long t = (long long)nk * n;

@@ -163,3 +163,16 @@ def test_solve_weak_correlation_full_size_fp64():
     assert [r["naux_kept"] for r in reps] == gold["naux_kept"]
     assert np.abs(roots - np.array(gold["roots"])).max() < 1e-8
     assert np.abs(np.array([r["omega_uncorr"] for r in reps]) - np.array(gold["omega_uncorr"])).max() < 1e-8
+
+
+def test_olsen_preconditioner_same_roots():
+    p, eo, ev, B = synth.preset("tiny-dense")
+    ref = np.linalg.eigvalsh(Problem(eo, ev, B).dense(3))[:3]
+    o = adc.adc3_default_opts()
+    o.precond = 2
+    roots, reps, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-8, opts=o)
+    assert st == 0 and np.abs(roots - ref).max() < 1e-8
+    eo, ev, B = synth.make_instance(3, 14, 40, 12, scale=0.05)
+    r0, _, _ = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 2, 1e-4, 1e-3, 1e-8)
+    r2, _, st2 = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 2, 1e-4, 1e-3, 1e-8, opts=o)
+    assert st2 == 0 and np.abs(r0 - r2).max() < 1e-9
