@@ -526,19 +526,20 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
         return res;
     }
     // Block orthonormalisation of the rows Tn[0..nn) against V[0..m) and within the block:
-    // unit rows, then (two CGS passes + Loewdin over the kept directions), repeated once when
-    // the block was strongly cancelled.  tmp holds nn rows.  Returns the number kept.
+    // unit rows, then (one CGS pass + Loewdin over the kept directions), repeated when the
+    // smallest kept Gram eigenvalue after the pass is below 1/2 (some direction lost more than
+    // ~30% of its length to V or to the block: the second pass restores orthogonality, as in
+    // the "twice is enough" rule).  tmp holds nn rows.  Returns the number kept.
     auto orthonormalise = [&](double* Tn, int nn, int m, double* tmp) -> int {
         k_dots(Tn, N, nn, Tn, N, nn, N, Gw, nn, part, s);
         k_rscale_rows(Tn, nn, N, Gw, nn, s);
         int acc = nn;
         bool again = true;
-        for (int round = 0; round < 2 && acc > 0 && again; ++round) {
-            if (m > 0)
-                for (int pass = 0; pass < 2; ++pass) {
-                    k_dots(V, N, m, Tn, N, acc, N, coef, acc, part, s);
-                    k_lincomb(Tn, N, acc, V, N, m, coef, acc, N, -1.0, 1.0, s);
-                }
+        for (int round = 0; round < 3 && acc > 0 && again; ++round) {
+            if (m > 0) {
+                k_dots(V, N, m, Tn, N, acc, N, coef, acc, part, s);
+                k_lincomb(Tn, N, acc, V, N, m, coef, acc, N, -1.0, 1.0, s);
+            }
             // Loewdin within the block: T' = (U w^-1/2)^T T over the kept directions
             k_dots(Tn, N, acc, Tn, N, acc, N, Gm, acc, part, s);
             k_symmetrize(Gm, acc, s);
@@ -1005,7 +1006,9 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s, op.precision);
             c3->mlp_w = op.mlp_weights;
             c3->graphs = op.sigma_graphs != 0;
-            DavResult a3 = davidson_impl(c3, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
+            // only roots 0..match of this basis are needed: the matched one and those below it
+            const int nr3 = std::min(nroots, match + 1);
+            DavResult a3 = davidson_impl(c3, ws, nr3, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
                                          op.precond == 1, nullptr, Y2k, nroots, op.precond == 2);
             R.omega_uncorr = a3.w[match];
             R.omega_lowp = a3.w_lowp.empty() ? a3.w[match] : a3.w_lowp[match];
