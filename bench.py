@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 mixed-precision solves")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner study")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="also solve the first N instances of the ragged batched workload (seeds 100..; 0 = skip)")
     ap.add_argument("--sigma-reps", type=int, default=10)
     ap.add_argument("--sigma-only", action="store_true",
                     help="profiling mode: only the isolated ADC(3) sigma builds plus a 2 GiB copy (counter calibration)")
@@ -114,6 +116,37 @@ def learned_study(adc, d, torch, np):
                          "wall_ratio": held["learned"]["wall_s"] / held["jacobi"]["wall_s"],
                          "max_abs_root_diff_Eh": dmax}}
     return {"scale": scale, "level": 3, "nroots": nroots, "conv": 1e-6, "shapes": out}
+
+
+def batched_study(adc, d, torch, np, n):
+    """The ragged batched workload: instances of seeds 100.. (nocc~U{5..30}, nvir~U{50..300},
+    naux = 3 nvir, literal scale), 8 roots, conv 1e-6, FP32 ladder, sigma graphs, 2 worker streams."""
+    import synth
+    inst = []
+    for s in range(100, 100 + n):
+        eo, ev, B = synth.batch_instance(s)
+        inst.append(dict(eps_occ=d(eo), eps_vir=d(ev), B=d(B), nroots=8, conv=1e-6))
+        del B
+    o = adc.adc3_default_opts()
+    o.precision = 1
+    o.sigma_graphs = 1
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        nbytes = adc.adc3_ea_solve_batched_workspace_bytes(inst, o, 2)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        roots, reps, sts, st = adc.adc3_ea_solve_batched(inst, o, 2, workspace=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    sig = sum(r["sigma_builds"] for rr in reps for r in rr)
+    sum_n = sum(int(x["eps_vir"].numel()) * (1 + int(x["eps_occ"].numel()) * int(x["eps_vir"].numel())) for x in inst)
+    del ws
+    torch.cuda.empty_cache()
+    return {"instances": n, "seeds": "100-%d" % (99 + n), "nroots": 8, "conv": 1e-6, "precision": "fp32 ladder",
+            "streams": 2, "sigma_graphs": True, "sum_N": sum_n, "workspace_GB": nbytes / 1e9, "time_s": dt,
+            "status": st, "statuses_ok": sum(1 for x in sts if x == 0), "sigma_builds": sig,
+            "sigma_builds_per_s": sig / dt, "iterations": [rr[0]["iters"] for rr in reps]}
 
 
 def cpu_baseline(shape, nvec):
@@ -280,6 +313,14 @@ def main():
             learned = learned_study(adc, d, torch, np)
         except Exception as e:
             learned = {"error": str(e)}
+    batched = None
+    if a.batched > 0:
+        del ws
+        torch.cuda.empty_cache()
+        try:
+            batched = batched_study(adc, d, torch, np, a.batched)
+        except Exception as e:
+            batched = {"error": str(e)}
     line = {
         "metric": "sigma-builds/s (whole SS-FNO-EA-ADC(3) solve) + time-to-5-roots, FP64, 1 GPU",
         "value": nsig / dt,
@@ -315,6 +356,8 @@ def main():
         "variant_weak_correlation": variant,
         "learned_preconditioner": learned,
     }
+    if batched is not None:
+        line["batched"] = batched
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline((p["nocc"], vk, xk), nroots)
     print(json.dumps(line), flush=True)
