@@ -46,11 +46,10 @@ void set_error(const std::string& msg) { g_msg = msg; }
 
 // ADC3_VERBOSE=1 in the environment prints one line per pipeline phase to stderr
 static int verbosity() {
-    static int v = -1;
-    if (v < 0) {
+    static const int v = [] {
         const char* e = std::getenv("ADC3_VERBOSE");
-        v = (e && e[0] >= '1' && e[0] <= '9') ? e[0] - '0' : 0;
-    }
+        return (e && e[0] >= '1' && e[0] <= '9') ? e[0] - '0' : 0;
+    }();
     return g_dry ? 0 : v;
 }
 static bool verbose() { return verbosity() >= 1; }

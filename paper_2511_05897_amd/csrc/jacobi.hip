@@ -228,12 +228,13 @@ void eig_small(double* A, int n, double* w, double* V, hipStream_t s) {
     if (n <= 0) return;
     if (n > SMALL_MAX) fail(-1, "eig_small: n too large");
     size_t lds = 2 * (size_t)n * (n + 1) * sizeof(double);
-    static bool attr_set = false;
-    if (!attr_set) {
+    // once per process (thread-safe initialisation; retried if it throws)
+    static const bool attr_set = [] {
         HIPCHK(hipFuncSetAttribute((const void*)jacobi_small_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)(2 * SMALL_MAX * (SMALL_MAX + 1) * sizeof(double))));
-        attr_set = true;
-    }
+        return true;
+    }();
+    (void)attr_set;
     hipLaunchKernelGGL(jacobi_small_kernel, dim3(1), dim3(SNT), lds, s, A, n, w, V);
     LAUNCHCHK();
 }

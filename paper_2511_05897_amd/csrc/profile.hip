@@ -2,6 +2,7 @@
 // on its stream at entry and exit; elapsed times are summed when queried.
 #include "internal.h"
 #include "../../include/adc3ea.h"
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -13,7 +14,7 @@ struct Rec {
     double flops, bytes;
 };
 std::mutex mu;
-bool enabled = false;
+std::atomic<bool> enabled{false};
 std::vector<Rec> recs;
 struct Acc {
     double ms = 0, flops = 0, bytes = 0;

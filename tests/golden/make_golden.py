@@ -1,11 +1,12 @@
 """Write the stored expected values of the full-size workloads.  Calls only oracle/ and synth.
 
-    python tests/golden/make_golden.py ssfno-o20v200x600 [scale]
+    python tests/golden/make_golden.py ssfno-o20v200x600 [scale] [conv]
 
 Writes tests/golden/<workload>[_s<scale>].json with the corrected roots, the
 uncorrected ADC(3) roots, the canonical and truncated ADC(2) roots and the kept
 virtual/auxiliary counts of the SS-FNO/NAF pipeline (Sec. "Computational
-Details", steps 2-4f), computed by the FP64 oracle with Davidson conv 1e-8.
+Details", steps 2-4f), computed by the FP64 oracle with Davidson conv 1e-8 (default) or
+the given conv (the literal scale, |omega| ~ 1e6 Eh, cannot reach 1e-8 in FP64).
 """
 import json
 import os
@@ -22,10 +23,11 @@ from oracle import ssfno  # noqa: E402
 def main():
     name = sys.argv[1]
     scale = float(sys.argv[2]) if len(sys.argv) > 2 else 1.0
+    conv = float(sys.argv[3]) if len(sys.argv) > 3 else 1e-8
     p, eo, ev, B = synth.preset(name, scale=scale)
     t0 = time.time()
-    r = ssfno.run(eo, ev, B, p["nroots"], p["fno_thresh"], p["naf_thresh"], 1e-8)
-    out = {"workload": name, "scale": scale, "oracle_conv": 1e-8, "seconds": time.time() - t0,
+    r = ssfno.run(eo, ev, B, p["nroots"], p["fno_thresh"], p["naf_thresh"], conv)
+    out = {"workload": name, "scale": scale, "oracle_conv": conv, "seconds": time.time() - t0,
            "roots": [float(x) for x in r["roots"]],
            "omega_uncorr": [float(x) for x in r["omega_uncorr"]],
            "omega_adc2_can": [float(x) for x in r.get("omega_adc2_can", [])],
