@@ -152,7 +152,6 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     c->diag = take(ws, c->N);
     c->Uz = take(ws, v * (long long)o * vv);
     if (level >= 3) {
-        c->G = take(ws, vv * vv);
         c->P1 = take(ws, oo * vv);
         c->P2 = take(ws, oo * vv);
     }
@@ -176,156 +175,170 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     c->gout = take(ws, NVMAX * c->N);
     c->sig_bytes = sigma_region_bytes(c);
     c->sig_base = ws.take<char>(c->sig_bytes);
-    // ---- everything below is temporary ----
-    const size_t mark = ws.mark();
-    GemmScratch gscr(ws, GEMM_SCRATCH);
-    double* Tt2 = take(ws, oo * vv);  // 2T - T~
-    k_comb_t(Tt2, T, oo, v, 2.0, -1.0, s);
-    // MP2 virtual density (per spin): sum_klc (2T^ce_kl - T^ec_kl) T^cd_kl
-    ein(ws, "klce,klcd->ed", 1.0, TV(Tt2, {o, o, v, v}), TV(T, {o, o, v, v}), 0.0, c->Dmp2, s);
-    // M11 through second order
-    double* P = take(ws, vv);
-    ein(ws, "klac,kblc->ab", 1.0, TV(Tt2, {o, o, v, v}), TV(c->ovov, {o, v, o, v}), 0.0, P, s);
-    k_fill(c->M11, vv, 0.0, s);
-    add_sym(c->M11, P, v, -1.0, s);
-    k_add_diag(c->M11, ev, v, s);
-    // coupling U_D[a][b][c][i], first order (ab|ic)
-    double* Ud = take(ws, vv * ov);
-    ein(ws, "Qab,Qic->abci", 1.0, TV(Bvv, {X, v, v}), TV(Bov, {X, o, v}), 0.0, Ud, s);
-
-    if (level >= 3) {
-        // ladder matrix G[(ab),(cd)] = (ac|bd) = sum_Q B^Q_ac B^Q_bd: batch over (a,b)
-        {
-            Gemm g;
-            g.M = v; g.N = v; g.K = X;
-            g.A = Bvv; g.sAm = 1; g.sAk = vv;  // A(c,Q) = Bvv[Q][a][c], batch offset a*v
-            g.B = Bvv; g.sBk = vv; g.sBn = 1;  // B(Q,d) = Bvv[Q][b][d], batch offset b*v
-            g.C = c->G; g.sCm = v; g.sCn = 1;  // C[a][b][c][d]
-            g.nb0 = v; g.bA0 = 0; g.bB0 = v; g.bC0 = vv;          // b0 = b
-            for (int a0 = 0; a0 < v; a0 += std::max(1, 65535 / v)) {
-                int na = std::min(v - a0, std::max(1, 65535 / v));
-                Gemm h = g;
-                h.A = Bvv + (long long)a0 * v;
-                h.C = c->G + (long long)a0 * v * vv;
-                h.nb1 = na; h.bA1 = v; h.bB1 = 0; h.bC1 = v * vv;  // b1 = a - a0
-                gemm(h, s);
-            }
-        }
-        double* oooo = take(ws, oo * oo);
-        ein(ws, "Qij,Qkl->ijkl", 1.0, TV(Boo, {X, o, o}), TV(Boo, {X, o, o}), 0.0, oooo, s);
-        double* ooov = take(ws, oo * ov);
-        ein(ws, "Qij,Qka->ijka", 1.0, TV(Boo, {X, o, o}), TV(Bov, {X, o, v}), 0.0, ooov, s);
-        // second-order doubles residual Y (alpha-beta block)
-        double* L = take(ws, oo * vv);
-        gemm_rm((int)oo, (int)vv, (int)vv, 1.0, T, vv, false, c->G, vv, false, 0.0, L, vv, s);
-        double* Y = take(ws, oo * vv);
-        k_copy(Y, L, oo * vv, s);
-        TV tT(T, {o, o, v, v}), tT2(Tt2, {o, o, v, v}), tovov(c->ovov, {o, v, o, v}), toovv(c->oovv, {o, o, v, v});
-        ein(ws, "klab,kilj->ijab", 1.0, tT, TV(oooo, {o, o, o, o}), 1.0, Y, s);
-        ein(ws, "ikac,jbkc->ijab", 1.0, tT2, tovov, 1.0, Y, s);
-        ein(ws, "ikac,kjbc->ijab", -1.0, tT, toovv, 1.0, Y, s);
-        ein(ws, "kjac,kibc->ijab", -1.0, tT, toovv, 1.0, Y, s);
-        ein(ws, "ikcb,kjac->ijab", -1.0, tT, toovv, 1.0, Y, s);
-        ein(ws, "jkbc,iakc->ijab", 1.0, tT2, tovov, 1.0, Y, s);
-        ein(ws, "jkbc,kiac->ijab", -1.0, tT, toovv, 1.0, Y, s);
-        double* U2 = Y;  // in place: U2 = Y / D
-        k_div_d2(U2, eo, ev, o, v, s);
-        // second-order singles u1[i][a]
-        double* W = take(ws, X * ov);
-        ein(ws, "Qkd,ikcd->Qic", 1.0, TV(Bov, {X, o, v}), tT2, 0.0, W, s);
-        double* u1 = take(ws, ov);
-        ein(ws, "Qac,Qic->ia", 1.0, TV(Bvv, {X, v, v}), TV(W, {X, o, v}), 0.0, u1, s);
-        ein(ws, "klac,kilc->ia", -1.0, tT2, TV(ooov, {o, o, o, v}), 1.0, u1, s);
-        k_div_d1(u1, eo, ev, o, v, s);
-        // second-order densities (per spin)
-        double* roo = take(ws, oo);
-        ein(ws, "mkcd,lkcd->ml", -1.0, tT2, tT, 0.0, roo, s);
-        const double* rvv = c->Dmp2;
-        // static self-energy  sum_pq <ap||bq> rho_pq
-        double* J = take(ws, X);
-        gemm_rm(X, 1, (int)oo, 1.0, Boo, oo, false, roo, 1, false, 0.0, J, 1, s);
-        gemm_rm(X, 1, (int)vv, 1.0, Bvv, vv, false, rvv, 1, false, 1.0, J, 1, s);
-        gemm_rm(X, 1, (int)ov, 2.0, Bov, ov, false, u1, 1, false, 1.0, J, 1, s);
-        gemm_rm((int)vv, 1, X, 2.0, Bvv, vv, true, J, 1, false, 1.0, c->M11, 1, s);
-        double* Z1 = take(ws, X * ov);
-        ein(ws, "ml,Qlb->Qmb", 1.0, TV(roo, {o, o}), TV(Bov, {X, o, v}), 0.0, Z1, s);
-        ein(ws, "Qma,Qmb->ab", -1.0, TV(Bov, {X, o, v}), TV(Z1, {X, o, v}), 1.0, c->M11, s);
-        double* Z2 = take(ws, X * vv);
-        ein(ws, "Qad,ed->Qae", 1.0, TV(Bvv, {X, v, v}), TV(rvv, {v, v}), 0.0, Z2, s);
-        ein(ws, "Qae,Qeb->ab", -1.0, TV(Z2, {X, v, v}), TV(Bvv, {X, v, v}), 1.0, c->M11, s);
-        double* Z3 = Z1;
-        ein(ws, "Qbc,kc->Qkb", 1.0, TV(Bvv, {X, v, v}), TV(u1, {o, v}), 0.0, Z3, s);
-        ein(ws, "Qka,Qkb->ab", -1.0, TV(Bov, {X, o, v}), TV(Z3, {X, o, v}), 1.0, c->M11, s);
-        ein(ws, "Qkb,Qka->ab", -1.0, TV(Bov, {X, o, v}), TV(Z3, {X, o, v}), 1.0, c->M11, s);
-        // second-order form with second-order amplitudes
-        double* U2t2 = take(ws, oo * vv);
-        k_comb_t(U2t2, U2, oo, v, 2.0, -1.0, s);
-        ein(ws, "klac,kblc->ab", 1.0, TV(U2t2, {o, o, v, v}), tovov, 0.0, P, s);
+    // ---- temporaries below; G is taken only after the U_D phase has released its own, so the
+    // setup peak is G plus the larger phase rather than G plus both ----
+    const size_t mark0 = ws.mark();
+    {
+        // phase A: D^MP2, M11 through second order, U_D (first and second order) -> U_z
+        GemmScratch gscr(ws, GEMM_SCRATCH);
+        double* Tt2 = take(ws, oo * vv);  // 2T - T~
+        k_comb_t(Tt2, T, oo, v, 2.0, -1.0, s);
+        // MP2 virtual density (per spin): sum_klc (2T^ce_kl - T^ec_kl) T^cd_kl
+        ein(ws, "klce,klcd->ed", 1.0, TV(Tt2, {o, o, v, v}), TV(T, {o, o, v, v}), 0.0, c->Dmp2, s);
+        // M11 through second order
+        double* P = take(ws, vv);
+        ein(ws, "klac,kblc->ab", 1.0, TV(Tt2, {o, o, v, v}), TV(c->ovov, {o, v, o, v}), 0.0, P, s);
+        k_fill(c->M11, vv, 0.0, s);
         add_sym(c->M11, P, v, -1.0, s);
-        // ladder part: - sym( sum_ekl T^ae_kl (2 L^be_kl - L^eb_kl) )
-        double* Lt2 = U2t2;
-        k_comb_t(Lt2, L, oo, v, 2.0, -1.0, s);
-        ein(ws, "klae,klbe->ab", 1.0, tT, TV(Lt2, {o, o, v, v}), 0.0, P, s);
-        add_sym(c->M11, P, v, -1.0, s);
-        // ring part
-        double* g1 = take(ws, oo * vv);   // [d][l][b][m] = (db|ml) - (dl|mb)
-        double* g2 = take(ws, oo * vv);   // [d][l][b][m] = (dl|mb)
-        double* g3 = take(ws, oo * vv);   // [d][l][b][m] = (db|ml)
-        {
-            int d_oovv[4] = {o, o, v, v}, p_oovv[4] = {2, 1, 3, 0};  // oovv[m][l][d][b] -> [d][l][b][m]
-            int d_ovov[4] = {o, v, o, v}, p_ovov[4] = {1, 0, 3, 2};  // ovov[l][d][m][b] -> [d][l][b][m]
-            k_permute4(g3, c->oovv, d_oovv, p_oovv, 1.0, 0.0, s);
-            k_permute4(g2, c->ovov, d_ovov, p_ovov, 1.0, 0.0, s);
-            k_copy(g1, g3, oo * vv, s);
-            k_axpby(g1, g2, oo * vv, -1.0, 1.0, s);
-        }
-        double* TmT = Lt2;  // T - T~
-        k_comb_t(TmT, T, oo, v, 1.0, -1.0, s);
-        TV tg1(g1, {v, o, v, o}), tg2(g2, {v, o, v, o}), tg3(g3, {v, o, v, o}), tTm(TmT, {o, o, v, v});
-        double* RA = take(ws, oo * vv);
-        double* RB = take(ws, oo * vv);
-        double* RC = take(ws, oo * vv);
-        ein(ws, "klcd,dlbm->ckbm", 1.0, tTm, tg1, 0.0, RA, s);
-        ein(ws, "klcd,dlbm->ckbm", -1.0, tT, tg2, 1.0, RA, s);
-        ein(ws, "klcd,dlbm->ckbm", 1.0, tT, tg1, 0.0, RB, s);
-        ein(ws, "klcd,dlbm->ckbm", -1.0, tTm, tg2, 1.0, RB, s);
-        ein(ws, "kldc,dlbm->ckbm", -1.0, tT, tg3, 0.0, RC, s);
-        TV tRA(RA, {v, o, v, o}), tRB(RB, {v, o, v, o}), tRC(RC, {v, o, v, o});
-        ein(ws, "kmac,ckbm->ab", 1.0, tTm, tRA, 0.0, P, s);
-        ein(ws, "mkac,ckbm->ab", -1.0, tT, tRB, 1.0, P, s);
-        ein(ws, "kmac,ckbm->ab", 1.0, tT, tRC, 1.0, P, s);
-        add_sym(c->M11, P, v, -1.0, s);
-        // coupling, second order
-        ein(ws, "klbc,ilka->abci", 1.0, tT, TV(ooov, {o, o, o, v}), 1.0, Ud, s);
-        double* ovvv = take(ws, ov * vv);
-        ein(ws, "Qka,Qcd->kacd", 1.0, TV(Bov, {X, o, v}), TV(Bvv, {X, v, v}), 0.0, ovvv, s);
-        TV tovvv(ovvv, {o, v, v, v});
-        ein(ws, "kibd,kacd->abci", -1.0, tT, tovvv, 1.0, Ud, s);
-        ein(ws, "ikcd,kdab->abci", 1.0, tT2, tovvv, 1.0, Ud, s);
-        ein(ws, "ikcd,kabd->abci", -1.0, tT, tovvv, 1.0, Ud, s);
-        // permuted integrals for the particle-hole sigma terms
-        {
+        k_add_diag(c->M11, ev, v, s);
+        // coupling U_D[a][b][c][i], first order (ab|ic)
+        double* Ud = take(ws, vv * ov);
+        ein(ws, "Qab,Qic->abci", 1.0, TV(Bvv, {X, v, v}), TV(Bov, {X, o, v}), 0.0, Ud, s);
+        if (level >= 3) {
+            TV tT(T, {o, o, v, v}), tT2(Tt2, {o, o, v, v});
+            double* ooov = take(ws, oo * ov);
+            ein(ws, "Qij,Qka->ijka", 1.0, TV(Boo, {X, o, o}), TV(Bov, {X, o, v}), 0.0, ooov, s);
+            // coupling, second order
+            ein(ws, "klbc,ilka->abci", 1.0, tT, TV(ooov, {o, o, o, v}), 1.0, Ud, s);
+            double* ovvv = take(ws, ov * vv);
+            ein(ws, "Qka,Qcd->kacd", 1.0, TV(Bov, {X, o, v}), TV(Bvv, {X, v, v}), 0.0, ovvv, s);
+            TV tovvv(ovvv, {o, v, v, v});
+            ein(ws, "kibd,kacd->abci", -1.0, tT, tovvv, 1.0, Ud, s);
+            ein(ws, "ikcd,kdab->abci", 1.0, tT2, tovvv, 1.0, Ud, s);
+            ein(ws, "ikcd,kabd->abci", -1.0, tT, tovvv, 1.0, Ud, s);
+            // permuted integrals for the particle-hole sigma terms
             int d_oovv[4] = {o, o, v, v};
             int p1[4] = {0, 2, 1, 3};  // [i][j][b][d] -> [i][b][j][d]
             k_permute4(c->P1, c->oovv, d_oovv, p1, 1.0, 0.0, s);
             k_permute4(c->P2, c->oovv, d_oovv, p1, 1.0, 0.0, s);  // same layout, read as [i][a][j][d]
         }
-    }
-    // U_z[a][i][b][c] = S + sqrt3 A over (b,c) of U_D[a][b][c][i]
-    {
+        // U_z[a][i][b][c] = S + sqrt3 A over (b,c) of U_D[a][b][c][i]
         double* Up = take(ws, vv * ov);
-        int d[4] = {v, v, v, o}, p[4] = {0, 3, 1, 2};
-        k_permute4(Up, Ud, d, p, 1.0, 0.0, s);
+        int d[4] = {v, v, v, o}, pm[4] = {0, 3, 1, 2};
+        k_permute4(Up, Ud, d, pm, 1.0, 0.0, s);
         k_fill(c->Uz, vv * ov, 0.0, s);
         k_d_to_z_add(c->Uz, Up, (long long)v * o, v, s);
+    }
+    ws.release(mark0);
+    if (level >= 3) {
+        c->G = take(ws, vv * vv);  // kept with the context
+        const size_t mark1 = ws.mark();
+        {
+            // phase B: G, then everything of M11 through third order that needs it
+            GemmScratch gscr(ws, GEMM_SCRATCH);
+            double* Tt2 = take(ws, oo * vv);
+            k_comb_t(Tt2, T, oo, v, 2.0, -1.0, s);
+            double* P = take(ws, vv);
+            // ladder matrix G[(ab),(cd)] = (ac|bd) = sum_Q B^Q_ac B^Q_bd: batch over (a,b)
+            {
+                Gemm g;
+                g.M = v; g.N = v; g.K = X;
+                g.A = Bvv; g.sAm = 1; g.sAk = vv;  // A(c,Q) = Bvv[Q][a][c], batch offset a*v
+                g.B = Bvv; g.sBk = vv; g.sBn = 1;  // B(Q,d) = Bvv[Q][b][d], batch offset b*v
+                g.C = c->G; g.sCm = v; g.sCn = 1;  // C[a][b][c][d]
+                g.nb0 = v; g.bA0 = 0; g.bB0 = v; g.bC0 = vv;          // b0 = b
+                for (int a0 = 0; a0 < v; a0 += std::max(1, 65535 / v)) {
+                    int na = std::min(v - a0, std::max(1, 65535 / v));
+                    Gemm h = g;
+                    h.A = Bvv + (long long)a0 * v;
+                    h.C = c->G + (long long)a0 * v * vv;
+                    h.nb1 = na; h.bA1 = v; h.bB1 = 0; h.bC1 = v * vv;  // b1 = a - a0
+                    gemm(h, s);
+                }
+            }
+            double* oooo = take(ws, oo * oo);
+            ein(ws, "Qij,Qkl->ijkl", 1.0, TV(Boo, {X, o, o}), TV(Boo, {X, o, o}), 0.0, oooo, s);
+            double* ooov = take(ws, oo * ov);
+            ein(ws, "Qij,Qka->ijka", 1.0, TV(Boo, {X, o, o}), TV(Bov, {X, o, v}), 0.0, ooov, s);
+            // second-order doubles residual Y (alpha-beta block)
+            double* L = take(ws, oo * vv);
+            gemm_rm((int)oo, (int)vv, (int)vv, 1.0, T, vv, false, c->G, vv, false, 0.0, L, vv, s);
+            double* Y = take(ws, oo * vv);
+            k_copy(Y, L, oo * vv, s);
+            TV tT(T, {o, o, v, v}), tT2(Tt2, {o, o, v, v}), tovov(c->ovov, {o, v, o, v}), toovv(c->oovv, {o, o, v, v});
+            ein(ws, "klab,kilj->ijab", 1.0, tT, TV(oooo, {o, o, o, o}), 1.0, Y, s);
+            ein(ws, "ikac,jbkc->ijab", 1.0, tT2, tovov, 1.0, Y, s);
+            ein(ws, "ikac,kjbc->ijab", -1.0, tT, toovv, 1.0, Y, s);
+            ein(ws, "kjac,kibc->ijab", -1.0, tT, toovv, 1.0, Y, s);
+            ein(ws, "ikcb,kjac->ijab", -1.0, tT, toovv, 1.0, Y, s);
+            ein(ws, "jkbc,iakc->ijab", 1.0, tT2, tovov, 1.0, Y, s);
+            ein(ws, "jkbc,kiac->ijab", -1.0, tT, toovv, 1.0, Y, s);
+            double* U2 = Y;  // in place: U2 = Y / D
+            k_div_d2(U2, eo, ev, o, v, s);
+            // second-order singles u1[i][a]
+            double* W = take(ws, X * ov);
+            ein(ws, "Qkd,ikcd->Qic", 1.0, TV(Bov, {X, o, v}), tT2, 0.0, W, s);
+            double* u1 = take(ws, ov);
+            ein(ws, "Qac,Qic->ia", 1.0, TV(Bvv, {X, v, v}), TV(W, {X, o, v}), 0.0, u1, s);
+            ein(ws, "klac,kilc->ia", -1.0, tT2, TV(ooov, {o, o, o, v}), 1.0, u1, s);
+            k_div_d1(u1, eo, ev, o, v, s);
+            // second-order densities (per spin)
+            double* roo = take(ws, oo);
+            ein(ws, "mkcd,lkcd->ml", -1.0, tT2, tT, 0.0, roo, s);
+            const double* rvv = c->Dmp2;
+            // static self-energy  sum_pq <ap||bq> rho_pq
+            double* J = take(ws, X);
+            gemm_rm(X, 1, (int)oo, 1.0, Boo, oo, false, roo, 1, false, 0.0, J, 1, s);
+            gemm_rm(X, 1, (int)vv, 1.0, Bvv, vv, false, rvv, 1, false, 1.0, J, 1, s);
+            gemm_rm(X, 1, (int)ov, 2.0, Bov, ov, false, u1, 1, false, 1.0, J, 1, s);
+            gemm_rm((int)vv, 1, X, 2.0, Bvv, vv, true, J, 1, false, 1.0, c->M11, 1, s);
+            double* Z1 = take(ws, X * ov);
+            ein(ws, "ml,Qlb->Qmb", 1.0, TV(roo, {o, o}), TV(Bov, {X, o, v}), 0.0, Z1, s);
+            ein(ws, "Qma,Qmb->ab", -1.0, TV(Bov, {X, o, v}), TV(Z1, {X, o, v}), 1.0, c->M11, s);
+            double* Z2 = take(ws, X * vv);
+            ein(ws, "Qad,ed->Qae", 1.0, TV(Bvv, {X, v, v}), TV(rvv, {v, v}), 0.0, Z2, s);
+            ein(ws, "Qae,Qeb->ab", -1.0, TV(Z2, {X, v, v}), TV(Bvv, {X, v, v}), 1.0, c->M11, s);
+            double* Z3 = Z1;
+            ein(ws, "Qbc,kc->Qkb", 1.0, TV(Bvv, {X, v, v}), TV(u1, {o, v}), 0.0, Z3, s);
+            ein(ws, "Qka,Qkb->ab", -1.0, TV(Bov, {X, o, v}), TV(Z3, {X, o, v}), 1.0, c->M11, s);
+            ein(ws, "Qkb,Qka->ab", -1.0, TV(Bov, {X, o, v}), TV(Z3, {X, o, v}), 1.0, c->M11, s);
+            // second-order form with second-order amplitudes
+            double* U2t2 = take(ws, oo * vv);
+            k_comb_t(U2t2, U2, oo, v, 2.0, -1.0, s);
+            ein(ws, "klac,kblc->ab", 1.0, TV(U2t2, {o, o, v, v}), tovov, 0.0, P, s);
+            add_sym(c->M11, P, v, -1.0, s);
+            // ladder part: - sym( sum_ekl T^ae_kl (2 L^be_kl - L^eb_kl) )
+            double* Lt2 = U2t2;
+            k_comb_t(Lt2, L, oo, v, 2.0, -1.0, s);
+            ein(ws, "klae,klbe->ab", 1.0, tT, TV(Lt2, {o, o, v, v}), 0.0, P, s);
+            add_sym(c->M11, P, v, -1.0, s);
+            // ring part
+            double* g1 = take(ws, oo * vv);   // [d][l][b][m] = (db|ml) - (dl|mb)
+            double* g2 = take(ws, oo * vv);   // [d][l][b][m] = (dl|mb)
+            double* g3 = take(ws, oo * vv);   // [d][l][b][m] = (db|ml)
+            {
+                int d_oovv[4] = {o, o, v, v}, p_oovv[4] = {2, 1, 3, 0};  // oovv[m][l][d][b] -> [d][l][b][m]
+                int d_ovov[4] = {o, v, o, v}, p_ovov[4] = {1, 0, 3, 2};  // ovov[l][d][m][b] -> [d][l][b][m]
+                k_permute4(g3, c->oovv, d_oovv, p_oovv, 1.0, 0.0, s);
+                k_permute4(g2, c->ovov, d_ovov, p_ovov, 1.0, 0.0, s);
+                k_copy(g1, g3, oo * vv, s);
+                k_axpby(g1, g2, oo * vv, -1.0, 1.0, s);
+            }
+            double* TmT = Lt2;  // T - T~
+            k_comb_t(TmT, T, oo, v, 1.0, -1.0, s);
+            TV tg1(g1, {v, o, v, o}), tg2(g2, {v, o, v, o}), tg3(g3, {v, o, v, o}), tTm(TmT, {o, o, v, v});
+            double* RA = take(ws, oo * vv);
+            double* RB = take(ws, oo * vv);
+            double* RC = take(ws, oo * vv);
+            ein(ws, "klcd,dlbm->ckbm", 1.0, tTm, tg1, 0.0, RA, s);
+            ein(ws, "klcd,dlbm->ckbm", -1.0, tT, tg2, 1.0, RA, s);
+            ein(ws, "klcd,dlbm->ckbm", 1.0, tT, tg1, 0.0, RB, s);
+            ein(ws, "klcd,dlbm->ckbm", -1.0, tTm, tg2, 1.0, RB, s);
+            ein(ws, "kldc,dlbm->ckbm", -1.0, tT, tg3, 0.0, RC, s);
+            TV tRA(RA, {v, o, v, o}), tRB(RB, {v, o, v, o}), tRC(RC, {v, o, v, o});
+            ein(ws, "kmac,ckbm->ab", 1.0, tTm, tRA, 0.0, P, s);
+            ein(ws, "mkac,ckbm->ab", -1.0, tT, tRB, 1.0, P, s);
+            ein(ws, "kmac,ckbm->ab", 1.0, tT, tRC, 1.0, P, s);
+            add_sym(c->M11, P, v, -1.0, s);
+        }
+        ws.release(mark1);
     }
     k_diag_adc(c->diag, c->M11, eo, ev, Bvv, c->oovv, c->ovov, o, v, X, level, s);
     if (prec > 0) {
         k_to_lowp(c->Uz32, c->Uz, v * (long long)o * vv, 1, s);
         if (level >= 3) k_to_lowp(c->Glo, c->G, vv * vv, prec, s);
     }
-    ws.release(mark);
-    c->ws = ws;  // snapshot (base/cap/used) for sigma temporaries
+    c->ws = ws;  // snapshot (base/cap/used) for later temporaries
     return c;
 }
 
