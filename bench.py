@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 mixed-precision solves")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner study")
+    ap.add_argument("--learned-full", action="store_true",
+                    help="also compare the learned preconditioner with Jacobi at o=30 v=400 X=1200 (251 GB)")
     ap.add_argument("--batched", type=int, default=0,
                     help="also solve the first N instances of the ragged batched workload (seeds 100..; 0 = skip)")
     ap.add_argument("--sigma-reps", type=int, default=10)
@@ -147,6 +149,57 @@ def batched_study(adc, d, torch, np, n):
             "streams": 2, "sigma_graphs": True, "sum_N": sum_n, "workspace_GB": nbytes / 1e9, "time_s": dt,
             "status": st, "statuses_ok": sum(1 for x in sts if x == 0), "sigma_builds": sig,
             "sigma_builds_per_s": sig / dt, "iterations": [rr[0]["iters"] for rr in reps]}
+
+
+def learned_full_size(adc, d, torch, np, scale):
+    """ADC(3) Davidson at o=30, v=400, X=1200 (seed 240, 5 roots, conv 1e-6): Jacobi, then the
+    learned preconditioner trained on seeds 200-239 of o=6, v=40, X=120 at the same scale."""
+    import synth
+    Fs, As, Ds = [], [], []
+    t0 = time.perf_counter()
+    for seed in range(200, 240):
+        eo, ev, B = synth.make_instance(6, 40, 120, seed, scale=scale)
+        ctx = adc.Context(d(eo), d(ev), d(B), 3, nroots=5)
+        F, A, D, _ = ctx.mlp_collect(5, 1e-6, 256, 50, seed)
+        Fs.append(F)
+        As.append(A)
+        Ds.append(D)
+        ctx.close()
+    w = torch.as_tensor(synth.mlp_init(1), device="cuda")
+    losses = adc.adc3_mlp_train(w, torch.cat(Fs), torch.cat(As), torch.cat(Ds), epochs=60, batch_groups=32,
+                                lr=2e-3, seed=7)
+    t_train = time.perf_counter() - t0
+    del Fs, As, Ds
+    print("learned-full: trained in %.1f s" % t_train, file=sys.stderr, flush=True)
+    p, eo, ev, B = synth.preset("learned-o30v400x1200", scale=scale)
+    tB = d(B)
+    del B
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx = adc.Context(d(eo), d(ev), tB, 3, nroots=5)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    print("learned-full: context set up in %.1f s" % t_setup, file=sys.stderr, flush=True)
+    out = {"shape": [30, 400, 1200], "seed": p["seed"], "scale": scale, "nroots": 5, "conv": 1e-6,
+           "N": int(ctx.N), "setup_s": t_setup, "train_s": t_train,
+           "loss_first_last": [float(losses[0]), float(losses[-1])]}
+    roots = {}
+    # the first solve also settles the ladder tuner for every row count the solve meets
+    for tag, weights in (("warm-up", None), ("learned", w), ("jacobi", None)):
+        ctx.set_preconditioner(weights)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        wr, _, rn, it, st = ctx.davidson(5, 1e-6)
+        torch.cuda.synchronize()
+        out[tag] = {"iterations": it, "wall_s": time.perf_counter() - t1, "status": st,
+                    "roots": [float(x) for x in wr]}
+        roots[tag] = wr
+        print("learned-full: %s %d iterations, %.1f s" % (tag, it, out[tag]["wall_s"]), file=sys.stderr, flush=True)
+    out["max_abs_root_diff_Eh"] = float(np.abs(roots["learned"] - roots["jacobi"]).max())
+    ctx.close()
+    del ctx, tB
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(shape, nvec):
@@ -313,9 +366,18 @@ def main():
             learned = learned_study(adc, d, torch, np)
         except Exception as e:
             learned = {"error": str(e)}
+    learned_full = None
+    if a.learned_full:
+        del ws
+        ws = None
+        torch.cuda.empty_cache()
+        try:
+            learned_full = learned_full_size(adc, d, torch, np, 0.3)
+        except Exception as e:
+            learned_full = {"error": str(e)}
     batched = None
     if a.batched > 0:
-        del ws
+        ws = None
         torch.cuda.empty_cache()
         try:
             batched = batched_study(adc, d, torch, np, a.batched)
@@ -356,6 +418,8 @@ def main():
         "variant_weak_correlation": variant,
         "learned_preconditioner": learned,
     }
+    if learned_full is not None:
+        line["learned_full_size"] = learned_full
     if batched is not None:
         line["batched"] = batched
     if not a.no_cpu_baseline:
