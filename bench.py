@@ -278,6 +278,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lad_ms, lad_n, lad_f, lad_b = adc.adc3_profile_query(adc.PROF_LADDER)
+    lad_bound = adc.adc3_profile_query_bound(adc.PROF_LADDER)
     sig_ms, sig_n, _, _ = adc.adc3_profile_query(adc.PROF_SIGMA)
     setup_ms, setup_n, _, _ = adc.adc3_profile_query(adc.PROF_SETUP)
     dav_ms, _, _, _ = adc.adc3_profile_query(adc.PROF_DAVIDSON)
@@ -324,6 +325,7 @@ def main():
                 torch.cuda.synchronize()
                 mdt = time.perf_counter() - m0
                 lms, ln, lf, lb = adc.adc3_profile_query(adc.PROF_LADDER_LP)
+                lbound = adc.adc3_profile_query_bound(adc.PROF_LADDER_LP)
                 adc.adc3_profile_enable(False)
                 del wsm
                 ach = lf / (lms * 1e-3) / 1e12 if lms > 0 else 0.0
@@ -332,7 +334,8 @@ def main():
                               "root_diff_vs_fp64_Eh": [float(x) for x in (rm - roots)],
                               "lowp_phase_root_error_Eh": [float(r["omega_lowp"] - r["omega_uncorr"]) for r in repm],
                               "ladder": {"launches": ln, "avg_launch_ms": lms / max(ln, 1),
-                                         "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak}}
+                                         "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak,
+                                         "bound_time_frac": lbound / lms if lms > 0 else None}}
             except Exception as e:
                 mixed[tag] = {"error": str(e)}
 
@@ -408,6 +411,7 @@ def main():
                      "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
                      "traffic_detail": traffic, "kernel_source_hash": src_hash,
+                     "bound_time_frac": lad_bound / lad_ms if lad_ms > 0 else None,
                      "launches": lad_n, "avg_launch_ms": lad_ms / max(lad_n, 1),
                      "flops_per_launch": lad_f / max(lad_n, 1)},
         "phases_ms_per_step": {"setup": setup_ms / a.steps, "davidson": dav_ms / a.steps,

@@ -267,9 +267,13 @@ int adc3_mlp_train(float* weights_dev, const double* feat_dev, const double* a0_
  * eigensolve, 5 = each reduced-precision sigma-ladder launch.  adc3_profile_enable(1) resets and starts; (0) stops.
  * adc3_profile_query synchronises the recorded events and returns the summed
  * milliseconds, the number of timed launches, and the summed flops and bytes.
+ * adc3_profile_query_bound returns, for the ladder ids (0, 5), the summed roofline time of
+ * the launches, each max(flops / matrix-core peak of its precision, bytes / 8 TB/s) with
+ * MI355X's published peaks (FP64 78.6, FP32 157.3, BF16 2500 TFLOP/s); 0 for other ids.
  * ------------------------------------------------------------------------- */
 void adc3_profile_enable(int on);
 int adc3_profile_query(int kernel, double* total_ms, long long* count, double* flops, double* bytes);
+int adc3_profile_query_bound(int kernel, double* bound_ms);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,7 @@ EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_byte
            "adc3_ea_intermediate", "adc3_profile_enable", "adc3_profile_query", "adc3_mlp_nparams",
            "adc3_ea_set_preconditioner", "adc3_mlp_collect", "adc3_mlp_workspace_bytes", "adc3_mlp_loss_grad",
            "adc3_mlp_forward", "adc3_mlp_train", "adc3_ea_precondition", "adc3_ea_solve_batched_workspace_bytes",
-           "adc3_ea_solve_batched", "adc3_ea_set_sigma_graphs"]
+           "adc3_ea_solve_batched", "adc3_ea_set_sigma_graphs", "adc3_profile_query_bound"]
 
 
 class adc3_opts(ctypes.Structure):
@@ -96,6 +96,8 @@ def load():
     lib.adc3_profile_enable.restype = None
     lib.adc3_profile_query.argtypes = [I, ctypes.POINTER(D), ctypes.POINTER(LL), ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.adc3_profile_query.restype = I
+    lib.adc3_profile_query_bound.argtypes = [I, ctypes.POINTER(D)]
+    lib.adc3_profile_query_bound.restype = I
     U64 = ctypes.c_ulonglong
     lib.adc3_mlp_nparams.argtypes = []
     lib.adc3_mlp_nparams.restype = I
@@ -395,3 +397,10 @@ def adc3_profile_query(kernel):
     ms, n, f, b = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
     _check(load().adc3_profile_query(kernel, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(f), ctypes.byref(b)))
     return ms.value, n.value, f.value, b.value
+
+
+def adc3_profile_query_bound(kernel):
+    """Summed roofline time (ms) of the timed launches of a ladder id."""
+    b = ctypes.c_double()
+    _check(load().adc3_profile_query_bound(kernel, ctypes.byref(b)))
+    return b.value

@@ -80,6 +80,8 @@ static void h2d(void* dst, const void* src, size_t bytes, hipStream_t s) {
 // context
 // ---------------------------------------------------------------------------
 constexpr int NVMAX = 16;  // vectors per sigma pass
+// MI355X published peaks (dense matrix-core rates; HBM3E bandwidth), for roofline bounds
+constexpr double PEAK_FP64_MFMA = 78.6e12, PEAK_FP32_MFMA = 157.3e12, PEAK_BF16_MFMA = 2.5e15, PEAK_HBM = 8.0e12;
 
 struct Ctx {
     int o = 0, v = 0, X = 0, level = 2;
@@ -375,8 +377,10 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
             k_copy2d(zb, ovv, rr + v, N, nv, ovv, 1.0, 0.0, s);
             // ladder: sum_cd (ac|bd) z_cd  (G symmetric)
             if (prec > 0) {
-                ProfScope p(PROF_LADDER_LP, s, 2.0 * nv * o * (double)vv * vv,
-                            (prec == 1 ? 4.0 : 2.0) * (double)vv * vv + 16.0 * nv * o * vv);
+                const double fl = 2.0 * nv * o * (double)vv * vv;
+                const double by = (prec == 1 ? 4.0 : 2.0) * (double)vv * vv + 16.0 * nv * o * vv;
+                ProfScope p(PROF_LADDER_LP, s, fl, by,
+                            1e3 * std::max(fl / (prec == 1 ? PEAK_FP32_MFMA : PEAK_BF16_MFMA), by / PEAK_HBM));
                 const int M = nv * o;
                 k_to_lowp(c->zlo, zb, (long long)M * vv, prec, s);
                 if (ladder_lp_supported(prec, M, (int)vv, (int)vv, c->zlo, vv, c->Glo, vv, c->sb, vv)) {
@@ -394,8 +398,9 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                     gemm_lp(g, prec, s, 1);
                 }
             } else {
-                ProfScope p(PROF_LADDER, s, 2.0 * nv * o * (double)vv * vv,
-                            8.0 * ((double)vv * vv + 2.0 * nv * o * vv));
+                const double fl = 2.0 * nv * o * (double)vv * vv;
+                const double by = 8.0 * ((double)vv * vv + 2.0 * nv * o * vv);
+                ProfScope p(PROF_LADDER, s, fl, by, 1e3 * std::max(fl / PEAK_FP64_MFMA, by / PEAK_HBM));
                 const int M = nv * o;
                 if (ladder_supported(M, (int)vv, (int)vv, zb, vv, c->G, vv, c->sb, vv)) {
                     const long long pe = 3 * NVMAX * (long long)o * vv;

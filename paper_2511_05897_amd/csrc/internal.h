@@ -122,9 +122,9 @@ enum ProfKernel { PROF_LADDER = 0, PROF_SIGMA = 1, PROF_SETUP = 2, PROF_DAVIDSON
 struct ProfScope {
     int k;
     hipStream_t s;
-    double flops, bytes;
+    double flops, bytes, bound_ms;  // bound_ms: the launch's roofline time, max(flops/peak, bytes/bandwidth)
     void* ev0 = nullptr;
-    ProfScope(int kernel, hipStream_t stream, double flops, double bytes);
+    ProfScope(int kernel, hipStream_t stream, double flops, double bytes, double bound_ms = 0.0);
     ~ProfScope();
 };
 

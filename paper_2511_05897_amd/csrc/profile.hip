@@ -11,13 +11,13 @@ namespace {
 struct Rec {
     hipEvent_t a, b;
     int k;
-    double flops, bytes;
+    double flops, bytes, bound_ms;
 };
 std::mutex mu;
 std::atomic<bool> enabled{false};
 std::vector<Rec> recs;
 struct Acc {
-    double ms = 0, flops = 0, bytes = 0;
+    double ms = 0, flops = 0, bytes = 0, bound_ms = 0;
     long long n = 0;
 } acc[PROF_N];
 
@@ -29,6 +29,7 @@ void drain() {
             acc[r.k].n += 1;
             acc[r.k].flops += r.flops;
             acc[r.k].bytes += r.bytes;
+            acc[r.k].bound_ms += r.bound_ms;
         }
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -37,7 +38,8 @@ void drain() {
 }
 }  // namespace
 
-ProfScope::ProfScope(int kernel, hipStream_t stream, double f, double b) : k(kernel), s(stream), flops(f), bytes(b) {
+ProfScope::ProfScope(int kernel, hipStream_t stream, double f, double b, double bound)
+    : k(kernel), s(stream), flops(f), bytes(b), bound_ms(bound) {
     if (!enabled || g_dry) return;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return;
@@ -53,7 +55,7 @@ ProfScope::~ProfScope() {
     if (hipEventCreate(&e) != hipSuccess) return;
     if (hipEventRecord(e, s) != hipSuccess) { (void)hipEventDestroy(e); return; }
     std::lock_guard<std::mutex> g(mu);
-    recs.push_back(Rec{(hipEvent_t)ev0, e, k, flops, bytes});
+    recs.push_back(Rec{(hipEvent_t)ev0, e, k, flops, bytes, bound_ms});
     if (recs.size() > 4096) drain();
 }
 
@@ -79,5 +81,17 @@ extern "C" int adc3_profile_query(int kernel, double* total_ms, long long* count
     if (count) *count = acc[kernel].n;
     if (flops) *flops = acc[kernel].flops;
     if (bytes) *bytes = acc[kernel].bytes;
+    return ADC3_OK;
+}
+
+extern "C" int adc3_profile_query_bound(int kernel, double* bound_ms) {
+    using namespace adc3;
+    if (kernel < 0 || kernel >= PROF_N || !bound_ms) {
+        set_error("adc3_profile_query_bound: unknown kernel id or NULL output");
+        return ADC3_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(mu);
+    drain();
+    *bound_ms = acc[kernel].bound_ms;
     return ADC3_OK;
 }
