@@ -243,6 +243,13 @@ void gemm(const Gemm& g, hipStream_t s, int tag) {
     // K <= 0 is valid: the kernel then writes C = beta*C.
     if (nb > 65535) fail(-1, "gemm: too many batches");
     const int sh = pick_shape(g, tag);
+    // large single GEMMs with both operands contiguous along their tile rows: the ladder kernel's
+    // tile (whole-M row blocks, 2 workgroups per CU, 16-byte loads) without splitting K
+    if (sh == SH_128x128 && nb == 1 && g.sAk == 1 && g.sBn == 1 && g.sCn == 1 &&
+        ladder_supported(g.M, g.N, g.K, g.A, g.sAm, g.B, g.sBk, g.C, g.sCm)) {
+        ladder_gemm(g.M, g.N, g.K, g.alpha, g.A, g.sAm, g.B, g.sBk, g.beta, g.C, g.sCm, 1, nullptr, 0, s);
+        return;
+    }
     const long long tiles = (long long)((g.N + tile_n(sh) - 1) / tile_n(sh)) * ((g.M + tile_m(sh) - 1) / tile_m(sh));
     const long long MN = (long long)g.M * g.N;
     // few output tiles and a long K: cut K into chunks (one batch each), then sum the
