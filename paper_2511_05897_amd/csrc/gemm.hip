@@ -247,7 +247,7 @@ void gemm(const Gemm& g, hipStream_t s, int tag) {
     // tile (whole-M row blocks, 2 workgroups per CU, 16-byte loads) without splitting K
     if (sh == SH_128x128 && nb == 1 && g.sAk == 1 && g.sBn == 1 && g.sCn == 1 &&
         ladder_supported(g.M, g.N, g.K, g.A, g.sAm, g.B, g.sBk, g.C, g.sCm)) {
-        ladder_gemm(g.M, g.N, g.K, g.alpha, g.A, g.sAm, g.B, g.sBk, g.beta, g.C, g.sCm, 1, nullptr, 0, s);
+        ladder_gemm(g.M, g.N, g.K, g.alpha, g.A, g.sAm, g.B, g.sBk, g.beta, g.C, g.sCm, 1, nullptr, 0, s, 2);
         return;
     }
     const long long tiles = (long long)((g.N + tile_n(sh) - 1) / tile_n(sh)) * ((g.M + tile_m(sh) - 1) / tile_m(sh));

@@ -45,7 +45,8 @@ struct LadderArgs {
     double alpha, beta;
 };
 
-// TAG 1 marks the tuner's trial launches (a separate symbol for profilers).
+// TAG 1 marks the tuner's trial launches, TAG 2 other large GEMMs on this tile (separate symbols
+// for profilers).
 template <int TM, int TAG>
 __global__ __launch_bounds__(LNT, 2) void ladder_f64_kernel(LadderArgs g) {
     constexpr int BM = 16 * TM;
@@ -431,8 +432,9 @@ void launch_tag(const LadderArgs& a, int tm, int mtiles, hipStream_t s) {
     }
 }
 
-void launch(const LadderArgs& a, int tm, int mtiles, bool trial, hipStream_t s) {
-    if (trial) launch_tag<1>(a, tm, mtiles, s);
+void launch(const LadderArgs& a, int tm, int mtiles, int tag, hipStream_t s) {
+    if (tag == 1) launch_tag<1>(a, tm, mtiles, s);
+    else if (tag == 2) launch_tag<2>(a, tm, mtiles, s);
     else launch_tag<0>(a, tm, mtiles, s);
     LAUNCHCHK();
 }
@@ -488,7 +490,7 @@ void ladder_gemm_lp(int prec, int M, int N, int K, double alpha, const void* Z, 
 
 void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long ldz, const double* G, long long ldg,
                  double beta, double* C, long long ldc, int nchunk, double* partial, long long partial_elems,
-                 hipStream_t s, bool trial) {
+                 hipStream_t s, int tag) {
     if (g_dry || M <= 0 || N <= 0) return;
     int tm, mtiles;
     ladder_rows(M, tm, mtiles);
@@ -501,7 +503,7 @@ void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long l
     a.nchunk = (K + a.Kc - 1) / a.Kc;
     a.ntn = (N + LBN - 1) / LBN;
     a.alpha = alpha; a.beta = beta;
-    launch(a, tm, mtiles, trial, s);
+    launch(a, tm, mtiles, tag, s);
     if (a.nchunk > 1) splitk_reduce(partial, a.nchunk, M, N, alpha, beta, C, ldc, 1, s);
 }
 
@@ -568,7 +570,7 @@ static void ladder_run(int prec, int M, int N, int K, const void* Z, long long l
                        double* C, long long ldc, int nchunk, double* partial, long long pe, hipStream_t s) {
     if (prec == 0)
         ladder_gemm(M, N, K, 1.0, (const double*)Z, ldz, (const double*)G, ldg, 0.0, C, ldc, nchunk, partial, pe, s,
-                    true);
+                    1);
     else
         ladder_gemm_lp(prec, M, N, K, 1.0, Z, ldz, G, ldg, 0.0, C, ldc, nchunk, partial, pe, s, true);
 }

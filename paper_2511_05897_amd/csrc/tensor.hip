@@ -88,9 +88,12 @@ void ein2(Arena& ws, const char* spec, double alpha, const double* A, const int*
     g.M = (int)M; g.N = (int)N; g.K = (int)K;
     g.alpha = alpha;
     if (M > 2147483647LL || N > 2147483647LL || K > 2147483647LL) fail(-1, "ein2: dimension too large");
+    // A large contraction gets row-major operands and output (a permute of each is cheap next to
+    // the GEMM), so that it runs on the row-contiguous fast tile
+    const bool big = 2.0 * (double)M * (double)N * (double)K >= 4e9;
     // A
     if (p.a == Ml + Kl) { g.A = A; g.sAm = K; g.sAk = 1; }
-    else if (p.a == Kl + Ml) { g.A = A; g.sAm = 1; g.sAk = M; }
+    else if (p.a == Kl + Ml && !big) { g.A = A; g.sAm = 1; g.sAk = M; }
     else {
         double* t = ws.take<double>(M * K);
         permute_any(t, A, p.a, adims, Ml + Kl, 1.0, 0.0, s);
@@ -98,7 +101,7 @@ void ein2(Arena& ws, const char* spec, double alpha, const double* A, const int*
     }
     // B
     if (p.b == Kl + Nl) { g.B = B; g.sBk = N; g.sBn = 1; }
-    else if (p.b == Nl + Kl) { g.B = B; g.sBk = 1; g.sBn = K; }
+    else if (p.b == Nl + Kl && !big) { g.B = B; g.sBk = 1; g.sBn = K; }
     else {
         double* t = ws.take<double>(K * N);
         permute_any(t, B, p.b, bdims, Kl + Nl, 1.0, 0.0, s);
@@ -106,7 +109,7 @@ void ein2(Arena& ws, const char* spec, double alpha, const double* A, const int*
     }
     // C
     if (p.o == Ml + Nl) { g.C = C; g.sCm = N; g.sCn = 1; g.beta = beta; gemm(g, s); }
-    else if (p.o == Nl + Ml) { g.C = C; g.sCm = 1; g.sCn = M; g.beta = beta; gemm(g, s); }
+    else if (p.o == Nl + Ml && !big) { g.C = C; g.sCm = 1; g.sCn = M; g.beta = beta; gemm(g, s); }
     else {
         double* t = ws.take<double>(M * N);
         g.C = t; g.sCm = N; g.sCn = 1; g.beta = 0.0;
