@@ -26,6 +26,11 @@ Readings where the paper is silent (each listed in the design notes):
   truncated basis (first one on ties), and the truncated ADC(3) root with the same
   index m.  With nothing truncated m = k, so corrected root k is canonical ADC(3)
   root k.
+
+Parity unpinned: the D^EA reading, the root matching rule and the thresholds' effect
+at the literal input scale have no printed worked example to pin them; they are
+pinned only by their limits (trace of D^EA, the untruncated limit reproducing
+canonical ADC(3), natural-orbital and NAF identities) in the tests.
 """
 import numpy as np
 
