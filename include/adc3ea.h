@@ -63,9 +63,13 @@ typedef struct {
                              Ritz vectors with FP64 sigma (FP64 residual correction) down to conv;
                              orthogonalisation, Rayleigh-Ritz, residual norms and every
                              eigendecomposition stay FP64.  Default 0. */
-    int precond;          /* 0: Jacobi (diagonal) preconditioner; 1: learned (needs mlp_weights), in the
-                             ADC(3) solves (ADC(2) stays Jacobi); 2: Olsen, t = (D-theta)^-1 (r - eps x) with
-                             eps making t orthogonal to the Ritz vector x in the D-theta metric */
+    int precond;          /* Davidson step.  0: Jacobi (diagonal) everywhere; 1: learned (needs
+                             mlp_weights) in the ADC(3) solves; 2: Olsen, t = (D-theta)^-1 (r - eps x),
+                             eps making t orthogonal to the Ritz vector x in the D-theta metric,
+                             everywhere; 3 (default): Jacobi in the ADC(3) solves.  Under 1 and 3 the
+                             ADC(2) solves, whose 2p1h block is diagonal, take the 1p block exactly:
+                             t1 = (M11 - theta)^-1 r1 (through the eigendecomposition of M11),
+                             t2 = r2 / (D2 - theta). */
     const float* mlp_weights; /* device, adc3_mlp_nparams() floats (see adc3_mlp_train); NULL default */
     int sigma_graphs;     /* 1: each sigma pass shape is captured once into a HIP graph and replayed
                              (needs a non-null stream; on the null stream sigma runs eagerly); default 0 */

@@ -90,6 +90,9 @@ struct Ctx {
     double *eo = nullptr, *ev = nullptr, *Boo = nullptr, *Bov = nullptr, *Bvv = nullptr;
     double *ovov = nullptr, *oovv = nullptr, *T = nullptr, *M11 = nullptr, *Uz = nullptr, *diag = nullptr;
     double *Dmp2 = nullptr;
+    // eigendecomposition of M11 for the block preconditioner (computed on first use)
+    double *m11_Q = nullptr, *m11_w = nullptr, *m11_tmp = nullptr;
+    bool m11_eig = false;
     double *G = nullptr;      // ladder (ac|bd) as [(ab),(cd)], level 3
     double *P1 = nullptr;     // (ij|bd) as [i][b][j][d], level 3
     double *P2 = nullptr;     // (ij|ad) as [i][a][j][d], level 3
@@ -150,6 +153,9 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     k_amp_t(c->ovov, eo, ev, o, v, c->T, s);
     const double* T = c->T;
     c->M11 = take(ws, vv);
+    c->m11_Q = take(ws, vv);
+    c->m11_w = take(ws, v);
+    c->m11_tmp = take(ws, vv + (long long)eig_large_scratch(v) + v);
     c->Dmp2 = take(ws, vv);
     c->diag = take(ws, c->N);
     c->Uz = take(ws, v * (long long)o * vv);
@@ -505,7 +511,8 @@ struct DavResult {
 static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int max_iter, int max_sub,
                                double* vec_out, hipStream_t s, int prec = 0, bool use_mlp = false,
                                Recorder* rec = nullptr, const double* guess = nullptr, int nguess_in = 0,
-                               bool olsen = false) {
+                               int pmode = 0) {
+    const bool olsen = pmode == 2, block1p = pmode == 3;
     if (prec > c->prec) prec = c->prec;
     ProfScope prof(PROF_DAVIDSON, s, 0.0, 0.0);
     const long long N = c->N;
@@ -588,6 +595,12 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     std::vector<double> one(1, 1.0);
     for (int k = 0; k < nguess - ng; ++k) h2d(V + (long long)(ng + k) * N + idx[k], one.data(), sizeof(double), s);
     int m = nguess;
+    if (block1p && !c->m11_eig) {
+        const long long vv = (long long)c->v * c->v;
+        k_copy(c->m11_tmp, c->M11, vv, s);
+        eig_large(c->m11_tmp, c->v, c->m11_w, c->m11_Q, c->m11_tmp + vv + c->v, s);
+        c->m11_eig = true;
+    }
     if (ng > 0) {
         m = orthonormalise(V, nguess, 0, S);
         if (m < nroots) fail(-4, "davidson: initial guesses are linearly dependent");
@@ -730,6 +743,14 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
                 const double rms = std::max(res.rn[k] / std::sqrt((double)N), 1e-300);
                 mlp_precondition(R + (long long)k * N, c->diag, res.w[k], rms, c->eo, c->ev, c->o, c->v, N, c->mlp_w,
                                  c->mlp_wb, Tn + (long long)j * N, mflag + j, s);
+            } else if (block1p) {
+                // 1p block exactly: t1 = (M11 - theta)^-1 r1 through M11 = Q diag(w) Q^T; 2p1h diagonal
+                double* y = c->m11_tmp + (long long)c->v * c->v;
+                const int v = c->v;
+                gemm_rm(1, v, v, 1.0, R + (long long)k * N, v, false, c->m11_Q, v, false, 0.0, y, v, s);
+                k_div_shift(y, c->m11_w, th + k, v, s);
+                gemm_rm(1, v, v, 1.0, y, v, false, c->m11_Q, v, true, 0.0, Tn + (long long)j * N, v, s);
+                k_precond(Tn + (long long)j * N + v, R + (long long)k * N + v, c->diag + v, th + k, 1, N - v, s);
             } else {
                 k_precond(Tn + (long long)j * N, R + (long long)k * N, c->diag, th + k, 1, N, s);
                 if (olsen) {
@@ -914,13 +935,18 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     SolveOut out;
     out.rep.assign(nroots, adc3_root_report{});
     const int level = op.level;
+    // Davidson step per level: ADC(2) solves take the exact 1p block unless Jacobi or Olsen is
+    // asked for (their 2p1h block is diagonal, so only the 1p block is approximated by the
+    // diagonal step); ADC(3) solves take Jacobi, Olsen, or the learned step
+    const int pm2 = (op.precond == 0 || op.precond == 2) ? op.precond : 3;
+    const int pm3 = op.precond == 2 ? 2 : 0;
     if (!(fno > 0) && !(naf > 0)) {
         const size_t mark = ws.mark();
         Ctx* c = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, level, s, op.precision);
         c->mlp_w = op.mlp_weights;
         c->graphs = op.sigma_graphs != 0;
         DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
-                                    op.precond == 1, nullptr, nullptr, 0, op.precond == 2);
+                                    op.precond == 1 && level >= 3, nullptr, nullptr, 0, level >= 3 ? pm3 : pm2);
         for (int k = 0; k < nroots; ++k) {
             auto& R = out.rep[k];
             R.omega = R.omega_uncorr = r.w[k];
@@ -943,7 +969,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     c0->graphs = op.sigma_graphs != 0;
     double* Y2 = take(ws, (long long)nroots * c0->N);
     DavResult r2 = davidson_impl(c0, ws, nroots, conv, op.max_iter, op.max_subspace, Y2, s, op.precision, false,
-                                 nullptr, nullptr, 0, op.precond == 2);
+                                 nullptr, nullptr, 0, pm2);
     out.all_conv = out.all_conv && r2.converged;
     VLOG("canonical ADC(2): %d roots, %d iterations, lowest %.10f", nroots, r2.iters, r2.w[0]);
     const int sig0 = (int)c0->sigma_count;
@@ -1001,7 +1027,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s, op.precision);
             c2->graphs = op.sigma_graphs != 0;
             DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s, op.precision,
-                                         false, nullptr, carried, nroots, op.precond == 2);
+                                         false, nullptr, carried, nroots, pm2);
             k_dots(Y2k, Nk, nroots, ref, Nk, 1, Nk, ovl, 1, part, s);
             std::vector<double> hov(nroots);
             d2h(hov.data(), ovl, nroots * sizeof(double), s);
@@ -1026,7 +1052,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             // only roots 0..match of this basis are needed: the matched one and those below it
             const int nr3 = std::min(nroots, match + 1);
             DavResult a3 = davidson_impl(c3, ws, nr3, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
-                                         op.precond == 1, nullptr, Y2k, nroots, op.precond == 2);
+                                         op.precond == 1, nullptr, Y2k, nroots, level >= 3 ? pm3 : pm2);
             R.omega_uncorr = a3.w[match];
             R.omega_lowp = a3.w_lowp.empty() ? a3.w[match] : a3.w_lowp[match];
             R.iters_lowp = a3.iters_lowp;
@@ -1084,7 +1110,7 @@ void adc3_default_opts(adc3_opts* o) {
     o->max_subspace = 0;
     o->fno_correction = 1;
     o->precision = 0;
-    o->precond = 0;
+    o->precond = 3;
     o->mlp_weights = nullptr;
     o->sigma_graphs = 0;
 }
@@ -1283,7 +1309,8 @@ static adc3_opts resolve_opts(const adc3_opts* opts) {
     if (o.level != 2 && o.level != 3) fail(ADC3_EINVAL, "opts.level must be 2 or 3");
     if (o.max_iter < 1) fail(ADC3_EINVAL, "opts.max_iter must be >= 1");
     if (o.precision < 0 || o.precision > 2) fail(ADC3_EUNSUP, "opts.precision must be 0 (FP64), 1 (FP32) or 2 (BF16)");
-    if (o.precond < 0 || o.precond > 2) fail(ADC3_EUNSUP, "opts.precond must be 0 (Jacobi), 1 (learned) or 2 (Olsen)");
+    if (o.precond < 0 || o.precond > 3)
+        fail(ADC3_EUNSUP, "opts.precond must be 0 (Jacobi), 1 (learned), 2 (Olsen) or 3 (exact 1p block)");
     if (o.precond == 1 && !o.mlp_weights) fail(ADC3_EINVAL, "opts.precond = 1 needs opts.mlp_weights");
     return o;
 }

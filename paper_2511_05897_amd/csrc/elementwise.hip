@@ -361,6 +361,21 @@ void k_residual(double* R, const double* AX, const double* X, const double* th, 
     hipLaunchKernelGGL(residual_kernel, dim3(nblocks(t)), dim3(NT), 0, s, R, AX, X, th, nk, n);
     LAUNCHCHK();
 }
+// y[a] /= (lam[a] - th[0])  (denominators clamped away from 0 as in the diagonal step)
+__global__ void div_shift_kernel(double* y, const double* lam, const double* th, int n) {
+    GRID_STRIDE(t, (long long)n) {
+        double den = lam[t] - th[0];
+        if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+        y[t] /= den;
+    }
+}
+
+void k_div_shift(double* y, const double* lam, const double* th, int n, hipStream_t s) {
+    if (g_dry || n <= 0) return;
+    hipLaunchKernelGGL(div_shift_kernel, dim3(nblocks(n)), dim3(NT), 0, s, y, lam, th, n);
+    LAUNCHCHK();
+}
+
 // T -= (s[0]/s[1]) B  (s[1] == 0: T unchanged)
 __global__ void olsen_kernel(double* T, const double* B, const double* sc, long long n) {
     const double d = sc[1];

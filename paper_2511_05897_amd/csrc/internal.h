@@ -157,6 +157,7 @@ void k_residual(double* R, const double* AX, const double* X, const double* thet
 // T[k][i] = R[k][i] / (D[i] - theta[k]) with |D - theta| >= floor
 void k_precond(double* T, const double* R, const double* D, const double* theta, int nk, long long n, hipStream_t s);
 void k_olsen(double* T, const double* B, const double* sc, long long n, hipStream_t s);  // T -= (sc[0]/sc[1]) B
+void k_div_shift(double* y, const double* lam, const double* th, int n, hipStream_t s);  // y /= lam - th[0]
 void k_scale_vec(double* x, long long n, const double* factor_dev, hipStream_t s);   // x *= factor[0]
 // row j of T[nn][n] *= 1/sqrt(G[j*ldg + j])  (rows with G <= 0 are zeroed)
 void k_rscale_rows(double* T, int nn, long long n, const double* G, int ldg, hipStream_t s);

@@ -176,3 +176,23 @@ def test_olsen_preconditioner_same_roots():
     r0, _, _ = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 2, 1e-4, 1e-3, 1e-8)
     r2, _, st2 = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 2, 1e-4, 1e-3, 1e-8, opts=o)
     assert st2 == 0 and np.abs(r0 - r2).max() < 1e-9
+
+
+def test_exact_1p_block_preconditioner_adc2():
+    # ADC(2): the 2p1h block is diagonal, so the Davidson step takes the 1p block exactly
+    p, eo, ev, B = synth.preset("tiny-dense")
+    ref = np.linalg.eigvalsh(Problem(eo, ev, B).dense(2))[:3]
+    for pc in (0, 3):
+        o = adc.adc3_default_opts()
+        o.level = 2
+        o.precond = pc
+        roots, reps, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-8, opts=o)
+        assert st == 0 and np.abs(roots - ref).max() < 1e-8
+    # full pipeline: Jacobi everywhere vs the default policy
+    eo, ev, B = synth.make_instance(3, 16, 40, 21, scale=0.05)
+    o = adc.adc3_default_opts()
+    o.precond = 0
+    r0, p0, _ = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 1e-4, 1e-3, 1e-8, opts=o)
+    r3, p3, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 1e-4, 1e-3, 1e-8)
+    assert st == 0 and np.abs(r0 - r3).max() < 1e-9
+    assert [x["nvir_kept"] for x in p0] == [x["nvir_kept"] for x in p3]

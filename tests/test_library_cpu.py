@@ -32,7 +32,7 @@ def test_exports_every_declared_symbol(lib):
 
 def test_default_opts(lib):
     o = adc.adc3_default_opts()
-    assert (o.level, o.max_iter, o.max_subspace, o.fno_correction, o.precision, o.precond) == (3, 500, 0, 1, 0, 0)
+    assert (o.level, o.max_iter, o.max_subspace, o.fno_correction, o.precision, o.precond) == (3, 500, 0, 1, 0, 3)
     assert not o.mlp_weights and o.sigma_graphs == 0
 
 
