@@ -889,13 +889,25 @@ static void transform_blocks(const Blocks& in, const double* U, int vk, Blocks& 
 }
 
 // Natural auxiliary functions (eqs 27-29): W = J_vv J_vv^T, keep w >= thr (thr <= 0 keeps all).
-static int naf_blocks(const Blocks& in, double thr, Blocks& out, Arena& ws, hipStream_t s) {
+// W is invariant under orthogonal rotations of the virtual basis: W_PQ = tr(B^P Pi B^Q Pi) with Pi
+// the projector onto the kept virtuals.  When nothing is truncated (Pi = 1) every root has the
+// same W, so the first root's eigenvectors are kept in `cache` and reused.
+struct NafCache {
+    double* N = nullptr;  // X x X, sorted eigenvectors
+    double* w = nullptr;  // X eigenvalues
+    bool valid = false;
+};
+
+static int naf_blocks(const Blocks& in, double thr, Blocks& out, Arena& ws, hipStream_t s, NafCache* cache = nullptr) {
     const int X = in.X, o = in.o, v = in.v;
     const long long vv = (long long)v * v;
     double* W = take(ws, (long long)X * X);
     double* w = take(ws, X);
     double* N = take(ws, (long long)X * X);
-    {
+    if (cache && cache->valid) {
+        k_copy(N, cache->N, (long long)X * X, s);
+        k_copy(w, cache->w, X, s);
+    } else {
         const size_t mark = ws.mark();
         double* wt = take(ws, X);
         double* Nt = take(ws, (long long)X * X);
@@ -905,6 +917,11 @@ static int naf_blocks(const Blocks& in, double thr, Blocks& out, Arena& ws, hipS
         eig_large(W, X, w, N, scr, s);
         k_sort_eig(w, N, X, 1, wt, Nt, s);
         ws.release(mark);
+        if (cache) {
+            k_copy(cache->N, N, (long long)X * X, s);
+            k_copy(cache->w, w, X, s);
+            cache->valid = !g_dry;
+        }
     }
     std::vector<double> hw(std::max(X, 1));
     d2h(hw.data(), w, X * sizeof(double), s);
@@ -973,6 +990,11 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     out.all_conv = out.all_conv && r2.converged;
     VLOG("canonical ADC(2): %d roots, %d iterations, lowest %.10f", nroots, r2.iters, r2.w[0]);
     const int sig0 = (int)c0->sigma_count;
+    NafCache naf_cache;
+    if (naf > 0) {
+        naf_cache.N = take(ws, (long long)X * X);
+        naf_cache.w = take(ws, X);
+    }
     // step 4: per root
     for (int k = 0; k < nroots; ++k) {
         const size_t mark = ws.mark();
@@ -990,7 +1012,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         transform_blocks(B0, U, vk, Bt, ws, s);
         Blocks Bn = Bt;
         int xk = X;
-        if (naf > 0) xk = naf_blocks(Bt, naf, Bn, ws, s);           // 4e
+        if (naf > 0) xk = naf_blocks(Bt, naf, Bn, ws, s, vk == v ? &naf_cache : nullptr);  // 4e
         VLOG("root %d: kept %d virtuals, %d auxiliary functions", k, vk, xk);
         const long long Nk = vk + (long long)o * vk * vk;
         if (nroots > Nk) fail(ADC3_EINVAL, "truncated space smaller than nroots");
