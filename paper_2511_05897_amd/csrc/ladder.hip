@@ -13,7 +13,8 @@
 //     give >= 4 workgroups per CU slot; with a multiple of 8 chunks, the workgroups that
 //     one XCD runs together share one chunk of Z in that XCD's L2.
 // Operands are read with 16-byte loads (both are contiguous along their tile rows) and
-// staged through double-buffered LDS.
+// staged through double-buffered LDS, the Z tile transposed to [k][m] so that the 16 lanes
+// of a fragment read 16 consecutive words.
 //
 // MFMA f64 16x16x4 (lane l of a wave64): A frag A[l%16][l/16], B frag B[l/16][l%16],
 // accumulator element r holds D[l/16 + 4r][l%16].
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f64_kernel(LadderArgs g) {
     constexpr int BM = 16 * TM;
     constexpr int PA = (BM * (LBK / 2) + LNT - 1) / LNT;  // 16-byte A loads per thread
     constexpr int PB = (LBK * (LBN / 2)) / LNT;            // 16-byte B loads per thread
-    __shared__ __attribute__((aligned(16))) double As[2][BM][LBK + APAD];
+    __shared__ __attribute__((aligned(16))) double As[2][LBK][BM + APAD];  // transposed: [k][m]
     __shared__ __attribute__((aligned(16))) double Bs[2][LBK][LBN + BPAD];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -103,8 +104,8 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f64_kernel(LadderArgs g) {
 #pragma unroll
         for (int p = 0; p < PA; ++p)
             if (arow[p] >= 0) {
-                As[buf][arow[p]][2 * akq[p]] = ra[p].x;
-                As[buf][arow[p]][2 * akq[p] + 1] = ra[p].y;
+                As[buf][2 * akq[p]][arow[p]] = ra[p].x;
+                As[buf][2 * akq[p] + 1][arow[p]] = ra[p].y;
             }
 #pragma unroll
         for (int p = 0; p < PB; ++p) *(d2v*)&Bs[buf][bkr[p]][2 * bnq[p]] = rb[p];
@@ -131,7 +132,7 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f64_kernel(LadderArgs g) {
             for (int j = 0; j < LTN; ++j) bf[j] = Bs[buf][kk + lk][cb + 16 * j + lr];
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
-                const double af = As[buf][16 * i + lr][kk + lk];
+                const double af = As[buf][kk + lk][16 * i + lr];
 #pragma unroll
                 for (int j = 0; j < LTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[j], acc[i][j], 0, 0, 0);
             }
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f32_kernel(LadderLP g) {
     constexpr int BM = 16 * TM;
     constexpr int PA = (BM * (FBK / 4) + LNT - 1) / LNT;
     constexpr int PB = (FBK * (LBN / 4)) / LNT;
-    __shared__ __attribute__((aligned(16))) float As[2][BM][FBK + 1];
+    __shared__ __attribute__((aligned(16))) float As[2][FBK][BM + 1];  // transposed: [k][m]
     __shared__ __attribute__((aligned(16))) float Bs[2][FBK][LBN + 4];
     const float* __restrict__ Z = (const float*)g.Z;
     const float* __restrict__ G = (const float*)g.G;
@@ -266,7 +267,7 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f32_kernel(LadderLP g) {
         for (int p = 0; p < PA; ++p)
             if (arow[p] >= 0) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) As[buf][arow[p]][4 * akq[p] + q] = ra[p][q];
+                for (int q = 0; q < 4; ++q) As[buf][4 * akq[p] + q][arow[p]] = ra[p][q];
             }
 #pragma unroll
         for (int p = 0; p < PB; ++p) *(f4v*)&Bs[buf][bkr[p]][4 * bnq[p]] = rb[p];
@@ -293,7 +294,7 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f32_kernel(LadderLP g) {
             for (int j = 0; j < LTN; ++j) bf[j] = Bs[buf][kk + lk][cb + 16 * j + lr];
 #pragma unroll
             for (int i = 0; i < TM; ++i) {
-                const float af = As[buf][16 * i + lr][kk + lk];
+                const float af = As[buf][kk + lk][16 * i + lr];
 #pragma unroll
                 for (int j = 0; j < LTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[j], acc[i][j], 0, 0, 0);
             }
