@@ -202,6 +202,37 @@ def learned_full_size(adc, d, torch, np, scale):
     return out
 
 
+def mixed_ladder_dominated(adc, d, torch, np):
+    """ADC(3) Davidson (5 roots, conv 1e-6) on o=20, v=300, X=900, seed 3, scale 0.3 -- a shape where the
+    ladder dominates each iteration -- with FP64, FP32-ladder and BF16-ladder sigma (the reduced
+    phases end with an FP64 restart).  Context setup (FP64 in every mode) is not timed."""
+    import synth
+    eo, ev, B = synth.make_instance(20, 300, 900, 3, scale=0.3)
+    tB = d(B)
+    del B
+    out, ref = {}, None
+    for prec, tag in ((0, "fp64"), (1, "fp32"), (2, "bf16")):
+        ctx = adc.Context(d(eo), d(ev), tB, 3, nroots=5, precision=prec)
+        ctx.davidson(5, 1e-6, precision=prec)  # warm-up: tuner, first launches
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w, _, rn, it, st = ctx.davidson(5, 1e-6, precision=prec)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if ref is None:
+            ref = w
+        out[tag] = {"davidson_s": dt, "iterations": it, "status": st,
+                    "max_abs_root_diff_vs_fp64_Eh": float(np.abs(w - ref).max())}
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    out["shape"] = [20, 300, 900]
+    out["roots_fp64"] = [float(x) for x in ref]
+    for tag in ("fp32", "bf16"):
+        out[tag]["speedup_vs_fp64"] = out["fp64"]["davidson_s"] / out[tag]["davidson_s"]
+    return out
+
+
 def cpu_baseline(shape, nvec):
     """The FP64 oracle's sigma build on the host: nvec ADC(3) sigma vectors on a
     synthetic instance of the truncated-basis shape (one-time intermediates not timed)."""
@@ -338,6 +369,10 @@ def main():
                                          "bound_time_frac": lbound / lms if lms > 0 else None}}
             except Exception as e:
                 mixed[tag] = {"error": str(e)}
+        try:
+            mixed["ladder_dominated_davidson"] = mixed_ladder_dominated(adc, d, torch, np)
+        except Exception as e:
+            mixed["ladder_dominated_davidson"] = {"error": str(e)}
 
     # the same workload with B scaled into the weakly correlated regime (SS-FNO then truncates)
     variant = None
