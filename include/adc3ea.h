@@ -73,6 +73,13 @@ typedef struct {
     const float* mlp_weights; /* device, adc3_mlp_nparams() floats (see adc3_mlp_train); NULL default */
     int sigma_graphs;     /* 1: each sigma pass shape is captured once into a HIP graph and replayed
                              (needs a non-null stream; on the null stream sigma runs eagerly); default 0 */
+    int ladder;           /* form of the ladder term sum_cd (ac|bd) r_cdi of the ADC(3) contexts:
+                             1 stored: (ac|bd) assembled once per basis from the DF factor (eq 25) and
+                               kept as a v^4 matrix, 2 M v^4 flops per application of M rows;
+                             2 assembled: sum_Q B^Q Z_i B^Q from the virtual block of the factor in
+                               every application, 4 X M v^3 flops and no v^4 storage;
+                             0 (default): stored unless the v^4 matrix of the canonical basis exceeds
+                               96 GB in FP64 (nvir > 331).  The choice holds for the whole solve. */
 } adc3_opts;
 
 /* Per-root report of adc3_ea_solve. */
@@ -168,7 +175,38 @@ int adc3_ea_setup(const double* eps_occ_dev, const double* eps_vir_dev, const do
                   void* workspace_dev, size_t workspace_bytes, hipStream_t stream,
                   adc3_ctx** ctx_out);
 
+/* As adc3_ea_setup_workspace_bytes / adc3_ea_setup, with the ladder form of a level-3
+ * context chosen as in adc3_opts.ladder (0 auto by nvir, 1 stored, 2 assembled from the
+ * factor).  The two calls above are these with ladder = 0.  Invalid ladder: 0 bytes /
+ * ADC3_EINVAL. */
+size_t adc3_ea_setup_workspace_bytes_ex(int nocc, int nvir, int naux, int level, int nroots, int precision,
+                                        int ladder);
+int adc3_ea_setup_ex(const double* eps_occ_dev, const double* eps_vir_dev, const double* B_dev,
+                     int nocc, int nvir, int naux, int level, int precision, int ladder,
+                     void* workspace_dev, size_t workspace_bytes, hipStream_t stream,
+                     adc3_ctx** ctx_out);
+
 void adc3_ctx_destroy(adc3_ctx* ctx);
+
+/* Element budget for one chunk of the large setup tensors (the o*na*v^2 slices of the
+ * 1p/2p1h coupling build are cut along the first virtual index to stay within it; the
+ * assembled ladder's intermediate may take twice it).  n > 0 sets it for the process (takes
+ * effect for contexts and workspace plans made afterwards); n <= 0 only queries.  Returns the
+ * previous value.  Default 2^29 (4.3 GB of FP64). */
+long long adc3_set_chunk_elems(long long n);
+
+/* The ladder term alone, assembled from the DF factor (the form of adc3_opts.ladder = 2):
+ *   C[m][a][b] = sum_cd (ac|bd) Z[m][c][d],  (ac|bd) = sum_Q Bvv[Q][a][c] Bvv[Q][b][d]  (eq 25),
+ * computed as sum_Q B^Q Z_m B^Q in chunks of auxiliary functions.  Bvv_dev [naux][nvir][nvir]
+ * (each block symmetric), Z_dev and C_dev [nrows][nvir][nvir], FP64, device, row-major; C is
+ * overwritten.  precision 1 / 2: Bvv and Z are rounded to FP32 / BF16 and the products
+ * accumulate in FP32 (C stays FP64).  The workspace holds the rounded copies and the
+ * intermediate; its size sets the chunk: at least adc3_ladder_workspace_bytes (one auxiliary
+ * function per chunk), naux times the intermediate part for a single chunk.  Stream-ordered,
+ * asynchronous; nvir <= 1024, nrows <= 65535. */
+size_t adc3_ladder_workspace_bytes(int nvir, int naux, int nrows, int precision);
+int adc3_ladder_apply(const double* Bvv_dev, const double* Z_dev, double* C_dev, int nvir, int naux, int nrows,
+                      int precision, void* workspace_dev, size_t workspace_bytes, hipStream_t stream);
 
 /* Dimension N of the context's vector space. */
 long long adc3_ea_dim(const adc3_ctx* ctx);

@@ -24,13 +24,15 @@ EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_byte
            "adc3_ea_intermediate", "adc3_profile_enable", "adc3_profile_query", "adc3_mlp_nparams",
            "adc3_ea_set_preconditioner", "adc3_mlp_collect", "adc3_mlp_workspace_bytes", "adc3_mlp_loss_grad",
            "adc3_mlp_forward", "adc3_mlp_train", "adc3_ea_precondition", "adc3_ea_solve_batched_workspace_bytes",
-           "adc3_ea_solve_batched", "adc3_ea_set_sigma_graphs", "adc3_profile_query_bound"]
+           "adc3_ea_solve_batched", "adc3_ea_set_sigma_graphs", "adc3_profile_query_bound",
+           "adc3_ea_setup_workspace_bytes_ex", "adc3_ea_setup_ex", "adc3_set_chunk_elems",
+           "adc3_ladder_workspace_bytes", "adc3_ladder_apply"]
 
 
 class adc3_opts(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int), ("max_iter", ctypes.c_int), ("max_subspace", ctypes.c_int),
                 ("fno_correction", ctypes.c_int), ("precision", ctypes.c_int), ("precond", ctypes.c_int),
-                ("mlp_weights", ctypes.c_void_p), ("sigma_graphs", ctypes.c_int)]
+                ("mlp_weights", ctypes.c_void_p), ("sigma_graphs", ctypes.c_int), ("ladder", ctypes.c_int)]
 
 
 class adc3_instance(ctypes.Structure):
@@ -77,6 +79,16 @@ def load():
     lib.adc3_ea_setup_workspace_bytes.restype = S
     lib.adc3_ea_setup.argtypes = [P, P, P, I, I, I, I, I, P, S, P, ctypes.POINTER(P)]
     lib.adc3_ea_setup.restype = I
+    lib.adc3_ea_setup_workspace_bytes_ex.argtypes = [I, I, I, I, I, I, I]
+    lib.adc3_ea_setup_workspace_bytes_ex.restype = S
+    lib.adc3_ea_setup_ex.argtypes = [P, P, P, I, I, I, I, I, I, P, S, P, ctypes.POINTER(P)]
+    lib.adc3_ea_setup_ex.restype = I
+    lib.adc3_set_chunk_elems.argtypes = [LL]
+    lib.adc3_set_chunk_elems.restype = LL
+    lib.adc3_ladder_workspace_bytes.argtypes = [I, I, I, I]
+    lib.adc3_ladder_workspace_bytes.restype = S
+    lib.adc3_ladder_apply.argtypes = [P, P, P, I, I, I, I, P, S, P]
+    lib.adc3_ladder_apply.restype = I
     lib.adc3_ctx_destroy.argtypes = [P]
     lib.adc3_ctx_destroy.restype = None
     lib.adc3_ea_dim.argtypes = [P]
@@ -233,25 +245,52 @@ def adc3_ea_solve_batched(instances, opts=None, nstreams=0, workspace=None):
     return out_r, out_p, list(sts), st
 
 
-def adc3_ea_setup_workspace_bytes(nocc, nvir, naux, level, nroots=0, precision=0):
-    return load().adc3_ea_setup_workspace_bytes(nocc, nvir, naux, level, nroots, precision)
+def adc3_ea_setup_workspace_bytes(nocc, nvir, naux, level, nroots=0, precision=0, ladder=0):
+    return load().adc3_ea_setup_workspace_bytes_ex(nocc, nvir, naux, level, nroots, precision, ladder)
+
+
+def adc3_set_chunk_elems(n):
+    """Set (n > 0) or query (n <= 0) the element budget of one chunk of the large setup tensors."""
+    return load().adc3_set_chunk_elems(int(n))
+
+
+def adc3_ladder_workspace_bytes(nvir, naux, nrows, precision=0):
+    return load().adc3_ladder_workspace_bytes(nvir, naux, nrows, precision)
+
+
+def adc3_ladder_apply(Bvv, Z, precision=0, out=None, workspace=None, workspace_bytes=None):
+    """C[m] = sum_Q B^Q Z[m] B^Q (the ladder term from the DF factor), Bvv [X][v][v], Z [M][v][v] FP64 device.
+    workspace_bytes (default: one chunk of all auxiliary functions) sets the chunking."""
+    import torch
+    X, v = int(Bvv.shape[0]), int(Bvv.shape[1])
+    M = int(Z.shape[0])
+    if out is None:
+        out = torch.empty_like(Z)
+    if workspace is None:
+        if workspace_bytes is None:
+            eb = 8 if precision == 0 else 4 if precision == 1 else 2
+            workspace_bytes = adc3_ladder_workspace_bytes(v, X, M, precision) + (max(X, 1) - 1) * M * v * v * eb + 512
+        workspace = _workspace(workspace_bytes)
+    _check(load().adc3_ladder_apply(_ptr(Bvv), _ptr(Z), _ptr(out), v, X, M, precision,
+                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream()))
+    return out
 
 
 class Context:
     """Secular-matrix context (adc3_ea_setup ... adc3_ctx_destroy)."""
 
-    def __init__(self, eps_occ, eps_vir, B, level, nroots=8, precision=0):
+    def __init__(self, eps_occ, eps_vir, B, level, nroots=8, precision=0, ladder=0):
         lib = load()
         self.nocc, self.nvir, self.naux = int(eps_occ.numel()), int(eps_vir.numel()), int(B.shape[0])
         self.level = level
         self.precision = precision
         self.workspace = _workspace(adc3_ea_setup_workspace_bytes(self.nocc, self.nvir, self.naux, level, nroots,
-                                                                  precision))
+                                                                  precision, ladder))
         h = ctypes.c_void_p()
-        _check(lib.adc3_ea_setup(_ptr(eps_occ), _ptr(eps_vir), _ptr(B), self.nocc, self.nvir, self.naux, level,
-                                 precision,
-                                 ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(), _stream(),
-                                 ctypes.byref(h)))
+        _check(lib.adc3_ea_setup_ex(_ptr(eps_occ), _ptr(eps_vir), _ptr(B), self.nocc, self.nvir, self.naux, level,
+                                    precision, ladder,
+                                    ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(), _stream(),
+                                    ctypes.byref(h)))
         self.handle = h
         self.N = lib.adc3_ea_dim(h)
 

@@ -26,6 +26,7 @@
 #include "../../include/adc3ea.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -93,7 +94,8 @@ struct Ctx {
     // eigendecomposition of M11 for the block preconditioner (computed on first use)
     double *m11_Q = nullptr, *m11_w = nullptr, *m11_tmp = nullptr;
     bool m11_eig = false;
-    double *G = nullptr;      // ladder (ac|bd) as [(ab),(cd)], level 3
+    double *G = nullptr;      // ladder (ac|bd) as [(ab),(cd)], level 3 (stored form)
+    bool df = false;          // ladder assembled from Bvv in every application instead of stored
     double *P1 = nullptr;     // (ij|bd) as [i][b][j][d], level 3
     double *P2 = nullptr;     // (ij|ad) as [i][a][j][d], level 3
     double *zb = nullptr, *xb = nullptr, *xtb = nullptr, *sdb = nullptr, *sb = nullptr;
@@ -101,6 +103,7 @@ struct Ctx {
     // reduced-precision copies (precision 1: FP32 ladder and coupling; 2: BF16 ladder, FP32 coupling)
     int prec = 0;
     void* Glo = nullptr;
+    void* Bvvlo = nullptr;  // reduced-precision Bvv for the assembled ladder
     void* zlo = nullptr;  // reduced-precision copy of the ladder's input rows
     float* Uz32 = nullptr;
     // learned preconditioner: weights (caller's device memory) and the BF16 W2 copy
@@ -119,6 +122,19 @@ struct Ctx {
 };
 
 static double* take(Arena& ws, long long n) { return ws.take<double>((size_t)std::max<long long>(n, 1)); }
+
+// The ladder is assembled from Bvv in each application (instead of stored as the v^4 matrix) when the
+// stored matrix would not leave room for the rest: above 96 GB in FP64 (v > 331).
+static bool ladder_df_auto(int v) { return (double)v * v * (double)v * v * 8.0 > 96e9; }
+// Element budget of one chunk of the large setup tensors (o*na*v^2 per tensor of the coupling build);
+// the assembled ladder's intermediate gets twice this.
+static std::atomic<long long> g_chunk_elems{1LL << 29};
+// Elements of the assembled ladder's intermediate for M rows: all X auxiliary functions at once when
+// that fits the budget, else chunks of them (at least one).
+static long long df_v_elems(int M, int v, int X) {
+    const long long per = (long long)M * v * v;
+    return std::max<long long>(1, std::min<long long>((long long)std::max(X, 1) * per, std::max<long long>(per, 2 * g_chunk_elems.load())));
+}
 static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, hipStream_t s, int prec);
 static size_t sigma_region_bytes(Ctx* c);
 
@@ -130,10 +146,12 @@ static void add_sym(double* M, double* P, int v, double a, hipStream_t s) {
 
 // Build the context from DF blocks (copied in).  Temporaries are released on return.
 static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const double* Boo_in, const double* Bov_in,
-                      const double* Bvv_in, int o, int v, int X, int level, hipStream_t s, int prec = 0) {
+                      const double* Bvv_in, int o, int v, int X, int level, hipStream_t s, int prec = 0,
+                      bool df = false) {
     ProfScope prof(PROF_SETUP, s, 0.0, 0.0);
     Ctx* c = new Ctx();
     c->o = o; c->v = v; c->X = X; c->level = level; c->prec = prec;
+    c->df = df && level >= 3;
     c->N = v + (long long)o * v * v;
     const long long oo = (long long)o * o, ov = (long long)o * v, vv = (long long)v * v;
     c->eo = take(ws, o); c->ev = take(ws, v);
@@ -166,8 +184,10 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     if (prec > 0) {
         c->Uz32 = ws.take<float>((size_t)std::max<long long>(v * (long long)o * vv, 1));
         if (level >= 3) {
-            if (prec == 1) c->Glo = ws.take<float>((size_t)(vv * vv));
-            else c->Glo = ws.take<unsigned short>((size_t)(vv * vv));
+            const long long ng = c->df ? std::max<long long>((long long)X * vv, 1) : vv * vv;
+            void*& lo = c->df ? c->Bvvlo : c->Glo;
+            if (prec == 1) lo = ws.take<float>((size_t)ng);
+            else lo = ws.take<unsigned short>((size_t)ng);
             c->zlo = ws.take<float>((size_t)(NVMAX * (long long)o * vv));
         }
     }
@@ -199,37 +219,79 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
         k_fill(c->M11, vv, 0.0, s);
         add_sym(c->M11, P, v, -1.0, s);
         k_add_diag(c->M11, ev, v, s);
-        // coupling U_D[a][b][c][i], first order (ab|ic)
-        double* Ud = take(ws, vv * ov);
-        ein(ws, "Qab,Qic->abci", 1.0, TV(Bvv, {X, v, v}), TV(Bov, {X, o, v}), 0.0, Ud, s);
         if (level >= 3) {
-            TV tT(T, {o, o, v, v}), tT2(Tt2, {o, o, v, v});
-            double* ooov = take(ws, oo * ov);
-            ein(ws, "Qij,Qka->ijka", 1.0, TV(Boo, {X, o, o}), TV(Bov, {X, o, v}), 0.0, ooov, s);
-            // coupling, second order
-            ein(ws, "klbc,ilka->abci", 1.0, tT, TV(ooov, {o, o, o, v}), 1.0, Ud, s);
-            double* ovvv = take(ws, ov * vv);
-            ein(ws, "Qka,Qcd->kacd", 1.0, TV(Bov, {X, o, v}), TV(Bvv, {X, v, v}), 0.0, ovvv, s);
-            TV tovvv(ovvv, {o, v, v, v});
-            ein(ws, "kibd,kacd->abci", -1.0, tT, tovvv, 1.0, Ud, s);
-            ein(ws, "ikcd,kdab->abci", 1.0, tT2, tovvv, 1.0, Ud, s);
-            ein(ws, "ikcd,kabd->abci", -1.0, tT, tovvv, 1.0, Ud, s);
             // permuted integrals for the particle-hole sigma terms
             int d_oovv[4] = {o, o, v, v};
             int p1[4] = {0, 2, 1, 3};  // [i][j][b][d] -> [i][b][j][d]
             k_permute4(c->P1, c->oovv, d_oovv, p1, 1.0, 0.0, s);
             k_permute4(c->P2, c->oovv, d_oovv, p1, 1.0, 0.0, s);  // same layout, read as [i][a][j][d]
         }
-        // U_z[a][i][b][c] = S + sqrt3 A over (b,c) of U_D[a][b][c][i]
-        double* Up = take(ws, vv * ov);
-        int d[4] = {v, v, v, o}, pm[4] = {0, 3, 1, 2};
-        k_permute4(Up, Ud, d, pm, 1.0, 0.0, s);
+        double* ooov = nullptr;
+        if (level >= 3) {
+            ooov = take(ws, oo * ov);
+            ein(ws, "Qij,Qka->ijka", 1.0, TV(Boo, {X, o, o}), TV(Bov, {X, o, v}), 0.0, ooov, s);
+        }
+        // U_D[a][b][c][i] (first order (ab|ic), second order below) and U_z[a][i][b][c] = S + sqrt3 A over
+        // (b,c), in chunks of the first virtual index a when the o v^3 tensors would crowd HBM (each
+        // chunk holds about six tensors of o*na*v^2 elements)
+        const int na = (int)std::max<long long>(1, std::min<long long>(v, g_chunk_elems.load() / std::max<long long>(o * vv, 1)));
+        double *Bvc = nullptr, *Boc = nullptr, *ooc = nullptr;
+        if (na < v) {
+            Bvc = take(ws, (long long)X * na * v);
+            if (level >= 3) {
+                Boc = take(ws, (long long)X * o * na);
+                ooc = take(ws, oo * o * na);
+            }
+        }
         k_fill(c->Uz, vv * ov, 0.0, s);
-        k_d_to_z_add(c->Uz, Up, (long long)v * o, v, s);
+        for (int a0 = 0; a0 < v; a0 += na) {
+            const int nc = std::min(na, v - a0);
+            const size_t mchunk = ws.mark();
+            const long long E = (long long)nc * v * v * o;
+            // the chunk's slices of Bvv [X][a][b] and Bov [X][k][a]
+            const double* Bvv_a = Bvv;
+            if (na < v) {
+                k_copy2d(Bvc, (long long)nc * v, Bvv + (long long)a0 * v, vv, X, (long long)nc * v, 1.0, 0.0, s);
+                Bvv_a = Bvc;
+            }
+            double* Ud = take(ws, E);
+            ein(ws, "Qab,Qic->abci", 1.0, TV(Bvv_a, {X, nc, v}), TV(Bov, {X, o, v}), 0.0, Ud, s);
+            if (level >= 3) {
+                TV tT(T, {o, o, v, v}), tT2(Tt2, {o, o, v, v});
+                const double *ooov_a = ooov, *Bov_a = Bov;
+                if (na < v) {
+                    k_copy2d(ooc, nc, ooov + a0, v, oo * o, nc, 1.0, 0.0, s);
+                    k_copy2d(Boc, nc, Bov + a0, v, (long long)X * o, nc, 1.0, 0.0, s);
+                    ooov_a = ooc;
+                    Bov_a = Boc;
+                }
+                // coupling, second order
+                ein(ws, "klbc,ilka->abci", 1.0, tT, TV(ooov_a, {o, o, o, nc}), 1.0, Ud, s);
+                // (ka|cd) for a in the chunk: [k][a][c][d]
+                double* ovvv1 = take(ws, E);
+                ein(ws, "Qka,Qcd->kacd", 1.0, TV(Bov_a, {X, o, nc}), TV(Bvv, {X, v, v}), 0.0, ovvv1, s);
+                TV t1(ovvv1, {o, nc, v, v});
+                ein(ws, "kibd,kacd->abci", -1.0, tT, t1, 1.0, Ud, s);
+                // (kd|ab) for a in the chunk: [k][d][a][b] (the same tensor when there is one chunk)
+                const double* ovvv2 = ovvv1;
+                if (na < v) {
+                    double* t = take(ws, E);
+                    ein(ws, "Qkd,Qab->kdab", 1.0, TV(Bov, {X, o, v}), TV(Bvv_a, {X, nc, v}), 0.0, t, s);
+                    ovvv2 = t;
+                }
+                ein(ws, "ikcd,kdab->abci", 1.0, tT2, TV(ovvv2, {o, v, nc, v}), 1.0, Ud, s);
+                ein(ws, "ikcd,kabd->abci", -1.0, tT, t1, 1.0, Ud, s);
+            }
+            double* Up = take(ws, E);
+            int d[4] = {nc, v, v, o}, pm[4] = {0, 3, 1, 2};
+            k_permute4(Up, Ud, d, pm, 1.0, 0.0, s);
+            k_d_to_z_add(c->Uz + (long long)a0 * o * vv, Up, (long long)nc * o, v, s);
+            ws.release(mchunk);
+        }
     }
     ws.release(mark0);
     if (level >= 3) {
-        c->G = take(ws, vv * vv);  // kept with the context
+        if (!c->df) c->G = take(ws, vv * vv);  // kept with the context
         const size_t mark1 = ws.mark();
         {
             // phase B: G, then everything of M11 through third order that needs it
@@ -238,7 +300,7 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             k_comb_t(Tt2, T, oo, v, 2.0, -1.0, s);
             double* P = take(ws, vv);
             // ladder matrix G[(ab),(cd)] = (ac|bd) = sum_Q B^Q_ac B^Q_bd: batch over (a,b)
-            {
+            if (!c->df) {
                 Gemm g;
                 g.M = v; g.N = v; g.K = X;
                 g.A = Bvv; g.sAm = 1; g.sAk = vv;  // A(c,Q) = Bvv[Q][a][c], batch offset a*v
@@ -260,7 +322,13 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             ein(ws, "Qij,Qka->ijka", 1.0, TV(Boo, {X, o, o}), TV(Bov, {X, o, v}), 0.0, ooov, s);
             // second-order doubles residual Y (alpha-beta block)
             double* L = take(ws, oo * vv);
-            gemm_rm((int)oo, (int)vv, (int)vv, 1.0, T, vv, false, c->G, vv, false, 0.0, L, vv, s);
+            if (c->df) {
+                const long long ve = df_v_elems((int)oo, v, X);
+                double* Vt = take(ws, ve);
+                df_ladder(0, (int)oo, v, X, Bvv, T, L, false, Vt, ve, s);
+            } else {
+                gemm_rm((int)oo, (int)vv, (int)vv, 1.0, T, vv, false, c->G, vv, false, 0.0, L, vv, s);
+            }
             double* Y = take(ws, oo * vv);
             k_copy(Y, L, oo * vv, s);
             TV tT(T, {o, o, v, v}), tT2(Tt2, {o, o, v, v}), tovov(c->ovov, {o, v, o, v}), toovv(c->oovv, {o, o, v, v});
@@ -344,7 +412,8 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     k_diag_adc(c->diag, c->M11, eo, ev, Bvv, c->oovv, c->ovov, o, v, X, level, s);
     if (prec > 0) {
         k_to_lowp(c->Uz32, c->Uz, v * (long long)o * vv, 1, s);
-        if (level >= 3) k_to_lowp(c->Glo, c->G, vv * vv, prec, s);
+        if (level >= 3 && c->df) k_to_lowp(c->Bvvlo, c->Bvv, (long long)X * vv, prec, s);
+        else if (level >= 3) k_to_lowp(c->Glo, c->G, vv * vv, prec, s);
     }
     c->ws = ws;  // snapshot (base/cap/used) for later temporaries
     return c;
@@ -382,7 +451,24 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
             double* zb = c->zb;
             k_copy2d(zb, ovv, rr + v, N, nv, ovv, 1.0, 0.0, s);
             // ladder: sum_cd (ac|bd) z_cd  (G symmetric)
-            if (prec > 0) {
+            if (c->df) {
+                // assembled from Bvv: 4 X M v^3 flops; the intermediate is written and read once
+                const int M = nv * o, X = c->X;
+                const long long ve = df_v_elems(M, v, X);
+                const double eb = prec == 0 ? 8.0 : prec == 1 ? 4.0 : 2.0;
+                const double fl = 4.0 * X * (double)M * v * (double)vv;
+                const double by = eb * (2.0 * X * (double)M * vv + (double)X * vv + M * (double)vv) + 8.0 * M * (double)vv;
+                const double pk = prec == 0 ? PEAK_FP64_MFMA : prec == 1 ? PEAK_FP32_MFMA : PEAK_BF16_MFMA;
+                ProfScope p(prec > 0 ? PROF_LADDER_LP : PROF_LADDER, s, fl, by, 1e3 * std::max(fl / pk, by / PEAK_HBM));
+                if (prec > 0) {
+                    void* V = prec == 1 ? (void*)ws.take<float>((size_t)ve) : (void*)ws.take<unsigned short>((size_t)ve);
+                    k_to_lowp(c->zlo, zb, (long long)M * vv, prec, s);
+                    df_ladder(prec, M, v, X, c->Bvvlo, c->zlo, c->sb, false, V, ve, s);
+                } else {
+                    double* V = take(ws, ve);
+                    df_ladder(0, M, v, X, c->Bvv, zb, c->sb, false, V, ve, s);
+                }
+            } else if (prec > 0) {
                 const double fl = 2.0 * nv * o * (double)vv * vv;
                 const double by = (prec == 1 ? 4.0 : 2.0) * (double)vv * vv + 16.0 * nv * o * vv;
                 ProfScope p(PROF_LADDER_LP, s, fl, by,
@@ -957,9 +1043,12 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     // diagonal step); ADC(3) solves take Jacobi, Olsen, or the learned step
     const int pm2 = (op.precond == 0 || op.precond == 2) ? op.precond : 3;
     const int pm3 = op.precond == 2 ? 2 : 0;
+    // one ladder form for every ADC(3) context of the solve, chosen from the canonical size (so the
+    // workspace plan holds for any truncation)
+    const bool df = op.ladder == 2 || (op.ladder == 0 && ladder_df_auto(v));
     if (!(fno > 0) && !(naf > 0)) {
         const size_t mark = ws.mark();
-        Ctx* c = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, level, s, op.precision);
+        Ctx* c = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, level, s, op.precision, df);
         c->mlp_w = op.mlp_weights;
         c->graphs = op.sigma_graphs != 0;
         DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
@@ -980,16 +1069,32 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         ws.release(mark);
         return out;
     }
-    // steps 2-3: canonical MP2 density and canonical ADC(2) roots
+    // steps 2-3: canonical MP2 density and canonical ADC(2) roots; the canonical context is released
+    // once the state-specific densities D^SS(k) = D^MP2 + D^EA(k) (steps 4a-4b) of all roots are formed
     const size_t mark0 = ws.mark();
-    Ctx* c0 = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, 2, s, op.precision);
-    c0->graphs = op.sigma_graphs != 0;
-    double* Y2 = take(ws, (long long)nroots * c0->N);
-    DavResult r2 = davidson_impl(c0, ws, nroots, conv, op.max_iter, op.max_subspace, Y2, s, op.precision, false,
-                                 nullptr, nullptr, 0, pm2);
+    const long long N0 = v + (long long)o * v * v, vv0 = (long long)v * v;
+    double* Y2 = take(ws, (long long)nroots * N0);
+    double* Dss = take(ws, (long long)nroots * vv0);
+    DavResult r2;
+    int sig0 = 0;
+    {
+        const size_t mc0 = ws.mark();
+        Ctx* c0 = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, 2, s, op.precision);
+        c0->graphs = op.sigma_graphs != 0;
+        r2 = davidson_impl(c0, ws, nroots, conv, op.max_iter, op.max_subspace, Y2, s, op.precision, false, nullptr,
+                           nullptr, 0, pm2);
+        GemmScratch gscr(ws, GEMM_SCRATCH);
+        for (int k = 0; k < nroots; ++k) {
+            double* D = Dss + (long long)k * vv0;
+            ea_density(ws, c0, Y2 + (long long)k * N0, D, s);          // 4a
+            k_axpby(D, c0->Dmp2, vv0, 1.0, 1.0, s);                       // 4b
+        }
+        sig0 = (int)c0->sigma_count;
+        delete c0;
+        ws.release(mc0);
+    }
     out.all_conv = out.all_conv && r2.converged;
     VLOG("canonical ADC(2): %d roots, %d iterations, lowest %.10f", nroots, r2.iters, r2.w[0]);
-    const int sig0 = (int)c0->sigma_count;
     NafCache naf_cache;
     if (naf > 0) {
         naf_cache.N = take(ws, (long long)X * X);
@@ -1001,9 +1106,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         auto& R = out.rep[k];
         GemmScratch gscr(ws, GEMM_SCRATCH);
         R.omega_adc2_can = r2.w[k];
-        double* D = take(ws, (long long)v * v);
-        ea_density(ws, c0, Y2 + (long long)k * c0->N, D, s);          // 4a
-        k_axpby(D, c0->Dmp2, (long long)v * v, 1.0, 1.0, s);          // 4b
+        const double* D = Dss + (long long)k * vv0;
         double* U = take(ws, (long long)v * v);
         double* enew = take(ws, v);
         int vk = natural_orbitals(ws, D, ev, v, fno, U, enew, s);     // 4c-4d
@@ -1027,7 +1130,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             const size_t mt = ws.mark();
             double* tmp = take(ws, (long long)o * v * vk);
             for (int q = 0; q < nroots; ++q) {
-                const double* yq = Y2 + (long long)q * c0->N;
+                const double* yq = Y2 + (long long)q * N0;
                 double* cq = carried + (long long)q * Nk;
                 gemm_rm(1, vk, v, 1.0, yq, v, false, U, vk, false, 0.0, cq, vk, s);
                 gemm_rm(o * v, vk, v, 1.0, yq + v, v, false, U, vk, false, 0.0, tmp, vk, s);
@@ -1068,7 +1171,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         }
         {
             const size_t m3 = ws.mark();
-            Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s, op.precision);
+            Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s, op.precision, df);
             c3->mlp_w = op.mlp_weights;
             c3->graphs = op.sigma_graphs != 0;
             // only roots 0..match of this basis are needed: the matched one and those below it
@@ -1093,7 +1196,6 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         R.omega = R.omega_uncorr + (op.fno_correction ? (R.omega_adc2_can - R.omega_adc2_fno) : 0.0);  // eq 30
         ws.release(mark);
     }
-    delete c0;
     ws.release(mark0);
     return out;
 }
@@ -1135,25 +1237,30 @@ void adc3_default_opts(adc3_opts* o) {
     o->precond = 3;
     o->mlp_weights = nullptr;
     o->sigma_graphs = 0;
+    o->ladder = 0;
 }
 
 const char* adc3_last_error(void) { return g_msg.c_str(); }
 
 static void check_dims(int nocc, int nvir, int naux) {
     if (nocc <= 0 || nvir <= 0 || naux < 0) fail(ADC3_EINVAL, "nocc and nvir must be > 0 and naux >= 0");
-    if ((long long)nvir * nvir * nvir * nvir > (1LL << 40)) fail(ADC3_EINVAL, "nvir too large for the stored ladder");
+    if (nvir > 1024) fail(ADC3_EINVAL, "nvir > 1024 is not supported");
 }
 
-size_t adc3_ea_setup_workspace_bytes(int nocc, int nvir, int naux, int level, int nroots, int precision) {
+size_t adc3_ea_setup_workspace_bytes_ex(int nocc, int nvir, int naux, int level, int nroots, int precision,
+                                        int ladder) {
     try {
         check_dims(nocc, nvir, naux);
         if (level != 2 && level != 3) return 0;
         if (precision < 0 || precision > 2) return 0;
+        if (ladder < 0 || ladder > 2) return 0;
+        const bool df = ladder == 2 || (ladder == 0 && ladder_df_auto(nvir));
         Arena ws;
         g_dry = true;
         const long long n = nocc + nvir;
         take(ws, (long long)naux * n * n);  // split blocks of the public setup
-        Ctx* c = build_ctx(ws, nullptr, nullptr, nullptr, nullptr, nullptr, nocc, nvir, naux, level, nullptr, precision);
+        Ctx* c = build_ctx(ws, nullptr, nullptr, nullptr, nullptr, nullptr, nocc, nvir, naux, level, nullptr, precision,
+                           df);
         {
             Arena w2 = ws;
             take(w2, 2LL * NVMAX * c->N);  // dense-matrix hook
@@ -1175,14 +1282,21 @@ size_t adc3_ea_setup_workspace_bytes(int nocc, int nvir, int naux, int level, in
     }
 }
 
-int adc3_ea_setup(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir, int naux,
-                  int level, int precision, void* workspace, size_t ws_bytes, hipStream_t stream, adc3_ctx** ctx_out) {
+size_t adc3_ea_setup_workspace_bytes(int nocc, int nvir, int naux, int level, int nroots, int precision) {
+    return adc3_ea_setup_workspace_bytes_ex(nocc, nvir, naux, level, nroots, precision, 0);
+}
+
+int adc3_ea_setup_ex(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir, int naux,
+                     int level, int precision, int ladder, void* workspace, size_t ws_bytes, hipStream_t stream,
+                     adc3_ctx** ctx_out) {
     API_BEGIN
     if (!ctx_out) fail(ADC3_EINVAL, "ctx_out is NULL");
     *ctx_out = nullptr;
     check_dims(nocc, nvir, naux);
     if (level != 2 && level != 3) fail(ADC3_EINVAL, "level must be 2 or 3");
     if (precision < 0 || precision > 2) fail(ADC3_EINVAL, "precision must be 0, 1 or 2");
+    if (ladder < 0 || ladder > 2) fail(ADC3_EINVAL, "ladder must be 0 (auto), 1 (stored) or 2 (assembled)");
+    const bool df = ladder == 2 || (ladder == 0 && ladder_df_auto(nvir));
     if (!eps_occ || !eps_vir || (!B && naux > 0) || !workspace) fail(ADC3_EINVAL, "NULL pointer argument");
     Arena ws;
     ws.base = (char*)workspace;
@@ -1195,13 +1309,19 @@ int adc3_ea_setup(const double* eps_occ, const double* eps_vir, const double* B,
     double* Bvv = take(ws, (long long)naux * nvir * nvir);
     k_split_B(B, naux, nocc, nvir, Boo, Bov, Bvv, stream);
     (void)n;
-    Ctx* c = build_ctx(ws, eps_occ, eps_vir, Boo, Bov, Bvv, nocc, nvir, naux, level, stream, precision);
+    Ctx* c = build_ctx(ws, eps_occ, eps_vir, Boo, Bov, Bvv, nocc, nvir, naux, level, stream, precision, df);
     (void)mark0;
     HIPCHK(hipStreamSynchronize(stream));
     adc3_ctx* h = new adc3_ctx{c};
     *ctx_out = h;
     return ADC3_OK;
     API_END
+}
+
+int adc3_ea_setup(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir, int naux,
+                  int level, int precision, void* workspace, size_t ws_bytes, hipStream_t stream, adc3_ctx** ctx_out) {
+    return adc3_ea_setup_ex(eps_occ, eps_vir, B, nocc, nvir, naux, level, precision, 0, workspace, ws_bytes, stream,
+                            ctx_out);
 }
 
 void adc3_ctx_destroy(adc3_ctx* ctx) {
@@ -1296,6 +1416,58 @@ int adc3_ea_intermediate(adc3_ctx* ctx, int which, double* out, long long* count
     API_END
 }
 
+long long adc3_set_chunk_elems(long long n) {
+    const long long prev = g_chunk_elems.load();
+    if (n > 0) g_chunk_elems.store(n);
+    return prev;
+}
+
+size_t adc3_ladder_workspace_bytes(int nvir, int naux, int nrows, int precision) {
+    if (nvir <= 0 || naux < 0 || nrows <= 0 || precision < 0 || precision > 2) return 0;
+    const size_t eb = precision == 0 ? 8 : precision == 1 ? 4 : 2;
+    const size_t vv = (size_t)nvir * nvir;
+    const size_t copies = precision == 0 ? 0 : (((size_t)naux * vv * eb + 255) & ~size_t(255)) + (((size_t)nrows * vv * eb + 255) & ~size_t(255));
+    return copies + (size_t)nrows * vv * eb;
+}
+
+int adc3_ladder_apply(const double* Bvv, const double* Z, double* C, int nvir, int naux, int nrows, int precision,
+                      void* workspace, size_t ws_bytes, hipStream_t stream) {
+    API_BEGIN
+    if (nvir <= 0 || naux < 0 || nrows <= 0) fail(ADC3_EINVAL, "nvir and nrows must be > 0 and naux >= 0");
+    if (nvir > 1024 || nrows > 65535) fail(ADC3_EINVAL, "nvir > 1024 or nrows > 65535 is not supported");
+    if (precision < 0 || precision > 2) fail(ADC3_EINVAL, "precision must be 0, 1 or 2");
+    if (!Bvv || !Z || !C || !workspace) fail(ADC3_EINVAL, "NULL pointer argument");
+    const size_t need = adc3_ladder_workspace_bytes(nvir, naux, nrows, precision);
+    if (ws_bytes < need) fail(ADC3_ENOMEM, "workspace too small: need at least " + std::to_string(need) + " bytes");
+    Arena ws;
+    ws.base = (char*)workspace;
+    ws.cap = ws_bytes;
+    const long long vv = (long long)nvir * nvir;
+    const void *Bp = Bvv, *Zp = Z;
+    if (precision > 0) {
+        void* Bl = precision == 1 ? (void*)ws.take<float>((size_t)std::max<long long>((long long)naux * vv, 1))
+                                  : (void*)ws.take<unsigned short>((size_t)std::max<long long>((long long)naux * vv, 1));
+        void* Zl = precision == 1 ? (void*)ws.take<float>((size_t)(nrows * vv))
+                                  : (void*)ws.take<unsigned short>((size_t)(nrows * vv));
+        k_to_lowp(Bl, Bvv, (long long)naux * vv, precision, stream);
+        k_to_lowp(Zl, Z, nrows * vv, precision, stream);
+        Bp = Bl;
+        Zp = Zl;
+    }
+    const size_t eb = precision == 0 ? 8 : precision == 1 ? 4 : 2;
+    const size_t off = (ws.used + 255) & ~size_t(255);
+    const long long ve = (long long)((ws_bytes - std::min(ws_bytes, off)) / eb);
+    if (ve < nrows * vv) fail(ADC3_ENOMEM, "workspace too small for one auxiliary function of the intermediate");
+    void* V = ws.base + off;
+    const double fl = 4.0 * naux * (double)nrows * nvir * (double)vv;
+    const double by = eb * (2.0 * naux * (double)nrows * vv + (double)naux * vv + nrows * (double)vv) + 8.0 * nrows * (double)vv;
+    const double pk = precision == 0 ? PEAK_FP64_MFMA : precision == 1 ? PEAK_FP32_MFMA : PEAK_BF16_MFMA;
+    ProfScope p(precision > 0 ? PROF_LADDER_LP : PROF_LADDER, stream, fl, by, 1e3 * std::max(fl / pk, by / PEAK_HBM));
+    df_ladder(precision, nrows, nvir, naux, Bp, Zp, C, false, V, ve, stream);
+    return ADC3_OK;
+    API_END
+}
+
 }  // extern "C"
 
 static void validate_inputs(const double* eo, const double* ev, const double* B, int o, int v, int X, hipStream_t s,
@@ -1334,6 +1506,7 @@ static adc3_opts resolve_opts(const adc3_opts* opts) {
     if (o.precond < 0 || o.precond > 3)
         fail(ADC3_EUNSUP, "opts.precond must be 0 (Jacobi), 1 (learned), 2 (Olsen) or 3 (exact 1p block)");
     if (o.precond == 1 && !o.mlp_weights) fail(ADC3_EINVAL, "opts.precond = 1 needs opts.mlp_weights");
+    if (o.ladder < 0 || o.ladder > 2) fail(ADC3_EINVAL, "opts.ladder must be 0 (auto), 1 (stored) or 2 (assembled)");
     return o;
 }
 

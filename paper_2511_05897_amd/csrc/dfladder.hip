@@ -1,0 +1,326 @@
+// The ladder term assembled from the DF factor, without the stored four-virtual matrix.
+//
+//   C_m = sum_Q B^Q Z_m B^Q,   i.e.  C_m[a][b] = sum_cd (ac|bd) Z_m[c][d],  (ac|bd) = sum_Q B^Q_ac B^Q_bd (eq 25)
+//
+// for rows m < M ((vector, occupied) pairs of a sigma pass, or (i,j) amplitude pairs), with
+// B^Q = Bvv[Q] the symmetric v x v virtual block of the factor.  Per chunk of q auxiliary
+// functions, two matrix-core contractions:
+//   1. V[m][a][Qi][e] = sum_c B^Q[a][c] Z_m[c][e]              batched over (Qi, m): q*M products v x v x v
+//   2. C[(m,a)][b]   += sum_(Qi,e) V[(m,a)][(Qi,e)] B^Q[e][b]  one GEMM with K = q*v
+// 4 X M v^3 flops in all, against 2 M v^4 for the stored matrix: the cheaper form once X < v/2,
+// and the only one once v^4 no longer fits in HBM (v = 600: 1 TB in FP64).
+//
+// One tile kernel serves both steps in three operand precisions (FP64 16x16x4 MFMA with FP64
+// accumulation; FP32 16x16x4 and BF16 16x16x32 MFMA with FP32 accumulation): 4 waves side by
+// side over 128 columns, TM blocks of 16 rows, double-buffered LDS slabs, 16-byte loads where
+// the shape allows (scalar loads otherwise), and two levels of batch offsets.
+//
+// MFMA layouts (lane l of a wave64):
+//   f64 16x16x4 / f32 16x16x4: A frag A[l%16][l/16], B frag B[l/16][l%16]
+//   bf16 16x16x32:             A frag A[l%16][8(l/16) .. +8], B frag B[8(l/16) .. +8][l%16]
+//   accumulator element r: f64 row l/16 + 4r; FP32-output instructions row 4(l/16) + r; column l%16.
+#include "internal.h"
+#include <algorithm>
+
+namespace adc3 {
+
+namespace {
+typedef double d2x __attribute__((ext_vector_type(2)));
+typedef double d4x __attribute__((ext_vector_type(4)));
+typedef float f4x __attribute__((ext_vector_type(4)));
+typedef __bf16 h8x __attribute__((ext_vector_type(8)));
+
+constexpr int DNT = 256, DBN = 128, DLTN = 2;  // 4 waves x 2 column blocks of 16
+
+struct DflArgs {
+    const void* A; long long lda, bA0, bA1;  // A[m][k], row-major
+    const void* B; long long ldb, bB0, bB1;  // B[k][n], row-major
+    void* C; long long ldc, bC0, bC1;        // C[m][n]
+    long long m_off;                         // first row of this launch
+    int M, N, K, nb0;
+    int accumulate;  // 1: C += A B, 0: C = A B
+    int vec;         // 1: 16-byte loads (widths, strides and bases are multiples of the vector)
+};
+
+// per-precision element type, vector of 16 bytes, slab depth and accumulator
+template <int P> struct Prec;
+template <> struct Prec<0> { typedef double T; typedef d2x V; typedef d4x Acc; static constexpr int W = 2, BK = 16; };
+template <> struct Prec<1> { typedef float T; typedef f4x V; typedef f4x Acc; static constexpr int W = 4, BK = 32; };
+template <> struct Prec<2> { typedef __bf16 T; typedef h8x V; typedef f4x Acc; static constexpr int W = 8, BK = 64; };
+
+template <int TO> struct Out;
+template <> struct Out<0> { typedef double T; };
+template <> struct Out<1> { typedef float T; };
+template <> struct Out<2> { typedef __bf16 T; };
+
+template <int P, int TO, int TM>
+__global__ __launch_bounds__(DNT, 2) void dfl_kernel(DflArgs g) {
+    typedef typename Prec<P>::T T;
+    typedef typename Prec<P>::V VT;
+    typedef typename Prec<P>::Acc Acc;
+    typedef typename Out<TO>::T OT;
+    constexpr int W = Prec<P>::W, BK = Prec<P>::BK, BM = 16 * TM;
+    constexpr int PA = (BM * (BK / W) + DNT - 1) / DNT;  // A vectors per thread and slab
+    constexpr int PB = (BK * (DBN / W)) / DNT;             // B vectors per thread and slab
+    // FP64/FP32: A transposed [k][m], B [k][n];  BF16: A [m][k], B transposed [n][k]
+    constexpr int AR = (P == 2) ? BM : BK, AC = (P == 2) ? BK + 8 : BM + 1;
+    constexpr int BR = (P == 2) ? DBN : BK, BC = (P == 2) ? BK + 8 : DBN + 16 / (int)sizeof(T);
+    __shared__ __attribute__((aligned(16))) T As[2][AR][AC];
+    __shared__ __attribute__((aligned(16))) T Bs[2][BR][BC];
+
+    const int z = blockIdx.z, b0 = z % g.nb0, b1 = z / g.nb0;
+    const T* __restrict__ A = (const T*)g.A + b0 * g.bA0 + b1 * g.bA1;
+    const T* __restrict__ B = (const T*)g.B + b0 * g.bB0 + b1 * g.bB1;
+    OT* __restrict__ C = (OT*)g.C + b0 * g.bC0 + b1 * g.bC1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const long long m0 = g.m_off + (long long)blockIdx.y * BM, n0 = (long long)blockIdx.x * DBN;
+    const int K = g.K;
+
+    int arow[PA], akq[PA], bkr[PB], bnq[PB];
+#pragma unroll
+    for (int p = 0; p < PA; ++p) {
+        const int idx = tid + DNT * p;
+        arow[p] = idx < BM * (BK / W) ? idx / (BK / W) : -1;
+        akq[p] = idx % (BK / W);
+    }
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        const int idx = tid + DNT * p;
+        bkr[p] = idx / (DBN / W);
+        bnq[p] = idx % (DBN / W);
+    }
+    VT ra[PA], rb[PB];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p) {
+            const long long m = m0 + arow[p];
+            const int k = k0 + W * akq[p];
+            VT x;
+#pragma unroll
+            for (int e = 0; e < W; ++e) x[e] = (T)0.0f;
+            if (arow[p] >= 0 && m < g.M) {
+                const T* src = A + m * g.lda + k;
+                if (g.vec) {
+                    if (k < K) x = *(const VT*)src;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < W; ++e)
+                        if (k + e < K) x[e] = src[e];
+                }
+            }
+            ra[p] = x;
+        }
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
+            const int k = k0 + bkr[p];
+            const long long n = n0 + W * bnq[p];
+            VT x;
+#pragma unroll
+            for (int e = 0; e < W; ++e) x[e] = (T)0.0f;
+            if (k < K) {
+                const T* src = B + (long long)k * g.ldb + n;
+                if (g.vec) {
+                    if (n < g.N) x = *(const VT*)src;
+                } else {
+#pragma unroll
+                    for (int e = 0; e < W; ++e)
+                        if (n + e < g.N) x[e] = src[e];
+                }
+            }
+            rb[p] = x;
+        }
+    };
+    auto stash = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < PA; ++p)
+            if (arow[p] >= 0) {
+                if constexpr (P == 2) {
+                    *(VT*)&As[buf][arow[p]][W * akq[p]] = ra[p];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < W; ++e) As[buf][W * akq[p] + e][arow[p]] = ra[p][e];
+                }
+            }
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
+            if constexpr (P == 2) {
+#pragma unroll
+                for (int e = 0; e < W; ++e) Bs[buf][W * bnq[p] + e][bkr[p]] = rb[p][e];
+            } else {
+                *(VT*)&Bs[buf][bkr[p]][W * bnq[p]] = rb[p];
+            }
+        }
+    };
+
+    Acc acc[TM][DLTN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < DLTN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[i][j][r] = 0;
+    const int nslab = (K + BK - 1) / BK;
+    if (nslab > 0) {
+        fetch(0);
+        stash(0);
+    }
+    __syncthreads();
+    const int cb = wave * (16 * DLTN);
+    for (int s = 0; s < nslab; ++s) {
+        const int buf = s & 1;
+        if (s + 1 < nslab) fetch((s + 1) * BK);
+        if constexpr (P == 2) {
+#pragma unroll
+            for (int ks = 0; ks < BK / 32; ++ks) {
+                h8x bf[DLTN];
+#pragma unroll
+                for (int j = 0; j < DLTN; ++j) bf[j] = *(const h8x*)&Bs[buf][cb + 16 * j + lr][32 * ks + 8 * lk];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const h8x af = *(const h8x*)&As[buf][16 * i + lr][32 * ks + 8 * lk];
+#pragma unroll
+                    for (int j = 0; j < DLTN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[j], acc[i][j], 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += 4) {
+                T bf[DLTN];
+#pragma unroll
+                for (int j = 0; j < DLTN; ++j) bf[j] = Bs[buf][kk + lk][cb + 16 * j + lr];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const T af = As[buf][kk + lk][16 * i + lr];
+#pragma unroll
+                    for (int j = 0; j < DLTN; ++j) {
+                        if constexpr (P == 0)
+                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[j], acc[i][j], 0, 0, 0);
+                        else
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[j], acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if (s + 1 < nslab) stash(buf ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < DLTN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long row = m0 + 16 * i + (P == 0 ? lk + 4 * r : 4 * lk + r);
+                const long long col = n0 + cb + 16 * j + lr;
+                if (row < g.M && col < g.N) {
+                    OT* c = C + row * g.ldc + col;
+                    if constexpr (TO == 0) {
+                        const double x = (double)acc[i][j][r];
+                        *c = g.accumulate ? *c + x : x;
+                    } else {
+                        const float x = (float)acc[i][j][r];
+                        *c = (OT)(g.accumulate ? (float)*c + x : x);
+                    }
+                }
+            }
+}
+
+template <int P, int TO, int TM>
+void launch_tm(const DflArgs& a, int mtiles, int nbatch, hipStream_t s) {
+    dim3 grid((unsigned)((a.N + DBN - 1) / DBN), (unsigned)mtiles, (unsigned)nbatch);
+    hipLaunchKernelGGL((dfl_kernel<P, TO, TM>), grid, dim3(DNT), 0, s, a);
+}
+
+template <int P, int TO>
+void launch_p(const DflArgs& a, int tm, int mtiles, int nbatch, hipStream_t s) {
+    switch (tm) {
+        case 1: launch_tm<P, TO, 1>(a, mtiles, nbatch, s); break;
+        case 2: launch_tm<P, TO, 2>(a, mtiles, nbatch, s); break;
+        case 3: launch_tm<P, TO, 3>(a, mtiles, nbatch, s); break;
+        case 4: launch_tm<P, TO, 4>(a, mtiles, nbatch, s); break;
+        case 5: launch_tm<P, TO, 5>(a, mtiles, nbatch, s); break;
+        case 6: launch_tm<P, TO, 6>(a, mtiles, nbatch, s); break;
+        case 7: launch_tm<P, TO, 7>(a, mtiles, nbatch, s); break;
+        default: launch_tm<P, TO, 8>(a, mtiles, nbatch, s); break;
+    }
+}
+
+int elem_bytes(int p) { return p == 0 ? 8 : p == 1 ? 4 : 2; }
+
+// C = A B (or C += A B) over nbatch = nb0 * nb1 batches; out_prec selects C's type
+// (0 FP64, 1 FP32, 2 BF16; for P = 0 only 0).  Rows are cut into launches of at most
+// 65535 row tiles.
+void dfl_gemm(int P, int out_prec, DflArgs a, int nb1, hipStream_t s) {
+    if (a.M <= 0 || a.N <= 0) return;
+    const int nbatch = a.nb0 * nb1;
+    if (nbatch <= 0 || nbatch > 65535) fail(-1, "dfladder: batch count out of range");
+    const int W = 16 / elem_bytes(P);
+    const auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    a.vec = (a.K % W == 0 && a.N % W == 0 && a.lda % W == 0 && a.ldb % W == 0 && a.bA0 % W == 0 && a.bA1 % W == 0 &&
+             a.bB0 % W == 0 && a.bB1 % W == 0 && al(a.A) && al(a.B)) ? 1 : 0;
+    // rows: as few tiles as possible, each as short as M allows (<= 128 rows)
+    int mt = (int)std::min<long long>(((long long)a.M + 127) / 128, 65535);
+    const long long rows_per_launch = (long long)mt * 128;
+    for (long long r0 = 0; r0 < a.M; r0 += rows_per_launch) {
+        DflArgs b = a;
+        b.m_off = r0;
+        const long long rows = std::min<long long>(a.M - r0, rows_per_launch);
+        const int mtiles = (int)((rows + 127) / 128);
+        const int tm = (int)((rows + 16LL * mtiles - 1) / (16LL * mtiles));
+        b.M = (int)std::min<long long>(a.M, r0 + rows);  // rows below M handled by this launch
+        if (P == 0) launch_p<0, 0>(b, tm, mtiles, nbatch, s);
+        else if (P == 1 && out_prec == 0) launch_p<1, 0>(b, tm, mtiles, nbatch, s);
+        else if (P == 1) launch_p<1, 1>(b, tm, mtiles, nbatch, s);
+        else if (out_prec == 0) launch_p<2, 0>(b, tm, mtiles, nbatch, s);
+        else launch_p<2, 2>(b, tm, mtiles, nbatch, s);
+        LAUNCHCHK();
+    }
+}
+}  // namespace
+
+long long df_ladder_chunk(int M, int v, int X, long long v_elems) {
+    const long long per = (long long)M * v * v;
+    long long q = std::max<long long>(1, v_elems / std::max<long long>(per, 1));
+    q = std::min<long long>(q, X);
+    q = std::min<long long>(q, std::max(1, 65535 / std::max(M, 1)));
+    return std::max<long long>(q, 1);
+}
+
+void df_ladder(int prec, int M, int v, int X, const void* Bvv, const void* Z, double* C, bool accumulate, void* V,
+               long long v_elems, hipStream_t s) {
+    if (g_dry) return;
+    if (M <= 0 || v <= 0) return;
+    if (M > 65535) fail(-1, "dfladder: too many rows");
+    const long long vv = (long long)v * v;
+    if (X <= 0) {
+        if (!accumulate) k_fill(C, (long long)M * vv, 0.0, s);
+        return;
+    }
+    const long long q = df_ladder_chunk(M, v, X, v_elems);
+    if (q * M * vv > v_elems) fail(-1, "dfladder: intermediate buffer too small");
+    const int eb = elem_bytes(prec);
+    for (long long Q0 = 0; Q0 < X; Q0 += q) {
+        const int qn = (int)std::min<long long>(q, X - Q0);
+        const char* Bq = (const char*)Bvv + Q0 * vv * eb;
+        // step 1: V[m][a][Qi][e] = sum_c B^Q[a][c] Z_m[c][e]  (batch b0 = Qi, b1 = m)
+        DflArgs a1{};
+        a1.A = Bq; a1.lda = v; a1.bA0 = vv; a1.bA1 = 0;
+        a1.B = Z; a1.ldb = v; a1.bB0 = 0; a1.bB1 = vv;
+        a1.C = V; a1.ldc = (long long)qn * v; a1.bC0 = v; a1.bC1 = (long long)qn * vv;
+        a1.M = v; a1.N = v; a1.K = v; a1.nb0 = qn;
+        a1.accumulate = 0;
+        dfl_gemm(prec, prec, a1, M, s);
+        // step 2: C[(m,a)][b] (+)= sum_(Qi,e) V[(m,a)][(Qi,e)] B^Q[e][b]
+        DflArgs a2{};
+        a2.A = V; a2.lda = (long long)qn * v;
+        a2.B = Bq; a2.ldb = v;
+        a2.C = C; a2.ldc = v;
+        a2.M = (int)((long long)M * v); a2.N = v; a2.K = qn * v; a2.nb0 = 1;
+        a2.accumulate = (accumulate || Q0 > 0) ? 1 : 0;
+        dfl_gemm(prec, 0, a2, 1, s);
+    }
+}
+
+}  // namespace adc3
