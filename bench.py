@@ -39,6 +39,9 @@ def parse():
                     help="also compare the learned preconditioner with Jacobi at o=30 v=400 X=1200 (251 GB)")
     ap.add_argument("--batched", type=int, default=0,
                     help="also solve the first N instances of the ragged batched workload (seeds 100..; 0 = skip)")
+    ap.add_argument("--large-mixed", type=float, default=0.0,
+                    help="also run the FP64 / FP32 / BF16 Davidson study of the o=40 v=600 X=1800 workload "
+                         "with B scaled by this factor (about 12 minutes; 0 = skip)")
     ap.add_argument("--sigma-reps", type=int, default=10)
     ap.add_argument("--sigma-only", action="store_true",
                     help="profiling mode: only the isolated ADC(3) sigma builds plus a 2 GiB copy (counter calibration)")
@@ -233,6 +236,57 @@ def mixed_ladder_dominated(adc, d, torch, np):
     return out
 
 
+def large_mixed_study(adc, d, torch, np, scale):
+    """ADC(3) Davidson of the large mixed-precision workload (o=40, v=600, X=1800, seed 2, canonical basis,
+    5 roots, conv 1e-6), B scaled by `scale`, with FP64, FP32-operand and BF16-operand sigma (each
+    reduced-precision Davidson ends with an FP64 restart).  The ladder is assembled from the DF factor in
+    every application (the stored v^4 matrix would take 1 TB).  Context setup (FP64 in every mode) is
+    timed on its own; the FP64 and FP32 runs share one context."""
+    import synth
+    p, eo, ev, B = synth.preset("mixed-o40v600x1800", scale=scale)
+    tB = d(B)
+    del B
+    nroots, conv = p["nroots"], p["conv"]
+    out = {"shape": [p["nocc"], p["nvir"], p["naux"]], "seed": p["seed"], "scale": scale, "nroots": nroots,
+           "conv": conv, "ladder": "assembled from the DF factor"}
+    ref = None
+    for cprec, runs in ((1, (0, 1)), (2, (2,))):
+        t0 = time.perf_counter()
+        ctx = adc.Context(d(eo), d(ev), tB, 3, nroots=nroots, precision=cprec)
+        torch.cuda.synchronize()
+        out["setup_s_precision%d_context" % cprec] = time.perf_counter() - t0
+        print("large mixed: context (precision %d) built" % cprec, file=sys.stderr, flush=True)
+        for pr in runs:
+            tag = ("fp64", "fp32", "bf16")[pr]
+            kind = adc.PROF_LADDER if pr == 0 else adc.PROF_LADDER_LP
+            adc.adc3_profile_enable(True)
+            t1 = time.perf_counter()
+            w, _, rn, it, st = ctx.davidson(nroots, conv, precision=pr)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            lms, ln, lf, lb = adc.adc3_profile_query(kind)
+            lbound = adc.adc3_profile_query_bound(kind)
+            sig_ms, _, _, _ = adc.adc3_profile_query(adc.PROF_SIGMA)
+            adc.adc3_profile_enable(False)
+            if ref is None:
+                ref = w
+            peak = (78.6, 157.3, 2500.0)[pr]
+            ach = lf / (lms * 1e-3) / 1e12 if lms > 0 else 0.0
+            out[tag] = {"davidson_s": dt, "iterations": it, "status": st, "roots": [float(x) for x in w],
+                        "max_resnorm": float(np.max(rn)),
+                        "root_diff_vs_fp64_Eh": [float(x) for x in (w - ref)],
+                        "sigma_ms": sig_ms,
+                        "ladder": {"launches": ln, "total_ms": lms, "achieved_tflops": ach, "peak_tflops": peak,
+                                   "frac": ach / peak, "bound_time_frac": lbound / lms if lms > 0 else None}}
+            print("large mixed: %s Davidson %.1f s, %d iterations" % (tag, dt, it), file=sys.stderr, flush=True)
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    for tag in ("fp32", "bf16"):
+        out[tag]["speedup_vs_fp64"] = out["fp64"]["davidson_s"] / out[tag]["davidson_s"]
+    return out
+
+
 def cpu_baseline(shape, nvec):
     """The FP64 oracle's sigma build on the host: nvec ADC(3) sigma vectors on a
     synthetic instance of the truncated-basis shape (one-time intermediates not timed)."""
@@ -421,6 +475,14 @@ def main():
             batched = batched_study(adc, d, torch, np, a.batched)
         except Exception as e:
             batched = {"error": str(e)}
+    large = None
+    if a.large_mixed > 0:
+        ws = None
+        torch.cuda.empty_cache()
+        try:
+            large = large_mixed_study(adc, d, torch, np, a.large_mixed)
+        except Exception as e:
+            large = {"error": str(e)}
     line = {
         "metric": "sigma-builds/s (whole SS-FNO-EA-ADC(3) solve) + time-to-5-roots, FP64, 1 GPU",
         "value": nsig / dt,
@@ -461,6 +523,8 @@ def main():
         line["learned_full_size"] = learned_full
     if batched is not None:
         line["batched"] = batched
+    if large is not None:
+        line["large_mixed_precision"] = large
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline((p["nocc"], vk, xk), nroots)
     print(json.dumps(line), flush=True)

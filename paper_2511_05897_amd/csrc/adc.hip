@@ -323,9 +323,12 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             // second-order doubles residual Y (alpha-beta block)
             double* L = take(ws, oo * vv);
             if (c->df) {
-                const long long ve = df_v_elems((int)oo, v, X);
+                // T^cd_ij = T^dc_ji, so L_ji = L_ij^T: only the pairs i <= j are contracted
+                const long long np = oo / 2 + o / 2 + (o % 2);  // o(o+1)/2
+                const long long ve = df_v_elems((int)np, v, X);
                 double* Vt = take(ws, ve);
-                df_ladder(0, (int)oo, v, X, Bvv, T, L, false, Vt, ve, s);
+                double* pr = take(ws, 2 * np * vv);
+                df_ladder_pairs(o, v, X, Bvv, T, L, pr, Vt, ve, s);
             } else {
                 gemm_rm((int)oo, (int)vv, (int)vv, 1.0, T, vv, false, c->G, vv, false, 0.0, L, vv, s);
             }
@@ -461,9 +464,10 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                 const double pk = prec == 0 ? PEAK_FP64_MFMA : prec == 1 ? PEAK_FP32_MFMA : PEAK_BF16_MFMA;
                 ProfScope p(prec > 0 ? PROF_LADDER_LP : PROF_LADDER, s, fl, by, 1e3 * std::max(fl / pk, by / PEAK_HBM));
                 if (prec > 0) {
-                    void* V = prec == 1 ? (void*)ws.take<float>((size_t)ve) : (void*)ws.take<unsigned short>((size_t)ve);
+                    const long long vl = prec == 2 ? ve + (long long)M * vv + 8 : ve;  // BF16: + Z transposed
+                    void* V = prec == 1 ? (void*)ws.take<float>((size_t)vl) : (void*)ws.take<unsigned short>((size_t)vl);
                     k_to_lowp(c->zlo, zb, (long long)M * vv, prec, s);
-                    df_ladder(prec, M, v, X, c->Bvvlo, c->zlo, c->sb, false, V, ve, s);
+                    df_ladder(prec, M, v, X, c->Bvvlo, c->zlo, c->sb, false, V, vl, s);
                 } else {
                     double* V = take(ws, ve);
                     df_ladder(0, M, v, X, c->Bvv, zb, c->sb, false, V, ve, s);
@@ -1427,7 +1431,8 @@ size_t adc3_ladder_workspace_bytes(int nvir, int naux, int nrows, int precision)
     const size_t eb = precision == 0 ? 8 : precision == 1 ? 4 : 2;
     const size_t vv = (size_t)nvir * nvir;
     const size_t copies = precision == 0 ? 0 : (((size_t)naux * vv * eb + 255) & ~size_t(255)) + (((size_t)nrows * vv * eb + 255) & ~size_t(255));
-    return copies + (size_t)nrows * vv * eb;
+    const size_t zt = precision == 2 ? ((size_t)nrows * vv + 8) * eb : 0;  // Z transposed (BF16)
+    return copies + zt + (size_t)nrows * vv * eb;
 }
 
 int adc3_ladder_apply(const double* Bvv, const double* Z, double* C, int nvir, int naux, int nrows, int precision,
@@ -1457,7 +1462,8 @@ int adc3_ladder_apply(const double* Bvv, const double* Z, double* C, int nvir, i
     const size_t eb = precision == 0 ? 8 : precision == 1 ? 4 : 2;
     const size_t off = (ws.used + 255) & ~size_t(255);
     const long long ve = (long long)((ws_bytes - std::min(ws_bytes, off)) / eb);
-    if (ve < nrows * vv) fail(ADC3_ENOMEM, "workspace too small for one auxiliary function of the intermediate");
+    if (ve < nrows * vv + (precision == 2 ? nrows * vv + 8 : 0))
+        fail(ADC3_ENOMEM, "workspace too small for one auxiliary function of the intermediate");
     void* V = ws.base + off;
     const double fl = 4.0 * naux * (double)nrows * nvir * (double)vv;
     const double by = eb * (2.0 * naux * (double)nrows * vv + (double)naux * vv + nrows * (double)vv) + 8.0 * nrows * (double)vv;

@@ -34,7 +34,9 @@ constexpr int DNT = 256, DBN = 128, DLTN = 2;  // 4 waves x 2 column blocks of 1
 
 struct DflArgs {
     const void* A; long long lda, bA0, bA1;  // A[m][k], row-major
-    const void* B; long long ldb, bB0, bB1;  // B[k][n], row-major
+    // B[k][n] row-major; with BT (BF16 only) B is read as Bt[n][k] at n*ldb + (k/kin)*ldbq + k%kin
+    const void* B; long long ldb, bB0, bB1, ldbq;
+    int kin;
     void* C; long long ldc, bC0, bC1;        // C[m][n]
     long long m_off;                         // first row of this launch
     int M, N, K, nb0;
@@ -53,8 +55,9 @@ template <> struct Out<0> { typedef double T; };
 template <> struct Out<1> { typedef float T; };
 template <> struct Out<2> { typedef __bf16 T; };
 
-template <int P, int TO, int TM>
+template <int P, int TO, int TM, bool BT>
 __global__ __launch_bounds__(DNT, 2) void dfl_kernel(DflArgs g) {
+    static_assert(!BT || P == 2, "B given as [n][k] only for BF16");
     typedef typename Prec<P>::T T;
     typedef typename Prec<P>::V VT;
     typedef typename Prec<P>::Acc Acc;
@@ -87,8 +90,13 @@ __global__ __launch_bounds__(DNT, 2) void dfl_kernel(DflArgs g) {
 #pragma unroll
     for (int p = 0; p < PB; ++p) {
         const int idx = tid + DNT * p;
-        bkr[p] = idx / (DBN / W);
-        bnq[p] = idx % (DBN / W);
+        if constexpr (BT) {  // bkr: column n, bnq: k vector
+            bkr[p] = idx / (BK / W);
+            bnq[p] = idx % (BK / W);
+        } else {
+            bkr[p] = idx / (DBN / W);
+            bnq[p] = idx % (DBN / W);
+        }
     }
     VT ra[PA], rb[PB];
     auto fetch = [&](int k0) {
@@ -113,11 +121,26 @@ __global__ __launch_bounds__(DNT, 2) void dfl_kernel(DflArgs g) {
         }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
-            const int k = k0 + bkr[p];
-            const long long n = n0 + W * bnq[p];
             VT x;
 #pragma unroll
             for (int e = 0; e < W; ++e) x[e] = (T)0.0f;
+            if constexpr (BT) {
+                const long long n = n0 + bkr[p];
+                const int k = k0 + W * bnq[p];
+                if (n < g.N) {
+                    if (g.vec) {
+                        if (k < K) x = *(const VT*)(B + n * g.ldb + (long long)(k / g.kin) * g.ldbq + k % g.kin);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < W; ++e)
+                            if (k + e < K) x[e] = B[n * g.ldb + (long long)((k + e) / g.kin) * g.ldbq + (k + e) % g.kin];
+                    }
+                }
+                rb[p] = x;
+                continue;
+            }
+            const int k = k0 + bkr[p];
+            const long long n = n0 + W * bnq[p];
             if (k < K) {
                 const T* src = B + (long long)k * g.ldb + n;
                 if (g.vec) {
@@ -144,7 +167,9 @@ __global__ __launch_bounds__(DNT, 2) void dfl_kernel(DflArgs g) {
             }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
-            if constexpr (P == 2) {
+            if constexpr (BT) {
+                *(VT*)&Bs[buf][bkr[p]][W * bnq[p]] = rb[p];
+            } else if constexpr (P == 2) {
 #pragma unroll
                 for (int e = 0; e < W; ++e) Bs[buf][W * bnq[p] + e][bkr[p]] = rb[p][e];
             } else {
@@ -227,23 +252,41 @@ __global__ __launch_bounds__(DNT, 2) void dfl_kernel(DflArgs g) {
             }
 }
 
-template <int P, int TO, int TM>
+template <int P, int TO, int TM, bool BT>
 void launch_tm(const DflArgs& a, int mtiles, int nbatch, hipStream_t s) {
     dim3 grid((unsigned)((a.N + DBN - 1) / DBN), (unsigned)mtiles, (unsigned)nbatch);
-    hipLaunchKernelGGL((dfl_kernel<P, TO, TM>), grid, dim3(DNT), 0, s, a);
+    hipLaunchKernelGGL((dfl_kernel<P, TO, TM, BT>), grid, dim3(DNT), 0, s, a);
 }
 
-template <int P, int TO>
+template <int P, int TO, bool BT = false>
 void launch_p(const DflArgs& a, int tm, int mtiles, int nbatch, hipStream_t s) {
     switch (tm) {
-        case 1: launch_tm<P, TO, 1>(a, mtiles, nbatch, s); break;
-        case 2: launch_tm<P, TO, 2>(a, mtiles, nbatch, s); break;
-        case 3: launch_tm<P, TO, 3>(a, mtiles, nbatch, s); break;
-        case 4: launch_tm<P, TO, 4>(a, mtiles, nbatch, s); break;
-        case 5: launch_tm<P, TO, 5>(a, mtiles, nbatch, s); break;
-        case 6: launch_tm<P, TO, 6>(a, mtiles, nbatch, s); break;
-        case 7: launch_tm<P, TO, 7>(a, mtiles, nbatch, s); break;
-        default: launch_tm<P, TO, 8>(a, mtiles, nbatch, s); break;
+        case 1: launch_tm<P, TO, 1, BT>(a, mtiles, nbatch, s); break;
+        case 2: launch_tm<P, TO, 2, BT>(a, mtiles, nbatch, s); break;
+        case 3: launch_tm<P, TO, 3, BT>(a, mtiles, nbatch, s); break;
+        case 4: launch_tm<P, TO, 4, BT>(a, mtiles, nbatch, s); break;
+        case 5: launch_tm<P, TO, 5, BT>(a, mtiles, nbatch, s); break;
+        case 6: launch_tm<P, TO, 6, BT>(a, mtiles, nbatch, s); break;
+        case 7: launch_tm<P, TO, 7, BT>(a, mtiles, nbatch, s); break;
+        default: launch_tm<P, TO, 8, BT>(a, mtiles, nbatch, s); break;
+    }
+}
+
+// dst[m][j][i] = src[m][i][j], m < nb, n x n blocks of BF16
+__global__ void transpose_bf16_kernel(unsigned short* dst, const unsigned short* src, int n, int nb) {
+    __shared__ unsigned short t[32][33];
+    const long long m = blockIdx.z;
+    const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+    const unsigned short* S = src + m * (long long)n * n;
+    unsigned short* D = dst + m * (long long)n * n;
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int i = i0 + r, j = j0 + threadIdx.x;
+        if (i < n && j < n) t[r][threadIdx.x] = S[(long long)i * n + j];
+    }
+    __syncthreads();
+    for (int r = threadIdx.y; r < 32; r += 8) {
+        const int j = j0 + r, i = i0 + threadIdx.x;
+        if (i < n && j < n) D[(long long)j * n + i] = t[threadIdx.x][r];
     }
 }
 
@@ -252,14 +295,16 @@ int elem_bytes(int p) { return p == 0 ? 8 : p == 1 ? 4 : 2; }
 // C = A B (or C += A B) over nbatch = nb0 * nb1 batches; out_prec selects C's type
 // (0 FP64, 1 FP32, 2 BF16; for P = 0 only 0).  Rows are cut into launches of at most
 // 65535 row tiles.
-void dfl_gemm(int P, int out_prec, DflArgs a, int nb1, hipStream_t s) {
+void dfl_gemm(int P, int out_prec, DflArgs a, int nb1, hipStream_t s, bool bt = false) {
     if (a.M <= 0 || a.N <= 0) return;
     const int nbatch = a.nb0 * nb1;
     if (nbatch <= 0 || nbatch > 65535) fail(-1, "dfladder: batch count out of range");
+    if (bt && (P != 2 || a.kin <= 0)) fail(-1, "dfladder: transposed B operand is BF16 only");
     const int W = 16 / elem_bytes(P);
     const auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
-    a.vec = (a.K % W == 0 && a.N % W == 0 && a.lda % W == 0 && a.ldb % W == 0 && a.bA0 % W == 0 && a.bA1 % W == 0 &&
-             a.bB0 % W == 0 && a.bB1 % W == 0 && al(a.A) && al(a.B)) ? 1 : 0;
+    a.vec = (a.K % W == 0 && (bt ? (a.kin % W == 0 && a.ldbq % W == 0) : a.N % W == 0) && a.lda % W == 0 &&
+             a.ldb % W == 0 && a.bA0 % W == 0 && a.bA1 % W == 0 && a.bB0 % W == 0 && a.bB1 % W == 0 && al(a.A) &&
+             al(a.B)) ? 1 : 0;
     // rows: as few tiles as possible, each as short as M allows (<= 128 rows)
     int mt = (int)std::min<long long>(((long long)a.M + 127) / 128, 65535);
     const long long rows_per_launch = (long long)mt * 128;
@@ -273,9 +318,39 @@ void dfl_gemm(int P, int out_prec, DflArgs a, int nb1, hipStream_t s) {
         if (P == 0) launch_p<0, 0>(b, tm, mtiles, nbatch, s);
         else if (P == 1 && out_prec == 0) launch_p<1, 0>(b, tm, mtiles, nbatch, s);
         else if (P == 1) launch_p<1, 1>(b, tm, mtiles, nbatch, s);
-        else if (out_prec == 0) launch_p<2, 0>(b, tm, mtiles, nbatch, s);
-        else launch_p<2, 2>(b, tm, mtiles, nbatch, s);
+        else if (out_prec == 0) launch_p<2, 0, true>(b, tm, mtiles, nbatch, s);
+        else launch_p<2, 2, true>(b, tm, mtiles, nbatch, s);
         LAUNCHCHK();
+    }
+}
+}  // namespace
+
+namespace {
+// upper-triangle pair index of (i, j), i <= j < o
+__device__ inline long long pair_index(int i, int j, int o) { return (long long)i * o - (long long)i * (i - 1) / 2 + (j - i); }
+
+// Tp[p(i,j)] = T[i][j] for i <= j   (blocks of vv)
+__global__ void pairs_gather_kernel(double* Tp, const double* T, int o, long long vv) {
+    const int i = blockIdx.y / o, j = blockIdx.y % o;
+    if (j < i) return;
+    const double* src = T + ((long long)i * o + j) * vv;
+    double* dst = Tp + pair_index(i, j, o) * vv;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < vv; t += (long long)gridDim.x * blockDim.x)
+        dst[t] = src[t];
+}
+
+// L[i][j] = Lp[p(i,j)], L[j][i] = Lp[p(i,j)]^T for i <= j   (v x v blocks)
+__global__ void pairs_scatter_kernel(double* L, const double* Lp, int o, int v) {
+    const int i = blockIdx.y / o, j = blockIdx.y % o;
+    if (j < i) return;
+    const long long vv = (long long)v * v;
+    const double* src = Lp + pair_index(i, j, o) * vv;
+    double* dij = L + ((long long)i * o + j) * vv;
+    double* dji = L + ((long long)j * o + i) * vv;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < vv; t += (long long)gridDim.x * blockDim.x) {
+        const long long a = t / v, b = t % v;
+        dij[t] = src[t];
+        if (i != j) dji[b * v + a] = src[t];
     }
 }
 }  // namespace
@@ -298,29 +373,58 @@ void df_ladder(int prec, int M, int v, int X, const void* Bvv, const void* Z, do
         if (!accumulate) k_fill(C, (long long)M * vv, 0.0, s);
         return;
     }
-    const long long q = df_ladder_chunk(M, v, X, v_elems);
-    if (q * M * vv > v_elems) fail(-1, "dfladder: intermediate buffer too small");
+    // BF16 reads both B operands as [n][k] (16-byte LDS stores): step 1 from Z transposed per row
+    // (kept at the end of the buffer), step 2 from B^Q itself, which is symmetric
+    const bool bt = prec == 2;
+    const long long zt_elems = bt ? (long long)M * vv + 8 : 0;
+    const long long avail = v_elems - zt_elems;
+    const long long q = df_ladder_chunk(M, v, X, avail);
+    if (q * M * vv > avail) fail(-1, "dfladder: intermediate buffer too small");
     const int eb = elem_bytes(prec);
+    const void* Zb = Z;
+    if (bt) {
+        unsigned short* Zt = (unsigned short*)V + ((v_elems - (long long)M * vv) & ~7LL);
+        dim3 grid((unsigned)((v + 31) / 32), (unsigned)((v + 31) / 32), (unsigned)M);
+        hipLaunchKernelGGL(transpose_bf16_kernel, grid, dim3(32, 8), 0, s, Zt, (const unsigned short*)Z, v, M);
+        LAUNCHCHK();
+        Zb = Zt;
+    }
     for (long long Q0 = 0; Q0 < X; Q0 += q) {
         const int qn = (int)std::min<long long>(q, X - Q0);
         const char* Bq = (const char*)Bvv + Q0 * vv * eb;
         // step 1: V[m][a][Qi][e] = sum_c B^Q[a][c] Z_m[c][e]  (batch b0 = Qi, b1 = m)
         DflArgs a1{};
         a1.A = Bq; a1.lda = v; a1.bA0 = vv; a1.bA1 = 0;
-        a1.B = Z; a1.ldb = v; a1.bB0 = 0; a1.bB1 = vv;
+        a1.B = Zb; a1.ldb = v; a1.bB0 = 0; a1.bB1 = vv; a1.ldbq = 0; a1.kin = v;
         a1.C = V; a1.ldc = (long long)qn * v; a1.bC0 = v; a1.bC1 = (long long)qn * vv;
         a1.M = v; a1.N = v; a1.K = v; a1.nb0 = qn;
         a1.accumulate = 0;
-        dfl_gemm(prec, prec, a1, M, s);
+        dfl_gemm(prec, prec, a1, M, s, bt);
         // step 2: C[(m,a)][b] (+)= sum_(Qi,e) V[(m,a)][(Qi,e)] B^Q[e][b]
         DflArgs a2{};
         a2.A = V; a2.lda = (long long)qn * v;
-        a2.B = Bq; a2.ldb = v;
+        a2.B = Bq; a2.ldb = v; a2.ldbq = vv; a2.kin = v;
         a2.C = C; a2.ldc = v;
         a2.M = (int)((long long)M * v); a2.N = v; a2.K = qn * v; a2.nb0 = 1;
         a2.accumulate = (accumulate || Q0 > 0) ? 1 : 0;
-        dfl_gemm(prec, 0, a2, 1, s);
+        dfl_gemm(prec, 0, a2, 1, s, bt);
     }
 }
 
+}  // namespace adc3
+
+namespace adc3 {
+void df_ladder_pairs(int o, int v, int X, const double* Bvv, const double* T, double* L, double* scratch, void* V,
+                     long long v_elems, hipStream_t s) {
+    if (g_dry) return;
+    const long long vv = (long long)v * v, np = (long long)o * (o + 1) / 2;
+    double* Tp = scratch;
+    double* Lp = scratch + np * vv;
+    const unsigned gx = (unsigned)std::min<long long>((vv + 255) / 256, 1024);
+    hipLaunchKernelGGL(pairs_gather_kernel, dim3(gx, (unsigned)(o * o)), dim3(256), 0, s, Tp, T, o, vv);
+    LAUNCHCHK();
+    df_ladder(0, (int)np, v, X, Bvv, Tp, Lp, false, V, v_elems, s);
+    hipLaunchKernelGGL(pairs_scatter_kernel, dim3(gx, (unsigned)(o * o)), dim3(256), 0, s, L, Lp, o, v);
+    LAUNCHCHK();
+}
 }  // namespace adc3

@@ -100,10 +100,15 @@ int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long 
                         double* C, long long ldc, double* partial, long long partial_elems, hipStream_t s);
 // ladder from the DF factor (dfladder.hip): C[m] (+)= sum_Q B^Q Z[m] B^Q for m < M, with Bvv [X][v][v]
 // and Z [M][v][v] in the operand precision prec (0 FP64, 1 FP32, 2 BF16), C FP64 [M][v][v]; V is an
-// intermediate of v_elems elements of that precision holding q*M*v*v for the chunk size q
+// intermediate of v_elems elements of that precision holding q*M*v*v for the chunk size q (BF16: plus
+// M*v*v + 8 for Z transposed)
 long long df_ladder_chunk(int M, int v, int X, long long v_elems);
 void df_ladder(int prec, int M, int v, int X, const void* Bvv, const void* Z, double* C, bool accumulate, void* V,
                long long v_elems, hipStream_t s);
+// FP64 ladder of amplitudes with T[j][i] = T[i][j]^T (o x o blocks of v x v): L[i][j] = sum_Q B^Q T[i][j] B^Q is
+// formed for i <= j only and L[j][i] = L[i][j]^T; scratch holds 2 * o(o+1)/2 * v*v doubles
+void df_ladder_pairs(int o, int v, int X, const double* Bvv, const double* T, double* L, double* scratch, void* V,
+                     long long v_elems, hipStream_t s);
 extern thread_local double* g_gemm_scratch;
 extern thread_local long long g_gemm_scratch_n;
 void gemm_lp(const GemmLP& g, int prec, hipStream_t s, int tag = 0);

@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol(lib):
 def test_default_opts(lib):
     o = adc.adc3_default_opts()
     assert (o.level, o.max_iter, o.max_subspace, o.fno_correction, o.precision, o.precond) == (3, 500, 0, 1, 0, 3)
-    assert not o.mlp_weights and o.sigma_graphs == 0
+    assert not o.mlp_weights and o.sigma_graphs == 0 and o.ladder == 0
 
 
 def _inst(shapes):
@@ -78,6 +78,45 @@ def test_workspace_planning(lib):
     assert adc.adc3_ea_solve_workspace_bytes(4, 20, 60, 3, o) > 0
     o.precision = 7
     assert adc.adc3_ea_solve_workspace_bytes(4, 20, 60, 3, o) == 0
+
+
+def test_ladder_form_planning(lib):
+    # the assembled ladder needs no v^4 matrix (its intermediate is X * rows * v^2 elements at most); at
+    # v = 600 it is the automatic choice
+    v4 = 100 ** 4 * 8
+    stored = adc.adc3_ea_setup_workspace_bytes(4, 100, 20, 3, 5, 0, 1)
+    assembled = adc.adc3_ea_setup_workspace_bytes(4, 100, 20, 3, 5, 0, 2)
+    assert stored > v4 and 0 < assembled and stored - assembled > v4 // 2
+    assert adc.adc3_ea_setup_workspace_bytes(4, 100, 20, 3, 5, 0, 0) == stored
+    assert adc.adc3_ea_setup_workspace_bytes(4, 100, 20, 3, 5, 0, 3) == 0
+    large = adc.adc3_ea_setup_workspace_bytes(40, 600, 150, 3, 5, 0, 0)
+    assert 0 < large < 600 ** 4 * 8 // 4
+    assert adc.adc3_ea_setup_workspace_bytes(40, 600, 150, 3, 5, 0, 2) == large
+    o = adc.adc3_default_opts()
+    assert 0 < adc.adc3_ea_solve_workspace_bytes(40, 600, 1800, 5, o) < 288e9
+    o.ladder = 3
+    assert adc.adc3_ea_solve_workspace_bytes(4, 20, 60, 3, o) == 0
+    assert adc.adc3_ea_setup_workspace_bytes(20, 1025, 60, 3, 3) == 0  # nvir limit
+
+
+def test_ladder_apply_sizes_and_chunk_budget(lib):
+    # FP64: the intermediate for one auxiliary function; FP32 / BF16 add the rounded copies (BF16 also Z^T)
+    assert adc.adc3_ladder_workspace_bytes(10, 4, 3, 0) == 3 * 100 * 8
+    assert adc.adc3_ladder_workspace_bytes(10, 4, 3, 1) >= (4 * 100 + 3 * 100 + 3 * 100) * 4
+    assert adc.adc3_ladder_workspace_bytes(10, 4, 3, 2) >= (4 * 100 + 3 * 100 + 3 * 100 + 3 * 100 + 8) * 2
+    assert adc.adc3_ladder_workspace_bytes(10, 4, 3, 3) == 0
+    assert adc.adc3_ladder_workspace_bytes(0, 4, 3, 0) == 0
+    st = lib.adc3_ladder_apply(None, None, None, 10, 4, 3, 0, None, 0, None)
+    assert st == adc.ADC3_EINVAL
+    prev = adc.adc3_set_chunk_elems(0)
+    assert prev == 1 << 29
+    base = adc.adc3_ea_setup_workspace_bytes(4, 20, 60, 3, 3, 0, 2)
+    assert adc.adc3_set_chunk_elems(4 * 20 * 20) == prev
+    try:
+        assert 0 < adc.adc3_ea_setup_workspace_bytes(4, 20, 60, 3, 3, 0, 2) < base
+    finally:
+        adc.adc3_set_chunk_elems(prev)
+    assert adc.adc3_set_chunk_elems(0) == prev
 
 
 def test_error_paths_without_device(lib):
