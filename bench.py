@@ -42,6 +42,10 @@ def parse():
     ap.add_argument("--large-mixed", type=float, default=0.0,
                     help="also run the FP64 / FP32 / BF16 Davidson study of the o=40 v=600 X=1800 workload "
                          "with B scaled by this factor (about 12 minutes; 0 = skip)")
+    ap.add_argument("--large-mixed-precs", default="0,1,2",
+                    help="Davidson precisions of the large study (0 FP64, 1 FP32, 2 BF16), comma-separated")
+    ap.add_argument("--large-mixed-ref", default="",
+                    help="FP64 roots of the large study from an earlier run (comma-separated), when 0 is not run")
     ap.add_argument("--sigma-reps", type=int, default=10)
     ap.add_argument("--sigma-only", action="store_true",
                     help="profiling mode: only the isolated ADC(3) sigma builds plus a 2 GiB copy (counter calibration)")
@@ -236,12 +240,13 @@ def mixed_ladder_dominated(adc, d, torch, np):
     return out
 
 
-def large_mixed_study(adc, d, torch, np, scale):
+def large_mixed_study(adc, d, torch, np, scale, precs=(0, 1, 2), ref=None):
     """ADC(3) Davidson of the large mixed-precision workload (o=40, v=600, X=1800, seed 2, canonical basis,
     5 roots, conv 1e-6), B scaled by `scale`, with FP64, FP32-operand and BF16-operand sigma (each
     reduced-precision Davidson ends with an FP64 restart).  The ladder is assembled from the DF factor in
     every application (the stored v^4 matrix would take 1 TB).  Context setup (FP64 in every mode) is
-    timed on its own; the FP64 and FP32 runs share one context."""
+    timed on its own; the FP64 run shares the first reduced-precision context.  `ref`: FP64 roots of an
+    earlier run when 0 is not in `precs`."""
     import synth
     p, eo, ev, B = synth.preset("mixed-o40v600x1800", scale=scale)
     tB = d(B)
@@ -249,8 +254,16 @@ def large_mixed_study(adc, d, torch, np, scale):
     nroots, conv = p["nroots"], p["conv"]
     out = {"shape": [p["nocc"], p["nvir"], p["naux"]], "seed": p["seed"], "scale": scale, "nroots": nroots,
            "conv": conv, "ladder": "assembled from the DF factor"}
-    ref = None
-    for cprec, runs in ((1, (0, 1)), (2, (2,))):
+    if ref is not None:
+        ref = np.asarray(ref, dtype=float)
+        out["fp64_roots_from_earlier_run"] = [float(x) for x in ref]
+    groups = []
+    lp = [x for x in (1, 2) if x in precs]
+    for i, cp in enumerate(lp):
+        groups.append((cp, ((0,) if (0 in precs and i == 0) else ()) + (cp,)))
+    if not lp and 0 in precs:
+        groups.append((0, (0,)))
+    for cprec, runs in groups:
         t0 = time.perf_counter()
         ctx = adc.Context(d(eo), d(ev), tB, 3, nroots=nroots, precision=cprec)
         torch.cuda.synchronize()
@@ -283,7 +296,8 @@ def large_mixed_study(adc, d, torch, np, scale):
         del ctx
         torch.cuda.empty_cache()
     for tag in ("fp32", "bf16"):
-        out[tag]["speedup_vs_fp64"] = out["fp64"]["davidson_s"] / out[tag]["davidson_s"]
+        if tag in out and "fp64" in out:
+            out[tag]["speedup_vs_fp64"] = out["fp64"]["davidson_s"] / out[tag]["davidson_s"]
     return out
 
 
@@ -480,7 +494,9 @@ def main():
         ws = None
         torch.cuda.empty_cache()
         try:
-            large = large_mixed_study(adc, d, torch, np, a.large_mixed)
+            precs = tuple(int(x) for x in a.large_mixed_precs.split(",") if x.strip())
+            ref = [float(x) for x in a.large_mixed_ref.split(",") if x.strip()] or None
+            large = large_mixed_study(adc, d, torch, np, a.large_mixed, precs, ref)
         except Exception as e:
             large = {"error": str(e)}
     line = {

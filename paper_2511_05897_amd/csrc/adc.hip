@@ -104,6 +104,7 @@ struct Ctx {
     int prec = 0;
     void* Glo = nullptr;
     void* Bvvlo = nullptr;  // reduced-precision Bvv for the assembled ladder
+    float* Bvv32 = nullptr; // BF16 contexts with the assembled ladder: an FP32 Bvv as well (middle phase)
     void* zlo = nullptr;  // reduced-precision copy of the ladder's input rows
     float* Uz32 = nullptr;
     // learned preconditioner: weights (caller's device memory) and the BF16 W2 copy
@@ -188,6 +189,7 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             void*& lo = c->df ? c->Bvvlo : c->Glo;
             if (prec == 1) lo = ws.take<float>((size_t)ng);
             else lo = ws.take<unsigned short>((size_t)ng);
+            if (prec == 2 && c->df) c->Bvv32 = ws.take<float>((size_t)ng);
             c->zlo = ws.take<float>((size_t)(NVMAX * (long long)o * vv));
         }
     }
@@ -415,8 +417,12 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     k_diag_adc(c->diag, c->M11, eo, ev, Bvv, c->oovv, c->ovov, o, v, X, level, s);
     if (prec > 0) {
         k_to_lowp(c->Uz32, c->Uz, v * (long long)o * vv, 1, s);
-        if (level >= 3 && c->df) k_to_lowp(c->Bvvlo, c->Bvv, (long long)X * vv, prec, s);
-        else if (level >= 3) k_to_lowp(c->Glo, c->G, vv * vv, prec, s);
+        if (level >= 3 && c->df) {
+            k_to_lowp(c->Bvvlo, c->Bvv, (long long)X * vv, prec, s);
+            if (c->Bvv32) k_to_lowp(c->Bvv32, c->Bvv, (long long)X * vv, 1, s);
+        } else if (level >= 3) {
+            k_to_lowp(c->Glo, c->G, vv * vv, prec, s);
+        }
     }
     c->ws = ws;  // snapshot (base/cap/used) for later temporaries
     return c;
@@ -467,7 +473,9 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                     const long long vl = prec == 2 ? ve + (long long)M * vv + 8 : ve;  // BF16: + Z transposed
                     void* V = prec == 1 ? (void*)ws.take<float>((size_t)vl) : (void*)ws.take<unsigned short>((size_t)vl);
                     k_to_lowp(c->zlo, zb, (long long)M * vv, prec, s);
-                    df_ladder(prec, M, v, X, c->Bvvlo, c->zlo, c->sb, false, V, vl, s);
+                    // FP32 sigma of a BF16 context (its middle phase) takes the FP32 copy of Bvv
+                    const void* Bl = (prec == 1 && c->prec == 2) ? (const void*)c->Bvv32 : c->Bvvlo;
+                    df_ladder(prec, M, v, X, Bl, c->zlo, c->sb, false, V, vl, s);
                 } else {
                     double* V = take(ws, ve);
                     df_ladder(0, M, v, X, c->Bvv, zb, c->sb, false, V, ve, s);
@@ -523,7 +531,7 @@ static size_t sigma_region_bytes(Ctx* c) {
     const bool was = g_dry;
     g_dry = true;
     size_t peak = 0;
-    for (int p : {0, c->prec}) {
+    for (int p : {0, c->prec, c->Bvv32 ? 1 : 0}) {
         Arena count;
         sigma_pass(c, count, nullptr, nullptr, NVMAX, nullptr, p);
         peak = std::max(peak, count.peak);
@@ -695,9 +703,12 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
         m = orthonormalise(V, nguess, 0, S);
         if (m < nroots) fail(-4, "davidson: initial guesses are linearly dependent");
     }
-    int phase = prec;  // > 0: reduced-precision sigma until its noise floor, then FP64 correction
-    double best_lp = INFINITY;
-    int stall = 0, it_lp = 0;
+    // phase > 0: reduced-precision sigma until its noise floor, then FP64 correction (a BF16 context with
+    // an FP32 copy of the factor passes through FP32 on the way)
+    int phase = prec;
+    std::vector<double> lp_best(nroots, INFINITY);
+    std::vector<int> lp_stall(nroots, 0);
+    int it_lp = 0;
     sigma_impl(c, ws, V, S, m, s, phase);
     k_dots(V, N, m, S, N, m, N, Gf, mmax, part, s);
     std::vector<double> thold(nroots, INFINITY), hw(mmax), hrn(nroots * nroots), prev_rn(nroots, INFINITY);
@@ -734,7 +745,9 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
         }
         if (!finite) fail(-4, "davidson: non-finite Ritz value or residual");
         if (phase > 0) {
-            // reduced-precision phase: stop at a tolerance set by the precision, or when it stalls
+            // reduced-precision phase: stop at a tolerance set by the precision, or once every root still
+            // above it has stalled (no 10% gain on its best residual in 4 iterations): slow progress of
+            // some roots while others still improve is convergence, not the precision's noise floor
             ++it_lp;
             double scale = 1.0, rmax = 0.0;
             for (int k = 0; k < nroots; ++k) {
@@ -742,19 +755,28 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
                 rmax = std::max(rmax, res.rn[k]);
             }
             const double tau = std::max(conv, (phase == 1 ? 1e-6 : 3e-3) * scale);
-            if (rmax < 0.9 * best_lp) { best_lp = rmax; stall = 0; } else ++stall;
-            if (rmax <= tau || stall >= 4 || it >= max_iter) {
-                // FP64 residual correction: restart from the Ritz vectors with FP64 sigma
+            bool all_stalled = true;
+            for (int k = 0; k < nroots; ++k) {
+                if (res.rn[k] < 0.9 * lp_best[k]) { lp_best[k] = res.rn[k]; lp_stall[k] = 0; } else ++lp_stall[k];
+                if (res.rn[k] > tau && lp_stall[k] < 4) all_stalled = false;
+            }
+            if (rmax <= tau || all_stalled || it >= max_iter) {
+                // residual correction in the next precision: restart from the Ritz vectors
                 const int nkeep = std::min(m, nkeep_max);
                 k_copy2d(coef, nkeep, Y, m, m, nkeep, 1.0, 0.0, s);
                 k_lincomb(Vk, N, nkeep, V, N, m, coef, nkeep, N, 1.0, 0.0, s);
                 k_copy(V, Vk, (long long)nkeep * N, s);
                 m = nkeep;
-                phase = 0;
-                res.iters_lowp = it_lp;
-                sigma_impl(c, ws, V, S, m, s, 0);
+                phase = (phase == 2 && c->Bvv32) ? 1 : 0;
+                std::fill(lp_best.begin(), lp_best.end(), INFINITY);
+                std::fill(lp_stall.begin(), lp_stall.end(), 0);
+                if (phase == 0) {
+                    res.iters_lowp = it_lp;
+                    for (int k = 0; k < nroots; ++k) res.w_lowp.push_back(res.w[k]);
+                }
+                sigma_impl(c, ws, V, S, m, s, phase);
                 k_dots(V, N, m, S, N, m, N, Gf, mmax, part, s);
-                for (int k = 0; k < nroots; ++k) { res.w_lowp.push_back(res.w[k]); thold[k] = INFINITY; }
+                for (int k = 0; k < nroots; ++k) thold[k] = INFINITY;
                 continue;
             }
         }

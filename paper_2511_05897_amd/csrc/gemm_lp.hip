@@ -264,6 +264,7 @@ void gemm_lp(const GemmLP& g, int prec, hipStream_t s, int tag) {
 void k_to_lowp(void* dst, const double* src, long long n, int prec, hipStream_t s) {
     if (g_dry) return;
     if (n <= 0) return;
+    if (!dst || !src) fail(-1, "k_to_lowp: NULL buffer");
     unsigned nb = (unsigned)std::min<long long>((n + 255) / 256, 8192);
     if (prec == 1) hipLaunchKernelGGL(to_f32_kernel, dim3(nb), dim3(256), 0, s, (float*)dst, src, n);
     else hipLaunchKernelGGL(to_bf16_kernel, dim3(nb), dim3(256), 0, s, (__bf16*)dst, src, n);
