@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--sigma-reps", type=int, default=10)
     ap.add_argument("--sigma-only", action="store_true",
                     help="profiling mode: only the isolated ADC(3) sigma builds plus a 2 GiB copy (counter calibration)")
+    ap.add_argument("--dfladder-only", action="store_true",
+                    help="profiling mode: the assembled ladder alone at o=40 v=600 X=1800 (5 vectors) in FP64, FP32 "
+                         "and BF16, plus a 2 GiB copy (counter calibration)")
     ap.add_argument("--variant-scale", type=float, default=0.018,
                     help="also time one solve with B scaled by this factor (weak correlation, FNO truncates); 0 = skip")
     return ap.parse_args()
@@ -301,6 +304,46 @@ def large_mixed_study(adc, d, torch, np, scale, precs=(0, 1, 2), ref=None):
     return out
 
 
+def dfladder_only(adc, torch, reps):
+    """The ladder assembled from the DF factor (adc3_ladder_apply) at the large workload's sigma shape:
+    v = 600, X = 1800, 200 rows (5 vectors x 40 occupied), 16 GiB of intermediate, `reps` calls per
+    precision after one untimed call; then a 2 GiB device copy for counter calibration."""
+    import synth
+    v, X, M = 600, 1800, 200
+    _, _, B = synth.make_instance(1, v, X, 2, scale=0.05)
+    Bvv = torch.as_tensor(B[:, 1:, 1:].copy(), dtype=torch.float64, device="cuda")
+    del B
+    Z = torch.randn((M, v, v), dtype=torch.float64, device="cuda")
+    out = torch.empty_like(Z)
+    res = {"mode": "dfladder-only", "nvir": v, "naux": X, "rows": M, "calls_per_precision": reps,
+           "flops_per_call": 4.0 * X * M * v ** 3}
+    for prec in (0, 1, 2):
+        ws = torch.empty(adc.adc3_ladder_workspace_bytes(v, X, M, prec) + (16 << 30), dtype=torch.uint8,
+                         device="cuda")
+        adc.adc3_ladder_apply(Bvv, Z, precision=prec, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        adc.adc3_profile_enable(True)
+        for _ in range(reps):
+            adc.adc3_ladder_apply(Bvv, Z, precision=prec, out=out, workspace=ws)
+        torch.cuda.synchronize()
+        kind = adc.PROF_LADDER if prec == 0 else adc.PROF_LADDER_LP
+        ms, n, fl, by = adc.adc3_profile_query(kind)
+        adc.adc3_profile_enable(False)
+        peak = (78.6, 157.3, 2500.0)[prec]
+        ach = fl / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        res[("fp64", "fp32", "bf16")[prec]] = {"avg_ms": ms / max(n, 1), "achieved_tflops": ach, "peak_tflops": peak,
+                                               "frac": ach / peak}
+        print("dfladder-only: precision %d done" % prec, file=sys.stderr, flush=True)
+        del ws
+        torch.cuda.empty_cache()
+    x = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    res["copy_bytes_each_way"] = 8 << 28
+    return res
+
+
 def cpu_baseline(shape, nvec):
     """The FP64 oracle's sigma build on the host: nvec ADC(3) sigma vectors on a
     synthetic instance of the truncated-basis shape (one-time intermediates not timed)."""
@@ -352,6 +395,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"mode": "sigma-only", "sigma_calls": a.sigma_reps, "nvec": 5,
                           "ladder_flops_per_launch": 2.0 * 100 * 200 ** 4, "copy_bytes_each_way": 8 << 28}))
+        return
+    if a.dfladder_only:
+        print(json.dumps(dfladder_only(adc, torch, a.sigma_reps)))
         return
     p, eo, ev, B = synth.preset(a.workload, scale=a.scale)
     teo, tev, tB = d(eo), d(ev), d(B)
