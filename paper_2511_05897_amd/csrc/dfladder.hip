@@ -71,13 +71,27 @@ __global__ __launch_bounds__(DNT, 2) void dfl_kernel(DflArgs g) {
     __shared__ __attribute__((aligned(16))) T As[2][AR][AC];
     __shared__ __attribute__((aligned(16))) T Bs[2][BR][BC];
 
-    const int z = blockIdx.z, b0 = z % g.nb0, b1 = z / g.nb0;
+    // Workgroup id H goes to XCD H % 8; give each XCD a contiguous range of the logical tile order
+    // (column tiles fastest, then row tiles, then batches), so that the workgroups sharing a row strip
+    // or a batch's operands run together under one L2
+    int tx, ty, tz;
+    {
+        const unsigned long long gx = gridDim.x, gy = gridDim.y;
+        const unsigned long long total = gx * gy * gridDim.z;
+        const unsigned long long H = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+        const unsigned long long per = total / 8, rem = total % 8, x = H % 8, j = H / 8;
+        const unsigned long long L = x * per + (x < rem ? x : rem) + j;
+        tx = (int)(L % gx);
+        ty = (int)((L / gx) % gy);
+        tz = (int)(L / (gx * gy));
+    }
+    const int z = tz, b0 = z % g.nb0, b1 = z / g.nb0;
     const T* __restrict__ A = (const T*)g.A + b0 * g.bA0 + b1 * g.bA1;
     const T* __restrict__ B = (const T*)g.B + b0 * g.bB0 + b1 * g.bB1;
     OT* __restrict__ C = (OT*)g.C + b0 * g.bC0 + b1 * g.bC1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const long long m0 = g.m_off + (long long)blockIdx.y * BM, n0 = (long long)blockIdx.x * DBN;
+    const long long m0 = g.m_off + (long long)ty * BM, n0 = (long long)tx * DBN;
     const int K = g.K;
 
     int arow[PA], akq[PA], bkr[PB], bnq[PB];
