@@ -70,6 +70,14 @@ LADDER_TRAFFIC = {
 }
 
 
+def min_factor(X, v, o, nv_max=16):
+    """F_lad,min / executed flops of a stored-ladder block of n_v vectors (executed: 2 o v^4 n_v), taking
+    the smaller ratio over n_v = 1..nv_max so the figure is never overstated."""
+    r = [min(4.0 * X * o * v ** 3 * n, 2.0 * X * v ** 4 + 2.0 * o * v ** 4 * n) / (2.0 * o * v ** 4 * n)
+         for n in range(1, nv_max + 1)]
+    return min(r)
+
+
 def ladder_traffic():
     import hashlib
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_05897_amd", "csrc", "ladder.hip")
@@ -572,7 +580,10 @@ def main():
                      "traffic_detail": traffic, "kernel_source_hash": src_hash,
                      "bound_time_frac": lad_bound / lad_ms if lad_ms > 0 else None,
                      "launches": lad_n, "avg_launch_ms": lad_ms / max(lad_n, 1),
-                     "flops_per_launch": lad_f / max(lad_n, 1)},
+                     "flops_per_launch": lad_f / max(lad_n, 1),
+                     # the same time against F_lad,min = min(4 X o v^3 n_v, 2 X v^4 + 2 o v^4 n_v) per block;
+                     # with the stored matrix (X after NAF below v^2) that is 4 X o v^3 n_v = (2X/v) x executed
+                     "frac_vs_min_factorisation": (achieved / PEAK_FP64_TFLOPS) * min_factor(xk, vk, p["nocc"])},
         "phases_ms_per_step": {"setup": setup_ms / a.steps, "davidson": dav_ms / a.steps,
                                "sigma": sig_ms / a.steps, "ladder": lad_ms / a.steps,
                                "large_eig": eig_ms / a.steps},
