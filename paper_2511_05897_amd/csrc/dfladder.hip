@@ -55,7 +55,9 @@ template <> struct Out<0> { typedef double T; };
 template <> struct Out<1> { typedef float T; };
 template <> struct Out<2> { typedef __bf16 T; };
 
-template <int P, int TO, int TM, bool BT>
+// VEC: 16-byte loads (K, the row strides, the batch offsets and, for B as [n][k], kin are multiples of
+// the vector and the bases are 16-byte aligned); otherwise element loads with a bound on each element
+template <int P, int TO, int TM, bool BT, bool VEC>
 __global__ __launch_bounds__(DNT, 2) void dfl_kernel(DflArgs g) {
     static_assert(!BT || P == 2, "B given as [n][k] only for BF16");
     typedef typename Prec<P>::T T;
@@ -113,59 +115,92 @@ __global__ __launch_bounds__(DNT, 2) void dfl_kernel(DflArgs g) {
         }
     }
     VT ra[PA], rb[PB];
+    // per-thread row pointers, fixed for the whole K loop
+    const T* ap[PA];
+    bool aok[PA];
+#pragma unroll
+    for (int p = 0; p < PA; ++p) {
+        const long long m = m0 + arow[p];
+        aok[p] = arow[p] >= 0 && m < g.M;
+        ap[p] = A + (aok[p] ? m * g.lda : 0) + W * akq[p];
+    }
+    const T* bp[PB];
+    bool bok[PB];
+#pragma unroll
+    for (int p = 0; p < PB; ++p) {
+        if constexpr (BT) {
+            const long long n = n0 + bkr[p];
+            bok[p] = n < g.N;
+            bp[p] = B + (bok[p] ? n * g.ldb : 0);
+        } else {
+            const long long n = n0 + W * bnq[p];
+            bok[p] = VEC ? n < g.N : true;
+            bp[p] = B + (long long)bkr[p] * g.ldb + n;
+        }
+    }
+    // B as [n][k]: k0 = kq * kin + kr, advanced by BK per slab without a division (kin >= BK)
+    const bool kstep = g.kin >= BK;
+    int kq = 0, kr = 0;
     auto fetch = [&](int k0) {
+        const VT zv = {};
 #pragma unroll
         for (int p = 0; p < PA; ++p) {
-            const long long m = m0 + arow[p];
             const int k = k0 + W * akq[p];
-            VT x;
-#pragma unroll
-            for (int e = 0; e < W; ++e) x[e] = (T)0.0f;
-            if (arow[p] >= 0 && m < g.M) {
-                const T* src = A + m * g.lda + k;
-                if (g.vec) {
-                    if (k < K) x = *(const VT*)src;
-                } else {
+            VT x = zv;
+            if constexpr (VEC) {
+                if (aok[p] && k < K) x = *(const VT*)(ap[p] + k0);
+            } else {
+                if (aok[p]) {
 #pragma unroll
                     for (int e = 0; e < W; ++e)
-                        if (k + e < K) x[e] = src[e];
+                        if (k + e < K) x[e] = ap[p][k0 + e];
                 }
             }
             ra[p] = x;
         }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
-            VT x;
-#pragma unroll
-            for (int e = 0; e < W; ++e) x[e] = (T)0.0f;
+            VT x = zv;
             if constexpr (BT) {
-                const long long n = n0 + bkr[p];
                 const int k = k0 + W * bnq[p];
-                if (n < g.N) {
-                    if (g.vec) {
-                        if (k < K) x = *(const VT*)(B + n * g.ldb + (long long)(k / g.kin) * g.ldbq + k % g.kin);
+                if (bok[p]) {
+                    if constexpr (VEC) {
+                        if (k < K) {
+                            long long off;
+                            if (kstep) {
+                                int r = kr + W * bnq[p], q = kq;
+                                if (r >= g.kin) { r -= g.kin; ++q; }
+                                off = (long long)q * g.ldbq + r;
+                            } else {
+                                off = (long long)(k / g.kin) * g.ldbq + k % g.kin;
+                            }
+                            x = *(const VT*)(bp[p] + off);
+                        }
                     } else {
 #pragma unroll
                         for (int e = 0; e < W; ++e)
-                            if (k + e < K) x[e] = B[n * g.ldb + (long long)((k + e) / g.kin) * g.ldbq + (k + e) % g.kin];
+                            if (k + e < K) x[e] = bp[p][(long long)((k + e) / g.kin) * g.ldbq + (k + e) % g.kin];
                     }
                 }
-                rb[p] = x;
-                continue;
-            }
-            const int k = k0 + bkr[p];
-            const long long n = n0 + W * bnq[p];
-            if (k < K) {
-                const T* src = B + (long long)k * g.ldb + n;
-                if (g.vec) {
-                    if (n < g.N) x = *(const VT*)src;
-                } else {
+            } else {
+                const int k = k0 + bkr[p];
+                if (k < K) {
+                    const T* src = bp[p] + (long long)k0 * g.ldb;
+                    if constexpr (VEC) {
+                        if (bok[p]) x = *(const VT*)src;
+                    } else {
+                        const long long n = n0 + W * bnq[p];
 #pragma unroll
-                    for (int e = 0; e < W; ++e)
-                        if (n + e < g.N) x[e] = src[e];
+                        for (int e = 0; e < W; ++e)
+                            if (n + e < g.N) x[e] = src[e];
+                    }
                 }
             }
             rb[p] = x;
+        }
+        if (kstep) {
+            kr += BK;
+            if (kr >= g.kin) { kr -= g.kin; ++kq; }
         }
     };
     auto stash = [&](int buf) {
@@ -269,7 +304,8 @@ __global__ __launch_bounds__(DNT, 2) void dfl_kernel(DflArgs g) {
 template <int P, int TO, int TM, bool BT>
 void launch_tm(const DflArgs& a, int mtiles, int nbatch, hipStream_t s) {
     dim3 grid((unsigned)((a.N + DBN - 1) / DBN), (unsigned)mtiles, (unsigned)nbatch);
-    hipLaunchKernelGGL((dfl_kernel<P, TO, TM, BT>), grid, dim3(DNT), 0, s, a);
+    if (a.vec) hipLaunchKernelGGL((dfl_kernel<P, TO, TM, BT, true>), grid, dim3(DNT), 0, s, a);
+    else hipLaunchKernelGGL((dfl_kernel<P, TO, TM, BT, false>), grid, dim3(DNT), 0, s, a);
 }
 
 template <int P, int TO, bool BT = false>

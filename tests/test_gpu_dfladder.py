@@ -156,3 +156,29 @@ def test_solve_assembled_ladder_matches_oracle():
         assert [r["nvir_kept"] for r in reps] == list(refp["nvir_kept"])
         assert [r["naux_kept"] for r in reps] == list(refp["naux_kept"])
         assert np.abs(roots - refp["roots"]).max() < tol, prec
+
+
+def test_sigma_graph_replays_with_assembled_ladder():
+    """Sigma passes with the assembled ladder captured into HIP graphs and replayed (FP64 and BF16 contexts),
+    against eager passes, with the program's own eager work between replays."""
+    o, v, X, seed = 3, 16, 24, 6
+    eo, ev, B = synth.make_instance(o, v, X, seed, scale=0.5)
+    P = Problem(eo, ev, B)
+    rng = np.random.default_rng(4)
+    rs = [rng.standard_normal((nv, P.dim())) for nv in (3, 17)]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        for prec in (0, 2):
+            ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, precision=prec, ladder=2)
+            eager = [host(ctx.sigma(dev(r), precision=prec)) for r in rs]
+            for r, e in zip(rs, eager):
+                assert relerr(e, P.sigma(r, 3)) < (1e-11 if prec == 0 else 2e-2)
+            ctx.set_sigma_graphs(True)
+            for rep in range(3):
+                for r, e in zip(rs, eager):
+                    out = host(ctx.sigma(dev(r), precision=prec))
+                    assert np.abs(out - e).max() <= 1e-14 * np.abs(e).max(), (prec, rep)
+                    x = torch.randn(1000, device="cuda", dtype=torch.float64)
+                    (x * 2.0).sum().item()
+            ctx.close()
+    torch.cuda.synchronize()
