@@ -754,7 +754,7 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
                 scale = std::max(scale, std::fabs(res.w[k]));
                 rmax = std::max(rmax, res.rn[k]);
             }
-            const double tau = std::max(conv, (phase == 1 ? 1e-6 : 3e-3) * scale);
+            const double tau = std::max(conv, (phase == 1 ? 1e-7 : 3e-4) * scale);
             bool all_stalled = true;
             for (int k = 0; k < nroots; ++k) {
                 if (res.rn[k] < 0.9 * lp_best[k]) { lp_best[k] = res.rn[k]; lp_stall[k] = 0; } else ++lp_stall[k];
