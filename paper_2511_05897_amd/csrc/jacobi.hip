@@ -2,7 +2,7 @@
 // ("circle method") ordering, so that every round rotates n/2 disjoint index pairs
 // in parallel.  Used for the Rayleigh-Ritz subspace matrix (small, one workgroup,
 // LDS resident), the natural-orbital and recanonicalisation matrices and the
-// natural-auxiliary-function matrix (large, one launch pair per round).
+// natural-auxiliary-function matrix (large, one launch per round, two buffers of A).
 #include "internal.h"
 #include <cmath>
 
@@ -107,21 +107,23 @@ __global__ __launch_bounds__(SNT) void jacobi_small_kernel(double* Ag, int n, do
     for (int i = tid; i < n; i += SNT) w[i] = A[i * ld + i];
 }
 
-// ---------------- large: global memory, one launch pair per round ----------------
-__global__ void jacobi_angles_kernel(const double* A, int n, int np, int r, double* cs) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= np / 2) return;
-    int p, q;
-    pair_of(r, k, np, p, q);
-    double c = 1.0, s = 0.0;
-    if (q < n) rot_of(A[(long long)p * n + p], A[(long long)q * n + q], A[(long long)p * n + q], c, s);
-    cs[2 * k] = c;
-    cs[2 * k + 1] = s;
-}
-
-// block-pair update A[P,P'] <- J_P^T A[P,P'] J_P'  and  V[:,P] <- V[:,P] J_P
-__global__ void jacobi_rotate_kernel(double* A, double* V, int n, int np, int r, const double* cs) {
+// ---------------- large: global memory, one launch per round ----------------
+// One round in one launch: every workgroup forms all the round's rotations from Ain (which no
+// workgroup writes in this round) in LDS, then applies its share of the block updates into Aout.
+// Every element of A belongs to exactly one (row pair, column pair) block, so Aout is written in full;
+// V is updated in place (each (row, pair) element by one thread).
+__global__ void jacobi_round_kernel(const double* Ain, double* Aout, double* V, int n, int np, int r) {
+    extern __shared__ double csh[];  // [2 * npair]
     const int npair = np / 2;
+    for (int k = threadIdx.x; k < npair; k += blockDim.x) {
+        int p, q;
+        pair_of(r, k, np, p, q);
+        double c = 1.0, s = 0.0;
+        if (q < n) rot_of(Ain[(long long)p * n + p], Ain[(long long)q * n + q], Ain[(long long)p * n + q], c, s);
+        csh[2 * k] = c;
+        csh[2 * k + 1] = s;
+    }
+    __syncthreads();
     long long nblk = (long long)npair * npair;
     long long nv = (long long)n * npair;
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nblk + nv;
@@ -131,30 +133,27 @@ __global__ void jacobi_rotate_kernel(double* A, double* V, int n, int np, int r,
             int p1, q1, p2, q2;
             pair_of(r, k1, np, p1, q1);
             pair_of(r, k2, np, p2, q2);
-            double c1 = cs[2 * k1], s1 = cs[2 * k1 + 1], c2 = cs[2 * k2], s2 = cs[2 * k2 + 1];
+            double c1 = csh[2 * k1], s1 = csh[2 * k1 + 1], c2 = csh[2 * k2], s2 = csh[2 * k2 + 1];
             bool v1 = q1 < n, v2 = q2 < n;
-            // rows p1 (and q1 if valid), columns p2 (and q2 if valid)
-            double a = A[(long long)p1 * n + p2];
-            double b = v2 ? A[(long long)p1 * n + q2] : 0.0;
-            double c = v1 ? A[(long long)q1 * n + p2] : 0.0;
-            double d = (v1 && v2) ? A[(long long)q1 * n + q2] : 0.0;
-            // rows: [p;q] <- [c1 -s1; s1 c1] [p;q]
+            double a = Ain[(long long)p1 * n + p2];
+            double b = v2 ? Ain[(long long)p1 * n + q2] : 0.0;
+            double c = v1 ? Ain[(long long)q1 * n + p2] : 0.0;
+            double d = (v1 && v2) ? Ain[(long long)q1 * n + q2] : 0.0;
             double ra = c1 * a - s1 * c, rb = c1 * b - s1 * d;
             double rc = s1 * a + c1 * c, rd = s1 * b + c1 * d;
-            // cols: [p q] <- [p q] [c2 s2; -s2 c2]
             double na = c2 * ra - s2 * rb, nb = s2 * ra + c2 * rb;
             double nc = c2 * rc - s2 * rd, nd = s2 * rc + c2 * rd;
-            A[(long long)p1 * n + p2] = na;
-            if (v2) A[(long long)p1 * n + q2] = nb;
-            if (v1) A[(long long)q1 * n + p2] = nc;
-            if (v1 && v2) A[(long long)q1 * n + q2] = nd;
+            Aout[(long long)p1 * n + p2] = na;
+            if (v2) Aout[(long long)p1 * n + q2] = nb;
+            if (v1) Aout[(long long)q1 * n + p2] = nc;
+            if (v1 && v2) Aout[(long long)q1 * n + q2] = nd;
         } else {
             long long u = t - nblk;
             int k = (int)(u / n), i = (int)(u % n);
             int p, q;
             pair_of(r, k, np, p, q);
             if (q >= n) continue;
-            double c = cs[2 * k], s = cs[2 * k + 1];
+            double c = csh[2 * k], s = csh[2 * k + 1];
             double vip = V[(long long)i * n + p], viq = V[(long long)i * n + q];
             V[(long long)i * n + p] = c * vip - s * viq;
             V[(long long)i * n + q] = s * vip + c * viq;
@@ -239,7 +238,8 @@ void eig_small(double* A, int n, double* w, double* V, hipStream_t s) {
     LAUNCHCHK();
 }
 
-size_t eig_large_scratch(int n) { return (size_t)(n + 2) + 4; }
+// second copy of A (rounds alternate between the two) + norms
+size_t eig_large_scratch(int n) { return (size_t)n * n + 8; }
 
 void eig_large(double* A, int n, double* w, double* V, double* scratch, hipStream_t s) {
     if (g_dry) return;
@@ -247,27 +247,31 @@ void eig_large(double* A, int n, double* w, double* V, double* scratch, hipStrea
     if (n <= 0) return;
     if (n <= SMALL_MAX) { eig_small(A, n, w, V, s); return; }
     const int np = n + (n & 1);
-    double* cs = scratch;            // np doubles
-    double* nrm = scratch + np;      // 2 doubles
+    double* A2 = scratch;                  // n*n doubles: the other buffer of the rounds
+    double* nrm = scratch + (long long)n * n;  // 2 doubles
     hipLaunchKernelGGL(eye_kernel, dim3(256), dim3(256), 0, s, V, n);
     LAUNCHCHK();
     long long work = (long long)(np / 2) * (np / 2) + (long long)n * (np / 2);
     unsigned gb = (unsigned)std::min<long long>((work + 255) / 256, 4096);
+    const size_t lds = (size_t)np * sizeof(double);  // 2 * (np/2) rotation coefficients
+    if (lds > 64 * 1024) fail(-1, "eig_large: n too large");
+    double* cur = A;
+    double* nxt = A2;
     double hn[2];
     for (int sweep = 0; sweep < 60; ++sweep) {
-        hipLaunchKernelGGL(offnorm_kernel, dim3(1), dim3(1024), 0, s, A, n, nrm);
+        hipLaunchKernelGGL(offnorm_kernel, dim3(1), dim3(1024), 0, s, cur, n, nrm);
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(hn, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (!std::isfinite(hn[0]) || !std::isfinite(hn[1])) fail(-4, "eigensolver: non-finite matrix");
         if (hn[0] <= 1e-30 * hn[1] || hn[0] == 0.0) break;
         for (int r = 0; r < np - 1; ++r) {
-            hipLaunchKernelGGL(jacobi_angles_kernel, dim3((np / 2 + 255) / 256), dim3(256), 0, s, A, n, np, r, cs);
-            hipLaunchKernelGGL(jacobi_rotate_kernel, dim3(gb), dim3(256), 0, s, A, V, n, np, r, cs);
+            hipLaunchKernelGGL(jacobi_round_kernel, dim3(gb), dim3(256), lds, s, cur, nxt, V, n, np, r);
+            std::swap(cur, nxt);
         }
         LAUNCHCHK();
     }
-    hipLaunchKernelGGL(diag_out_kernel, dim3((n + 255) / 256), dim3(256), 0, s, A, n, w);
+    hipLaunchKernelGGL(diag_out_kernel, dim3((n + 255) / 256), dim3(256), 0, s, cur, n, w);
     LAUNCHCHK();
 }
 
