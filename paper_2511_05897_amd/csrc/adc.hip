@@ -461,7 +461,9 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
             k_copy2d(zb, ovv, rr + v, N, nv, ovv, 1.0, 0.0, s);
             // ladder: sum_cd (ac|bd) z_cd  (G symmetric)
             if (c->df) {
-                // assembled from Bvv: 4 X M v^3 flops; the intermediate is written and read once
+                // assembled from Bvv: 4 X M v^3 flops; the intermediate is written and read once (and its
+                // region is reused by the particle-hole terms below)
+                const size_t mk = ws.mark();
                 const int M = nv * o, X = c->X;
                 const long long ve = df_v_elems(M, v, X);
                 const double eb = prec == 0 ? 8.0 : prec == 1 ? 4.0 : 2.0;
@@ -480,6 +482,7 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                     double* V = take(ws, ve);
                     df_ladder(0, M, v, X, c->Bvv, zb, c->sb, false, V, ve, s);
                 }
+                ws.release(mk);
             } else if (prec > 0) {
                 const double fl = 2.0 * nv * o * (double)vv * vv;
                 const double by = (prec == 1 ? 4.0 : 2.0) * (double)vv * vv + 16.0 * nv * o * vv;
@@ -514,13 +517,31 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                     gemm_rm(M, (int)vv, (int)vv, 1.0, zb, vv, false, c->G, vv, false, 0.0, c->sb, vv, s, 1);
                 }
             }
-            // particle-hole terms on the alpha-beta determinants
-            k_z_to_x(zb, c->xb, c->xtb, (long long)nv * o, v, s);
-            TV tx(c->xb, {nv, o, v, v}), txt(c->xtb, {nv, o, v, v});
-            ein(ws, "ibjd,njad->niab", 1.0, TV(c->ovov, {o, v, o, v}), txt, 0.0, c->sdb, s);
-            ein(ws, "ibjd,njad->niab", -1.0, TV(c->P1, {o, v, o, v}), tx, 1.0, c->sdb, s);
-            ein(ws, "iajd,njdb->niab", -1.0, TV(c->P2, {o, v, o, v}), tx, 1.0, c->sdb, s);
-            k_d_to_z_add(c->sb, c->sdb, (long long)nv * o, v, s);
+            // particle-hole terms on the alpha-beta determinants x (z = S + sqrt3 A of x per block):
+            //   d[n][i][a][b] = sum_jd (ib|jd) xt[n][j][a][d] - (ij|bd) x[n][j][a][d] - (ij|ad) x[n][j][d][b]
+            // as three GEMMs with rows (n,a) against the symmetric [(j,d)][(i,b)] matrices ovov, P1, P2
+            // (the ladder tile streams each once per row tile), then sigma_z += S(d) + sqrt3 A(d)
+            {
+                const int Mph = nv * v, ovi = o * v;
+                double *Y1 = c->xb, *Y2 = c->xtb, *Y3 = c->sdb;
+                k_ph_prep(zb, Y1, Y2, Y3, nv, o, v, s);
+                double* C12 = zb;  // z is not needed any more
+                double* C3 = take(ws, NVMAX * (long long)o * vv);
+                const long long pe = NVMAX * (long long)o * vv;
+                double* part = take(ws, pe);
+                if (ladder_supported(Mph, ovi, ovi, Y1, ovi, c->ovov, ovi, C12, ovi)) {
+                    // the tuner's trial launches write C12 = Y1 ovov, which the first product overwrites
+                    const int nch = ladder_tuned_chunks(0, Mph, ovi, ovi, Y1, ovi, c->ovov, ovi, C12, ovi, part, pe, s);
+                    ladder_gemm(Mph, ovi, ovi, 1.0, Y1, ovi, c->ovov, ovi, 0.0, C12, ovi, nch, part, pe, s, 2);
+                    ladder_gemm(Mph, ovi, ovi, -1.0, Y2, ovi, c->P1, ovi, 1.0, C12, ovi, nch, part, pe, s, 2);
+                    ladder_gemm(Mph, ovi, ovi, 1.0, Y3, ovi, c->P2, ovi, 0.0, C3, ovi, nch, part, pe, s, 2);
+                } else {
+                    gemm_rm(Mph, ovi, ovi, 1.0, Y1, ovi, false, c->ovov, ovi, false, 0.0, C12, ovi, s);
+                    gemm_rm(Mph, ovi, ovi, -1.0, Y2, ovi, false, c->P1, ovi, false, 1.0, C12, ovi, s);
+                    gemm_rm(Mph, ovi, ovi, 1.0, Y3, ovi, false, c->P2, ovi, false, 0.0, C3, ovi, s);
+                }
+                k_ph_fin(c->sb, C12, C3, nv, o, v, s);
+            }
             k_copy2d(ss + v, N, c->sb, ovv, nv, ovv, 1.0, 1.0, s);
         }
     }

@@ -194,6 +194,41 @@ __global__ void d_to_z_add_kernel(double* acc, const double* d, long long nblk, 
     }
 }
 
+// Operands of the particle-hole terms, from z (blocks [n][j] of v x v, x = z_S + z_A/sqrt3 per block):
+//   Y2[(n,a)][(j,d)] = x[n][j][a][d],  Y1 = 2 x[n][j][a][d] - x[n][j][d][a],  Y3[(n,a)][(j,d)] = x[n][j][d][a]
+// rows (n,a) of length o*v, so that each term is one GEMM against a symmetric [(j,d)][(i,b)] matrix.
+__global__ void ph_prep_kernel(const double* z, double* Y1, double* Y2, double* Y3, int nv, int o, int v) {
+    const double is3 = 0.57735026918962576451;  // 1/sqrt(3)
+    const long long vv = (long long)v * v, ov = (long long)o * v, tot = (long long)nv * o * vv;
+    GRID_STRIDE(t, tot) {
+        const long long blk = t / vv;  // n * o + j
+        const int r = (int)(t % vv), a = r / v, d = r % v;
+        const int n = (int)(blk / o), j = (int)(blk % o);
+        const double zad = z[t], zda = z[blk * vv + (long long)d * v + a];
+        const double sy = 0.5 * (zad + zda), an = 0.5 * (zad - zda);
+        const double xad = sy + an * is3, xda = sy - an * is3;
+        const long long out = ((long long)n * v + a) * ov + (long long)j * v + d;
+        Y1[out] = 2.0 * xad - xda;
+        Y2[out] = xad;
+        Y3[out] = xda;
+    }
+}
+
+// acc[n][i][a][b] += S(d) + sqrt3 A(d) over (a,b), d[n][i][a][b] = C12[(n,a)][(i,b)] - C3[(n,b)][(i,a)]
+__global__ void ph_fin_kernel(double* acc, const double* C12, const double* C3, int nv, int o, int v) {
+    const double s3 = 1.73205080756887729353;
+    const long long vv = (long long)v * v, ov = (long long)o * v, tot = (long long)nv * o * vv;
+    GRID_STRIDE(t, tot) {
+        const long long blk = t / vv;  // n * o + i
+        const int r = (int)(t % vv), a = r / v, b = r % v;
+        const long long n = blk / o, i = blk % o;
+        const long long ra = (n * v + a) * ov + i * v, rb = (n * v + b) * ov + i * v;
+        const double dab = C12[ra + b] - C3[rb + a];
+        const double dba = C12[rb + a] - C3[ra + b];
+        acc[t] += 0.5 * (dab + dba) + s3 * 0.5 * (dab - dba);
+    }
+}
+
 __global__ void k0_add_kernel(double* s2, const double* z, const double* eo, const double* ev, int o, int v,
                               int nvec, long long ld) {
     long long per = (long long)o * v * v, tot = per * nvec;
@@ -428,6 +463,20 @@ void k_z_to_x(const double* z, double* x, double* xt, long long nblk, int v, hip
     long long n = nblk * v * v;
     if (n <= 0) return;
     hipLaunchKernelGGL(z_to_x_kernel, dim3(nblocks(n)), dim3(NT), 0, s, z, x, xt, nblk, v);
+    LAUNCHCHK();
+}
+void k_ph_prep(const double* z, double* Y1, double* Y2, double* Y3, int nv, int o, int v, hipStream_t s) {
+    if (g_dry) return;
+    long long n = (long long)nv * o * v * v;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(ph_prep_kernel, dim3(nblocks(n)), dim3(NT), 0, s, z, Y1, Y2, Y3, nv, o, v);
+    LAUNCHCHK();
+}
+void k_ph_fin(double* acc, const double* C12, const double* C3, int nv, int o, int v, hipStream_t s) {
+    if (g_dry) return;
+    long long n = (long long)nv * o * v * v;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(ph_fin_kernel, dim3(nblocks(n)), dim3(NT), 0, s, acc, C12, C3, nv, o, v);
     LAUNCHCHK();
 }
 void k_d_to_z_add(double* acc, const double* d, long long nblk, int v, hipStream_t s) {

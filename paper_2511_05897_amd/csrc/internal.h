@@ -180,6 +180,11 @@ void k_check_B(const double* B, int X, int n, double* flags, hipStream_t s);
 void k_z_to_x(const double* z, double* x, double* xt, long long nblk, int v, hipStream_t s);
 // acc += S(d) + sqrt3*A(d)
 void k_d_to_z_add(double* acc, const double* d, long long nblk, int v, hipStream_t s);
+// particle-hole terms: operands from z ([nv][o] blocks of v x v) as rows (n,a) x cols (j,d):
+// Y2 = x[n][j][a][d], Y1 = 2x[n][j][a][d] - x[n][j][d][a], Y3 = x[n][j][d][a]
+void k_ph_prep(const double* z, double* Y1, double* Y2, double* Y3, int nv, int o, int v, hipStream_t s);
+// acc[n][i][a][b] += S(d) + sqrt3 A(d), d[n][i][a][b] = C12[(n,a)][(i,b)] - C3[(n,b)][(i,a)]
+void k_ph_fin(double* acc, const double* C12, const double* C3, int nv, int o, int v, hipStream_t s);
 // sigma2 += K0 * z, K0[i][a][b] = ev_a + ev_b - eo_i;  z/sigma2 with vector stride ld
 void k_k0_add(double* s2, const double* z, const double* eo, const double* ev, int o, int v, int nvec,
               long long ld, hipStream_t s);
