@@ -732,7 +732,7 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     int it_lp = 0;
     sigma_impl(c, ws, V, S, m, s, phase);
     k_dots(V, N, m, S, N, m, N, Gf, mmax, part, s);
-    std::vector<double> thold(nroots, INFINITY), hw(mmax), hrn(nroots * nroots), prev_rn(nroots, INFINITY);
+    std::vector<double> thold(nroots, INFINITY), hrn(nroots * nroots + nroots), prev_rn(nroots, INFINITY);
     std::vector<char> mlp_on(nroots, (use_mlp && c->mlp_w) ? 1 : 0);
     std::vector<double> mlp_best(nroots, INFINITY);
     std::vector<int> mlp_stall(nroots, 0);
@@ -746,8 +746,6 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
         k_symmetrize(Gm, m, s);
         eig_small(Gm, m, ev, Y, s);
         k_sort_eig(ev, Y, m, 0, Gw, Gw + m, s);  // ascending, deterministic signs
-        d2h(hw.data(), ev, m * sizeof(double), s);
-        for (int k = 0; k < nroots; ++k) res.w[k] = hw[k];
         // Ritz vectors X = Y^T V, AX = Y^T S (first nroots columns of Y)
         k_copy2d(coef, nroots, Y, m, m, nroots, 1.0, 0.0, s);
         k_lincomb(Xr, N, nroots, V, N, m, coef, nroots, N, 1.0, 0.0, s);
@@ -755,7 +753,10 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
         k_copy(th, ev, nroots, s);
         k_residual(R, AX, Xr, th, nroots, N, s);
         k_dots(R, N, nroots, R, N, nroots, N, Gw, nroots, part, s);
-        d2h(hrn.data(), Gw, (size_t)nroots * nroots * sizeof(double), s);
+        // the Ritz values travel with the residual Gram: one read-back per iteration
+        k_copy(Gw + (long long)nroots * nroots, ev, nroots, s);
+        d2h(hrn.data(), Gw, (size_t)(nroots * nroots + nroots) * sizeof(double), s);
+        for (int k = 0; k < nroots; ++k) res.w[k] = hrn[(size_t)nroots * nroots + k];
         std::vector<int> todo;
         bool finite = true;
         for (int k = 0; k < nroots; ++k) {
