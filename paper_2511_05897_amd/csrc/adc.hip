@@ -706,9 +706,27 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
     const int ng = guess ? std::min(nguess_in, nguess) : 0;
     std::vector<double> hd(N);
     d2h(hd.data(), c->diag, N * sizeof(double), s);
-    std::vector<long long> idx(N);
-    for (long long i = 0; i < N; ++i) idx[i] = i;
-    std::stable_sort(idx.begin(), idx.end(), [&](long long a, long long b) { return hd[a] < hd[b]; });
+    // the (nguess - ng) lowest (value, index) pairs, ascending: a bounded max-heap, O(N log k), gives the
+    // same entries as a stable sort of all N by value
+    const int kneed = nguess - ng;
+    std::vector<long long> idx;
+    if (kneed > 0) {
+        std::vector<std::pair<double, long long>> heap;
+        heap.reserve(kneed + 1);
+        for (long long i = 0; i < N; ++i) {
+            const std::pair<double, long long> e(hd[i], i);
+            if ((int)heap.size() < kneed) {
+                heap.push_back(e);
+                std::push_heap(heap.begin(), heap.end());
+            } else if (e < heap.front()) {
+                std::pop_heap(heap.begin(), heap.end());
+                heap.back() = e;
+                std::push_heap(heap.begin(), heap.end());
+            }
+        }
+        std::sort_heap(heap.begin(), heap.end());
+        for (const auto& e : heap) idx.push_back(e.second);
+    }
     k_fill(V, (long long)nguess * N, 0.0, s);
     if (ng > 0) k_copy(V, guess, (long long)ng * N, s);
     std::vector<double> one(1, 1.0);
