@@ -70,18 +70,30 @@ LADDER_TRAFFIC = {
 }
 
 
+def stored_pair_elems(v):
+    """Elements of the stored ladder's pair blocks (c <= d and c < d sides, each padded to a multiple of 8)."""
+    lp = (v * (v + 1) // 2 + 7) // 8 * 8
+    lm = (v * (v - 1) // 2 + 7) // 8 * 8
+    return lp * lp + lm * lm
+
+
 def min_factor(X, v, o, nv_max=16):
-    """F_lad,min / executed flops of a stored-ladder block of n_v vectors (executed: 2 o v^4 n_v), taking
-    the smaller ratio over n_v = 1..nv_max so the figure is never overstated."""
-    r = [min(4.0 * X * o * v ** 3 * n, 2.0 * X * v ** 4 + 2.0 * o * v ** 4 * n) / (2.0 * o * v ** 4 * n)
-         for n in range(1, nv_max + 1)]
+    """F_lad,min / executed flops of a stored-ladder block of n_v vectors, executed = 2 o n_v (lp^2 + lm^2)
+    (the two pair blocks, about o v^4 n_v), F_lad,min = min(4 X o v^3 n_v (assembled from the factor),
+    executed); the smaller ratio over n_v = 1..nv_max, so the figure is never overstated."""
+    ex = [2.0 * o * n * stored_pair_elems(v) for n in range(1, nv_max + 1)]
+    r = [min(4.0 * X * o * v ** 3 * n, e) / e for n, e in zip(range(1, nv_max + 1), ex)]
     return min(r)
 
 
 def ladder_traffic():
+    """The ladder kernel's source and the pair-block packing that sets its launch shapes, hashed together."""
     import hashlib
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_05897_amd", "csrc", "ladder.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2511_05897_amd", "csrc")
+    h = hashlib.sha256()
+    for f in ("ladder.hip", "ladder_sa.hip"):
+        h.update(open(os.path.join(d, f), "rb").read())
+    h = h.hexdigest()[:16]
     return h, LADDER_TRAFFIC.get(h)
 
 
@@ -581,8 +593,8 @@ def main():
                      "bound_time_frac": lad_bound / lad_ms if lad_ms > 0 else None,
                      "launches": lad_n, "avg_launch_ms": lad_ms / max(lad_n, 1),
                      "flops_per_launch": lad_f / max(lad_n, 1),
-                     # the same time against F_lad,min = min(4 X o v^3 n_v, 2 X v^4 + 2 o v^4 n_v) per block;
-                     # with the stored matrix (X after NAF below v^2) that is 4 X o v^3 n_v = (2X/v) x executed
+                     # the same time against F_lad,min = min(4 X o v^3 n_v, executed) per block (the stored pair
+                     # blocks execute about o v^4 n_v flops, below the assembled form's when 4 X > v)
                      "frac_vs_min_factorisation": (achieved / PEAK_FP64_TFLOPS) * min_factor(xk, vk, p["nocc"])},
         "phases_ms_per_step": {"setup": setup_ms / a.steps, "davidson": dav_ms / a.steps,
                                "sigma": sig_ms / a.steps, "ladder": lad_ms / a.steps,

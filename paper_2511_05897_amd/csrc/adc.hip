@@ -94,7 +94,9 @@ struct Ctx {
     // eigendecomposition of M11 for the block preconditioner (computed on first use)
     double *m11_Q = nullptr, *m11_w = nullptr, *m11_tmp = nullptr;
     bool m11_eig = false;
-    double *G = nullptr;      // ladder (ac|bd) as [(ab),(cd)], level 3 (stored form)
+    // stored ladder (level 3): the pair-symmetric block G+ [sa_lp(v)]^2 followed by the antisymmetric
+    // block G- [sa_lm(v)]^2 (Gm points at it)
+    double *G = nullptr, *Gm = nullptr;
     bool df = false;          // ladder assembled from Bvv in every application instead of stored
     double *P1 = nullptr;     // (ij|bd) as [i][b][j][d], level 3
     double *P2 = nullptr;     // (ij|ad) as [i][a][j][d], level 3
@@ -102,7 +104,8 @@ struct Ctx {
     long long sigma_count = 0;
     // reduced-precision copies (precision 1: FP32 ladder and coupling; 2: BF16 ladder, FP32 coupling)
     int prec = 0;
-    void* Glo = nullptr;
+    void* Glo = nullptr;    // reduced-precision G+ followed by G-
+    void* Gmlo = nullptr;
     void* Bvvlo = nullptr;  // reduced-precision Bvv for the assembled ladder
     float* Bvv32 = nullptr; // BF16 contexts with the assembled ladder: an FP32 Bvv as well (middle phase)
     void* zlo = nullptr;  // reduced-precision copy of the ladder's input rows
@@ -124,9 +127,10 @@ struct Ctx {
 
 static double* take(Arena& ws, long long n) { return ws.take<double>((size_t)std::max<long long>(n, 1)); }
 
-// The ladder is assembled from Bvv in each application (instead of stored as the v^4 matrix) when the
-// stored matrix would not leave room for the rest: above 96 GB in FP64 (v > 331).
-static bool ladder_df_auto(int v) { return (double)v * v * (double)v * v * 8.0 > 96e9; }
+// The ladder is assembled from Bvv in each application (instead of stored) when the stored blocks
+// (about v^4 / 2 elements) would not leave room for the rest: above 96 GB in FP64 (v > 393).
+static long long stored_ladder_elems(int v) { return sa_lp(v) * sa_lp(v) + sa_lm(v) * sa_lm(v); }
+static bool ladder_df_auto(int v) { return (double)stored_ladder_elems(v) * 8.0 > 96e9; }
 // Element budget of one chunk of the large setup tensors (o*na*v^2 per tensor of the coupling build);
 // the assembled ladder's intermediate gets twice this.
 static std::atomic<long long> g_chunk_elems{1LL << 29};
@@ -185,12 +189,14 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     if (prec > 0) {
         c->Uz32 = ws.take<float>((size_t)std::max<long long>(v * (long long)o * vv, 1));
         if (level >= 3) {
-            const long long ng = c->df ? std::max<long long>((long long)X * vv, 1) : vv * vv;
+            const long long ng = c->df ? std::max<long long>((long long)X * vv, 1) : stored_ladder_elems(v);
             void*& lo = c->df ? c->Bvvlo : c->Glo;
             if (prec == 1) lo = ws.take<float>((size_t)ng);
             else lo = ws.take<unsigned short>((size_t)ng);
+            if (!c->df && lo) c->Gmlo = (char*)lo + sa_lp(v) * sa_lp(v) * (prec == 1 ? 4 : 2);
             if (prec == 2 && c->df) c->Bvv32 = ws.take<float>((size_t)ng);
-            c->zlo = ws.take<float>((size_t)(NVMAX * (long long)o * vv));
+            // the ladder's input rows: v^2 elements (assembled) or the two packed blocks (stored)
+            c->zlo = ws.take<float>((size_t)(NVMAX * (long long)o * (sa_lp(v) + sa_lm(v))));
         }
     }
     c->mlp_wb = ws.take<unsigned short>(256 * 256);
@@ -293,7 +299,10 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     }
     ws.release(mark0);
     if (level >= 3) {
-        if (!c->df) c->G = take(ws, vv * vv);  // kept with the context
+        if (!c->df) {
+            c->G = take(ws, stored_ladder_elems(v));  // kept with the context
+            c->Gm = c->G + sa_lp(v) * sa_lp(v);
+        }
         const size_t mark1 = ws.mark();
         {
             // phase B: G, then everything of M11 through third order that needs it
@@ -301,22 +310,31 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             double* Tt2 = take(ws, oo * vv);
             k_comb_t(Tt2, T, oo, v, 2.0, -1.0, s);
             double* P = take(ws, vv);
-            // ladder matrix G[(ab),(cd)] = (ac|bd) = sum_Q B^Q_ac B^Q_bd: batch over (a,b)
+            // stored ladder: full rows G[(ab),(cd)] = (ac|bd) = sum_Q B^Q_ac B^Q_bd (b >= a) for a chunk of a,
+            // one batched GEMM per a over b, then folded into the pair blocks G+ and G-
             if (!c->df) {
-                Gemm g;
-                g.M = v; g.N = v; g.K = X;
-                g.A = Bvv; g.sAm = 1; g.sAk = vv;  // A(c,Q) = Bvv[Q][a][c], batch offset a*v
-                g.B = Bvv; g.sBk = vv; g.sBn = 1;  // B(Q,d) = Bvv[Q][b][d], batch offset b*v
-                g.C = c->G; g.sCm = v; g.sCn = 1;  // C[a][b][c][d]
-                g.nb0 = v; g.bA0 = 0; g.bB0 = v; g.bC0 = vv;          // b0 = b
-                for (int a0 = 0; a0 < v; a0 += std::max(1, 65535 / v)) {
-                    int na = std::min(v - a0, std::max(1, 65535 / v));
-                    Gemm h = g;
-                    h.A = Bvv + (long long)a0 * v;
-                    h.C = c->G + (long long)a0 * v * vv;
-                    h.nb1 = na; h.bA1 = v; h.bB1 = 0; h.bC1 = v * vv;  // b1 = a - a0
-                    gemm(h, s);
+                const long long v3 = (long long)v * vv;
+                // chunk: at most an eighth of the stored blocks (and the chunk budget)
+                const long long budget = std::min<long long>(g_chunk_elems.load(), stored_ladder_elems(v) / 8);
+                const int na = (int)std::max<long long>(
+                    1, std::min<long long>({(long long)v, budget / std::max<long long>(v3, 1), 65535 / v}));
+                const size_t mg = ws.mark();
+                double* Gf = take(ws, (long long)na * v3);
+                for (int a0 = 0; a0 < v; a0 += na) {
+                    const int nc = std::min(na, v - a0);
+                    for (int a = a0; a < a0 + nc; ++a) {
+                        Gemm g;
+                        g.M = v; g.N = v; g.K = X;
+                        g.A = Bvv + (long long)a * v; g.sAm = 1; g.sAk = vv;  // A(c,Q) = Bvv[Q][a][c]
+                        g.B = Bvv + (long long)a * v; g.sBk = vv; g.sBn = 1;  // B(Q,d) = Bvv[Q][b][d], b from a
+                        g.C = Gf + (long long)(a - a0) * v3 + (long long)a * vv; g.sCm = v; g.sCn = 1;
+                        g.nb0 = v - a; g.bB0 = v; g.bC0 = vv;
+                        gemm(g, s);
+                    }
+                    k_sa_form(Gf, a0, nc, v, c->G, c->Gm, s);
                 }
+                k_sa_zero_pad_rows(c->G, c->Gm, v, s);
+                ws.release(mg);
             }
             double* oooo = take(ws, oo * oo);
             ein(ws, "Qij,Qkl->ijkl", 1.0, TV(Boo, {X, o, o}), TV(Boo, {X, o, o}), 0.0, oooo, s);
@@ -332,7 +350,16 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
                 double* pr = take(ws, 2 * np * vv);
                 df_ladder_pairs(o, v, X, Bvv, T, L, pr, Vt, ve, s);
             } else {
-                gemm_rm((int)oo, (int)vv, (int)vv, 1.0, T, vv, false, c->G, vv, false, 0.0, L, vv, s);
+                // through the pair blocks: L = unpack(G+ w+(T), G- w-(T))
+                const long long lp = sa_lp(v), lm = sa_lm(v);
+                double* W = take(ws, oo * (lp + lm));
+                double* CW = take(ws, oo * (lp + lm));
+                k_sa_pack(T, vv, (int)oo, v, W, W + oo * lp, s);
+                gemm_rm((int)oo, (int)lp, (int)lp, 1.0, W, lp, false, c->G, lp, false, 0.0, CW, lp, s);
+                if (lm > 0)
+                    gemm_rm((int)oo, (int)lm, (int)lm, 1.0, W + oo * lp, lm, false, c->Gm, lm, false, 0.0, CW + oo * lp,
+                            lm, s);
+                k_sa_unpack(CW, CW + oo * lp, (int)oo, v, L, vv, s);
             }
             double* Y = take(ws, oo * vv);
             k_copy(Y, L, oo * vv, s);
@@ -421,7 +448,7 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             k_to_lowp(c->Bvvlo, c->Bvv, (long long)X * vv, prec, s);
             if (c->Bvv32) k_to_lowp(c->Bvv32, c->Bvv, (long long)X * vv, 1, s);
         } else if (level >= 3) {
-            k_to_lowp(c->Glo, c->G, vv * vv, prec, s);
+            k_to_lowp(c->Glo, c->G, stored_ladder_elems(v), prec, s);
         }
     }
     c->ws = ws;  // snapshot (base/cap/used) for later temporaries
@@ -483,39 +510,55 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                     df_ladder(0, M, v, X, c->Bvv, zb, c->sb, false, V, ve, s);
                 }
                 ws.release(mk);
-            } else if (prec > 0) {
-                const double fl = 2.0 * nv * o * (double)vv * vv;
-                const double by = (prec == 1 ? 4.0 : 2.0) * (double)vv * vv + 16.0 * nv * o * vv;
-                ProfScope p(PROF_LADDER_LP, s, fl, by,
-                            1e3 * std::max(fl / (prec == 1 ? PEAK_FP32_MFMA : PEAK_BF16_MFMA), by / PEAK_HBM));
-                const int M = nv * o;
-                k_to_lowp(c->zlo, zb, (long long)M * vv, prec, s);
-                if (ladder_lp_supported(prec, M, (int)vv, (int)vv, c->zlo, vv, c->Glo, vv, c->sb, vv)) {
-                    const long long pe = 3 * NVMAX * (long long)o * vv;
-                    const int nch =
-                        ladder_tuned_chunks(prec, M, (int)vv, (int)vv, c->zlo, vv, c->Glo, vv, c->sb, vv, c->xb, pe, s);
-                    ladder_gemm_lp(prec, M, (int)vv, (int)vv, 1.0, c->zlo, vv, c->Glo, vv, 0.0, c->sb, vv, nch, c->xb,
-                                   pe, s);
-                } else {
-                    GemmLP g;
-                    g.M = M; g.N = (int)vv; g.K = (int)vv;
-                    g.A = zb; g.sAm = vv; g.sAk = 1;
-                    g.B = c->Glo; g.sBk = vv; g.sBn = 1;
-                    g.C = c->sb; g.sCm = vv; g.sCn = 1;
-                    gemm_lp(g, prec, s, 1);
-                }
             } else {
-                const double fl = 2.0 * nv * o * (double)vv * vv;
-                const double by = 8.0 * ((double)vv * vv + 2.0 * nv * o * vv);
-                ProfScope p(PROF_LADDER, s, fl, by, 1e3 * std::max(fl / PEAK_FP64_MFMA, by / PEAK_HBM));
+                // stored ladder through its pair blocks: w+- = pack(z), C+- = w+- G+-, sigma_z = unpack(C+-);
+                // one profiled launch per block
                 const int M = nv * o;
-                if (ladder_supported(M, (int)vv, (int)vv, zb, vv, c->G, vv, c->sb, vv)) {
-                    const long long pe = 3 * NVMAX * (long long)o * vv;
-                    const int nch = ladder_tuned_chunks(0, M, (int)vv, (int)vv, zb, vv, c->G, vv, c->sb, vv, c->xb, pe, s);
-                    ladder_gemm(M, (int)vv, (int)vv, 1.0, zb, vv, c->G, vv, 0.0, c->sb, vv, nch, c->xb, pe, s);
-                } else {
-                    gemm_rm(M, (int)vv, (int)vv, 1.0, zb, vv, false, c->G, vv, false, 0.0, c->sb, vv, s, 1);
+                const long long lp = sa_lp(v), lm = sa_lm(v);
+                const size_t mk = ws.mark();
+                double* W = take(ws, (long long)M * (lp + lm));
+                double* CW = take(ws, (long long)M * (lp + lm));
+                const long long pe = 3 * NVMAX * (long long)o * vv;
+                k_sa_pack(zb, vv, M, v, W, W + (long long)M * lp, s);
+                if (prec > 0) k_to_lowp(c->zlo, W, (long long)M * (lp + lm), prec, s);
+                const int eb = prec == 0 ? 8 : prec == 1 ? 4 : 2;
+                const double pk = prec == 0 ? PEAK_FP64_MFMA : prec == 1 ? PEAK_FP32_MFMA : PEAK_BF16_MFMA;
+                for (int blk = 0; blk < 2; ++blk) {
+                    const long long n = blk == 0 ? lp : lm;
+                    if (n == 0) continue;
+                    const long long woff = blk == 0 ? 0 : (long long)M * lp;
+                    double* C = CW + woff;
+                    const double fl = 2.0 * M * (double)n * n;
+                    const double by = eb * (double)n * n + (eb + 8.0) * M * (double)n;
+                    ProfScope p(prec > 0 ? PROF_LADDER_LP : PROF_LADDER, s, fl, by,
+                                1e3 * std::max(fl / pk, by / PEAK_HBM));
+                    if (prec > 0) {
+                        const void* Z = (const char*)c->zlo + woff * eb;
+                        const void* Gl = blk == 0 ? c->Glo : c->Gmlo;
+                        if (ladder_lp_supported(prec, M, (int)n, (int)n, Z, n, Gl, n, C, n)) {
+                            const int nch = ladder_tuned_chunks(prec, M, (int)n, (int)n, Z, n, Gl, n, C, n, c->xb, pe, s);
+                            ladder_gemm_lp(prec, M, (int)n, (int)n, 1.0, Z, n, Gl, n, 0.0, C, n, nch, c->xb, pe, s);
+                        } else {
+                            GemmLP g;
+                            g.M = M; g.N = (int)n; g.K = (int)n;
+                            g.A = W + woff; g.sAm = n; g.sAk = 1;
+                            g.B = Gl; g.sBk = n; g.sBn = 1;
+                            g.C = C; g.sCm = n; g.sCn = 1;
+                            gemm_lp(g, prec, s, 1);
+                        }
+                    } else {
+                        const double* Z = W + woff;
+                        const double* Gb = blk == 0 ? c->G : c->Gm;
+                        if (ladder_supported(M, (int)n, (int)n, Z, n, Gb, n, C, n)) {
+                            const int nch = ladder_tuned_chunks(0, M, (int)n, (int)n, Z, n, Gb, n, C, n, c->xb, pe, s);
+                            ladder_gemm(M, (int)n, (int)n, 1.0, Z, n, Gb, n, 0.0, C, n, nch, c->xb, pe, s);
+                        } else {
+                            gemm_rm(M, (int)n, (int)n, 1.0, Z, n, false, Gb, n, false, 0.0, C, n, s, 1);
+                        }
+                    }
                 }
+                k_sa_unpack(CW, CW + (long long)M * lp, M, v, c->sb, vv, s);
+                ws.release(mk);
             }
             // particle-hole terms on the alpha-beta determinants x (z = S + sqrt3 A of x per block):
             //   d[n][i][a][b] = sum_jd (ib|jd) xt[n][j][a][d] - (ij|bd) x[n][j][a][d] - (ij|ad) x[n][j][d][b]

@@ -181,6 +181,18 @@ void k_z_to_x(const double* z, double* x, double* xt, long long nblk, int v, hip
 // acc += S(d) + sqrt3*A(d)
 void k_d_to_z_add(double* acc, const double* d, long long nblk, int v, hipStream_t s);
 // particle-hole terms: operands from z ([nv][o] blocks of v x v) as rows (n,a) x cols (j,d):
+// Stored ladder in pair-symmetric (a <= b) and pair-antisymmetric (a < b) blocks, each padded to a
+// leading dimension that is a multiple of 8 (sa_lp(v), sa_lm(v); the padding is zero).
+long long sa_lp(int v);
+long long sa_lm(int v);
+// w+[m][lp] = z[c][d] + z[d][c] (c < d), z[c][c];  w-[m][lm] = z[c][d] - z[d][c]  (z rows of v*v, stride ldz)
+void k_sa_pack(const double* z, long long ldz, int M, int v, double* Ws, double* Wa, hipStream_t s);
+// out[m][a][b] = C+[(ab)] + C-[(ab)] (a < b), C+[(ba)] - C-[(ba)] (a > b), C+[(aa)]  (row stride ldo)
+void k_sa_unpack(const double* Cs, const double* Ca, int M, int v, double* out, long long ldo, hipStream_t s);
+// G+ / G- rows (a,b), a in [a0, a0+na), from the full rows Gf[a-a0][b][c][d] (b >= a read)
+void k_sa_form(const double* Gf, int a0, int na, int v, double* Gp, double* Gm, hipStream_t s);
+// zero the padding rows of G+ and G-
+void k_sa_zero_pad_rows(double* Gp, double* Gm, int v, hipStream_t s);
 // Y2 = x[n][j][a][d], Y1 = 2x[n][j][a][d] - x[n][j][d][a], Y3 = x[n][j][d][a]
 void k_ph_prep(const double* z, double* Y1, double* Y2, double* Y3, int nv, int o, int v, hipStream_t s);
 // acc[n][i][a][b] += S(d) + sqrt3 A(d), d[n][i][a][b] = C12[(n,a)][(i,b)] - C3[(n,b)][(i,a)]

@@ -1,0 +1,148 @@
+// The stored ladder in pair-symmetric and pair-antisymmetric blocks.
+//
+// The ladder sigma_z[a][b] = sum_cd (ac|bd) z[c][d] maps the part of z that is symmetric under
+// c <-> d to a result symmetric under a <-> b, and the antisymmetric part to an antisymmetric
+// result, because (ac|bd) = (bd|ac) for any real factorisation (pq|rs) = sum_Q B^Q_pq B^Q_rs.
+// So the v^2 x v^2 matrix falls into two blocks over the pairs c <= d and c < d:
+//   G+[(ab),(cd)] = ((ac|bd) + (ad|bc)) / 2   (a <= b, c <= d),  input w+ = z[c][d] + z[d][c] (c < d), z[c][c]
+//   G-[(ab),(cd)] = ((ac|bd) - (ad|bc)) / 2   (a <  b, c <  d),  input w- = z[c][d] - z[d][c]
+// and sigma[a][b] = (G+ w+)[(ab)] + (G- w-)[(ab)] for a < b, (G+ w+)[(ba)] - (G- w-)[(ba)] for a > b,
+// (G+ w+)[(aa)] on the diagonal.  Both blocks are symmetric matrices; together they hold about half
+// of the v^4 elements, so each application streams and multiplies half as much.  This is an exact
+// rearrangement of the contraction (only the rounding order changes).
+//
+// Pair order is row-major over the upper triangle (a, then b).  Each block's leading dimension is
+// padded to a multiple of 8 with zeros (16-byte loads in every precision of the ladder kernels).
+#include "internal.h"
+#include <algorithm>
+
+namespace adc3 {
+
+namespace {
+constexpr int NT = 256;
+
+__device__ inline long long pidx(int a, int b, int v) {  // a <= b
+    return (long long)a * v - (long long)a * (a - 1) / 2 + (b - a);
+}
+__device__ inline long long qidx(int a, int b, int v) {  // a < b
+    return (long long)a * (v - 1) - (long long)a * (a - 1) / 2 + (b - a - 1);
+}
+
+// Rows m of z[m][v][v] (row stride ldz) -> w+[m][lp], w-[m][lm]; the padding columns are zeroed by
+// the threads past M v^2.
+__global__ void sa_pack_kernel(const double* z, long long ldz, int M, int v, double* Ws, double* Wa, long long lp,
+                               long long lm) {
+    const long long vv = (long long)v * v, main = (long long)M * vv, np = (long long)v * (v + 1) / 2,
+                    nm = (long long)v * (v - 1) / 2;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < main + 8LL * M;
+         t += (long long)gridDim.x * blockDim.x) {
+        if (t < main) {
+            const long long m = t / vv;
+            const int r = (int)(t - m * vv), a = r / v, b = r % v;
+            if (a > b) continue;
+            const double* zm = z + m * ldz;
+            if (a == b) {
+                Ws[m * lp + pidx(a, a, v)] = zm[(long long)a * v + a];
+            } else {
+                const double x = zm[(long long)a * v + b], y = zm[(long long)b * v + a];
+                Ws[m * lp + pidx(a, b, v)] = x + y;
+                Wa[m * lm + qidx(a, b, v)] = x - y;
+            }
+        } else {
+            const long long u = t - main, m = u / 8;
+            const int k = (int)(u % 8);
+            if (np + k < lp) Ws[m * lp + np + k] = 0.0;
+            if (nm + k < lm) Wa[m * lm + nm + k] = 0.0;
+        }
+    }
+}
+
+__global__ void sa_unpack_kernel(const double* Cs, const double* Ca, int M, int v, long long lp, long long lm,
+                                 double* out, long long ldo) {
+    const long long vv = (long long)v * v, n = (long long)M * vv;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+        const long long m = t / vv;
+        const int r = (int)(t - m * vv), a = r / v, b = r % v;
+        double x;
+        if (a == b) x = Cs[m * lp + pidx(a, a, v)];
+        else if (a < b) x = Cs[m * lp + pidx(a, b, v)] + Ca[m * lm + qidx(a, b, v)];
+        else x = Cs[m * lp + pidx(b, a, v)] - Ca[m * lm + qidx(b, a, v)];
+        out[m * ldo + r] = x;
+    }
+}
+
+// Gf holds the full ladder rows (a,b) for a in [a0, a0+na), all b, as [a-a0][b][c][d]; only the rows
+// b >= a are read.  One block row per (a,b); columns (c,d) plus 8 padding columns.
+__global__ void sa_form_kernel(const double* Gf, int a0, int v, double* Gp, double* Gm, long long lp, long long lm) {
+    const int r = blockIdx.y, a = a0 + r / v, b = r % v;
+    if (b < a) return;
+    const long long vv = (long long)v * v, np = (long long)v * (v + 1) / 2, nm = (long long)v * (v - 1) / 2;
+    const long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    double* gp = Gp + pidx(a, b, v) * lp;
+    double* gm = a < b ? Gm + qidx(a, b, v) * lm : nullptr;
+    if (t < vv) {
+        const int c = (int)(t / v), d = (int)(t % v);
+        if (c > d) return;
+        const double* row = Gf + (long long)r * vv;
+        const double g1 = row[(long long)c * v + d], g2 = row[(long long)d * v + c];
+        gp[pidx(c, d, v)] = 0.5 * (g1 + g2);
+        if (gm && c < d) gm[qidx(c, d, v)] = 0.5 * (g1 - g2);
+    } else if (t < vv + 8) {
+        const int k = (int)(t - vv);
+        if (np + k < lp) gp[np + k] = 0.0;
+        if (gm && nm + k < lm) gm[nm + k] = 0.0;
+    }
+}
+
+__global__ void sa_zero_rows_kernel(double* Gp, double* Gm, int v, long long lp, long long lm) {
+    const long long np = (long long)v * (v + 1) / 2, nm = (long long)v * (v - 1) / 2;
+    const long long n1 = (lp - np) * lp, n2 = (lm - nm) * lm;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n1 + n2;
+         t += (long long)gridDim.x * blockDim.x) {
+        if (t < n1) Gp[np * lp + t] = 0.0;
+        else Gm[nm * lm + (t - n1)] = 0.0;
+    }
+}
+
+inline unsigned grid_for(long long n) {
+    long long b = (n + NT - 1) / NT;
+    return (unsigned)std::max<long long>(1, std::min<long long>(b, 8192));
+}
+}  // namespace
+
+long long sa_lp(int v) { return ((long long)v * (v + 1) / 2 + 7) / 8 * 8; }
+long long sa_lm(int v) { return ((long long)v * (v - 1) / 2 + 7) / 8 * 8; }
+
+void k_sa_pack(const double* z, long long ldz, int M, int v, double* Ws, double* Wa, hipStream_t s) {
+    if (g_dry || M <= 0 || v <= 0) return;
+    const long long n = (long long)M * v * v + 8LL * M;
+    hipLaunchKernelGGL(sa_pack_kernel, dim3(grid_for(n)), dim3(NT), 0, s, z, ldz, M, v, Ws, Wa, sa_lp(v), sa_lm(v));
+    LAUNCHCHK();
+}
+
+void k_sa_unpack(const double* Cs, const double* Ca, int M, int v, double* out, long long ldo, hipStream_t s) {
+    if (g_dry || M <= 0 || v <= 0) return;
+    hipLaunchKernelGGL(sa_unpack_kernel, dim3(grid_for((long long)M * v * v)), dim3(NT), 0, s, Cs, Ca, M, v, sa_lp(v),
+                       sa_lm(v), out, ldo);
+    LAUNCHCHK();
+}
+
+void k_sa_form(const double* Gf, int a0, int na, int v, double* Gp, double* Gm, hipStream_t s) {
+    if (g_dry || na <= 0 || v <= 0) return;
+    const long long cols = (long long)v * v + 8;
+    if ((long long)na * v > 65535) fail(-1, "k_sa_form: chunk too large");
+    hipLaunchKernelGGL(sa_form_kernel, dim3((unsigned)((cols + NT - 1) / NT), (unsigned)(na * v)), dim3(NT), 0, s, Gf,
+                       a0, v, Gp, Gm, sa_lp(v), sa_lm(v));
+    LAUNCHCHK();
+}
+
+void k_sa_zero_pad_rows(double* Gp, double* Gm, int v, hipStream_t s) {
+    if (g_dry || v <= 0) return;
+    const long long lp = sa_lp(v), lm = sa_lm(v);
+    const long long n = (lp - (long long)v * (v + 1) / 2) * lp + (lm - (long long)v * (v - 1) / 2) * lm;
+    if (n <= 0) return;
+    hipLaunchKernelGGL(sa_zero_rows_kernel, dim3(grid_for(n)), dim3(NT), 0, s, Gp, Gm, v, lp, lm);
+    LAUNCHCHK();
+}
+
+}  // namespace adc3
