@@ -241,7 +241,7 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
         }
         // U_D[a][b][c][i] (first order (ab|ic), second order below) and U_z[a][i][b][c] = S + sqrt3 A over
         // (b,c), in chunks of the first virtual index a when the o v^3 tensors would crowd HBM (each
-        // chunk holds about six tensors of o*na*v^2 elements)
+        // chunk holds a few tensors of o*na*v^2 elements)
         const int na = (int)std::max<long long>(1, std::min<long long>(v, g_chunk_elems.load() / std::max<long long>(o * vv, 1)));
         double *Bvc = nullptr, *Boc = nullptr, *ooc = nullptr;
         if (na < v) {
@@ -250,6 +250,15 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
                 Boc = take(ws, (long long)X * o * na);
                 ooc = take(ws, oo * o * na);
             }
+        }
+        // second-order coupling term sum_kd (2T-T~)_ik^cd (kd|ab) = sum_Q B^Q_ab W^Q_ic, W^Q_ic = sum_kd B^Q_kd
+        // (2T-T~)_ik^cd: folded into the first-order product as B^Q_ab (B^Q_ic + W^Q_ic)
+        const double* Bov_u = Bov;
+        if (level >= 3) {
+            double* Bw = take(ws, X * ov);
+            ein(ws, "Qkd,ikcd->Qic", 1.0, TV(Bov, {X, o, v}), TV(Tt2, {o, o, v, v}), 0.0, Bw, s);
+            k_axpby(Bw, Bov, X * ov, 1.0, 1.0, s);
+            Bov_u = Bw;
         }
         k_fill(c->Uz, vv * ov, 0.0, s);
         for (int a0 = 0; a0 < v; a0 += na) {
@@ -263,9 +272,9 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
                 Bvv_a = Bvc;
             }
             double* Ud = take(ws, E);
-            ein(ws, "Qab,Qic->abci", 1.0, TV(Bvv_a, {X, nc, v}), TV(Bov, {X, o, v}), 0.0, Ud, s);
+            ein(ws, "Qab,Qic->abci", 1.0, TV(Bvv_a, {X, nc, v}), TV(Bov_u, {X, o, v}), 0.0, Ud, s);
             if (level >= 3) {
-                TV tT(T, {o, o, v, v}), tT2(Tt2, {o, o, v, v});
+                TV tT(T, {o, o, v, v});
                 const double *ooov_a = ooov, *Bov_a = Bov;
                 if (na < v) {
                     k_copy2d(ooc, nc, ooov + a0, v, oo * o, nc, 1.0, 0.0, s);
@@ -280,14 +289,6 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
                 ein(ws, "Qka,Qcd->kacd", 1.0, TV(Bov_a, {X, o, nc}), TV(Bvv, {X, v, v}), 0.0, ovvv1, s);
                 TV t1(ovvv1, {o, nc, v, v});
                 ein(ws, "kibd,kacd->abci", -1.0, tT, t1, 1.0, Ud, s);
-                // (kd|ab) for a in the chunk: [k][d][a][b] (the same tensor when there is one chunk)
-                const double* ovvv2 = ovvv1;
-                if (na < v) {
-                    double* t = take(ws, E);
-                    ein(ws, "Qkd,Qab->kdab", 1.0, TV(Bov, {X, o, v}), TV(Bvv_a, {X, nc, v}), 0.0, t, s);
-                    ovvv2 = t;
-                }
-                ein(ws, "ikcd,kdab->abci", 1.0, tT2, TV(ovvv2, {o, v, nc, v}), 1.0, Ud, s);
                 ein(ws, "ikcd,kabd->abci", -1.0, tT, t1, 1.0, Ud, s);
             }
             double* Up = take(ws, E);
