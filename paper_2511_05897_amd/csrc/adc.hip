@@ -563,24 +563,35 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
             }
             // particle-hole terms on the alpha-beta determinants x (z = S + sqrt3 A of x per block):
             //   d[n][i][a][b] = sum_jd (ib|jd) xt[n][j][a][d] - (ij|bd) x[n][j][a][d] - (ij|ad) x[n][j][d][b]
-            // as three GEMMs with rows (n,a) against the symmetric [(j,d)][(i,b)] matrices ovov, P1, P2
-            // (the ladder tile streams each once per row tile), then sigma_z += S(d) + sqrt3 A(d)
+            // with rows (n,a) and columns (i,b): the first product through the DF factor,
+            // (Y1 B^T) B with B = Bov as [Q][(j,d)] (its contraction indices j,d sit in one factor), the other
+            // two as GEMMs against the symmetric [(j,d)][(i,b)] matrices P1, P2 (the ladder tile streams each
+            // once per row tile); then sigma_z += S(d) + sqrt3 A(d)
             {
-                const int Mph = nv * v, ovi = o * v;
+                const int Mph = nv * v, ovi = o * v, X = c->X;
                 double *Y1 = c->xb, *Y2 = c->xtb, *Y3 = c->sdb;
                 k_ph_prep(zb, Y1, Y2, Y3, nv, o, v, s);
                 double* C12 = zb;  // z is not needed any more
                 double* C3 = take(ws, NVMAX * (long long)o * vv);
                 const long long pe = NVMAX * (long long)o * vv;
                 double* part = take(ws, pe);
-                if (ladder_supported(Mph, ovi, ovi, Y1, ovi, c->ovov, ovi, C12, ovi)) {
-                    // the tuner's trial launches write C12 = Y1 ovov, which the first product overwrites
-                    const int nch = ladder_tuned_chunks(0, Mph, ovi, ovi, Y1, ovi, c->ovov, ovi, C12, ovi, part, pe, s);
-                    ladder_gemm(Mph, ovi, ovi, 1.0, Y1, ovi, c->ovov, ovi, 0.0, C12, ovi, nch, part, pe, s, 2);
+                double* Wq = take(ws, (long long)NVMAX * v * X);
+                const bool lad = ladder_supported(Mph, ovi, ovi, Y2, ovi, c->P1, ovi, C12, ovi);
+                // the tuner's trial launches write C12, which the first product overwrites
+                const int nch = lad ? ladder_tuned_chunks(0, Mph, ovi, ovi, Y2, ovi, c->P1, ovi, C12, ovi, part, pe, s) : 1;
+                {
+                    Gemm g;  // Wq[(n,a)][Q] = sum_(j,d) Y1[(n,a)][(j,d)] Bov[Q][(j,d)]
+                    g.M = Mph; g.N = X; g.K = ovi;
+                    g.A = Y1; g.sAm = ovi; g.sAk = 1;
+                    g.B = c->Bov; g.sBk = 1; g.sBn = ovi;
+                    g.C = Wq; g.sCm = X; g.sCn = 1;
+                    gemm_split(g, s);
+                }
+                gemm_rm(Mph, ovi, X, 1.0, Wq, X, false, c->Bov, ovi, false, 0.0, C12, ovi, s);
+                if (lad) {
                     ladder_gemm(Mph, ovi, ovi, -1.0, Y2, ovi, c->P1, ovi, 1.0, C12, ovi, nch, part, pe, s, 2);
                     ladder_gemm(Mph, ovi, ovi, 1.0, Y3, ovi, c->P2, ovi, 0.0, C3, ovi, nch, part, pe, s, 2);
                 } else {
-                    gemm_rm(Mph, ovi, ovi, 1.0, Y1, ovi, false, c->ovov, ovi, false, 0.0, C12, ovi, s);
                     gemm_rm(Mph, ovi, ovi, -1.0, Y2, ovi, false, c->P1, ovi, false, 1.0, C12, ovi, s);
                     gemm_rm(Mph, ovi, ovi, 1.0, Y3, ovi, false, c->P2, ovi, false, 0.0, C3, ovi, s);
                 }

@@ -235,7 +235,13 @@ GemmScratch::~GemmScratch() {
     g_gemm_scratch_n = prev_n;
 }
 
-void gemm(const Gemm& g, hipStream_t s, int tag) {
+static void gemm_impl(const Gemm& g, hipStream_t s, int tag, int kmin_split);
+
+void gemm(const Gemm& g, hipStream_t s, int tag) { gemm_impl(g, s, tag, 4096); }
+
+void gemm_split(const Gemm& g, hipStream_t s, int tag) { gemm_impl(g, s, tag, 512); }
+
+static void gemm_impl(const Gemm& g, hipStream_t s, int tag, int kmin_split) {
     if (g_dry) return;
     if (g.M <= 0 || g.N <= 0) return;
     long long nb = (long long)g.nb0 * g.nb1;
@@ -254,7 +260,7 @@ void gemm(const Gemm& g, hipStream_t s, int tag) {
     const long long MN = (long long)g.M * g.N;
     // few output tiles and a long K: cut K into chunks (one batch each), then sum the
     // partial tiles in a fixed order (deterministic)
-    if (nb == 1 && tiles < 256 && g.K >= 4096 && g_gemm_scratch) {
+    if (nb == 1 && tiles < 256 && g.K >= kmin_split && g_gemm_scratch) {
         long long nchunk = std::min<long long>((g.K + 255) / 256, (2048 + tiles - 1) / tiles);
         nchunk = std::min<long long>(nchunk, g_gemm_scratch_n / std::max<long long>(MN, 1));
         nchunk = std::min<long long>(nchunk, 65535);

@@ -67,6 +67,8 @@ struct Gemm {
     int Klast = -1;  // if >= 0: K of the batches with b0 == nb0-1 (ragged last K chunk)
 };
 void gemm(const Gemm& g, hipStream_t s, int tag = 0);
+// as gemm, but a single GEMM with few output tiles splits K from K >= 512 on (gemm: K >= 4096)
+void gemm_split(const Gemm& g, hipStream_t s, int tag = 0);
 // reduced-precision GEMM, FP32 accumulation, FP64 C (see gemm_lp.hip):
 // A FP64 (converted on load), B in the reduced type (prec 1: float, 2: bf16)
 struct GemmLP {
