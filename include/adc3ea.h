@@ -208,6 +208,19 @@ size_t adc3_ladder_workspace_bytes(int nvir, int naux, int nrows, int precision)
 int adc3_ladder_apply(const double* Bvv_dev, const double* Z_dev, double* C_dev, int nvir, int naux, int nrows,
                       int precision, void* workspace_dev, size_t workspace_bytes, hipStream_t stream);
 
+/* Symmetric eigensolver of the natural-orbital and natural-auxiliary-function steps (Sec.
+ * "Frozen Natural Orbitals", eq 9 and the recanonicalisation of eqs 12-13; Sec. "Natural
+ * Auxiliary Functions", eq 28): FP64 cyclic Jacobi.  A_dev[n][n] device, row-major, read only
+ * (its symmetric part (A + A^T)/2 is diagonalised); w_dev[n] receives the eigenvalues in
+ * ascending order, V_dev[n][n] the eigenvectors as columns (V[i][k] = component i of vector k),
+ * each with its largest-magnitude component positive (first index on ties).  The workspace holds
+ * a copy of A and the solver's scratch: at least adc3_eigh_workspace_bytes(n) bytes.  1 <= n <=
+ * 4096.  Synchronises the stream (the sweep loop reads the off-diagonal norm back);
+ * ADC3_ENUMERIC for a non-finite matrix. */
+size_t adc3_eigh_workspace_bytes(int n);
+int adc3_eigh(const double* A_dev, double* w_dev, double* V_dev, int n, void* workspace_dev, size_t workspace_bytes,
+              hipStream_t stream);
+
 /* Dimension N of the context's vector space. */
 long long adc3_ea_dim(const adc3_ctx* ctx);
 

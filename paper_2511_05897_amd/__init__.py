@@ -26,7 +26,7 @@ EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_byte
            "adc3_mlp_forward", "adc3_mlp_train", "adc3_ea_precondition", "adc3_ea_solve_batched_workspace_bytes",
            "adc3_ea_solve_batched", "adc3_ea_set_sigma_graphs", "adc3_profile_query_bound",
            "adc3_ea_setup_workspace_bytes_ex", "adc3_ea_setup_ex", "adc3_set_chunk_elems",
-           "adc3_ladder_workspace_bytes", "adc3_ladder_apply"]
+           "adc3_ladder_workspace_bytes", "adc3_ladder_apply", "adc3_eigh_workspace_bytes", "adc3_eigh"]
 
 
 class adc3_opts(ctypes.Structure):
@@ -88,6 +88,10 @@ def load():
     lib.adc3_ladder_workspace_bytes.argtypes = [I, I, I, I]
     lib.adc3_ladder_workspace_bytes.restype = S
     lib.adc3_ladder_apply.argtypes = [P, P, P, I, I, I, I, P, S, P]
+    lib.adc3_eigh_workspace_bytes.argtypes = [I]
+    lib.adc3_eigh_workspace_bytes.restype = S
+    lib.adc3_eigh.argtypes = [P, P, P, I, P, S, P]
+    lib.adc3_eigh.restype = I
     lib.adc3_ladder_apply.restype = I
     lib.adc3_ctx_destroy.argtypes = [P]
     lib.adc3_ctx_destroy.restype = None
@@ -274,6 +278,21 @@ def adc3_ladder_apply(Bvv, Z, precision=0, out=None, workspace=None, workspace_b
     _check(load().adc3_ladder_apply(_ptr(Bvv), _ptr(Z), _ptr(out), v, X, M, precision,
                                     ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream()))
     return out
+
+
+def adc3_eigh_workspace_bytes(n):
+    return load().adc3_eigh_workspace_bytes(n)
+
+
+def adc3_eigh(A):
+    """Eigenvalues (ascending) and eigenvectors (columns) of the symmetric part of A [n][n] (FP64 device)."""
+    import torch
+    n = int(A.shape[0])
+    w = torch.empty(n, dtype=torch.float64, device=A.device)
+    V = torch.empty((n, n), dtype=torch.float64, device=A.device)
+    ws = _workspace(adc3_eigh_workspace_bytes(n))
+    _check(load().adc3_eigh(_ptr(A), _ptr(w), _ptr(V), n, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return w, V
 
 
 class Context:

@@ -1591,6 +1591,33 @@ int adc3_ladder_apply(const double* Bvv, const double* Z, double* C, int nvir, i
     API_END
 }
 
+size_t adc3_eigh_workspace_bytes(int n) {
+    if (n <= 0 || n > 4096) return 0;
+    return ((size_t)2 * n * n + eig_large_scratch(n) + n) * sizeof(double) + 4 * 256;
+}
+
+int adc3_eigh(const double* A, double* w, double* V, int n, void* workspace, size_t ws_bytes, hipStream_t stream) {
+    API_BEGIN
+    if (n <= 0 || n > 4096) fail(ADC3_EINVAL, "n must be in 1..4096");
+    if (!A || !w || !V || !workspace) fail(ADC3_EINVAL, "NULL pointer argument");
+    const size_t need = adc3_eigh_workspace_bytes(n);
+    if (ws_bytes < need) fail(ADC3_ENOMEM, "workspace too small: need at least " + std::to_string(need) + " bytes");
+    Arena ws;
+    ws.base = (char*)workspace;
+    ws.cap = ws_bytes;
+    const long long nn = (long long)n * n;
+    double* Ac = take(ws, nn);
+    double* scr = take(ws, (long long)eig_large_scratch(n));
+    double* wt = take(ws, n);
+    double* Vt = take(ws, nn);
+    k_copy(Ac, A, nn, stream);
+    k_symmetrize(Ac, n, stream);
+    eig_large(Ac, n, w, V, scr, stream);
+    k_sort_eig(w, V, n, 0, wt, Vt, stream);
+    return ADC3_OK;
+    API_END
+}
+
 }  // extern "C"
 
 static void validate_inputs(const double* eo, const double* ev, const double* B, int o, int v, int X, hipStream_t s,

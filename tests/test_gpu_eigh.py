@@ -1,0 +1,96 @@
+"""The FP64 symmetric eigensolver of the natural-orbital and NAF steps (adc3_eigh) against
+numpy.linalg.eigh, at sizes that take each of its two forms: n <= 96 (one workgroup, A and V in
+LDS) and n > 96 (one launch per round, two buffers of A).  Spectra: random symmetric matrices, and
+density-matrix-like ones
+(Q diag(lambda) Q^T with lambda spread over 1 .. 1e-12, the occupation spectrum of eq 9).
+
+Tolerances (Jacobi is accurate to rounding in the matrix norm): eigenvalues 1e-12 ||A||_F,
+orthonormality 1e-12, residual ||A V - V diag(w)|| 1e-11 ||A||_F, eigenvectors of well-separated
+eigenvalues equal to numpy's (same sign convention) to 1e-9.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2511_05897_amd as adc  # noqa: E402
+
+SIZES = [1, 2, 7, 96, 97, 150, 200, 333]
+
+
+def sign_fix(V):
+    idx = np.argmax(np.abs(V), axis=0)
+    s = np.sign(V[idx, np.arange(V.shape[1])])
+    s[s == 0] = 1.0
+    return V * s
+
+
+def random_sym(n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n))
+    return 0.5 * (A + A.T)
+
+
+def density_like(n, seed):
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = 10.0 ** rng.uniform(-12, 0, n)
+    return (Q * lam) @ Q.T
+
+
+def check(A):
+    n = A.shape[0]
+    w, V = adc.adc3_eigh(torch.as_tensor(A, device="cuda"))
+    torch.cuda.synchronize()
+    w, V = w.cpu().numpy(), V.cpu().numpy()
+    wr, Vr = np.linalg.eigh(A)
+    nrm = np.linalg.norm(A)
+    assert np.all(np.diff(w) >= 0)
+    assert np.abs(w - wr).max() <= 1e-12 * nrm
+    assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-12
+    assert np.abs(A @ V - V * w).max() <= 1e-11 * nrm
+    # sign convention: the largest-magnitude component of each vector is positive
+    assert np.all(V[np.argmax(np.abs(V), axis=0), np.arange(n)] > 0)
+    # eigenvectors of eigenvalues separated from their neighbours by 1e-3 ||A||
+    gap = np.minimum(np.diff(wr, prepend=-np.inf), np.diff(wr, append=np.inf))
+    sep = gap > 1e-3 * nrm
+    if sep.any():
+        assert np.abs(V[:, sep] - sign_fix(Vr)[:, sep]).max() <= 1e-9
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_eigh_random_symmetric(n):
+    check(random_sym(n, n))
+
+
+@pytest.mark.parametrize("n", [96, 97, 200])
+def test_eigh_density_like_spectrum(n):
+    check(density_like(n, 100 + n))
+
+
+def test_eigh_degenerate_and_diagonal():
+    # an exactly diagonal matrix (no rotation) and a repeated eigenvalue (any orthonormal basis of the
+    # eigenspace is valid: orthonormality and residual are checked, not the vectors)
+    for n in (5, 120, 240):
+        d = np.arange(n, dtype=np.float64)[::-1].copy()
+        w, V = adc.adc3_eigh(torch.as_tensor(np.diag(d), device="cuda"))
+        assert np.array_equal(w.cpu().numpy(), np.sort(d))
+        assert np.array_equal(np.abs(V.cpu().numpy()), np.eye(n)[:, ::-1])
+        rng = np.random.default_rng(n)
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        lam = np.repeat([1.0, 2.0], [n // 2, n - n // 2])
+        A = (Q * lam) @ Q.T
+        w, V = adc.adc3_eigh(torch.as_tensor(A, device="cuda"))
+        w, V = w.cpu().numpy(), V.cpu().numpy()
+        assert np.abs(w - np.sort(lam)).max() <= 1e-12 * np.linalg.norm(A)
+        assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-12
+        assert np.abs(A @ V - V * w).max() <= 1e-11 * np.linalg.norm(A)
+
+
+def test_eigh_rejects_non_finite():
+    A = random_sym(150, 3)
+    A[4, 7] = A[7, 4] = np.nan
+    with pytest.raises(adc.ADCError) as e:
+        adc.adc3_eigh(torch.as_tensor(A, device="cuda"))
+    assert e.value.status == -4

@@ -129,6 +129,15 @@ def test_ladder_apply_sizes_and_chunk_budget(lib):
     assert adc.adc3_set_chunk_elems(0) == prev
 
 
+def test_eigh_sizes_and_arguments(lib):
+    assert adc.adc3_eigh_workspace_bytes(0) == 0 and adc.adc3_eigh_workspace_bytes(4097) == 0
+    assert adc.adc3_eigh_workspace_bytes(200) >= 2 * 200 * 200 * 8
+    st = lib.adc3_eigh(None, None, None, 10, None, 0, None)
+    assert st == adc.ADC3_EINVAL
+    st = lib.adc3_eigh(None, None, None, 0, None, 0, None)
+    assert st == adc.ADC3_EINVAL
+
+
 def test_error_paths_without_device(lib):
     """Arguments are validated before any launch: NULL inputs are rejected with EINVAL."""
     o = adc.adc3_default_opts()
