@@ -351,16 +351,21 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
                 double* pr = take(ws, 2 * np * vv);
                 df_ladder_pairs(o, v, X, Bvv, T, L, pr, Vt, ve, s);
             } else {
-                // through the pair blocks: L = unpack(G+ w+(T), G- w-(T))
-                const long long lp = sa_lp(v), lm = sa_lm(v);
-                double* W = take(ws, oo * (lp + lm));
-                double* CW = take(ws, oo * (lp + lm));
-                k_sa_pack(T, vv, (int)oo, v, W, W + oo * lp, s);
-                gemm_rm((int)oo, (int)lp, (int)lp, 1.0, W, lp, false, c->G, lp, false, 0.0, CW, lp, s);
+                // through the pair blocks, for the occupied pairs i <= j only (L_ji = L_ij^T):
+                // L = unpack(G+ w+(T), G- w-(T))
+                const long long lp = sa_lp(v), lm = sa_lm(v), np = (long long)o * (o + 1) / 2;
+                double* Tp = take(ws, np * vv);
+                double* Lp = take(ws, np * vv);
+                double* W = take(ws, np * (lp + lm));
+                double* CW = take(ws, np * (lp + lm));
+                k_pairs_gather(Tp, T, o, v, s);
+                k_sa_pack(Tp, vv, (int)np, v, W, W + np * lp, s);
+                gemm_rm((int)np, (int)lp, (int)lp, 1.0, W, lp, false, c->G, lp, false, 0.0, CW, lp, s);
                 if (lm > 0)
-                    gemm_rm((int)oo, (int)lm, (int)lm, 1.0, W + oo * lp, lm, false, c->Gm, lm, false, 0.0, CW + oo * lp,
+                    gemm_rm((int)np, (int)lm, (int)lm, 1.0, W + np * lp, lm, false, c->Gm, lm, false, 0.0, CW + np * lp,
                             lm, s);
-                k_sa_unpack(CW, CW + oo * lp, (int)oo, v, L, vv, s);
+                k_sa_unpack(CW, CW + np * lp, (int)np, v, Lp, vv, s);
+                k_pairs_scatter(L, Lp, o, v, s);
             }
             double* Y = take(ws, oo * vv);
             k_copy(Y, L, oo * vv, s);

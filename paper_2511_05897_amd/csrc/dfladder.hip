@@ -464,6 +464,22 @@ void df_ladder(int prec, int M, int v, int X, const void* Bvv, const void* Z, do
 }  // namespace adc3
 
 namespace adc3 {
+void k_pairs_gather(double* Tp, const double* T, int o, int v, hipStream_t s) {
+    if (g_dry || o <= 0 || v <= 0) return;
+    const long long vv = (long long)v * v;
+    const unsigned gx = (unsigned)std::min<long long>((vv + 255) / 256, 1024);
+    hipLaunchKernelGGL(pairs_gather_kernel, dim3(gx, (unsigned)(o * o)), dim3(256), 0, s, Tp, T, o, vv);
+    LAUNCHCHK();
+}
+
+void k_pairs_scatter(double* L, const double* Lp, int o, int v, hipStream_t s) {
+    if (g_dry || o <= 0 || v <= 0) return;
+    const long long vv = (long long)v * v;
+    const unsigned gx = (unsigned)std::min<long long>((vv + 255) / 256, 1024);
+    hipLaunchKernelGGL(pairs_scatter_kernel, dim3(gx, (unsigned)(o * o)), dim3(256), 0, s, L, Lp, o, v);
+    LAUNCHCHK();
+}
+
 void df_ladder_pairs(int o, int v, int X, const double* Bvv, const double* T, double* L, double* scratch, void* V,
                      long long v_elems, hipStream_t s) {
     if (g_dry) return;

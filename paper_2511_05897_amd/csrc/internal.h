@@ -108,9 +108,13 @@ long long df_ladder_chunk(int M, int v, int X, long long v_elems);
 void df_ladder(int prec, int M, int v, int X, const void* Bvv, const void* Z, double* C, bool accumulate, void* V,
                long long v_elems, hipStream_t s);
 // FP64 ladder of amplitudes with T[j][i] = T[i][j]^T (o x o blocks of v x v): L[i][j] = sum_Q B^Q T[i][j] B^Q is
-// formed for i <= j only and L[j][i] = L[i][j]^T; scratch holds 2 * o(o+1)/2 * v*v doubles
+// formed for i <= j only and L[j][i] = L[i][j]^T; scratch holds 2 * o(o+1)/2 * v*v doubles.
+// k_pairs_gather: Tp[p(i,j)] = T[i][j] for i <= j (v x v blocks, pairs row-major over i <= j);
+// k_pairs_scatter: L[i][j] = Lp[p(i,j)], L[j][i] = Lp[p(i,j)]^T.
 void df_ladder_pairs(int o, int v, int X, const double* Bvv, const double* T, double* L, double* scratch, void* V,
                      long long v_elems, hipStream_t s);
+void k_pairs_gather(double* Tp, const double* T, int o, int v, hipStream_t s);
+void k_pairs_scatter(double* L, const double* Lp, int o, int v, hipStream_t s);
 extern thread_local double* g_gemm_scratch;
 extern thread_local long long g_gemm_scratch_n;
 void gemm_lp(const GemmLP& g, int prec, hipStream_t s, int tag = 0);
