@@ -221,6 +221,16 @@ size_t adc3_eigh_workspace_bytes(int n);
 int adc3_eigh(const double* A_dev, double* w_dev, double* V_dev, int n, void* workspace_dev, size_t workspace_bytes,
               hipStream_t stream);
 
+/* The same eigensolver for nb independent matrices of one order n, as the solve uses it for the
+ * natural orbitals and their recanonicalisation of all roots at once: A_dev[nb][n][n] device
+ * (read only), w_dev[nb][n] (ascending per matrix), V_dev[nb][n][n] (columns, sign convention as
+ * adc3_eigh).  Each matrix stops at its own convergence; the rounds of all matrices share one
+ * launch.  Workspace: adc3_eigh_batched_workspace_bytes(n, nb).  1 <= n <= 4096,
+ * 1 <= nb <= 65535.  Synchronises the stream; ADC3_ENUMERIC if any matrix is non-finite. */
+size_t adc3_eigh_batched_workspace_bytes(int n, int nb);
+int adc3_eigh_batched(const double* A_dev, double* w_dev, double* V_dev, int n, int nb, void* workspace_dev,
+                      size_t workspace_bytes, hipStream_t stream);
+
 /* Dimension N of the context's vector space. */
 long long adc3_ea_dim(const adc3_ctx* ctx);
 

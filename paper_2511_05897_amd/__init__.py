@@ -26,7 +26,8 @@ EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_byte
            "adc3_mlp_forward", "adc3_mlp_train", "adc3_ea_precondition", "adc3_ea_solve_batched_workspace_bytes",
            "adc3_ea_solve_batched", "adc3_ea_set_sigma_graphs", "adc3_profile_query_bound",
            "adc3_ea_setup_workspace_bytes_ex", "adc3_ea_setup_ex", "adc3_set_chunk_elems",
-           "adc3_ladder_workspace_bytes", "adc3_ladder_apply", "adc3_eigh_workspace_bytes", "adc3_eigh"]
+           "adc3_ladder_workspace_bytes", "adc3_ladder_apply", "adc3_eigh_workspace_bytes", "adc3_eigh",
+           "adc3_eigh_batched_workspace_bytes", "adc3_eigh_batched"]
 
 
 class adc3_opts(ctypes.Structure):
@@ -92,6 +93,10 @@ def load():
     lib.adc3_eigh_workspace_bytes.restype = S
     lib.adc3_eigh.argtypes = [P, P, P, I, P, S, P]
     lib.adc3_eigh.restype = I
+    lib.adc3_eigh_batched_workspace_bytes.argtypes = [I, I]
+    lib.adc3_eigh_batched_workspace_bytes.restype = S
+    lib.adc3_eigh_batched.argtypes = [P, P, P, I, I, P, S, P]
+    lib.adc3_eigh_batched.restype = I
     lib.adc3_ladder_apply.restype = I
     lib.adc3_ctx_destroy.argtypes = [P]
     lib.adc3_ctx_destroy.restype = None
@@ -292,6 +297,18 @@ def adc3_eigh(A):
     V = torch.empty((n, n), dtype=torch.float64, device=A.device)
     ws = _workspace(adc3_eigh_workspace_bytes(n))
     _check(load().adc3_eigh(_ptr(A), _ptr(w), _ptr(V), n, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    return w, V
+
+
+def adc3_eigh_batched(A):
+    """Eigenvalues (ascending) and eigenvectors of each symmetric part of A [nb][n][n] (FP64 device)."""
+    import torch
+    nb, n = int(A.shape[0]), int(A.shape[1])
+    w = torch.empty((nb, n), dtype=torch.float64, device=A.device)
+    V = torch.empty((nb, n, n), dtype=torch.float64, device=A.device)
+    ws = _workspace(load().adc3_eigh_batched_workspace_bytes(n, nb))
+    _check(load().adc3_eigh_batched(_ptr(A), _ptr(w), _ptr(V), n, nb, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    _stream()))
     return w, V
 
 

@@ -1031,47 +1031,67 @@ static void ea_density(Arena& ws, const Ctx* c, const double* vec, double* D, hi
     ws.release(mark);
 }
 
-// Natural orbitals of D (eq 9), kept eta > thr (eqs 10-11; thr <= 0 keeps all),
-// recanonicalised (eqs 12-13); returns kept count, writes U[v][vk] (eq 14) and e_new[vk].
-static int natural_orbitals(Arena& ws, const double* D, const double* ev, int v, double thr, double* U,
-                            double* e_new, hipStream_t s) {
+// Natural orbitals of D^SS (eq 9), kept eta > thr (eqs 10-11; thr <= 0 keeps all), recanonicalised
+// (eqs 12-13), U = V~ Z (eq 14), for every root at once (Dss [nr][v][v]), the eigenproblems of all roots
+// solved as batches (one launch per Jacobi round for the whole batch; the recanonicalisation in groups of
+// roots with the same kept count).  U_all[k] holds U of root k as [v][vk_k], e_all[k] its vk_k energies
+// (row stride v), vks[k] the kept count.
+static void natural_orbitals_all(Arena& ws, const double* Dss, const double* ev, int v, double thr, int nr,
+                                 double* U_all, double* e_all, std::vector<int>& vks, hipStream_t s) {
     const long long vv = (long long)v * v;
     const size_t mark = ws.mark();
-    double* A = take(ws, vv);
-    double* w = take(ws, v);
-    double* V = take(ws, vv);
+    double* A = take(ws, nr * vv);
+    double* w = take(ws, (long long)nr * v);
+    double* V = take(ws, nr * vv);
     double* wt = take(ws, v);
     double* Vt = take(ws, vv);
-    double* scr = take(ws, (long long)eig_large_scratch(v));
-    k_copy(A, D, vv, s);
-    k_symmetrize(A, v, s);
-    eig_large(A, v, w, V, scr, s);
-    k_sort_eig(w, V, v, 1, wt, Vt, s);  // descending occupation
-    std::vector<double> hw(v);
-    d2h(hw.data(), w, v * sizeof(double), s);
-    int vk = 0;
-    if (g_dry || !(thr > 0)) vk = v;
-    else
-        for (int a = 0; a < v; ++a) vk += hw[a] > thr;
-    if (vk > 0) {
-        // F~ = V~^T diag(e) V~ (V~ = first vk columns of V)
-        double* EV = take(ws, (long long)v * vk);
-        k_copy2d(EV, vk, V, v, v, vk, 1.0, 0.0, s);
-        double* EVs = take(ws, (long long)v * vk);
-        k_scale_rows(EVs, EV, ev, v, vk, s);
-        double* F = take(ws, (long long)vk * vk);
-        gemm_rm(vk, vk, v, 1.0, EV, vk, true, EVs, vk, false, 0.0, F, vk, s);
-        k_symmetrize(F, vk, s);
-        double* Z = take(ws, (long long)vk * vk);
-        double* zt = take(ws, (long long)vk * vk);
-        double* scr2 = take(ws, (long long)eig_large_scratch(vk));
-        eig_large(F, vk, e_new, Z, scr2, s);
-        k_sort_eig(e_new, Z, vk, 0, wt, zt, s);
-        gemm_rm(v, vk, vk, 1.0, EV, vk, false, Z, vk, false, 0.0, U, vk, s);
-        k_colsign(U, vk, v, vk, s);
+    double* scr = take(ws, (long long)eig_batched_scratch(v, nr));
+    k_copy(A, Dss, nr * vv, s);
+    for (int k = 0; k < nr; ++k) k_symmetrize(A + k * vv, v, s);
+    eig_batched(A, v, nr, w, V, scr, s);
+    for (int k = 0; k < nr; ++k) k_sort_eig(w + (long long)k * v, V + k * vv, v, 1, wt, Vt, s);  // descending
+    std::vector<double> hw((size_t)nr * v);
+    d2h(hw.data(), w, (size_t)nr * v * sizeof(double), s);
+    vks.assign(nr, 0);
+    for (int k = 0; k < nr; ++k) {
+        if (g_dry || !(thr > 0)) vks[k] = v;
+        else
+            for (int a = 0; a < v; ++a) vks[k] += hw[(size_t)k * v + a] > thr;
+    }
+    // F~_k = V~_k^T diag(e) V~_k (V~_k = first vk_k columns of V_k), batched over roots with equal vk
+    double* EV = take(ws, nr * vv);
+    double* EVs = take(ws, vv);
+    double* F = take(ws, nr * vv);
+    double* Z = take(ws, nr * vv);
+    double* en = take(ws, (long long)nr * v);
+    double* zt = take(ws, vv);
+    double* scr2 = take(ws, (long long)eig_batched_scratch(v, nr));
+    std::vector<char> done(nr, 0);
+    for (int k0 = 0; k0 < nr; ++k0) {
+        const int vk = vks[k0];
+        if (done[k0] || vk < 1) continue;
+        std::vector<int> grp;
+        for (int k = k0; k < nr; ++k)
+            if (!done[k] && vks[k] == vk) { grp.push_back(k); done[k] = 1; }
+        const long long kk = (long long)vk * vk;
+        for (size_t j = 0; j < grp.size(); ++j) {
+            double* EVk = EV + grp[j] * vv;
+            k_copy2d(EVk, vk, V + grp[j] * vv, v, v, vk, 1.0, 0.0, s);
+            k_scale_rows(EVs, EVk, ev, v, vk, s);
+            gemm_rm(vk, vk, v, 1.0, EVk, vk, true, EVs, vk, false, 0.0, F + j * kk, vk, s);
+            k_symmetrize(F + j * kk, vk, s);
+        }
+        eig_batched(F, vk, (int)grp.size(), en, Z, scr2, s);
+        for (size_t j = 0; j < grp.size(); ++j) {
+            const int k = grp[j];
+            k_sort_eig(en + j * vk, Z + j * kk, vk, 0, wt, zt, s);
+            double* U = U_all + k * vv;
+            gemm_rm(v, vk, vk, 1.0, EV + k * vv, vk, false, Z + j * kk, vk, false, 0.0, U, vk, s);
+            k_colsign(U, vk, v, vk, s);
+            k_copy(e_all + (long long)k * v, en + j * vk, vk, s);
+        }
     }
     ws.release(mark);
-    return vk;
 }
 
 // New factor blocks in the truncated virtual basis: Bov U, U^T Bvv U (eqs 14-16).
@@ -1221,6 +1241,11 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     }
     out.all_conv = out.all_conv && r2.converged;
     VLOG("canonical ADC(2): %d roots, %d iterations, lowest %.10f", nroots, r2.iters, r2.w[0]);
+    // steps 4c-4d for every root: natural orbitals, truncation and recanonicalisation
+    double* U_all = take(ws, (long long)nroots * vv0);
+    double* e_all = take(ws, (long long)nroots * v);
+    std::vector<int> vks;
+    natural_orbitals_all(ws, Dss, ev, v, fno, nroots, U_all, e_all, vks, s);
     NafCache naf_cache;
     if (naf > 0) {
         naf_cache.N = take(ws, (long long)X * X);
@@ -1232,10 +1257,9 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         auto& R = out.rep[k];
         GemmScratch gscr(ws, GEMM_SCRATCH);
         R.omega_adc2_can = r2.w[k];
-        const double* D = Dss + (long long)k * vv0;
-        double* U = take(ws, (long long)v * v);
-        double* enew = take(ws, v);
-        int vk = natural_orbitals(ws, D, ev, v, fno, U, enew, s);     // 4c-4d
+        const double* U = U_all + (long long)k * vv0;
+        const double* enew = e_all + (long long)k * v;
+        const int vk = vks[k];                                        // 4c-4d
         if (vk < 1) fail(ADC3_EINVAL, "SS-FNO threshold removes every virtual orbital");
         Blocks Bt;
         transform_blocks(B0, U, vk, Bt, ws, s);
@@ -1619,6 +1643,39 @@ int adc3_eigh(const double* A, double* w, double* V, int n, void* workspace, siz
     k_symmetrize(Ac, n, stream);
     eig_large(Ac, n, w, V, scr, stream);
     k_sort_eig(w, V, n, 0, wt, Vt, stream);
+    return ADC3_OK;
+    API_END
+}
+
+size_t adc3_eigh_batched_workspace_bytes(int n, int nb) {
+    if (n <= 0 || n > 4096 || nb <= 0 || nb > 65535) return 0;
+    const size_t nn = (size_t)n * n;
+    return ((size_t)nb * nn * 2 + eig_batched_scratch(n, nb) + n + nn + (size_t)nb * n) * sizeof(double) + 6 * 256;
+}
+
+int adc3_eigh_batched(const double* A, double* w, double* V, int n, int nb, void* workspace, size_t ws_bytes,
+                      hipStream_t stream) {
+    API_BEGIN
+    if (n <= 0 || n > 4096 || nb <= 0 || nb > 65535) fail(ADC3_EINVAL, "n must be in 1..4096 and nb in 1..65535");
+    if (!A || !w || !V || !workspace) fail(ADC3_EINVAL, "NULL pointer argument");
+    const size_t need = adc3_eigh_batched_workspace_bytes(n, nb);
+    if (ws_bytes < need) fail(ADC3_ENOMEM, "workspace too small: need at least " + std::to_string(need) + " bytes");
+    Arena ws;
+    ws.base = (char*)workspace;
+    ws.cap = ws_bytes;
+    const long long nn = (long long)n * n;
+    double* Ac = take(ws, nb * nn);
+    double* Vu = take(ws, nb * nn);
+    double* scr = take(ws, (long long)eig_batched_scratch(n, nb));
+    double* wt = take(ws, n);
+    double* Vt = take(ws, nn);
+    k_copy(Ac, A, nb * nn, stream);
+    for (int b = 0; b < nb; ++b) k_symmetrize(Ac + b * nn, n, stream);
+    eig_batched(Ac, n, nb, w, Vu, scr, stream);
+    for (int b = 0; b < nb; ++b) {
+        k_sort_eig(w + (long long)b * n, Vu + b * nn, n, 0, wt, Vt, stream);
+        k_copy(V + b * nn, Vu + b * nn, nn, stream);
+    }
     return ADC3_OK;
     API_END
 }

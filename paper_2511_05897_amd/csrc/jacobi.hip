@@ -5,6 +5,7 @@
 // natural-auxiliary-function matrix (large, one launch per round, two buffers of A).
 #include "internal.h"
 #include <cmath>
+#include <vector>
 
 namespace adc3 {
 
@@ -161,6 +162,101 @@ __global__ void jacobi_round_kernel(const double* Ain, double* Aout, double* V, 
     }
 }
 
+// Batched round: blockIdx.y picks the matrix (order n, contiguous [nb][n][n] buffers); matrices whose
+// flag is 0 (converged) are left as they are.
+__global__ void jacobi_round_batched_kernel(const double* Ain, double* Aout, double* Vb, int n, int np, int r,
+                                            const int* active) {
+    const int bm = blockIdx.y;
+    if (!active[bm]) return;
+    const long long nn = (long long)n * n;
+    const double* Ai = Ain + bm * nn;
+    double* Ao = Aout + bm * nn;
+    double* V = Vb + bm * nn;
+    extern __shared__ double csh[];  // [2 * npair]
+    const int npair = np / 2;
+    for (int k = threadIdx.x; k < npair; k += blockDim.x) {
+        int p, q;
+        pair_of(r, k, np, p, q);
+        double c = 1.0, s = 0.0;
+        if (q < n) rot_of(Ai[(long long)p * n + p], Ai[(long long)q * n + q], Ai[(long long)p * n + q], c, s);
+        csh[2 * k] = c;
+        csh[2 * k + 1] = s;
+    }
+    __syncthreads();
+    long long nblk = (long long)npair * npair;
+    long long nv = (long long)n * npair;
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nblk + nv;
+         t += (long long)gridDim.x * blockDim.x) {
+        if (t < nblk) {
+            int k1 = (int)(t / npair), k2 = (int)(t % npair);
+            int p1, q1, p2, q2;
+            pair_of(r, k1, np, p1, q1);
+            pair_of(r, k2, np, p2, q2);
+            double c1 = csh[2 * k1], s1 = csh[2 * k1 + 1], c2 = csh[2 * k2], s2 = csh[2 * k2 + 1];
+            bool v1 = q1 < n, v2 = q2 < n;
+            double a = Ai[(long long)p1 * n + p2];
+            double b = v2 ? Ai[(long long)p1 * n + q2] : 0.0;
+            double c = v1 ? Ai[(long long)q1 * n + p2] : 0.0;
+            double d = (v1 && v2) ? Ai[(long long)q1 * n + q2] : 0.0;
+            double ra = c1 * a - s1 * c, rb = c1 * b - s1 * d;
+            double rc = s1 * a + c1 * c, rd = s1 * b + c1 * d;
+            double na = c2 * ra - s2 * rb, nb = s2 * ra + c2 * rb;
+            double nc = c2 * rc - s2 * rd, nd = s2 * rc + c2 * rd;
+            Ao[(long long)p1 * n + p2] = na;
+            if (v2) Ao[(long long)p1 * n + q2] = nb;
+            if (v1) Ao[(long long)q1 * n + p2] = nc;
+            if (v1 && v2) Ao[(long long)q1 * n + q2] = nd;
+        } else {
+            long long u = t - nblk;
+            int k = (int)(u / n), i = (int)(u % n);
+            int p, q;
+            pair_of(r, k, np, p, q);
+            if (q >= n) continue;
+            double c = csh[2 * k], s = csh[2 * k + 1];
+            double vip = V[(long long)i * n + p], viq = V[(long long)i * n + q];
+            V[(long long)i * n + p] = c * vip - s * viq;
+            V[(long long)i * n + q] = s * vip + c * viq;
+        }
+    }
+}
+
+// Per matrix of the batch (one workgroup each): off-diagonal and total squared norms into nrm[2b..2b+1];
+// an active matrix whose off-diagonal norm has reached the threshold (or is not finite) is marked done.
+__global__ void offnorm_batched_kernel(const double* A, int n, double* nrm, int* active) {
+    const int bm = blockIdx.x;
+    if (!active[bm]) return;
+    const double* Ab = A + (long long)bm * n * n;
+    __shared__ double r1[16], r2[16];
+    double off = 0.0, tot = 0.0;
+    long long nn = (long long)n * n;
+    for (long long t = threadIdx.x; t < nn; t += blockDim.x) {
+        double a = Ab[t];
+        tot += a * a;
+        if (t / n != t % n) off += a * a;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        off += __shfl_down(off, o, 64);
+        tot += __shfl_down(tot, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) { r1[threadIdx.x >> 6] = off; r2[threadIdx.x >> 6] = tot; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0, b = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { a += r1[k]; b += r2[k]; }
+        nrm[2 * bm] = a;
+        nrm[2 * bm + 1] = b;
+        if (!(a == a && b == b) || !(b < INFINITY) || a <= 1e-30 * b || a == 0.0) active[bm] = 0;
+    }
+}
+
+// w[b][i] = A_b[i][i], A_b taken from A or A2 as src[b] says
+__global__ void diag_out_batched_kernel(const double* A, const double* A2, const int* src, int n, double* w) {
+    const int bm = blockIdx.y, i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* Ab = (src[bm] ? A2 : A) + (long long)bm * n * n;
+    w[(long long)bm * n + i] = Ab[(long long)i * n + i];
+}
+
 __global__ void offnorm_kernel(const double* A, int n, double* out) {
     __shared__ double r1[16], r2[16];
     double off = 0.0, tot = 0.0;
@@ -273,6 +369,68 @@ void eig_large(double* A, int n, double* w, double* V, double* scratch, hipStrea
     }
     hipLaunchKernelGGL(diag_out_kernel, dim3((n + 255) / 256), dim3(256), 0, s, cur, n, w);
     LAUNCHCHK();
+}
+
+// second copies of the nb matrices, norms, flags
+size_t eig_batched_scratch(int n, int nb) { return (size_t)nb * n * n + 4 * (size_t)nb + 8; }
+
+void eig_batched(double* A, int n, int nb, double* w, double* V, double* scratch, hipStream_t s) {
+    if (g_dry) return;
+    ProfScope prof(PROF_EIG, s, 0.0, 0.0);
+    if (n <= 0 || nb <= 0) return;
+    const long long nn = (long long)n * n;
+    if (n <= SMALL_MAX || nb == 1) {
+        for (int b = 0; b < nb; ++b) eig_large(A + b * nn, n, w + (long long)b * n, V + b * nn, scratch, s);
+        return;
+    }
+    const int np = n + (n & 1);
+    double* A2 = scratch;
+    double* nrm = scratch + nb * nn;                 // [nb][2]
+    int* active = (int*)(nrm + 2 * (long long)nb);   // [nb]
+    int* src = active + nb;                           // [nb]
+    std::vector<int> hact(nb, 1), hsrc(nb, 0);
+    std::vector<double> hn(2 * (size_t)nb);
+    HIPCHK(hipMemcpyAsync(active, hact.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+    for (int b = 0; b < nb; ++b) {
+        hipLaunchKernelGGL(eye_kernel, dim3(256), dim3(256), 0, s, V + b * nn, n);
+        LAUNCHCHK();
+    }
+    long long work = (long long)(np / 2) * (np / 2) + (long long)n * (np / 2);
+    unsigned gb = (unsigned)std::min<long long>((work + 255) / 256, 4096);
+    const size_t lds = (size_t)np * sizeof(double);
+    if (lds > 64 * 1024) fail(-1, "eig_batched: n too large");
+    int parity = 0;  // 0: current matrices in A, 1: in A2
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        hipLaunchKernelGGL(offnorm_batched_kernel, dim3(nb), dim3(1024), 0, s, parity ? A2 : A, n, nrm, active);
+        LAUNCHCHK();
+        std::vector<int> now(nb);
+        HIPCHK(hipMemcpyAsync(now.data(), active, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(hn.data(), nrm, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int left = 0;
+        for (int b = 0; b < nb; ++b) {
+            if (hact[b] && !now[b]) {
+                if (!std::isfinite(hn[2 * b]) || !std::isfinite(hn[2 * b + 1]))
+                    fail(-4, "eigensolver: non-finite matrix");
+                hsrc[b] = parity;  // converged here: its matrix stays in the current buffer
+            }
+            hact[b] = now[b];
+            left += now[b];
+        }
+        if (left == 0) break;
+        for (int r = 0; r < np - 1; ++r) {
+            hipLaunchKernelGGL(jacobi_round_batched_kernel, dim3(gb, nb), dim3(256), lds, s, parity ? A2 : A,
+                               parity ? A : A2, V, n, np, r, active);
+            parity ^= 1;
+        }
+        LAUNCHCHK();
+    }
+    for (int b = 0; b < nb; ++b)
+        if (hact[b]) hsrc[b] = parity;  // not converged within the sweep limit: the last buffer
+    HIPCHK(hipMemcpyAsync(src, hsrc.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(diag_out_batched_kernel, dim3((n + 255) / 256, nb), dim3(256), 0, s, A, A2, src, n, w);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));  // the host arrays of the copies above go out of scope here
 }
 
 void k_sort_eig(double* w, double* V, int n, int desc, double* wtmp, double* Vtmp, hipStream_t s) {

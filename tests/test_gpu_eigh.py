@@ -94,3 +94,29 @@ def test_eigh_rejects_non_finite():
     with pytest.raises(adc.ADCError) as e:
         adc.adc3_eigh(torch.as_tensor(A, device="cuda"))
     assert e.value.status == -4
+
+
+@pytest.mark.parametrize("n", [40, 150, 200])
+def test_eigh_batched_matches_single(n):
+    """A batch mixing spectra that converge after different numbers of sweeps (random, density-like,
+    already diagonal): every matrix against numpy, and bit for bit against the single-matrix solver."""
+    mats = [random_sym(n, 1), density_like(n, 2), np.diag(np.linspace(1.0, 2.0, n)), density_like(n, 3),
+            random_sym(n, 4)]
+    A = np.stack(mats)
+    w, V = adc.adc3_eigh_batched(torch.as_tensor(A, device="cuda"))
+    w, V = w.cpu().numpy(), V.cpu().numpy()
+    for b, M in enumerate(mats):
+        nrm = np.linalg.norm(M)
+        assert np.abs(w[b] - np.linalg.eigvalsh(M)).max() <= 1e-12 * nrm, b
+        assert np.abs(V[b].T @ V[b] - np.eye(n)).max() <= 1e-12, b
+        assert np.abs(M @ V[b] - V[b] * w[b]).max() <= 1e-11 * nrm, b
+        w1, V1 = adc.adc3_eigh(torch.as_tensor(M, device="cuda"))
+        assert np.array_equal(w1.cpu().numpy(), w[b]) and np.array_equal(V1.cpu().numpy(), V[b]), b
+
+
+def test_eigh_batched_rejects_non_finite():
+    A = np.stack([random_sym(120, 5), random_sym(120, 6)])
+    A[1, 3, 3] = np.inf
+    with pytest.raises(adc.ADCError) as e:
+        adc.adc3_eigh_batched(torch.as_tensor(A, device="cuda"))
+    assert e.value.status == -4

@@ -136,6 +136,9 @@ def test_eigh_sizes_and_arguments(lib):
     assert st == adc.ADC3_EINVAL
     st = lib.adc3_eigh(None, None, None, 0, None, 0, None)
     assert st == adc.ADC3_EINVAL
+    assert lib.adc3_eigh_batched_workspace_bytes(100, 0) == 0 and lib.adc3_eigh_batched_workspace_bytes(0, 3) == 0
+    assert lib.adc3_eigh_batched_workspace_bytes(100, 5) >= 5 * 2 * 100 * 100 * 8
+    assert lib.adc3_eigh_batched(None, None, None, 100, 5, None, 0, None) == adc.ADC3_EINVAL
 
 
 def test_error_paths_without_device(lib):
