@@ -63,9 +63,21 @@ static bool verbose() { return verbosity() >= 1; }
         }                                         \
     } while (0)
 
+// Small read-backs go through a pinned staging buffer (one per host thread, kept for the process):
+// the Davidson loop reads back a few numbers several times per iteration, and a copy into pageable
+// memory is staged by the runtime at a higher latency.
 static void d2h(void* dst, const void* src, size_t bytes, hipStream_t s) {
     if (g_dry) {
         std::memset(dst, 0, bytes);
+        return;
+    }
+    constexpr size_t PIN = 1 << 20;
+    thread_local void* pin = nullptr;
+    if (bytes <= PIN) {
+        if (!pin) HIPCHK(hipHostMalloc(&pin, PIN, hipHostMallocDefault));
+        HIPCHK(hipMemcpyAsync(pin, src, bytes, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        std::memcpy(dst, pin, bytes);
         return;
     }
     HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));

@@ -31,6 +31,59 @@ __global__ void sum_partials_kernel(const double* partial, long long nchunk, int
         else G[(long long)r * ldg + q] = s;
     }
 }
+// Small Gram blocks (at most 64 products, e.g. residual norms and the Gram of a new block): one pass
+// on the vector ALUs.  Workgroup (c, g) takes elements [c*chunk, (c+1)*chunk) and rows [g*PG, g*PG+PG)
+// of X against all nq (<= NQ) rows of Y; the products accumulate in registers, then a fixed-order
+// block reduction writes partial[c][p][q].
+template <int NQ, int PG>
+__global__ __launch_bounds__(256) void dots_small_kernel(const double* X, long long ldx, int np, const double* Y,
+                                                         long long ldy, int nq, long long n, long long chunk,
+                                                         double* partial) {
+    const long long c0 = (long long)blockIdx.x * chunk, c1 = min(n, c0 + chunk);
+    const int p0 = blockIdx.y * PG;
+    double acc[PG][NQ];
+#pragma unroll
+    for (int p = 0; p < PG; ++p)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[p][q] = 0.0;
+    for (long long t = c0 + threadIdx.x; t < c1; t += 256) {
+        double y[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) y[q] = q < nq ? Y[q * ldy + t] : 0.0;
+#pragma unroll
+        for (int p = 0; p < PG; ++p) {
+            if (p0 + p < np) {
+                const double x = X[(p0 + p) * ldx + t];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) acc[p][q] += x * y[q];
+            }
+        }
+    }
+    __shared__ double red[4][PG * NQ];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int p = 0; p < PG; ++p)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            double v = acc[p][q];
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+            if (lane == 0) red[wave][p * NQ + q] = v;
+        }
+    __syncthreads();
+    for (int k = threadIdx.x; k < PG * NQ; k += 256) {
+        const int p = k / NQ, q = k % NQ;
+        if (p0 + p < np && q < nq)
+            partial[((long long)blockIdx.x * np + p0 + p) * nq + q] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+    }
+}
+
+template <int NQ>
+void launch_dots_small(const double* X, long long ldx, int np, const double* Y, long long ldy, int nq, long long n,
+                       long long chunk, long long nchunk, double* partial, hipStream_t s) {
+    constexpr int PG = 64 / NQ;
+    dim3 grid((unsigned)nchunk, (unsigned)((np + PG - 1) / PG));
+    hipLaunchKernelGGL((dots_small_kernel<NQ, PG>), grid, dim3(256), 0, s, X, ldx, np, Y, ldy, nq, n, chunk, partial);
+}
 }  // namespace
 
 size_t dots_partial_elems(int np, int nq, long long n) {
@@ -48,6 +101,26 @@ void k_dots(const double* X, long long ldx, int np, const double* Y, long long l
     const long long lda = swapped ? ldy : ldx, ldb = swapped ? ldx : ldy;
     const int M = swapped ? nq : np, N = swapped ? np : nq;
     const long long MN = (long long)M * N;
+    // at most 64 products with one row group: the vector-ALU pass (A's rows against B's columns, the
+    // partials laid out [chunk][M][N] as the GEMM's)
+    if (n > 0 && M <= 16 && M * N <= 64 && (long long)N * ((M + 3) / 4 * 4) <= 64) {
+        const long long ch = std::max<long long>(2048, (n + 511) / 512);
+        const long long nch = (n + ch - 1) / ch;
+        if (nch <= 65535 && nch * MN <= (long long)dots_partial_elems(np, nq, n)) {
+            // rows of the output: the N operand rows against M (<= 16) operand rows
+            if (M <= 1) launch_dots_small<1>(B, ldb, N, A, lda, M, n, ch, nch, partial, s);
+            else if (M <= 2) launch_dots_small<2>(B, ldb, N, A, lda, M, n, ch, nch, partial, s);
+            else if (M <= 4) launch_dots_small<4>(B, ldb, N, A, lda, M, n, ch, nch, partial, s);
+            else if (M <= 8) launch_dots_small<8>(B, ldb, N, A, lda, M, n, ch, nch, partial, s);
+            else launch_dots_small<16>(B, ldb, N, A, lda, M, n, ch, nch, partial, s);
+            LAUNCHCHK();
+            // partial[c][r][m] with r over the N operand: the transposed block of the GEMM's layout
+            hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)MN), dim3(256), 0, s, partial, nch, N, M,
+                               swapped ? 0 : 1, G, ldg);
+            LAUNCHCHK();
+            return;
+        }
+    }
     const long long CH = chunk_of(n);
     long long nchunk = (n + CH - 1) / CH;
     if (nchunk == 0) {
