@@ -77,6 +77,56 @@ __global__ __launch_bounds__(256) void dots_small_kernel(const double* X, long l
     }
 }
 
+// Y[q][t] = alpha * sum_p C[p][q] X[p][t] + beta * Y[q][t] for nq <= NQ rows: each thread E elements
+// (stride 256), the coefficients uniform across the wave, X streamed once.
+template <int NQ, int E>
+__global__ __launch_bounds__(256) void lincomb_kernel(double* Y, long long ldy, int nq, const double* X, long long ldx,
+                                                      int np, const double* C, int ldc, long long n, double alpha,
+                                                      double beta) {
+    const long long base = (long long)blockIdx.x * (256 * E) + threadIdx.x;
+    double acc[E][NQ];
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[e][q] = 0.0;
+    for (int p = 0; p < np; ++p) {
+        double x[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const long long t = base + 256LL * e;
+            x[e] = t < n ? X[p * ldx + t] : 0.0;
+        }
+        const double* cp = C + (long long)p * ldc;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const double c = q < nq ? cp[q] : 0.0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[e][q] += c * x[e];
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        if (q >= nq) break;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const long long t = base + 256LL * e;
+            if (t < n) {
+                double* y = Y + q * ldy + t;
+                *y = alpha * acc[e][q] + (beta == 0.0 ? 0.0 : beta * *y);
+            }
+        }
+    }
+}
+
+template <int NQ>
+void launch_lincomb(double* Y, long long ldy, int nq, const double* X, long long ldx, int np, const double* C, int ldc,
+                    long long n, double alpha, double beta, hipStream_t s) {
+    constexpr int E = NQ <= 8 ? 4 : 2;
+    const long long nb = (n + 256 * E - 1) / (256 * E);
+    hipLaunchKernelGGL((lincomb_kernel<NQ, E>), dim3((unsigned)nb), dim3(256), 0, s, Y, ldy, nq, X, ldx, np, C, ldc, n,
+                       alpha, beta);
+}
+
 template <int NQ>
 void launch_dots_small(const double* X, long long ldx, int np, const double* Y, long long ldy, int nq, long long n,
                        long long chunk, long long nchunk, double* partial, hipStream_t s) {
@@ -146,6 +196,16 @@ void k_lincomb(double* Y, long long ldy, int nq, const double* X, long long ldx,
                long long n, double alpha, double beta, hipStream_t s) {
     if (g_dry) return;
     if (nq <= 0 || n <= 0) return;
+    // few output rows: the streaming kernel (one pass over X, coefficients in scalar registers)
+    if (nq <= 16 && np <= 128 && (n + 1023) / 1024 <= 0x7fffffffLL) {
+        if (nq <= 1) launch_lincomb<1>(Y, ldy, nq, X, ldx, np, C, ldc, n, alpha, beta, s);
+        else if (nq <= 2) launch_lincomb<2>(Y, ldy, nq, X, ldx, np, C, ldc, n, alpha, beta, s);
+        else if (nq <= 4) launch_lincomb<4>(Y, ldy, nq, X, ldx, np, C, ldc, n, alpha, beta, s);
+        else if (nq <= 8) launch_lincomb<8>(Y, ldy, nq, X, ldx, np, C, ldc, n, alpha, beta, s);
+        else launch_lincomb<16>(Y, ldy, nq, X, ldx, np, C, ldc, n, alpha, beta, s);
+        LAUNCHCHK();
+        return;
+    }
     for (long long c0 = 0; c0 < n; c0 += 2000000000LL) {
         long long nn = std::min<long long>(n - c0, 2000000000LL);
         Gemm g;
