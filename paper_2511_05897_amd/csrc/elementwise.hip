@@ -19,6 +19,62 @@ __global__ void axpby_kernel(double* y, const double* x, long long n, double a, 
 }
 
 struct P4 { int d[4]; int perm[4]; };
+
+// Permutes for the two cases of the innermost axes (input axis 3 and the input axis that becomes the
+// output's axis 3):
+//   * the same axis: element per thread, 32-bit index arithmetic (both sides contiguous);
+//   * different axes X, Y: 32 x 32 tiles of (X, Y) transposed through LDS so that reads run along X and
+//     writes along Y; the other two axes P, Q come from the grid.
+struct P4T {
+    int d[4];
+    long long st[4], os[4];  // input strides, output strides, both indexed by input axis
+    int X, Y, P, Q;
+    unsigned q0, q1;  // same-innermost case: output strides of the first two output axes / d[3]
+};
+
+__global__ void permute4_same_kernel(double* out, const double* in, P4T p, unsigned n, double alpha, double beta) {
+    // output order of the input axes: o0 o1 o2 then axis 3
+    const unsigned d3 = (unsigned)p.d[3];
+    for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+        const unsigned i3 = t % d3, r = t / d3;
+        // r enumerates the other three axes in output order (p.X, p.Y, p.P: decreasing output stride)
+        const unsigned a0 = r / p.q0, r1 = r - a0 * p.q0;
+        const unsigned a1 = r1 / p.q1, a2 = r1 - a1 * p.q1;
+        long long off = i3;
+        off += (long long)a0 * p.st[p.X] + (long long)a1 * p.st[p.Y] + (long long)a2 * p.st[p.P];
+        const double v = alpha * in[off];
+        out[t] = (beta == 0.0) ? v : v + beta * out[t];
+    }
+}
+
+__global__ __launch_bounds__(256) void permute4_tile_kernel(double* out, const double* in, P4T p, int nty,
+                                                            double alpha, double beta) {
+    __shared__ double tile[32][33];
+    const int tx = blockIdx.x / nty, ty = blockIdx.x % nty;
+    const long long bin = (long long)blockIdx.y * p.st[p.P] + (long long)blockIdx.z * p.st[p.Q];
+    const long long bout = (long long)blockIdx.y * p.os[p.P] + (long long)blockIdx.z * p.os[p.Q];
+    const int x0 = tx * 32, y0 = ty * 32;
+    const int dx = p.d[p.X], dy = p.d[p.Y];
+    {
+        const int x = x0 + threadIdx.x;
+        for (int j = threadIdx.y; j < 32; j += 8) {
+            const int y = y0 + j;
+            if (x < dx && y < dy) tile[j][threadIdx.x] = in[bin + (long long)y * p.st[p.Y] + x];
+        }
+    }
+    __syncthreads();
+    {
+        const int y = y0 + threadIdx.x;
+        for (int j = threadIdx.y; j < 32; j += 8) {
+            const int x = x0 + j;
+            if (x < dx && y < dy) {
+                const long long o = bout + (long long)x * p.os[p.X] + y;
+                const double v = alpha * tile[threadIdx.x][j];
+                out[o] = (beta == 0.0) ? v : v + beta * out[o];
+            }
+        }
+    }
+}
 __global__ void permute4_kernel(double* out, const double* in, P4 p, double alpha, double beta) {
     // output dims
     long long od[4], is[4];
@@ -333,6 +389,38 @@ void k_permute4(double* out, const double* in, const int din[4], const int perm[
     long long n = 1;
     for (int k = 0; k < 4; ++k) { p.d[k] = din[k]; p.perm[k] = perm[k]; n *= din[k]; }
     if (n <= 0) return;
+    // strides of each input axis in the input and in the output
+    P4T t;
+    long long ost[4];
+    ost[3] = 1;
+    for (int k = 2; k >= 0; --k) ost[k] = ost[k + 1] * din[perm[k + 1]];
+    t.st[3] = 1;
+    for (int k = 2; k >= 0; --k) t.st[k] = t.st[k + 1] * din[k + 1];
+    for (int k = 0; k < 4; ++k) { t.d[k] = din[k]; t.os[perm[k]] = ost[k]; }
+    const int X = 3, Y = perm[3];
+    if (X != Y) {
+        int others[2], no = 0;
+        for (int a = 0; a < 4; ++a)
+            if (a != X && a != Y) others[no++] = a;
+        t.X = X; t.Y = Y; t.P = others[0]; t.Q = others[1];
+        const int ntx = (din[X] + 31) / 32, nty = (din[Y] + 31) / 32;
+        if ((long long)ntx * nty <= 0x7fffffffLL && din[t.P] <= 65535 && din[t.Q] <= 65535) {
+            hipLaunchKernelGGL(permute4_tile_kernel, dim3((unsigned)(ntx * nty), (unsigned)din[t.P], (unsigned)din[t.Q]),
+                               dim3(32, 8), 0, s, out, in, t, nty, alpha, beta);
+            LAUNCHCHK();
+            return;
+        }
+    } else if (n < 0x7fffffffLL) {
+        // the other three axes in output order (decreasing output stride)
+        int ax[3], na = 0;
+        for (int k = 0; k < 3; ++k) ax[na++] = perm[k];
+        t.X = ax[0]; t.Y = ax[1]; t.P = ax[2]; t.Q = 3;
+        t.q0 = (unsigned)(ost[0] / din[3]);
+        t.q1 = (unsigned)(ost[1] / din[3]);
+        hipLaunchKernelGGL(permute4_same_kernel, dim3(nblocks(n)), dim3(NT), 0, s, out, in, t, (unsigned)n, alpha, beta);
+        LAUNCHCHK();
+        return;
+    }
     hipLaunchKernelGGL(permute4_kernel, dim3(nblocks(n)), dim3(NT), 0, s, out, in, p, alpha, beta);
     LAUNCHCHK();
 }
