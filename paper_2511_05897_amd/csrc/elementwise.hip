@@ -11,6 +11,17 @@ inline unsigned nblocks(long long n) {
     return (unsigned)(b < 1 ? 1 : b);
 }
 #define GRID_STRIDE(i, n) for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
+// Kernels over nblk blocks of v*v elements: blocks along y (grid-stride beyond 65535), the v*v elements of
+// a block along x, so that the per-element index arithmetic is 32-bit.
+#define BLOCK_ROWS(blk, nblk) for (long long blk = blockIdx.y; blk < (nblk); blk += gridDim.y)
+#define BLOCK_COLS(r, vv) for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < (vv); r += gridDim.x * blockDim.x)
+inline dim3 block_grid(long long nblk, long long vv) {
+    long long gx = (vv + NT - 1) / NT;
+    if (gx > 1024) gx = 1024;
+    long long gy = nblk < 1 ? 1 : nblk;
+    if (gy > 65535) gy = 65535;
+    return dim3((unsigned)(gx < 1 ? 1 : gx), (unsigned)gy);
+}
 
 __global__ void fill_kernel(double* x, long long n, double v) { GRID_STRIDE(i, n) x[i] = v; }
 __global__ void copy_kernel(double* d, const double* s, long long n) { GRID_STRIDE(i, n) d[i] = s[i]; }
@@ -241,12 +252,15 @@ __global__ void z_to_x_kernel(const double* z, double* x, double* xt, long long 
 
 __global__ void d_to_z_add_kernel(double* acc, const double* d, long long nblk, int v) {
     const double s3 = 1.73205080756887729353;
-    long long vv = (long long)v * v, tot = nblk * vv;
-    GRID_STRIDE(t, tot) {
-        long long blk = t / vv;
-        int r = (int)(t % vv), a = r / v, b = r % v;
-        double dab = d[t], dba = d[blk * vv + (long long)b * v + a];
-        acc[t] += 0.5 * (dab + dba) + s3 * 0.5 * (dab - dba);
+    const int vv = v * v;
+    BLOCK_ROWS(blk, nblk) {
+        const double* db = d + blk * vv;
+        double* ab = acc + blk * vv;
+        BLOCK_COLS(r, vv) {
+            const int a = r / v, b = r - (r / v) * v;
+            const double dab = db[r], dba = db[b * v + a];
+            ab[r] += 0.5 * (dab + dba) + s3 * 0.5 * (dab - dba);
+        }
     }
 }
 
@@ -255,12 +269,12 @@ __global__ void d_to_z_add_kernel(double* acc, const double* d, long long nblk, 
 // rows (n,a) of length o*v, so that each term is one GEMM against a symmetric [(j,d)][(i,b)] matrix.
 __global__ void ph_prep_kernel(const double* z, double* Y1, double* Y2, double* Y3, int nv, int o, int v) {
     const double is3 = 0.57735026918962576451;  // 1/sqrt(3)
-    const long long vv = (long long)v * v, ov = (long long)o * v, tot = (long long)nv * o * vv;
-    GRID_STRIDE(t, tot) {
-        const long long blk = t / vv;  // n * o + j
-        const int r = (int)(t % vv), a = r / v, d = r % v;
+    const int vv = v * v;
+    const long long ov = (long long)o * v;
+    BLOCK_ROWS(blk, (long long)nv * o) BLOCK_COLS(r, vv) {  // blk = n * o + j
+        const int a = r / v, d = r - (r / v) * v;
         const int n = (int)(blk / o), j = (int)(blk % o);
-        const double zad = z[t], zda = z[blk * vv + (long long)d * v + a];
+        const double zad = z[blk * vv + r], zda = z[blk * vv + d * v + a];
         const double sy = 0.5 * (zad + zda), an = 0.5 * (zad - zda);
         const double xad = sy + an * is3, xda = sy - an * is3;
         const long long out = ((long long)n * v + a) * ov + (long long)j * v + d;
@@ -273,26 +287,32 @@ __global__ void ph_prep_kernel(const double* z, double* Y1, double* Y2, double* 
 // acc[n][i][a][b] += S(d) + sqrt3 A(d) over (a,b), d[n][i][a][b] = C12[(n,a)][(i,b)] - C3[(n,b)][(i,a)]
 __global__ void ph_fin_kernel(double* acc, const double* C12, const double* C3, int nv, int o, int v) {
     const double s3 = 1.73205080756887729353;
-    const long long vv = (long long)v * v, ov = (long long)o * v, tot = (long long)nv * o * vv;
-    GRID_STRIDE(t, tot) {
-        const long long blk = t / vv;  // n * o + i
-        const int r = (int)(t % vv), a = r / v, b = r % v;
+    const int vv = v * v;
+    const long long ov = (long long)o * v;
+    BLOCK_ROWS(blk, (long long)nv * o) {  // blk = n * o + i
         const long long n = blk / o, i = blk % o;
-        const long long ra = (n * v + a) * ov + i * v, rb = (n * v + b) * ov + i * v;
-        const double dab = C12[ra + b] - C3[rb + a];
-        const double dba = C12[rb + a] - C3[ra + b];
-        acc[t] += 0.5 * (dab + dba) + s3 * 0.5 * (dab - dba);
+        BLOCK_COLS(r, vv) {
+            const int a = r / v, b = r - (r / v) * v;
+            const long long ra = (n * v + a) * ov + i * v, rb = (n * v + b) * ov + i * v;
+            const double dab = C12[ra + b] - C3[rb + a];
+            const double dba = C12[rb + a] - C3[ra + b];
+            acc[blk * vv + r] += 0.5 * (dab + dba) + s3 * 0.5 * (dab - dba);
+        }
     }
 }
 
 __global__ void k0_add_kernel(double* s2, const double* z, const double* eo, const double* ev, int o, int v,
                               int nvec, long long ld) {
-    long long per = (long long)o * v * v, tot = per * nvec;
-    GRID_STRIDE(t, tot) {
-        long long vec = t / per, r = t % per;
-        int b = (int)(r % v); long long q = r / v;
-        int a = (int)(q % v); int i = (int)(q / v);
-        s2[vec * ld + r] += (ev[a] + ev[b] - eo[i]) * z[vec * ld + r];
+    const int vv = v * v;
+    BLOCK_ROWS(blk, (long long)nvec * o) {  // blk = vec * o + i
+        const long long vec = blk / o;
+        const int i = (int)(blk % o);
+        const long long base = vec * ld + (long long)i * vv;
+        const double ei = eo[i];
+        BLOCK_COLS(r, vv) {
+            const int a = r / v, b = r - (r / v) * v;
+            s2[base + r] += (ev[a] + ev[b] - ei) * z[base + r];
+        }
     }
 }
 
@@ -557,21 +577,23 @@ void k_ph_prep(const double* z, double* Y1, double* Y2, double* Y3, int nv, int 
     if (g_dry) return;
     long long n = (long long)nv * o * v * v;
     if (n <= 0) return;
-    hipLaunchKernelGGL(ph_prep_kernel, dim3(nblocks(n)), dim3(NT), 0, s, z, Y1, Y2, Y3, nv, o, v);
+    hipLaunchKernelGGL(ph_prep_kernel, block_grid((long long)nv * o, (long long)v * v), dim3(NT), 0, s, z, Y1, Y2, Y3, nv,
+                       o, v);
     LAUNCHCHK();
 }
 void k_ph_fin(double* acc, const double* C12, const double* C3, int nv, int o, int v, hipStream_t s) {
     if (g_dry) return;
     long long n = (long long)nv * o * v * v;
     if (n <= 0) return;
-    hipLaunchKernelGGL(ph_fin_kernel, dim3(nblocks(n)), dim3(NT), 0, s, acc, C12, C3, nv, o, v);
+    hipLaunchKernelGGL(ph_fin_kernel, block_grid((long long)nv * o, (long long)v * v), dim3(NT), 0, s, acc, C12, C3, nv,
+                       o, v);
     LAUNCHCHK();
 }
 void k_d_to_z_add(double* acc, const double* d, long long nblk, int v, hipStream_t s) {
     if (g_dry) return;
     long long n = nblk * v * v;
     if (n <= 0) return;
-    hipLaunchKernelGGL(d_to_z_add_kernel, dim3(nblocks(n)), dim3(NT), 0, s, acc, d, nblk, v);
+    hipLaunchKernelGGL(d_to_z_add_kernel, block_grid(nblk, (long long)v * v), dim3(NT), 0, s, acc, d, nblk, v);
     LAUNCHCHK();
 }
 void k_k0_add(double* s2, const double* z, const double* eo, const double* ev, int o, int v, int nvec,
@@ -579,7 +601,8 @@ void k_k0_add(double* s2, const double* z, const double* eo, const double* ev, i
     if (g_dry) return;
     long long n = (long long)o * v * v * nvec;
     if (n <= 0) return;
-    hipLaunchKernelGGL(k0_add_kernel, dim3(nblocks(n)), dim3(NT), 0, s, s2, z, eo, ev, o, v, nvec, ld);
+    hipLaunchKernelGGL(k0_add_kernel, block_grid((long long)nvec * o, (long long)v * v), dim3(NT), 0, s, s2, z, eo, ev, o,
+                       v, nvec, ld);
     LAUNCHCHK();
 }
 void k_symmetrize(double* A, int n, hipStream_t s) {

@@ -32,42 +32,46 @@ __device__ inline long long qidx(int a, int b, int v) {  // a < b
 // the threads past M v^2.
 __global__ void sa_pack_kernel(const double* z, long long ldz, int M, int v, double* Ws, double* Wa, long long lp,
                                long long lm) {
-    const long long vv = (long long)v * v, main = (long long)M * vv, np = (long long)v * (v + 1) / 2,
-                    nm = (long long)v * (v - 1) / 2;
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < main + 8LL * M;
-         t += (long long)gridDim.x * blockDim.x) {
-        if (t < main) {
-            const long long m = t / vv;
-            const int r = (int)(t - m * vv), a = r / v, b = r % v;
-            if (a > b) continue;
-            const double* zm = z + m * ldz;
-            if (a == b) {
-                Ws[m * lp + pidx(a, a, v)] = zm[(long long)a * v + a];
+    const int vv = v * v;
+    const long long np = (long long)v * (v + 1) / 2, nm = (long long)v * (v - 1) / 2;
+    for (long long m = blockIdx.y; m < M; m += gridDim.y) {
+        const double* zm = z + m * ldz;
+        double* ws = Ws + m * lp;
+        double* wa = Wa + m * lm;
+        for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < vv + 8; r += gridDim.x * blockDim.x) {
+            if (r < vv) {
+                const int a = r / v, b = r - (r / v) * v;
+                if (a > b) continue;
+                if (a == b) {
+                    ws[pidx(a, a, v)] = zm[r];
+                } else {
+                    const double x = zm[r], y = zm[b * v + a];
+                    ws[pidx(a, b, v)] = x + y;
+                    wa[qidx(a, b, v)] = x - y;
+                }
             } else {
-                const double x = zm[(long long)a * v + b], y = zm[(long long)b * v + a];
-                Ws[m * lp + pidx(a, b, v)] = x + y;
-                Wa[m * lm + qidx(a, b, v)] = x - y;
+                const int k = r - vv;
+                if (np + k < lp) ws[np + k] = 0.0;
+                if (nm + k < lm) wa[nm + k] = 0.0;
             }
-        } else {
-            const long long u = t - main, m = u / 8;
-            const int k = (int)(u % 8);
-            if (np + k < lp) Ws[m * lp + np + k] = 0.0;
-            if (nm + k < lm) Wa[m * lm + nm + k] = 0.0;
         }
     }
 }
 
 __global__ void sa_unpack_kernel(const double* Cs, const double* Ca, int M, int v, long long lp, long long lm,
                                  double* out, long long ldo) {
-    const long long vv = (long long)v * v, n = (long long)M * vv;
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
-        const long long m = t / vv;
-        const int r = (int)(t - m * vv), a = r / v, b = r % v;
-        double x;
-        if (a == b) x = Cs[m * lp + pidx(a, a, v)];
-        else if (a < b) x = Cs[m * lp + pidx(a, b, v)] + Ca[m * lm + qidx(a, b, v)];
-        else x = Cs[m * lp + pidx(b, a, v)] - Ca[m * lm + qidx(b, a, v)];
-        out[m * ldo + r] = x;
+    const int vv = v * v;
+    for (long long m = blockIdx.y; m < M; m += gridDim.y) {
+        const double* cs = Cs + m * lp;
+        const double* ca = Ca + m * lm;
+        for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < vv; r += gridDim.x * blockDim.x) {
+            const int a = r / v, b = r - (r / v) * v;
+            double x;
+            if (a == b) x = cs[pidx(a, a, v)];
+            else if (a < b) x = cs[pidx(a, b, v)] + ca[qidx(a, b, v)];
+            else x = cs[pidx(b, a, v)] - ca[qidx(b, a, v)];
+            out[m * ldo + r] = x;
+        }
     }
 }
 
@@ -104,6 +108,12 @@ __global__ void sa_zero_rows_kernel(double* Gp, double* Gm, int v, long long lp,
     }
 }
 
+inline dim3 grid_rows(long long rows, long long cols) {
+    const long long gx = std::max<long long>(1, std::min<long long>((cols + NT - 1) / NT, 1024));
+    const long long gy = std::max<long long>(1, std::min<long long>(rows, 65535));
+    return dim3((unsigned)gx, (unsigned)gy);
+}
+
 inline unsigned grid_for(long long n) {
     long long b = (n + NT - 1) / NT;
     return (unsigned)std::max<long long>(1, std::min<long long>(b, 8192));
@@ -115,15 +125,15 @@ long long sa_lm(int v) { return ((long long)v * (v - 1) / 2 + 7) / 8 * 8; }
 
 void k_sa_pack(const double* z, long long ldz, int M, int v, double* Ws, double* Wa, hipStream_t s) {
     if (g_dry || M <= 0 || v <= 0) return;
-    const long long n = (long long)M * v * v + 8LL * M;
-    hipLaunchKernelGGL(sa_pack_kernel, dim3(grid_for(n)), dim3(NT), 0, s, z, ldz, M, v, Ws, Wa, sa_lp(v), sa_lm(v));
+    hipLaunchKernelGGL(sa_pack_kernel, grid_rows(M, (long long)v * v + 8), dim3(NT), 0, s, z, ldz, M, v, Ws, Wa, sa_lp(v),
+                       sa_lm(v));
     LAUNCHCHK();
 }
 
 void k_sa_unpack(const double* Cs, const double* Ca, int M, int v, double* out, long long ldo, hipStream_t s) {
     if (g_dry || M <= 0 || v <= 0) return;
-    hipLaunchKernelGGL(sa_unpack_kernel, dim3(grid_for((long long)M * v * v)), dim3(NT), 0, s, Cs, Ca, M, v, sa_lp(v),
-                       sa_lm(v), out, ldo);
+    hipLaunchKernelGGL(sa_unpack_kernel, grid_rows(M, (long long)v * v), dim3(NT), 0, s, Cs, Ca, M, v, sa_lp(v), sa_lm(v),
+                       out, ldo);
     LAUNCHCHK();
 }
 
