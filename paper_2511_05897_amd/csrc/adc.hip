@@ -1185,6 +1185,27 @@ static int naf_blocks(const Blocks& in, double thr, Blocks& out, Arena& ws, hipS
     return xk;
 }
 
+// The ADC(2) 1p block M11 = diag(e) - sym(P), P_ab = sum_klc (2T - T~)_kl^ac (kb|lc), of a basis (the same
+// steps as the context build), into M11 [v][v].
+static void m11_adc2(Arena& ws, const double* eo, const double* ev, const Blocks& B, double* M11, hipStream_t s) {
+    const int o = B.o, v = B.v, X = B.X;
+    const long long oo = (long long)o * o, ov = (long long)o * v, vv = (long long)v * v;
+    const size_t mark = ws.mark();
+    GemmScratch gscr(ws, GEMM_SCRATCH);
+    double* ovov = take(ws, ov * ov);
+    ein(ws, "Qia,Qjb->iajb", 1.0, TV(B.Bov, {X, o, v}), TV(B.Bov, {X, o, v}), 0.0, ovov, s);
+    double* T = take(ws, oo * vv);
+    k_amp_t(ovov, eo, ev, o, v, T, s);
+    double* Tt2 = take(ws, oo * vv);
+    k_comb_t(Tt2, T, oo, v, 2.0, -1.0, s);
+    double* P = take(ws, vv);
+    ein(ws, "klac,kblc->ab", 1.0, TV(Tt2, {o, o, v, v}), TV(ovov, {o, v, o, v}), 0.0, P, s);
+    k_fill(M11, vv, 0.0, s);
+    add_sym(M11, P, v, -1.0, s);
+    k_add_diag(M11, ev, v, s);
+    ws.release(mark);
+}
+
 struct SolveOut {
     std::vector<adc3_root_report> rep;
     bool all_conv = true;
@@ -1263,6 +1284,48 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         naf_cache.N = take(ws, (long long)X * X);
         naf_cache.w = take(ws, X);
     }
+    // the truncated ADC(2) solves precondition with the exact 1p block: the eigendecompositions of the
+    // roots' M11 solved as batches (roots with equal kept counts together) before the per-root solves,
+    // for the roots where that pays and costs no second NAF eigensolver: kept count above the
+    // one-workgroup solver's size and the NAF result shared (nothing truncated) or not asked for
+    double* m11Q = nullptr;
+    double* m11w = nullptr;
+    std::vector<char> m11_pre(nroots, 0);
+    for (int k = 0; k < nroots; ++k) m11_pre[k] = pm2 == 3 && vks[k] > 96 && (!(naf > 0) || vks[k] == v);
+    if (std::count(m11_pre.begin(), m11_pre.end(), 1) >= 2) {
+        m11Q = take(ws, (long long)nroots * vv0);
+        m11w = take(ws, (long long)nroots * v);
+        const size_t mm = ws.mark();
+        double* A = take(ws, (long long)nroots * vv0);
+        double* w = take(ws, (long long)nroots * v);
+        double* Q = take(ws, (long long)nroots * vv0);
+        double* scr = take(ws, (long long)eig_batched_scratch(v, nroots));
+        std::vector<char> done(nroots, 0);
+        for (int k0 = 0; k0 < nroots; ++k0) {
+            const int vk = vks[k0];
+            if (done[k0] || !m11_pre[k0]) continue;
+            std::vector<int> grp;
+            for (int k = k0; k < nroots; ++k)
+                if (!done[k] && m11_pre[k] && vks[k] == vk) { grp.push_back(k); done[k] = 1; }
+            const long long kk = (long long)vk * vk;
+            for (size_t j = 0; j < grp.size(); ++j) {
+                const size_t mb = ws.mark();
+                GemmScratch gscr(ws, GEMM_SCRATCH);
+                Blocks Bt, Bn;
+                transform_blocks(B0, U_all + (long long)grp[j] * vv0, vk, Bt, ws, s);
+                Bn = Bt;
+                if (naf > 0) naf_blocks(Bt, naf, Bn, ws, s, vk == v ? &naf_cache : nullptr);
+                m11_adc2(ws, eo, e_all + (long long)grp[j] * v, Bn, A + j * kk, s);
+                ws.release(mb);
+            }
+            eig_batched(A, vk, (int)grp.size(), w, Q, scr, s);
+            for (size_t j = 0; j < grp.size(); ++j) {
+                k_copy(m11Q + (long long)grp[j] * vv0, Q + j * kk, kk, s);
+                k_copy(m11w + (long long)grp[j] * v, w + (long long)j * vk, vk, s);
+            }
+        }
+        ws.release(mm);
+    }
     // step 4: per root
     for (int k = 0; k < nroots; ++k) {
         const size_t mark = ws.mark();
@@ -1313,6 +1376,11 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             const size_t m2 = ws.mark();
             Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s, op.precision);
             c2->graphs = op.sigma_graphs != 0;
+            if (m11Q && m11_pre[k]) {
+                k_copy(c2->m11_Q, m11Q + (long long)k * vv0, (long long)vk * vk, s);
+                k_copy(c2->m11_w, m11w + (long long)k * v, vk, s);
+                c2->m11_eig = true;
+            }
             DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s, op.precision,
                                          false, nullptr, carried, nroots, pm2);
             k_dots(Y2k, Nk, nroots, ref, Nk, 1, Nk, ovl, 1, part, s);
