@@ -111,7 +111,6 @@ struct Ctx {
     double *G = nullptr, *Gm = nullptr;
     bool df = false;          // ladder assembled from Bvv in every application instead of stored
     double *P1 = nullptr;     // (ij|bd) as [i][b][j][d], level 3
-    double *P2 = nullptr;     // (ij|ad) as [i][a][j][d], level 3
     double *zb = nullptr, *xb = nullptr, *xtb = nullptr, *sdb = nullptr, *sb = nullptr;
     long long sigma_count = 0;
     // reduced-precision copies (precision 1: FP32 ladder and coupling; 2: BF16 ladder, FP32 coupling)
@@ -196,7 +195,6 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     c->Uz = take(ws, v * (long long)o * vv);
     if (level >= 3) {
         c->P1 = take(ws, oo * vv);
-        c->P2 = take(ws, oo * vv);
     }
     if (prec > 0) {
         c->Uz32 = ws.take<float>((size_t)std::max<long long>(v * (long long)o * vv, 1));
@@ -244,7 +242,6 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             int d_oovv[4] = {o, o, v, v};
             int p1[4] = {0, 2, 1, 3};  // [i][j][b][d] -> [i][b][j][d]
             k_permute4(c->P1, c->oovv, d_oovv, p1, 1.0, 0.0, s);
-            k_permute4(c->P2, c->oovv, d_oovv, p1, 1.0, 0.0, s);  // same layout, read as [i][a][j][d]
         }
         double* ooov = nullptr;
         if (level >= 3) {
@@ -582,20 +579,21 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
             //   d[n][i][a][b] = sum_jd (ib|jd) xt[n][j][a][d] - (ij|bd) x[n][j][a][d] - (ij|ad) x[n][j][d][b]
             // with rows (n,a) and columns (i,b): the first product through the DF factor,
             // (Y1 B^T) B with B = Bov as [Q][(j,d)] (its contraction indices j,d sit in one factor), the other
-            // two as GEMMs against the symmetric [(j,d)][(i,b)] matrices P1, P2 (the ladder tile streams each
-            // once per row tile); then sigma_z += S(d) + sqrt3 A(d)
+            // two (both against the same symmetric [(j,d)][(i,b)] matrix P1 = (ij|bd)) as one GEMM over the
+            // stacked rows [Y2; Y3] (the ladder tile streams P1 once per row tile); then
+            // sigma_z += S(d) + sqrt3 A(d)
             {
                 const int Mph = nv * v, ovi = o * v, X = c->X;
-                double *Y1 = c->xb, *Y2 = c->xtb, *Y3 = c->sdb;
+                double *Y1 = c->xb, *Y2 = c->xtb;
+                double* Y3 = Y2 + (long long)Mph * ovi;  // stacked under Y2 (inside the xtb/sdb region)
                 k_ph_prep(zb, Y1, Y2, Y3, nv, o, v, s);
-                double* C12 = zb;  // z is not needed any more
-                double* C3 = take(ws, NVMAX * (long long)o * vv);
-                const long long pe = NVMAX * (long long)o * vv;
+                double* D = zb;  // z is not needed any more: the factor product goes here
+                double* E = take(ws, 2 * NVMAX * (long long)o * vv);
+                const long long pe = 2 * NVMAX * (long long)o * vv;
                 double* part = take(ws, pe);
                 double* Wq = take(ws, (long long)NVMAX * v * X);
-                const bool lad = ladder_supported(Mph, ovi, ovi, Y2, ovi, c->P1, ovi, C12, ovi);
-                // the tuner's trial launches write C12, which the first product overwrites
-                const int nch = lad ? ladder_tuned_chunks(0, Mph, ovi, ovi, Y2, ovi, c->P1, ovi, C12, ovi, part, pe, s) : 1;
+                const bool lad = ladder_supported(2 * Mph, ovi, ovi, Y2, ovi, c->P1, ovi, E, ovi);
+                const int nch = lad ? ladder_tuned_chunks(0, 2 * Mph, ovi, ovi, Y2, ovi, c->P1, ovi, E, ovi, part, pe, s) : 1;
                 {
                     Gemm g;  // Wq[(n,a)][Q] = sum_(j,d) Y1[(n,a)][(j,d)] Bov[Q][(j,d)]
                     g.M = Mph; g.N = X; g.K = ovi;
@@ -604,15 +602,10 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                     g.C = Wq; g.sCm = X; g.sCn = 1;
                     gemm_split(g, s);
                 }
-                gemm_rm(Mph, ovi, X, 1.0, Wq, X, false, c->Bov, ovi, false, 0.0, C12, ovi, s);
-                if (lad) {
-                    ladder_gemm(Mph, ovi, ovi, -1.0, Y2, ovi, c->P1, ovi, 1.0, C12, ovi, nch, part, pe, s, 2);
-                    ladder_gemm(Mph, ovi, ovi, 1.0, Y3, ovi, c->P2, ovi, 0.0, C3, ovi, nch, part, pe, s, 2);
-                } else {
-                    gemm_rm(Mph, ovi, ovi, -1.0, Y2, ovi, false, c->P1, ovi, false, 1.0, C12, ovi, s);
-                    gemm_rm(Mph, ovi, ovi, 1.0, Y3, ovi, false, c->P2, ovi, false, 0.0, C3, ovi, s);
-                }
-                k_ph_fin(c->sb, C12, C3, nv, o, v, s);
+                gemm_rm(Mph, ovi, X, 1.0, Wq, X, false, c->Bov, ovi, false, 0.0, D, ovi, s);
+                if (lad) ladder_gemm(2 * Mph, ovi, ovi, 1.0, Y2, ovi, c->P1, ovi, 0.0, E, ovi, nch, part, pe, s, 2);
+                else gemm_rm(2 * Mph, ovi, ovi, 1.0, Y2, ovi, false, c->P1, ovi, false, 0.0, E, ovi, s);
+                k_ph_fin(c->sb, D, E, E + (long long)Mph * ovi, nv, o, v, s);
             }
             k_copy2d(ss + v, N, c->sb, ovv, nv, ovv, 1.0, 1.0, s);
         }

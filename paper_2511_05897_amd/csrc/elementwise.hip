@@ -285,7 +285,7 @@ __global__ void ph_prep_kernel(const double* z, double* Y1, double* Y2, double* 
 }
 
 // acc[n][i][a][b] += S(d) + sqrt3 A(d) over (a,b), d[n][i][a][b] = C12[(n,a)][(i,b)] - C3[(n,b)][(i,a)]
-__global__ void ph_fin_kernel(double* acc, const double* C12, const double* C3, int nv, int o, int v) {
+__global__ void ph_fin_kernel(double* acc, const double* D, const double* E2, const double* E3, int nv, int o, int v) {
     const double s3 = 1.73205080756887729353;
     const int vv = v * v;
     const long long ov = (long long)o * v;
@@ -294,8 +294,8 @@ __global__ void ph_fin_kernel(double* acc, const double* C12, const double* C3, 
         BLOCK_COLS(r, vv) {
             const int a = r / v, b = r - (r / v) * v;
             const long long ra = (n * v + a) * ov + i * v, rb = (n * v + b) * ov + i * v;
-            const double dab = C12[ra + b] - C3[rb + a];
-            const double dba = C12[rb + a] - C3[ra + b];
+            const double dab = D[ra + b] - E2[ra + b] - E3[rb + a];
+            const double dba = D[rb + a] - E2[rb + a] - E3[ra + b];
             acc[blk * vv + r] += 0.5 * (dab + dba) + s3 * 0.5 * (dab - dba);
         }
     }
@@ -581,11 +581,11 @@ void k_ph_prep(const double* z, double* Y1, double* Y2, double* Y3, int nv, int 
                        o, v);
     LAUNCHCHK();
 }
-void k_ph_fin(double* acc, const double* C12, const double* C3, int nv, int o, int v, hipStream_t s) {
+void k_ph_fin(double* acc, const double* D, const double* E2, const double* E3, int nv, int o, int v, hipStream_t s) {
     if (g_dry) return;
     long long n = (long long)nv * o * v * v;
     if (n <= 0) return;
-    hipLaunchKernelGGL(ph_fin_kernel, block_grid((long long)nv * o, (long long)v * v), dim3(NT), 0, s, acc, C12, C3, nv,
+    hipLaunchKernelGGL(ph_fin_kernel, block_grid((long long)nv * o, (long long)v * v), dim3(NT), 0, s, acc, D, E2, E3, nv,
                        o, v);
     LAUNCHCHK();
 }

@@ -201,8 +201,8 @@ void k_sa_form(const double* Gf, int a0, int na, int v, double* Gp, double* Gm, 
 void k_sa_zero_pad_rows(double* Gp, double* Gm, int v, hipStream_t s);
 // Y2 = x[n][j][a][d], Y1 = 2x[n][j][a][d] - x[n][j][d][a], Y3 = x[n][j][d][a]
 void k_ph_prep(const double* z, double* Y1, double* Y2, double* Y3, int nv, int o, int v, hipStream_t s);
-// acc[n][i][a][b] += S(d) + sqrt3 A(d), d[n][i][a][b] = C12[(n,a)][(i,b)] - C3[(n,b)][(i,a)]
-void k_ph_fin(double* acc, const double* C12, const double* C3, int nv, int o, int v, hipStream_t s);
+// acc[n][i][a][b] += S(d) + sqrt3 A(d), d[n][i][a][b] = D[(n,a)][(i,b)] - E2[(n,a)][(i,b)] - E3[(n,b)][(i,a)]
+void k_ph_fin(double* acc, const double* D, const double* E2, const double* E3, int nv, int o, int v, hipStream_t s);
 // sigma2 += K0 * z, K0[i][a][b] = ev_a + ev_b - eo_i;  z/sigma2 with vector stride ld
 void k_k0_add(double* s2, const double* z, const double* eo, const double* ev, int o, int v, int nvec,
               long long ld, hipStream_t s);
