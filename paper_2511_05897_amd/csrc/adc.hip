@@ -320,8 +320,9 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             double* Tt2 = take(ws, oo * vv);
             k_comb_t(Tt2, T, oo, v, 2.0, -1.0, s);
             double* P = take(ws, vv);
-            // stored ladder: full rows G[(ab),(cd)] = (ac|bd) = sum_Q B^Q_ac B^Q_bd (b >= a) for a chunk of a,
-            // one batched GEMM per a over b, then folded into the pair blocks G+ and G-
+            // stored ladder: for a chunk of a, (ac|bd) = sum_Q B^Q_ac B^Q_bd as one GEMM with rows (a,c) (from a
+            // transposed copy of Bvv) and columns (b,d), b from the chunk's first a, then folded into the pair
+            // blocks G+ and G-
             if (!c->df) {
                 const long long v3 = (long long)v * vv;
                 // chunk: at most an eighth of the stored blocks (and the chunk budget)
@@ -330,18 +331,17 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
                     1, std::min<long long>({(long long)v, budget / std::max<long long>(v3, 1), 65535 / v}));
                 const size_t mg = ws.mark();
                 double* Gf = take(ws, (long long)na * v3);
+                double* BT = take(ws, vv * X);  // [(a,c)][Q]
+                {
+                    int d4[4] = {1, X, v, v}, p4[4] = {0, 2, 3, 1};
+                    k_permute4(BT, Bvv, d4, p4, 1.0, 0.0, s);
+                }
                 for (int a0 = 0; a0 < v; a0 += na) {
                     const int nc = std::min(na, v - a0);
-                    for (int a = a0; a < a0 + nc; ++a) {
-                        Gemm g;
-                        g.M = v; g.N = v; g.K = X;
-                        g.A = Bvv + (long long)a * v; g.sAm = 1; g.sAk = vv;  // A(c,Q) = Bvv[Q][a][c]
-                        g.B = Bvv + (long long)a * v; g.sBk = vv; g.sBn = 1;  // B(Q,d) = Bvv[Q][b][d], b from a
-                        g.C = Gf + (long long)(a - a0) * v3 + (long long)a * vv; g.sCm = v; g.sCn = 1;
-                        g.nb0 = v - a; g.bB0 = v; g.bC0 = vv;
-                        gemm(g, s);
-                    }
-                    k_sa_form(Gf, a0, nc, v, c->G, c->Gm, s);
+                    const long long ldf = (long long)(v - a0) * v;
+                    gemm_rm(nc * v, (int)ldf, X, 1.0, BT + (long long)a0 * v * X, X, false, Bvv + (long long)a0 * v, vv,
+                            false, 0.0, Gf, ldf, s);
+                    k_sa_form(Gf, ldf, a0, nc, v, c->G, c->Gm, s);
                 }
                 k_sa_zero_pad_rows(c->G, c->Gm, v, s);
                 ws.release(mg);

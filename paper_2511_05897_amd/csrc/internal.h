@@ -195,8 +195,8 @@ long long sa_lm(int v);
 void k_sa_pack(const double* z, long long ldz, int M, int v, double* Ws, double* Wa, hipStream_t s);
 // out[m][a][b] = C+[(ab)] + C-[(ab)] (a < b), C+[(ba)] - C-[(ba)] (a > b), C+[(aa)]  (row stride ldo)
 void k_sa_unpack(const double* Cs, const double* Ca, int M, int v, double* out, long long ldo, hipStream_t s);
-// G+ / G- rows (a,b), a in [a0, a0+na), from the full rows Gf[a-a0][b][c][d] (b >= a read)
-void k_sa_form(const double* Gf, int a0, int na, int v, double* Gp, double* Gm, hipStream_t s);
+// G+ / G- rows (a,b), a in [a0, a0+na), b >= a, from (ac|bd) = Gf[((a-a0) v + c) ldf + (b-a0) v + d]
+void k_sa_form(const double* Gf, long long ldf, int a0, int na, int v, double* Gp, double* Gm, hipStream_t s);
 // zero the padding rows of G+ and G-
 void k_sa_zero_pad_rows(double* Gp, double* Gm, int v, hipStream_t s);
 // Y2 = x[n][j][a][d], Y1 = 2x[n][j][a][d] - x[n][j][d][a], Y3 = x[n][j][d][a]
