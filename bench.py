@@ -268,7 +268,7 @@ def large_mixed_study(adc, d, torch, np, scale, precs=(0, 1, 2), ref=None):
     """ADC(3) Davidson of the large mixed-precision workload (o=40, v=600, X=1800, seed 2, canonical basis,
     5 roots, conv 1e-6), B scaled by `scale`, with FP64, FP32-operand and BF16-operand sigma (each
     reduced-precision Davidson ends with an FP64 restart).  The ladder is assembled from the DF factor in
-    every application (the stored v^4 matrix would take 1 TB).  Context setup (FP64 in every mode) is
+    every application (its stored pair blocks would take 518 GB).  Context setup (FP64 in every mode) is
     timed on its own; the FP64 run shares the first reduced-precision context.  `ref`: FP64 roots of an
     earlier run when 0 is not in `precs`."""
     import synth
