@@ -536,6 +536,18 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                 const long long pe = 3 * NVMAX * (long long)o * vv;
                 k_sa_pack(zb, vv, M, v, W, W + (long long)M * lp, s);
                 if (prec > 0) k_to_lowp(c->zlo, W, (long long)M * (lp + lm), prec, s);
+                // FP64 with >= 48 rows: the packed rows k-major, for the kernel that copies both tiles
+                // straight into LDS (below that the G stream bounds the product and the row-major kernel,
+                // with more workgroups per CU, streams it faster)
+                const long long ldt = (M + 1) / 2 * 2;
+                double* Wt = prec == 0 ? take(ws, ldt * (lp + lm)) : nullptr;
+                int ltm, lmt;
+                ladder_rows(M, ltm, lmt);
+                const bool kmajor = prec == 0 && ltm >= 3;
+                if (kmajor) {
+                    k_transpose(W, lp, M, lp, Wt, ldt, s);
+                    k_transpose(W + (long long)M * lp, lm, M, lm, Wt + ldt * lp, ldt, s);
+                }
                 const int eb = prec == 0 ? 8 : prec == 1 ? 4 : 2;
                 const double pk = prec == 0 ? PEAK_FP64_MFMA : prec == 1 ? PEAK_FP32_MFMA : PEAK_BF16_MFMA;
                 for (int blk = 0; blk < 2; ++blk) {
@@ -564,7 +576,13 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                     } else {
                         const double* Z = W + woff;
                         const double* Gb = blk == 0 ? c->G : c->Gm;
-                        if (ladder_supported(M, (int)n, (int)n, Z, n, Gb, n, C, n)) {
+                        const double* Zt = kmajor ? Wt + (blk == 0 ? 0 : ldt * lp) : nullptr;
+                        if (kmajor && ladder_t_supported(M, (int)n, (int)n, Zt, ldt, Gb, n) &&
+                            ladder_gemm_t(M, (int)n, (int)n, 1.0, Zt, ldt, Gb, n, 0.0, C, n,
+                                          ladder_tuned_chunks(3, M, (int)n, (int)n, Zt, ldt, Gb, n, C, n, c->xb, pe, s),
+                                          c->xb, pe, s)) {
+                            // done on the k-major kernel
+                        } else if (ladder_supported(M, (int)n, (int)n, Z, n, Gb, n, C, n)) {
                             const int nch = ladder_tuned_chunks(0, M, (int)n, (int)n, Z, n, Gb, n, C, n, c->xb, pe, s);
                             ladder_gemm(M, (int)n, (int)n, 1.0, Z, n, Gb, n, 0.0, C, n, nch, c->xb, pe, s);
                         } else {

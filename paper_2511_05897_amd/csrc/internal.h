@@ -92,12 +92,20 @@ void ladder_rows(int M, int& tm, int& mtiles);
 void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long ldz, const double* G, long long ldg,
                  double beta, double* C, long long ldc, int nchunk, double* partial, long long partial_elems,
                  hipStream_t s, int tag = 0);  // tag: 0 sigma ladder, 1 tuner trial, 2 other GEMM
+// the same product with Z k-major (Zt[k][m], ldz >= M): both tiles copied HBM -> LDS by buffer loads.
+// Each chunk must stay below 2^31 bytes: nchunk is raised to ladder_t_min_chunks (0: shape not
+// supported).  Returns false, with nothing launched, when those chunks do not fit the partial buffer.
+int ladder_t_min_chunks(int K, long long ldz, long long ldg);
+bool ladder_t_supported(int M, int N, int K, const double* Zt, long long ldz, const double* G, long long ldg);
+bool ladder_gemm_t(int M, int N, int K, double alpha, const double* Zt, long long ldz, const double* G, long long ldg,
+                   double beta, double* C, long long ldc, int nchunk, double* partial, long long partial_elems,
+                   hipStream_t s, int tag = 0);  // tag: 0 sigma ladder, 1 tuner trial
 bool ladder_lp_supported(int prec, int M, int N, int K, const void* Z, long long ldz, const void* G, long long ldg,
                          const double* C, long long ldc);
 void ladder_gemm_lp(int prec, int M, int N, int K, double alpha, const void* Z, long long ldz, const void* G,
                     long long ldg, double beta, double* C, long long ldc, int nchunk, double* partial,
                     long long partial_elems, hipStream_t s, bool trial = false);
-// chunk count for a ladder shape (prec 0 FP64, 1 FP32, 2 BF16), measured on first use
+// chunk count for a ladder shape (prec 0 FP64, 1 FP32, 2 BF16, 3 FP64 with Z k-major), measured on first use
 int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long ldz, const void* G, long long ldg,
                         double* C, long long ldc, double* partial, long long partial_elems, hipStream_t s);
 // ladder from the DF factor (dfladder.hip): C[m] (+)= sum_Q B^Q Z[m] B^Q for m < M, with Bvv [X][v][v]
@@ -195,6 +203,8 @@ long long sa_lm(int v);
 void k_sa_pack(const double* z, long long ldz, int M, int v, double* Ws, double* Wa, hipStream_t s);
 // out[m][a][b] = C+[(ab)] + C-[(ab)] (a < b), C+[(ba)] - C-[(ba)] (a > b), C+[(aa)]  (row stride ldo)
 void k_sa_unpack(const double* Cs, const double* Ca, int M, int v, double* out, long long ldo, hipStream_t s);
+// dst[c][r] = src[r][c] for r < rows, c < cols (tiled through LDS)
+void k_transpose(const double* src, long long lds, int rows, long long cols, double* dst, long long ldd, hipStream_t s);
 // G+ / G- rows (a,b), a in [a0, a0+na), b >= a, from (ac|bd) = Gf[((a-a0) v + c) ldf + (b-a0) v + d]
 void k_sa_form(const double* Gf, long long ldf, int a0, int na, int v, double* Gp, double* Gm, hipStream_t s);
 // zero the padding rows of G+ and G-

@@ -84,47 +84,43 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f64_kernel(LadderArgs g) {
         bkr[p] = idx / (LBN / 2);
         bnq[p] = idx % (LBN / 2);
     }
-    d2v ra[PA], rb[PB];
+    // Every load is issued, from an address clamped into the operands; the elements outside
+    // the tile or the chunk are zeroed when the slab is written to LDS.  Without branches around
+    // the loads the compiler can wait for one register set while the next is still in flight.
     const d2v z2 = {0.0, 0.0};
-    auto fetch = [&](int k0) {
+    auto fetch = [&](int k0, d2v(&ra)[PA], d2v(&rb)[PB]) {
 #pragma unroll
         for (int p = 0; p < PA; ++p) {
-            const long long m = m0 + arow[p];
-            const int k = k0 + 2 * akq[p];
-            ra[p] = (arow[p] >= 0 && m < g.M && k < ke) ? *(const d2v*)(g.Z + m * g.ldz + k) : z2;
+            const long long m = std::min(m0 + std::max(arow[p], 0), (long long)g.M - 1);
+            const int k = std::min(k0 + 2 * akq[p], g.K - 2);
+            ra[p] = *(const d2v*)(g.Z + m * g.ldz + k);
         }
 #pragma unroll
         for (int p = 0; p < PB; ++p) {
-            const int k = k0 + bkr[p];
-            const long long n = n0 + 2 * bnq[p];
-            rb[p] = (k < ke && n < g.N) ? *(const d2v*)(g.G + (long long)k * g.ldg + n) : z2;
+            const int k = std::min(k0 + bkr[p], g.K - 1);
+            const long long n = std::min(n0 + 2 * bnq[p], (long long)g.N - 2);
+            rb[p] = *(const d2v*)(g.G + (long long)k * g.ldg + n);
         }
     };
-    auto stash = [&](int buf) {
+    auto stash = [&](int buf, int k0, const d2v(&ra)[PA], const d2v(&rb)[PB]) {
 #pragma unroll
         for (int p = 0; p < PA; ++p)
             if (arow[p] >= 0) {
-                As[buf][2 * akq[p]][arow[p]] = ra[p].x;
-                As[buf][2 * akq[p] + 1][arow[p]] = ra[p].y;
+                const d2v x = (m0 + arow[p] < g.M && k0 + 2 * akq[p] < ke) ? ra[p] : z2;
+                As[buf][2 * akq[p]][arow[p]] = x.x;
+                As[buf][2 * akq[p] + 1][arow[p]] = x.y;
             }
 #pragma unroll
-        for (int p = 0; p < PB; ++p) *(d2v*)&Bs[buf][bkr[p]][2 * bnq[p]] = rb[p];
+        for (int p = 0; p < PB; ++p)
+            *(d2v*)&Bs[buf][bkr[p]][2 * bnq[p]] = (k0 + bkr[p] < ke && n0 + 2 * bnq[p] < g.N) ? rb[p] : z2;
     };
     d4v acc[TM][LTN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < LTN; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
-    const int nslab = (ke - kb + LBK - 1) / LBK;
-    if (nslab > 0) {
-        fetch(kb);
-        stash(0);
-    }
-    __syncthreads();
     const int cb = wave * (16 * LTN);
-    for (int s = 0; s < nslab; ++s) {
-        const int buf = s & 1;
-        if (s + 1 < nslab) fetch(kb + (s + 1) * LBK);
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int kk = 0; kk < LBK; kk += 4) {
             double bf[LTN];
@@ -137,10 +133,144 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f64_kernel(LadderArgs g) {
                 for (int j = 0; j < LTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[j], acc[i][j], 0, 0, 0);
             }
         }
-        if (s + 1 < nslab) stash(buf ^ 1);
+    };
+    const int nslab = (ke - kb + LBK - 1) / LBK;
+    // two slabs in flight in two register sets: slab s+2 is fetched while slab s is multiplied
+    // and slab s+1 (fetched one slab earlier) is written to LDS after it
+    d2v ra0[PA], rb0[PB], ra1[PA], rb1[PB];
+    fetch(kb, ra0, rb0);
+    fetch(kb + LBK, ra1, rb1);
+    stash(0, kb, ra0, rb0);
+    __syncthreads();
+    auto step = [&](int s, d2v(&rc)[PA], d2v(&rbc)[PB], const d2v(&rn)[PA], const d2v(&rbn)[PB]) {
+        fetch(kb + (s + 2) * LBK, rc, rbc);
+        compute(s & 1);
+        stash((s & 1) ^ 1, kb + (s + 1) * LBK, rn, rbn);
         __syncthreads();
+    };
+    int s = 0;
+    for (; s + 1 < nslab; s += 2) {  // no branch inside the body, so no wait on the set in flight
+        step(s, ra0, rb0, ra1, rb1);
+        step(s + 1, ra1, rb1, ra0, rb0);
     }
+    if (s < nslab) step(s, ra0, rb0, ra1, rb1);
     // epilogue: partial sums, or the final alpha/beta update when K is not split
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < LTN; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const long long row = m0 + 16 * i + lk + 4 * r;
+                const long long col = n0 + cb + 16 * j + lr;
+                if (row < g.M && col < g.N) {
+                    if (g.nchunk > 1) {
+                        g.P[((long long)chunk * g.M + row) * g.N + col] = acc[i][j][r];
+                    } else {
+                        double* c = g.C + row * g.ldc + col;
+                        const double v = g.alpha * acc[i][j][r];
+                        *c = (g.beta == 0.0) ? v : v + g.beta * (*c);
+                    }
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// The same product with Z given k-major (Zt[k][m], as G is [k][n]).  Both tiles then are
+// plain row copies, so they go from HBM straight into LDS by buffer loads (16 bytes a lane,
+// no registers, no stash): one load per tile row and wave, addressed by a per-lane offset
+// fixed for the kernel and a per-slab scalar offset.  The buffer descriptors cover the
+// chunk's rows only, so rows past the chunk's end read as zero and need no masking; columns
+// past M or N may read neighbouring data, which only reaches output rows or columns that are
+// never written.  The two LDS buffers are separate arrays so that the compiler can tell the
+// loads into one from the reads of the other and waits for the loads only at the barrier.
+// Byte offsets within a chunk are 32-bit: the host keeps each chunk below 2^31 bytes.
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+__device__ inline __amdgpu_buffer_rsrc_t chunk_rsrc(const double* base, long long bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ inline void block_tile(int nchunk, int ntn, int& chunk, int& nt) {
+    const int b = blockIdx.x;
+    if ((nchunk & 7) == 0) {
+        const int q = b >> 3;
+        chunk = (q / ntn) * 8 + (b & 7);
+        nt = q % ntn;
+    } else {
+        chunk = b / ntn;
+        nt = b % ntn;
+    }
+}
+
+template <int TM, int TAG>
+__global__ __launch_bounds__(LNT, 2) void ladder_f64t_kernel(LadderArgs g) {
+    constexpr int BM = 16 * TM, RA = BM + 2, RB = LBN + 2;  // LDS row strides (doubles)
+    __shared__ __attribute__((aligned(16))) double As0[LBK][RA], As1[LBK][RA];
+    __shared__ __attribute__((aligned(16))) double Bs0[LBK][RB], Bs1[LBK][RB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    int chunk, nt;
+    block_tile(g.nchunk, g.ntn, chunk, nt);
+    const long long m0 = (long long)blockIdx.y * BM, n0 = (long long)nt * LBN;
+    const int kb = chunk * g.Kc, ke = min(g.K, kb + g.Kc);
+    const __amdgpu_buffer_rsrc_t ra = chunk_rsrc(g.Z + (long long)kb * g.ldz + m0, (long long)(ke - kb) * g.ldz * 8 - m0 * 8);
+    const __amdgpu_buffer_rsrc_t rb = chunk_rsrc(g.G + (long long)kb * g.ldg + n0, (long long)(ke - kb) * g.ldg * 8 - n0 * 8);
+    // wave w copies rows 4w .. 4w+3 of both tiles; lane l the two elements at column 2l
+    const bool acol = 2 * lane < BM;
+    unsigned voa[4], vob[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        voa[r] = (unsigned)(((4 * wave + r) * g.ldz + 2 * lane) * 8);
+        vob[r] = (unsigned)(((4 * wave + r) * g.ldg + 2 * lane) * 8);
+    }
+    auto issue = [&](double(&At)[LBK][RA], double(&Bt)[LBK][RB], int s) {
+        const int soa = s * LBK * (int)g.ldz * 8, sob = s * LBK * (int)g.ldg * 8;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (acol) __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)&At[4 * wave + r][0], 16, voa[r], soa, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr)&Bt[4 * wave + r][0], 16, vob[r], sob, 0, 0);
+        }
+    };
+    d4v acc[TM][LTN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < LTN; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
+    const int cb = wave * (16 * LTN);
+    auto compute = [&](const double(&At)[LBK][RA], const double(&Bt)[LBK][RB]) {
+#pragma unroll
+        for (int kk = 0; kk < LBK; kk += 4) {
+            double bf[LTN];
+#pragma unroll
+            for (int j = 0; j < LTN; ++j) bf[j] = Bt[kk + lk][cb + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const double af = At[kk + lk][16 * i + lr];
+#pragma unroll
+                for (int j = 0; j < LTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    };
+    // all of this wave's loads have landed in LDS (and its LDS reads are done), then the barrier
+    auto sync = [] {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    };
+    const int nslab = (ke - kb + LBK - 1) / LBK;
+    issue(As0, Bs0, 0);
+    sync();
+    int s = 0;
+    for (; s + 1 < nslab; s += 2) {
+        issue(As1, Bs1, s + 1);
+        compute(As0, Bs0);
+        sync();
+        if (s + 2 < nslab) issue(As0, Bs0, s + 2);
+        compute(As1, Bs1);
+        sync();
+    }
+    if (s < nslab) compute(As0, Bs0);
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -181,18 +311,6 @@ struct LadderLP {
     int M, N, K, Kc, ntn, nchunk;
     double alpha, beta;
 };
-
-__device__ inline void block_tile(int nchunk, int ntn, int& chunk, int& nt) {
-    const int b = blockIdx.x;
-    if ((nchunk & 7) == 0) {
-        const int q = b >> 3;
-        chunk = (q / ntn) * 8 + (b & 7);
-        nt = q % ntn;
-    } else {
-        chunk = b / ntn;
-        nt = b % ntn;
-    }
-}
 
 template <int TM>
 __device__ inline void store_f32_tile(const LadderLP& g, f4v (&acc)[TM][LTN], long long m0, long long n0, int cb,
@@ -439,6 +557,25 @@ void launch(const LadderArgs& a, int tm, int mtiles, int tag, hipStream_t s) {
     else launch_tag<0>(a, tm, mtiles, s);
     LAUNCHCHK();
 }
+
+template <int TM, int TAG>
+void launch_t_tm(const LadderArgs& a, int mtiles, hipStream_t s) {
+    hipLaunchKernelGGL((ladder_f64t_kernel<TM, TAG>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
+}
+
+template <int TAG>
+void launch_t_tag(const LadderArgs& a, int tm, int mtiles, hipStream_t s) {
+    switch (tm) {
+        case 1: launch_t_tm<1, TAG>(a, mtiles, s); break;
+        case 2: launch_t_tm<2, TAG>(a, mtiles, s); break;
+        case 3: launch_t_tm<3, TAG>(a, mtiles, s); break;
+        case 4: launch_t_tm<4, TAG>(a, mtiles, s); break;
+        case 5: launch_t_tm<5, TAG>(a, mtiles, s); break;
+        case 6: launch_t_tm<6, TAG>(a, mtiles, s); break;
+        case 7: launch_t_tm<7, TAG>(a, mtiles, s); break;
+        default: launch_t_tm<8, TAG>(a, mtiles, s); break;
+    }
+}
 }  // namespace
 
 // Row tiling: as few tiles of <= 128 rows as possible (each tile streams G once), each
@@ -518,6 +655,50 @@ void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long l
 // chunk counts sum in a different order, so the last bits of sigma can differ between
 // choices, never between two calls that use the same choice.
 // ---------------------------------------------------------------------------
+// Chunks of the k-major kernel are addressed with 32-bit byte offsets: the smallest chunk count
+// whose chunks (a multiple of 64 rows each) stay below 2^31 bytes in both operands, or 0 when
+// not even 64 rows fit.
+int ladder_t_min_chunks(int K, long long ldz, long long ldg) {
+    const long long ld = std::max(ldz, ldg);
+    if (K <= 0 || ld <= 0) return 0;
+    const long long kcmax = ((1LL << 31) - 1) / (8 * ld) / 64 * 64;
+    if (kcmax < 64) return 0;
+    int n = (int)std::max<long long>(1, (K + kcmax - 1) / kcmax);
+    while (ladder_chunk_len(K, n) > kcmax) ++n;
+    return n;
+}
+
+bool ladder_t_supported(int M, int N, int K, const double* Zt, long long ldz, const double* G, long long ldg) {
+    auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    return M > 0 && N > 0 && K > 0 && ldz >= M && ldg >= N && ldz % 2 == 0 && ldg % 2 == 0 && al16(Zt) && al16(G) &&
+           ladder_t_min_chunks(K, ldz, ldg) > 0;
+}
+
+bool ladder_gemm_t(int M, int N, int K, double alpha, const double* Zt, long long ldz, const double* G, long long ldg,
+                   double beta, double* C, long long ldc, int nchunk, double* partial, long long partial_elems,
+                   hipStream_t s, int tag) {
+    if (M <= 0 || N <= 0) return true;
+    const int nmin = ladder_t_min_chunks(K, ldz, ldg);
+    if (nmin <= 0) return false;
+    nchunk = std::max(nmin, std::min(nchunk, (K + 255) / 256));
+    if (nchunk > 1 && (!partial || (long long)nchunk * M * N > partial_elems)) return false;
+    if (g_dry) return true;
+    int tm, mtiles;
+    ladder_rows(M, tm, mtiles);
+    LadderArgs a;
+    a.Z = Zt; a.ldz = ldz; a.G = G; a.ldg = ldg; a.C = C; a.ldc = ldc; a.P = partial;
+    a.M = M; a.N = N; a.K = K;
+    a.Kc = ladder_chunk_len(K, nchunk);
+    a.nchunk = (K + a.Kc - 1) / a.Kc;
+    a.ntn = (N + LBN - 1) / LBN;
+    a.alpha = alpha; a.beta = beta;
+    if (tag == 1) launch_t_tag<1>(a, tm, mtiles, s);
+    else launch_t_tag<0>(a, tm, mtiles, s);
+    LAUNCHCHK();
+    if (a.nchunk > 1) splitk_reduce(partial, a.nchunk, M, N, alpha, beta, C, ldc, 1, s);
+    return true;
+}
+
 namespace {
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune;
@@ -535,7 +716,7 @@ std::string arch_name() {
 std::string tune_key(int prec, int M, int N, int K) {
     int tm, mt;
     ladder_rows(M, tm, mt);
-    return std::string(prec == 0 ? "ladder_f64 " : prec == 1 ? "ladder_f32 " : "ladder_bf16 ") + arch_name() + " " + std::to_string(tm) + " " + std::to_string(mt) + " " +
+    return std::string(prec == 0 ? "ladder_f64 " : prec == 1 ? "ladder_f32 " : prec == 2 ? "ladder_bf16 " : "ladder_f64t ") + arch_name() + " " + std::to_string(tm) + " " + std::to_string(mt) + " " +
            std::to_string(N) + " " + std::to_string(K);
 }
 
@@ -572,6 +753,8 @@ static void ladder_run(int prec, int M, int N, int K, const void* Z, long long l
     if (prec == 0)
         ladder_gemm(M, N, K, 1.0, (const double*)Z, ldz, (const double*)G, ldg, 0.0, C, ldc, nchunk, partial, pe, s,
                     1);
+    else if (prec == 3)
+        ladder_gemm_t(M, N, K, 1.0, (const double*)Z, ldz, (const double*)G, ldg, 0.0, C, ldc, nchunk, partial, pe, s, 1);
     else
         ladder_gemm_lp(prec, M, N, K, 1.0, Z, ldz, G, ldg, 0.0, C, ldc, nchunk, partial, pe, s, true);
 }
@@ -580,7 +763,7 @@ int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long 
                         double* C, long long ldc, double* partial, long long partial_elems, hipStream_t s) {
     const char* fixed = std::getenv("ADC3_LADDER_CHUNKS");
     if (fixed && *fixed) return std::max(1, std::atoi(fixed));
-    const int def = 8;
+    const int def = std::max(8, prec == 3 ? ladder_t_min_chunks(K, ldz, ldg) : 1);
     if (g_dry) return def;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return def;
@@ -591,12 +774,16 @@ int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long 
         auto it = g_tune.find(key);
         if (it != g_tune.end()) return it->second;
     }
+    // prec 3 is the FP64 kernel with Z k-major, whose chunks have a minimum count
+    const int nmin = prec == 3 ? ladder_t_min_chunks(K, ldz, ldg) : 1;
     std::vector<int> cand;
     for (int c : {1, 2, 4, 8, 16}) {
+        if (c < nmin) continue;
         if (c > 1 && (long long)c * M * N > partial_elems) continue;
         if (c > 1 && K / c < 256) continue;
         cand.push_back(c);
     }
+    if (cand.empty()) return std::max(nmin, 1);
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));

@@ -76,6 +76,29 @@ __global__ void sa_unpack_kernel(const double* Cs, const double* Ca, int M, int 
     }
 }
 
+// 32 x 32 tiles through LDS (one padding column against bank conflicts); 256 threads, each moving
+// 4 elements in and 4 out, both sides coalesced along the tile's rows
+constexpr int TT = 32;
+__global__ void transpose_kernel(const double* src, long long lds, int rows, long long cols, double* dst, long long ldd) {
+    __shared__ double t[TT][TT + 1];
+    const long long c0 = (long long)blockIdx.x * TT;
+    const int r0 = blockIdx.y * TT;
+    const int tx = threadIdx.x & (TT - 1), ty = threadIdx.x / TT;  // ty 0..7
+#pragma unroll
+    for (int q = 0; q < TT; q += 8) {
+        const int r = r0 + ty + q;
+        const long long c = c0 + tx;
+        if (r < rows && c < cols) t[ty + q][tx] = src[(long long)r * lds + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TT; q += 8) {
+        const long long c = c0 + ty + q;
+        const int r = r0 + tx;
+        if (r < rows && c < cols) dst[c * ldd + r] = t[tx][ty + q];
+    }
+}
+
 inline dim3 grid_rows(long long rows, long long cols) {
     const long long gx = std::max<long long>(1, std::min<long long>((cols + NT - 1) / NT, 1024));
     const long long gy = std::max<long long>(1, std::min<long long>(rows, 65535));
@@ -83,6 +106,14 @@ inline dim3 grid_rows(long long rows, long long cols) {
 }
 
 }  // namespace
+
+void k_transpose(const double* src, long long lds, int rows, long long cols, double* dst, long long ldd, hipStream_t s) {
+    if (g_dry || rows <= 0 || cols <= 0) return;
+    const long long gx = (cols + TT - 1) / TT, gy = (rows + TT - 1) / TT;
+    if (gx > 0x7fffffffLL || gy > 65535) fail(-1, "transpose too large");
+    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, s, src, lds, rows, cols, dst, ldd);
+    LAUNCHCHK();
+}
 
 long long sa_lp(int v) { return ((long long)v * (v + 1) / 2 + 7) / 8 * 8; }
 long long sa_lm(int v) { return ((long long)v * (v - 1) / 2 + 7) / 8 * 8; }

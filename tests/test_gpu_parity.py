@@ -219,3 +219,22 @@ def test_exact_1p_block_preconditioner_adc2():
     r3, p3, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 1e-4, 1e-3, 1e-8)
     assert st == 0 and np.abs(r0 - r3).max() < 1e-9
     assert [x["nvir_kept"] for x in p0] == [x["nvir_kept"] for x in p3]
+
+
+# Stored-ladder row tiles: at >= 48 rows (n_vec * o) the FP64 ladder runs on the kernel that takes
+# the packed rows k-major and copies both tiles into LDS by buffer loads (rows past a K chunk read
+# as zero).  Cases: one row tile with ragged rows (42, 72, 33 rows), two row tiles (160 rows),
+# ragged column tiles (pair counts 861/820, 3240/3160, 2080/2016 padded to multiples of 8), and
+# K split into 1, 3 or 8 chunks or the tuned count.
+@pytest.mark.parametrize("o,v,X,nvec", [(6, 41, 60, 7), (10, 41, 60, 16), (3, 64, 90, 11), (8, 80, 120, 9)],
+                         ids=lambda c: str(c))
+@pytest.mark.parametrize("chunks", ["", "1", "3", "8"])
+def test_sigma_stored_ladder_row_tiles(o, v, X, nvec, chunks, monkeypatch):
+    monkeypatch.setenv("ADC3_LADDER_CHUNKS", chunks)
+    eo, ev, B = synth.make_instance(o, v, X, 7, scale=0.3)
+    P = Problem(eo, ev, B)
+    ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, nroots=0)
+    r = np.random.default_rng(3).standard_normal((nvec, P.dim()))
+    s_gpu = host(ctx.sigma(dev(r)))
+    ctx.close()
+    assert relerr(s_gpu, P.sigma(r, 3)) < 1e-11
