@@ -62,12 +62,12 @@ def parse():
 # for a copy of known size.  Keyed by a hash of the kernel's source and of the pair-block packing
 # that sets its launch shapes: a change to either reports null until it is measured again.
 LADDER_TRAFFIC = {
-    "b62b37e04e5fd89e": {
-        "bytes_per_launch": 3.413e9, "read_bytes": 3.285e9, "written_bytes": 0.128e9,
+    "18cee04ac33dc018": {
+        "bytes_per_launch": 3.434e9, "read_bytes": 3.306e9, "written_bytes": 0.129e9,
         "fetch_scale": 2.0, "write_scale": 1.0,
-        "measured_on": "sigma ladder o=20 v=200 X=128, 5 vectors (M=100), 8 K-chunks; mean of the "
-                       "pair-symmetric (3.450 GB) and pair-antisymmetric (3.376 GB) block launches",
-        "profile": "profiles/ladder_f64_o20v200x128_sigma_counters.md"},
+        "measured_on": "sigma ladder o=20 v=200 X=128, 5 vectors (M=100, ladder_f64t_kernel), 8 K-chunks; mean of "
+                       "the pair-symmetric (3.478 GB) and pair-antisymmetric (3.391 GB) block launches",
+        "profile": "profiles/ladder_f64t_o20v200x128_sigma_counters.md"},
 }
 
 
@@ -586,7 +586,8 @@ def main():
                    "nvir_kept": [r["nvir_kept"] for r in reps], "naux_kept": [r["naux_kept"] for r in reps]},
         "roots": [float(x) for x in roots],
         "status": st,
-        "roofline": {"kernel": "sigma ladder (ladder_f64_kernel)", "bound": "mfma",
+        "roofline": {"kernel": "sigma ladder (ladder_f64t_kernel; ladder_f64_kernel for row tiles of <= 32 rows)",
+                     "bound": "mfma",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_TFLOPS,
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
