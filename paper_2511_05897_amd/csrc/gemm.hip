@@ -249,6 +249,12 @@ static void gemm_impl(const Gemm& g, hipStream_t s, int tag, int kmin_split) {
     // K <= 0 is valid: the kernel then writes C = beta*C.
     if (nb > 65535) fail(-1, "gemm: too many batches");
     const int sh = pick_shape(g, tag);
+    // large single GEMMs with A k-major and B, C row-major: the ladder kernel that copies both tiles
+    // straight into LDS, when K fits one of its chunks
+    if (sh == SH_128x128 && nb == 1 && g.sAm == 1 && g.sBn == 1 && g.sCn == 1 &&
+        ladder_t_supported(g.M, g.N, g.K, g.A, g.sAk, g.B, g.sBk) && ladder_t_min_chunks(g.K, g.sAk, g.sBk) == 1 &&
+        ladder_gemm_t(g.M, g.N, g.K, g.alpha, g.A, g.sAk, g.B, g.sBk, g.beta, g.C, g.sCm, 1, nullptr, 0, s, 2))
+        return;
     // large single GEMMs with both operands contiguous along their tile rows: the ladder kernel's
     // tile (whole-M row blocks, 2 workgroups per CU, 16-byte loads) without splitting K
     if (sh == SH_128x128 && nb == 1 && g.sAk == 1 && g.sBn == 1 && g.sCn == 1 &&

@@ -99,7 +99,7 @@ int ladder_t_min_chunks(int K, long long ldz, long long ldg);
 bool ladder_t_supported(int M, int N, int K, const double* Zt, long long ldz, const double* G, long long ldg);
 bool ladder_gemm_t(int M, int N, int K, double alpha, const double* Zt, long long ldz, const double* G, long long ldg,
                    double beta, double* C, long long ldc, int nchunk, double* partial, long long partial_elems,
-                   hipStream_t s, int tag = 0);  // tag: 0 sigma ladder, 1 tuner trial
+                   hipStream_t s, int tag = 0);  // tag: 0 sigma ladder, 1 tuner trial, 2 other GEMM
 bool ladder_lp_supported(int prec, int M, int N, int K, const void* Z, long long ldz, const void* G, long long ldg,
                          const double* C, long long ldc);
 void ladder_gemm_lp(int prec, int M, int N, int K, double alpha, const void* Z, long long ldz, const void* G,

@@ -693,6 +693,7 @@ bool ladder_gemm_t(int M, int N, int K, double alpha, const double* Zt, long lon
     a.ntn = (N + LBN - 1) / LBN;
     a.alpha = alpha; a.beta = beta;
     if (tag == 1) launch_t_tag<1>(a, tm, mtiles, s);
+    else if (tag == 2) launch_t_tag<2>(a, tm, mtiles, s);
     else launch_t_tag<0>(a, tm, mtiles, s);
     LAUNCHCHK();
     if (a.nchunk > 1) splitk_reduce(partial, a.nchunk, M, N, alpha, beta, C, ldc, 1, s);

@@ -88,11 +88,29 @@ void ein2(Arena& ws, const char* spec, double alpha, const double* A, const int*
     g.M = (int)M; g.N = (int)N; g.K = (int)K;
     g.alpha = alpha;
     if (M > 2147483647LL || N > 2147483647LL || K > 2147483647LL) fail(-1, "ein2: dimension too large");
-    // A large contraction gets row-major operands and output (a permute of each is cheap next to
-    // the GEMM), so that it runs on the row-contiguous fast tile
+    // A large contraction gets row-major B and output and a contiguous A (a permute of each is cheap
+    // next to the GEMM), so that it runs on the ladder tiles: A k-major ([K..,M..], both tiles copied
+    // straight into LDS) when the whole product is one chunk of that kernel, else row-major
     const bool big = 2.0 * (double)M * (double)N * (double)K >= 4e9;
+    const bool kmajor = big && M >= 128 && N >= 128 && ((M + 127) / 128) * ((N + 127) / 128) >= 512 && N % 2 == 0 &&
+                        ladder_t_min_chunks((int)K, M + (M & 1), N) == 1 &&
+                        (p.b != Kl + Nl || ((uintptr_t)B & 15) == 0);
     // A
-    if (p.a == Ml + Kl) { g.A = A; g.sAm = K; g.sAk = 1; }
+    if (kmajor) {
+        if (p.a == Kl + Ml && M % 2 == 0) { g.A = A; g.sAm = 1; g.sAk = M; }
+        else {
+            const long long ldm = M + (M & 1);  // even, for 16-byte rows
+            double* t = ws.take<double>(K * ldm);
+            if (ldm == M) {
+                permute_any(t, A, p.a, adims, Kl + Ml, 1.0, 0.0, s);
+            } else {
+                double* u = ws.take<double>(K * M);
+                permute_any(u, A, p.a, adims, Kl + Ml, 1.0, 0.0, s);
+                k_copy2d(t, ldm, u, M, K, M, 1.0, 0.0, s);
+            }
+            g.A = t; g.sAm = 1; g.sAk = ldm;
+        }
+    } else if (p.a == Ml + Kl) { g.A = A; g.sAm = K; g.sAk = 1; }
     else if (p.a == Kl + Ml && !big) { g.A = A; g.sAm = 1; g.sAk = M; }
     else {
         double* t = ws.take<double>(M * K);

@@ -238,3 +238,19 @@ def test_sigma_stored_ladder_row_tiles(o, v, X, nvec, chunks, monkeypatch):
     s_gpu = host(ctx.sigma(dev(r)))
     ctx.close()
     assert relerr(s_gpu, P.sigma(r, 3)) < 1e-11
+
+
+# Contractions of >= 4 GFLOP in the setup run on the ladder tiles: with A k-major (copied into LDS by
+# buffer loads) when the product has >= 512 tiles of 128 x 128, an even column count and fits one chunk
+# (o=10 v=120: the o^2 v^4 coupling terms are 1200 x 14400 x 1200 products), else with A row-major
+# (o=9 v=121: odd column counts).
+@pytest.mark.parametrize("o,v,X", [(10, 120, 150), (9, 121, 140)], ids=lambda c: str(c))
+def test_intermediates_large_contractions(o, v, X):
+    eo, ev, B = synth.make_instance(o, v, X, 5, scale=0.3)
+    P = Problem(eo, ev, B)
+    ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, nroots=0)
+    Uz = host(ctx.intermediate(1)).reshape(v, o, v, v)
+    M11 = host(ctx.intermediate(0)).reshape(v, v)
+    ctx.close()
+    assert relerr(Uz, P.coupling_z(3)) < 1e-11
+    assert relerr(M11, P.m11(3)) < 1e-11
