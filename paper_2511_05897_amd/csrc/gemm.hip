@@ -267,7 +267,9 @@ static void gemm_impl(const Gemm& g, hipStream_t s, int tag, int kmin_split) {
     // few output tiles and a long K: cut K into chunks (one batch each), then sum the
     // partial tiles in a fixed order (deterministic)
     if (nb == 1 && tiles < 256 && g.K >= kmin_split && g_gemm_scratch) {
-        long long nchunk = std::min<long long>((g.K + 255) / 256, (2048 + tiles - 1) / tiles);
+        // about 512 workgroups (2 per CU): at o=20 v=200 the 1p coupling product (one tile, K = o v^2)
+        // takes 291 + 8 us (GEMM + reduction) with 512 chunks, 306 + 21 us with 2048, 385 + 6 us with 256
+        long long nchunk = std::min<long long>((g.K + 255) / 256, (512 + tiles - 1) / tiles);
         nchunk = std::min<long long>(nchunk, g_gemm_scratch_n / std::max<long long>(MN, 1));
         nchunk = std::min<long long>(nchunk, 65535);
         if (nchunk >= 2) {

@@ -76,24 +76,45 @@ __global__ __launch_bounds__(SNT) void jacobi_small_kernel(double* Ag, int n, do
                 pp[tid] = p; qq[tid] = q; cs[tid] = c; sn[tid] = s;
             }
             __syncthreads();
-            for (int t = tid; t < npair * n; t += SNT) {
-                int k = t / n, j = t % n;
-                int p = pp[k], q = qq[k];
-                if (q >= n) continue;
-                double c = cs[k], s = sn[k];
-                double apj = A[p * ld + j], aqj = A[q * ld + j];
-                A[p * ld + j] = c * apj - s * aqj;
-                A[q * ld + j] = s * apj + c * aqj;
+            // The round's rotations act on disjoint index pairs, so each 2x2 block (row pair k1, column
+            // pair k2) of A is updated in place by one thread: rows rotated first, then columns, the same
+            // arithmetic as a full row pass followed by a full column pass.  A pair whose q is past n
+            // (odd n) is the single index p with the identity rotation.  V's columns are rotated alongside.
+            for (int t = tid; t < npair * npair; t += SNT) {
+                const int k1 = t / npair, k2 = t - (t / npair) * npair;
+                const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+                const bool h1 = q1 < n, h2 = q2 < n;
+                const double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
+                const double x00 = A[p1 * ld + p2];
+                const double x01 = h2 ? A[p1 * ld + q2] : 0.0;
+                const double x10 = h1 ? A[q1 * ld + p2] : 0.0;
+                const double x11 = h1 && h2 ? A[q1 * ld + q2] : 0.0;
+                // rows
+                double y00 = x00, y01 = x01, y10 = x10, y11 = x11;
+                if (h1) {
+                    y00 = c1 * x00 - s1 * x10;
+                    y10 = s1 * x00 + c1 * x10;
+                    y01 = c1 * x01 - s1 * x11;
+                    y11 = s1 * x01 + c1 * x11;
+                }
+                // columns
+                if (h2) {
+                    A[p1 * ld + p2] = c2 * y00 - s2 * y01;
+                    A[p1 * ld + q2] = s2 * y00 + c2 * y01;
+                    if (h1) {
+                        A[q1 * ld + p2] = c2 * y10 - s2 * y11;
+                        A[q1 * ld + q2] = s2 * y10 + c2 * y11;
+                    }
+                } else {
+                    A[p1 * ld + p2] = y00;
+                    if (h1) A[q1 * ld + p2] = y10;
+                }
             }
-            __syncthreads();
             for (int t = tid; t < npair * n; t += SNT) {
                 int k = t / n, i = t % n;
                 int p = pp[k], q = qq[k];
                 if (q >= n) continue;
                 double c = cs[k], s = sn[k];
-                double aip = A[i * ld + p], aiq = A[i * ld + q];
-                A[i * ld + p] = c * aip - s * aiq;
-                A[i * ld + q] = s * aip + c * aiq;
                 double vip = V[i * ld + p], viq = V[i * ld + q];
                 V[i * ld + p] = c * vip - s * viq;
                 V[i * ld + q] = s * vip + c * viq;
