@@ -546,14 +546,17 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                 // FP64 with >= 48 rows: the packed rows k-major, for the kernel that copies both tiles
                 // straight into LDS (below that the G stream bounds the product and the row-major kernel,
                 // with more workgroups per CU, streams it faster)
-                const long long ldt = (M + 1) / 2 * 2;
-                double* Wt = prec == 0 ? take(ws, ldt * (lp + lm)) : nullptr;
+                // (FP32: the same, converted to FP32, rows padded to a multiple of 4)
+                const long long ldt = prec == 1 ? (M + 3) / 4 * 4 : (M + 1) / 2 * 2;
+                double* Wt = prec <= 1 ? take(ws, ldt * (lp + lm)) : nullptr;
+                float* Wt32 = prec == 1 ? (float*)take(ws, (ldt * (lp + lm) + 1) / 2) : nullptr;
                 int ltm, lmt;
                 ladder_rows(M, ltm, lmt);
-                const bool kmajor = prec == 0 && ltm >= 3;
+                const bool kmajor = prec <= 1 && ltm >= 3;
                 if (kmajor) {
                     k_transpose(W, lp, M, lp, Wt, ldt, s);
                     k_transpose(W + (long long)M * lp, lm, M, lm, Wt + ldt * lp, ldt, s);
+                    if (prec == 1) k_to_lowp(Wt32, Wt, ldt * (lp + lm), 1, s);
                 }
                 const int eb = prec == 0 ? 8 : prec == 1 ? 4 : 2;
                 const double pk = prec == 0 ? PEAK_FP64_MFMA : prec == 1 ? PEAK_FP32_MFMA : PEAK_BF16_MFMA;
@@ -569,7 +572,13 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                     if (prec > 0) {
                         const void* Z = (const char*)c->zlo + woff * eb;
                         const void* Gl = blk == 0 ? c->Glo : c->Gmlo;
-                        if (ladder_lp_supported(prec, M, (int)n, (int)n, Z, n, Gl, n, C, n)) {
+                        const float* Zt32 = kmajor && prec == 1 ? Wt32 + (blk == 0 ? 0 : ldt * lp) : nullptr;
+                        if (Zt32 && ladder_t32_supported(M, (int)n, (int)n, Zt32, ldt, (const float*)Gl, n) &&
+                            ladder_gemm_t32(M, (int)n, (int)n, 1.0, Zt32, ldt, (const float*)Gl, n, 0.0, C, n,
+                                            ladder_tuned_chunks(4, M, (int)n, (int)n, Zt32, ldt, Gl, n, C, n, c->xb, pe, s),
+                                            c->xb, pe, s)) {
+                            // done on the k-major FP32 kernel
+                        } else if (ladder_lp_supported(prec, M, (int)n, (int)n, Z, n, Gl, n, C, n)) {
                             const int nch = ladder_tuned_chunks(prec, M, (int)n, (int)n, Z, n, Gl, n, C, n, c->xb, pe, s);
                             ladder_gemm_lp(prec, M, (int)n, (int)n, 1.0, Z, n, Gl, n, 0.0, C, n, nch, c->xb, pe, s);
                         } else {

@@ -100,12 +100,18 @@ bool ladder_t_supported(int M, int N, int K, const double* Zt, long long ldz, co
 bool ladder_gemm_t(int M, int N, int K, double alpha, const double* Zt, long long ldz, const double* G, long long ldg,
                    double beta, double* C, long long ldc, int nchunk, double* partial, long long partial_elems,
                    hipStream_t s, int tag = 0);  // tag: 0 sigma ladder, 1 tuner trial, 2 other GEMM
+// FP32 operands (FP32 accumulation, FP64 partial sums / output), Z k-major, ldz and ldg multiples of 4
+int ladder_t32_min_chunks(int K, long long ldz, long long ldg);
+bool ladder_t32_supported(int M, int N, int K, const float* Zt, long long ldz, const float* G, long long ldg);
+bool ladder_gemm_t32(int M, int N, int K, double alpha, const float* Zt, long long ldz, const float* G, long long ldg,
+                     double beta, double* C, long long ldc, int nchunk, double* partial, long long partial_elems,
+                     hipStream_t s, int tag = 0);
 bool ladder_lp_supported(int prec, int M, int N, int K, const void* Z, long long ldz, const void* G, long long ldg,
                          const double* C, long long ldc);
 void ladder_gemm_lp(int prec, int M, int N, int K, double alpha, const void* Z, long long ldz, const void* G,
                     long long ldg, double beta, double* C, long long ldc, int nchunk, double* partial,
                     long long partial_elems, hipStream_t s, bool trial = false);
-// chunk count for a ladder shape (prec 0 FP64, 1 FP32, 2 BF16, 3 FP64 with Z k-major), measured on first use
+// chunk count for a ladder shape (prec 0 FP64, 1 FP32, 2 BF16, 3 FP64 / 4 FP32 with Z k-major), measured on first use
 int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long ldz, const void* G, long long ldg,
                         double* C, long long ldc, double* partial, long long partial_elems, hipStream_t s);
 // ladder from the DF factor (dfladder.hip): C[m] (+)= sum_Q B^Q Z[m] B^Q for m < M, with Bvv [X][v][v]

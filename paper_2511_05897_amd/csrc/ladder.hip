@@ -423,6 +423,84 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f32_kernel(LadderLP g) {
     store_f32_tile<TM>(g, acc, m0, n0, cb, chunk, lr, lk);
 }
 
+// FP32 with Z k-major, both tiles copied HBM -> LDS by buffer loads as in ladder_f64t_kernel.  A
+// tile row of 128 floats is 512 bytes, so each copy instruction moves one row on half the lanes,
+// which lets every LDS row keep its padding.  32-deep slabs, two LDS buffers (separate arrays).
+constexpr int FTK = 32;
+template <int TM, int TAG>
+__global__ __launch_bounds__(LNT, 2) void ladder_f32t_kernel(LadderLP g) {
+    constexpr int BM = 16 * TM, RA = BM + 4, RB = LBN + 4;  // LDS row strides (floats)
+    __shared__ __attribute__((aligned(16))) float As0[FTK][RA], As1[FTK][RA];
+    __shared__ __attribute__((aligned(16))) float Bs0[FTK][RB], Bs1[FTK][RB];
+    const float* __restrict__ Z = (const float*)g.Z;
+    const float* __restrict__ G = (const float*)g.G;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    int chunk, nt;
+    block_tile(g.nchunk, g.ntn, chunk, nt);
+    const long long m0 = (long long)blockIdx.y * BM, n0 = (long long)nt * LBN;
+    const int kb = chunk * g.Kc, ke = min(g.K, kb + g.Kc);
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(Z + (long long)kb * g.ldz + m0), (short)0, (int)((long long)(ke - kb) * g.ldz * 4 - m0 * 4), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(G + (long long)kb * g.ldg + n0), (short)0, (int)((long long)(ke - kb) * g.ldg * 4 - n0 * 4), 0x00020000);
+    // wave w copies rows 8w .. 8w+7 of both tiles; lane l < 32 the four elements at column 4l
+    const bool bcol = lane < 32, acol = 4 * lane < BM;
+    unsigned voa[8], vob[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        voa[r] = (unsigned)(((8 * wave + r) * g.ldz + 4 * lane) * 4);
+        vob[r] = (unsigned)(((8 * wave + r) * g.ldg + 4 * lane) * 4);
+    }
+    auto issue = [&](float(&At)[FTK][RA], float(&Bt)[FTK][RB], int s) {
+        const int soa = s * FTK * (int)g.ldz * 4, sob = s * FTK * (int)g.ldg * 4;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            if (acol) __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr)&At[8 * wave + r][0], 16, voa[r], soa, 0, 0);
+            if (bcol) __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr)&Bt[8 * wave + r][0], 16, vob[r], sob, 0, 0);
+        }
+    };
+    f4v acc[TM][LTN];
+    const f4v z4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < LTN; ++j) acc[i][j] = z4;
+    const int cb = wave * (16 * LTN);
+    auto compute = [&](const float(&At)[FTK][RA], const float(&Bt)[FTK][RB]) {
+#pragma unroll
+        for (int kk = 0; kk < FTK; kk += 4) {
+            float bf[LTN];
+#pragma unroll
+            for (int j = 0; j < LTN; ++j) bf[j] = Bt[kk + lk][cb + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const float af = At[kk + lk][16 * i + lr];
+#pragma unroll
+                for (int j = 0; j < LTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    };
+    auto sync = [] {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    };
+    const int nslab = (ke - kb + FTK - 1) / FTK;
+    issue(As0, Bs0, 0);
+    sync();
+    int s = 0;
+    for (; s + 1 < nslab; s += 2) {
+        issue(As1, Bs1, s + 1);
+        compute(As0, Bs0);
+        sync();
+        if (s + 2 < nslab) issue(As0, Bs0, s + 2);
+        compute(As1, Bs1);
+        sync();
+    }
+    if (s < nslab) compute(As0, Bs0);
+    store_f32_tile<TM>(g, acc, m0, n0, cb, chunk, lr, lk);
+}
+
 constexpr int HBK = 64, HPAD = 8;
 template <int TM, int TAG>
 __global__ __launch_bounds__(LNT, 2) void ladder_bf16_kernel(LadderLP g) {
@@ -523,6 +601,25 @@ void launch_lp_tag(const LadderLP& a, int prec, int tm, int mtiles, hipStream_t 
         case 6: launch_lp_tm<6, TAG>(a, prec, mtiles, s); break;
         case 7: launch_lp_tm<7, TAG>(a, prec, mtiles, s); break;
         default: launch_lp_tm<8, TAG>(a, prec, mtiles, s); break;
+    }
+}
+
+template <int TM, int TAG>
+void launch_f32t_tm(const LadderLP& a, int mtiles, hipStream_t s) {
+    hipLaunchKernelGGL((ladder_f32t_kernel<TM, TAG>), dim3(a.nchunk * a.ntn, mtiles), dim3(LNT), 0, s, a);
+}
+
+template <int TAG>
+void launch_f32t_tag(const LadderLP& a, int tm, int mtiles, hipStream_t s) {
+    switch (tm) {
+        case 1: launch_f32t_tm<1, TAG>(a, mtiles, s); break;
+        case 2: launch_f32t_tm<2, TAG>(a, mtiles, s); break;
+        case 3: launch_f32t_tm<3, TAG>(a, mtiles, s); break;
+        case 4: launch_f32t_tm<4, TAG>(a, mtiles, s); break;
+        case 5: launch_f32t_tm<5, TAG>(a, mtiles, s); break;
+        case 6: launch_f32t_tm<6, TAG>(a, mtiles, s); break;
+        case 7: launch_f32t_tm<7, TAG>(a, mtiles, s); break;
+        default: launch_f32t_tm<8, TAG>(a, mtiles, s); break;
     }
 }
 
@@ -700,6 +797,47 @@ bool ladder_gemm_t(int M, int N, int K, double alpha, const double* Zt, long lon
     return true;
 }
 
+int ladder_t32_min_chunks(int K, long long ldz, long long ldg) {
+    const long long ld = std::max(ldz, ldg);
+    if (K <= 0 || ld <= 0) return 0;
+    const long long kcmax = ((1LL << 31) - 1) / (4 * ld) / 64 * 64;
+    if (kcmax < 64) return 0;
+    int n = (int)std::max<long long>(1, (K + kcmax - 1) / kcmax);
+    while (ladder_chunk_len(K, n) > kcmax) ++n;
+    return n;
+}
+
+bool ladder_t32_supported(int M, int N, int K, const float* Zt, long long ldz, const float* G, long long ldg) {
+    auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    return M > 0 && N > 0 && K > 0 && ldz >= M && ldg >= N && ldz % 4 == 0 && ldg % 4 == 0 && al16(Zt) && al16(G) &&
+           ladder_t32_min_chunks(K, ldz, ldg) > 0;
+}
+
+bool ladder_gemm_t32(int M, int N, int K, double alpha, const float* Zt, long long ldz, const float* G, long long ldg,
+                     double beta, double* C, long long ldc, int nchunk, double* partial, long long partial_elems,
+                     hipStream_t s, int tag) {
+    if (M <= 0 || N <= 0) return true;
+    const int nmin = ladder_t32_min_chunks(K, ldz, ldg);
+    if (nmin <= 0) return false;
+    nchunk = std::max(nmin, std::min(nchunk, (K + 255) / 256));
+    if (nchunk > 1 && (!partial || (long long)nchunk * M * N > partial_elems)) return false;
+    if (g_dry) return true;
+    int tm, mtiles;
+    ladder_rows(M, tm, mtiles);
+    LadderLP a;
+    a.Z = Zt; a.ldz = ldz; a.G = G; a.ldg = ldg; a.C = C; a.ldc = ldc; a.P = partial;
+    a.M = M; a.N = N; a.K = K;
+    a.Kc = ladder_chunk_len(K, nchunk);
+    a.nchunk = (K + a.Kc - 1) / a.Kc;
+    a.ntn = (N + LBN - 1) / LBN;
+    a.alpha = alpha; a.beta = beta;
+    if (tag == 1) launch_f32t_tag<1>(a, tm, mtiles, s);
+    else launch_f32t_tag<0>(a, tm, mtiles, s);
+    LAUNCHCHK();
+    if (a.nchunk > 1) splitk_reduce(partial, a.nchunk, M, N, alpha, beta, C, ldc, 1, s);
+    return true;
+}
+
 namespace {
 std::mutex g_tune_mu;
 std::map<std::string, int> g_tune;
@@ -717,7 +855,7 @@ std::string arch_name() {
 std::string tune_key(int prec, int M, int N, int K) {
     int tm, mt;
     ladder_rows(M, tm, mt);
-    return std::string(prec == 0 ? "ladder_f64 " : prec == 1 ? "ladder_f32 " : prec == 2 ? "ladder_bf16 " : "ladder_f64t ") + arch_name() + " " + std::to_string(tm) + " " + std::to_string(mt) + " " +
+    return std::string(prec == 0 ? "ladder_f64 " : prec == 1 ? "ladder_f32 " : prec == 2 ? "ladder_bf16 " : prec == 3 ? "ladder_f64t " : "ladder_f32t ") + arch_name() + " " + std::to_string(tm) + " " + std::to_string(mt) + " " +
            std::to_string(N) + " " + std::to_string(K);
 }
 
@@ -756,6 +894,8 @@ static void ladder_run(int prec, int M, int N, int K, const void* Z, long long l
                     1);
     else if (prec == 3)
         ladder_gemm_t(M, N, K, 1.0, (const double*)Z, ldz, (const double*)G, ldg, 0.0, C, ldc, nchunk, partial, pe, s, 1);
+    else if (prec == 4)
+        ladder_gemm_t32(M, N, K, 1.0, (const float*)Z, ldz, (const float*)G, ldg, 0.0, C, ldc, nchunk, partial, pe, s, 1);
     else
         ladder_gemm_lp(prec, M, N, K, 1.0, Z, ldz, G, ldg, 0.0, C, ldc, nchunk, partial, pe, s, true);
 }
@@ -764,7 +904,7 @@ int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long 
                         double* C, long long ldc, double* partial, long long partial_elems, hipStream_t s) {
     const char* fixed = std::getenv("ADC3_LADDER_CHUNKS");
     if (fixed && *fixed) return std::max(1, std::atoi(fixed));
-    const int def = std::max(8, prec == 3 ? ladder_t_min_chunks(K, ldz, ldg) : 1);
+    const int def = std::max(8, prec == 3 ? ladder_t_min_chunks(K, ldz, ldg) : prec == 4 ? ladder_t32_min_chunks(K, ldz, ldg) : 1);
     if (g_dry) return def;
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return def;
@@ -776,7 +916,7 @@ int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long 
         if (it != g_tune.end()) return it->second;
     }
     // prec 3 is the FP64 kernel with Z k-major, whose chunks have a minimum count
-    const int nmin = prec == 3 ? ladder_t_min_chunks(K, ldz, ldg) : 1;
+    const int nmin = prec == 3 ? ladder_t_min_chunks(K, ldz, ldg) : prec == 4 ? ladder_t32_min_chunks(K, ldz, ldg) : 1;
     std::vector<int> cand;
     for (int c : {1, 2, 4, 8, 16}) {
         if (c < nmin) continue;

@@ -73,3 +73,21 @@ def test_mixed_solve_weak_correlation_full_size(prec):
     assert err.max() < 1e-6
     assert [r["nvir_kept"] for r in reps] == gold["nvir_kept"]
     assert [r["naux_kept"] for r in reps] == gold["naux_kept"]
+
+
+# FP32 ladder at >= 48 rows (n_vec * o): the kernel with the packed rows k-major in FP32, both tiles
+# copied into LDS by buffer loads.  One and two row tiles, ragged column tiles, 1, 3 or tuned K chunks;
+# the FP32 sigma error against the FP64 oracle stays at the FP32 level of the small case above.
+@pytest.mark.parametrize("o,v,X,nvec", [(6, 41, 60, 7), (10, 41, 60, 16), (8, 80, 120, 9)], ids=lambda c: str(c))
+@pytest.mark.parametrize("chunks", ["", "1", "3"])
+def test_fp32_sigma_stored_ladder_row_tiles(o, v, X, nvec, chunks, monkeypatch):
+    monkeypatch.setenv("ADC3_LADDER_CHUNKS", chunks)
+    eo, ev, B = synth.make_instance(o, v, X, 7, scale=0.3)
+    P = Problem(eo, ev, B)
+    ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, nroots=0, precision=1)
+    r = np.random.default_rng(3).standard_normal((nvec, P.dim()))
+    ref = P.sigma(r, 3)
+    slo = host(ctx.sigma(dev(r), precision=1))
+    ctx.close()
+    err = np.abs(slo - ref).max() / np.abs(ref).max()
+    assert 0 < err < 2e-5, err
