@@ -391,7 +391,7 @@ def cpu_baseline(shape, nvec):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
