@@ -369,10 +369,25 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
                 double* CW = take(ws, np * (lp + lm));
                 k_pairs_gather(Tp, T, o, v, s);
                 k_sa_pack(Tp, vv, (int)np, v, W, W + np * lp, s);
-                gemm_rm((int)np, (int)lp, (int)lp, 1.0, W, lp, false, c->G, lp, false, 0.0, CW, lp, s);
-                if (lm > 0)
-                    gemm_rm((int)np, (int)lm, (int)lm, 1.0, W + np * lp, lm, false, c->Gm, lm, false, 0.0, CW + np * lp,
-                            lm, s);
+                // the packed rows k-major for the ladder kernel that copies both tiles into LDS (K split
+                // into 8 chunks, partial sums here), else the GEMM
+                const long long ldt = (np + 1) / 2 * 2;
+                double* Wt = take(ws, ldt * (lp + lm));
+                double* part = take(ws, 8 * np * lp);
+                k_transpose(W, lp, (int)np, lp, Wt, ldt, s);
+                if (lm > 0) k_transpose(W + np * lp, lm, (int)np, lm, Wt + ldt * lp, ldt, s);
+                for (int blk = 0; blk < 2; ++blk) {
+                    const long long n = blk == 0 ? lp : lm;
+                    if (n == 0) continue;
+                    const double* Gb = blk == 0 ? c->G : c->Gm;
+                    const double* Zt = Wt + (blk == 0 ? 0 : ldt * lp);
+                    double* C = CW + (blk == 0 ? 0 : np * lp);
+                    if (!(ladder_t_supported((int)np, (int)n, (int)n, Zt, ldt, Gb, n) &&
+                          ladder_gemm_t((int)np, (int)n, (int)n, 1.0, Zt, ldt, Gb, n, 0.0, C, n, 8, part, 8 * np * lp, s,
+                                        2)))
+                        gemm_rm((int)np, (int)n, (int)n, 1.0, W + (blk == 0 ? 0 : np * lp), n, false, Gb, n, false, 0.0,
+                                C, n, s);
+                }
                 k_sa_unpack(CW, CW + np * lp, (int)np, v, Lp, vv, s);
                 k_pairs_scatter(L, Lp, o, v, s);
             }
