@@ -239,17 +239,26 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f64t_kernel(LadderArgs g) {
 #pragma unroll
         for (int j = 0; j < LTN; ++j) acc[i][j] = d4v{0.0, 0.0, 0.0, 0.0};
     const int cb = wave * (16 * LTN);
+    // Rows and columns are dealt to the MFMA blocks in interleaved pairs, so that one 16-byte LDS read
+    // fetches the fragments of two blocks: row block 2h+e holds rows 32h + 2t + e, column block j holds
+    // columns cb + 2t + j (t the fragment index, e and j 0 or 1); an odd TM reads its last row block
+    // (rows 16(TM-1) + t) singly.  The epilogue maps the blocks back.
     auto compute = [&](const double(&At)[LBK][RA], const double(&Bt)[LBK][RB]) {
 #pragma unroll
         for (int kk = 0; kk < LBK; kk += 4) {
-            double bf[LTN];
+            const d2v bq = *(const d2v*)&Bt[kk + lk][cb + 2 * lr];
 #pragma unroll
-            for (int j = 0; j < LTN; ++j) bf[j] = Bt[kk + lk][cb + 16 * j + lr];
-#pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                const double af = At[kk + lk][16 * i + lr];
-#pragma unroll
-                for (int j = 0; j < LTN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[j], acc[i][j], 0, 0, 0);
+            for (int h = 0; h < TM / 2; ++h) {
+                const d2v aq = *(const d2v*)&At[kk + lk][32 * h + 2 * lr];
+                acc[2 * h][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq.x, bq.x, acc[2 * h][0], 0, 0, 0);
+                acc[2 * h][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq.x, bq.y, acc[2 * h][1], 0, 0, 0);
+                acc[2 * h + 1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq.y, bq.x, acc[2 * h + 1][0], 0, 0, 0);
+                acc[2 * h + 1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(aq.y, bq.y, acc[2 * h + 1][1], 0, 0, 0);
+            }
+            if constexpr (TM & 1) {
+                const double af = At[kk + lk][16 * (TM - 1) + lr];
+                acc[TM - 1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bq.x, acc[TM - 1][0], 0, 0, 0);
+                acc[TM - 1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bq.y, acc[TM - 1][1], 0, 0, 0);
             }
         }
     };
@@ -277,8 +286,9 @@ __global__ __launch_bounds__(LNT, 2) void ladder_f64t_kernel(LadderArgs g) {
         for (int j = 0; j < LTN; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const long long row = m0 + 16 * i + lk + 4 * r;
-                const long long col = n0 + cb + 16 * j + lr;
+                const int t = lk + 4 * r;  // the block's output row
+                const long long row = m0 + ((TM & 1) && i == TM - 1 ? 16 * i + t : 32 * (i >> 1) + 2 * t + (i & 1));
+                const long long col = n0 + cb + 2 * lr + j;
                 if (row < g.M && col < g.N) {
                     if (g.nchunk > 1) {
                         g.P[((long long)chunk * g.M + row) * g.N + col] = acc[i][j][r];
