@@ -1,4 +1,4 @@
-// The sigma ladder as a dedicated FP64 matrix-core kernel.
+// The sigma ladder as dedicated matrix-core kernels (FP64, and FP32 / BF16 operands).
 //
 //   C[m][n] = alpha * sum_k Z[m][k] G[k][n] + beta * C[m][n]
 //
@@ -12,9 +12,12 @@
 //   * K is split into chunks (deterministic partial sums, reduced in a fixed order) to
 //     give >= 4 workgroups per CU slot; with a multiple of 8 chunks, the workgroups that
 //     one XCD runs together share one chunk of Z in that XCD's L2.
-// Operands are read with 16-byte loads (both are contiguous along their tile rows) and
-// staged through double-buffered LDS, the Z tile transposed to [k][m] so that the 16 lanes
-// of a fragment read 16 consecutive words.
+// Two FP64 forms: ladder_f64_kernel takes Z row-major and stages both tiles through
+// registers into double-buffered LDS (16-byte loads, the Z tile transposed to [k][m] on the
+// way, so that the 16 lanes of a fragment read 16 consecutive words); ladder_f64t_kernel
+// takes Z k-major ([k][m], as G is [k][n]) and copies both tiles straight from HBM into LDS
+// with buffer loads (its own comment below).  The sigma pass uses the second for row tiles
+// of 48 or more rows.
 //
 // MFMA f64 16x16x4 (lane l of a wave64): A frag A[l%16][l/16], B frag B[l/16][l%16],
 // accumulator element r holds D[l/16 + 4r][l%16].

@@ -13,7 +13,8 @@
 //
 // Pair order is row-major over the upper triangle (a, then b).  Each block's leading dimension is
 // padded to a multiple of 8 with zeros (16-byte loads in every precision of the ladder kernels).  This file
-// holds the packing of the input rows and the unpacking of the result; ladder_form.hip forms the blocks.
+// holds the packing of the input rows, their k-major transpose (for the ladder kernels that copy both
+// tiles straight into LDS) and the unpacking of the result; ladder_form.hip forms the blocks.
 #include "internal.h"
 #include <algorithm>
 
