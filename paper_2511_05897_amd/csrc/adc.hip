@@ -641,8 +641,16 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                 const long long pe = 2 * NVMAX * (long long)o * vv;
                 double* part = take(ws, pe);
                 double* Wq = take(ws, (long long)NVMAX * v * X);
-                const bool lad = ladder_supported(2 * Mph, ovi, ovi, Y2, ovi, c->P1, ovi, E, ovi);
-                const int nch = lad ? ladder_tuned_chunks(0, 2 * Mph, ovi, ovi, Y2, ovi, c->P1, ovi, E, ovi, part, pe, s) : 1;
+                // [Y2; Y3] k-major for the ladder kernel that copies both tiles into LDS, else the row-major tile
+                const long long ldy = 2LL * Mph;
+                double* Yt = take(ws, (long long)ovi * 2 * NVMAX * v);
+                const bool tk = ladder_t_supported(2 * Mph, ovi, ovi, Yt, ldy, c->P1, ovi) &&
+                                ladder_t_min_chunks(ovi, ldy, ovi) == 1;
+                if (tk) k_transpose(Y2, ovi, 2 * Mph, ovi, Yt, ldy, s);
+                const bool lad = !tk && ladder_supported(2 * Mph, ovi, ovi, Y2, ovi, c->P1, ovi, E, ovi);
+                const int nch = tk    ? ladder_tuned_chunks(3, 2 * Mph, ovi, ovi, Yt, ldy, c->P1, ovi, E, ovi, part, pe, s)
+                                : lad ? ladder_tuned_chunks(0, 2 * Mph, ovi, ovi, Y2, ovi, c->P1, ovi, E, ovi, part, pe, s)
+                                      : 1;
                 {
                     Gemm g;  // Wq[(n,a)][Q] = sum_(j,d) Y1[(n,a)][(j,d)] Bov[Q][(j,d)]
                     g.M = Mph; g.N = X; g.K = ovi;
@@ -652,8 +660,15 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                     gemm_split(g, s);
                 }
                 gemm_rm(Mph, ovi, X, 1.0, Wq, X, false, c->Bov, ovi, false, 0.0, D, ovi, s);
-                if (lad) ladder_gemm(2 * Mph, ovi, ovi, 1.0, Y2, ovi, c->P1, ovi, 0.0, E, ovi, nch, part, pe, s, 2);
-                else gemm_rm(2 * Mph, ovi, ovi, 1.0, Y2, ovi, false, c->P1, ovi, false, 0.0, E, ovi, s);
+                // (a fixed chunk count may not fit the partial buffer: clamped, as the row-major path does)
+                const int ncht = (int)std::max<long long>(1, std::min<long long>(nch, pe / (2LL * Mph * ovi)));
+                if (tk && ladder_gemm_t(2 * Mph, ovi, ovi, 1.0, Yt, ldy, c->P1, ovi, 0.0, E, ovi, ncht, part, pe, s, 2)) {
+                    // done on the k-major kernel
+                } else if (lad) {
+                    ladder_gemm(2 * Mph, ovi, ovi, 1.0, Y2, ovi, c->P1, ovi, 0.0, E, ovi, nch, part, pe, s, 2);
+                } else {
+                    gemm_rm(2 * Mph, ovi, ovi, 1.0, Y2, ovi, false, c->P1, ovi, false, 0.0, E, ovi, s);
+                }
                 k_ph_fin(c->sb, D, E, E + (long long)Mph * ovi, nv, o, v, s);
             }
             k_copy2d(ss + v, N, c->sb, ovv, nv, ovv, 1.0, 1.0, s);
