@@ -49,6 +49,17 @@ def d_to_z(s):
     return sym(s) + SQ3 * asym(s)
 
 
+def ladder_rows(Bvv, amp, a_idx):
+    """Selected rows of the ladder term: out[k, b] = sum_cd (ac|bd) amp[c, d] for a = a_idx[k], with
+    (ac|bd) = sum_Q B^Q_ac B^Q_bd (eq 25) and amp [v, v] one 2p1h block.  For spot checks at sizes
+    where whole rows of every vector are too dear: cost X v^2 per selected a."""
+    out = np.empty((len(a_idx), Bvv.shape[1]))
+    for k, a in enumerate(a_idx):
+        W = Bvv[:, a, :] @ amp                      # [Q, d] = sum_c B^Q_ac amp_cd
+        out[k] = np.einsum("Qd,Qbd->b", W, Bvv)     # sum_Q sum_d W[Q, d] B^Q_bd
+    return out
+
+
 class Problem:
     """Integrals and intermediates of one closed-shell instance."""
 

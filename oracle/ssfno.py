@@ -27,10 +27,19 @@ Readings where the paper is silent (each listed in the design notes):
   index m.  With nothing truncated m = k, so corrected root k is canonical ADC(3)
   root k.
 
-Parity unpinned: the D^EA reading, the root matching rule and the thresholds' effect
-at the literal input scale have no printed worked example to pin them; they are
-pinned only by their limits (trace of D^EA, the untruncated limit reproducing
-canonical ADC(3), natural-orbital and NAF identities) in the tests.
+Pins (no printed worked example exists, so each reading is pinned to a definition):
+* D^EA equals, element by element, the spin-averaged virtual one-particle density of
+  the (N+1)-electron determinant vector that the doublet coordinates describe on the
+  zeroth-order intermediate states, built with creation/annihilation operators in the
+  tier-0 determinant spaces; D^MP2 (and the oo and ov second-order densities) equal
+  the densities of the Rayleigh-Schroedinger ground state there.
+* Root matching follows a state through a truncation that reorders the spectrum: the
+  matched truncated ADC(2) root lies within 1e-3 Eh of the canonical one, for a
+  1p-dominated state (where the 1p-only overlap rule agrees) and for a 2p1h satellite
+  (where the 1p-only rule picks a different state).
+* The thresholds' effect at the literal input scale stays parity-unpinned: only the
+  untruncated limit (canonical ADC(3) reproduced) and the natural-orbital and NAF
+  identities pin it.
 """
 import numpy as np
 

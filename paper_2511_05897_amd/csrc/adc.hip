@@ -2,11 +2,13 @@
 //
 // Closed-shell, density-fitted (eq 25): integrals with at most two virtual indices
 // are formed once ((ia|jb), (ij|ab)); three-virtual integrals only enter the
-// one-time 1p/2p1h coupling build; the four-virtual integrals (ac|bd) are assembled
-// once per basis from the DF factor on the matrix cores and kept in HBM as the
-// ladder matrix G[(ab),(cd)] (v^4 doubles: 12.8 GB at v = 200, one of the design
-// choices HBM capacity allows), so every ladder application in the Davidson loop
-// is one GEMM.
+// one-time 1p/2p1h coupling build.  The ladder term sum_cd (ac|bd) z_cd takes one of
+// two forms: stored, where (ac|bd) is assembled once per basis from the DF factor on
+// the matrix cores and kept in HBM as its pair-symmetric and pair-antisymmetric
+// blocks G+ [(a<=b)][(c<=d)] and G- [(a<b)][(c<d)] (about v^4/2 doubles: 6.4 GB at
+// v = 200), so a ladder application is two products against G+ and G- between a pack
+// and an unpack of z; or assembled, sum_Q B^Q z B^Q from the factor in every
+// application, when the stored blocks would exceed 96 GB in FP64 (v > 393).
 //
 // Vector layout: r = [r1[v], z[o][v][v]], z orthonormal doublet coordinates;
 // x = z_S + z_A/sqrt(3) are the alpha-beta determinant coefficients and
@@ -63,21 +65,29 @@ static bool verbose() { return verbosity() >= 1; }
         }                                         \
     } while (0)
 
-// Small read-backs go through a pinned staging buffer (one per host thread, kept for the process):
-// the Davidson loop reads back a few numbers several times per iteration, and a copy into pageable
-// memory is staged by the runtime at a higher latency.
+// Small read-backs go through a pinned staging buffer (one per host thread, freed when the thread
+// ends): the Davidson loop reads back a few numbers several times per iteration, and a copy into
+// pageable memory is staged by the runtime at a higher latency.
+namespace {
+struct PinnedStage {
+    void* p = nullptr;
+    ~PinnedStage() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+}  // namespace
 static void d2h(void* dst, const void* src, size_t bytes, hipStream_t s) {
     if (g_dry) {
         std::memset(dst, 0, bytes);
         return;
     }
     constexpr size_t PIN = 1 << 20;
-    thread_local void* pin = nullptr;
+    thread_local PinnedStage pin;
     if (bytes <= PIN) {
-        if (!pin) HIPCHK(hipHostMalloc(&pin, PIN, hipHostMallocDefault));
-        HIPCHK(hipMemcpyAsync(pin, src, bytes, hipMemcpyDeviceToHost, s));
+        if (!pin.p) HIPCHK(hipHostMalloc(&pin.p, PIN, hipHostMallocDefault));
+        HIPCHK(hipMemcpyAsync(pin.p, src, bytes, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        std::memcpy(dst, pin, bytes);
+        std::memcpy(dst, pin.p, bytes);
         return;
     }
     HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
@@ -558,7 +568,7 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                 const long long pe = 3 * NVMAX * (long long)o * vv;
                 k_sa_pack(zb, vv, M, v, W, W + (long long)M * lp, s);
                 if (prec > 0) k_to_lowp(c->zlo, W, (long long)M * (lp + lm), prec, s);
-                // FP64 with >= 48 rows: the packed rows k-major, for the kernel that copies both tiles
+                // FP64 with >= 3 row blocks (33 rows and up): the packed rows k-major, for the kernel that copies both tiles
                 // straight into LDS (below that the G stream bounds the product and the row-major kernel,
                 // with more workgroups per CU, streams it faster)
                 // (FP32: the same, converted to FP32, rows padded to a multiple of 4)

@@ -3,7 +3,10 @@
 //   C[m][n] = alpha * sum_k Z[m][k] G[k][n] + beta * C[m][n]
 //
 // m runs over (vector, occupied) pairs (a few hundred at most), k and n over virtual
-// pairs (v^2 each), G[(cd)][(ab)] = (ac|bd) is the stored ladder matrix (symmetric).
+// pairs, and G is one of the stored ladder's two symmetric blocks:
+// G+[(cd)][(ab)] = ((ac|bd) + (ad|bc))/2 over c<=d, a<=b, or G-[(cd)][(ab)] =
+// ((ac|bd) - (ad|bc))/2 over c<d, a<b (each side padded to a multiple of 8).  The
+// same kernels serve the setup's large contractions (tag 2).
 // The kernel is shaped by three facts of this contraction on CDNA4:
 //   * all m rows fit one tile (TM blocks of 16 rows), so G streams from HBM exactly once;
 //   * FP64 MFMA is the bound (2 flops per G element per row, >= 20 rows), so the tile
@@ -17,7 +20,7 @@
 // way, so that the 16 lanes of a fragment read 16 consecutive words); ladder_f64t_kernel
 // takes Z k-major ([k][m], as G is [k][n]) and copies both tiles straight from HBM into LDS
 // with buffer loads (its own comment below).  The sigma pass uses the second for row tiles
-// of 48 or more rows.
+// of three or more 16-row blocks (33 rows and up).
 //
 // MFMA f64 16x16x4 (lane l of a wave64): A frag A[l%16][l/16], B frag B[l/16][l%16],
 // accumulator element r holds D[l/16 + 4r][l%16].
@@ -856,13 +859,21 @@ std::mutex g_tune_mu;
 std::map<std::string, int> g_tune;
 bool g_tune_loaded = false;
 
+// architecture name of the current device, looked up once per device (the key of tuned shapes)
 std::string arch_name() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+    static std::mutex mu;
+    static std::map<int, std::string> names;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = names.find(dev);
+    if (it != names.end()) return it->second;
     hipDeviceProp_t pr;
     if (hipGetDeviceProperties(&pr, dev) != hipSuccess) return "unknown";
     std::string a = pr.gcnArchName;
-    return a.substr(0, a.find(':'));
+    a = a.substr(0, a.find(':'));
+    names[dev] = a;
+    return a;
 }
 
 std::string tune_key(int prec, int M, int N, int K) {
@@ -919,8 +930,8 @@ int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long 
     if (fixed && *fixed) return std::max(1, std::atoi(fixed));
     const int def = std::max(8, prec == 3 ? ladder_t_min_chunks(K, ldz, ldg) : prec == 4 ? ladder_t32_min_chunks(K, ldz, ldg) : 1);
     if (g_dry) return def;
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return def;
+    // a count tuned earlier for this shape holds under graph capture too (the eager pass before a
+    // capture tunes it); only the trial launches themselves must stay out of a capture
     const std::string key = tune_key(prec, M, N, K);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -928,6 +939,8 @@ int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long 
         auto it = g_tune.find(key);
         if (it != g_tune.end()) return it->second;
     }
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return def;
     // prec 3 is the FP64 kernel with Z k-major, whose chunks have a minimum count
     const int nmin = prec == 3 ? ladder_t_min_chunks(K, ldz, ldg) : prec == 4 ? ladder_t32_min_chunks(K, ldz, ldg) : 1;
     std::vector<int> cand;

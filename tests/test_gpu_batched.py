@@ -23,8 +23,11 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def test_sigma_graph_replays_match_eager():
-    eo, ev, B = synth.make_instance(4, 20, 60, 3, scale=0.5)
+# v=20: one K-chunk candidate; v=64 (pair blocks of 2080 / 2016): the tuner times 1, 2, 4 and 8 chunks,
+# and the captured pass must use the count the eager pass settled (else replays differ in rounding)
+@pytest.mark.parametrize("o,v,X", [(4, 20, 60), (4, 64, 96)], ids=lambda c: str(c))
+def test_sigma_graph_replays_match_eager(o, v, X):
+    eo, ev, B = synth.make_instance(o, v, X, 3, scale=0.5)
     P = Problem(eo, ev, B)
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):

@@ -96,6 +96,39 @@ def test_ladder_apply_large_workload_shape_sampled_rows(large_shape, prec):
     torch.cuda.empty_cache()
 
 
+@pytest.fixture(scope="module")
+def full_large_shape():
+    """The large workload itself: o=40, v=600, X=1800, seed 2 (its virtual block Bvv, 5.2 GB), 200 rows
+    (5 vectors x 40 occupied).  The oracle samples rows a of chosen vectors m: 9 x 600 elements."""
+    eo, ev, B = synth.make_instance(40, 600, 1800, 2)
+    Bvv = np.ascontiguousarray(B[:, 40:, 40:])
+    del B
+    Z = np.random.default_rng(13).standard_normal((200, 600, 600))
+    from oracle.adc_cs import ladder_rows
+    ms, aa = (0, 117, 199), (0, 311, 599)
+    refs = {m: ladder_rows(Bvv, Z[m], aa) for m in ms}
+    return Bvv, Z, ms, aa, refs
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_ladder_apply_full_large_workload_sampled(full_large_shape, prec):
+    """sum_Q B^Q Z B^Q at v=600, X=1800, 200 rows (the assembled ladder of the large workload's canonical
+    basis), 8 GB of intermediate per chunk; sampled elements against the oracle in all three precisions."""
+    Bvv, Z, ms, aa, refs = full_large_shape
+    M, v, X = Z.shape[0], Z.shape[1], Bvv.shape[0]
+    print("assembled ladder v=%d X=%d rows=%d precision %d" % (v, X, M, prec), flush=True)
+    Bd = dev(Bvv)
+    out = adc.adc3_ladder_apply(Bd, dev(Z), precision=prec,
+                                workspace_bytes=adc.adc3_ladder_workspace_bytes(v, X, M, prec) + (8 << 30))
+    scale = max(np.abs(r).max() for r in refs.values())
+    for m in ms:
+        got = host(out[m])[list(aa)]
+        err = np.abs(got - refs[m]).max() / scale
+        assert err < LP_TOL[prec], (m, err)
+    del out, Bd
+    torch.cuda.empty_cache()
+
+
 SMALL = [(3, 7, 15, 3, 0.5), (2, 9, 20, 4, 1.0), (5, 17, 40, 5, 0.3)]
 
 

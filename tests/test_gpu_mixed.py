@@ -75,10 +75,11 @@ def test_mixed_solve_weak_correlation_full_size(prec):
     assert [r["naux_kept"] for r in reps] == gold["naux_kept"]
 
 
-# FP32 ladder at >= 48 rows (n_vec * o): the kernel with the packed rows k-major in FP32, both tiles
+# FP32 ladder from three 16-row blocks on (33 rows, n_vec * o): the kernel with the packed rows k-major in FP32, both tiles
 # copied into LDS by buffer loads.  One and two row tiles, ragged column tiles, 1, 3 or tuned K chunks;
 # the FP32 sigma error against the FP64 oracle stays at the FP32 level of the small case above.
-@pytest.mark.parametrize("o,v,X,nvec", [(6, 41, 60, 7), (10, 41, 60, 16), (8, 80, 120, 9)], ids=lambda c: str(c))
+@pytest.mark.parametrize("o,v,X,nvec", [(6, 41, 60, 7), (10, 41, 60, 16), (8, 80, 120, 9), (16, 45, 70, 4),
+                                        (16, 45, 70, 6), (20, 44, 66, 5), (16, 45, 70, 8)], ids=lambda c: str(c))
 @pytest.mark.parametrize("chunks", ["", "1", "3"])
 def test_fp32_sigma_stored_ladder_row_tiles(o, v, X, nvec, chunks, monkeypatch):
     monkeypatch.setenv("ADC3_LADDER_CHUNKS", chunks)

@@ -221,7 +221,7 @@ def test_exact_1p_block_preconditioner_adc2():
     assert [x["nvir_kept"] for x in p0] == [x["nvir_kept"] for x in p3]
 
 
-# Stored-ladder row tiles: at >= 48 rows (n_vec * o) the FP64 ladder runs on the kernel that takes
+# Stored-ladder row tiles: from three 16-row blocks on (33 rows, n_vec * o) the FP64 ladder runs on the kernel that takes
 # the packed rows k-major and copies both tiles into LDS by buffer loads (rows past a K chunk read
 # as zero).  Cases: one row tile with ragged rows (42, 72, 33 rows), two row tiles (160 rows),
 # ragged column tiles (pair counts 861/820, 3240/3160, 2080/2016 padded to multiples of 8), and
@@ -254,3 +254,50 @@ def test_intermediates_large_contractions(o, v, X):
     ctx.close()
     assert relerr(Uz, P.coupling_z(3)) < 1e-11
     assert relerr(M11, P.m11(3)) < 1e-11
+
+
+# The row-tile heights the solves run: M = n_vec * o rows in one tile of TM 16-row blocks, TM = 4, 6, 7, 8
+# (64, 96, 100, 128 rows); TM even takes the epilogue that stores two fragments per LDS read, TM = 7 is the
+# benchmark's 5-vector pass of o = 20.  K in 1 or 3 chunks or the tuned count.
+@pytest.mark.parametrize("o,v,X,nvec", [(16, 45, 70, 4), (16, 45, 70, 6), (20, 44, 66, 5), (16, 45, 70, 8)],
+                         ids=lambda c: str(c))
+@pytest.mark.parametrize("chunks", ["", "1", "3"])
+def test_sigma_stored_ladder_tile_heights(o, v, X, nvec, chunks, monkeypatch):
+    monkeypatch.setenv("ADC3_LADDER_CHUNKS", chunks)
+    eo, ev, B = synth.make_instance(o, v, X, 11, scale=0.3)
+    P = Problem(eo, ev, B)
+    ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, nroots=0)
+    r = np.random.default_rng(5).standard_normal((nvec, P.dim()))
+    s_gpu = host(ctx.sigma(dev(r)))
+    ctx.close()
+    assert relerr(s_gpu, P.sigma(r, 3)) < 1e-11
+
+
+def _sigma_2p1h_ref(P, z):
+    """2p1h part of sigma for vectors with r1 = 0: K0 z + the first-order 2p1h terms (ladder and
+    particle-hole), from the oracle's own pieces (the coupling block, which r1 = 0 does not reach, is
+    left out so that the oracle stays cheap at the benchmark size)."""
+    from oracle.adc_cs import d_to_z, z_to_x
+    return P.k0() * z + d_to_z(P.k1_D(z_to_x(z)))
+
+
+# The benchmark's own sigma shape: o = 20, v = 200 after SS-FNO, X = 128 after NAF, 5 vectors
+# (M = 100 rows, ladder_f64t_kernel with TM = 7), where each pair block (20104^2 doubles, 3.2 GB)
+# needs at least two K chunks to keep byte offsets below 2^31; tuned and fixed chunk counts.  One
+# vector (20 rows) runs the row-major kernel.
+_BENCH_REF = {}
+
+
+@pytest.mark.parametrize("nvec,chunks", [(5, ""), (5, "2"), (5, "8"), (1, "")])
+def test_sigma_benchmark_shape(nvec, chunks, monkeypatch):
+    monkeypatch.setenv("ADC3_LADDER_CHUNKS", chunks)
+    o, v, X = 20, 200, 128
+    eo, ev, B = synth.make_instance(o, v, X, 1, scale=0.3)
+    z = np.random.default_rng(7).standard_normal((nvec, o, v, v))
+    if nvec not in _BENCH_REF:
+        _BENCH_REF[nvec] = _sigma_2p1h_ref(Problem(eo, ev, B), z)
+    ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, nroots=0)
+    r = np.concatenate([np.zeros((nvec, v)), z.reshape(nvec, -1)], axis=1)
+    s_gpu = host(ctx.sigma(dev(r)))[:, v:].reshape(nvec, o, v, v)
+    ctx.close()
+    assert relerr(s_gpu, _BENCH_REF[nvec]) < 1e-11

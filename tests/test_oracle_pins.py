@@ -142,3 +142,14 @@ def test_mp2_density_traces():
     assert abs(np.trace(P.mp2_density_vv()) + np.trace(P.mp2_density_oo())) < 1e-12
     D = P.mp2_density_vv()
     assert np.abs(D - D.T).max() < 1e-14
+
+
+def test_ladder_rows_match_full_ladder():
+    """The oracle's row sampler of the ladder equals the explicit four-index contraction."""
+    from oracle.adc_cs import ladder_rows
+    eo, ev, B = _inst(2, 7, 9, 4, 1.0)
+    g = np.einsum("Qpq,Qrs->pqrs", B, B)[2:, 2:, 2:, 2:]
+    amp = np.random.default_rng(2).standard_normal((7, 7))
+    full = np.einsum("acbd,cd->ab", g, amp)
+    rows = [0, 3, 6]
+    assert np.abs(ladder_rows(B[:, 2:, 2:], amp, rows) - full[rows]).max() < 1e-12 * np.abs(full).max()

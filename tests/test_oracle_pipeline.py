@@ -1,5 +1,6 @@
 """Pins of the oracle's solver and SS-FNO/NAF pipeline."""
 import numpy as np
+import pytest
 
 import synth
 from oracle import ssfno
@@ -61,3 +62,152 @@ def test_ea_density_trace_invariant():
     r1, z = P.split(vec)
     # spin-summed trace = |r1|^2 + 2 |2p1h|^2
     assert abs(2 * np.trace(D) - (r1 @ r1 + 2 * np.sum(z * z))) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# The densities of the SS-FNO step pinned to their definitions in the determinant spaces of the
+# intermediate-state oracle (tier 0): one-particle densities <Psi| c+_p c_q |Psi> of explicit
+# (N+1)- and N-electron vectors, built from creation and annihilation operators.
+# ---------------------------------------------------------------------------
+from oracle import adc_so  # noqa: E402
+from oracle.adc_cs import z_to_x  # noqa: E402
+from oracle.isr import ISR  # noqa: E402
+
+
+def _tier0(o=2, v=3, X=6, seed=5, sc=0.4):
+    eo, ev, B = synth.make_instance(o, v, X, seed, scale=sc)
+    return eo, ev, B, ISR(eo, ev, B), Problem(eo, ev, B)
+
+
+def _density(isr, bra, ket, p, q, nelec):
+    return bra @ (isr.lad.one_body(p, q, nelec) @ ket)
+
+
+def _reference_det(isr):
+    S = isr.lad.spaces[isr.N]
+    phi0 = np.zeros(S.dim)
+    phi0[S.index[(1 << isr.N) - 1]] = 1.0
+    return phi0
+
+
+def _state_vector(isr, o, v, vec):
+    """(N+1)-electron determinant vector of the zeroth-order intermediate states with doublet coordinates
+    vec = (r1, z): sum_A u_A c+_A Phi0 + sum_(A<B, I) u_ABI c+_A c+_B c_I Phi0, u = C vec (spin-orbitals)."""
+    N = isr.N
+    u = adc_so.doublet_embedding(o, v) @ vec
+    phi0 = _reference_det(isr)
+    nv = 2 * v
+    out = np.zeros(isr.lad.spaces[N + 1].dim)
+    for A in range(nv):
+        out += u[A] * isr.lad.apply("c", N + A, N, phi0)
+    cls2 = [(A, B, I) for A in range(nv) for B in range(nv) if A < B for I in range(2 * o)]
+    for k, (A, B, I) in enumerate(cls2):
+        if u[nv + k] != 0.0:
+            w = isr.lad.apply("a", I, N, phi0)
+            w = isr.lad.apply("c", N + B, N - 1, w)
+            out += u[nv + k] * isr.lad.apply("c", N + A, N, w)
+    return out
+
+
+def _spin_averaged_vv(isr, o, v, psi, nelec):
+    ra = np.array([[_density(isr, psi, psi, 2 * (o + a), 2 * (o + b), nelec) for b in range(v)] for a in range(v)])
+    rb = np.array([[_density(isr, psi, psi, 2 * (o + a) + 1, 2 * (o + b) + 1, nelec) for b in range(v)]
+                   for a in range(v)])
+    return 0.5 * (ra + rb)
+
+
+def _ea_density_swapped_beta(P, vec):
+    """A plausible mistake: the beta electron's term with the index order of the alpha one."""
+    r1, z = P.split(vec)
+    x = z_to_x(z)
+    y = x - x.transpose(0, 2, 1)
+    rho = np.outer(r1, r1) + 2.0 * np.einsum("iac,ibc->ab", x, x) + np.einsum("iac,ibc->ab", y, y)
+    return 0.5 * rho
+
+
+def _ea_density_x_for_y(P, vec):
+    """A plausible mistake: the same-spin amplitudes y replaced by x."""
+    r1, z = P.split(vec)
+    x = z_to_x(z)
+    rho = np.outer(r1, r1) + 2.0 * np.einsum("iac,ibc->ab", x, x) + np.einsum("ica,icb->ab", x, x)
+    return 0.5 * rho
+
+
+@pytest.mark.parametrize("case", [(2, 3, 6, 5, 0.4), (1, 4, 5, 7, 0.6)])
+def test_ea_density_is_the_determinant_density(case):
+    """D^EA (eq 17 reading) = the spin-averaged virtual density of the (N+1)-electron state that the
+    doublet coordinates describe on the zeroth-order intermediate states (c+_a Phi0, c+_a c+_b c_i Phi0):
+    for a random state and for ADC(2) eigenvectors.  Two plausible mistakes must fail."""
+    o, v = case[0], case[1]
+    eo, ev, B, isr, P = _tier0(*case)
+    rng = np.random.default_rng(1)
+    vecs = [rng.standard_normal(P.dim())]
+    w, Y = np.linalg.eigh(P.dense(2))
+    vecs += [Y[:, 0], Y[:, 2]]
+    for vec in vecs:
+        vec = vec / np.linalg.norm(vec)
+        psi = _state_vector(isr, o, v, vec)
+        assert abs(psi @ psi - 1.0) < 1e-13
+        ref = _spin_averaged_vv(isr, o, v, psi, isr.N + 1)
+        D = ssfno.ea_density(P, vec)
+        assert np.abs(D - ref).max() < 1e-14
+        assert np.abs(_ea_density_swapped_beta(P, vec) - ref).max() > 1e-8
+        assert np.abs(_ea_density_x_for_y(P, vec) - ref).max() > 1e-8
+
+
+@pytest.mark.parametrize("case", [(2, 3, 6, 5, 0.4), (1, 4, 5, 7, 0.6), (2, 4, 7, 3, 0.3)])
+def test_mp2_densities_are_the_second_order_densities(case):
+    """D^MP2 (per spin, eq 17 reading), the occupied block and the singles u1 that enter the static
+    self-energy = the second-order one-particle densities of the Rayleigh-Schroedinger ground state
+    Psi0 = Phi0 + Psi1 + Psi2 (intermediate normalisation): vv <Psi1|c+_a c_b|Psi1>,
+    oo <Psi1|c+_i c_j|Psi1> - delta_ij <Psi1|Psi1>, ov <Phi0|c+_i c_a|Psi2>."""
+    o, v = case[0], case[1]
+    eo, ev, B, isr, P = _tier0(*case)
+    N = isr.N
+    psi1, psi2 = isr.psi0[1], isr.psi0[2]
+    phi0 = _reference_det(isr)
+    vv = np.array([[_density(isr, psi1, psi1, 2 * (o + a), 2 * (o + b), N) for b in range(v)] for a in range(v)])
+    oo = np.array([[_density(isr, psi1, psi1, 2 * i, 2 * j, N) - (i == j) * (psi1 @ psi1) for j in range(o)]
+                   for i in range(o)])
+    ov = np.array([[_density(isr, phi0, psi2, 2 * i, 2 * (o + a), N) for a in range(v)] for i in range(o)])
+    assert np.abs(vv).max() > 1e-4 and np.abs(oo).max() > 1e-4 and np.abs(ov).max() > 1e-5
+    assert np.abs(P.mp2_density_vv() - vv).max() < 1e-15
+    assert np.abs(P.mp2_density_oo() - oo).max() < 1e-15
+    assert np.abs(P.second_order()[3] - ov).max() < 1e-15
+    # a plausible mistake: the exchange-like term with the wrong sign
+    T = P.T
+    wrong = np.einsum("klce,klcd->ed", 2.0 * T + T.transpose(0, 1, 3, 2), T)
+    assert np.abs(wrong - vv).max() > 1e-6
+
+
+def _matching_detail(o, v, X, seed, sc, thr, k, nroots=4):
+    eo, ev, B = synth.make_instance(o, v, X, seed, scale=sc)
+    P0 = Problem(eo, ev, B)
+    w2, Y2, _ = ssfno.solve_roots(P0, 2, nroots, 1e-10)
+    Dss = P0.mp2_density_vv() + ssfno.ea_density(P0, Y2[k])
+    U, en, eta, nk = ssfno.natural_orbitals(Dss, ev, thr)
+    Pk = Problem(eo, en, ssfno.transform_B(B, o, U))
+    w2k, Y2k, _ = ssfno.solve_roots(Pk, 2, nroots, 1e-10)
+    ref = ssfno.carry_vector(Y2[k], o, v, U)
+    m_full = int(np.argmax(np.abs(Y2k @ ref)))
+    m_1p = int(np.argmax(np.abs(Y2k[:, :nk] @ ref[:nk])))
+    r1norm = float(np.linalg.norm(Y2[k][:v]))
+    return w2, w2k, m_full, m_1p, r1norm, (eo, ev, B)
+
+
+def test_root_matching_follows_the_state_through_reordering():
+    """Root k of a truncated basis (eq 30 needs the same state in both bases).  A mild change of basis
+    moves a state's energy only slightly, so the matched truncated ADC(2) root must lie close to the
+    canonical one.  (a) A 1p-dominated state that the truncation reorders (canonical root 3 becomes
+    truncated root 1): the full-vector overlap rule and the 1p-overlap rule both pick it, index
+    matching would not.  (b) A 2p1h satellite (|r1| ~ 0.03): the full-vector rule follows it; the
+    1p-overlap rule, whose overlaps are all ~1e-3 there, picks a state 0.29 Eh away."""
+    w2, w2k, m_full, m_1p, r1n, inst = _matching_detail(2, 8, 16, 5, 0.05, 1e-3, 3)
+    assert r1n > 0.99 and m_full == m_1p == 1
+    assert abs(w2k[m_full] - w2[3]) < 1e-3 and abs(w2k[3] - w2[3]) > 1e-3
+    eo, ev, B = inst
+    run = ssfno.run(eo, ev, B, 4, 1e-3, 0.0, 1e-10)
+    assert abs(run["omega_adc2_fno"][3] - w2k[1]) < 1e-12
+    w2, w2k, m_full, m_1p, r1n, _ = _matching_detail(2, 8, 16, 7, 0.1, 1e-4, 1)
+    assert r1n < 0.05 and m_full == 1 and m_1p != m_full
+    assert abs(w2k[m_full] - w2[1]) < 1e-3 < abs(w2k[m_1p] - w2[1])
