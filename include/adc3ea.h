@@ -75,11 +75,30 @@ typedef struct {
                              (needs a non-null stream; on the null stream sigma runs eagerly); default 0 */
     int ladder;           /* form of the ladder term sum_cd (ac|bd) r_cdi of the ADC(3) contexts:
                              1 stored: (ac|bd) assembled once per basis from the DF factor (eq 25) and
-                               kept as a v^4 matrix, 2 M v^4 flops per application of M rows;
+                               kept as its pair-symmetric and pair-antisymmetric blocks (about v^4/2
+                               elements), about M v^4 flops per application of M rows;
                              2 assembled: sum_Q B^Q Z_i B^Q from the virtual block of the factor in
                                every application, 4 X M v^3 flops and no v^4 storage;
-                             0 (default): stored unless the v^4 matrix of the canonical basis exceeds
-                               96 GB in FP64 (nvir > 331).  The choice holds for the whole solve. */
+                             0 (default): stored unless the pair blocks of the canonical basis exceed
+                               96 GB in FP64 (nvir > 393).  The choice holds for the whole solve. */
+    double sm_x;          /* level 3: the scaled-matrix ADC of Sec. "ADC Theory" (equation after eq 5),
+                             M = M_ADC(2) + sm_x (M_ADC(3) - M_ADC(2)): the third-order part of M11, the
+                             second-order part of the 1p/2p1h coupling and the first-order 2p1h terms
+                             scaled by sm_x; 0 gives ADC(2), 1 (default) ADC(3), 0.5 the usual choice.
+                             In [0, 1].  The truncated ADC(2) solves of eq 30 are unaffected. */
+    int fno_mode;         /* natural orbitals of the virtual truncation (eqs 9-16): 0 (default) state
+                             specific, D^SS(k) = D^MP2 + D^EA(k) per root (eq 17); 1 ground-state MP2-FNO,
+                             D^MP2 alone, one truncated basis shared by all roots (each root matched in it
+                             as above) */
+    double fno_keep_frac; /* > 0: keep ceil(fno_keep_frac * nvir) natural orbitals (largest occupations)
+                             instead of those above fno_thresh (a percentage-of-virtuals truncation); 0
+                             (default): by threshold.  In [0, 1]; > 0 runs the truncated pipeline. */
+    const double* init_guess; /* device [n_guess][N] (N of the canonical basis), nullable: start vectors of
+                             the canonical-basis Davidson (the ADC(level) solve without truncation, else
+                             the canonical ADC(2) solve of step 3), taken before the diagonal guesses;
+                             resuming from vectors_out of an unconverged run reaches the same roots */
+    int n_guess;          /* number of init_guess vectors (0 default) */
+    double* vectors_out;  /* device [nroots][N], nullable: the Ritz vectors of that canonical-basis solve */
 } adc3_opts;
 
 /* Per-root report of adc3_ea_solve. */
@@ -95,6 +114,12 @@ typedef struct {
     int sigma_builds;      /* sigma vectors built for this root (all solves) */
     double omega_lowp;     /* precision 1/2: root k when the reduced-precision phase ended */
     int iters_lowp;        /* precision 1/2: Davidson iterations in the reduced-precision phase */
+    double err_bound;      /* bound on |omega - the same combination of exact eigenvalues of the FP64
+                              matrices|: each eigenvalue that enters omega (ADC(3) root, and with eq 30 the
+                              canonical and truncated ADC(2) roots) lies within its FP64 residual 2-norm of
+                              an eigenvalue of its matrix (symmetric M), so their sum bounds the error; in
+                              every precision the last Davidson phase runs FP64 sigma, so it also bounds the
+                              mixed-precision result's distance from the FP64 one */
 } adc3_root_report;
 
 void adc3_default_opts(adc3_opts* opts);
@@ -186,6 +211,13 @@ int adc3_ea_setup_ex(const double* eps_occ_dev, const double* eps_vir_dev, const
                      void* workspace_dev, size_t workspace_bytes, hipStream_t stream,
                      adc3_ctx** ctx_out);
 
+/* A level-3 context of the scaled-matrix ADC, M = M_ADC(2) + sm_x (M_ADC(3) - M_ADC(2)) (Sec. "ADC
+ * Theory", equation after eq 5; see adc3_opts.sm_x), sm_x in [0, 1]; ladder and workspace as
+ * adc3_ea_setup_ex with level 3. */
+int adc3_ea_setup_sm(const double* eps_occ_dev, const double* eps_vir_dev, const double* B_dev,
+                     int nocc, int nvir, int naux, double sm_x, int precision, int ladder,
+                     void* workspace_dev, size_t workspace_bytes, hipStream_t stream, adc3_ctx** ctx_out);
+
 void adc3_ctx_destroy(adc3_ctx* ctx);
 
 /* Element budget for one chunk of the large setup tensors (the o*na*v^2 slices of the
@@ -245,10 +277,23 @@ int adc3_ea_diagonal(adc3_ctx* ctx, double* diag_dev, hipStream_t stream);
 
 /* Lowest nroots eigenpairs of M by block Davidson (FP64).  omega[nroots] host;
  * vectors_dev[nroots][N] device (nullable); resnorm[nroots] host (nullable);
- * iters (host, nullable) receives the iteration count. */
+ * iters (host, nullable) receives the iteration count.  Returns ADC3_WNOCONV (outputs valid:
+ * the current Ritz values and vectors) after max_iter iterations, ADC3_ENUMERIC for a non-finite
+ * Ritz value or residual. */
 int adc3_ea_davidson(adc3_ctx* ctx, int nroots, double conv, int max_iter, int max_subspace,
                      int precision, double* omega, double* vectors_dev, double* resnorm, int* iters,
                      hipStream_t stream);
+
+/* The same with caller start vectors guess_dev[n_guess][N] (device; orthonormalised as a block and
+ * taken before the diagonal guesses): resuming from the vectors of an unconverged call converges to
+ * the same roots in fewer iterations.  ADC3_ENUMERIC if the guesses are linearly dependent. */
+int adc3_ea_davidson_guess(adc3_ctx* ctx, int nroots, double conv, int max_iter, int max_subspace,
+                           int precision, const double* guess_dev, int n_guess, double* omega,
+                           double* vectors_dev, double* resnorm, int* iters, hipStream_t stream);
+
+/* Test hook of the error path: the next Davidson iteration >= iteration (> 0) on any context writes
+ * NaN into one new sigma vector, once; that solve then returns ADC3_ENUMERIC.  0 disarms. */
+void adc3_debug_inject_nan(int iteration);
 
 /* Test hook: dense M (N <= 20000) into M_dev[N][ldm] device. */
 int adc3_ea_dense_matrix(adc3_ctx* ctx, double* M_dev, int ldm, hipStream_t stream);

@@ -305,3 +305,20 @@ class Problem:
     def dense(self, level):
         n = self.dim()
         return self.sigma(np.eye(n), level)
+
+    # ------------------------------------------------------------------
+    # scaled-matrix ADC (Sec. "ADC Theory", the equation after eq 5): the paper states that x = 0
+    # gives ADC(2) and x = 1 ADC(3); its formula M0 + M1 + M2 + x M3 taken literally would keep the
+    # second-order coupling and the first-order 2p1h terms at x = 0, so the reading is
+    # M_sm = M_ADC(2) + x (M_ADC(3) - M_ADC(2)), which meets both statements.
+    # ------------------------------------------------------------------
+    def sigma_sm(self, r, x):
+        s2 = self.sigma(r, 2)
+        return s2 + x * (self.sigma(r, 3) - s2)
+
+    def diagonal_sm(self, x):
+        d2 = self.diagonal(2)
+        return d2 + x * (self.diagonal(3) - d2)
+
+    def dense_sm(self, x):
+        return self.sigma_sm(np.eye(self.dim()), x)

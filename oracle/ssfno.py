@@ -65,12 +65,18 @@ def ea_density(P, vec):
     return 0.5 * rho
 
 
-def natural_orbitals(D, eps_vir, thresh):
-    """Eqs 9-14: returns (U [v, vk], eps_new [vk], eta [v] descending, kept count)."""
+def natural_orbitals(D, eps_vir, thresh, keep_n=0):
+    """Eqs 9-14: returns (U [v, vk], eps_new [vk], eta [v] descending, kept count).
+
+    keep_n > 0 keeps that many orbitals of largest occupation instead of those above thresh
+    (the percentage-of-virtuals truncation the paper compares against)."""
     eta, V = np.linalg.eigh(D)
     order = np.argsort(-eta, kind="stable")
     eta, V = eta[order], fix_signs(V[:, order])
-    keep = eta > thresh if thresh > 0 else np.ones(eta.size, bool)
+    if keep_n > 0:
+        keep = np.arange(eta.size) < keep_n
+    else:
+        keep = eta > thresh if thresh > 0 else np.ones(eta.size, bool)
     Vt = V[:, keep]
     F = Vt.T @ np.diag(eps_vir) @ Vt
     F = 0.5 * (F + F.T)
@@ -110,15 +116,20 @@ def naf(B, nocc, thresh):
     return Bn, w, int(keep.sum())
 
 
-def solve_roots(P, level, nroots, conv, dense_limit=4000):
-    """Lowest nroots eigenpairs of ADC(level): dense eigh for small spaces, Davidson otherwise."""
+def solve_roots(P, level, nroots, conv, dense_limit=4000, sm_x=1.0):
+    """Lowest nroots eigenpairs of ADC(level) (level 3 with sm_x != 1: the scaled-matrix ADC):
+    dense eigh for small spaces, Davidson otherwise."""
     n = P.dim()
+    sm = level == 3 and sm_x != 1.0
     if n <= dense_limit:
-        M = P.dense(level)
+        M = P.dense_sm(sm_x) if sm else P.dense(level)
         M = 0.5 * (M + M.T)
         w, Y = np.linalg.eigh(M)
         return w[:nroots], Y[:, :nroots].T, True
-    w, X, rn, it, ok = davidson(lambda V: P.sigma(V, level), P.diagonal(level), nroots, conv=conv)
+    if sm:
+        w, X, rn, it, ok = davidson(lambda V: P.sigma_sm(V, sm_x), P.diagonal_sm(sm_x), nroots, conv=conv)
+    else:
+        w, X, rn, it, ok = davidson(lambda V: P.sigma(V, level), P.diagonal(level), nroots, conv=conv)
     return w, X, ok
 
 
@@ -130,13 +141,19 @@ def carry_vector(vec, o, v, U):
     return np.concatenate([r1, z2.reshape(-1)])
 
 
-def run(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, dense_limit=4000):
-    """The whole method.  Returns a dict with the corrected roots and per-root details."""
+def run(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, dense_limit=4000, sm_x=1.0, fno_mode="ss",
+        keep_frac=0.0):
+    """The whole method.  Returns a dict with the corrected roots and per-root details.
+
+    sm_x: the final level is the scaled-matrix ADC M_ADC(2) + sm_x (M_ADC(3) - M_ADC(2)) (1: ADC(3)).
+    fno_mode "ss": state-specific D^SS(k) = D^MP2 + D^EA(k) (eq 17); "mp2": ground-state MP2-FNO,
+    D^MP2 alone for every root.  keep_frac > 0: keep ceil(keep_frac * nvir) natural orbitals."""
     o, v = eps_occ.size, eps_vir.size
     P0 = Problem(eps_occ, eps_vir, B)
     out = {"nocc": o, "nvir": v, "naux": B.shape[0]}
-    if fno_thresh <= 0 and naf_thresh <= 0:
-        w3, Y3, ok = solve_roots(P0, 3, nroots, conv, dense_limit)
+    keep_n = int(np.ceil(keep_frac * v - 1e-9)) if keep_frac > 0 else 0
+    if fno_thresh <= 0 and naf_thresh <= 0 and keep_n == 0:
+        w3, Y3, ok = solve_roots(P0, 3, nroots, conv, dense_limit, sm_x)
         out.update(roots=w3, omega_uncorr=w3, converged=ok, nvir_kept=[v] * nroots, naux_kept=[B.shape[0]] * nroots)
         return out
     w2, Y2, ok2 = solve_roots(P0, 2, nroots, conv, dense_limit)
@@ -144,8 +161,8 @@ def run(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, dense_limit=4
     out.update(omega_adc2_can=w2, e_mp2=P0.mp2_energy(), d_mp2=Dmp2)
     roots, unc, a2f, nk, xk, eta_all = [], [], [], [], [], []
     for k in range(nroots):
-        Dss = Dmp2 + ea_density(P0, Y2[k])
-        U, e_new, eta, nkeep = natural_orbitals(Dss, eps_vir, fno_thresh)
+        Dss = Dmp2 + ea_density(P0, Y2[k]) if fno_mode == "ss" else Dmp2
+        U, e_new, eta, nkeep = natural_orbitals(Dss, eps_vir, fno_thresh, max(keep_n, 0))
         Bt = transform_B(B, o, U)
         if naf_thresh > 0:
             Bt, wnaf, xkeep = naf(Bt, o, naf_thresh)
@@ -153,7 +170,7 @@ def run(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, dense_limit=4
             xkeep = B.shape[0]
         Pk = Problem(eps_occ, e_new, Bt)
         w2k, Y2k, _ = solve_roots(Pk, 2, nroots, conv, dense_limit)
-        w3k, Y3k, _ = solve_roots(Pk, 3, nroots, conv, dense_limit)
+        w3k, Y3k, _ = solve_roots(Pk, 3, nroots, conv, dense_limit, sm_x)
         ref = carry_vector(Y2[k], o, v, U)
         ov = np.abs(Y2k @ ref)
         m2 = m3 = int(np.argmax(ov))

@@ -27,13 +27,17 @@ EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_byte
            "adc3_ea_solve_batched", "adc3_ea_set_sigma_graphs", "adc3_profile_query_bound",
            "adc3_ea_setup_workspace_bytes_ex", "adc3_ea_setup_ex", "adc3_set_chunk_elems",
            "adc3_ladder_workspace_bytes", "adc3_ladder_apply", "adc3_eigh_workspace_bytes", "adc3_eigh",
-           "adc3_eigh_batched_workspace_bytes", "adc3_eigh_batched"]
+           "adc3_eigh_batched_workspace_bytes", "adc3_eigh_batched",
+           "adc3_ea_davidson_guess", "adc3_ea_setup_sm", "adc3_debug_inject_nan"]
+
 
 
 class adc3_opts(ctypes.Structure):
     _fields_ = [("level", ctypes.c_int), ("max_iter", ctypes.c_int), ("max_subspace", ctypes.c_int),
                 ("fno_correction", ctypes.c_int), ("precision", ctypes.c_int), ("precond", ctypes.c_int),
-                ("mlp_weights", ctypes.c_void_p), ("sigma_graphs", ctypes.c_int), ("ladder", ctypes.c_int)]
+                ("mlp_weights", ctypes.c_void_p), ("sigma_graphs", ctypes.c_int), ("ladder", ctypes.c_int),
+                ("sm_x", ctypes.c_double), ("fno_mode", ctypes.c_int), ("fno_keep_frac", ctypes.c_double),
+                ("init_guess", ctypes.c_void_p), ("n_guess", ctypes.c_int), ("vectors_out", ctypes.c_void_p)]
 
 
 class adc3_instance(ctypes.Structure):
@@ -47,7 +51,7 @@ class adc3_root_report(ctypes.Structure):
                 ("omega_adc2_can", ctypes.c_double), ("omega_adc2_fno", ctypes.c_double),
                 ("resnorm", ctypes.c_double), ("nvir_kept", ctypes.c_int), ("naux_kept", ctypes.c_int),
                 ("iters", ctypes.c_int), ("sigma_builds", ctypes.c_int), ("omega_lowp", ctypes.c_double),
-                ("iters_lowp", ctypes.c_int)]
+                ("iters_lowp", ctypes.c_int), ("err_bound", ctypes.c_double)]
 
 
 class ADCError(RuntimeError):
@@ -109,6 +113,13 @@ def load():
     lib.adc3_ea_davidson.argtypes = [P, I, D, I, I, I, ctypes.POINTER(D), P, ctypes.POINTER(D),
                                      ctypes.POINTER(I), P]
     lib.adc3_ea_davidson.restype = I
+    lib.adc3_ea_davidson_guess.argtypes = [P, I, D, I, I, I, P, I, ctypes.POINTER(D), P, ctypes.POINTER(D),
+                                           ctypes.POINTER(I), P]
+    lib.adc3_ea_davidson_guess.restype = I
+    lib.adc3_ea_setup_sm.argtypes = [P, P, P, I, I, I, D, I, I, P, S, P, ctypes.POINTER(P)]
+    lib.adc3_ea_setup_sm.restype = I
+    lib.adc3_debug_inject_nan.argtypes = [I]
+    lib.adc3_debug_inject_nan.restype = None
     lib.adc3_ea_dense_matrix.argtypes = [P, P, I, P]
     lib.adc3_ea_dense_matrix.restype = I
     lib.adc3_ea_intermediate.argtypes = [P, I, P, ctypes.POINTER(LL), P]
@@ -315,7 +326,8 @@ def adc3_eigh_batched(A):
 class Context:
     """Secular-matrix context (adc3_ea_setup ... adc3_ctx_destroy)."""
 
-    def __init__(self, eps_occ, eps_vir, B, level, nroots=8, precision=0, ladder=0):
+    def __init__(self, eps_occ, eps_vir, B, level, nroots=8, precision=0, ladder=0, sm_x=None):
+        """level 2 or 3; sm_x (level 3 only): the scaled-matrix ADC M_ADC(2) + sm_x (M_ADC(3) - M_ADC(2))."""
         lib = load()
         self.nocc, self.nvir, self.naux = int(eps_occ.numel()), int(eps_vir.numel()), int(B.shape[0])
         self.level = level
@@ -323,10 +335,15 @@ class Context:
         self.workspace = _workspace(adc3_ea_setup_workspace_bytes(self.nocc, self.nvir, self.naux, level, nroots,
                                                                   precision, ladder))
         h = ctypes.c_void_p()
-        _check(lib.adc3_ea_setup_ex(_ptr(eps_occ), _ptr(eps_vir), _ptr(B), self.nocc, self.nvir, self.naux, level,
-                                    precision, ladder,
-                                    ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(), _stream(),
-                                    ctypes.byref(h)))
+        ws = (ctypes.c_void_p(self.workspace.data_ptr()), self.workspace.numel(), _stream(), ctypes.byref(h))
+        if sm_x is None:
+            _check(lib.adc3_ea_setup_ex(_ptr(eps_occ), _ptr(eps_vir), _ptr(B), self.nocc, self.nvir, self.naux,
+                                        level, precision, ladder, *ws))
+        else:
+            if level != 3:
+                raise ValueError("sm_x needs level 3")
+            _check(lib.adc3_ea_setup_sm(_ptr(eps_occ), _ptr(eps_vir), _ptr(B), self.nocc, self.nvir, self.naux,
+                                        float(sm_x), precision, ladder, *ws))
         self.handle = h
         self.N = lib.adc3_ea_dim(h)
 
@@ -356,14 +373,18 @@ class Context:
         _check(load().adc3_ea_diagonal(self.handle, _ptr(d), _stream()))
         return d
 
-    def davidson(self, nroots, conv, max_iter=500, max_subspace=0, want_vectors=False, precision=0):
+    def davidson(self, nroots, conv, max_iter=500, max_subspace=0, want_vectors=False, precision=0, guess=None):
+        """(omega, vectors or None, resnorm, iterations, status); guess: device [n][N] start vectors."""
         import torch
         w = (ctypes.c_double * nroots)()
         rn = (ctypes.c_double * nroots)()
         it = ctypes.c_int()
         vec = torch.empty((nroots, self.N), dtype=torch.float64, device="cuda") if want_vectors else None
-        st = load().adc3_ea_davidson(self.handle, nroots, conv, max_iter, max_subspace, precision, w,
-                                     _ptr(vec) if vec is not None else None, rn, ctypes.byref(it), _stream())
+        g = guess.contiguous() if guess is not None else None
+        ng = 0 if g is None else (1 if g.dim() == 1 else int(g.shape[0]))
+        st = load().adc3_ea_davidson_guess(self.handle, nroots, conv, max_iter, max_subspace, precision,
+                                           _ptr(g) if g is not None else None, ng, w,
+                                           _ptr(vec) if vec is not None else None, rn, ctypes.byref(it), _stream())
         _check(st, allow_noconv=True)
         return np.array(w[:]), vec, np.array(rn[:]), it.value, st
 
@@ -414,6 +435,11 @@ class Context:
 
 
 adc3_ea_setup = Context
+
+
+def adc3_debug_inject_nan(iteration):
+    """Arm the error-path hook: the next Davidson iteration >= iteration writes NaN into one sigma vector."""
+    load().adc3_debug_inject_nan(int(iteration))
 
 
 def adc3_mlp_nparams():

@@ -108,6 +108,7 @@ constexpr double PEAK_FP64_MFMA = 78.6e12, PEAK_FP32_MFMA = 157.3e12, PEAK_BF16_
 
 struct Ctx {
     int o = 0, v = 0, X = 0, level = 2;
+    double smx = 1.0;  // level 3: M = M_ADC(2) + smx (M_ADC(3) - M_ADC(2)) (scaled third order; 1 = ADC(3))
     long long N = 0;
     Arena ws;
     double *eo = nullptr, *ev = nullptr, *Boo = nullptr, *Bov = nullptr, *Bvv = nullptr;
@@ -173,10 +174,11 @@ static void add_sym(double* M, double* P, int v, double a, hipStream_t s) {
 // Build the context from DF blocks (copied in).  Temporaries are released on return.
 static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const double* Boo_in, const double* Bov_in,
                       const double* Bvv_in, int o, int v, int X, int level, hipStream_t s, int prec = 0,
-                      bool df = false) {
+                      bool df = false, double smx = 1.0) {
     ProfScope prof(PROF_SETUP, s, 0.0, 0.0);
     Ctx* c = new Ctx();
     c->o = o; c->v = v; c->X = X; c->level = level; c->prec = prec;
+    c->smx = level >= 3 ? smx : 1.0;
     c->df = df && level >= 3;
     c->N = v + (long long)o * v * v;
     const long long oo = (long long)o * o, ov = (long long)o * v, vv = (long long)v * v;
@@ -276,7 +278,7 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
         if (level >= 3) {
             double* Bw = take(ws, X * ov);
             ein(ws, "Qkd,ikcd->Qic", 1.0, TV(Bov, {X, o, v}), TV(Tt2, {o, o, v, v}), 0.0, Bw, s);
-            k_axpby(Bw, Bov, X * ov, 1.0, 1.0, s);
+            k_axpby(Bw, Bov, X * ov, 1.0, c->smx, s);  // B + smx W (second order scaled for sm-ADC)
             Bov_u = Bw;
         }
         k_fill(c->Uz, vv * ov, 0.0, s);
@@ -301,14 +303,15 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
                     ooov_a = ooc;
                     Bov_a = Boc;
                 }
-                // coupling, second order
-                ein(ws, "klbc,ilka->abci", 1.0, tT, TV(ooov_a, {o, o, o, nc}), 1.0, Ud, s);
+                // coupling, second order (scaled by smx for sm-ADC)
+                const double x2 = c->smx;
+                ein(ws, "klbc,ilka->abci", x2, tT, TV(ooov_a, {o, o, o, nc}), 1.0, Ud, s);
                 // (ka|cd) for a in the chunk: [k][a][c][d]
                 double* ovvv1 = take(ws, E);
                 ein(ws, "Qka,Qcd->kacd", 1.0, TV(Bov_a, {X, o, nc}), TV(Bvv, {X, v, v}), 0.0, ovvv1, s);
                 TV t1(ovvv1, {o, nc, v, v});
-                ein(ws, "kibd,kacd->abci", -1.0, tT, t1, 1.0, Ud, s);
-                ein(ws, "ikcd,kabd->abci", -1.0, tT, t1, 1.0, Ud, s);
+                ein(ws, "kibd,kacd->abci", -x2, tT, t1, 1.0, Ud, s);
+                ein(ws, "ikcd,kabd->abci", -x2, tT, t1, 1.0, Ud, s);
             }
             double* Up = take(ws, E);
             int d[4] = {nc, v, v, o}, pm[4] = {0, 3, 1, 2};
@@ -324,6 +327,12 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             c->Gm = c->G + sa_lp(v) * sa_lp(v);
         }
         const size_t mark1 = ws.mark();
+        // sm-ADC: M11 through second order, kept to scale the third-order part afterwards
+        double* M11_2 = nullptr;
+        if (c->smx != 1.0) {
+            M11_2 = take(ws, vv);
+            k_copy(M11_2, c->M11, vv, s);
+        }
         {
             // phase B: G, then everything of M11 through third order that needs it
             GemmScratch gscr(ws, GEMM_SCRATCH);
@@ -479,9 +488,10 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             ein(ws, "kmac,ckbm->ab", 1.0, tT, tRC, 1.0, P, s);
             add_sym(c->M11, P, v, -1.0, s);
         }
+        if (M11_2) k_axpby(c->M11, M11_2, vv, 1.0 - c->smx, c->smx, s);  // M11_2 + smx (M11_3 - M11_2)
         ws.release(mark1);
     }
-    k_diag_adc(c->diag, c->M11, eo, ev, Bvv, c->oovv, c->ovov, o, v, X, level, s);
+    k_diag_adc(c->diag, c->M11, eo, ev, Bvv, c->oovv, c->ovov, o, v, X, level, s, c->smx);
     if (prec > 0) {
         k_to_lowp(c->Uz32, c->Uz, v * (long long)o * vv, 1, s);
         if (level >= 3 && c->df) {
@@ -681,7 +691,8 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
                 }
                 k_ph_fin(c->sb, D, E, E + (long long)Mph * ovi, nv, o, v, s);
             }
-            k_copy2d(ss + v, N, c->sb, ovv, nv, ovv, 1.0, 1.0, s);
+            // first-order 2p1h terms (ladder + particle-hole), scaled by smx for sm-ADC
+            k_copy2d(ss + v, N, c->sb, ovv, nv, ovv, c->smx, 1.0, s);
         }
     }
 }
@@ -758,6 +769,10 @@ struct Recorder {
     const double* xf = nullptr;                        // converged vectors [nroots][N]
     double *F = nullptr, *A0 = nullptr, *D = nullptr;  // caller buffers [Gmax][S][6], [Gmax][S], [Gmax][S]
 };
+
+// Failure injection for tests of the error path (adc3_debug_inject_nan): the next Davidson that
+// reaches this iteration writes NaN into the sigma vector of its first new direction, once.
+static std::atomic<int> g_nan_at{0};
 
 struct DavResult {
     std::vector<double> w, rn;
@@ -1073,6 +1088,10 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
             break;
         }
         sigma_impl(c, ws, V + (long long)m * N, S + (long long)m * N, acc, s, phase);
+        {
+            int at = g_nan_at.load();
+            if (at > 0 && it >= at && g_nan_at.compare_exchange_strong(at, 0)) k_fill(S + (long long)m * N, N, NAN, s);
+        }
         // new Gram columns V[0..m+acc) . S[m..m+acc), mirrored into the new rows
         k_dots(V, N, m + acc, S + (long long)m * N, N, acc, N, Gf + m, mmax, part, s);
         k_mirror_cols(Gf, mmax, m, acc, s);
@@ -1116,7 +1135,8 @@ static void ea_density(Arena& ws, const Ctx* c, const double* vec, double* D, hi
 // roots with the same kept count).  U_all[k] holds U of root k as [v][vk_k], e_all[k] its vk_k energies
 // (row stride v), vks[k] the kept count.
 static void natural_orbitals_all(Arena& ws, const double* Dss, const double* ev, int v, double thr, int nr,
-                                 double* U_all, double* e_all, std::vector<int>& vks, hipStream_t s) {
+                                 double* U_all, double* e_all, std::vector<int>& vks, hipStream_t s,
+                                 int keep_n = 0) {
     const long long vv = (long long)v * v;
     const size_t mark = ws.mark();
     double* A = take(ws, nr * vv);
@@ -1133,7 +1153,8 @@ static void natural_orbitals_all(Arena& ws, const double* Dss, const double* ev,
     d2h(hw.data(), w, (size_t)nr * v * sizeof(double), s);
     vks.assign(nr, 0);
     for (int k = 0; k < nr; ++k) {
-        if (g_dry || !(thr > 0)) vks[k] = v;
+        if (g_dry || (keep_n <= 0 && !(thr > 0))) vks[k] = v;
+        else if (keep_n > 0) vks[k] = std::min(keep_n, v);  // a fixed share of the virtuals, largest occupations
         else
             for (int a = 0; a < v; ++a) vks[k] += hw[(size_t)k * v + a] > thr;
     }
@@ -1278,12 +1299,19 @@ struct SolveOut {
     bool all_conv = true;
 };
 
+// Truncation of the virtual space asked for by the options (SS-FNO or MP2-FNO, by threshold or by
+// share of the virtuals) or of the auxiliary basis (NAF)?
+static bool truncates(double fno, double naf, const adc3_opts& op) {
+    return fno > 0 || naf > 0 || op.fno_keep_frac > 0;
+}
+
 static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const Blocks& B0, int nroots, double fno,
                            double naf, double conv, const adc3_opts& op, hipStream_t s) {
     const int o = B0.o, v = B0.v, X = B0.X;
     SolveOut out;
     out.rep.assign(nroots, adc3_root_report{});
     const int level = op.level;
+    const double smx = level >= 3 ? op.sm_x : 1.0;
     // Davidson step per level: ADC(2) solves take the exact 1p block unless Jacobi or Olsen is
     // asked for (their 2p1h block is diagonal, so only the 1p block is approximated by the
     // diagonal step); ADC(3) solves take Jacobi, Olsen, or the learned step
@@ -1292,19 +1320,23 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     // one ladder form for every ADC(3) context of the solve, chosen from the canonical size (so the
     // workspace plan holds for any truncation)
     const bool df = op.ladder == 2 || (op.ladder == 0 && ladder_df_auto(v));
-    if (!(fno > 0) && !(naf > 0)) {
+    const long long N0 = v + (long long)o * v * v, vv0 = (long long)v * v;
+    const int ng = op.init_guess ? (int)std::min<long long>(op.n_guess, N0) : 0;
+    if (!truncates(fno, naf, op)) {
         const size_t mark = ws.mark();
-        Ctx* c = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, level, s, op.precision, df);
+        Ctx* c = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, level, s, op.precision, df, smx);
         c->mlp_w = op.mlp_weights;
         c->graphs = op.sigma_graphs != 0;
-        DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
-                                    op.precond == 1 && level >= 3, nullptr, nullptr, 0, level >= 3 ? pm3 : pm2);
+        DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, op.vectors_out, s,
+                                    op.precision, op.precond == 1 && level >= 3, nullptr, op.init_guess, ng,
+                                    level >= 3 ? pm3 : pm2);
         for (int k = 0; k < nroots; ++k) {
             auto& R = out.rep[k];
             R.omega = R.omega_uncorr = r.w[k];
             R.omega_lowp = r.w_lowp.empty() ? r.w[k] : r.w_lowp[k];
             R.iters_lowp = r.iters_lowp;
             R.resnorm = r.rn[k];
+            R.err_bound = r.rn[k];
             R.nvir_kept = v;
             R.naux_kept = X;
             R.iters = r.iters;
@@ -1315,12 +1347,16 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         ws.release(mark);
         return out;
     }
+    // Natural-orbital bases: one per root from D^SS(k) = D^MP2 + D^EA(k) (state-specific, eq 17), or
+    // one shared by all roots from D^MP2 alone (ground-state MP2-FNO)
+    const bool shared = op.fno_mode == 1;
+    const int nb = shared ? 1 : nroots;
+    const int keep_n = op.fno_keep_frac > 0 ? (int)std::max(1.0, std::ceil(op.fno_keep_frac * v - 1e-9)) : 0;
     // steps 2-3: canonical MP2 density and canonical ADC(2) roots; the canonical context is released
-    // once the state-specific densities D^SS(k) = D^MP2 + D^EA(k) (steps 4a-4b) of all roots are formed
+    // once the densities of all bases (steps 4a-4b) are formed
     const size_t mark0 = ws.mark();
-    const long long N0 = v + (long long)o * v * v, vv0 = (long long)v * v;
     double* Y2 = take(ws, (long long)nroots * N0);
-    double* Dss = take(ws, (long long)nroots * vv0);
+    double* Dss = take(ws, (long long)nb * vv0);
     DavResult r2;
     int sig0 = 0;
     {
@@ -1328,12 +1364,17 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         Ctx* c0 = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, 2, s, op.precision);
         c0->graphs = op.sigma_graphs != 0;
         r2 = davidson_impl(c0, ws, nroots, conv, op.max_iter, op.max_subspace, Y2, s, op.precision, false, nullptr,
-                           nullptr, 0, pm2);
+                           op.init_guess, ng, pm2);
+        if (op.vectors_out) k_copy(op.vectors_out, Y2, (long long)nroots * N0, s);
         GemmScratch gscr(ws, GEMM_SCRATCH);
-        for (int k = 0; k < nroots; ++k) {
-            double* D = Dss + (long long)k * vv0;
-            ea_density(ws, c0, Y2 + (long long)k * N0, D, s);          // 4a
-            k_axpby(D, c0->Dmp2, vv0, 1.0, 1.0, s);                       // 4b
+        for (int b = 0; b < nb; ++b) {
+            double* D = Dss + (long long)b * vv0;
+            if (shared) {
+                k_copy(D, c0->Dmp2, vv0, s);                               // MP2-FNO: D^MP2 only
+            } else {
+                ea_density(ws, c0, Y2 + (long long)b * N0, D, s);          // 4a
+                k_axpby(D, c0->Dmp2, vv0, 1.0, 1.0, s);                     // 4b
+            }
         }
         sig0 = (int)c0->sigma_count;
         delete c0;
@@ -1341,39 +1382,39 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     }
     out.all_conv = out.all_conv && r2.converged;
     VLOG("canonical ADC(2): %d roots, %d iterations, lowest %.10f", nroots, r2.iters, r2.w[0]);
-    // steps 4c-4d for every root: natural orbitals, truncation and recanonicalisation
-    double* U_all = take(ws, (long long)nroots * vv0);
-    double* e_all = take(ws, (long long)nroots * v);
+    // steps 4c-4d for every basis: natural orbitals, truncation and recanonicalisation
+    double* U_all = take(ws, (long long)nb * vv0);
+    double* e_all = take(ws, (long long)nb * v);
     std::vector<int> vks;
-    natural_orbitals_all(ws, Dss, ev, v, fno, nroots, U_all, e_all, vks, s);
+    natural_orbitals_all(ws, Dss, ev, v, fno, nb, U_all, e_all, vks, s, keep_n);
     NafCache naf_cache;
     if (naf > 0) {
         naf_cache.N = take(ws, (long long)X * X);
         naf_cache.w = take(ws, X);
     }
     // the truncated ADC(2) solves precondition with the exact 1p block: the eigendecompositions of the
-    // roots' M11 solved as batches (roots with equal kept counts together) before the per-root solves,
-    // for the roots where that pays and costs no second NAF eigensolver: kept count above the
-    // one-workgroup solver's size and the NAF result shared (nothing truncated) or not asked for
+    // bases' M11 solved as batches (bases with equal kept counts together) before the per-basis solves,
+    // where that pays and costs no second NAF eigensolver: kept count above the one-workgroup solver's
+    // size and the NAF result shared (nothing truncated) or not asked for
     double* m11Q = nullptr;
     double* m11w = nullptr;
-    std::vector<char> m11_pre(nroots, 0);
-    for (int k = 0; k < nroots; ++k) m11_pre[k] = pm2 == 3 && vks[k] > 96 && (!(naf > 0) || vks[k] == v);
+    std::vector<char> m11_pre(nb, 0);
+    for (int b = 0; b < nb; ++b) m11_pre[b] = pm2 == 3 && vks[b] > 96 && (!(naf > 0) || vks[b] == v);
     if (std::count(m11_pre.begin(), m11_pre.end(), 1) >= 2) {
-        m11Q = take(ws, (long long)nroots * vv0);
-        m11w = take(ws, (long long)nroots * v);
+        m11Q = take(ws, (long long)nb * vv0);
+        m11w = take(ws, (long long)nb * v);
         const size_t mm = ws.mark();
-        double* A = take(ws, (long long)nroots * vv0);
-        double* w = take(ws, (long long)nroots * v);
-        double* Q = take(ws, (long long)nroots * vv0);
-        double* scr = take(ws, (long long)eig_batched_scratch(v, nroots));
-        std::vector<char> done(nroots, 0);
-        for (int k0 = 0; k0 < nroots; ++k0) {
-            const int vk = vks[k0];
-            if (done[k0] || !m11_pre[k0]) continue;
+        double* A = take(ws, (long long)nb * vv0);
+        double* w = take(ws, (long long)nb * v);
+        double* Q = take(ws, (long long)nb * vv0);
+        double* scr = take(ws, (long long)eig_batched_scratch(v, nb));
+        std::vector<char> done(nb, 0);
+        for (int b0 = 0; b0 < nb; ++b0) {
+            const int vk = vks[b0];
+            if (done[b0] || !m11_pre[b0]) continue;
             std::vector<int> grp;
-            for (int k = k0; k < nroots; ++k)
-                if (!done[k] && m11_pre[k] && vks[k] == vk) { grp.push_back(k); done[k] = 1; }
+            for (int b = b0; b < nb; ++b)
+                if (!done[b] && m11_pre[b] && vks[b] == vk) { grp.push_back(b); done[b] = 1; }
             const long long kk = (long long)vk * vk;
             for (size_t j = 0; j < grp.size(); ++j) {
                 const size_t mb = ws.mark();
@@ -1393,26 +1434,29 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         }
         ws.release(mm);
     }
-    // step 4: per root
-    for (int k = 0; k < nroots; ++k) {
+    // step 4 per basis: the roots it serves (root b for a state-specific basis, all for a shared one)
+    for (int b = 0; b < nb; ++b) {
         const size_t mark = ws.mark();
-        auto& R = out.rep[k];
         GemmScratch gscr(ws, GEMM_SCRATCH);
-        R.omega_adc2_can = r2.w[k];
-        const double* U = U_all + (long long)k * vv0;
-        const double* enew = e_all + (long long)k * v;
-        const int vk = vks[k];                                        // 4c-4d
+        std::vector<int> ks;
+        if (shared)
+            for (int k = 0; k < nroots; ++k) ks.push_back(k);
+        else
+            ks.push_back(b);
+        const double* U = U_all + (long long)b * vv0;
+        const double* enew = e_all + (long long)b * v;
+        const int vk = vks[b];                                        // 4c-4d
         if (vk < 1) fail(ADC3_EINVAL, "SS-FNO threshold removes every virtual orbital");
         Blocks Bt;
         transform_blocks(B0, U, vk, Bt, ws, s);
         Blocks Bn = Bt;
         int xk = X;
         if (naf > 0) xk = naf_blocks(Bt, naf, Bn, ws, s, vk == v ? &naf_cache : nullptr);  // 4e
-        VLOG("root %d: kept %d virtuals, %d auxiliary functions", k, vk, xk);
+        VLOG("basis %d: kept %d virtuals, %d auxiliary functions", b, vk, xk);
         const long long Nk = vk + (long long)o * vk * vk;
         if (nroots > Nk) fail(ADC3_EINVAL, "truncated space smaller than nroots");
         int sig = 0;
-        int match = k;
+        std::vector<int> match(nroots, 0);
         // the canonical ADC(2) vectors carried into the truncated basis (r1 U, U^T z_i U): vector k is
         // the reference for root matching, all of them start the truncated ADC(2) solve, whose vectors
         // in turn start the truncated ADC(3) solve
@@ -1436,31 +1480,36 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             }
             ws.release(mt);
         }
+        DavResult a2;
         {
-            const double* ref = carried + (long long)k * Nk;
-            double* ovl = take(ws, 64);
-            double* part = take(ws, (long long)dots_partial_elems(nroots, 1, Nk));
+            double* ovl = take(ws, (long long)nroots * nroots);
+            double* part = take(ws, (long long)dots_partial_elems(nroots, nroots, Nk));
             const size_t m2 = ws.mark();
             Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s, op.precision);
             c2->graphs = op.sigma_graphs != 0;
-            if (m11Q && m11_pre[k]) {
-                k_copy(c2->m11_Q, m11Q + (long long)k * vv0, (long long)vk * vk, s);
-                k_copy(c2->m11_w, m11w + (long long)k * v, vk, s);
+            if (m11Q && m11_pre[b]) {
+                k_copy(c2->m11_Q, m11Q + (long long)b * vv0, (long long)vk * vk, s);
+                k_copy(c2->m11_w, m11w + (long long)b * v, vk, s);
                 c2->m11_eig = true;
             }
-            DavResult a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s, op.precision,
-                                         false, nullptr, carried, nroots, pm2);
-            k_dots(Y2k, Nk, nroots, ref, Nk, 1, Nk, ovl, 1, part, s);
-            std::vector<double> hov(nroots);
-            d2h(hov.data(), ovl, nroots * sizeof(double), s);
-            if (!g_dry) {
-                match = 0;
-                for (int q = 1; q < nroots; ++q)
-                    if (std::fabs(hov[q]) > std::fabs(hov[match])) match = q;
+            a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s, op.precision, false,
+                               nullptr, carried, nroots, pm2);
+            // overlaps of the truncated ADC(2) vectors with every carried canonical vector: ovl[k][q]
+            k_dots(carried, Nk, nroots, Y2k, Nk, nroots, Nk, ovl, nroots, part, s);
+            std::vector<double> hov((size_t)nroots * nroots);
+            d2h(hov.data(), ovl, hov.size() * sizeof(double), s);
+            for (int k : ks) {
+                match[k] = k;
+                if (!g_dry) {
+                    int m = 0;
+                    for (int q = 1; q < nroots; ++q)
+                        if (std::fabs(hov[(size_t)k * nroots + q]) > std::fabs(hov[(size_t)k * nroots + m])) m = q;
+                    match[k] = m;
+                }
+                out.rep[k].omega_adc2_fno = a2.w[match[k]];
+                VLOG("root %d: truncated ADC(2) %d iterations, matched root %d (overlap %.4f)", k, a2.iters,
+                     match[k], std::fabs(hov[(size_t)k * nroots + match[k]]));
             }
-            R.omega_adc2_fno = a2.w[match];
-            VLOG("root %d: truncated ADC(2) %d iterations, matched root %d (overlap %.4f)", k, a2.iters, match,
-                 std::fabs(hov[match]));
             out.all_conv = out.all_conv && a2.converged;
             sig += (int)c2->sigma_count;
             delete c2;
@@ -1468,31 +1517,40 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         }
         {
             const size_t m3 = ws.mark();
-            Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s, op.precision, df);
+            Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s, op.precision, df, smx);
             c3->mlp_w = op.mlp_weights;
             c3->graphs = op.sigma_graphs != 0;
-            // only roots 0..match of this basis are needed: the matched one and those below it
-            const int nr3 = std::min(nroots, match + 1);
+            // only the roots up to the highest matched one of this basis are needed
+            int mmax = 0;
+            for (int k : ks) mmax = std::max(mmax, match[k]);
+            const int nr3 = std::min(nroots, mmax + 1);
             DavResult a3 = davidson_impl(c3, ws, nr3, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
                                          op.precond == 1, nullptr, Y2k, nroots, level >= 3 ? pm3 : pm2);
-            R.omega_uncorr = a3.w[match];
-            R.omega_lowp = a3.w_lowp.empty() ? a3.w[match] : a3.w_lowp[match];
-            R.iters_lowp = a3.iters_lowp;
-            VLOG("root %d: truncated ADC(3) %d iterations, omega %.10f, |r| %.2e", k, a3.iters, a3.w[match],
-                 a3.rn[match]);
-            R.resnorm = a3.rn[match];
-            R.iters = a3.iters;
+            for (int k : ks) {
+                auto& R = out.rep[k];
+                const int m = match[k];
+                R.omega_adc2_can = r2.w[k];
+                R.omega_uncorr = a3.w[m];
+                R.omega_lowp = a3.w_lowp.empty() ? a3.w[m] : a3.w_lowp[m];
+                R.iters_lowp = a3.iters_lowp;
+                VLOG("root %d: truncated ADC(3) %d iterations, omega %.10f, |r| %.2e", k, a3.iters, a3.w[m], a3.rn[m]);
+                R.resnorm = a3.rn[m];
+                R.iters = a3.iters;
+                R.nvir_kept = vk;
+                R.naux_kept = xk;
+                R.omega = R.omega_uncorr + (op.fno_correction ? (R.omega_adc2_can - R.omega_adc2_fno) : 0.0);  // eq 30
+                // each of the three eigenvalues lies within its residual norm of an eigenvalue of its matrix
+                R.err_bound = a3.rn[m] + (op.fno_correction ? r2.rn[k] + a2.rn[m] : 0.0);
+            }
             out.all_conv = out.all_conv && a3.converged;
             sig += (int)c3->sigma_count;
             delete c3;
             ws.release(m3);
         }
-        R.nvir_kept = vk;
-        R.naux_kept = xk;
-        R.sigma_builds = sig + (k == 0 ? sig0 : 0);
-        R.omega = R.omega_uncorr + (op.fno_correction ? (R.omega_adc2_can - R.omega_adc2_fno) : 0.0);  // eq 30
+        for (size_t j = 0; j < ks.size(); ++j) out.rep[ks[j]].sigma_builds = j == 0 ? sig : 0;
         ws.release(mark);
     }
+    out.rep[0].sigma_builds += sig0;
     ws.release(mark0);
     return out;
 }
@@ -1507,6 +1565,10 @@ using namespace adc3;
 struct adc3_ctx {
     Ctx* c;
 };
+
+static int setup_impl(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir, int naux,
+                      int level, int precision, int ladder, double smx, void* workspace, size_t ws_bytes,
+                      hipStream_t stream, adc3_ctx** ctx_out);
 
 #define API_BEGIN try {
 #define API_END                                   \
@@ -1535,6 +1597,12 @@ void adc3_default_opts(adc3_opts* o) {
     o->mlp_weights = nullptr;
     o->sigma_graphs = 0;
     o->ladder = 0;
+    o->sm_x = 1.0;
+    o->fno_mode = 0;
+    o->fno_keep_frac = 0.0;
+    o->init_guess = nullptr;
+    o->n_guess = 0;
+    o->vectors_out = nullptr;
 }
 
 const char* adc3_last_error(void) { return g_msg.c_str(); }
@@ -1587,6 +1655,17 @@ int adc3_ea_setup_ex(const double* eps_occ, const double* eps_vir, const double*
                      int level, int precision, int ladder, void* workspace, size_t ws_bytes, hipStream_t stream,
                      adc3_ctx** ctx_out) {
     API_BEGIN
+    return setup_impl(eps_occ, eps_vir, B, nocc, nvir, naux, level, precision, ladder, 1.0, workspace, ws_bytes,
+                      stream, ctx_out);
+    API_END
+}
+
+}  // extern "C"
+
+static int setup_impl(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir, int naux,
+                      int level, int precision, int ladder, double smx, void* workspace, size_t ws_bytes,
+                      hipStream_t stream, adc3_ctx** ctx_out) {
+    {
     if (!ctx_out) fail(ADC3_EINVAL, "ctx_out is NULL");
     *ctx_out = nullptr;
     check_dims(nocc, nvir, naux);
@@ -1606,12 +1685,24 @@ int adc3_ea_setup_ex(const double* eps_occ, const double* eps_vir, const double*
     double* Bvv = take(ws, (long long)naux * nvir * nvir);
     k_split_B(B, naux, nocc, nvir, Boo, Bov, Bvv, stream);
     (void)n;
-    Ctx* c = build_ctx(ws, eps_occ, eps_vir, Boo, Bov, Bvv, nocc, nvir, naux, level, stream, precision, df);
+    Ctx* c = build_ctx(ws, eps_occ, eps_vir, Boo, Bov, Bvv, nocc, nvir, naux, level, stream, precision, df, smx);
     (void)mark0;
     HIPCHK(hipStreamSynchronize(stream));
     adc3_ctx* h = new adc3_ctx{c};
     *ctx_out = h;
     return ADC3_OK;
+    }
+}
+
+extern "C" {
+
+int adc3_ea_setup_sm(const double* eps_occ, const double* eps_vir, const double* B, int nocc, int nvir, int naux,
+                     double sm_x, int precision, int ladder, void* workspace, size_t ws_bytes, hipStream_t stream,
+                     adc3_ctx** ctx_out) {
+    API_BEGIN
+    if (!(sm_x >= 0.0 && sm_x <= 1.0)) fail(ADC3_EINVAL, "sm_x must lie in [0, 1]");
+    return setup_impl(eps_occ, eps_vir, B, nocc, nvir, naux, 3, precision, ladder, sm_x, workspace, ws_bytes, stream,
+                      ctx_out);
     API_END
 }
 
@@ -1651,16 +1742,24 @@ int adc3_ea_diagonal(adc3_ctx* ctx, double* diag, hipStream_t stream) {
 
 int adc3_ea_davidson(adc3_ctx* ctx, int nroots, double conv, int max_iter, int max_subspace, int precision,
                      double* omega, double* vectors, double* resnorm, int* iters, hipStream_t stream) {
+    return adc3_ea_davidson_guess(ctx, nroots, conv, max_iter, max_subspace, precision, nullptr, 0, omega, vectors,
+                                  resnorm, iters, stream);
+}
+
+int adc3_ea_davidson_guess(adc3_ctx* ctx, int nroots, double conv, int max_iter, int max_subspace, int precision,
+                           const double* guess, int n_guess, double* omega, double* vectors, double* resnorm,
+                           int* iters, hipStream_t stream) {
     API_BEGIN
     if (!ctx || !omega) fail(ADC3_EINVAL, "NULL argument");
     if (!(conv > 0)) fail(ADC3_EINVAL, "conv must be > 0");
     if (nroots < 1 || nroots > ctx->c->N) fail(ADC3_EINVAL, "nroots out of range");
     if (max_iter < 1) fail(ADC3_EINVAL, "max_iter must be >= 1");
+    if (n_guess < 0 || (n_guess > 0 && !guess)) fail(ADC3_EINVAL, "n_guess > 0 needs guess vectors");
     if (precision != 0 && precision != ctx->c->prec)
         fail(ADC3_EINVAL, "precision must be 0 (FP64) or the context's setup precision");
     Arena ws = ctx->c->ws;
     DavResult r = davidson_impl(ctx->c, ws, nroots, conv, max_iter, max_subspace, vectors, stream, precision,
-                                ctx->c->mlp_w != nullptr);
+                                ctx->c->mlp_w != nullptr, nullptr, guess, n_guess);
     for (int k = 0; k < nroots; ++k) {
         omega[k] = r.w[k];
         if (resnorm) resnorm[k] = r.rn[k];
@@ -1866,6 +1965,10 @@ static adc3_opts resolve_opts(const adc3_opts* opts) {
         fail(ADC3_EUNSUP, "opts.precond must be 0 (Jacobi), 1 (learned), 2 (Olsen) or 3 (exact 1p block)");
     if (o.precond == 1 && !o.mlp_weights) fail(ADC3_EINVAL, "opts.precond = 1 needs opts.mlp_weights");
     if (o.ladder < 0 || o.ladder > 2) fail(ADC3_EINVAL, "opts.ladder must be 0 (auto), 1 (stored) or 2 (assembled)");
+    if (!(o.sm_x >= 0.0 && o.sm_x <= 1.0)) fail(ADC3_EINVAL, "opts.sm_x must lie in [0, 1]");
+    if (o.fno_mode != 0 && o.fno_mode != 1) fail(ADC3_EINVAL, "opts.fno_mode must be 0 (state-specific) or 1 (MP2)");
+    if (!(o.fno_keep_frac >= 0.0 && o.fno_keep_frac <= 1.0)) fail(ADC3_EINVAL, "opts.fno_keep_frac must lie in [0, 1]");
+    if (o.n_guess < 0 || (o.n_guess > 0 && !o.init_guess)) fail(ADC3_EINVAL, "opts.n_guess > 0 needs opts.init_guess");
     return o;
 }
 
@@ -2080,6 +2183,8 @@ extern "C" int adc3_ea_solve_batched(const adc3_instance* inst, int ninst, const
     return worst;
     API_END
 }
+
+extern "C" void adc3_debug_inject_nan(int iteration) { g_nan_at.store(std::max(iteration, 0)); }
 
 extern "C" int adc3_ea_set_sigma_graphs(adc3_ctx* ctx, int on) {
     API_BEGIN

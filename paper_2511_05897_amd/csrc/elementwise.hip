@@ -344,7 +344,7 @@ __global__ void add_diag_kernel(double* A, const double* d, int n) {
 // diag[0..v) = diag(M11); diag[v + (i*v + a)*v + b] = K0 + (level>=3) K1 diagonal in z coordinates
 __global__ void diag_adc_kernel(double* diag, const double* M11, const double* eo, const double* ev,
                                 const double* Bvv, const double* oovv, const double* ovov, int o, int v,
-                                int X, int level) {
+                                int X, int level, double x1) {
     const double s3 = 1.73205080756887729353;
     long long vv = (long long)v * v;
     GRID_STRIDE(t, vv) {
@@ -369,13 +369,13 @@ __global__ void diag_adc_kernel(double* diag, const double* M11, const double* e
                 double aiia = ovov[(((long long)i * v + a) * o + i) * v + a];
                 double biib = ovov[(((long long)i * v + b) * o + i) * v + b];
                 if (a == b) {
-                    d += aabb - 2.0 * aaii + aiia;
+                    d += x1 * (aabb - 2.0 * aaii + aiia);
                 } else {
                     double kabab = aabb - bbii - aaii + 2.0 * biib;
                     double kbaba = aabb - aaii - bbii + 2.0 * aiia;
                     double kabba = abab - biib;
                     double kbaab = abab - aiia;
-                    d += al * ga * kabab + al * de * kabba + be * ga * kbaab + be * de * kbaba;
+                    d += x1 * (al * ga * kabab + al * de * kabba + be * ga * kbaab + be * de * kbaba);
                 }
             }
             diag[v + ((long long)i * v + a) * v + b] = d;
@@ -626,12 +626,12 @@ void k_add_diag(double* A, const double* d, int n, hipStream_t s) {
     LAUNCHCHK();
 }
 void k_diag_adc(double* diag, const double* M11, const double* eo, const double* ev, const double* Bvv,
-                const double* oovv, const double* ovov, int o, int v, int X, int level, hipStream_t s) {
+                const double* oovv, const double* ovov, int o, int v, int X, int level, hipStream_t s, double x1) {
     if (g_dry) return;
     long long n = (long long)v * v;
     if (n <= 0) return;
     hipLaunchKernelGGL(diag_adc_kernel, dim3(nblocks(n)), dim3(NT), 0, s, diag, M11, eo, ev, Bvv, oovv, ovov, o,
-                       v, X, level);
+                       v, X, level, x1);
     LAUNCHCHK();
 }
 

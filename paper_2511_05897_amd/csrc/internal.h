@@ -226,8 +226,10 @@ void k_symmetrize(double* A, int n, hipStream_t s);   // A = (A + A^T)/2
 // G[(m0+j)*ld + i] = G[i*ld + m0 + j] for i < m0 + nc, j < nc  (new columns mirrored into rows)
 void k_mirror_cols(double* G, int ld, int m0, int nc, hipStream_t s);
 void k_add_diag(double* A, const double* d, int n, hipStream_t s);
+// diagonal of M; x1 scales the first-order 2p1h terms (level 3; sm-ADC)
 void k_diag_adc(double* diag, const double* M11, const double* eo, const double* ev, const double* Bvv,
-                const double* oovv, const double* ovov, int o, int v, int X, int level, hipStream_t s);
+                const double* oovv, const double* ovov, int o, int v, int X, int level, hipStream_t s,
+                double x1 = 1.0);
 
 // ---------------------------------------------------------------------------
 // reductions (deterministic, FP64)

@@ -1,0 +1,149 @@
+"""The boundary's options and failure paths through the C ABI, against the FP64 oracle:
+
+* scaled-matrix ADC (sm_x; the equation after eq 5): sigma and diagonal of an sm context, roots of
+  canonical and truncated solves, and its limits (x = 0 gives ADC(2), x = 1 ADC(3));
+* ground-state MP2-FNO (fno_mode 1) and the percentage-of-virtuals truncation (fno_keep_frac);
+* caller guesses and Ritz vectors out (resume after an unconverged run), max_iter = 1 -> ADC3_WNOCONV,
+  a NaN injected into a sigma vector -> ADC3_ENUMERIC;
+* the per-root error bound: |omega - omega_oracle| <= err_bound (FP64 and mixed precision).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ssfno
+from oracle.adc_cs import Problem
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2511_05897_amd as adc  # noqa: E402
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.mark.parametrize("x", [0.0, 0.5, 0.8])
+@pytest.mark.parametrize("ladder", [1, 2])
+def test_sm_sigma_and_diagonal(x, ladder):
+    eo, ev, B = synth.make_instance(4, 17, 40, 5, scale=0.3)
+    P = Problem(eo, ev, B)
+    r = np.random.default_rng(2).standard_normal((6, P.dim()))
+    ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, sm_x=x, ladder=ladder)
+    assert relerr(host(ctx.sigma(dev(r))), P.sigma_sm(r, x)) < 1e-11
+    assert relerr(host(ctx.diagonal()), P.diagonal_sm(x)) < 1e-11
+    ctx.close()
+
+
+def test_sm_solves_match_oracle():
+    p, eo, ev, B = synth.preset("tiny-dense")
+    P = Problem(eo, ev, B)
+    o = adc.adc3_default_opts()
+    for x in (0.0, 0.5, 1.0):
+        o.sm_x = x
+        roots, reps, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-8, opts=o)
+        ref = np.linalg.eigvalsh(P.dense_sm(x))[:3]
+        assert st == adc.ADC3_OK and np.abs(roots - ref).max() < 1e-8, x
+    ref2 = np.linalg.eigvalsh(P.dense(2))[:3]
+    o.sm_x = 0.0
+    roots, _, _ = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-8, opts=o)
+    assert np.abs(roots - ref2).max() < 1e-8
+    # truncated pipeline with the sm final level
+    eo, ev, B = synth.make_instance(3, 10, 24, 8, scale=0.3)
+    refp = ssfno.run(eo, ev, B, 3, 1e-4, 1e-2, 1e-9, sm_x=0.5)
+    o.sm_x = 0.5
+    roots, reps, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 1e-4, 1e-2, 1e-9, opts=o)
+    assert st == adc.ADC3_OK
+    assert [r["nvir_kept"] for r in reps] == list(refp["nvir_kept"])
+    assert np.abs(roots - refp["roots"]).max() < 1e-8
+
+
+@pytest.mark.parametrize("mode,frac,thr", [(1, 0.0, 1e-4), (1, 0.55, 0.0), (0, 0.55, 0.0), (1, 0.4, 0.0)])
+def test_mp2_fno_and_share_of_virtuals(mode, frac, thr):
+    eo, ev, B = synth.make_instance(3, 10, 24, 8, scale=0.3)
+    refp = ssfno.run(eo, ev, B, 3, thr, 1e-2, 1e-9, fno_mode="mp2" if mode == 1 else "ss", keep_frac=frac)
+    o = adc.adc3_default_opts()
+    o.fno_mode, o.fno_keep_frac = mode, frac
+    roots, reps, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, thr, 1e-2, 1e-9, opts=o)
+    assert st == adc.ADC3_OK
+    assert [r["nvir_kept"] for r in reps] == list(refp["nvir_kept"])
+    assert [r["naux_kept"] for r in reps] == list(refp["naux_kept"])
+    assert np.abs(roots - refp["roots"]).max() < 1e-8
+    assert np.abs(np.array([r["omega_adc2_fno"] for r in reps]) - refp["omega_adc2_fno"]).max() < 1e-8
+
+
+def test_max_iter_one_is_not_converged_and_resume_reaches_the_roots():
+    p, eo, ev, B = synth.preset("tiny-dense")
+    ref = np.linalg.eigvalsh(Problem(eo, ev, B).dense(3))[:3]
+    N = 20 + 4 * 20 * 20
+    vec = torch.zeros((3, N), dtype=torch.float64, device="cuda")
+    o = adc.adc3_default_opts()
+    o.max_iter = 1
+    roots, reps, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-8, opts=o)
+    assert st == adc.ADC3_WNOCONV and np.all(np.isfinite(roots))
+    fresh, frep, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-8)
+    assert st == adc.ADC3_OK
+    o.max_iter = 6
+    o.vectors_out = vec.data_ptr()
+    r6, rep6, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-8, opts=o)
+    assert st == adc.ADC3_WNOCONV
+    assert np.abs(host(vec)).max() > 0  # Ritz vectors of the unconverged run
+    o2 = adc.adc3_default_opts()
+    o2.init_guess, o2.n_guess = vec.data_ptr(), 3
+    res, rrep, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-8, opts=o2)
+    assert st == adc.ADC3_OK and np.abs(res - ref).max() < 1e-8
+    assert rrep[0]["iters"] < frep[0]["iters"], (rrep[0]["iters"], frep[0]["iters"])
+    # the same through the context API
+    ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, nroots=3)
+    w, V, rn, it, st = ctx.davidson(3, 1e-8, max_iter=5, want_vectors=True)
+    assert st == adc.ADC3_WNOCONV
+    w2, V2, rn2, it2, st = ctx.davidson(3, 1e-8, want_vectors=True, guess=V)
+    w0, _, _, it0, _ = ctx.davidson(3, 1e-8)
+    assert st == adc.ADC3_OK and np.abs(w2 - ref).max() < 1e-8 and it2 < it0
+    ctx.close()
+
+
+def test_injected_nan_is_a_numeric_error():
+    p, eo, ev, B = synth.preset("tiny-dense")
+    adc.adc3_debug_inject_nan(2)
+    try:
+        with pytest.raises(adc.ADCError) as e:
+            adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-8)
+        assert e.value.status == adc.ADC3_ENUMERIC
+    finally:
+        adc.adc3_debug_inject_nan(0)
+    roots, _, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 0.0, 0.0, 1e-8)
+    assert st == adc.ADC3_OK
+    ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, nroots=3)
+    adc.adc3_debug_inject_nan(3)
+    try:
+        with pytest.raises(adc.ADCError) as e:
+            ctx.davidson(3, 1e-8)
+        assert e.value.status == adc.ADC3_ENUMERIC
+    finally:
+        adc.adc3_debug_inject_nan(0)
+        ctx.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_error_bound_holds(prec):
+    eo, ev, B = synth.make_instance(3, 10, 24, 8, scale=0.3)
+    refp = ssfno.run(eo, ev, B, 3, 1e-4, 1e-2, 1e-10)
+    o = adc.adc3_default_opts()
+    o.precision = prec
+    for conv in (1e-4, 1e-7):
+        roots, reps, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, 1e-4, 1e-2, conv, opts=o)
+        assert st == adc.ADC3_OK
+        for k, r in enumerate(reps):
+            assert 0 < r["err_bound"] <= 3 * conv + 1e-12
+            assert abs(roots[k] - refp["roots"][k]) <= r["err_bound"] + 1e-12, (conv, k)

@@ -211,3 +211,48 @@ def test_root_matching_follows_the_state_through_reordering():
     w2, w2k, m_full, m_1p, r1n, _ = _matching_detail(2, 8, 16, 7, 0.1, 1e-4, 1)
     assert r1n < 0.05 and m_full == 1 and m_1p != m_full
     assert abs(w2k[m_full] - w2[1]) < 1e-3 < abs(w2k[m_1p] - w2[1])
+
+
+@pytest.mark.parametrize("case", [(2, 3, 6, 5, 0.4), (1, 4, 5, 7, 0.6)])
+def test_sm_adc_against_intermediate_states(case):
+    """Scaled-matrix ADC (the equation after eq 5; reading M_ADC(2) + x (M_ADC(3) - M_ADC(2))): the
+    oracle's matrix equals C^T [M2 + x (M3 - M2)] C with M2, M3 the order-truncated intermediate-state
+    matrices of tier 0 (x = 0 gives ADC(2), x = 1 ADC(3), as the paper states), and the part x scales is
+    exactly M11 at third order, the coupling at second order and the 2p1h block at first order."""
+    o, v = case[0], case[1]
+    eo, ev, B, isr, P = _tier0(*case)
+    C = adc_so.doublet_embedding(o, v)
+    M2, M3 = isr.adc_matrix(2), isr.adc_matrix(3)
+    n1 = 2 * v
+    third = np.zeros_like(M2)
+    third[:n1, :n1] = isr.M[3][:n1, :n1]
+    third[:n1, n1:] = isr.M[2][:n1, n1:]
+    third[n1:, :n1] = isr.M[2][n1:, :n1]
+    third[n1:, n1:] = isr.M[1][n1:, n1:]
+    assert np.abs((M3 - M2) - third).max() < 1e-14
+    for x in (0.0, 0.5, 0.3, 1.0):
+        ref = C.T @ (M2 + x * third) @ C
+        assert np.abs(P.dense_sm(x).T - ref).max() < 1e-12
+        assert np.abs(P.diagonal_sm(x) - np.diag(ref)).max() < 1e-12
+    assert np.abs(P.dense_sm(0.0) - P.dense(2)).max() < 1e-13
+    assert np.abs(P.dense_sm(1.0) - P.dense(3)).max() < 1e-13
+
+
+def test_mp2_fno_and_share_of_virtuals():
+    """Ground-state MP2-FNO: every root in the one basis of D^MP2; the percentage-of-virtuals truncation
+    keeps ceil(frac v) orbitals; nothing truncated reproduces canonical ADC(3); the shared basis equals the
+    state-specific pipeline run on D^MP2 alone (here: same kept counts for all roots)."""
+    eo, ev, B = synth.make_instance(3, 10, 24, 8, 0.3)
+    can = ssfno.run(eo, ev, B, 3, 0.0, 0.0, 1e-9)["roots"]
+    r = ssfno.run(eo, ev, B, 3, 1e-300, 0.0, 1e-9, fno_mode="mp2")
+    assert r["nvir_kept"] == [10] * 3 and np.abs(r["roots"] - can).max() < 1e-10
+    r = ssfno.run(eo, ev, B, 3, 0.0, 0.0, 1e-9, keep_frac=1.0)
+    assert r["nvir_kept"] == [10] * 3 and np.abs(r["roots"] - can).max() < 1e-10
+    r = ssfno.run(eo, ev, B, 3, 0.0, 0.0, 1e-9, fno_mode="mp2", keep_frac=0.55)
+    assert r["nvir_kept"] == [6] * 3
+    U, e, eta, k = ssfno.natural_orbitals(Problem(eo, ev, B).mp2_density_vv(), ev, 0.0, 6)
+    assert k == 6 and np.all(eta[:6] >= eta[6:].max())
+    s = ssfno.run(eo, ev, B, 3, 0.0, 0.0, 1e-9, keep_frac=0.55)
+    assert s["nvir_kept"] == [6] * 3
+    # the state-specific densities pick other orbitals than D^MP2 alone
+    assert np.abs(np.array(s["roots"]) - np.array(r["roots"])).max() > 1e-8
