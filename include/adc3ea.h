@@ -240,6 +240,19 @@ size_t adc3_ladder_workspace_bytes(int nvir, int naux, int nrows, int precision)
 int adc3_ladder_apply(const double* Bvv_dev, const double* Z_dev, double* C_dev, int nvir, int naux, int nrows,
                       int precision, void* workspace_dev, size_t workspace_bytes, hipStream_t stream);
 
+/* The same ladder term for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): identical arguments and results,
+ * with no workspace argument.  Its scratch (the rounded copies of Bvv and Z for precision 1 / 2 and
+ * the intermediate) is one static device array of ADC3_STATIC_SCRATCH_BYTES per GPU, held from the
+ * library's first use on that GPU until the process ends; the call makes no allocation of any kind.
+ * Shapes whose adc3_ladder_workspace_bytes exceeds ADC3_STATIC_SCRATCH_BYTES return ADC3_ENOMEM
+ * before any launch.  Every call on one GPU shares that GPU's array: calls that overlap on a GPU
+ * (other streams, other host threads) race and must be serialised by the caller.  Stream-ordered,
+ * asynchronous. */
+#define ADC3_STATIC_SCRATCH_BYTES (256u << 20)
+int adc3_ladder_apply_static(const double* Bvv_dev, const double* Z_dev, double* C_dev, int nvir, int naux,
+                             int nrows, int precision, hipStream_t stream);
+
 /* Symmetric eigensolver of the natural-orbital and natural-auxiliary-function steps (Sec.
  * "Frozen Natural Orbitals", eq 9 and the recanonicalisation of eqs 12-13; Sec. "Natural
  * Auxiliary Functions", eq 28): FP64 cyclic Jacobi.  A_dev[n][n] device, row-major, read only

@@ -27,9 +27,11 @@ EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_byte
            "adc3_ea_solve_batched", "adc3_ea_set_sigma_graphs", "adc3_profile_query_bound",
            "adc3_ea_setup_workspace_bytes_ex", "adc3_ea_setup_ex", "adc3_set_chunk_elems",
            "adc3_ladder_workspace_bytes", "adc3_ladder_apply", "adc3_eigh_workspace_bytes", "adc3_eigh",
-           "adc3_eigh_batched_workspace_bytes", "adc3_eigh_batched",
+           "adc3_eigh_batched_workspace_bytes", "adc3_eigh_batched", "adc3_ladder_apply_static",
            "adc3_ea_davidson_guess", "adc3_ea_setup_sm", "adc3_debug_inject_nan"]
 
+# size of the static device scratch of adc3_ladder_apply_static (ADC3_STATIC_SCRATCH_BYTES)
+STATIC_SCRATCH_BYTES = 256 << 20
 
 
 class adc3_opts(ctypes.Structure):
@@ -102,6 +104,8 @@ def load():
     lib.adc3_eigh_batched.argtypes = [P, P, P, I, I, P, S, P]
     lib.adc3_eigh_batched.restype = I
     lib.adc3_ladder_apply.restype = I
+    lib.adc3_ladder_apply_static.argtypes = [P, P, P, I, I, I, I, P]
+    lib.adc3_ladder_apply_static.restype = I
     lib.adc3_ctx_destroy.argtypes = [P]
     lib.adc3_ctx_destroy.restype = None
     lib.adc3_ea_dim.argtypes = [P]
@@ -293,6 +297,18 @@ def adc3_ladder_apply(Bvv, Z, precision=0, out=None, workspace=None, workspace_b
         workspace = _workspace(workspace_bytes)
     _check(load().adc3_ladder_apply(_ptr(Bvv), _ptr(Z), _ptr(out), v, X, M, precision,
                                     ctypes.c_void_p(workspace.data_ptr()), workspace.numel(), _stream()))
+    return out
+
+
+def adc3_ladder_apply_static(Bvv, Z, precision=0, out=None):
+    """The same ladder as adc3_ladder_apply with the library's static device scratch (no allocation by
+    the library; calls on one GPU must not overlap)."""
+    import torch
+    X, v = int(Bvv.shape[0]), int(Bvv.shape[1])
+    M = int(Z.shape[0])
+    if out is None:
+        out = torch.empty_like(Z)
+    _check(load().adc3_ladder_apply_static(_ptr(Bvv), _ptr(Z), _ptr(out), v, X, M, precision, _stream()))
     return out
 
 

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libadc3ea.so")
-SOURCES = ["gemm.hip", "elementwise.hip", "jacobi.hip", "reduce.hip", "tensor.hip", "adc.hip", "profile.hip", "gemm_lp.hip", "mlp.hip", "ladder.hip", "dfladder.hip", "ladder_sa.hip", "ladder_form.hip"]
+SOURCES = ["gemm.hip", "elementwise.hip", "jacobi.hip", "reduce.hip", "tensor.hip", "adc.hip", "profile.hip", "gemm_lp.hip", "mlp.hip", "ladder.hip", "dfladder.hip", "ladder_sa.hip", "ladder_form.hip", "static_scratch.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # packed FP32 instructions are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
