@@ -99,6 +99,10 @@ typedef struct {
                              resuming from vectors_out of an unconverged run reaches the same roots */
     int n_guess;          /* number of init_guess vectors (0 default) */
     double* vectors_out;  /* device [nroots][N], nullable: the Ritz vectors of that canonical-basis solve */
+    double* dyson_out;    /* device [nroots][nocc+nvir], nullable: spectral amplitudes x_kp = sum_A Y_Ak f_Ap
+                             (eqs 7-8) of each reported root in the canonical MO basis (occupied first),
+                             i.e. the Dyson-orbital coefficients; each vector's largest-magnitude entry made
+                             positive.  See adc3_ea_spectral_amplitudes for f. */
 } adc3_opts;
 
 /* Per-root report of adc3_ea_solve. */
@@ -120,6 +124,7 @@ typedef struct {
                               an eigenvalue of its matrix (symmetric M), so their sum bounds the error; in
                               every precision the last Davidson phase runs FP64 sigma, so it also bounds the
                               mixed-precision result's distance from the FP64 one */
+    double pole_strength;  /* sum_p x_kp^2 of the root's spectral amplitudes (eq 7) */
 } adc3_root_report;
 
 void adc3_default_opts(adc3_opts* opts);
@@ -303,6 +308,14 @@ int adc3_ea_davidson(adc3_ctx* ctx, int nroots, double conv, int max_iter, int m
 int adc3_ea_davidson_guess(adc3_ctx* ctx, int nroots, double conv, int max_iter, int max_subspace,
                            int precision, const double* guess_dev, int n_guess, double* omega,
                            double* vectors_dev, double* resnorm, int* iters, hipStream_t stream);
+
+/* Spectral amplitudes (eqs 7-8) of nvec vectors vecs_dev[nvec][N] of the context's space (device):
+ * x_dev[nvec][nocc+nvir] (device, occupied orbitals first), x_kp = sum_A Y_kA f_Ap with
+ * f_Ap = <Psi~_A| c+_p |Psi0> for p of the attached electron's spin, kept through second order in the
+ * 1p rows and first order in the 2p1h rows:  f_ab = delta_ab - D^MP2_ab / 2,  f_aj = -u1_ja (second-
+ * order singles),  f_(iab),j = -[(S + sqrt3 A) T_ji]_ab (z coordinates), f_(iab),b' = 0.  No sign fixing. */
+int adc3_ea_spectral_amplitudes(adc3_ctx* ctx, const double* vecs_dev, int nvec, double* x_dev,
+                                hipStream_t stream);
 
 /* Test hook of the error path: the next Davidson iteration >= iteration (> 0) on any context writes
  * NaN into one new sigma vector, once; that solve then returns ADC3_ENUMERIC.  0 disarms. */

@@ -307,6 +307,29 @@ class Problem:
         return self.sigma(np.eye(n), level)
 
     # ------------------------------------------------------------------
+    # spectral amplitudes (eqs 7-8): x = Y^T f, f_Ap = <Psi~_A| c+_p |Psi0>, p an alpha spin-orbital
+    # (the doublet states here have M_s = +1/2).  f is kept through second order in the 1p block and
+    # first order in the 2p1h block (the orders of ADC(2)'s transition amplitudes); its closed forms
+    # were read off the intermediate states of tier 0 order by order:
+    #   f[a, b] = delta_ab - D^MP2_ab / 2           (b virtual; D per spin)
+    #   f[a, j] = -u1[j, a]                          (j occupied; u1 the second-order singles)
+    #   f[(i,a,b), j] = -(S + sqrt3 A)(T[j,i])_ab    (z coordinates; no first-order part for virtual p)
+    # ------------------------------------------------------------------
+    def transition_amplitudes(self):
+        """f[N, o + v]: rows in (r1, z) coordinates, columns the spatial orbitals (occupied first)."""
+        o, v = self.o, self.v
+        f = np.zeros((self.dim(), o + v))
+        f[:v, o:] = np.eye(v) - 0.5 * self.mp2_density_vv()
+        f[:v, :o] = -self.second_order()[3].T
+        for j in range(o):
+            f[v:, j] = -d_to_z(self.T[j]).reshape(-1)   # T[j][i, a, b] = T^ab_ji
+        return f
+
+    def spectral_amplitudes(self, vecs):
+        """x[k, p] = sum_A Y[k, A] f[A, p] for eigenvectors vecs[k] (eq 7)."""
+        return np.asarray(vecs) @ self.transition_amplitudes()
+
+    # ------------------------------------------------------------------
     # scaled-matrix ADC (Sec. "ADC Theory", the equation after eq 5): the paper states that x = 0
     # gives ADC(2) and x = 1 ADC(3); its formula M0 + M1 + M2 + x M3 taken literally would keep the
     # second-order coupling and the first-order 2p1h terms at x = 0, so the reading is

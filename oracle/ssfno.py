@@ -12,7 +12,9 @@ Steps (Sec. "Computational Details", steps 2-4f):
       (eqs 12-13) and map the DF factor to the new virtuals (eqs 14-16);
   4e  natural auxiliary functions from W = J_vv J_vv^T (eqs 27-29);
       EA-ADC(2) and EA-ADC(3) in the truncated basis;
-  4f  omega_corr = omega_FNO-ADC(3) + omega_can-ADC(2) - omega_FNO-ADC(2) (eq 30).
+  4f  omega_corr = omega_FNO-ADC(3) + omega_can-ADC(2) - omega_FNO-ADC(2) (eq 30);
+      spectral amplitudes x = Y^T f of each matched root (eqs 7-8), carried back to the
+      canonical virtuals through U (the Dyson-orbital coefficients).
 
 Readings where the paper is silent (each listed in the design notes):
 * D^MP2_ab (per spin) = sum_klc (2T^ac_kl - T^ca_kl) T^bc_kl.
@@ -141,6 +143,12 @@ def carry_vector(vec, o, v, U):
     return np.concatenate([r1, z2.reshape(-1)])
 
 
+def dyson_sign(x):
+    """Sign convention of the reported spectral amplitudes: largest-|.| entry positive (first on ties)."""
+    x = np.array(x, dtype=float)
+    return x if x[np.argmax(np.abs(x))] >= 0 else -x
+
+
 def run(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, dense_limit=4000, sm_x=1.0, fno_mode="ss",
         keep_frac=0.0):
     """The whole method.  Returns a dict with the corrected roots and per-root details.
@@ -154,12 +162,14 @@ def run(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, dense_limit=4
     keep_n = int(np.ceil(keep_frac * v - 1e-9)) if keep_frac > 0 else 0
     if fno_thresh <= 0 and naf_thresh <= 0 and keep_n == 0:
         w3, Y3, ok = solve_roots(P0, 3, nroots, conv, dense_limit, sm_x)
-        out.update(roots=w3, omega_uncorr=w3, converged=ok, nvir_kept=[v] * nroots, naux_kept=[B.shape[0]] * nroots)
+        dy = np.array([dyson_sign(x) for x in P0.spectral_amplitudes(Y3)])
+        out.update(roots=w3, omega_uncorr=w3, converged=ok, nvir_kept=[v] * nroots, naux_kept=[B.shape[0]] * nroots,
+                   dyson=dy, pole_strength=np.sum(dy * dy, axis=1))
         return out
     w2, Y2, ok2 = solve_roots(P0, 2, nroots, conv, dense_limit)
     Dmp2 = P0.mp2_density_vv()
     out.update(omega_adc2_can=w2, e_mp2=P0.mp2_energy(), d_mp2=Dmp2)
-    roots, unc, a2f, nk, xk, eta_all = [], [], [], [], [], []
+    roots, unc, a2f, nk, xk, eta_all, dys = [], [], [], [], [], [], []
     for k in range(nroots):
         Dss = Dmp2 + ea_density(P0, Y2[k]) if fno_mode == "ss" else Dmp2
         U, e_new, eta, nkeep = natural_orbitals(Dss, eps_vir, fno_thresh, max(keep_n, 0))
@@ -175,11 +185,15 @@ def run(eps_occ, eps_vir, B, nroots, fno_thresh, naf_thresh, conv, dense_limit=4
         ov = np.abs(Y2k @ ref)
         m2 = m3 = int(np.argmax(ov))
         unc.append(w3k[m3])
+        xt = Pk.spectral_amplitudes(Y3k[m3])              # eq 7 in the truncated basis
+        dys.append(dyson_sign(np.concatenate([xt[:o], U @ xt[o:]])))
         a2f.append(w2k[m2])
         roots.append(w3k[m3] + w2[k] - w2k[m2])
         nk.append(nkeep)
         xk.append(xkeep)
         eta_all.append(eta)
+    dys = np.array(dys)
     out.update(roots=np.array(roots), omega_uncorr=np.array(unc), omega_adc2_fno=np.array(a2f),
-               nvir_kept=nk, naux_kept=xk, eta=eta_all, converged=ok2)
+               nvir_kept=nk, naux_kept=xk, eta=eta_all, converged=ok2, dyson=dys,
+               pole_strength=np.sum(dys * dys, axis=1))
     return out

@@ -28,7 +28,7 @@ EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_byte
            "adc3_ea_setup_workspace_bytes_ex", "adc3_ea_setup_ex", "adc3_set_chunk_elems",
            "adc3_ladder_workspace_bytes", "adc3_ladder_apply", "adc3_eigh_workspace_bytes", "adc3_eigh",
            "adc3_eigh_batched_workspace_bytes", "adc3_eigh_batched", "adc3_ladder_apply_static",
-           "adc3_ea_davidson_guess", "adc3_ea_setup_sm", "adc3_debug_inject_nan"]
+           "adc3_ea_davidson_guess", "adc3_ea_setup_sm", "adc3_debug_inject_nan", "adc3_ea_spectral_amplitudes"]
 
 # size of the static device scratch of adc3_ladder_apply_static (ADC3_STATIC_SCRATCH_BYTES)
 STATIC_SCRATCH_BYTES = 256 << 20
@@ -39,7 +39,8 @@ class adc3_opts(ctypes.Structure):
                 ("fno_correction", ctypes.c_int), ("precision", ctypes.c_int), ("precond", ctypes.c_int),
                 ("mlp_weights", ctypes.c_void_p), ("sigma_graphs", ctypes.c_int), ("ladder", ctypes.c_int),
                 ("sm_x", ctypes.c_double), ("fno_mode", ctypes.c_int), ("fno_keep_frac", ctypes.c_double),
-                ("init_guess", ctypes.c_void_p), ("n_guess", ctypes.c_int), ("vectors_out", ctypes.c_void_p)]
+                ("init_guess", ctypes.c_void_p), ("n_guess", ctypes.c_int), ("vectors_out", ctypes.c_void_p),
+                ("dyson_out", ctypes.c_void_p)]
 
 
 class adc3_instance(ctypes.Structure):
@@ -53,7 +54,7 @@ class adc3_root_report(ctypes.Structure):
                 ("omega_adc2_can", ctypes.c_double), ("omega_adc2_fno", ctypes.c_double),
                 ("resnorm", ctypes.c_double), ("nvir_kept", ctypes.c_int), ("naux_kept", ctypes.c_int),
                 ("iters", ctypes.c_int), ("sigma_builds", ctypes.c_int), ("omega_lowp", ctypes.c_double),
-                ("iters_lowp", ctypes.c_int), ("err_bound", ctypes.c_double)]
+                ("iters_lowp", ctypes.c_int), ("err_bound", ctypes.c_double), ("pole_strength", ctypes.c_double)]
 
 
 class ADCError(RuntimeError):
@@ -122,6 +123,8 @@ def load():
     lib.adc3_ea_davidson_guess.restype = I
     lib.adc3_ea_setup_sm.argtypes = [P, P, P, I, I, I, D, I, I, P, S, P, ctypes.POINTER(P)]
     lib.adc3_ea_setup_sm.restype = I
+    lib.adc3_ea_spectral_amplitudes.argtypes = [P, P, I, P, P]
+    lib.adc3_ea_spectral_amplitudes.restype = I
     lib.adc3_debug_inject_nan.argtypes = [I]
     lib.adc3_debug_inject_nan.restype = None
     lib.adc3_ea_dense_matrix.argtypes = [P, P, I, P]
@@ -434,6 +437,15 @@ class Context:
         _check(st, allow_noconv=True)
         g = ng.value
         return F[:g], A[:g], T[:g], st
+
+    def spectral_amplitudes(self, vecs):
+        """x[nvec, nocc + nvir] = Y^T f (eqs 7-8) of device vectors vecs[nvec, N] in this basis."""
+        import torch
+        vecs = vecs.contiguous()
+        n = 1 if vecs.dim() == 1 else int(vecs.shape[0])
+        x = torch.empty((n, self.nocc + self.nvir), dtype=torch.float64, device="cuda")
+        _check(load().adc3_ea_spectral_amplitudes(self.handle, _ptr(vecs), n, _ptr(x), _stream()))
+        return x
 
     def dense(self):
         import torch

@@ -114,6 +114,7 @@ struct Ctx {
     double *eo = nullptr, *ev = nullptr, *Boo = nullptr, *Bov = nullptr, *Bvv = nullptr;
     double *ovov = nullptr, *oovv = nullptr, *T = nullptr, *M11 = nullptr, *Uz = nullptr, *diag = nullptr;
     double *Dmp2 = nullptr;
+    double *u1 = nullptr;  // second-order singles [o][v]: static self-energy and spectral amplitudes
     // eigendecomposition of M11 for the block preconditioner (computed on first use)
     double *m11_Q = nullptr, *m11_w = nullptr, *m11_tmp = nullptr;
     bool m11_eig = false;
@@ -203,6 +204,7 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
     c->m11_w = take(ws, v);
     c->m11_tmp = take(ws, vv + (long long)eig_large_scratch(v) + v);
     c->Dmp2 = take(ws, vv);
+    c->u1 = take(ws, ov);
     c->diag = take(ws, c->N);
     c->Uz = take(ws, v * (long long)o * vv);
     if (level >= 3) {
@@ -255,11 +257,15 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             int p1[4] = {0, 2, 1, 3};  // [i][j][b][d] -> [i][b][j][d]
             k_permute4(c->P1, c->oovv, d_oovv, p1, 1.0, 0.0, s);
         }
-        double* ooov = nullptr;
-        if (level >= 3) {
-            ooov = take(ws, oo * ov);
-            ein(ws, "Qij,Qka->ijka", 1.0, TV(Boo, {X, o, o}), TV(Bov, {X, o, v}), 0.0, ooov, s);
-        }
+        double* ooov = take(ws, oo * ov);
+        ein(ws, "Qij,Qka->ijka", 1.0, TV(Boo, {X, o, o}), TV(Bov, {X, o, v}), 0.0, ooov, s);
+        // W^Q_ic = sum_kd B^Q_kd (2T-T~)_ik^cd, and the second-order singles
+        // u1_ia = [sum_Qc B^Q_ac W^Q_ic - sum_klc (2T-T~)_kl^ac (ki|lc)] / (e_i - e_a)
+        double* Bw = take(ws, X * ov);
+        ein(ws, "Qkd,ikcd->Qic", 1.0, TV(Bov, {X, o, v}), TV(Tt2, {o, o, v, v}), 0.0, Bw, s);
+        ein(ws, "Qac,Qic->ia", 1.0, TV(Bvv, {X, v, v}), TV(Bw, {X, o, v}), 0.0, c->u1, s);
+        ein(ws, "klac,kilc->ia", -1.0, TV(Tt2, {o, o, v, v}), TV(ooov, {o, o, o, v}), 1.0, c->u1, s);
+        k_div_d1(c->u1, eo, ev, o, v, s);
         // U_D[a][b][c][i] (first order (ab|ic), second order below) and U_z[a][i][b][c] = S + sqrt3 A over
         // (b,c), in chunks of the first virtual index a when the o v^3 tensors would crowd HBM (each
         // chunk holds a few tensors of o*na*v^2 elements)
@@ -276,8 +282,6 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
         // (2T-T~)_ik^cd: folded into the first-order product as B^Q_ab (B^Q_ic + W^Q_ic)
         const double* Bov_u = Bov;
         if (level >= 3) {
-            double* Bw = take(ws, X * ov);
-            ein(ws, "Qkd,ikcd->Qic", 1.0, TV(Bov, {X, o, v}), TV(Tt2, {o, o, v, v}), 0.0, Bw, s);
             k_axpby(Bw, Bov, X * ov, 1.0, c->smx, s);  // B + smx W (second order scaled for sm-ADC)
             Bov_u = Bw;
         }
@@ -422,13 +426,7 @@ static Ctx* build_ctx(Arena& ws, const double* eo_in, const double* ev_in, const
             ein(ws, "jkbc,kiac->ijab", -1.0, tT, toovv, 1.0, Y, s);
             double* U2 = Y;  // in place: U2 = Y / D
             k_div_d2(U2, eo, ev, o, v, s);
-            // second-order singles u1[i][a]
-            double* W = take(ws, X * ov);
-            ein(ws, "Qkd,ikcd->Qic", 1.0, TV(Bov, {X, o, v}), tT2, 0.0, W, s);
-            double* u1 = take(ws, ov);
-            ein(ws, "Qac,Qic->ia", 1.0, TV(Bvv, {X, v, v}), TV(W, {X, o, v}), 0.0, u1, s);
-            ein(ws, "klac,kilc->ia", -1.0, tT2, TV(ooov, {o, o, o, v}), 1.0, u1, s);
-            k_div_d1(u1, eo, ev, o, v, s);
+            const double* u1 = c->u1;  // second-order singles (formed with the coupling)
             // second-order densities (per spin)
             double* roo = take(ws, oo);
             ein(ws, "mkcd,lkcd->ml", -1.0, tT2, tT, 0.0, roo, s);
@@ -1129,6 +1127,21 @@ static void ea_density(Arena& ws, const Ctx* c, const double* vec, double* D, hi
     ws.release(mark);
 }
 
+// Spectral amplitudes x = Y^T f (eqs 7-8) of one vector in the context's basis, x[o + v] (occupied
+// orbitals first), with f_Ap = <Psi~_A| c+_p |Psi0> through second order in the 1p rows and first order
+// in the 2p1h rows:  x_b = y1_b - (D^MP2 y1)_b / 2 (virtual b);  x_j = -(u1 y1)_j - sum_iab
+// [(S + sqrt3 A) z]_iab T^ab_ji (occupied j).  tmp holds o v^2 doubles.
+static void spectral_amplitudes(const Ctx* c, const double* vec, double* x, double* tmp, hipStream_t s) {
+    const int o = c->o, v = c->v;
+    const long long ovv = (long long)o * v * v;
+    gemm_rm(1, v, v, -0.5, vec, v, false, c->Dmp2, v, false, 0.0, x + o, v, s);
+    k_axpby(x + o, vec, v, 1.0, 1.0, s);
+    k_fill(tmp, ovv, 0.0, s);
+    k_d_to_z_add(tmp, vec + v, o, v, s);
+    gemm_rm(1, o, (int)ovv, -1.0, tmp, ovv, false, c->T, ovv, true, 0.0, x, o, s);
+    gemm_rm(1, o, v, -1.0, vec, v, false, c->u1, v, true, 1.0, x, o, s);
+}
+
 // Natural orbitals of D^SS (eq 9), kept eta > thr (eqs 10-11; thr <= 0 keeps all), recanonicalised
 // (eqs 12-13), U = V~ Z (eq 14), for every root at once (Dss [nr][v][v]), the eigenproblems of all roots
 // solved as batches (one launch per Jacobi round for the whole batch; the recanonicalisation in groups of
@@ -1299,6 +1312,28 @@ struct SolveOut {
     bool all_conv = true;
 };
 
+// Pole strengths and Dyson-orbital coefficients from the spectral amplitudes xd[nroots][o + v] (canonical
+// MO basis): each vector's sign fixed so that its largest-magnitude entry is positive (first on ties),
+// P_k = sum_p x_kp^2 into the reports, the fixed vectors to dyson_out (device, nullable).
+static void finish_amplitudes(double* xd, int nroots, int n, std::vector<adc3_root_report>& rep, double* dyson_out,
+                              hipStream_t s) {
+    std::vector<double> h((size_t)nroots * n);
+    d2h(h.data(), xd, h.size() * sizeof(double), s);
+    for (int k = 0; k < nroots; ++k) {
+        double* x = h.data() + (size_t)k * n;
+        int imax = 0;
+        double ps = 0.0;
+        for (int p = 0; p < n; ++p) {
+            ps += x[p] * x[p];
+            if (std::fabs(x[p]) > std::fabs(x[imax])) imax = p;
+        }
+        if (x[imax] < 0)
+            for (int p = 0; p < n; ++p) x[p] = -x[p];
+        rep[k].pole_strength = ps;
+    }
+    if (dyson_out) h2d(dyson_out, h.data(), h.size() * sizeof(double), s);
+}
+
 // Truncation of the virtual space asked for by the options (SS-FNO or MP2-FNO, by threshold or by
 // share of the virtuals) or of the auxiliary basis (NAF)?
 static bool truncates(double fno, double naf, const adc3_opts& op) {
@@ -1327,9 +1362,19 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         Ctx* c = build_ctx(ws, eo, ev, B0.Boo, B0.Bov, B0.Bvv, o, v, X, level, s, op.precision, df, smx);
         c->mlp_w = op.mlp_weights;
         c->graphs = op.sigma_graphs != 0;
-        DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, op.vectors_out, s,
+        double* vecs = op.vectors_out ? op.vectors_out : take(ws, (long long)nroots * N0);
+        DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, vecs, s,
                                     op.precision, op.precond == 1 && level >= 3, nullptr, op.init_guess, ng,
                                     level >= 3 ? pm3 : pm2);
+        {
+            const size_t mx = ws.mark();
+            double* xd = take(ws, (long long)nroots * (o + v));
+            double* tmp = take(ws, (long long)o * v * v);
+            for (int k = 0; k < nroots; ++k)
+                spectral_amplitudes(c, vecs + (long long)k * N0, xd + (long long)k * (o + v), tmp, s);
+            if (!g_dry) finish_amplitudes(xd, nroots, o + v, out.rep, op.dyson_out, s);
+            ws.release(mx);
+        }
         for (int k = 0; k < nroots; ++k) {
             auto& R = out.rep[k];
             R.omega = R.omega_uncorr = r.w[k];
@@ -1357,6 +1402,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     const size_t mark0 = ws.mark();
     double* Y2 = take(ws, (long long)nroots * N0);
     double* Dss = take(ws, (long long)nb * vv0);
+    double* xd = take(ws, (long long)nroots * (o + v));  // spectral amplitudes, canonical MO basis
     DavResult r2;
     int sig0 = 0;
     {
@@ -1524,8 +1570,23 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             int mmax = 0;
             for (int k : ks) mmax = std::max(mmax, match[k]);
             const int nr3 = std::min(nroots, mmax + 1);
-            DavResult a3 = davidson_impl(c3, ws, nr3, conv, op.max_iter, op.max_subspace, nullptr, s, op.precision,
+            double* X3 = take(ws, (long long)nr3 * Nk);
+            DavResult a3 = davidson_impl(c3, ws, nr3, conv, op.max_iter, op.max_subspace, X3, s, op.precision,
                                          op.precond == 1, nullptr, Y2k, nroots, level >= 3 ? pm3 : pm2);
+            {
+                // spectral amplitudes of the matched roots in this basis, virtual part carried back to the
+                // canonical virtuals through U (x_p = sum_a U[p][a] x~_a)
+                const size_t mx = ws.mark();
+                double* xk = take(ws, o + vk);
+                double* tmp = take(ws, (long long)o * vk * vk);
+                for (int k : ks) {
+                    double* xo = xd + (long long)k * (o + v);
+                    spectral_amplitudes(c3, X3 + (long long)match[k] * Nk, xk, tmp, s);
+                    k_copy(xo, xk, o, s);
+                    gemm_rm(1, v, vk, 1.0, xk + o, vk, false, U, vk, true, 0.0, xo + o, v, s);
+                }
+                ws.release(mx);
+            }
             for (int k : ks) {
                 auto& R = out.rep[k];
                 const int m = match[k];
@@ -1551,6 +1612,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         ws.release(mark);
     }
     out.rep[0].sigma_builds += sig0;
+    if (!g_dry) finish_amplitudes(xd, nroots, o + v, out.rep, op.dyson_out, s);
     ws.release(mark0);
     return out;
 }
@@ -1603,6 +1665,7 @@ void adc3_default_opts(adc3_opts* o) {
     o->init_guess = nullptr;
     o->n_guess = 0;
     o->vectors_out = nullptr;
+    o->dyson_out = nullptr;
 }
 
 const char* adc3_last_error(void) { return g_msg.c_str(); }
@@ -2181,6 +2244,20 @@ extern "C" int adc3_ea_solve_batched(const adc3_instance* inst, int ninst, const
     }
     if (worst < 0) set_error(first_msg);
     return worst;
+    API_END
+}
+
+extern "C" int adc3_ea_spectral_amplitudes(adc3_ctx* ctx, const double* vecs, int nvec, double* x,
+                                           hipStream_t stream) {
+    API_BEGIN
+    if (!ctx || !vecs || !x) fail(ADC3_EINVAL, "NULL argument");
+    if (nvec < 0) fail(ADC3_EINVAL, "nvec < 0");
+    Ctx* c = ctx->c;
+    Arena ws = c->ws;
+    double* tmp = take(ws, (long long)c->o * c->v * c->v);
+    for (int k = 0; k < nvec; ++k)
+        spectral_amplitudes(c, vecs + (long long)k * c->N, x + (long long)k * (c->o + c->v), tmp, stream);
+    return ADC3_OK;
     API_END
 }
 

@@ -147,3 +147,37 @@ def test_error_bound_holds(prec):
         for k, r in enumerate(reps):
             assert 0 < r["err_bound"] <= 3 * conv + 1e-12
             assert abs(roots[k] - refp["roots"][k]) <= r["err_bound"] + 1e-12, (conv, k)
+
+
+def test_spectral_amplitudes_of_vectors():
+    eo, ev, B = synth.make_instance(4, 13, 30, 6, scale=0.4)
+    P = Problem(eo, ev, B)
+    r = np.random.default_rng(8).standard_normal((5, P.dim()))
+    for level in (2, 3):
+        ctx = adc.Context(dev(eo), dev(ev), dev(B), level)
+        x = host(ctx.spectral_amplitudes(dev(r)))
+        assert relerr(x, P.spectral_amplitudes(r)) < 1e-12
+        ctx.close()
+
+
+@pytest.mark.parametrize("fno,naf", [(0.0, 0.0), (1e-4, 1e-2)])
+def test_dyson_orbitals_and_pole_strengths(fno, naf):
+    """Spectral amplitudes of the reported roots (eqs 7-8) in the canonical MO basis, against the oracle
+    pipeline; conv 1e-10 so that the eigenvectors agree to ~1e-9."""
+    if fno > 0:
+        eo, ev, B = synth.make_instance(3, 10, 24, 8, scale=0.3)
+    else:
+        p, eo, ev, B = synth.preset("tiny-dense")
+    refp = ssfno.run(eo, ev, B, 3, fno, naf, 1e-11)
+    o = adc.adc3_default_opts()
+    dy = torch.zeros((3, eo.size + ev.size), dtype=torch.float64, device="cuda")
+    o.dyson_out = dy.data_ptr()
+    roots, reps, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 3, fno, naf, 1e-10, opts=o)
+    assert st == adc.ADC3_OK
+    x = host(dy)
+    assert np.abs(x - refp["dyson"]).max() < 1e-7
+    ps = np.array([r["pole_strength"] for r in reps])
+    assert np.abs(ps - refp["pole_strength"]).max() < 1e-7
+    assert np.all(ps > 0)
+    if fno > 0:  # scale 0.3: 1p-dominated roots, pole strengths near 1 (the literal scale's strong
+        assert np.all(ps < 1.5)  # correlation takes the second-order f far from that: 6.6, 2.0, 1.2)

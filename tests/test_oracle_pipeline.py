@@ -256,3 +256,67 @@ def test_mp2_fno_and_share_of_virtuals():
     assert s["nvir_kept"] == [6] * 3
     # the state-specific densities pick other orbitals than D^MP2 alone
     assert np.abs(np.array(s["roots"]) - np.array(r["roots"])).max() > 1e-8
+
+
+def _tier0_transition_series(isr):
+    """Order coefficients of f_Ap = <Psi~_A| c+_p |Psi0> (eq 8) from the tier-0 intermediate states, with
+    Psi0 normalised (the series is kept in intermediate normalisation); p runs over spin-orbitals."""
+    from oracle.isr import ORDER
+    N, psi = isr.N, isr.psi0
+    S = np.array([sum(psi[k] @ psi[n - k] for k in range(n + 1)) for n in range(ORDER + 1)])
+    inv = np.zeros(ORDER + 1)
+    inv[0], inv[2], inv[3] = 1.0, -0.5 * S[2], -0.5 * S[3]
+    psin = np.array([sum(inv[k] * psi[n - k] for k in range(n + 1)) for n in range(ORDER + 1)])
+    norb = isr.lad.spaces[N].norb
+    f = np.zeros((ORDER + 1, isr.Y.shape[1], norb))
+    for n in range(ORDER + 1):
+        for k in range(n + 1):
+            cp = np.stack([isr.lad.apply("c", p, N, psin[n - k]) for p in range(norb)])
+            f[n] += isr.Y[k] @ cp.T
+    return f
+
+
+@pytest.mark.parametrize("case", [(2, 3, 6, 5, 0.4), (1, 4, 5, 7, 0.6), (2, 4, 7, 3, 0.3)])
+def test_transition_amplitudes_against_intermediate_states(case):
+    """f (eq 8) of the oracle = the tier-0 series of <Psi~_A| c+_p alpha |Psi0> in doublet coordinates,
+    through second order in the 1p rows and first order in the 2p1h rows; the first-order 1p rows and the
+    first-order 2p1h rows of virtual p vanish identically.  Sum rule of the 1p rows' virtual columns and the
+    2p1h rows' occupied columns: f^T f = 1 - (second-order occupation) through second order, i.e.
+    delta - D^MP2 (vv) and -D^MP2_oo (oo)."""
+    o, v = case[0], case[1]
+    eo, ev, B, isr, P = _tier0(*case)
+    C = adc_so.doublet_embedding(o, v)
+    fs = _tier0_transition_series(isr)
+    fz = [C.T @ fs[n][:, 0::2] for n in range(fs.shape[0])]  # alpha spin-orbitals -> spatial columns
+    f = P.transition_amplitudes()
+    ref = np.zeros_like(f)
+    ref[:v] = fz[0][:v] + fz[1][:v] + fz[2][:v]
+    ref[v:] = fz[0][v:] + fz[1][v:]
+    assert np.abs(f - ref).max() < 1e-14
+    assert np.abs(fz[1][:v]).max() < 1e-15 and np.abs(fz[1][v:, o:]).max() < 1e-15
+    assert np.abs(fz[2][:v, :o]).max() > 1e-5  # the second-order singles do enter
+    ftf = f.T @ f
+    D = P.mp2_density_vv()
+    u1 = P.second_order()[3]
+    # virtual columns: (1 - D/2)^2 = 1 - D through second order
+    assert np.abs(ftf[o:, o:] - (np.eye(v) - D + 0.25 * D @ D)).max() < 1e-14
+    # occupied columns: the 2p1h rows' norm is the second-order hole occupation -D_oo (an identity of the
+    # z transform that ties f's normalisation to the pinned occupied density), plus the singles' square
+    assert np.abs(ftf[:o, :o] - u1 @ u1.T + P.mp2_density_oo()).max() < 1e-14
+
+
+def test_spectral_amplitudes_of_roots():
+    """x = Y^T f (eq 7) for the lowest ADC(3) roots; a 1p-dominated root has pole strength near 1 and a
+    2p1h satellite a small one; x equals the tier-0 amplitudes of the same eigenvectors."""
+    o, v = 2, 3
+    eo, ev, B, isr, P = _tier0(o, v, 6, 5, 0.4)
+    w, Y = np.linalg.eigh(P.dense(3))
+    x = P.spectral_amplitudes(Y.T)
+    ps = np.sum(x * x, axis=1)
+    r1 = np.sum(Y[:v] ** 2, axis=0)
+    assert ps[np.argmax(r1)] > 0.9 and ps[np.argmin(r1)] < 0.1
+    C = adc_so.doublet_embedding(o, v)
+    fs = _tier0_transition_series(isr)
+    f0 = C.T @ (fs[0] + fs[1] + fs[2])[:, 0::2]
+    f0[v:] = (C.T @ (fs[0] + fs[1])[:, 0::2])[v:]
+    assert np.abs(x - Y.T @ f0).max() < 1e-14
