@@ -40,7 +40,7 @@ class adc3_opts(ctypes.Structure):
                 ("mlp_weights", ctypes.c_void_p), ("sigma_graphs", ctypes.c_int), ("ladder", ctypes.c_int),
                 ("sm_x", ctypes.c_double), ("fno_mode", ctypes.c_int), ("fno_keep_frac", ctypes.c_double),
                 ("init_guess", ctypes.c_void_p), ("n_guess", ctypes.c_int), ("vectors_out", ctypes.c_void_p),
-                ("dyson_out", ctypes.c_void_p)]
+                ("dyson_out", ctypes.c_void_p), ("lockstep", ctypes.c_int)]
 
 
 class adc3_instance(ctypes.Structure):

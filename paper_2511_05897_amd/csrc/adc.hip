@@ -1102,6 +1102,488 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
 }
 
 // ---------------------------------------------------------------------------
+// Lockstep block Davidson: many independent Davidson problems (instances of a ragged batch, or the
+// per-root bases of one SS-FNO solve) advanced together, a fixed chunk of iterations per replay of one
+// HIP graph that holds every active problem's iterations on its own stream.  The iteration has a fixed
+// shape so that nothing in it needs the host: every iteration adds exactly nroots directions (the
+// preconditioned residuals; those of converged roots, and directions lost to orthogonalisation, are
+// zero vectors whose Gram rows are decoupled), the subspace size follows the iteration count, and the
+// convergence flags, residual norms and Ritz values stay on the device until the chunk ends.
+// ---------------------------------------------------------------------------
+// iterations per graph replay (ADC3_DAV_CHUNK overrides; default 3)
+static int lockstep_chunk() {
+    static const int c = [] {
+        const char* e = std::getenv("ADC3_DAV_CHUNK");
+        const int v = (e && *e) ? std::atoi(e) : 3;
+        return std::max(1, std::min(v, 64));
+    }();
+    return c;
+}
+
+struct LockJob {
+    // problem (set by the caller)
+    Ctx* c = nullptr;
+    int nroots = 1, max_iter = 500, max_sub = 0;
+    double conv = 1e-6;
+    int pmode = 0;  // 0 Jacobi, 3 exact 1p block (ADC(2) contexts)
+    int prec = 0;   // precision of the first phase (reduced-precision sigma until its floor, then FP64)
+    const double* guess = nullptr;
+    int nguess_in = 0;
+    double* vec_out = nullptr;  // [nroots][N], nullable
+    Arena* arena = nullptr;     // where the job's buffers are taken (jobs may share one)
+    // state
+    hipStream_t s = nullptr;
+    long long N = 0;
+    int mmax = 0, nb = 0, nguess = 0, nkeep = 0, m = 0, it = 0, phase = 0, it_lp = 0;
+    double *V = nullptr, *S = nullptr, *Xr = nullptr, *AX = nullptr, *R = nullptr, *Gm = nullptr, *Gf = nullptr,
+           *Gw = nullptr, *ev = nullptr, *Y = nullptr, *ev2 = nullptr, *Y2 = nullptr, *th = nullptr, *thold = nullptr,
+           *coef = nullptr, *Vk = nullptr, *Sk = nullptr, *part = nullptr, *valid = nullptr, *active = nullptr,
+           *status = nullptr, *tmp = nullptr, *Yb = nullptr, *gscr = nullptr, *nvalid = nullptr;
+    bool done = false;
+    std::vector<double> lp_best;
+    std::vector<int> lp_stall;
+    DavResult res;
+    long long sigma_builds = 0;
+    size_t status_off = 0;  // offset (doubles) of this job's status in the host read-back buffer
+};
+
+// does the problem's space hold the fixed block shape (guesses plus one block of nroots directions)?
+static bool lock_fits(const LockJob& j) {
+    const long long N = j.c->N;
+    int mmax = j.max_sub > 0 ? j.max_sub : std::max(8 * j.nroots, 40);
+    mmax = std::max(mmax, 2 * j.nroots + 1);
+    mmax = (int)std::min<long long>(std::min(mmax, 96), N);
+    return j.nroots <= 40 && mmax >= 2 * j.nroots;
+}
+
+static void lock_alloc(LockJob& j, Arena& ws) {
+    Ctx* c = j.c;
+    const long long N = c->N;
+    j.N = N;
+    if (j.nroots < 1 || j.nroots > N) fail(-1, "lockstep davidson: nroots out of range");
+    if (j.nroots > 40) fail(-1, "lockstep davidson: at most 40 roots per problem");
+    int mmax = j.max_sub > 0 ? j.max_sub : std::max(8 * j.nroots, 40);
+    mmax = std::max(mmax, 2 * j.nroots + 1);
+    j.mmax = (int)std::min<long long>(std::min(mmax, 96), N);
+    j.nb = j.nroots;
+    j.nguess = (int)std::min<long long>(N, std::min(j.nroots + 4, j.mmax - j.nb));
+    j.nguess = std::max(j.nguess, j.nroots);
+    if (j.nguess + j.nb > j.mmax) fail(-1, "lockstep davidson: space too small for the fixed block shape");
+    j.nkeep = std::max(j.nroots, std::min(2 * j.nroots + 2, j.mmax - j.nb));
+    const int mm = j.mmax, nr = j.nroots;
+    j.V = take(ws, (long long)mm * N);
+    j.S = take(ws, (long long)mm * N);
+    j.Xr = take(ws, (long long)nr * N);
+    j.AX = take(ws, (long long)nr * N);
+    j.R = take(ws, (long long)nr * N);
+    j.Vk = take(ws, (long long)j.nkeep * N);
+    j.Sk = take(ws, (long long)j.nkeep * N);
+    j.tmp = take(ws, (long long)std::max(j.nb, j.nguess) * N);
+    j.Gm = take(ws, (long long)mm * mm);
+    j.Gf = take(ws, (long long)mm * mm);
+    j.Gw = take(ws, (long long)mm * mm + mm);
+    j.ev = take(ws, mm);
+    j.Y = take(ws, (long long)mm * mm);
+    j.ev2 = take(ws, mm);
+    j.Y2 = take(ws, (long long)mm * mm);
+    j.th = take(ws, nr);
+    j.thold = take(ws, nr);
+    j.coef = take(ws, (long long)mm * mm);
+    j.valid = take(ws, mm);
+    j.active = take(ws, nr);
+    j.status = take(ws, 2 + 2 * nr);
+    j.nvalid = take(ws, 1);
+    j.Yb = take(ws, (long long)nr * c->v);
+    j.part = take(ws, (long long)dots_partial_elems(mm, mm, N));
+    j.gscr = take(ws, GEMM_SCRATCH);
+    j.res.w.assign(nr, 0.0);
+    j.res.rn.assign(nr, 0.0);
+    j.lp_best.assign(nr, INFINITY);
+    j.lp_stall.assign(nr, 0);
+}
+
+// GEMM scratch of a job while its work is issued (its own region: jobs run concurrently)
+struct JobScratch {
+    Arena a;
+    GemmScratch g;
+    explicit JobScratch(LockJob& j) : a(scratch_arena(j)), g(a, GEMM_SCRATCH) {}
+    static Arena scratch_arena(LockJob& j) {
+        Arena x;
+        x.base = (char*)j.gscr;
+        x.cap = GEMM_SCRATCH * sizeof(double) + 256;
+        return x;
+    }
+};
+
+// Tn[nn] against V[0..m) and within the block, two rounds of (classical Gram-Schmidt, Loewdin): directions
+// whose Loewdin eigenvalue falls to <= 1e-14 become zero vectors and their valid flag 0 (valid[m..m+nn))
+static void lock_ortho(LockJob& j, double* Tn, int nn, int m) {
+    const long long N = j.N;
+    hipStream_t s = j.s;
+    k_dots(Tn, N, nn, Tn, N, nn, N, j.Gw, nn, j.part, s);
+    k_rscale_rows(Tn, nn, N, j.Gw, nn, s);
+    for (int round = 0; round < 2; ++round) {
+        if (m > 0) {
+            k_dots(j.V, N, m, Tn, N, nn, N, j.coef, nn, j.part, s);
+            k_lincomb(Tn, N, nn, j.V, N, m, j.coef, nn, N, -1.0, 1.0, s);
+        }
+        k_dots(Tn, N, nn, Tn, N, nn, N, j.Gm, nn, j.part, s);
+        k_symmetrize(j.Gm, nn, s);
+        eig_small(j.Gm, nn, j.ev2, j.Y2, s);
+        k_sort_eig(j.ev2, j.Y2, nn, 1, j.Gw, j.Gw + nn, s);
+        k_lowdin_masked(j.coef, j.Y2, j.ev2, nn, 1e-14, j.valid + m, s);
+        k_lincomb(j.tmp, N, nn, Tn, N, nn, j.coef, nn, N, 1.0, 0.0, s);
+        k_copy(Tn, j.tmp, (long long)nn * N, s);
+    }
+}
+
+static void lock_sigma(LockJob& j, const double* r, double* sg, int nvec) {
+    Arena w = j.c->ws;
+    const bool g = j.c->graphs;
+    j.c->graphs = false;  // the pass is recorded into the lockstep graph, not captured on its own
+    sigma_impl(j.c, w, r, sg, nvec, j.s, j.phase);
+    j.c->graphs = g;
+    j.sigma_builds += nvec;
+}
+
+// Rayleigh-Ritz over V[0..m) (masked directions decoupled), Ritz vectors, residuals, device status
+static void lock_rr(LockJob& j) {
+    const long long N = j.N;
+    const int m = j.m, nr = j.nroots;
+    hipStream_t s = j.s;
+    k_copy2d(j.Gm, m, j.Gf, j.mmax, m, m, 1.0, 0.0, s);
+    k_symmetrize(j.Gm, m, s);
+    k_mask_gram(j.Gm, m, j.valid, j.nvalid, s);
+    eig_small(j.Gm, m, j.ev, j.Y, s);
+    k_sort_eig(j.ev, j.Y, m, 0, j.Gw, j.Gw + m, s);
+    k_copy2d(j.coef, nr, j.Y, m, m, nr, 1.0, 0.0, s);
+    k_lincomb(j.Xr, N, nr, j.V, N, m, j.coef, nr, N, 1.0, 0.0, s);
+    k_lincomb(j.AX, N, nr, j.S, N, m, j.coef, nr, N, 1.0, 0.0, s);
+    k_copy(j.th, j.ev, nr, s);
+    k_residual(j.R, j.AX, j.Xr, j.th, nr, N, s);
+    k_dots(j.R, N, nr, j.R, N, nr, N, j.Gw, nr, j.part, s);
+    k_dav_status(j.Gw, nr, j.th, j.thold, j.conv, j.active, j.status, s);
+    ++j.it;
+}
+
+// keep the nk lowest Ritz vectors of the last Rayleigh-Ritz (V, S and the Gram follow)
+static void lock_collapse(LockJob& j, int nk, bool keep_sigma) {
+    const long long N = j.N;
+    hipStream_t s = j.s;
+    k_copy2d(j.coef, nk, j.Y, j.m, j.m, nk, 1.0, 0.0, s);
+    k_lincomb(j.Vk, N, nk, j.V, N, j.m, j.coef, nk, N, 1.0, 0.0, s);
+    k_copy(j.V, j.Vk, (long long)nk * N, s);
+    if (keep_sigma) {
+        k_lincomb(j.Sk, N, nk, j.S, N, j.m, j.coef, nk, N, 1.0, 0.0, s);
+        k_copy(j.S, j.Sk, (long long)nk * N, s);
+        k_dots(j.V, N, nk, j.S, N, nk, N, j.Gf, j.mmax, j.part, s);
+    }
+    k_valid_first(j.valid, nk, j.nvalid, s);
+    j.m = nk;
+}
+
+// one iteration, device work only: collapse when the block does not fit, expand by nb preconditioned
+// residuals (zero for converged roots), sigma, Gram columns, Rayleigh-Ritz and status
+static void lock_iterate(LockJob& j) {
+    JobScratch scr(j);
+    const long long N = j.N;
+    hipStream_t s = j.s;
+    Ctx* c = j.c;
+    if (j.m + j.nb > j.mmax) lock_collapse(j, j.nkeep, true);
+    double* Tn = j.V + (long long)j.m * N;
+    k_precond(Tn, j.R, c->diag, j.th, j.nroots, N, s);
+    if (j.pmode == 3) {
+        // 1p block exactly: t1 = Q (w - theta)^-1 Q^T r1 per root
+        const int v = c->v;
+        gemm_rm(j.nroots, v, v, 1.0, j.R, N, false, c->m11_Q, v, false, 0.0, j.Yb, v, s);
+        for (int k = 0; k < j.nroots; ++k) k_div_shift(j.Yb + (long long)k * v, c->m11_w, j.th + k, v, s);
+        gemm_rm(j.nroots, v, v, 1.0, j.Yb, v, false, c->m11_Q, v, true, 0.0, Tn, N, s);
+    }
+    k_rows_mask(Tn, j.nb, N, j.active, s);
+    lock_ortho(j, Tn, j.nb, j.m);
+    lock_sigma(j, Tn, j.S + (long long)j.m * N, j.nb);
+    {
+        // failure-injection hook (eager iterations only, never recorded into a graph)
+        int at = g_nan_at.load();
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (at > 0 && j.it + 1 >= at && hipStreamIsCapturing(s, &cap) == hipSuccess &&
+            cap == hipStreamCaptureStatusNone && g_nan_at.compare_exchange_strong(at, 0))
+            k_fill(j.S + (long long)j.m * N, N, NAN, s);
+    }
+    k_dots(j.V, N, j.m + j.nb, j.S + (long long)j.m * N, N, j.nb, N, j.Gf + j.m, j.mmax, j.part, s);
+    k_mirror_cols(j.Gf, j.mmax, j.m, j.nb, s);
+    j.m += j.nb;
+    lock_rr(j);
+}
+
+// host-side state of one iteration without issuing it (a replay of a captured chunk)
+static void lock_iterate_host(LockJob& j) {
+    if (j.m + j.nb > j.mmax) j.m = j.nkeep;
+    j.m += j.nb;
+    j.sigma_builds += j.nb;
+    ++j.it;
+}
+
+// eager start: guesses, first sigma block, Rayleigh-Ritz (the first iteration)
+static void lock_start(LockJob& j) {
+    JobScratch scr(j);
+    Ctx* c = j.c;
+    const long long N = j.N;
+    hipStream_t s = j.s;
+    j.phase = std::min(j.prec, c->prec);
+    const int ng = j.guess ? std::min(j.nguess_in, j.nguess) : 0;
+    std::vector<double> hd(N);
+    d2h(hd.data(), c->diag, N * sizeof(double), s);
+    const int kneed = j.nguess - ng;
+    std::vector<std::pair<double, long long>> heap;
+    heap.reserve(kneed + 1);
+    for (long long i = 0; i < N && kneed > 0; ++i) {
+        const std::pair<double, long long> e(hd[i], i);
+        if ((int)heap.size() < kneed) {
+            heap.push_back(e);
+            std::push_heap(heap.begin(), heap.end());
+        } else if (e < heap.front()) {
+            std::pop_heap(heap.begin(), heap.end());
+            heap.back() = e;
+            std::push_heap(heap.begin(), heap.end());
+        }
+    }
+    std::sort_heap(heap.begin(), heap.end());
+    k_fill(j.V, (long long)j.nguess * N, 0.0, s);
+    if (ng > 0) k_copy(j.V, j.guess, (long long)ng * N, s);
+    std::vector<double> one(1, 1.0);
+    for (int k = 0; k < kneed; ++k) h2d(j.V + (long long)(ng + k) * N + heap[k].second, one.data(), sizeof(double), s);
+    if (j.pmode == 3 && !c->m11_eig) {
+        const long long vv = (long long)c->v * c->v;
+        k_copy(c->m11_tmp, c->M11, vv, s);
+        eig_large(c->m11_tmp, c->v, c->m11_w, c->m11_Q, c->m11_tmp + vv + c->v, s);
+        c->m11_eig = true;
+    }
+    lock_ortho(j, j.V, j.nguess, 0);
+    j.m = j.nguess;
+    lock_sigma(j, j.V, j.S, j.m);
+    k_dots(j.V, N, j.m, j.S, N, j.m, N, j.Gf, j.mmax, j.part, s);
+    k_fill(j.thold, j.nroots, INFINITY, s);
+    lock_rr(j);
+}
+
+// restart from the Ritz vectors in the next precision (reduced-precision phase at its noise floor)
+static void lock_restart(LockJob& j, int phase) {
+    JobScratch scr(j);
+    const long long N = j.N;
+    lock_collapse(j, std::min(j.m, j.nkeep), false);
+    j.phase = phase;
+    lock_sigma(j, j.V, j.S, j.m);
+    k_dots(j.V, N, j.m, j.S, N, j.m, N, j.Gf, j.mmax, j.part, j.s);
+    k_fill(j.thold, j.nroots, INFINITY, j.s);
+    lock_rr(j);
+}
+
+// Runs every job to convergence (or its max_iter).  Jobs start eagerly on streams of their own, then
+// advance `chunk` iterations per replay of one graph that forks from `main` into every active job's
+// stream and joins back; after each replay the jobs' status words come back in one copy.  Graphs are
+// kept per (job, subspace size, phase, chunk) set, so a repeating collapse cycle replays them.
+static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int chunk) {
+    // spaces too small for the fixed shape (a few truncated virtuals) take the one-at-a-time Davidson
+    std::vector<LockJob*> jobs;
+    for (auto* j : jobs_in) {
+        if (lock_fits(*j)) {
+            jobs.push_back(j);
+            continue;
+        }
+        const long long before = j->c->sigma_count;
+        j->res = davidson_impl(j->c, *j->arena, j->nroots, j->conv, j->max_iter, j->max_sub, j->vec_out, caller,
+                               j->prec, false, nullptr, j->guess, j->nguess_in, j->pmode);
+        j->sigma_builds = j->c->sigma_count - before;
+        j->done = true;
+    }
+    if (jobs.empty()) return;
+    if (g_dry) {
+        for (auto* j : jobs) {
+            lock_alloc(*j, *j->arena);
+            Arena w = j->c->ws;
+            sigma_impl(j->c, w, nullptr, nullptr, std::min(NVMAX, j->nguess), nullptr, j->prec);
+        }
+        return;
+    }
+    const int nj = (int)jobs.size();
+    size_t tot = 0;
+    for (auto* j : jobs) {
+        lock_alloc(*j, *j->arena);
+        j->status_off = tot;
+        tot += 2 + 2 * j->nroots;
+    }
+    struct Res {
+        hipStream_t main = nullptr;  // the graphs' stream (capture needs a stream of its own)
+        std::vector<hipStream_t> st;
+        std::vector<hipEvent_t> ev;
+        hipEvent_t fork = nullptr;
+        double* host = nullptr;
+        std::map<std::string, hipGraphExec_t> graphs;
+        ~Res() {
+            for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+            for (auto e : ev) (void)hipEventDestroy(e);
+            if (fork) (void)hipEventDestroy(fork);
+            for (auto x : st) (void)hipStreamDestroy(x);
+            if (main) (void)hipStreamDestroy(main);
+            if (host) (void)hipHostFree(host);
+        }
+    } rs;
+    HIPCHK(hipHostMalloc((void**)&rs.host, std::max<size_t>(tot, 1) * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&rs.fork, hipEventDisableTiming));
+    HIPCHK(hipStreamCreateWithFlags(&rs.main, hipStreamNonBlocking));
+    hipStream_t main = rs.main;
+    HIPCHK(hipEventRecord(rs.fork, caller));
+    HIPCHK(hipStreamWaitEvent(main, rs.fork, 0));
+    for (int i = 0; i < nj; ++i) {
+        hipStream_t x = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        rs.st.push_back(x);
+        hipEvent_t e = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        rs.ev.push_back(e);
+        jobs[i]->s = x;
+        HIPCHK(hipStreamWaitEvent(x, rs.fork, 0));
+    }
+    for (auto* j : jobs) lock_start(*j);
+    auto read_status = [&](const std::vector<int>& ids, hipStream_t s) {
+        for (int i : ids)
+            HIPCHK(hipMemcpyAsync(rs.host + jobs[i]->status_off, jobs[i]->status,
+                                  (2 + 2 * jobs[i]->nroots) * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+    };
+    // the start's status: each job's own stream
+    for (int i = 0; i < nj; ++i) read_status({i}, jobs[i]->s);
+    // evaluation with restarts handled per job index
+    auto step_eval = [&](int i) {
+        LockJob& j = *jobs[i];
+        for (;;) {
+            const double* h = rs.host + j.status_off;
+            const int nr = j.nroots;
+            for (int k = 0; k < nr; ++k) {
+                j.res.rn[k] = h[2 + k];
+                j.res.w[k] = h[2 + nr + k];
+            }
+            if (h[1] == 0.0) fail(ADC3_ENUMERIC, "davidson: non-finite Ritz value or residual");
+            if (j.phase > 0) {
+                double scale = 1.0, rmax = 0.0;
+                for (int k = 0; k < nr; ++k) {
+                    scale = std::max(scale, std::fabs(j.res.w[k]));
+                    rmax = std::max(rmax, j.res.rn[k]);
+                }
+                const double tau = std::max(j.conv, (j.phase == 1 ? 1e-7 : 3e-4) * scale);
+                bool all_stalled = true;
+                for (int k = 0; k < nr; ++k) {
+                    if (j.res.rn[k] < 0.9 * j.lp_best[k]) { j.lp_best[k] = j.res.rn[k]; j.lp_stall[k] = 0; }
+                    else j.lp_stall[k] += std::max(1, chunk);
+                    if (j.res.rn[k] > tau && j.lp_stall[k] < 4) all_stalled = false;
+                }
+                if (rmax <= tau || all_stalled || j.it >= j.max_iter) {
+                    const int next = (j.phase == 2 && j.c->Bvv32) ? 1 : 0;
+                    if (next == 0) {
+                        j.res.iters_lowp = j.it;
+                        j.res.w_lowp = j.res.w;
+                    }
+                    std::fill(j.lp_best.begin(), j.lp_best.end(), INFINITY);
+                    std::fill(j.lp_stall.begin(), j.lp_stall.end(), 0);
+                    lock_restart(j, next);
+                    read_status({i}, j.s);
+                    continue;  // evaluate the restart's Rayleigh-Ritz
+                }
+                return;
+            }
+            if (h[0] != 0.0 || j.it >= j.max_iter) {
+                j.done = true;
+                j.res.converged = h[0] != 0.0;
+                j.res.iters = j.it;
+            }
+            return;
+        }
+    };
+    for (int i = 0; i < nj; ++i) step_eval(i);
+    // a job's first chunk in a precision runs eagerly: the ladder tuner settles the block's shape before
+    // any capture
+    std::vector<int> tuned(nj, -1);
+    for (;;) {
+        std::vector<int> act;
+        for (int i = 0; i < nj; ++i)
+            if (!jobs[i]->done) act.push_back(i);
+        if (act.empty()) break;
+        std::vector<int> eager;
+        for (int i : act)
+            if (tuned[i] != jobs[i]->phase) eager.push_back(i);
+        if (!eager.empty()) {
+            for (int i : eager) {
+                LockJob& j = *jobs[i];
+                const int K = std::max(1, std::min(chunk, j.max_iter - j.it));
+                for (int k = 0; k < K; ++k) lock_iterate(j);
+                tuned[i] = j.phase;
+            }
+            for (int i : eager) read_status({i}, jobs[i]->s);
+            for (int i : eager) step_eval(i);
+            continue;
+        }
+        // every active job's stream has finished its eager work: the graph forks from main
+        for (int i : act) {
+            HIPCHK(hipEventRecord(rs.ev[i], jobs[i]->s));
+            HIPCHK(hipStreamWaitEvent(main, rs.ev[i], 0));
+        }
+        std::vector<int> K(nj, 0);
+        std::string key;
+        for (int i : act) {
+            K[i] = std::max(1, std::min(chunk, jobs[i]->max_iter - jobs[i]->it));
+            key += std::to_string(i) + ":" + std::to_string(jobs[i]->m) + ":" + std::to_string(jobs[i]->phase) + ":" +
+                   std::to_string(K[i]) + ";";
+        }
+        auto g = rs.graphs.find(key);
+        if (g == rs.graphs.end()) {
+            hipGraph_t gr = nullptr;
+            HIPCHK(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
+            try {
+                HIPCHK(hipEventRecord(rs.fork, main));
+                for (int i : act) {
+                    LockJob& j = *jobs[i];
+                    HIPCHK(hipStreamWaitEvent(j.s, rs.fork, 0));
+                    for (int k = 0; k < K[i]; ++k) lock_iterate(j);
+                    HIPCHK(hipEventRecord(rs.ev[i], j.s));
+                    HIPCHK(hipStreamWaitEvent(main, rs.ev[i], 0));
+                }
+            } catch (...) {
+                // close the capture so that no stream is left capturing
+                hipGraph_t bad = nullptr;
+                (void)hipStreamEndCapture(main, &bad);
+                if (bad) (void)hipGraphDestroy(bad);
+                throw;
+            }
+            HIPCHK(hipStreamEndCapture(main, &gr));
+            hipGraphExec_t ex = nullptr;
+            HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+            HIPCHK(hipGraphDestroy(gr));
+            g = rs.graphs.emplace(key, ex).first;
+        } else {
+            for (int i : act)
+                for (int k = 0; k < K[i]; ++k) lock_iterate_host(*jobs[i]);
+        }
+        HIPCHK(hipGraphLaunch(g->second, main));
+        read_status(act, main);
+        // eager work of the next round (restarts) runs on each job's stream after the replay
+        HIPCHK(hipEventRecord(rs.fork, main));
+        for (int i : act) HIPCHK(hipStreamWaitEvent(jobs[i]->s, rs.fork, 0));
+        for (int i : act) step_eval(i);
+    }
+    for (int i = 0; i < nj; ++i) {
+        LockJob& j = *jobs[i];
+        if (j.vec_out) k_copy(j.vec_out, j.Xr, (long long)j.nroots * j.N, j.s);
+        HIPCHK(hipEventRecord(rs.ev[i], j.s));
+        HIPCHK(hipStreamWaitEvent(main, rs.ev[i], 0));
+    }
+    HIPCHK(hipStreamSynchronize(main));
+    HIPCHK(hipEventRecord(rs.fork, main));
+    HIPCHK(hipStreamWaitEvent(caller, rs.fork, 0));
+    for (auto* j : jobs) j->s = nullptr;
+}
+
+// ---------------------------------------------------------------------------
 // SS-FNO / NAF pipeline (Sec. "Computational Details", steps 2-4f)
 // ---------------------------------------------------------------------------
 struct Blocks {
@@ -1363,9 +1845,25 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         c->mlp_w = op.mlp_weights;
         c->graphs = op.sigma_graphs != 0;
         double* vecs = op.vectors_out ? op.vectors_out : take(ws, (long long)nroots * N0);
-        DavResult r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, vecs, s,
-                                    op.precision, op.precond == 1 && level >= 3, nullptr, op.init_guess, ng,
-                                    level >= 3 ? pm3 : pm2);
+        DavResult r;
+        if (op.lockstep && op.precond != 1 && op.precond != 2) {
+            // the lockstep engine with one problem: fixed-shape iterations replayed from graphs
+            LockJob j;
+            j.c = c;
+            j.nroots = nroots; j.conv = conv; j.max_iter = op.max_iter; j.max_sub = op.max_subspace;
+            j.pmode = level >= 3 ? pm3 : pm2; j.prec = op.precision;
+            j.guess = op.init_guess; j.nguess_in = ng; j.vec_out = vecs;
+            j.arena = &ws;
+            std::vector<LockJob*> jp{&j};
+            const size_t mj = ws.mark();
+            lockstep_run(jp, s, lockstep_chunk());
+            ws.release(mj);
+            r = j.res;
+            c->sigma_count = j.sigma_builds;
+        } else {
+            r = davidson_impl(c, ws, nroots, conv, op.max_iter, op.max_subspace, vecs, s, op.precision,
+                              op.precond == 1 && level >= 3, nullptr, op.init_guess, ng, level >= 3 ? pm3 : pm2);
+        }
         {
             const size_t mx = ws.mark();
             double* xd = take(ws, (long long)nroots * (o + v));
@@ -1480,8 +1978,174 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         }
         ws.release(mm);
     }
+    // step 4, all bases together: their truncated ADC(2) solves in one lockstep Davidson, then their
+    // ADC(3) solves in another (the Learned and Olsen steps are not in the lockstep engine)
+    const bool lock = op.lockstep != 0 && op.precond != 1 && op.precond != 2;
+    if (lock) {
+        GemmScratch gscr(ws, GEMM_SCRATCH);
+        std::vector<Blocks> Bn(nb);
+        std::vector<int> xks(nb, X);
+        std::vector<long long> Nks(nb);
+        std::vector<double*> carried(nb), Y2k(nb);
+        for (int b = 0; b < nb; ++b) {
+            const int vk = vks[b];
+            if (vk < 1) fail(ADC3_EINVAL, "SS-FNO threshold removes every virtual orbital");
+            const double* U = U_all + (long long)b * vv0;
+            Blocks Bt;
+            transform_blocks(B0, U, vk, Bt, ws, s);
+            Bn[b] = Bt;
+            if (naf > 0) xks[b] = naf_blocks(Bt, naf, Bn[b], ws, s, vk == v ? &naf_cache : nullptr);
+            const long long Nk = vk + (long long)o * vk * vk;
+            if (nroots > Nk) fail(ADC3_EINVAL, "truncated space smaller than nroots");
+            Nks[b] = Nk;
+            carried[b] = take(ws, (long long)nroots * Nk);
+            Y2k[b] = take(ws, (long long)nroots * Nk);
+            const size_t mt = ws.mark();
+            double* tmp = take(ws, (long long)o * v * vk);
+            for (int q = 0; q < nroots; ++q) {
+                const double* yq = Y2 + (long long)q * N0;
+                double* cq = carried[b] + (long long)q * Nk;
+                gemm_rm(1, vk, v, 1.0, yq, v, false, U, vk, false, 0.0, cq, vk, s);
+                gemm_rm(o * v, vk, v, 1.0, yq + v, v, false, U, vk, false, 0.0, tmp, vk, s);
+                Gemm g;
+                g.M = vk; g.N = vk; g.K = v;
+                g.A = U; g.sAm = 1; g.sAk = vk;
+                g.B = tmp; g.sBk = vk; g.sBn = 1; g.bB0 = (long long)v * vk;
+                g.C = cq + vk; g.sCm = vk; g.sCn = 1; g.bC0 = (long long)vk * vk;
+                g.nb0 = o;
+                gemm(g, s);
+            }
+            ws.release(mt);
+        }
+        std::vector<std::vector<int>> ks(nb);
+        for (int b = 0; b < nb; ++b) {
+            if (shared)
+                for (int k = 0; k < nroots; ++k) ks[b].push_back(k);
+            else
+                ks[b].push_back(b);
+        }
+        std::vector<int> match(nroots, 0);
+        std::vector<DavResult> a2(nb);
+        long long sig = 0;
+        {
+            const size_t m2 = ws.mark();
+            std::vector<Ctx*> c2(nb, nullptr);
+            std::vector<LockJob> jobs(nb);
+            std::vector<LockJob*> jp;
+            for (int b = 0; b < nb; ++b) {
+                c2[b] = build_ctx(ws, eo, e_all + (long long)b * v, Bn[b].Boo, Bn[b].Bov, Bn[b].Bvv, o, vks[b],
+                                  Bn[b].X, 2, s, op.precision);
+                if (m11Q && m11_pre[b]) {
+                    k_copy(c2[b]->m11_Q, m11Q + (long long)b * vv0, (long long)vks[b] * vks[b], s);
+                    k_copy(c2[b]->m11_w, m11w + (long long)b * v, vks[b], s);
+                    c2[b]->m11_eig = true;
+                }
+            }
+            for (int b = 0; b < nb; ++b) {
+                LockJob& j = jobs[b];
+                j.c = c2[b];
+                j.nroots = nroots; j.conv = conv; j.max_iter = op.max_iter; j.max_sub = op.max_subspace;
+                j.pmode = pm2; j.prec = op.precision;
+                j.guess = carried[b]; j.nguess_in = nroots; j.vec_out = Y2k[b];
+                j.arena = &ws;
+                jp.push_back(&j);
+            }
+            const size_t mj = ws.mark();
+            lockstep_run(jp, s, lockstep_chunk());
+            ws.release(mj);
+            for (int b = 0; b < nb; ++b) {
+                a2[b] = jobs[b].res;
+                sig += jobs[b].sigma_builds;
+                out.all_conv = out.all_conv && a2[b].converged;
+            }
+            // overlaps of the truncated ADC(2) vectors with the carried canonical ones
+            for (int b = 0; b < nb; ++b) {
+                const size_t mo = ws.mark();
+                double* ovl = take(ws, (long long)nroots * nroots);
+                double* part = take(ws, (long long)dots_partial_elems(nroots, nroots, Nks[b]));
+                k_dots(carried[b], Nks[b], nroots, Y2k[b], Nks[b], nroots, Nks[b], ovl, nroots, part, s);
+                std::vector<double> hov((size_t)nroots * nroots);
+                d2h(hov.data(), ovl, hov.size() * sizeof(double), s);
+                for (int k : ks[b]) {
+                    match[k] = k;
+                    if (!g_dry) {
+                        int m = 0;
+                        for (int q = 1; q < nroots; ++q)
+                            if (std::fabs(hov[(size_t)k * nroots + q]) > std::fabs(hov[(size_t)k * nroots + m])) m = q;
+                        match[k] = m;
+                    }
+                    out.rep[k].omega_adc2_fno = a2[b].w[match[k]];
+                }
+                ws.release(mo);
+            }
+            for (int b = 0; b < nb; ++b) delete c2[b];
+            ws.release(m2);
+        }
+        {
+            const size_t m3 = ws.mark();
+            std::vector<Ctx*> c3(nb, nullptr);
+            std::vector<double*> X3(nb);
+            std::vector<int> nr3(nb, 1);
+            for (int b = 0; b < nb; ++b) {
+                c3[b] = build_ctx(ws, eo, e_all + (long long)b * v, Bn[b].Boo, Bn[b].Bov, Bn[b].Bvv, o, vks[b],
+                                  Bn[b].X, level, s, op.precision, df, smx);
+                int mm = 0;
+                for (int k : ks[b]) mm = std::max(mm, match[k]);
+                nr3[b] = g_dry ? nroots : std::min(nroots, mm + 1);
+                X3[b] = take(ws, (long long)nr3[b] * Nks[b]);
+            }
+            std::vector<LockJob> jobs(nb);
+            std::vector<LockJob*> jp;
+            for (int b = 0; b < nb; ++b) {
+                LockJob& j = jobs[b];
+                j.c = c3[b];
+                j.nroots = nr3[b]; j.conv = conv; j.max_iter = op.max_iter; j.max_sub = op.max_subspace;
+                j.pmode = level >= 3 ? pm3 : pm2; j.prec = op.precision;
+                j.guess = Y2k[b]; j.nguess_in = nroots; j.vec_out = X3[b];
+                j.arena = &ws;
+                jp.push_back(&j);
+            }
+            {
+                const size_t mj = ws.mark();
+                lockstep_run(jp, s, lockstep_chunk());
+                ws.release(mj);
+            }
+            const size_t mx = ws.mark();
+            for (int b = 0; b < nb; ++b) {
+                const DavResult& a3 = jobs[b].res;
+                const int vk = vks[b];
+                sig += jobs[b].sigma_builds;
+                out.all_conv = out.all_conv && a3.converged;
+                double* xk = take(ws, o + vk);
+                double* tmp = take(ws, (long long)o * vk * vk);
+                const double* U = U_all + (long long)b * vv0;
+                for (int k : ks[b]) {
+                    auto& R = out.rep[k];
+                    const int m = match[k];
+                    R.omega_adc2_can = r2.w[k];
+                    R.omega_uncorr = a3.w[m];
+                    R.omega_lowp = a3.w_lowp.empty() ? a3.w[m] : a3.w_lowp[m];
+                    R.iters_lowp = a3.iters_lowp;
+                    R.resnorm = a3.rn[m];
+                    R.iters = a3.iters;
+                    R.nvir_kept = vk;
+                    R.naux_kept = xks[b];
+                    R.omega = R.omega_uncorr + (op.fno_correction ? (R.omega_adc2_can - R.omega_adc2_fno) : 0.0);
+                    R.err_bound = a3.rn[m] + (op.fno_correction ? r2.rn[k] + a2[b].rn[m] : 0.0);
+                    double* xo = xd + (long long)k * (o + v);
+                    spectral_amplitudes(c3[b], X3[b] + (long long)m * Nks[b], xk, tmp, s);
+                    k_copy(xo, xk, o, s);
+                    gemm_rm(1, v, vk, 1.0, xk + o, vk, false, U, vk, true, 0.0, xo + o, v, s);
+                }
+                ws.release(mx);
+            }
+            for (int b = 0; b < nb; ++b) delete c3[b];
+            ws.release(m3);
+        }
+        for (int k = 0; k < nroots; ++k) out.rep[k].sigma_builds = k == 0 ? (int)sig : 0;
+    }
     // step 4 per basis: the roots it serves (root b for a state-specific basis, all for a shared one)
-    for (int b = 0; b < nb; ++b) {
+    for (int b = 0; b < nb && !lock; ++b) {
         const size_t mark = ws.mark();
         GemmScratch gscr(ws, GEMM_SCRATCH);
         std::vector<int> ks;
@@ -1666,6 +2330,7 @@ void adc3_default_opts(adc3_opts* o) {
     o->n_guess = 0;
     o->vectors_out = nullptr;
     o->dyson_out = nullptr;
+    o->lockstep = 0;
 }
 
 const char* adc3_last_error(void) { return g_msg.c_str(); }
@@ -2032,6 +2697,7 @@ static adc3_opts resolve_opts(const adc3_opts* opts) {
     if (o.fno_mode != 0 && o.fno_mode != 1) fail(ADC3_EINVAL, "opts.fno_mode must be 0 (state-specific) or 1 (MP2)");
     if (!(o.fno_keep_frac >= 0.0 && o.fno_keep_frac <= 1.0)) fail(ADC3_EINVAL, "opts.fno_keep_frac must lie in [0, 1]");
     if (o.n_guess < 0 || (o.n_guess > 0 && !o.init_guess)) fail(ADC3_EINVAL, "opts.n_guess > 0 needs opts.init_guess");
+    if (o.lockstep != 0 && o.lockstep != 1) fail(ADC3_EINVAL, "opts.lockstep must be 0 or 1");
     return o;
 }
 
@@ -2173,6 +2839,126 @@ extern "C" size_t adc3_ea_solve_batched_workspace_bytes(const adc3_instance* ins
     }
 }
 
+// The batch in lockstep (opts.lockstep): waves of one instance per slot (each slot's instances in the
+// plan's order, largest first), each wave's canonical solves built in their slots' workspace slices and
+// their Davidsons advanced together by the lockstep engine on `stream`; an instance that truncates runs
+// its own pipeline (its bases in lockstep) when its turn comes.  One host thread throughout.
+static void batched_lockstep(const adc3_instance* inst, int ninst, const adc3_opts& op, const BatchPlan& P, int nw,
+                             const std::vector<long long>& first, double* roots_out, adc3_root_report* reports,
+                             std::vector<int>& st, std::vector<std::string>& msg, void* workspace, hipStream_t s) {
+    std::vector<std::vector<int>> slot(nw);
+    {
+        std::vector<int> order(ninst);
+        for (int i = 0; i < ninst; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int b) { return instance_cost(inst[a]) > instance_cost(inst[b]); });
+        for (int i : order) slot[P.worker[i]].push_back(i);
+    }
+    size_t nwave = 0;
+    for (auto& v : slot) nwave = std::max(nwave, v.size());
+    for (size_t w = 0; w < nwave; ++w) {
+        std::vector<Arena> ar(nw);
+        std::vector<Ctx*> ctx(nw, nullptr);
+        std::vector<LockJob> jobs(nw);
+        std::vector<double*> vecs(nw, nullptr);
+        std::vector<int> who(nw, -1);
+        std::vector<LockJob*> jp;
+        for (int sl = 0; sl < nw; ++sl) {
+            if (w >= slot[sl].size()) continue;
+            const int i = slot[sl][w];
+            const adc3_instance& in = inst[i];
+            ar[sl].base = (char*)workspace + P.offset[sl];
+            ar[sl].cap = P.bytes[sl];
+            try {
+                check_dims(in.nocc, in.nvir, in.naux);
+                if (!in.eps_occ || !in.eps_vir || (!in.B && in.naux > 0)) fail(ADC3_EINVAL, "NULL pointer argument");
+                const long long N = in.nvir + (long long)in.nocc * in.nvir * in.nvir;
+                if (in.nroots < 1 || in.nroots > N) fail(ADC3_EINVAL, "nroots must be in [1, N]");
+                if (!(in.conv > 0) || !std::isfinite(in.conv)) fail(ADC3_EINVAL, "conv must be a positive number");
+                validate_inputs(in.eps_occ, in.eps_vir, in.B, in.nocc, in.nvir, in.naux, s, ar[sl]);
+                Blocks B0;
+                B0.X = in.naux; B0.o = in.nocc; B0.v = in.nvir;
+                B0.Boo = take(ar[sl], (long long)in.naux * in.nocc * in.nocc);
+                B0.Bov = take(ar[sl], (long long)in.naux * in.nocc * in.nvir);
+                B0.Bvv = take(ar[sl], (long long)in.naux * in.nvir * in.nvir);
+                k_split_B(in.B, in.naux, in.nocc, in.nvir, B0.Boo, B0.Bov, B0.Bvv, s);
+                if (truncates(in.fno_thresh, in.naf_thresh, op)) {
+                    SolveOut r = solve_impl(ar[sl], in.eps_occ, in.eps_vir, B0, in.nroots, in.fno_thresh,
+                                            in.naf_thresh, in.conv, op, s);
+                    HIPCHK(hipStreamSynchronize(s));
+                    for (int k = 0; k < in.nroots; ++k) {
+                        roots_out[first[i] + k] = r.rep[k].omega;
+                        if (reports) reports[first[i] + k] = r.rep[k];
+                    }
+                    st[i] = r.all_conv ? ADC3_OK : ADC3_WNOCONV;
+                    continue;
+                }
+                const bool df = op.ladder == 2 || (op.ladder == 0 && ladder_df_auto(in.nvir));
+                ctx[sl] = build_ctx(ar[sl], in.eps_occ, in.eps_vir, B0.Boo, B0.Bov, B0.Bvv, in.nocc, in.nvir, in.naux,
+                                    op.level, s, op.precision, df, op.level >= 3 ? op.sm_x : 1.0);
+                vecs[sl] = take(ar[sl], (long long)in.nroots * N);
+                LockJob& j = jobs[sl];
+                j.c = ctx[sl];
+                j.nroots = in.nroots; j.conv = in.conv; j.max_iter = op.max_iter; j.max_sub = op.max_subspace;
+                j.pmode = op.level >= 3 ? 0 : ((op.precond == 0) ? 0 : 3);
+                j.prec = op.precision;
+                j.vec_out = vecs[sl];
+                j.arena = &ar[sl];
+                who[sl] = i;
+                jp.push_back(&j);
+            } catch (const Error& e) {
+                g_dry = false;
+                st[i] = e.status;
+                msg[i] = e.msg;
+                if (ctx[sl]) { delete ctx[sl]; ctx[sl] = nullptr; }
+            }
+        }
+        if (!jp.empty()) {
+            try {
+                lockstep_run(jp, s, lockstep_chunk());
+                for (int sl = 0; sl < nw; ++sl) {
+                    if (who[sl] < 0) continue;
+                    const int i = who[sl];
+                    const adc3_instance& in = inst[i];
+                    const DavResult& r = jobs[sl].res;
+                    std::vector<adc3_root_report> rep(in.nroots, adc3_root_report{});
+                    const int o = in.nocc, v = in.nvir;
+                    double* xd = take(ar[sl], (long long)in.nroots * (o + v));
+                    double* tmp = take(ar[sl], (long long)o * v * v);
+                    for (int k = 0; k < in.nroots; ++k) {
+                        auto& R = rep[k];
+                        R.omega = R.omega_uncorr = r.w[k];
+                        R.omega_lowp = r.w_lowp.empty() ? r.w[k] : r.w_lowp[k];
+                        R.iters_lowp = r.iters_lowp;
+                        R.resnorm = R.err_bound = r.rn[k];
+                        R.nvir_kept = v;
+                        R.naux_kept = in.naux;
+                        R.iters = r.iters;
+                        R.sigma_builds = k == 0 ? (int)jobs[sl].sigma_builds : 0;
+                        spectral_amplitudes(ctx[sl], vecs[sl] + (long long)k * ctx[sl]->N, xd + (long long)k * (o + v),
+                                            tmp, s);
+                    }
+                    finish_amplitudes(xd, in.nroots, o + v, rep, nullptr, s);
+                    for (int k = 0; k < in.nroots; ++k) {
+                        roots_out[first[i] + k] = rep[k].omega;
+                        if (reports) reports[first[i] + k] = rep[k];
+                    }
+                    st[i] = r.converged ? ADC3_OK : ADC3_WNOCONV;
+                }
+            } catch (const Error& e) {
+                g_dry = false;
+                for (int sl = 0; sl < nw; ++sl)
+                    if (who[sl] >= 0) { st[who[sl]] = e.status; msg[who[sl]] = e.msg; }
+                if (e.status == ADC3_EHIP) {
+                    for (auto* c : ctx) delete c;
+                    throw;
+                }
+            }
+        }
+        for (auto* c : ctx) delete c;
+    }
+}
+
 extern "C" int adc3_ea_solve_batched(const adc3_instance* inst, int ninst, const adc3_opts* opts, int nstreams,
                                      double* roots_out, adc3_root_report* reports, int* status_out, void* workspace,
                                      size_t ws_bytes, hipStream_t stream) {
@@ -2184,6 +2970,24 @@ extern "C" int adc3_ea_solve_batched(const adc3_instance* inst, int ninst, const
     if (P.total > ws_bytes) fail(ADC3_ENOMEM, "workspace too small: need " + std::to_string(P.total) + " bytes");
     std::vector<long long> first(ninst + 1, 0);
     for (int i = 0; i < ninst; ++i) first[i + 1] = first[i] + std::max(inst[i].nroots, 0);
+    if (op.lockstep) {
+        std::vector<int> st(ninst, ADC3_OK);
+        std::vector<std::string> msg(ninst);
+        batched_lockstep(inst, ninst, op, P, nw, first, roots_out, reports, st, msg, workspace, stream);
+        int worst = ADC3_OK;
+        std::string first_msg;
+        for (int i = 0; i < ninst; ++i) {
+            if (status_out) status_out[i] = st[i];
+            if (st[i] < 0 && (worst >= 0 || st[i] < worst)) {
+                if (first_msg.empty()) first_msg = "instance " + std::to_string(i) + ": " + msg[i];
+                worst = st[i];
+            } else if (st[i] == ADC3_WNOCONV && worst == ADC3_OK) {
+                worst = ADC3_WNOCONV;
+            }
+        }
+        if (worst < 0) set_error(first_msg);
+        return worst;
+    }
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     hipEvent_t ready;

@@ -382,7 +382,125 @@ __global__ void diag_adc_kernel(double* diag, const double* M11, const double* e
         }
     }
 }
+// ---- fixed-shape block Davidson: convergence and masking decided on the device ----
+// directions j < m with valid[j] == 0 are decoupled: their row and column of the Gram matrix are
+// zeroed and their diagonal set above every eigenvalue of the valid block (its Gershgorin bound plus a
+// margin), so their Ritz values sort after every real one without swamping the eigensolver's norms;
+// cnt[0] = number of valid directions.  One workgroup.
+__global__ void mask_gram_kernel(double* G, int m, const double* valid, double* cnt) {
+    __shared__ double bnd[256];
+    double b = -INFINITY;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        if (valid[i] == 0.0) continue;
+        double r = G[(long long)i * m + i];
+        for (int j = 0; j < m; ++j)
+            if (j != i && valid[j] != 0.0) r += fabs(G[(long long)i * m + j]);
+        b = fmax(b, r);
+    }
+    bnd[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) bnd[threadIdx.x] = fmax(bnd[threadIdx.x], bnd[threadIdx.x + h]);
+        __syncthreads();
+    }
+    const double top = bnd[0];
+    const double shift = isfinite(top) ? top + 1.0 + fabs(top) : 1.0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < m * m; t += blockDim.x) {
+        const int i = t / m, j = t % m;
+        if (valid[i] == 0.0 || valid[j] == 0.0) G[t] = (i == j) ? shift : 0.0;
+    }
+    if (threadIdx.x == 0) {
+        int n = 0;
+        for (int i = 0; i < m; ++i) n += valid[i] != 0.0;
+        cnt[0] = (double)n;
+    }
+}
+
+// one workgroup: per root k, rn = sqrt(Gw[k][k]), converged when rn <= conv and |th - thold| <= conv;
+// active[k] = !converged; thold = th; status = [all converged, all finite, rn[nroots], th[nroots]]
+__global__ void dav_status_kernel(const double* Gw, int nroots, const double* th, double* thold, double conv,
+                                  double* active, double* status) {
+    __shared__ unsigned char okf[64], finf[64];
+    for (int k = threadIdx.x; k < nroots; k += blockDim.x) {
+        const double rn = sqrt(fmax(Gw[(long long)k * nroots + k], 0.0));
+        const double w = th[k];
+        const bool fin = isfinite(rn) && isfinite(w);
+        const bool ok = fin && rn <= conv && fabs(w - thold[k]) <= conv;
+        active[k] = ok ? 0.0 : 1.0;
+        thold[k] = w;
+        status[2 + k] = rn;
+        status[2 + nroots + k] = w;
+        okf[k] = ok;
+        finf[k] = fin;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nconv = 0, nfin = 0;
+        for (int k = 0; k < nroots; ++k) { nconv += okf[k]; nfin += finf[k]; }
+        status[0] = nconv == nroots ? 1.0 : 0.0;
+        status[1] = nfin == nroots ? 1.0 : 0.0;
+    }
+}
+
+// rows j of T[nn][n] with active[j] == 0 set to zero
+__global__ void rows_mask_kernel(double* T, int nn, long long n, const double* active) {
+    const long long tot = (long long)nn * n;
+    GRID_STRIDE(t, tot) {
+        if (active[t / n] == 0.0) T[t] = 0.0;
+    }
+}
+
+// Loewdin coefficients over all nn directions: column q = U[:, q] / sqrt(w[q]) if w[q] > thr, else 0;
+// valid[q] = (w[q] > thr)
+__global__ void lowdin_masked_kernel(double* coef, const double* U, const double* w, int nn, double thr,
+                                     double* valid) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nn * nn) return;
+    const int q = t % nn;
+    const bool keep = w[q] > thr && isfinite(w[q]);
+    coef[t] = keep ? U[t] / sqrt(w[q]) : 0.0;
+    if (t < nn) valid[t] = (w[t] > thr && isfinite(w[t])) ? 1.0 : 0.0;
+}
+
+// after a Rayleigh-Ritz sorted ascending, the first cnt[0] Ritz vectors are the valid ones
+__global__ void valid_first_kernel(double* valid, int n, const double* cnt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) valid[t] = t < (int)cnt[0] ? 1.0 : 0.0;
+}
 }  // namespace
+
+void k_mask_gram(double* G, int m, const double* valid, double* cnt, hipStream_t s) {
+    if (g_dry || m <= 0) return;
+    hipLaunchKernelGGL(mask_gram_kernel, dim3(1), dim3(256), 0, s, G, m, valid, cnt);
+    LAUNCHCHK();
+}
+void k_dav_status(const double* Gw, int nroots, const double* th, double* thold, double conv, double* active,
+                  double* status, hipStream_t s) {
+    if (g_dry || nroots <= 0) return;
+    if (nroots > 64) fail(-1, "dav_status: at most 64 roots");
+    hipLaunchKernelGGL(dav_status_kernel, dim3(1), dim3(64), 0, s, Gw, nroots, th, thold, conv, active, status);
+    LAUNCHCHK();
+}
+void k_rows_mask(double* T, int nn, long long n, const double* active, hipStream_t s) {
+    if (g_dry) return;
+    const long long t = (long long)nn * n;
+    if (t <= 0) return;
+    hipLaunchKernelGGL(rows_mask_kernel, dim3(nblocks(t)), dim3(NT), 0, s, T, nn, n, active);
+    LAUNCHCHK();
+}
+void k_lowdin_masked(double* coef, const double* U, const double* w, int nn, double thr, double* valid,
+                     hipStream_t s) {
+    if (g_dry || nn <= 0) return;
+    hipLaunchKernelGGL(lowdin_masked_kernel, dim3((nn * nn + 255) / 256), dim3(256), 0, s, coef, U, w, nn, thr,
+                       valid);
+    LAUNCHCHK();
+}
+void k_valid_first(double* valid, int n, const double* cnt, hipStream_t s) {
+    if (g_dry || n <= 0) return;
+    hipLaunchKernelGGL(valid_first_kernel, dim3((n + 255) / 256), dim3(256), 0, s, valid, n, cnt);
+    LAUNCHCHK();
+}
 
 void k_fill(double* x, long long n, double v, hipStream_t s) {
     if (g_dry) return;

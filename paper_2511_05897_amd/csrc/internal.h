@@ -194,6 +194,19 @@ void k_scale_vec(double* x, long long n, const double* factor_dev, hipStream_t s
 void k_rscale_rows(double* T, int nn, long long n, const double* G, int ldg, hipStream_t s);
 // coef[j*keep + q] = U[j*acc + q] / sqrt(w[q]),  j < acc, q < keep
 void k_lowdin_coef(double* coef, const double* U, const double* w, int acc, int keep, hipStream_t s);
+// fixed-shape block Davidson helpers (no host decisions):
+// G[m][m]: rows/columns of directions with valid[j] == 0 zeroed, their diagonal set above the valid
+// block's Gershgorin bound; cnt[0] = number of valid directions
+void k_mask_gram(double* G, int m, const double* valid, double* cnt, hipStream_t s);
+// per root: rn = sqrt(Gw[k][k]), converged = rn <= conv && |th - thold| <= conv; active = !converged;
+// thold = th; status = [all converged, all finite, rn[nroots], th[nroots]]  (one workgroup)
+void k_dav_status(const double* Gw, int nroots, const double* th, double* thold, double conv, double* active,
+                  double* status, hipStream_t s);
+void k_rows_mask(double* T, int nn, long long n, const double* active, hipStream_t s);  // zero inactive rows
+// coef[j*nn + q] = U[j*nn + q] / sqrt(w[q]) for w[q] > thr, else 0; valid[q] = w[q] > thr
+void k_lowdin_masked(double* coef, const double* U, const double* w, int nn, double thr, double* valid,
+                     hipStream_t s);
+void k_valid_first(double* valid, int n, const double* cnt, hipStream_t s);  // valid[t] = t < cnt[0]
 // flags[0] = 1 if any non-finite; flags[1] = max |B_Qpq - B_Qqp|; flags[2] = max |B|
 void k_check_B(const double* B, int X, int n, double* flags, hipStream_t s);
 // z -> x = z_S + z_A/sqrt3 and xt = 2x - x^T  (blocks of v*v)
