@@ -37,8 +37,12 @@ def parse():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner study")
     ap.add_argument("--learned-full", action="store_true",
                     help="also compare the learned preconditioner with Jacobi at o=30 v=400 X=1200 (251 GB)")
-    ap.add_argument("--batched", type=int, default=0,
+    ap.add_argument("--batched", type=int, default=64,
                     help="also solve the first N instances of the ragged batched workload (seeds 100..; 0 = skip)")
+    ap.add_argument("--batched-threads", action="store_true",
+                    help="also run the batched workload with one host thread per worker stream (no lockstep)")
+    ap.add_argument("--no-lockstep", action="store_true",
+                    help="skip the headline workload's solve with the per-root bases in lockstep")
     ap.add_argument("--large-mixed", type=float, default=0.0,
                     help="also run the FP64 / FP32 / BF16 Davidson study of the o=40 v=600 X=1800 workload "
                          "with B scaled by this factor (about 12 minutes; 0 = skip)")
@@ -152,35 +156,52 @@ def learned_study(adc, d, torch, np):
     return {"scale": scale, "level": 3, "nroots": nroots, "conv": 1e-6, "shapes": out}
 
 
-def batched_study(adc, d, torch, np, n):
+def batched_study(adc, d, torch, np, n, modes=(1,)):
     """The ragged batched workload: instances of seeds 100.. (nocc~U{5..30}, nvir~U{50..300},
-    naux = 3 nvir, literal scale), 8 roots, conv 1e-6, FP32 ladder, sigma graphs, 2 worker streams."""
+    naux = 3 nvir, literal scale), 8 roots, conv 1e-6, FP32 ladder, 2 worker slots.  Mode 1: the
+    lockstep block Davidson (waves of two instances, a chunk of iterations of both per graph replay,
+    device-side convergence flags); mode 0: one host thread per worker stream, sigma passes replayed
+    from graphs.  Instance generation is not timed."""
     import synth
     inst = []
+    g0 = time.perf_counter()
     for s in range(100, 100 + n):
         eo, ev, B = synth.batch_instance(s)
         inst.append(dict(eps_occ=d(eo), eps_vir=d(ev), B=d(B), nroots=8, conv=1e-6))
         del B
-    o = adc.adc3_default_opts()
-    o.precision = 1
-    o.sigma_graphs = 1
-    side = torch.cuda.Stream()
-    with torch.cuda.stream(side):
-        nbytes = adc.adc3_ea_solve_batched_workspace_bytes(inst, o, 2)
-        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        roots, reps, sts, st = adc.adc3_ea_solve_batched(inst, o, 2, workspace=ws)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-    sig = sum(r["sigma_builds"] for rr in reps for r in rr)
+    gen_s = time.perf_counter() - g0
     sum_n = sum(int(x["eps_vir"].numel()) * (1 + int(x["eps_occ"].numel()) * int(x["eps_vir"].numel())) for x in inst)
-    del ws
-    torch.cuda.empty_cache()
-    return {"instances": n, "seeds": "100-%d" % (99 + n), "nroots": 8, "conv": 1e-6, "precision": "fp32 ladder",
-            "streams": 2, "sigma_graphs": True, "sum_N": sum_n, "workspace_GB": nbytes / 1e9, "time_s": dt,
-            "status": st, "statuses_ok": sum(1 for x in sts if x == 0), "sigma_builds": sig,
-            "sigma_builds_per_s": sig / dt, "iterations": [rr[0]["iters"] for rr in reps]}
+    out = {"instances": n, "seeds": "100-%d" % (99 + n), "nroots": 8, "conv": 1e-6, "precision": "fp32 ladder",
+           "slots": 2, "sum_N": sum_n, "generation_s_untimed": gen_s}
+    ref = None
+    for mode in modes:
+        o = adc.adc3_default_opts()
+        o.precision = 1
+        o.sigma_graphs = 1
+        o.lockstep = mode
+        side = torch.cuda.Stream()
+        with torch.cuda.stream(side):
+            nbytes = adc.adc3_ea_solve_batched_workspace_bytes(inst, o, 2)
+            ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            roots, reps, sts, st = adc.adc3_ea_solve_batched(inst, o, 2, workspace=ws)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        sig = sum(r["sigma_builds"] for rr in reps for r in rr)
+        res = {"time_s": dt, "workspace_GB": nbytes / 1e9, "status": st, "statuses": [int(x) for x in sts],
+               "statuses_ok": sum(1 for x in sts if x == 0), "sigma_builds": sig, "sigma_builds_per_s": sig / dt,
+               "iterations": [rr[0]["iters"] for rr in reps],
+               "max_resnorm": float(max(r["resnorm"] for rr in reps for r in rr))}
+        if ref is None:
+            ref = roots
+        else:
+            res["max_rel_root_diff_vs_first_mode"] = float(max(
+                np.abs(a - b).max() / max(1.0, np.abs(a).max()) for a, b in zip(ref, roots)))
+        out["lockstep" if mode else "threads"] = res
+        del ws
+        torch.cuda.empty_cache()
+    return out
 
 
 def learned_full_size(adc, d, torch, np, scale):
@@ -383,9 +404,41 @@ def cpu_baseline(shape, nvec):
     P.sigma(r, 3)
     dt = time.perf_counter() - t0
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    # the oracle's whole solve of the tiny dense workload (o=4, v=20, X=60: every ADC(3) intermediate,
+    # the dense 1620 x 1620 matrix and its full diagonalisation)
+    p1, eo1, ev1, B1 = synth.preset("tiny-dense")
+    t1 = time.perf_counter()
+    M = Problem(eo1, ev1, B1).dense(3)
+    np.linalg.eigvalsh(0.5 * (M + M.T))
+    tiny_s = time.perf_counter() - t1
     return {"value": nvec / dt, "unit": "sigma-builds/s", "cores": int(threads), "kind": "oracle",
             "sample": "%d ADC(3) sigma vectors, o=%d v=%d X=%d (the SS-FNO/NAF basis shape of the workload), "
-                      "NumPy FP64; intermediates built once, untimed; %.2f s" % (nvec, o, v, X, dt)}
+                      "NumPy FP64; intermediates built once, untimed; %.2f s" % (nvec, o, v, X, dt),
+            "compare_with": "sigma_adc3_isolated (the same sigma shape on the GPU)",
+            "time_to_roots_tiny_dense_s": tiny_s, "host": host_info()}
+
+
+def host_info():
+    """CPU model, logical CPUs and the BLAS NumPy links (for the CPU baseline record)."""
+    import numpy as np
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = ""
+    try:
+        cfg = np.show_config(mode="dicts")
+        b = cfg.get("Build Dependencies", {}).get("blas", {})
+        blas = "%s %s" % (b.get("name", ""), b.get("version", ""))
+    except Exception:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "blas": blas.strip(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def main():
@@ -437,10 +490,12 @@ def main():
     torch.cuda.synchronize()
     adc.adc3_profile_enable(True)
     nsig = 0
+    nsig3 = 0
     t0 = time.perf_counter()
     for k in range(a.steps):
         roots, reps, st = run()
         nsig += sum(r["sigma_builds"] for r in reps)
+        nsig3 += sum(r["sigma_builds_final"] for r in reps)
         print("step %d done" % k, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
@@ -513,6 +568,31 @@ def main():
         except Exception as e:
             mixed["ladder_dominated_davidson"] = {"error": str(e)}
 
+    # the same solve with the five roots' truncated bases solved together (lockstep block Davidson:
+    # their ADC(2) solves in one graph-replayed Davidson, then their ADC(3) solves)
+    lockstep = None
+    if not a.no_lockstep:
+        try:
+            ol = adc.adc3_default_opts()
+            ol.lockstep = 1
+            wsl = torch.empty(adc.adc3_ea_solve_workspace_bytes(p["nocc"], p["nvir"], p["naux"], nroots, ol),
+                              dtype=torch.uint8, device="cuda")
+            adc.adc3_ea_solve(teo, tev, tB, nroots, p["fno_thresh"], p["naf_thresh"], p["conv"], ol, workspace=wsl)
+            torch.cuda.synchronize()
+            l0 = time.perf_counter()
+            rl, repl, stl = adc.adc3_ea_solve(teo, tev, tB, nroots, p["fno_thresh"], p["naf_thresh"], p["conv"], ol,
+                                              workspace=wsl)
+            torch.cuda.synchronize()
+            ldt = time.perf_counter() - l0
+            lockstep = {"time_to_roots_s": ldt, "speedup_vs_sequential": (dt / a.steps) / ldt, "status": stl,
+                        "sigma_builds": sum(r["sigma_builds"] for r in repl),
+                        "max_abs_root_diff_vs_sequential_Eh": float(np.abs(rl - roots).max()),
+                        "workspace_GB": wsl.numel() / 1e9}
+            del wsl
+            torch.cuda.empty_cache()
+        except Exception as e:
+            lockstep = {"error": str(e)}
+
     # the same workload with B scaled into the weakly correlated regime (SS-FNO then truncates)
     variant = None
     if a.variant_scale > 0:
@@ -557,7 +637,7 @@ def main():
         ws = None
         torch.cuda.empty_cache()
         try:
-            batched = batched_study(adc, d, torch, np, a.batched)
+            batched = batched_study(adc, d, torch, np, a.batched, (1, 0) if a.batched_threads else (1,))
         except Exception as e:
             batched = {"error": str(e)}
     large = None
@@ -590,6 +670,11 @@ def main():
                    "nvir_kept": [r["nvir_kept"] for r in reps], "naux_kept": [r["naux_kept"] for r in reps]},
         "roots": [float(x) for x in roots],
         "status": st,
+        # the sigma builds above mix the cheap ADC(2) solves (canonical and truncated) with the ADC(3) ones;
+        # these count the ADC(3) sigma vectors alone over the same timed wall time
+        "sigma_builds_per_step": nsig / a.steps,
+        "sigma_builds_adc3_per_step": nsig3 / a.steps,
+        "sigma_adc3_per_s_whole_solve": nsig3 / dt,
         "roofline": {"kernel": "sigma ladder (ladder_f64t_kernel; ladder_f64_kernel for row tiles of <= 32 rows)",
                      "bound": "mfma",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
@@ -606,6 +691,7 @@ def main():
                                "sigma": sig_ms / a.steps, "ladder": lad_ms / a.steps,
                                "large_eig": eig_ms / a.steps},
         "sigma_adc3_isolated": iso,
+        "lockstep": lockstep,
         "mixed_precision": mixed,
         "variant_weak_correlation": variant,
         "learned_preconditioner": learned,

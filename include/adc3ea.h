@@ -125,7 +125,9 @@ typedef struct {
     int nvir_kept;         /* virtuals kept by SS-FNO (eq 11) */
     int naux_kept;         /* auxiliary functions kept by NAF (eq 29) */
     int iters;             /* Davidson iterations of the ADC(3) solve */
-    int sigma_builds;      /* sigma vectors built for this root (all solves) */
+    int sigma_builds;      /* sigma vectors built by the solves of this root's basis (all phases); a solve
+                              shared by several roots counts on the first of them only, so the sum over
+                              the roots is the call's total */
     double omega_lowp;     /* precision 1/2: root k when the reduced-precision phase ended */
     int iters_lowp;        /* precision 1/2: Davidson iterations in the reduced-precision phase */
     double err_bound;      /* bound on |omega - the same combination of exact eigenvalues of the FP64
@@ -135,6 +137,7 @@ typedef struct {
                               every precision the last Davidson phase runs FP64 sigma, so it also bounds the
                               mixed-precision result's distance from the FP64 one */
     double pole_strength;  /* sum_p x_kp^2 of the root's spectral amplitudes (eq 7) */
+    int sigma_builds_final; /* the part of sigma_builds made by the final-level (ADC(3) or sm-ADC) solves */
 } adc3_root_report;
 
 void adc3_default_opts(adc3_opts* opts);

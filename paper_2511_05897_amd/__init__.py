@@ -54,7 +54,8 @@ class adc3_root_report(ctypes.Structure):
                 ("omega_adc2_can", ctypes.c_double), ("omega_adc2_fno", ctypes.c_double),
                 ("resnorm", ctypes.c_double), ("nvir_kept", ctypes.c_int), ("naux_kept", ctypes.c_int),
                 ("iters", ctypes.c_int), ("sigma_builds", ctypes.c_int), ("omega_lowp", ctypes.c_double),
-                ("iters_lowp", ctypes.c_int), ("err_bound", ctypes.c_double), ("pole_strength", ctypes.c_double)]
+                ("iters_lowp", ctypes.c_int), ("err_bound", ctypes.c_double), ("pole_strength", ctypes.c_double),
+                ("sigma_builds_final", ctypes.c_int)]
 
 
 class ADCError(RuntimeError):

@@ -1883,7 +1883,8 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             R.nvir_kept = v;
             R.naux_kept = X;
             R.iters = r.iters;
-            R.sigma_builds = (int)c->sigma_count;
+            R.sigma_builds = k == 0 ? (int)c->sigma_count : 0;  // the solve's sigma builds, counted once
+            R.sigma_builds_final = R.sigma_builds;
         }
         out.all_conv = r.converged;
         delete c;
@@ -2026,7 +2027,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         }
         std::vector<int> match(nroots, 0);
         std::vector<DavResult> a2(nb);
-        long long sig = 0;
+        long long sig = 0, sig3 = 0;
         {
             const size_t m2 = ws.mark();
             std::vector<Ctx*> c2(nb, nullptr);
@@ -2115,6 +2116,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
                 const DavResult& a3 = jobs[b].res;
                 const int vk = vks[b];
                 sig += jobs[b].sigma_builds;
+                sig3 += jobs[b].sigma_builds;
                 out.all_conv = out.all_conv && a3.converged;
                 double* xk = take(ws, o + vk);
                 double* tmp = take(ws, (long long)o * vk * vk);
@@ -2142,7 +2144,10 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             for (int b = 0; b < nb; ++b) delete c3[b];
             ws.release(m3);
         }
-        for (int k = 0; k < nroots; ++k) out.rep[k].sigma_builds = k == 0 ? (int)sig : 0;
+        for (int k = 0; k < nroots; ++k) {
+            out.rep[k].sigma_builds = k == 0 ? (int)sig : 0;
+            out.rep[k].sigma_builds_final = k == 0 ? (int)sig3 : 0;
+        }
     }
     // step 4 per basis: the roots it serves (root b for a state-specific basis, all for a shared one)
     for (int b = 0; b < nb && !lock; ++b) {
@@ -2165,7 +2170,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         VLOG("basis %d: kept %d virtuals, %d auxiliary functions", b, vk, xk);
         const long long Nk = vk + (long long)o * vk * vk;
         if (nroots > Nk) fail(ADC3_EINVAL, "truncated space smaller than nroots");
-        int sig = 0;
+        int sig = 0, sig3 = 0;
         std::vector<int> match(nroots, 0);
         // the canonical ADC(2) vectors carried into the truncated basis (r1 U, U^T z_i U): vector k is
         // the reference for root matching, all of them start the truncated ADC(2) solve, whose vectors
@@ -2269,10 +2274,14 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             }
             out.all_conv = out.all_conv && a3.converged;
             sig += (int)c3->sigma_count;
+            sig3 = (int)c3->sigma_count;
             delete c3;
             ws.release(m3);
         }
-        for (size_t j = 0; j < ks.size(); ++j) out.rep[ks[j]].sigma_builds = j == 0 ? sig : 0;
+        for (size_t j = 0; j < ks.size(); ++j) {
+            out.rep[ks[j]].sigma_builds = j == 0 ? sig : 0;
+            out.rep[ks[j]].sigma_builds_final = j == 0 ? sig3 : 0;
+        }
         ws.release(mark);
     }
     out.rep[0].sigma_builds += sig0;
@@ -2701,7 +2710,9 @@ static adc3_opts resolve_opts(const adc3_opts* opts) {
     return o;
 }
 
-static void plan_solve(int nocc, int nvir, int naux, int nroots, const adc3_opts& op, Arena& ws) {
+// Workspace plan of one solve (a dry run with allocations counted): path 0 the canonical solve only,
+// 1 the truncated pipeline only, 2 both (thresholds not known yet).
+static void plan_solve(int nocc, int nvir, int naux, int nroots, const adc3_opts& op, Arena& ws, int path = 2) {
     g_dry = true;
     const long long n = nocc + nvir;
     Blocks B0;
@@ -2710,11 +2721,15 @@ static void plan_solve(int nocc, int nvir, int naux, int nroots, const adc3_opts
     B0.Bov = take(ws, (long long)naux * nocc * nvir);
     B0.Bvv = take(ws, (long long)naux * nvir * nvir);
     (void)n;
-    solve_impl(ws, nullptr, nullptr, B0, nroots, 1.0, 1.0, 1.0, op, nullptr);   // truncation path
-    Arena ws2;
-    ws2.used = 0;
-    solve_impl(ws2, nullptr, nullptr, B0, nroots, 0.0, 0.0, 1.0, op, nullptr); // canonical path
-    ws.peak = std::max(ws.peak, ws2.peak + (size_t)(3 * naux * n * n * sizeof(double)));
+    adc3_opts oc = op;
+    oc.fno_keep_frac = 0.0;  // the canonical path's plan must not take the truncated route
+    if (path != 0) solve_impl(ws, nullptr, nullptr, B0, nroots, 1.0, 1.0, 1.0, op, nullptr);  // truncation path
+    if (path != 1) {
+        Arena ws2;
+        ws2.used = 0;
+        solve_impl(ws2, nullptr, nullptr, B0, nroots, 0.0, 0.0, 1.0, oc, nullptr);  // canonical path
+        ws.peak = std::max(ws.peak, ws2.peak + (size_t)(3 * naux * n * n * sizeof(double)));
+    }
     g_dry = false;
 }
 
@@ -2747,7 +2762,7 @@ static int solve_one(const double* eps_occ, const double* eps_vir, const double*
     ws.cap = ws_bytes;
     {
         Arena plan;
-        plan_solve(nocc, nvir, naux, nroots, op, plan);
+        plan_solve(nocc, nvir, naux, nroots, op, plan, truncates(fno_thresh, naf_thresh, op) ? 1 : 0);
         if (plan.peak > ws_bytes) fail(ADC3_ENOMEM, "workspace too small: need " + std::to_string(plan.peak) + " bytes");
     }
     validate_inputs(eps_occ, eps_vir, B, nocc, nvir, naux, stream, ws);
@@ -2813,7 +2828,8 @@ BatchPlan plan_batch(const adc3_instance* inst, int ninst, const adc3_opts& op, 
         load[w] += instance_cost(inst[i]);
         check_dims(inst[i].nocc, inst[i].nvir, inst[i].naux);
         Arena plan;
-        plan_solve(inst[i].nocc, inst[i].nvir, inst[i].naux, inst[i].nroots, op, plan);
+        plan_solve(inst[i].nocc, inst[i].nvir, inst[i].naux, inst[i].nroots, op, plan,
+                   truncates(inst[i].fno_thresh, inst[i].naf_thresh, op) ? 1 : 0);
         P.bytes[w] = std::max(P.bytes[w], (plan.peak + (1 << 20) + 255) / 256 * 256);
     }
     P.offset.assign(nworkers, 0);
@@ -2934,7 +2950,7 @@ static void batched_lockstep(const adc3_instance* inst, int ninst, const adc3_op
                         R.nvir_kept = v;
                         R.naux_kept = in.naux;
                         R.iters = r.iters;
-                        R.sigma_builds = k == 0 ? (int)jobs[sl].sigma_builds : 0;
+                        R.sigma_builds = R.sigma_builds_final = k == 0 ? (int)jobs[sl].sigma_builds : 0;
                         spectral_amplitudes(ctx[sl], vecs[sl] + (long long)k * ctx[sl]->N, xd + (long long)k * (o + v),
                                             tmp, s);
                     }

@@ -15,6 +15,8 @@
 //   * K is split into chunks (deterministic partial sums, reduced in a fixed order) to
 //     give >= 4 workgroups per CU slot; with a multiple of 8 chunks, the workgroups that
 //     one XCD runs together share one chunk of Z in that XCD's L2.
+// The chunk count and the row tiling (the default, or one more, shorter row tile) are chosen
+// per shape by measurement on first use (ladder_tuned_chunks).
 // Two FP64 forms: ladder_f64_kernel takes Z row-major and stages both tiles through
 // registers into double-buffered LDS (16-byte loads, the Z tile transposed to [k][m] on the
 // way, so that the 16 lanes of a fragment read 16 consecutive words); ladder_f64t_kernel
@@ -698,6 +700,25 @@ void ladder_rows(int M, int& tm, int& mtiles) {
     tm = (M + 16 * mtiles - 1) / (16 * mtiles);
 }
 
+namespace {
+thread_local int t_trial_rows = 0;  // row-tile count of a tuner trial launch (0: none)
+}
+static int tuned_rows(int prec, int M, int N, int K);
+
+// The row tiling a launch uses: the tuner's measured choice for the shape (more, shorter tiles: G
+// streamed once per tile, more workgroups) where it has one, else the default above.
+static void rows_for(int prec, int M, int N, int K, int& tm, int& mtiles) {
+    ladder_rows(M, tm, mtiles);
+    const int mt = t_trial_rows > 0 ? t_trial_rows : tuned_rows(prec, M, N, K);
+    if (mt > mtiles) {
+        const int t = (M + 16 * mt - 1) / (16 * mt);
+        if (t >= 1 && t <= 8) {
+            tm = t;
+            mtiles = mt;
+        }
+    }
+}
+
 bool ladder_supported(int M, int N, int K, const double* Z, long long ldz, const double* G, long long ldg,
                       const double* C, long long ldc) {
     auto al16 = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
@@ -725,7 +746,7 @@ void ladder_gemm_lp(int prec, int M, int N, int K, double alpha, const void* Z, 
                     long long partial_elems, hipStream_t s, bool trial) {
     if (g_dry || M <= 0 || N <= 0) return;
     int tm, mtiles;
-    ladder_rows(M, tm, mtiles);
+    rows_for(prec, M, N, K, tm, mtiles);
     nchunk = std::max(1, std::min(nchunk, (K + 255) / 256));
     if (nchunk > 1 && (!partial || (long long)nchunk * M * N > partial_elems)) nchunk = 1;
     LadderLP a;
@@ -744,7 +765,7 @@ void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long l
                  hipStream_t s, int tag) {
     if (g_dry || M <= 0 || N <= 0) return;
     int tm, mtiles;
-    ladder_rows(M, tm, mtiles);
+    rows_for(0, M, N, K, tm, mtiles);
     nchunk = std::max(1, std::min(nchunk, (K + 255) / 256));
     if (nchunk > 1 && (!partial || (long long)nchunk * M * N > partial_elems)) nchunk = 1;
     LadderArgs a;
@@ -797,7 +818,7 @@ bool ladder_gemm_t(int M, int N, int K, double alpha, const double* Zt, long lon
     if (nchunk > 1 && (!partial || (long long)nchunk * M * N > partial_elems)) return false;
     if (g_dry) return true;
     int tm, mtiles;
-    ladder_rows(M, tm, mtiles);
+    rows_for(3, M, N, K, tm, mtiles);
     LadderArgs a;
     a.Z = Zt; a.ldz = ldz; a.G = G; a.ldg = ldg; a.C = C; a.ldc = ldc; a.P = partial;
     a.M = M; a.N = N; a.K = K;
@@ -839,7 +860,7 @@ bool ladder_gemm_t32(int M, int N, int K, double alpha, const float* Zt, long lo
     if (nchunk > 1 && (!partial || (long long)nchunk * M * N > partial_elems)) return false;
     if (g_dry) return true;
     int tm, mtiles;
-    ladder_rows(M, tm, mtiles);
+    rows_for(4, M, N, K, tm, mtiles);
     LadderLP a;
     a.Z = Zt; a.ldz = ldz; a.G = G; a.ldg = ldg; a.C = C; a.ldc = ldc; a.P = partial;
     a.M = M; a.N = N; a.K = K;
@@ -901,6 +922,8 @@ void load_cache() {
     std::fclose(f);
 }
 
+std::string rows_key(const std::string& key) { return key + " rows"; }
+
 void store_cache(const std::string& key, int v) {
     const char* path = std::getenv("ADC3_TUNE_CACHE");
     if (!path || !*path) return;
@@ -910,6 +933,15 @@ void store_cache(const std::string& key, int v) {
     std::fclose(f);
 }
 }  // namespace
+
+static int tuned_rows(int prec, int M, int N, int K) {
+    if (g_dry) return 0;
+    const std::string key = rows_key(tune_key(prec, M, N, K));
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache();
+    auto it = g_tune.find(key);
+    return it == g_tune.end() ? 0 : it->second;
+}
 
 static void ladder_run(int prec, int M, int N, int K, const void* Z, long long ldz, const void* G, long long ldg,
                        double* C, long long ldc, int nchunk, double* partial, long long pe, hipStream_t s) {
@@ -951,27 +983,46 @@ int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long 
         cand.push_back(c);
     }
     if (cand.empty()) return std::max(nmin, 1);
+    // row tilings: the default (fewest tiles), and one more, shorter tile (twice the workgroups for a
+    // single tile, G streamed once more) where K chunks alone cannot give the chip 512 workgroups
+    int tm0, mt0;
+    ladder_rows(M, tm0, mt0);
+    std::vector<int> rows{mt0};
+    const long long ntn = (N + LBN - 1) / LBN;
+    if (M > 16 * mt0 && ntn * mt0 * cand.back() < 512) rows.push_back(mt0 + 1);
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    int best = cand.empty() ? 1 : cand[0];
+    int best = cand[0], best_rows = mt0;
     float best_ms = 1e30f;
-    for (int c : cand) {
-        ladder_run(prec, M, N, K, Z, ldz, G, ldg, C, ldc, c, partial, partial_elems, s);  // warm-up
-        HIPCHK(hipEventRecord(e0, s));
-        for (int rep = 0; rep < 2; ++rep) ladder_run(prec, M, N, K, Z, ldz, G, ldg, C, ldc, c, partial, partial_elems, s);
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best_ms) { best_ms = ms; best = c; }
+    try {
+        for (int mt : rows) {
+            t_trial_rows = mt;
+            for (int c : cand) {
+                ladder_run(prec, M, N, K, Z, ldz, G, ldg, C, ldc, c, partial, partial_elems, s);  // warm-up
+                HIPCHK(hipEventRecord(e0, s));
+                for (int rep = 0; rep < 2; ++rep)
+                    ladder_run(prec, M, N, K, Z, ldz, G, ldg, C, ldc, c, partial, partial_elems, s);
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) { best_ms = ms; best = c; best_rows = mt; }
+            }
+        }
+    } catch (...) {
+        t_trial_rows = 0;
+        throw;
     }
+    t_trial_rows = 0;
     HIPCHK(hipEventDestroy(e0));
     HIPCHK(hipEventDestroy(e1));
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[key] = best;
+        g_tune[rows_key(key)] = best_rows;
         store_cache(key, best);
+        store_cache(rows_key(key), best_rows);
     }
     return best;
 }
