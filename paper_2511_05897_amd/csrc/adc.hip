@@ -149,6 +149,8 @@ struct Ctx {
 };
 
 static double* take(Arena& ws, long long n) { return ws.take<double>((size_t)std::max<long long>(n, 1)); }
+// stand-in vectors of the counting dry runs (never dereferenced: no work is issued in a dry run)
+static double* dry_vec() { return reinterpret_cast<double*>(ARENA_COUNT_BASE); }
 
 // The ladder is assembled from Bvv in each application (instead of stored) when the stored blocks
 // (about v^4 / 2 elements) would not leave room for the rest: above 96 GB in FP64 (v > 393).
@@ -702,7 +704,7 @@ static size_t sigma_region_bytes(Ctx* c) {
     size_t peak = 0;
     for (int p : {0, c->prec, c->Bvv32 ? 1 : 0}) {
         Arena count;
-        sigma_pass(c, count, nullptr, nullptr, NVMAX, nullptr, p);
+        sigma_pass(c, count, dry_vec(), dry_vec(), NVMAX, nullptr, p);
         peak = std::max(peak, count.peak);
     }
     g_dry = was;
@@ -1402,7 +1404,7 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
         for (auto* j : jobs) {
             lock_alloc(*j, *j->arena);
             Arena w = j->c->ws;
-            sigma_impl(j->c, w, nullptr, nullptr, std::min(NVMAX, j->nguess), nullptr, j->prec);
+            sigma_impl(j->c, w, dry_vec(), dry_vec(), std::min(NVMAX, j->nguess), nullptr, j->prec);
         }
         return;
     }
@@ -2361,12 +2363,12 @@ size_t adc3_ea_setup_workspace_bytes_ex(int nocc, int nvir, int naux, int level,
         g_dry = true;
         const long long n = nocc + nvir;
         take(ws, (long long)naux * n * n);  // split blocks of the public setup
-        Ctx* c = build_ctx(ws, nullptr, nullptr, nullptr, nullptr, nullptr, nocc, nvir, naux, level, nullptr, precision,
+        Ctx* c = build_ctx(ws, dry_vec(), dry_vec(), dry_vec(), dry_vec(), dry_vec(), nocc, nvir, naux, level, nullptr, precision,
                            df);
         {
             Arena w2 = ws;
             take(w2, 2LL * NVMAX * c->N);  // dense-matrix hook
-            sigma_impl(c, w2, nullptr, nullptr, NVMAX, nullptr, precision);
+            sigma_impl(c, w2, dry_vec(), dry_vec(), NVMAX, nullptr, precision);
             ws.peak = std::max(ws.peak, w2.peak);
         }
         if (nroots > 0) {
@@ -2723,11 +2725,11 @@ static void plan_solve(int nocc, int nvir, int naux, int nroots, const adc3_opts
     (void)n;
     adc3_opts oc = op;
     oc.fno_keep_frac = 0.0;  // the canonical path's plan must not take the truncated route
-    if (path != 0) solve_impl(ws, nullptr, nullptr, B0, nroots, 1.0, 1.0, 1.0, op, nullptr);  // truncation path
+    if (path != 0) solve_impl(ws, dry_vec(), dry_vec(), B0, nroots, 1.0, 1.0, 1.0, op, nullptr);  // truncation path
     if (path != 1) {
         Arena ws2;
         ws2.used = 0;
-        solve_impl(ws2, nullptr, nullptr, B0, nroots, 0.0, 0.0, 1.0, oc, nullptr);  // canonical path
+        solve_impl(ws2, dry_vec(), dry_vec(), B0, nroots, 0.0, 0.0, 1.0, oc, nullptr);  // canonical path
         ws.peak = std::max(ws.peak, ws2.peak + (size_t)(3 * naux * n * n * sizeof(double)));
     }
     g_dry = false;

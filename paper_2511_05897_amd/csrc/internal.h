@@ -31,8 +31,11 @@ void set_error(const std::string& msg);
 #define LAUNCHCHK() HIPCHK(hipGetLastError())
 
 // ---------------------------------------------------------------------------
-// bump allocator over the caller's workspace; base == nullptr only counts bytes
+// bump allocator over the caller's workspace; base == nullptr only counts bytes (the pointers it
+// then hands out lie in a fake, never dereferenced range, so that offsets applied to them by the
+// counting dry runs stay defined)
 // ---------------------------------------------------------------------------
+constexpr uintptr_t ARENA_COUNT_BASE = uintptr_t(1) << 44;
 struct Arena {
     char* base = nullptr;
     size_t cap = 0;
@@ -44,7 +47,7 @@ struct Arena {
         size_t bytes = count * sizeof(T);
         used = off + bytes;
         if (used > peak) peak = used;
-        if (base == nullptr) return nullptr;
+        if (base == nullptr) return reinterpret_cast<T*>(ARENA_COUNT_BASE + off);
         if (used > cap) fail(-2, "workspace too small: need at least " + std::to_string(used) + " bytes");
         return reinterpret_cast<T*>(base + off);
     }
