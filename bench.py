@@ -204,54 +204,65 @@ def batched_study(adc, d, torch, np, n, modes=(1,)):
     return out
 
 
-def learned_full_size(adc, d, torch, np, scale):
-    """ADC(3) Davidson at o=30, v=400, X=1200 (seed 240, 5 roots, conv 1e-6): Jacobi, then the
-    learned preconditioner trained on seeds 200-239 of o=6, v=40, X=120 at the same scale."""
+def learned_full_size(adc, d, torch, np, scale, train_seeds=range(200, 206), eval_seeds=(240, 241)):
+    """The learned preconditioner at its own workload's shape: o=30, v=400, X=1200, scale 0.3, 5 roots,
+    conv 1e-6, the ladder stored as its pair blocks (102 GB).  Training data from Jacobi solves of
+    `train_seeds` (fewer than the workload's 40 seeds 200-239: each solve here takes seconds), GPU
+    training, then Jacobi and learned solves of the held-out `eval_seeds` (iterations, wall time, roots)."""
     import synth
+    shape, nroots, conv = (30, 400, 1200), 5, 1e-6
     Fs, As, Ds = [], [], []
     t0 = time.perf_counter()
-    for seed in range(200, 240):
-        eo, ev, B = synth.make_instance(6, 40, 120, seed, scale=scale)
-        ctx = adc.Context(d(eo), d(ev), d(B), 3, nroots=5)
-        F, A, D, _ = ctx.mlp_collect(5, 1e-6, 256, 50, seed)
+    for seed in train_seeds:
+        eo, ev, B = synth.make_instance(*shape, seed, scale=scale)
+        ctx = adc.Context(d(eo), d(ev), d(B), 3, nroots=nroots, ladder=1)
+        del B
+        F, A, D, _ = ctx.mlp_collect(nroots, conv, 256, 50, seed)
         Fs.append(F)
         As.append(A)
         Ds.append(D)
         ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+        print("learned-full: collected seed %d" % seed, file=sys.stderr, flush=True)
+    t_collect = time.perf_counter() - t0
     w = torch.as_tensor(synth.mlp_init(1), device="cuda")
-    losses = adc.adc3_mlp_train(w, torch.cat(Fs), torch.cat(As), torch.cat(Ds), epochs=60, batch_groups=32,
-                                lr=2e-3, seed=7)
-    t_train = time.perf_counter() - t0
-    del Fs, As, Ds
-    print("learned-full: trained in %.1f s" % t_train, file=sys.stderr, flush=True)
-    p, eo, ev, B = synth.preset("learned-o30v400x1200", scale=scale)
-    tB = d(B)
-    del B
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ctx = adc.Context(d(eo), d(ev), tB, 3, nroots=5)
+    F, A, D = torch.cat(Fs), torch.cat(As), torch.cat(Ds)
+    losses = adc.adc3_mlp_train(w, F, A, D, epochs=60, batch_groups=32, lr=2e-3, seed=7)
     torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    print("learned-full: context set up in %.1f s" % t_setup, file=sys.stderr, flush=True)
-    out = {"shape": [30, 400, 1200], "seed": p["seed"], "scale": scale, "nroots": 5, "conv": 1e-6,
-           "N": int(ctx.N), "setup_s": t_setup, "train_s": t_train,
-           "loss_first_last": [float(losses[0]), float(losses[-1])]}
-    roots = {}
-    # the first solve also settles the ladder tuner for every row count the solve meets
-    for tag, weights in (("warm-up", None), ("learned", w), ("jacobi", None)):
-        ctx.set_preconditioner(weights)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        wr, _, rn, it, st = ctx.davidson(5, 1e-6)
-        torch.cuda.synchronize()
-        out[tag] = {"iterations": it, "wall_s": time.perf_counter() - t1, "status": st,
-                    "roots": [float(x) for x in wr]}
-        roots[tag] = wr
-        print("learned-full: %s %d iterations, %.1f s" % (tag, it, out[tag]["wall_s"]), file=sys.stderr, flush=True)
-    out["max_abs_root_diff_Eh"] = float(np.abs(roots["learned"] - roots["jacobi"]).max())
-    ctx.close()
-    del ctx, tB
-    torch.cuda.empty_cache()
+    t_train = time.perf_counter() - t0
+    out = {"shape": list(shape), "scale": scale, "nroots": nroots, "conv": conv, "ladder": "stored pair blocks",
+           "train_seeds": [int(x) for x in train_seeds], "groups": int(F.shape[0]), "collect_s": t_collect,
+           "train_s": t_train, "loss_first_last": [float(losses[0]), float(losses[-1])], "eval": {}}
+    del Fs, As, Ds, F, A, D
+    tot = {"jacobi": [0, 0.0], "learned": [0, 0.0]}
+    for seed in eval_seeds:
+        eo, ev, B = synth.make_instance(*shape, seed, scale=scale)
+        ctx = adc.Context(d(eo), d(ev), d(B), 3, nroots=nroots, ladder=1)
+        del B
+        ctx.davidson(nroots, conv)  # warm-up: the ladder tuner settles every row count the solve meets
+        res = {}
+        for tag, weights in (("learned", w), ("jacobi", None)):
+            ctx.set_preconditioner(weights)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            wr, _, rn, it, st = ctx.davidson(nroots, conv)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t1
+            res[tag] = {"iterations": it, "wall_s": dt, "status": st, "roots": [float(x) for x in wr]}
+            tot[tag][0] += it
+            tot[tag][1] += dt
+            print("learned-full: seed %d %s %d iterations %.2f s" % (seed, tag, it, dt), file=sys.stderr, flush=True)
+        res["max_abs_root_diff_Eh"] = float(np.abs(np.array(res["learned"]["roots"]) -
+                                                   np.array(res["jacobi"]["roots"])).max())
+        out["eval"][str(seed)] = res
+        ctx.close()
+        del ctx
+        torch.cuda.empty_cache()
+    out["iterations_learned_vs_jacobi"] = [tot["learned"][0], tot["jacobi"][0]]
+    out["wall_s_learned_vs_jacobi"] = [tot["learned"][1], tot["jacobi"][1]]
+    out["wall_ratio"] = tot["learned"][1] / tot["jacobi"][1]
     return out
 
 

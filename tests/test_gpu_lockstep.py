@@ -151,3 +151,51 @@ def test_lockstep_guesses_max_iter_and_nan():
         assert e.value.status == adc.ADC3_ENUMERIC
     finally:
         adc.adc3_debug_inject_nan(0)
+
+
+def _golden(name):
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name + ".json")))
+
+
+@pytest.mark.parametrize("prec,conv,tol", [(0, 1e-8, 1e-8), (1, 1e-7, 1e-6), (2, 1e-7, 1e-6)])
+def test_large_workload_like_solve_matches_golden(prec, conv, tol):
+    """A scaled-down instance of the large mixed-precision workload: o=16, v=160, X=480, seed 2, B x 0.05,
+    5 canonical roots, the ladder assembled from the factor in every application (that workload's form),
+    FP64 and FP32 / BF16 sigma with the FP64 restart, against the oracle's golden (conv 1e-9)."""
+    g = _golden("large-like-o16v160x480_s0.05")
+    eo, ev, B = synth.make_instance(g["nocc"], g["nvir"], g["naux"], g["seed"], scale=g["scale"])
+    print("large-like solve precision %d" % prec, flush=True)
+    o = adc.adc3_default_opts()
+    o.ladder, o.precision = 2, prec
+    roots, reps, st = adc.adc3_ea_solve(dev(eo), dev(ev), dev(B), 5, 0.0, 0.0, conv, opts=o)
+    assert st == adc.ADC3_OK
+    err = np.abs(roots - np.array(g["roots"]))
+    print("root errors vs the oracle", err)
+    assert err.max() < tol
+    assert all(abs(r["omega"] - w) <= r["err_bound"] + 1e-12 for r, w in zip(reps, g["roots"]))
+
+
+def test_batched_workload_instances_match_goldens():
+    """Instances of the ragged batched workload (literal scale, 8 roots, conv 1e-6) with stored oracle roots:
+    the lockstep batch in the workload's configuration (FP32 ladder, sigma graphs, two slots)."""
+    import glob
+    import os
+    files = sorted(glob.glob(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "batch-seed*.json")))
+    assert len(files) >= 3
+    gold = [_golden(os.path.basename(f)[:-5]) for f in files]
+    inst = []
+    for gd in gold:
+        eo, ev, B = synth.batch_instance(gd["seed"])
+        inst.append(dict(eps_occ=dev(eo), eps_vir=dev(ev), B=dev(B), nroots=8, conv=1e-6))
+    print("batched goldens: %d instances" % len(inst), flush=True)
+    o = _opts(precision=1, sigma_graphs=1)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        roots, reps, sts, st = adc.adc3_ea_solve_batched(inst, opts=o, nstreams=2)
+    torch.cuda.synchronize()
+    assert st == 0 and all(s == 0 for s in sts)
+    for gd, r in zip(gold, roots):
+        ref = np.array(gd["roots"])
+        assert np.all(np.abs(r - ref) <= 1e-6 + 1e-12 * np.abs(ref)), (gd["seed"], np.abs(r - ref).max())
