@@ -10,15 +10,20 @@
 // 4 X M v^3 flops in all, against 2 M v^4 for the stored matrix: the cheaper form once X < v/2,
 // and the only one once v^4 no longer fits in HBM (v = 600: 1 TB in FP64).
 //
-// One tile kernel serves both steps in three operand precisions (FP64 16x16x4 MFMA with FP64
-// accumulation; FP32 16x16x4 and BF16 16x16x32 MFMA with FP32 accumulation): 4 waves side by
-// side over 128 columns, TM blocks of 16 rows, double-buffered LDS slabs, 16-byte loads where
-// the shape allows (scalar loads otherwise), and two levels of batch offsets.
+// FP64 and FP32 operands: one tile kernel serves both steps (16x16x4 MFMA, FP64 or FP32
+// accumulation): 4 waves side by side over 128 columns, TM blocks of 16 rows, double-buffered
+// LDS slabs, 16-byte loads where the shape allows (scalar loads otherwise), and two levels of
+// batch offsets.  BF16 operands: both steps read their operands k-contiguous (Z transposed per row
+// for step 1, the rows of B^Q itself for step 2, through its symmetry) and run on a kernel of
+// their own (dfb_kernel, 32x32x16 MFMA, tiles copied HBM -> LDS by buffer loads); shapes it
+// cannot take (v not a multiple of 8) fall back to the tile kernel with BF16 16x16x32 MFMA.
 //
 // MFMA layouts (lane l of a wave64):
 //   f64 16x16x4 / f32 16x16x4: A frag A[l%16][l/16], B frag B[l/16][l%16]
 //   bf16 16x16x32:             A frag A[l%16][8(l/16) .. +8], B frag B[8(l/16) .. +8][l%16]
-//   accumulator element r: f64 row l/16 + 4r; FP32-output instructions row 4(l/16) + r; column l%16.
+//   bf16 32x32x16:             A frag A[l%32][8(l/32) .. +8], B frag B[8(l/32) .. +8][l%32]
+//   accumulator element r: f64 row l/16 + 4r; FP32-output 16x16 instructions row 4(l/16) + r,
+//   column l%16; 32x32x16 row 8(r/4) + 4(l/32) + r%4, column l%32.
 #include "internal.h"
 #include <algorithm>
 
@@ -322,6 +327,247 @@ void launch_p(const DflArgs& a, int tm, int mtiles, int nbatch, hipStream_t s) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// BF16 operands, both k-contiguous:  C[m][n] (+)= sum_k A[m][k] Bt[n][k]  on v_mfma_f32_32x32x16_bf16.
+// K is a list of nseg segments of seglen elements (segment g of row m at A + m lda + g segA, of row n
+// at Bt + n ldb + g segB), so that step 2 reads B^Q rows straight from the factor, one segment per
+// auxiliary function.  Workgroup tile (64 WM) x 128 from 4 waves in 2 x 2, each (32 WM) x 64 as WM x 2
+// blocks of 32 x 32; slabs of 32 k.  Both tiles go from HBM into LDS by buffer loads (16 bytes a lane,
+// no registers): one load fills 1 KB, 16 rows of 64 bytes, and lane i fetches the chunk (of 8 k) that
+// belongs at LDS position (row i/4, slot i%4) under the swizzle slot = chunk ^ ((row / 4) % 4), which
+// lets 16 lanes reading one chunk of 16 consecutive rows hit 16 different bank groups.  Every offset
+// is per lane and relative to a per-workgroup descriptor that ends at the tile's last valid element:
+// rows past M or N and chunks past a segment's end get an offset past the descriptor and read as zero,
+// so partial slabs and tiles need no masking.  Chunks never straddle a segment (seglen % 8 == 0).
+// ---------------------------------------------------------------------------
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef float f16x __attribute__((ext_vector_type(16)));
+
+struct DfbArgs {
+    const __bf16* A; long long lda, bA0, bA1, segA;
+    const __bf16* Bt; long long ldb, bB0, bB1, segB;
+    void* C; long long ldc, bC0, bC1;
+    long long m_off;
+    int M, N, nseg, seglen, nb0;
+    int accumulate;
+};
+
+constexpr unsigned DFB_OOR = 0xFFFFFFF0u;  // an offset past every descriptor of this kernel
+
+// WM x WN blocks of 32 x 32 per wave; WAR waves along the rows and 4 / WAR along the columns; NST
+// pipeline stages (slab t copied NST - 1 slabs ahead); OCC workgroups per CU for the register budget.
+template <int WM, int WN, int WAR, int NST, int OCC, int TO>
+__global__ __launch_bounds__(256, OCC) void dfb_kernel(DfbArgs g) {
+    constexpr int WAC = 4 / WAR;
+    constexpr int BM = 32 * WM * WAR, BN = 32 * WN * WAC;
+    constexpr int LA = BM / 16, LB = BN / 16;  // 1 KB loads per slab and tile
+    static_assert(WAR * WAC == 4 && LA % 4 == 0 && LB % 4 == 0, "every wave issues the same number of loads");
+    static_assert(NST == 2 || NST == 3, "two or three stages");
+    constexpr int SE = (BM + BN) * 32;  // one stage: the A tile, then the B tile
+    // separate arrays per stage, so that the compiler tells the copies into one stage from the reads of
+    // another and waits for the copies only where asked
+    __shared__ __attribute__((aligned(16))) __bf16 S0[SE], S1[SE], S2[NST == 3 ? SE : 8];
+    int tx, ty, tz;
+    {  // XCD-contiguous ranges of the tile order (column tiles, then row tiles, then batches)
+        const unsigned long long gx = gridDim.x, gy = gridDim.y;
+        const unsigned long long total = gx * gy * gridDim.z;
+        const unsigned long long H = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+        const unsigned long long per = total / 8, rem = total % 8, x = H % 8, j = H / 8;
+        const unsigned long long L = x * per + (x < rem ? x : rem) + j;
+        tx = (int)(L % gx);
+        ty = (int)((L / gx) % gy);
+        tz = (int)(L / (gx * gy));
+    }
+    const int b0 = tz % g.nb0, b1 = tz / g.nb0;
+    const long long m0 = g.m_off + (long long)ty * BM, n0 = (long long)tx * BN;
+    const int rows = (int)min((long long)BM, (long long)g.M - m0), cols = (int)min((long long)BN, (long long)g.N - n0);
+    const long long kext = (long long)(g.nseg - 1);
+    const __bf16* Ab = g.A + b0 * g.bA0 + b1 * g.bA1 + m0 * g.lda;
+    const __bf16* Bb = g.Bt + b0 * g.bB0 + b1 * g.bB1 + n0 * g.ldb;
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)Ab, (short)0, (int)(((rows - 1) * g.lda + kext * g.segA + g.seglen) * 2), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)Bb, (short)0, (int)(((cols - 1) * g.ldb + kext * g.segB + g.seglen) * 2), 0x00020000);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // this lane's row and chunk in each of the wave's loads (fixed for the kernel)
+    constexpr int NA = LA / 4, NB = LB / 4;
+    unsigned rowa[NA], rowb[NB];
+    int cha[NA], chb[NB];
+#pragma unroll
+    for (int t = 0; t < NA; ++t) {
+        const int r = 16 * (wave + 4 * t) + (lane >> 2);
+        rowa[t] = (unsigned)(r * g.lda * 2);
+        cha[t] = (lane & 3) ^ ((r >> 2) & 3);
+    }
+#pragma unroll
+    for (int t = 0; t < NB; ++t) {
+        const int r = 16 * (wave + 4 * t) + (lane >> 2);
+        rowb[t] = (unsigned)(r * g.ldb * 2);
+        chb[t] = (lane & 3) ^ ((r >> 2) & 3);
+    }
+    // a slab past the last one (seg == nseg) is copied as zeros: every offset past the descriptor
+    auto issue = [&](__bf16(&St)[SE], int seg, int e0) {
+        const unsigned sa = (unsigned)((seg * g.segA + e0) * 2), sb = (unsigned)((seg * g.segB + e0) * 2);
+        const int lim = seg < g.nseg ? g.seglen : 0;  // chunks at or past lim read as zero
+#pragma unroll
+        for (int t = 0; t < NA; ++t) {
+            const int e = e0 + 8 * cha[t];
+            const unsigned off = e < lim ? rowa[t] + sa + 16u * cha[t] : DFB_OOR;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_ptr_t)&St[512 * (wave + 4 * t)], 16, off, 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < NB; ++t) {
+            const int e = e0 + 8 * chb[t];
+            const unsigned off = e < lim ? rowb[t] + sb + 16u * chb[t] : DFB_OOR;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_ptr_t)&St[BM * 32 + 512 * (wave + 4 * t)], 16, off, 0, 0,
+                                                     0);
+        }
+    };
+    f16x acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+    const int wr0 = (wave / WAC) * 32 * WM, wc0 = (wave % WAC) * 32 * WN;
+    const int fr = lane & 31, fk = lane >> 5;
+    // Rows of a fragment start at multiples of 32, so a row's swizzle is that of its lane (fr / 4 % 4).
+    const int sw = (fr >> 2) & 3;
+    // per 16-deep step: the fragments of WM row blocks and WN column blocks, then their WM WN products
+    auto compute = [&](const __bf16(&St)[SE]) {
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const int co = 8 * ((2 * ks + fk) ^ sw);
+            h8x aq[WM], bq[WN];
+#pragma unroll
+            for (int j = 0; j < WN; ++j) bq[j] = *(const h8x*)&St[BM * 32 + 32 * (wc0 + 32 * j + fr) + co];
+#pragma unroll
+            for (int i = 0; i < WM; ++i) aq[i] = *(const h8x*)&St[32 * (wr0 + 32 * i + fr) + co];
+#pragma unroll
+            for (int i = 0; i < WM; ++i)
+#pragma unroll
+                for (int j = 0; j < WN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aq[i], bq[j], acc[i][j], 0, 0, 0);
+        }
+    };
+    const int nsl = (g.seglen + 31) / 32, nslab = g.nseg * nsl;
+    // slab t covers segment t / nsl, elements 32 (t % nsl) .. of it; advanced without a division
+    int seg = 0, e0 = 0;
+    auto next = [&] {
+        e0 += 32;
+        if (e0 >= g.seglen) { e0 = 0; ++seg; }
+    };
+    // Slab t lives in stage t % NST and is copied NST - 1 slabs ahead.  After slab t each wave waits until
+    // only the copies of the slabs after t + 1 are outstanding (loads complete in issue order), then the
+    // barrier makes slab t + 1 visible to all.  The last steps copy zero slabs into stages that are not
+    // read again, so that every step has the same shape and the compiler's wait analysis sees no branch.
+    constexpr int NL = NA + NB;
+    static_assert((NST - 2) * NL < 16, "vmcnt immediate");
+    // s_waitcnt immediates: vmcnt(n) with expcnt and lgkmcnt left at their maxima (no wait on them)
+    constexpr int WAIT_STEP = (NST - 2) * NL | (0x7 << 4) | (0xF << 8), WAIT_0 = (0x7 << 4) | (0xF << 8);
+    // the barrier alone: __syncthreads() would also wait for every copy in flight (its release fence
+    // covers the copies into LDS).  The empty asm statements keep the compiler from moving LDS reads
+    // across it.
+    auto barrier = [] {
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
+    auto step = [&](const __bf16(&Sc)[SE], __bf16(&Sn)[SE]) {
+        issue(Sn, seg, e0);
+        next();
+        compute(Sc);
+        __builtin_amdgcn_s_waitcnt(WAIT_STEP);
+        barrier();
+    };
+    issue(S0, seg, e0);
+    next();
+    if constexpr (NST == 3) {
+        issue(S1, seg, e0);
+        next();
+    }
+    __builtin_amdgcn_s_waitcnt(WAIT_STEP);
+    barrier();
+    int t = 0;
+    if constexpr (NST == 2) {
+        for (; t + 2 <= nslab; t += 2) {
+            step(S0, S1);
+            step(S1, S0);
+        }
+        if (t < nslab) step(S0, S1);
+    } else {
+        for (; t + 3 <= nslab; t += 3) {
+            step(S0, S2);
+            step(S1, S0);
+            step(S2, S1);
+        }
+        if (t < nslab) step(S0, S2);
+        if (t + 1 < nslab) step(S1, S0);
+    }
+    __builtin_amdgcn_s_waitcnt(WAIT_0);
+    // accumulator element r of lane l: row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+    typedef typename Out<TO>::T OT;
+    OT* C = (OT*)g.C + b0 * g.bC0 + b1 * g.bC1;
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int lr = wr0 + 32 * i + 8 * (r >> 2) + 4 * fk + (r & 3);
+                const int lc = wc0 + 32 * j + fr;
+                if (lr < rows && lc < cols) {
+                    OT* c = C + (m0 + lr) * g.ldc + n0 + lc;
+                    if constexpr (TO == 0) {
+                        const double x = (double)acc[i][j][r];
+                        *c = g.accumulate ? *c + x : x;
+                    } else {
+                        *c = (OT)acc[i][j][r];
+                    }
+                }
+            }
+}
+
+// can the k-contiguous BF16 kernel take this product?  (16-byte chunks that never straddle a segment,
+// per-tile byte extents within the 32-bit descriptor range)
+bool dfb_ok(const DfbArgs& a, int bm) {
+    const auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    const long long ext = (long long)(a.nseg - 1);
+    return a.seglen % 8 == 0 && a.lda % 8 == 0 && a.ldb % 8 == 0 && a.segA % 8 == 0 && a.segB % 8 == 0 &&
+           a.bA0 % 8 == 0 && a.bA1 % 8 == 0 && a.bB0 % 8 == 0 && a.bB1 % 8 == 0 && al(a.A) && al(a.Bt) &&
+           ((bm - 1) * a.lda + ext * a.segA + a.seglen) * 2 < (1LL << 31) &&
+           (127 * a.ldb + ext * a.segB + a.seglen) * 2 < (1LL << 31);
+}
+
+template <int WM, int WN, int WAR, int NST, int OCC, int TO>
+void dfb_launch(const DfbArgs& a, int nbatch, hipStream_t s) {
+    constexpr int BM = 32 * WM * WAR, BN = 32 * WN * (4 / WAR);
+    const long long rows_per_launch = 65535LL * BM;
+    for (long long r0 = 0; r0 < a.M; r0 += rows_per_launch) {
+        DfbArgs b = a;
+        b.m_off = r0;
+        b.M = (int)std::min<long long>(a.M, r0 + rows_per_launch);
+        const long long rows = b.M - r0;
+        dim3 grid((unsigned)((a.N + BN - 1) / BN), (unsigned)((rows + BM - 1) / BM), (unsigned)nbatch);
+        hipLaunchKernelGGL((dfb_kernel<WM, WN, WAR, NST, OCC, TO>), grid, dim3(256), 0, s, b);
+        LAUNCHCHK();
+    }
+}
+
+// 256 x 128 workgroup tiles (4 x 2 blocks per wave), or 128 x 128 (2 x 2) where 256-row tiles would pad M
+// more; two stages, two workgroups per CU.  Measured against the alternatives at v = 600, X = 1800, 200
+// rows: three stages, and 512 x 128 tiles with 4 x 4 blocks per wave at one workgroup per CU, were within
+// -2% .. +16% of this choice.
+template <int TO>
+void dfb_gemm(DfbArgs a, int nb1, hipStream_t s) {
+    if (a.M <= 0 || a.N <= 0) return;
+    const int nbatch = a.nb0 * nb1;
+    if (nbatch <= 0 || nbatch > 65535) fail(-1, "dfladder: batch count out of range");
+    if (((a.M + 255) / 256) * 256 <= ((a.M + 127) / 128) * 128) dfb_launch<4, 2, 2, 2, 2, TO>(a, nbatch, s);
+    else dfb_launch<2, 2, 2, 2, 2, TO>(a, nbatch, s);
+}
+
 // dst[m][j][i] = src[m][i][j], m < nb, n x n blocks of BF16
 __global__ void transpose_bf16_kernel(unsigned short* dst, const unsigned short* src, int n, int nb) {
     __shared__ unsigned short t[32][33];
@@ -428,8 +674,15 @@ void df_ladder(int prec, int M, int v, int X, const void* Bvv, const void* Z, do
     const bool bt = prec == 2;
     const long long zt_elems = bt ? (long long)M * vv + 8 : 0;
     const long long avail = v_elems - zt_elems;
-    const long long q = df_ladder_chunk(M, v, X, avail);
-    if (q * M * vv > avail) fail(-1, "dfladder: intermediate buffer too small");
+    // BF16 on the k-contiguous kernel: the intermediate's segments start every vp elements, vp = v rounded
+    // up to 64 (128 bytes) when the buffer allows, so that the row pieces one workgroup of step 1 writes
+    // never share a cache line with another's
+    const long long vround = (v + 63) / 64 * 64;
+    const long long vp = (bt && v % 8 == 0 && avail >= (long long)M * v * vround) ? vround : v;
+    const long long q = vp == v ? df_ladder_chunk(M, v, X, avail)
+                                : std::max<long long>(1, std::min<long long>(std::min<long long>(X, avail / ((long long)M * v * vp)),
+                                                                             std::max(1, 65535 / std::max(M, 1))));
+    if (q * M * v * vp > avail) fail(-1, "dfladder: intermediate buffer too small");
     const int eb = elem_bytes(prec);
     const void* Zb = Z;
     if (bt) {
@@ -442,6 +695,25 @@ void df_ladder(int prec, int M, int v, int X, const void* Bvv, const void* Z, do
     for (long long Q0 = 0; Q0 < X; Q0 += q) {
         const int qn = (int)std::min<long long>(q, X - Q0);
         const char* Bq = (const char*)Bvv + Q0 * vv * eb;
+        if (bt) {
+            // both steps on the k-contiguous kernel when the shape allows
+            DfbArgs s1{};
+            s1.A = (const __bf16*)Bq; s1.lda = v; s1.bA0 = vv; s1.bA1 = 0; s1.segA = 0;
+            s1.Bt = (const __bf16*)Zb; s1.ldb = v; s1.bB0 = 0; s1.bB1 = vv; s1.segB = 0;
+            s1.C = V; s1.ldc = (long long)qn * vp; s1.bC0 = vp; s1.bC1 = (long long)qn * v * vp;
+            s1.M = v; s1.N = v; s1.nseg = 1; s1.seglen = v; s1.nb0 = qn; s1.accumulate = 0;
+            DfbArgs s2{};
+            s2.A = (const __bf16*)V; s2.lda = (long long)qn * vp; s2.segA = vp;
+            s2.Bt = (const __bf16*)Bq; s2.ldb = v; s2.segB = vv;
+            s2.C = C; s2.ldc = v;
+            s2.M = (int)((long long)M * v); s2.N = v; s2.nseg = qn; s2.seglen = v; s2.nb0 = 1;
+            s2.accumulate = (accumulate || Q0 > 0) ? 1 : 0;
+            if (dfb_ok(s1, 256) && dfb_ok(s2, 256)) {
+                dfb_gemm<2>(s1, M, s);
+                dfb_gemm<0>(s2, 1, s);
+                continue;
+            }
+        }
         // step 1: V[m][a][Qi][e] = sum_c B^Q[a][c] Z_m[c][e]  (batch b0 = Qi, b1 = m)
         DflArgs a1{};
         a1.A = Bq; a1.lda = v; a1.bA0 = vv; a1.bA1 = 0;
