@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--sigma-reps", type=int, default=10)
     ap.add_argument("--sigma-only", action="store_true",
                     help="profiling mode: only the isolated ADC(3) sigma builds plus a 2 GiB copy (counter calibration)")
+    ap.add_argument("--sigma-precision", type=int, default=0,
+                    help="precision of the --sigma-only context and its sigma calls (0 FP64, 1 FP32, 2 BF16 ladder)")
     ap.add_argument("--dfladder-only", action="store_true",
                     help="profiling mode: the assembled ladder alone at o=40 v=600 X=1800 (5 vectors) in FP64, FP32 "
                          "and BF16, plus a 2 GiB copy (counter calibration)")
@@ -500,18 +502,18 @@ def main():
     if a.sigma_only:
         # ADC(3) sigma builds in the SS-FNO/NAF basis shape of the default workload
         e2, v2, B2 = synth.make_instance(20, 200, 128, 1)
-        ctx = adc.Context(d(e2), d(v2), d(B2), 3, nroots=0)
+        ctx = adc.Context(d(e2), d(v2), d(B2), 3, nroots=0, precision=a.sigma_precision)
         r = torch.randn((5, ctx.N), dtype=torch.float64, device="cuda")
         out = torch.empty_like(r)
         for _ in range(a.sigma_reps):
-            ctx.sigma(r, out)
+            ctx.sigma(r, out, precision=a.sigma_precision)
         torch.cuda.synchronize()
         # plain copy of known size: 2 GiB read + 2 GiB written
         x = torch.empty(1 << 28, dtype=torch.float64, device="cuda").fill_(1.0)
         y = torch.empty_like(x)
         y.copy_(x)
         torch.cuda.synchronize()
-        print(json.dumps({"mode": "sigma-only", "sigma_calls": a.sigma_reps, "nvec": 5,
+        print(json.dumps({"mode": "sigma-only", "sigma_calls": a.sigma_reps, "nvec": 5, "precision": a.sigma_precision,
                           "ladder_flops_per_launch": 2.0 * 100 * 200 ** 4, "copy_bytes_each_way": 8 << 28}))
         return
     if a.dfladder_only:
