@@ -104,11 +104,11 @@ typedef struct {
                              i.e. the Dyson-orbital coefficients; each vector's largest-magnitude entry made
                              positive.  See adc3_ea_spectral_amplitudes for f. */
     int lockstep;         /* 1: Davidson solves that do not depend on each other run together in one
-                             lockstep block Davidson (a build addition): each iteration has a fixed shape
-                             (nroots new directions, converged roots' ones zeroed, the subspace size a
-                             function of the iteration count) and keeps its convergence flags on the
+                             lockstep block Davidson (a build addition): each iteration of a chunk has a
+                             fixed shape (one new direction per root not converged when the chunk began,
+                             those converging within it zeroed) and keeps its convergence flags on the
                              device, and a chunk of iterations of every active solve is one HIP graph
-                             replay; the host reads the flags once per chunk.  adc3_ea_solve: the
+                             replay; the host reads the flags once per chunk and sets the next block.  adc3_ea_solve: the
                              truncated ADC(2) solves of all roots' bases, then their ADC(3) solves
                              (all bases held at once: more workspace); adc3_ea_solve_batched: the
                              instances in waves of nstreams.  Jacobi and exact-1p steps only (precond 1

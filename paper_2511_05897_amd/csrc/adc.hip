@@ -34,6 +34,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <set>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1107,10 +1108,11 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
 // Lockstep block Davidson: many independent Davidson problems (instances of a ragged batch, or the
 // per-root bases of one SS-FNO solve) advanced together, a fixed chunk of iterations per replay of one
 // HIP graph that holds every active problem's iterations on its own stream.  The iteration has a fixed
-// shape so that nothing in it needs the host: every iteration adds exactly nroots directions (the
-// preconditioned residuals; those of converged roots, and directions lost to orthogonalisation, are
-// zero vectors whose Gram rows are decoupled), the subspace size follows the iteration count, and the
-// convergence flags, residual norms and Ritz values stay on the device until the chunk ends.
+// shape so that nothing in it needs the host: every iteration of a chunk adds the same nb directions (the
+// preconditioned residuals of the roots not converged when the chunk began; those that converge within
+// it, and directions lost to orthogonalisation, are zero vectors whose Gram rows are decoupled), the
+// host knows the subspace size from the block widths, and the convergence flags, residual norms and
+// Ritz values stay on the device until the chunk ends.
 // ---------------------------------------------------------------------------
 // iterations per graph replay (ADC3_DAV_CHUNK overrides; default 3)
 static int lockstep_chunk() {
@@ -1141,12 +1143,16 @@ struct LockJob {
            *Gw = nullptr, *ev = nullptr, *Y = nullptr, *ev2 = nullptr, *Y2 = nullptr, *th = nullptr, *thold = nullptr,
            *coef = nullptr, *Vk = nullptr, *Sk = nullptr, *part = nullptr, *valid = nullptr, *active = nullptr,
            *status = nullptr, *tmp = nullptr, *Yb = nullptr, *gscr = nullptr, *nvalid = nullptr;
+    // the block: nb <= nroots new directions per iteration, those of the roots idx[0..nb) (device), chosen at
+    // each chunk boundary from the status; thg, actg their Ritz values and flags; Yr their raw 1p parts
+    double *idx = nullptr, *thg = nullptr, *actg = nullptr, *Yr = nullptr;
     bool done = false;
     std::vector<double> lp_best;
     std::vector<int> lp_stall;
     DavResult res;
     long long sigma_builds = 0;
     size_t status_off = 0;  // offset (doubles) of this job's status in the host read-back buffer
+    size_t idx_off = 0;     // offset (doubles) of this job's block indices in the pinned staging buffer
 };
 
 // does the problem's space hold the fixed block shape (guesses plus one block of nroots directions)?
@@ -1193,7 +1199,11 @@ static void lock_alloc(LockJob& j, Arena& ws) {
     j.coef = take(ws, (long long)mm * mm);
     j.valid = take(ws, mm);
     j.active = take(ws, nr);
-    j.status = take(ws, 2 + 2 * nr);
+    j.status = take(ws, 2 + 3 * nr);
+    j.idx = take(ws, nr);
+    j.thg = take(ws, nr);
+    j.actg = take(ws, nr);
+    j.Yr = take(ws, (long long)nr * c->v);
     j.nvalid = take(ws, 1);
     j.Yb = take(ws, (long long)nr * c->v);
     j.part = take(ws, (long long)dots_partial_elems(mm, mm, N));
@@ -1293,15 +1303,17 @@ static void lock_iterate(LockJob& j) {
     Ctx* c = j.c;
     if (j.m + j.nb > j.mmax) lock_collapse(j, j.nkeep, true);
     double* Tn = j.V + (long long)j.m * N;
-    k_precond(Tn, j.R, c->diag, j.th, j.nroots, N, s);
+    // the block's roots: Ritz values, flags (and raw 1p residuals for the exact 1p step) gathered
+    k_block_gather(j.thg, j.actg, j.pmode == 3 ? j.Yr : nullptr, c->v, j.th, j.active, j.R, N, j.idx, j.nb, s);
+    k_precond_idx(Tn, j.R, c->diag, j.th, j.idx, j.nb, N, s);
     if (j.pmode == 3) {
         // 1p block exactly: t1 = Q (w - theta)^-1 Q^T r1 per root
         const int v = c->v;
-        gemm_rm(j.nroots, v, v, 1.0, j.R, N, false, c->m11_Q, v, false, 0.0, j.Yb, v, s);
-        for (int k = 0; k < j.nroots; ++k) k_div_shift(j.Yb + (long long)k * v, c->m11_w, j.th + k, v, s);
-        gemm_rm(j.nroots, v, v, 1.0, j.Yb, v, false, c->m11_Q, v, true, 0.0, Tn, N, s);
+        gemm_rm(j.nb, v, v, 1.0, j.Yr, v, false, c->m11_Q, v, false, 0.0, j.Yb, v, s);
+        for (int k = 0; k < j.nb; ++k) k_div_shift(j.Yb + (long long)k * v, c->m11_w, j.thg + k, v, s);
+        gemm_rm(j.nb, v, v, 1.0, j.Yb, v, false, c->m11_Q, v, true, 0.0, Tn, N, s);
     }
-    k_rows_mask(Tn, j.nb, N, j.active, s);
+    k_rows_mask(Tn, j.nb, N, j.actg, s);
     lock_ortho(j, Tn, j.nb, j.m);
     lock_sigma(j, Tn, j.S + (long long)j.m * N, j.nb);
     {
@@ -1413,7 +1425,9 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
     for (auto* j : jobs) {
         lock_alloc(*j, *j->arena);
         j->status_off = tot;
-        tot += 2 + 2 * j->nroots;
+        tot += 2 + 3 * j->nroots;
+        j->idx_off = tot;
+        tot += j->nroots;
     }
     struct Res {
         hipStream_t main = nullptr;  // the graphs' stream (capture needs a stream of its own)
@@ -1451,7 +1465,7 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
     auto read_status = [&](const std::vector<int>& ids, hipStream_t s) {
         for (int i : ids)
             HIPCHK(hipMemcpyAsync(rs.host + jobs[i]->status_off, jobs[i]->status,
-                                  (2 + 2 * jobs[i]->nroots) * sizeof(double), hipMemcpyDeviceToHost, s));
+                                  (2 + 3 * jobs[i]->nroots) * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
     };
     // the start's status: each job's own stream
@@ -1502,10 +1516,31 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
             return;
         }
     };
-    for (int i = 0; i < nj; ++i) step_eval(i);
-    // a job's first chunk in a precision runs eagerly: the ladder tuner settles the block's shape before
-    // any capture
-    std::vector<int> tuned(nj, -1);
+    // the next chunk's block: the roots the status marks active, in root order (all of them when none is,
+    // which only a phase that is about to restart can see); the indices go up on the job's stream
+    auto set_block = [&](int i) {
+        LockJob& j = *jobs[i];
+        if (j.done) return;
+        const double* h = rs.host + j.status_off;
+        double* st = rs.host + j.idx_off;
+        const int nr = j.nroots;
+        int nb = 0;
+        for (int k = 0; k < nr; ++k)
+            if (h[2 + 2 * nr + k] != 0.0) st[nb++] = (double)k;
+        if (nb == 0) {
+            for (int k = 0; k < nr; ++k) st[k] = (double)k;
+            nb = nr;
+        }
+        j.nb = nb;
+        HIPCHK(hipMemcpyAsync(j.idx, st, nb * sizeof(double), hipMemcpyHostToDevice, j.s));
+    };
+    for (int i = 0; i < nj; ++i) {
+        step_eval(i);
+        set_block(i);
+    }
+    // a job's first chunk at each (precision, block width) runs eagerly: the ladder tuner settles the
+    // block's shapes before any capture
+    std::vector<std::set<int>> tuned(nj);  // (phase, block width) pairs a job has run eagerly
     for (;;) {
         std::vector<int> act;
         for (int i = 0; i < nj; ++i)
@@ -1513,16 +1548,19 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
         if (act.empty()) break;
         std::vector<int> eager;
         for (int i : act)
-            if (tuned[i] != jobs[i]->phase) eager.push_back(i);
+            if (!tuned[i].count(jobs[i]->phase * 64 + jobs[i]->nb)) eager.push_back(i);
         if (!eager.empty()) {
             for (int i : eager) {
                 LockJob& j = *jobs[i];
                 const int K = std::max(1, std::min(chunk, j.max_iter - j.it));
+                tuned[i].insert(j.phase * 64 + j.nb);
                 for (int k = 0; k < K; ++k) lock_iterate(j);
-                tuned[i] = j.phase;
             }
             for (int i : eager) read_status({i}, jobs[i]->s);
-            for (int i : eager) step_eval(i);
+            for (int i : eager) {
+                step_eval(i);
+                set_block(i);
+            }
             continue;
         }
         // every active job's stream has finished its eager work: the graph forks from main
@@ -1535,7 +1573,7 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
         for (int i : act) {
             K[i] = std::max(1, std::min(chunk, jobs[i]->max_iter - jobs[i]->it));
             key += std::to_string(i) + ":" + std::to_string(jobs[i]->m) + ":" + std::to_string(jobs[i]->phase) + ":" +
-                   std::to_string(K[i]) + ";";
+                   std::to_string(K[i]) + ":" + std::to_string(jobs[i]->nb) + ";";
         }
         auto g = rs.graphs.find(key);
         if (g == rs.graphs.end()) {
@@ -1571,7 +1609,10 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
         // eager work of the next round (restarts) runs on each job's stream after the replay
         HIPCHK(hipEventRecord(rs.fork, main));
         for (int i : act) HIPCHK(hipStreamWaitEvent(jobs[i]->s, rs.fork, 0));
-        for (int i : act) step_eval(i);
+        for (int i : act) {
+            step_eval(i);
+            set_block(i);
+        }
     }
     for (int i = 0; i < nj; ++i) {
         LockJob& j = *jobs[i];

@@ -418,7 +418,8 @@ __global__ void mask_gram_kernel(double* G, int m, const double* valid, double* 
 }
 
 // one workgroup: per root k, rn = sqrt(Gw[k][k]), converged when rn <= conv and |th - thold| <= conv;
-// active[k] = !converged; thold = th; status = [all converged, all finite, rn[nroots], th[nroots]]
+// active[k] = !converged; thold = th; status = [all converged, all finite, rn[nroots], th[nroots],
+// active[nroots]]
 __global__ void dav_status_kernel(const double* Gw, int nroots, const double* th, double* thold, double conv,
                                   double* active, double* status) {
     __shared__ unsigned char okf[64], finf[64];
@@ -431,6 +432,7 @@ __global__ void dav_status_kernel(const double* Gw, int nroots, const double* th
         thold[k] = w;
         status[2 + k] = rn;
         status[2 + nroots + k] = w;
+        status[2 + 2 * nroots + k] = ok ? 0.0 : 1.0;
         okf[k] = ok;
         finf[k] = fin;
     }
@@ -461,6 +463,33 @@ __global__ void lowdin_masked_kernel(double* coef, const double* U, const double
     const bool keep = w[q] > thr && isfinite(w[q]);
     coef[t] = keep ? U[t] / sqrt(w[q]) : 0.0;
     if (t < nn) valid[t] = (w[t] > thr && isfinite(w[t])) ? 1.0 : 0.0;
+}
+
+__global__ void block_gather_kernel(double* thg, double* actg, double* rows, int ncol, const double* th,
+                                    const double* active, const double* R, long long ldr, const double* idx, int nb) {
+    const long long tot = (long long)nb * ncol;
+    GRID_STRIDE(t, tot) {
+        const int r = (int)(t / ncol);
+        rows[t] = R[(long long)idx[r] * ldr + t % ncol];
+    }
+    if (blockIdx.x == 0)
+        for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+            thg[r] = th[(int)idx[r]];
+            actg[r] = active[(int)idx[r]];
+        }
+}
+
+__global__ void precond_idx_kernel(double* T, const double* R, const double* D, const double* th, const double* idx,
+                                   int nb, long long n) {
+    const long long tot = (long long)nb * n;
+    GRID_STRIDE(t, tot) {
+        const int r = (int)(t / n);
+        const long long e = t - (long long)r * n;
+        const int k = (int)idx[r];
+        double den = D[e] - th[k];
+        if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+        T[t] = R[(long long)k * n + e] / den;
+    }
 }
 
 // after a Rayleigh-Ritz sorted ascending, the first cnt[0] Ritz vectors are the valid ones
@@ -494,6 +523,23 @@ void k_lowdin_masked(double* coef, const double* U, const double* w, int nn, dou
     if (g_dry || nn <= 0) return;
     hipLaunchKernelGGL(lowdin_masked_kernel, dim3((nn * nn + 255) / 256), dim3(256), 0, s, coef, U, w, nn, thr,
                        valid);
+    LAUNCHCHK();
+}
+void k_block_gather(double* thg, double* actg, double* rows, int ncol, const double* th, const double* active,
+                    const double* R, long long ldr, const double* idx, int nb, hipStream_t s) {
+    if (g_dry || nb <= 0) return;
+    const int nc = rows ? ncol : 0;
+    const long long t = std::max<long long>((long long)nb * nc, 1);
+    hipLaunchKernelGGL(block_gather_kernel, dim3(nblocks(t)), dim3(NT), 0, s, thg, actg, rows, nc, th, active, R, ldr,
+                       idx, nb);
+    LAUNCHCHK();
+}
+void k_precond_idx(double* T, const double* R, const double* D, const double* theta, const double* idx, int nb,
+                   long long n, hipStream_t s) {
+    if (g_dry) return;
+    const long long t = (long long)nb * n;
+    if (t <= 0) return;
+    hipLaunchKernelGGL(precond_idx_kernel, dim3(nblocks(t)), dim3(NT), 0, s, T, R, D, theta, idx, nb, n);
     LAUNCHCHK();
 }
 void k_valid_first(double* valid, int n, const double* cnt, hipStream_t s) {

@@ -202,10 +202,17 @@ void k_lowdin_coef(double* coef, const double* U, const double* w, int acc, int 
 // block's Gershgorin bound; cnt[0] = number of valid directions
 void k_mask_gram(double* G, int m, const double* valid, double* cnt, hipStream_t s);
 // per root: rn = sqrt(Gw[k][k]), converged = rn <= conv && |th - thold| <= conv; active = !converged;
-// thold = th; status = [all converged, all finite, rn[nroots], th[nroots]]  (one workgroup)
+// thold = th; status = [all converged, all finite, rn[nroots], th[nroots], active[nroots]]  (one workgroup)
 void k_dav_status(const double* Gw, int nroots, const double* th, double* thold, double conv, double* active,
                   double* status, hipStream_t s);
 void k_rows_mask(double* T, int nn, long long n, const double* active, hipStream_t s);  // zero inactive rows
+// the block of the roots idx[0..nb): thg[r] = th[idx[r]], actg[r] = active[idx[r]]; with rows != nullptr also
+// rows[r][0..ncol) = R[idx[r]][0..ncol) (R rows of length ldr)
+void k_block_gather(double* thg, double* actg, double* rows, int ncol, const double* th, const double* active,
+                    const double* R, long long ldr, const double* idx, int nb, hipStream_t s);
+// T[r] = R[idx[r]] / (D - th[idx[r]]) elementwise (the Jacobi step of root idx[r]), r < nb
+void k_precond_idx(double* T, const double* R, const double* D, const double* theta, const double* idx, int nb,
+                   long long n, hipStream_t s);
 // coef[j*nn + q] = U[j*nn + q] / sqrt(w[q]) for w[q] > thr, else 0; valid[q] = w[q] > thr
 void k_lowdin_masked(double* coef, const double* U, const double* w, int nn, double thr, double* valid,
                      hipStream_t s);
