@@ -154,6 +154,8 @@ def learned_study(adc, d, torch, np):
         losses = adc.adc3_mlp_train(w, F, A, D, epochs=60, batch_groups=32, lr=2e-3, seed=7)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t0
+        print("learned: o%dv%dx%d collected in %.1f s, trained in %.1f s" % (*shape, t_collect, t_train),
+              file=sys.stderr, flush=True)
         held = {"jacobi": {"iterations": 0, "wall_s": 0.0}, "learned": {"iterations": 0, "wall_s": 0.0}}
         dmax, statuses = 0.0, []
         for seed in range(240, 244):
@@ -180,6 +182,7 @@ def learned_study(adc, d, torch, np):
                          "iteration_ratio": held["learned"]["iterations"] / max(held["jacobi"]["iterations"], 1),
                          "wall_ratio": held["learned"]["wall_s"] / held["jacobi"]["wall_s"],
                          "max_abs_root_diff_Eh": dmax}}
+        print("learned: o%dv%dx%d held-out solves done" % shape, file=sys.stderr, flush=True)
     return {"scale": scale, "level": 3, "nroots": nroots, "conv": 1e-6, "shapes": out}
 
 
@@ -199,6 +202,7 @@ def batched_study(adc, d, torch, np, n, modes=((0, "threads_cold_tuner"), (1, "l
         inst.append(dict(eps_occ=d(eo), eps_vir=d(ev), B=d(B), nroots=8, conv=1e-6))
         del B
     gen_s = time.perf_counter() - g0
+    print("batched: %d instances generated in %.1f s" % (n, gen_s), file=sys.stderr, flush=True)
     sum_n = sum(int(x["eps_vir"].numel()) * (1 + int(x["eps_occ"].numel()) * int(x["eps_vir"].numel())) for x in inst)
     out = {"instances": n, "seeds": "100-%d" % (99 + n), "nroots": 8, "conv": 1e-6, "precision": "fp32 ladder",
            "slots": 2, "sum_N": sum_n, "generation_s_untimed": gen_s}
@@ -233,6 +237,7 @@ def batched_study(adc, d, torch, np, n, modes=((0, "threads_cold_tuner"), (1, "l
             res["max_rel_root_diff_vs_first_run"] = float(max(
                 np.abs(a - b).max() / max(1.0, np.abs(a).max()) for a, b in zip(ref, roots)))
         out[label] = res
+        print("batched: %s %.1f s, %d of %d converged" % (label, dt, res["statuses_ok"], n), file=sys.stderr, flush=True)
         del ws
         torch.cuda.empty_cache()
     return out
@@ -572,6 +577,7 @@ def main():
             sdt = time.perf_counter() - s0
             iso = {"value": a.sigma_reps * nroots / sdt, "unit": "sigma-builds/s", "nvec_per_call": nroots,
                    "shape": {"nocc": p["nocc"], "nvir": vk, "naux": xk}}
+            print("isolated ADC(3) sigma: %.0f sigma-builds/s" % iso["value"], file=sys.stderr, flush=True)
             ctx.close()
             del ctx
         except Exception as e:  # reported, never silent
@@ -610,10 +616,12 @@ def main():
                               "ladder": {"launches": ln, "avg_launch_ms": lms / max(ln, 1),
                                          "achieved_tflops": ach, "peak_tflops": peak, "frac": ach / peak,
                                          "bound_time_frac": lbound / lms if lms > 0 else None}}
+                print("mixed precision %s: %.3f s to the roots" % (tag, mdt), file=sys.stderr, flush=True)
             except Exception as e:
                 mixed[tag] = {"error": str(e)}
         try:
             mixed["ladder_dominated_davidson"] = mixed_ladder_dominated(adc, d, torch, np)
+            print("mixed precision: ladder-dominated Davidson done", file=sys.stderr, flush=True)
         except Exception as e:
             mixed["ladder_dominated_davidson"] = {"error": str(e)}
 
@@ -637,6 +645,7 @@ def main():
                         "sigma_builds": sum(r["sigma_builds"] for r in repl),
                         "max_abs_root_diff_vs_sequential_Eh": float(np.abs(rl - roots).max()),
                         "workspace_GB": wsl.numel() / 1e9}
+            print("lockstep: %.3f s to the roots" % ldt, file=sys.stderr, flush=True)
             del wsl
             torch.cuda.empty_cache()
         except Exception as e:
@@ -662,6 +671,7 @@ def main():
                        "sigma_builds_per_s": sum(r["sigma_builds"] for r in repv) / vdt,
                        "roots": [float(x) for x in rv], "status": stv,
                        "nvir_kept": [r["nvir_kept"] for r in repv], "naux_kept": [r["naux_kept"] for r in repv]}
+            print("weak-correlation variant: %.3f s to the roots" % vdt, file=sys.stderr, flush=True)
             del tBv
         except Exception as e:
             variant = {"error": str(e)}
