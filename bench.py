@@ -23,6 +23,9 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 matrix peak
 PEAK_HBM_GBS = 8000.0
+# worker slots of the batched study: three slices of the largest instance's plan (193 GB of workspace) fit
+# in HBM beside the inputs; measured with worker threads: 1 slot 47.6 s, 2 slots 36.3 s, 3 slots 31.7 s
+BATCH_SLOTS = 3
 
 
 def parse():
@@ -188,10 +191,10 @@ def learned_study(adc, d, torch, np):
 
 def batched_study(adc, d, torch, np, n, modes=((0, "threads_cold_tuner"), (1, "lockstep"), (0, "threads"))):
     """The ragged batched workload: instances of seeds 100.. (nocc~U{5..30}, nvir~U{50..300},
-    naux = 3 nvir, literal scale), 8 roots, conv 1e-6, FP32 ladder, 2 worker slots.  Engine 1: the
-    lockstep block Davidson (waves of two instances, a chunk of iterations of both per graph replay,
-    device-side convergence flags); engine 0: one host thread per worker stream, sigma passes replayed
-    from graphs.  The first run of a process also pays the ladder tuner's trial launches for every new
+    naux = 3 nvir, literal scale), 8 roots, conv 1e-6, FP32 ladder, BATCH_SLOTS worker slots.  Engine 1:
+    the lockstep block Davidson (waves of one instance per slot, chunks of iterations replayed from graphs
+    on each instance's stream, device-side convergence flags); engine 0: one host thread per worker
+    stream, sigma passes replayed from graphs.  The first run of a process also pays the ladder tuner's trial launches for every new
     shape (about 64 x 2 x 2 of them), so the engines are compared on later runs.  Instance generation is
     not timed."""
     import synth
@@ -205,7 +208,7 @@ def batched_study(adc, d, torch, np, n, modes=((0, "threads_cold_tuner"), (1, "l
     print("batched: %d instances generated in %.1f s" % (n, gen_s), file=sys.stderr, flush=True)
     sum_n = sum(int(x["eps_vir"].numel()) * (1 + int(x["eps_occ"].numel()) * int(x["eps_vir"].numel())) for x in inst)
     out = {"instances": n, "seeds": "100-%d" % (99 + n), "nroots": 8, "conv": 1e-6, "precision": "fp32 ladder",
-           "slots": 2, "sum_N": sum_n, "generation_s_untimed": gen_s}
+           "slots": BATCH_SLOTS, "sum_N": sum_n, "generation_s_untimed": gen_s}
     ref = None
     for mode, label in modes:
         o = adc.adc3_default_opts()
@@ -214,11 +217,11 @@ def batched_study(adc, d, torch, np, n, modes=((0, "threads_cold_tuner"), (1, "l
         o.lockstep = mode
         side = torch.cuda.Stream()
         with torch.cuda.stream(side):
-            nbytes = adc.adc3_ea_solve_batched_workspace_bytes(inst, o, 2)
+            nbytes = adc.adc3_ea_solve_batched_workspace_bytes(inst, o, BATCH_SLOTS)
             ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            roots, reps, sts, st = adc.adc3_ea_solve_batched(inst, o, 2, workspace=ws)
+            roots, reps, sts, st = adc.adc3_ea_solve_batched(inst, o, BATCH_SLOTS, workspace=ws)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
         sig = sum(rr[0]["sigma_builds"] for rr in reps)  # each instance's count sits on its root 0

@@ -107,8 +107,9 @@ typedef struct {
                              lockstep block Davidson (a build addition): each iteration of a chunk has a
                              fixed shape (one new direction per root not converged when the chunk began,
                              those converging within it zeroed) and keeps its convergence flags on the
-                             device, and a chunk of iterations of every active solve is one HIP graph
-                             replay; the host reads the flags once per chunk and sets the next block.  adc3_ea_solve: the
+                             device, and each solve's chunks of iterations are replayed from HIP graphs on
+                             its own stream; the host reads the flags once per chunk and sets the next
+                             block.  adc3_ea_solve: the
                              truncated ADC(2) solves of all roots' bases, then their ADC(3) solves
                              (all bases held at once: more workspace); adc3_ea_solve_batched: the
                              instances in waves of nstreams.  Jacobi and exact-1p steps only (precond 1

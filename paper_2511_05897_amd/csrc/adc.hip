@@ -1394,9 +1394,10 @@ static void lock_restart(LockJob& j, int phase) {
 }
 
 // Runs every job to convergence (or its max_iter).  Jobs start eagerly on streams of their own, then
-// advance `chunk` iterations per replay of one graph that forks from `main` into every active job's
-// stream and joins back; after each replay the jobs' status words come back in one copy.  Graphs are
-// kept per (job, subspace size, phase, chunk) set, so a repeating collapse cycle replays them.
+// advance `chunk` iterations per replay of a graph of their own, launched on their own stream (so that
+// the jobs run concurrently); after the replays every job's status comes back and the host decides
+// restarts and the next blocks.  Graphs are kept per (job, subspace size, phase, chunk, block width),
+// so a repeating collapse cycle replays them.
 static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int chunk) {
     // spaces too small for the fixed shape (a few truncated virtuals) take the one-at-a-time Davidson
     std::vector<LockJob*> jobs;
@@ -1430,12 +1431,13 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
         tot += j->nroots;
     }
     struct Res {
-        hipStream_t main = nullptr;  // the graphs' stream (capture needs a stream of its own)
+        hipStream_t main = nullptr;  // forks from the caller's stream into the jobs' streams and joins them back
         std::vector<hipStream_t> st;
         std::vector<hipEvent_t> ev;
         hipEvent_t fork = nullptr;
         double* host = nullptr;
         std::map<std::string, hipGraphExec_t> graphs;
+        std::set<std::string> seen;  // chunk shapes issued once without a graph
         ~Res() {
             for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
             for (auto e : ev) (void)hipEventDestroy(e);
@@ -1538,77 +1540,59 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
         step_eval(i);
         set_block(i);
     }
-    // a job's first chunk at each (precision, block width) runs eagerly: the ladder tuner settles the
-    // block's shapes before any capture
     std::vector<std::set<int>> tuned(nj);  // (phase, block width) pairs a job has run eagerly
     for (;;) {
         std::vector<int> act;
         for (int i = 0; i < nj; ++i)
             if (!jobs[i]->done) act.push_back(i);
         if (act.empty()) break;
-        std::vector<int> eager;
-        for (int i : act)
-            if (!tuned[i].count(jobs[i]->phase * 64 + jobs[i]->nb)) eager.push_back(i);
-        if (!eager.empty()) {
-            for (int i : eager) {
-                LockJob& j = *jobs[i];
-                const int K = std::max(1, std::min(chunk, j.max_iter - j.it));
-                tuned[i].insert(j.phase * 64 + j.nb);
+        // one graph per job and chunk shape, captured on and replayed on the job's own stream, so that the
+        // jobs' chunks run concurrently (the nodes of one graph run one after another).  A job's first chunk
+        // at a (precision, block width) runs eagerly, so that the ladder tuner settles its shapes before any
+        // capture; a shape is captured the second time it comes up (a collapse cycle repeats its shapes), and
+        // the first time its chunk is issued directly: a capture that is never replayed only costs host
+        // time, during which the other jobs' streams run dry.  Every job advances in every round.
+        for (int i : act) {
+            LockJob& j = *jobs[i];
+            const int K = std::max(1, std::min(chunk, j.max_iter - j.it));
+            if (tuned[i].insert(j.phase * 64 + j.nb).second) {
                 for (int k = 0; k < K; ++k) lock_iterate(j);
+                continue;
             }
-            for (int i : eager) read_status({i}, jobs[i]->s);
-            for (int i : eager) {
-                step_eval(i);
-                set_block(i);
+            const std::string key = std::to_string(i) + ":" + std::to_string(j.m) + ":" + std::to_string(j.phase) +
+                                    ":" + std::to_string(K) + ":" + std::to_string(j.nb);
+            auto g = rs.graphs.find(key);
+            if (g == rs.graphs.end() && rs.seen.insert(key).second) {
+                for (int k = 0; k < K; ++k) lock_iterate(j);
+                continue;
             }
-            continue;
-        }
-        // every active job's stream has finished its eager work: the graph forks from main
-        for (int i : act) {
-            HIPCHK(hipEventRecord(rs.ev[i], jobs[i]->s));
-            HIPCHK(hipStreamWaitEvent(main, rs.ev[i], 0));
-        }
-        std::vector<int> K(nj, 0);
-        std::string key;
-        for (int i : act) {
-            K[i] = std::max(1, std::min(chunk, jobs[i]->max_iter - jobs[i]->it));
-            key += std::to_string(i) + ":" + std::to_string(jobs[i]->m) + ":" + std::to_string(jobs[i]->phase) + ":" +
-                   std::to_string(K[i]) + ":" + std::to_string(jobs[i]->nb) + ";";
-        }
-        auto g = rs.graphs.find(key);
-        if (g == rs.graphs.end()) {
-            hipGraph_t gr = nullptr;
-            HIPCHK(hipStreamBeginCapture(main, hipStreamCaptureModeThreadLocal));
-            try {
-                HIPCHK(hipEventRecord(rs.fork, main));
-                for (int i : act) {
-                    LockJob& j = *jobs[i];
-                    HIPCHK(hipStreamWaitEvent(j.s, rs.fork, 0));
-                    for (int k = 0; k < K[i]; ++k) lock_iterate(j);
-                    HIPCHK(hipEventRecord(rs.ev[i], j.s));
-                    HIPCHK(hipStreamWaitEvent(main, rs.ev[i], 0));
+            if (g == rs.graphs.end()) {
+                hipGraph_t gr = nullptr;
+                HIPCHK(hipStreamBeginCapture(j.s, hipStreamCaptureModeThreadLocal));
+                try {
+                    for (int k = 0; k < K; ++k) lock_iterate(j);
+                } catch (...) {
+                    // close the capture so that no stream is left capturing
+                    hipGraph_t bad = nullptr;
+                    (void)hipStreamEndCapture(j.s, &bad);
+                    if (bad) (void)hipGraphDestroy(bad);
+                    throw;
                 }
-            } catch (...) {
-                // close the capture so that no stream is left capturing
-                hipGraph_t bad = nullptr;
-                (void)hipStreamEndCapture(main, &bad);
-                if (bad) (void)hipGraphDestroy(bad);
-                throw;
+                HIPCHK(hipStreamEndCapture(j.s, &gr));
+                hipGraphExec_t ex = nullptr;
+                HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+                HIPCHK(hipGraphDestroy(gr));
+                g = rs.graphs.emplace(key, ex).first;
+            } else {
+                for (int k = 0; k < K; ++k) lock_iterate_host(j);
             }
-            HIPCHK(hipStreamEndCapture(main, &gr));
-            hipGraphExec_t ex = nullptr;
-            HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
-            HIPCHK(hipGraphDestroy(gr));
-            g = rs.graphs.emplace(key, ex).first;
-        } else {
-            for (int i : act)
-                for (int k = 0; k < K[i]; ++k) lock_iterate_host(*jobs[i]);
+            HIPCHK(hipGraphLaunch(g->second, j.s));
         }
-        HIPCHK(hipGraphLaunch(g->second, main));
-        read_status(act, main);
-        // eager work of the next round (restarts) runs on each job's stream after the replay
-        HIPCHK(hipEventRecord(rs.fork, main));
-        for (int i : act) HIPCHK(hipStreamWaitEvent(jobs[i]->s, rs.fork, 0));
+        // every job's status after its chunk, in one wait
+        for (int i : act)
+            HIPCHK(hipMemcpyAsync(rs.host + jobs[i]->status_off, jobs[i]->status,
+                                  (2 + 3 * jobs[i]->nroots) * sizeof(double), hipMemcpyDeviceToHost, jobs[i]->s));
+        for (int i : act) HIPCHK(hipStreamSynchronize(jobs[i]->s));
         for (int i : act) {
             step_eval(i);
             set_block(i);

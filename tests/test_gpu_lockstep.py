@@ -1,5 +1,6 @@
 """The lockstep block Davidson (opts.lockstep = 1): fixed-shape iterations with the convergence flags on
-the device, a chunk of iterations of every active solve per HIP-graph replay.  Against the FP64 oracle
+the device, each solve's chunks of iterations replayed from HIP graphs on its own stream, the block
+shrinking to the roots still active at each chunk boundary.  Against the FP64 oracle
 (1e-8 Eh FP64, 1e-6 Eh mixed precision) and the one-solve-at-a-time path:
 
 * one canonical solve (tiny dense workload: full diagonalisation of the oracle's matrix);
