@@ -113,7 +113,9 @@ typedef struct {
                              truncated ADC(2) solves of all roots' bases, then their ADC(3) solves
                              (all bases held at once: more workspace); adc3_ea_solve_batched: the
                              instances in waves of nstreams.  Jacobi and exact-1p steps only (precond 1
-                             and 2 keep the sequential solves).  0 (default): one solve at a time. */
+                             and 2 keep the sequential solves).  0: one solve at a time.  -1 (default):
+                             lockstep for the per-root bases of one solve when there are two or more,
+                             one solve at a time otherwise, worker threads for batches. */
 } adc3_opts;
 
 /* Per-root report of adc3_ea_solve. */

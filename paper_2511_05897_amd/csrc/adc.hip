@@ -1873,7 +1873,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         c->graphs = op.sigma_graphs != 0;
         double* vecs = op.vectors_out ? op.vectors_out : take(ws, (long long)nroots * N0);
         DavResult r;
-        if (op.lockstep && op.precond != 1 && op.precond != 2) {
+        if (op.lockstep == 1 && op.precond != 1 && op.precond != 2) {
             // the lockstep engine with one problem: fixed-shape iterations replayed from graphs
             LockJob j;
             j.c = c;
@@ -2008,7 +2008,13 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
     }
     // step 4, all bases together: their truncated ADC(2) solves in one lockstep Davidson, then their
     // ADC(3) solves in another (the Learned and Olsen steps are not in the lockstep engine)
-    const bool lock = op.lockstep != 0 && op.precond != 1 && op.precond != 2;
+    // (opts.lockstep -1, the default: whenever there are two bases or more and their stored ladders, at the
+    // untruncated size, take at most the stored ladder's budget of 96 GB together; planning and the solve
+    // take the same decision)
+    const bool df_all = op.ladder == 2 || (op.ladder == 0 && ladder_df_auto(v));
+    const double lock_ladder_bytes = (double)nb * 4.0 * (double)v * v * v * v;
+    const bool lock_auto = nb >= 2 && !df_all && lock_ladder_bytes <= 96e9;
+    const bool lock = (op.lockstep == 1 || (op.lockstep < 0 && lock_auto)) && op.precond != 1 && op.precond != 2;
     if (lock) {
         GemmScratch gscr(ws, GEMM_SCRATCH);
         std::vector<Blocks> Bn(nb);
@@ -2366,7 +2372,7 @@ void adc3_default_opts(adc3_opts* o) {
     o->n_guess = 0;
     o->vectors_out = nullptr;
     o->dyson_out = nullptr;
-    o->lockstep = 0;
+    o->lockstep = -1;
 }
 
 const char* adc3_last_error(void) { return g_msg.c_str(); }
@@ -2733,7 +2739,7 @@ static adc3_opts resolve_opts(const adc3_opts* opts) {
     if (o.fno_mode != 0 && o.fno_mode != 1) fail(ADC3_EINVAL, "opts.fno_mode must be 0 (state-specific) or 1 (MP2)");
     if (!(o.fno_keep_frac >= 0.0 && o.fno_keep_frac <= 1.0)) fail(ADC3_EINVAL, "opts.fno_keep_frac must lie in [0, 1]");
     if (o.n_guess < 0 || (o.n_guess > 0 && !o.init_guess)) fail(ADC3_EINVAL, "opts.n_guess > 0 needs opts.init_guess");
-    if (o.lockstep != 0 && o.lockstep != 1) fail(ADC3_EINVAL, "opts.lockstep must be 0 or 1");
+    if (o.lockstep < -1 || o.lockstep > 1) fail(ADC3_EINVAL, "opts.lockstep must be -1, 0 or 1");
     return o;
 }
 
@@ -3013,7 +3019,7 @@ extern "C" int adc3_ea_solve_batched(const adc3_instance* inst, int ninst, const
     if (P.total > ws_bytes) fail(ADC3_ENOMEM, "workspace too small: need " + std::to_string(P.total) + " bytes");
     std::vector<long long> first(ninst + 1, 0);
     for (int i = 0; i < ninst; ++i) first[i + 1] = first[i] + std::max(inst[i].nroots, 0);
-    if (op.lockstep) {
+    if (op.lockstep == 1) {
         std::vector<int> st(ninst, ADC3_OK);
         std::vector<std::string> msg(ninst);
         batched_lockstep(inst, ninst, op, P, nw, first, roots_out, reports, st, msg, workspace, stream);

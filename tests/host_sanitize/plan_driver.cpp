@@ -41,7 +41,7 @@ int main() {
     adc3_opts o;
     adc3_default_opts(&o);
     for (const Shape& sh : kShapes)
-        for (int lock = 0; lock < 2; ++lock)
+        for (int lock = -1; lock < 2; ++lock)
             for (int prec = 0; prec < 3; ++prec)
                 for (int mode = 0; mode < 2; ++mode) {
                     adc3_opts p = o;
