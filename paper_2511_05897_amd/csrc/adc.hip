@@ -36,6 +36,7 @@
 #include <map>
 #include <set>
 #include <string>
+#include <exception>
 #include <thread>
 #include <vector>
 
@@ -1436,10 +1437,11 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
         std::vector<hipEvent_t> ev;
         hipEvent_t fork = nullptr;
         double* host = nullptr;
-        std::map<std::string, hipGraphExec_t> graphs;
-        std::set<std::string> seen;  // chunk shapes issued once without a graph
+        std::vector<std::map<std::string, hipGraphExec_t>> graphs;  // per job
+        std::vector<std::set<std::string>> seen;  // per job: chunk shapes issued once without a graph
         ~Res() {
-            for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+            for (auto& m : graphs)
+                for (auto& kv : m) (void)hipGraphExecDestroy(kv.second);
             for (auto e : ev) (void)hipEventDestroy(e);
             if (fork) (void)hipEventDestroy(fork);
             for (auto x : st) (void)hipStreamDestroy(x);
@@ -1447,6 +1449,8 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
             if (host) (void)hipHostFree(host);
         }
     } rs;
+    rs.graphs.resize(nj);
+    rs.seen.resize(nj);
     HIPCHK(hipHostMalloc((void**)&rs.host, std::max<size_t>(tot, 1) * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&rs.fork, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&rs.main, hipStreamNonBlocking));
@@ -1551,51 +1555,74 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
         // at a (precision, block width) runs eagerly, so that the ladder tuner settles its shapes before any
         // capture; a shape is captured the second time it comes up (a collapse cycle repeats its shapes), and
         // the first time its chunk is issued directly: a capture that is never replayed only costs host
-        // time, during which the other jobs' streams run dry.  Every job advances in every round.
-        for (int i : act) {
+        // time.  Every job advances in every round, each issued, waited for and evaluated by a host thread
+        // of its own (small problems' chunks take about as long to issue as to run), the round ending when
+        // all have.
+        auto advance = [&](int i) {
             LockJob& j = *jobs[i];
             const int K = std::max(1, std::min(chunk, j.max_iter - j.it));
             if (tuned[i].insert(j.phase * 64 + j.nb).second) {
                 for (int k = 0; k < K; ++k) lock_iterate(j);
-                continue;
-            }
-            const std::string key = std::to_string(i) + ":" + std::to_string(j.m) + ":" + std::to_string(j.phase) +
-                                    ":" + std::to_string(K) + ":" + std::to_string(j.nb);
-            auto g = rs.graphs.find(key);
-            if (g == rs.graphs.end() && rs.seen.insert(key).second) {
-                for (int k = 0; k < K; ++k) lock_iterate(j);
-                continue;
-            }
-            if (g == rs.graphs.end()) {
-                hipGraph_t gr = nullptr;
-                HIPCHK(hipStreamBeginCapture(j.s, hipStreamCaptureModeThreadLocal));
-                try {
-                    for (int k = 0; k < K; ++k) lock_iterate(j);
-                } catch (...) {
-                    // close the capture so that no stream is left capturing
-                    hipGraph_t bad = nullptr;
-                    (void)hipStreamEndCapture(j.s, &bad);
-                    if (bad) (void)hipGraphDestroy(bad);
-                    throw;
-                }
-                HIPCHK(hipStreamEndCapture(j.s, &gr));
-                hipGraphExec_t ex = nullptr;
-                HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
-                HIPCHK(hipGraphDestroy(gr));
-                g = rs.graphs.emplace(key, ex).first;
             } else {
-                for (int k = 0; k < K; ++k) lock_iterate_host(j);
+                const std::string key = std::to_string(j.m) + ":" + std::to_string(j.phase) + ":" +
+                                        std::to_string(K) + ":" + std::to_string(j.nb);
+                auto& graphs = rs.graphs[i];
+                auto g = graphs.find(key);
+                if (g == graphs.end() && rs.seen[i].insert(key).second) {
+                    for (int k = 0; k < K; ++k) lock_iterate(j);
+                } else {
+                    if (g == graphs.end()) {
+                        hipGraph_t gr = nullptr;
+                        HIPCHK(hipStreamBeginCapture(j.s, hipStreamCaptureModeThreadLocal));
+                        try {
+                            for (int k = 0; k < K; ++k) lock_iterate(j);
+                        } catch (...) {
+                            // close the capture so that no stream is left capturing
+                            hipGraph_t bad = nullptr;
+                            (void)hipStreamEndCapture(j.s, &bad);
+                            if (bad) (void)hipGraphDestroy(bad);
+                            throw;
+                        }
+                        HIPCHK(hipStreamEndCapture(j.s, &gr));
+                        hipGraphExec_t ex = nullptr;
+                        HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+                        HIPCHK(hipGraphDestroy(gr));
+                        g = graphs.emplace(key, ex).first;
+                    } else {
+                        for (int k = 0; k < K; ++k) lock_iterate_host(j);
+                    }
+                    HIPCHK(hipGraphLaunch(g->second, j.s));
+                }
             }
-            HIPCHK(hipGraphLaunch(g->second, j.s));
-        }
-        // every job's status after its chunk, in one wait
-        for (int i : act)
-            HIPCHK(hipMemcpyAsync(rs.host + jobs[i]->status_off, jobs[i]->status,
-                                  (2 + 3 * jobs[i]->nroots) * sizeof(double), hipMemcpyDeviceToHost, jobs[i]->s));
-        for (int i : act) HIPCHK(hipStreamSynchronize(jobs[i]->s));
-        for (int i : act) {
+            // the job's status after its chunk
+            HIPCHK(hipMemcpyAsync(rs.host + j.status_off, j.status, (2 + 3 * j.nroots) * sizeof(double),
+                                  hipMemcpyDeviceToHost, j.s));
+            HIPCHK(hipStreamSynchronize(j.s));
             step_eval(i);
             set_block(i);
+        };
+        if (act.size() == 1) {
+            advance(act[0]);
+        } else {
+            std::vector<std::exception_ptr> errs(act.size());
+            std::vector<std::thread> th;
+            th.reserve(act.size() - 1);
+            for (size_t t = 1; t < act.size(); ++t)
+                th.emplace_back([&, t] {
+                    try {
+                        advance(act[t]);
+                    } catch (...) {
+                        errs[t] = std::current_exception();
+                    }
+                });
+            try {
+                advance(act[0]);
+            } catch (...) {
+                errs[0] = std::current_exception();
+            }
+            for (auto& x : th) x.join();
+            for (auto& e : errs)
+                if (e) std::rethrow_exception(e);
         }
     }
     for (int i = 0; i < nj; ++i) {
@@ -2905,17 +2932,46 @@ static void batched_lockstep(const adc3_instance* inst, int ninst, const adc3_op
     }
     size_t nwave = 0;
     for (auto& v : slot) nwave = std::max(nwave, v.size());
+    struct SlotStreams {
+        std::vector<hipStream_t> st;
+        std::vector<hipEvent_t> ev;
+        hipEvent_t wave = nullptr;
+        ~SlotStreams() {
+            if (wave) (void)hipEventDestroy(wave);
+            for (auto e : ev) (void)hipEventDestroy(e);
+            for (auto x : st) (void)hipStreamDestroy(x);
+        }
+    } slr;
+    HIPCHK(hipEventCreateWithFlags(&slr.wave, hipEventDisableTiming));
+    for (int sl = 0; sl < nw; ++sl) {
+        hipStream_t x = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        slr.st.push_back(x);
+        hipEvent_t e = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        slr.ev.push_back(e);
+    }
+    const std::vector<hipStream_t>& sls = slr.st;
+    const std::vector<hipEvent_t>& sev = slr.ev;
     for (size_t w = 0; w < nwave; ++w) {
+        // the slots' streams start after everything on the caller's stream: the inputs, and the previous
+        // wave's work on the same workspace slices
+        HIPCHK(hipEventRecord(slr.wave, s));
+        for (int sl = 0; sl < nw; ++sl) HIPCHK(hipStreamWaitEvent(sls[sl], slr.wave, 0));
+        std::vector<std::exception_ptr> errs(nw);
         std::vector<Arena> ar(nw);
         std::vector<Ctx*> ctx(nw, nullptr);
         std::vector<LockJob> jobs(nw);
         std::vector<double*> vecs(nw, nullptr);
         std::vector<int> who(nw, -1);
         std::vector<LockJob*> jp;
-        for (int sl = 0; sl < nw; ++sl) {
-            if (w >= slot[sl].size()) continue;
+        // each slot's instance is checked and its context built on the slot's own stream by a host thread
+        // of its own, so that the wave's setups overlap (an instance that truncates runs its whole pipeline
+        // there); the wave's Davidsons then start together, ordered after every setup
+        auto prepare = [&](int sl) {
             const int i = slot[sl][w];
             const adc3_instance& in = inst[i];
+            hipStream_t ss = sls[sl];
             ar[sl].base = (char*)workspace + P.offset[sl];
             ar[sl].cap = P.bytes[sl];
             try {
@@ -2924,27 +2980,27 @@ static void batched_lockstep(const adc3_instance* inst, int ninst, const adc3_op
                 const long long N = in.nvir + (long long)in.nocc * in.nvir * in.nvir;
                 if (in.nroots < 1 || in.nroots > N) fail(ADC3_EINVAL, "nroots must be in [1, N]");
                 if (!(in.conv > 0) || !std::isfinite(in.conv)) fail(ADC3_EINVAL, "conv must be a positive number");
-                validate_inputs(in.eps_occ, in.eps_vir, in.B, in.nocc, in.nvir, in.naux, s, ar[sl]);
+                validate_inputs(in.eps_occ, in.eps_vir, in.B, in.nocc, in.nvir, in.naux, ss, ar[sl]);
                 Blocks B0;
                 B0.X = in.naux; B0.o = in.nocc; B0.v = in.nvir;
                 B0.Boo = take(ar[sl], (long long)in.naux * in.nocc * in.nocc);
                 B0.Bov = take(ar[sl], (long long)in.naux * in.nocc * in.nvir);
                 B0.Bvv = take(ar[sl], (long long)in.naux * in.nvir * in.nvir);
-                k_split_B(in.B, in.naux, in.nocc, in.nvir, B0.Boo, B0.Bov, B0.Bvv, s);
+                k_split_B(in.B, in.naux, in.nocc, in.nvir, B0.Boo, B0.Bov, B0.Bvv, ss);
                 if (truncates(in.fno_thresh, in.naf_thresh, op)) {
                     SolveOut r = solve_impl(ar[sl], in.eps_occ, in.eps_vir, B0, in.nroots, in.fno_thresh,
-                                            in.naf_thresh, in.conv, op, s);
-                    HIPCHK(hipStreamSynchronize(s));
+                                            in.naf_thresh, in.conv, op, ss);
+                    HIPCHK(hipStreamSynchronize(ss));
                     for (int k = 0; k < in.nroots; ++k) {
                         roots_out[first[i] + k] = r.rep[k].omega;
                         if (reports) reports[first[i] + k] = r.rep[k];
                     }
                     st[i] = r.all_conv ? ADC3_OK : ADC3_WNOCONV;
-                    continue;
+                    return;
                 }
                 const bool df = op.ladder == 2 || (op.ladder == 0 && ladder_df_auto(in.nvir));
                 ctx[sl] = build_ctx(ar[sl], in.eps_occ, in.eps_vir, B0.Boo, B0.Bov, B0.Bvv, in.nocc, in.nvir, in.naux,
-                                    op.level, s, op.precision, df, op.level >= 3 ? op.sm_x : 1.0);
+                                    op.level, ss, op.precision, df, op.level >= 3 ? op.sm_x : 1.0);
                 vecs[sl] = take(ar[sl], (long long)in.nroots * N);
                 LockJob& j = jobs[sl];
                 j.c = ctx[sl];
@@ -2954,13 +3010,31 @@ static void batched_lockstep(const adc3_instance* inst, int ninst, const adc3_op
                 j.vec_out = vecs[sl];
                 j.arena = &ar[sl];
                 who[sl] = i;
-                jp.push_back(&j);
             } catch (const Error& e) {
                 g_dry = false;
                 st[i] = e.status;
                 msg[i] = e.msg;
                 if (ctx[sl]) { delete ctx[sl]; ctx[sl] = nullptr; }
+                if (e.status == ADC3_EHIP) errs[sl] = std::current_exception();
+            } catch (...) {
+                if (ctx[sl]) { delete ctx[sl]; ctx[sl] = nullptr; }
+                errs[sl] = std::current_exception();
             }
+        };
+        {
+            std::vector<std::thread> th;
+            for (int sl = 1; sl < nw; ++sl)
+                if (w < slot[sl].size()) th.emplace_back(prepare, sl);
+            if (w < slot[0].size()) prepare(0);
+            for (auto& x : th) x.join();
+        }
+        for (auto& e : errs)
+            if (e) std::rethrow_exception(e);
+        for (int sl = 0; sl < nw; ++sl) {
+            if (w >= slot[sl].size()) continue;
+            HIPCHK(hipEventRecord(sev[sl], sls[sl]));
+            HIPCHK(hipStreamWaitEvent(s, sev[sl], 0));
+            if (who[sl] >= 0) jp.push_back(&jobs[sl]);
         }
         if (!jp.empty()) {
             try {
