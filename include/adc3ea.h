@@ -103,19 +103,23 @@ typedef struct {
                              (eqs 7-8) of each reported root in the canonical MO basis (occupied first),
                              i.e. the Dyson-orbital coefficients; each vector's largest-magnitude entry made
                              positive.  See adc3_ea_spectral_amplitudes for f. */
-    int lockstep;         /* 1: Davidson solves that do not depend on each other run together in one
-                             lockstep block Davidson (a build addition): each iteration of a chunk has a
-                             fixed shape (one new direction per root not converged when the chunk began,
-                             those converging within it zeroed) and keeps its convergence flags on the
-                             device, and each solve's chunks of iterations are replayed from HIP graphs on
-                             its own stream; the host reads the flags once per chunk and sets the next
-                             block.  adc3_ea_solve: the
-                             truncated ADC(2) solves of all roots' bases, then their ADC(3) solves
-                             (all bases held at once: more workspace); adc3_ea_solve_batched: the
-                             instances in waves of nstreams.  Jacobi and exact-1p steps only (precond 1
-                             and 2 keep the sequential solves).  0: one solve at a time.  -1 (default):
-                             lockstep for the per-root bases of one solve when there are two or more,
-                             one solve at a time otherwise, worker threads for batches. */
+    int lockstep;         /* Engine of Davidson solves that do not depend on each other (a build
+                             addition).  adc3_ea_solve: the truncated ADC(2) solves of all roots' bases,
+                             then their ADC(3) solves (all bases held at once: more workspace);
+                             adc3_ea_solve_batched: the instances.
+                             1: one lockstep block Davidson: each iteration of a chunk has a fixed shape
+                             (one new direction per root not converged when the chunk began, those
+                             converging within it zeroed) and keeps its convergence flags on the device,
+                             and each solve's chunks of iterations are replayed from HIP graphs on its own
+                             stream; the host reads the flags once per chunk and sets the next block.
+                             Batches: the instances in waves of nstreams.  Jacobi and exact-1p steps only
+                             (precond 1 and 2 keep one solve at a time).
+                             2: each solve on a host thread and a stream of its own, with the one-at-a-time
+                             solver (the same iterations and roots as 0, the solves' kernels overlapping).
+                             Batches: worker threads, as 0.
+                             0: one solve at a time (batches: worker threads, one per stream).
+                             -1 (default): 2 for the per-root bases of one solve when there are two or more
+                             and their stored ladders take at most 96 GB together, else 0. */
 } adc3_opts;
 
 /* Per-root report of adc3_ea_solve. */

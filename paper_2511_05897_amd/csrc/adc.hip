@@ -1136,6 +1136,7 @@ struct LockJob {
     int nguess_in = 0;
     double* vec_out = nullptr;  // [nroots][N], nullable
     Arena* arena = nullptr;     // where the job's buffers are taken (jobs may share one)
+    bool mlp = false;           // the learned step (the thread engine only; the context holds the weights)
     // state
     hipStream_t s = nullptr;
     long long N = 0;
@@ -1545,85 +1546,88 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
         set_block(i);
     }
     std::vector<std::set<int>> tuned(nj);  // (phase, block width) pairs a job has run eagerly
-    for (;;) {
-        std::vector<int> act;
-        for (int i = 0; i < nj; ++i)
-            if (!jobs[i]->done) act.push_back(i);
-        if (act.empty()) break;
-        // one graph per job and chunk shape, captured on and replayed on the job's own stream, so that the
-        // jobs' chunks run concurrently (the nodes of one graph run one after another).  A job's first chunk
-        // at a (precision, block width) runs eagerly, so that the ladder tuner settles its shapes before any
-        // capture; a shape is captured the second time it comes up (a collapse cycle repeats its shapes), and
-        // the first time its chunk is issued directly: a capture that is never replayed only costs host
-        // time.  Every job advances in every round, each issued, waited for and evaluated by a host thread
-        // of its own (small problems' chunks take about as long to issue as to run), the round ending when
-        // all have.
-        auto advance = [&](int i) {
-            LockJob& j = *jobs[i];
-            const int K = std::max(1, std::min(chunk, j.max_iter - j.it));
-            if (tuned[i].insert(j.phase * 64 + j.nb).second) {
+    // one graph per job and chunk shape, captured on and replayed on the job's own stream, so that the
+    // jobs' chunks run concurrently (the nodes of one graph run one after another).  A job's first chunk
+    // at a (precision, block width) runs eagerly, so that the ladder tuner settles its shapes before any
+    // capture; a shape is captured the second time it comes up (a collapse cycle repeats its shapes), and
+    // the first time its chunk is issued directly: a capture that is never replayed only costs host
+    // time.  Each job is issued, waited for and evaluated by a host thread of its own, chunk after chunk
+    // until it ends, without waiting for the other jobs' chunks (problems of different sizes and root
+    // counts take chunks of different lengths).
+    auto advance = [&](int i) {
+        LockJob& j = *jobs[i];
+        const int K = std::max(1, std::min(chunk, j.max_iter - j.it));
+        if (tuned[i].insert(j.phase * 64 + j.nb).second) {
+            for (int k = 0; k < K; ++k) lock_iterate(j);
+        } else {
+            const std::string key = std::to_string(j.m) + ":" + std::to_string(j.phase) + ":" +
+                                    std::to_string(K) + ":" + std::to_string(j.nb);
+            auto& graphs = rs.graphs[i];
+            auto g = graphs.find(key);
+            if (g == graphs.end() && rs.seen[i].insert(key).second) {
                 for (int k = 0; k < K; ++k) lock_iterate(j);
             } else {
-                const std::string key = std::to_string(j.m) + ":" + std::to_string(j.phase) + ":" +
-                                        std::to_string(K) + ":" + std::to_string(j.nb);
-                auto& graphs = rs.graphs[i];
-                auto g = graphs.find(key);
-                if (g == graphs.end() && rs.seen[i].insert(key).second) {
-                    for (int k = 0; k < K; ++k) lock_iterate(j);
-                } else {
-                    if (g == graphs.end()) {
-                        hipGraph_t gr = nullptr;
-                        HIPCHK(hipStreamBeginCapture(j.s, hipStreamCaptureModeThreadLocal));
-                        try {
-                            for (int k = 0; k < K; ++k) lock_iterate(j);
-                        } catch (...) {
-                            // close the capture so that no stream is left capturing
-                            hipGraph_t bad = nullptr;
-                            (void)hipStreamEndCapture(j.s, &bad);
-                            if (bad) (void)hipGraphDestroy(bad);
-                            throw;
-                        }
-                        HIPCHK(hipStreamEndCapture(j.s, &gr));
-                        hipGraphExec_t ex = nullptr;
-                        HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
-                        HIPCHK(hipGraphDestroy(gr));
-                        g = graphs.emplace(key, ex).first;
-                    } else {
-                        for (int k = 0; k < K; ++k) lock_iterate_host(j);
-                    }
-                    HIPCHK(hipGraphLaunch(g->second, j.s));
-                }
-            }
-            // the job's status after its chunk
-            HIPCHK(hipMemcpyAsync(rs.host + j.status_off, j.status, (2 + 3 * j.nroots) * sizeof(double),
-                                  hipMemcpyDeviceToHost, j.s));
-            HIPCHK(hipStreamSynchronize(j.s));
-            step_eval(i);
-            set_block(i);
-        };
-        if (act.size() == 1) {
-            advance(act[0]);
-        } else {
-            std::vector<std::exception_ptr> errs(act.size());
-            std::vector<std::thread> th;
-            th.reserve(act.size() - 1);
-            for (size_t t = 1; t < act.size(); ++t)
-                th.emplace_back([&, t] {
+                if (g == graphs.end()) {
+                    hipGraph_t gr = nullptr;
+                    HIPCHK(hipStreamBeginCapture(j.s, hipStreamCaptureModeThreadLocal));
                     try {
-                        advance(act[t]);
+                        for (int k = 0; k < K; ++k) lock_iterate(j);
                     } catch (...) {
-                        errs[t] = std::current_exception();
+                        // close the capture so that no stream is left capturing
+                        hipGraph_t bad = nullptr;
+                        (void)hipStreamEndCapture(j.s, &bad);
+                        if (bad) (void)hipGraphDestroy(bad);
+                        throw;
                     }
-                });
-            try {
-                advance(act[0]);
-            } catch (...) {
-                errs[0] = std::current_exception();
+                    HIPCHK(hipStreamEndCapture(j.s, &gr));
+                    hipGraphExec_t ex = nullptr;
+                    HIPCHK(hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0));
+                    HIPCHK(hipGraphDestroy(gr));
+                    g = graphs.emplace(key, ex).first;
+                } else {
+                    for (int k = 0; k < K; ++k) lock_iterate_host(j);
+                }
+                HIPCHK(hipGraphLaunch(g->second, j.s));
             }
-            for (auto& x : th) x.join();
-            for (auto& e : errs)
-                if (e) std::rethrow_exception(e);
         }
+        // the job's status after its chunk
+        HIPCHK(hipMemcpyAsync(rs.host + j.status_off, j.status, (2 + 3 * j.nroots) * sizeof(double),
+                              hipMemcpyDeviceToHost, j.s));
+        HIPCHK(hipStreamSynchronize(j.s));
+        step_eval(i);
+        set_block(i);
+    };
+    std::atomic<bool> stop{false};
+    auto run = [&](int i) {
+        while (!jobs[i]->done && !stop.load()) advance(i);
+    };
+    std::vector<int> act;
+    for (int i = 0; i < nj; ++i)
+        if (!jobs[i]->done) act.push_back(i);
+    if (act.size() == 1) {
+        run(act[0]);
+    } else if (!act.empty()) {
+        std::vector<std::exception_ptr> errs(act.size());
+        std::vector<std::thread> th;
+        th.reserve(act.size() - 1);
+        for (size_t t = 1; t < act.size(); ++t)
+            th.emplace_back([&, t] {
+                try {
+                    run(act[t]);
+                } catch (...) {
+                    errs[t] = std::current_exception();
+                    stop.store(true);
+                }
+            });
+        try {
+            run(act[0]);
+        } catch (...) {
+            errs[0] = std::current_exception();
+            stop.store(true);
+        }
+        for (auto& x : th) x.join();
+        for (auto& e : errs)
+            if (e) std::rethrow_exception(e);
     }
     for (int i = 0; i < nj; ++i) {
         LockJob& j = *jobs[i];
@@ -1635,6 +1639,82 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
     HIPCHK(hipEventRecord(rs.fork, main));
     HIPCHK(hipStreamWaitEvent(caller, rs.fork, 0));
     for (auto* j : jobs) j->s = nullptr;
+}
+
+// The jobs' Davidsons on the one-at-a-time solver, each on a host thread and a stream of its own, in
+// slices of the jobs' arena (sized by a dry run of the solver): the problems' kernels overlap on the GPU,
+// and each problem takes its host decisions at every iteration without waiting for the others.
+static void threads_run(std::vector<LockJob*>& jobs, hipStream_t caller) {
+    const int nj = (int)jobs.size();
+    std::vector<Arena> sub(nj);
+    for (int i = 0; i < nj; ++i) {
+        LockJob& j = *jobs[i];
+        size_t bytes = 0;
+        {
+            const bool was = g_dry;
+            g_dry = true;
+            Arena count;
+            // (the dry run's result, zero roots of the right count, stands for the job's in a planning run)
+            j.res = davidson_impl(j.c, count, j.nroots, j.conv, j.max_iter, j.max_sub, nullptr, nullptr, j.prec, j.mlp,
+                                  nullptr, j.guess, j.nguess_in, j.pmode);
+            g_dry = was;
+            bytes = (count.peak + GEMM_SCRATCH * sizeof(double) + 4096 + 255) / 256 * 256;
+        }
+        sub[i].base = j.arena->take<char>(bytes);
+        sub[i].cap = bytes;
+    }
+    if (g_dry || nj == 0) return;
+    struct Res {
+        std::vector<hipStream_t> st;
+        std::vector<hipEvent_t> ev;
+        hipEvent_t fork = nullptr;
+        ~Res() {
+            for (auto e : ev) (void)hipEventDestroy(e);
+            if (fork) (void)hipEventDestroy(fork);
+            for (auto x : st) (void)hipStreamDestroy(x);
+        }
+    } rs;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipEventCreateWithFlags(&rs.fork, hipEventDisableTiming));
+    HIPCHK(hipEventRecord(rs.fork, caller));
+    for (int i = 0; i < nj; ++i) {
+        hipStream_t x = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+        rs.st.push_back(x);
+        hipEvent_t e = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        rs.ev.push_back(e);
+        HIPCHK(hipStreamWaitEvent(x, rs.fork, 0));
+    }
+    std::vector<std::exception_ptr> errs(nj);
+    auto run = [&](int i) {
+        try {
+            HIPCHK(hipSetDevice(dev));
+            LockJob& j = *jobs[i];
+            GemmScratch g(sub[i], GEMM_SCRATCH);
+            const long long before = j.c->sigma_count;
+            j.res = davidson_impl(j.c, sub[i], j.nroots, j.conv, j.max_iter, j.max_sub, j.vec_out, rs.st[i], j.prec,
+                                  j.mlp, nullptr, j.guess, j.nguess_in, j.pmode);
+            j.sigma_builds = j.c->sigma_count - before;
+            j.done = true;
+        } catch (...) {
+            errs[i] = std::current_exception();
+        }
+    };
+    {
+        std::vector<std::thread> th;
+        for (int i = 1; i < nj; ++i) th.emplace_back(run, i);
+        run(0);
+        for (auto& x : th) x.join();
+    }
+    for (int i = 0; i < nj; ++i) {
+        HIPCHK(hipEventRecord(rs.ev[i], rs.st[i]));
+        HIPCHK(hipStreamWaitEvent(caller, rs.ev[i], 0));
+    }
+    HIPCHK(hipStreamSynchronize(caller));
+    for (auto& e : errs)
+        if (e) std::rethrow_exception(e);
 }
 
 // ---------------------------------------------------------------------------
@@ -2033,16 +2113,24 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         }
         ws.release(mm);
     }
-    // step 4, all bases together: their truncated ADC(2) solves in one lockstep Davidson, then their
-    // ADC(3) solves in another (the Learned and Olsen steps are not in the lockstep engine)
-    // (opts.lockstep -1, the default: whenever there are two bases or more and their stored ladders, at the
-    // untruncated size, take at most the stored ladder's budget of 96 GB together; planning and the solve
-    // take the same decision)
+    // step 4, all bases together: their truncated ADC(2) solves, then their ADC(3) solves, either in the
+    // lockstep block Davidson (opts.lockstep 1; not with the learned and Olsen steps) or each on a host
+    // thread and stream of its own (opts.lockstep 2, and the default -1 whenever there are two bases or
+    // more and their stored ladders, at the untruncated size, take at most the stored ladder's budget of
+    // 96 GB together); else one basis after the other.  Planning and the solve take the same decision.
     const bool df_all = op.ladder == 2 || (op.ladder == 0 && ladder_df_auto(v));
     const double lock_ladder_bytes = (double)nb * 4.0 * (double)v * v * v * v;
-    const bool lock_auto = nb >= 2 && !df_all && lock_ladder_bytes <= 96e9;
-    const bool lock = (op.lockstep == 1 || (op.lockstep < 0 && lock_auto)) && op.precond != 1 && op.precond != 2;
-    if (lock) {
+    const bool together_auto = nb >= 2 && !df_all && lock_ladder_bytes <= 96e9;
+    const int engine = (op.lockstep == 1 && op.precond != 1 && op.precond != 2) ? 1
+                       : (op.lockstep == 2 || (op.lockstep < 0 && together_auto)) ? 2
+                                                                                   : 0;
+    auto run_jobs = [&](std::vector<LockJob*>& jp) {
+        const size_t mj = ws.mark();
+        if (engine == 1) lockstep_run(jp, s, lockstep_chunk());
+        else threads_run(jp, s);
+        ws.release(mj);
+    };
+    if (engine != 0) {
         GemmScratch gscr(ws, GEMM_SCRATCH);
         std::vector<Blocks> Bn(nb);
         std::vector<int> xks(nb, X);
@@ -2087,7 +2175,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         }
         std::vector<int> match(nroots, 0);
         std::vector<DavResult> a2(nb);
-        long long sig = 0, sig3 = 0;
+        std::vector<long long> sig(nb, 0), sig3(nb, 0);  // per basis: all its solves, its final-level solve
         {
             const size_t m2 = ws.mark();
             std::vector<Ctx*> c2(nb, nullptr);
@@ -2096,6 +2184,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             for (int b = 0; b < nb; ++b) {
                 c2[b] = build_ctx(ws, eo, e_all + (long long)b * v, Bn[b].Boo, Bn[b].Bov, Bn[b].Bvv, o, vks[b],
                                   Bn[b].X, 2, s, op.precision);
+                c2[b]->graphs = op.sigma_graphs != 0;
                 if (m11Q && m11_pre[b]) {
                     k_copy(c2[b]->m11_Q, m11Q + (long long)b * vv0, (long long)vks[b] * vks[b], s);
                     k_copy(c2[b]->m11_w, m11w + (long long)b * v, vks[b], s);
@@ -2111,12 +2200,10 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
                 j.arena = &ws;
                 jp.push_back(&j);
             }
-            const size_t mj = ws.mark();
-            lockstep_run(jp, s, lockstep_chunk());
-            ws.release(mj);
+            run_jobs(jp);
             for (int b = 0; b < nb; ++b) {
                 a2[b] = jobs[b].res;
-                sig += jobs[b].sigma_builds;
+                sig[b] += jobs[b].sigma_builds;
                 out.all_conv = out.all_conv && a2[b].converged;
             }
             // overlaps of the truncated ADC(2) vectors with the carried canonical ones
@@ -2150,6 +2237,8 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             for (int b = 0; b < nb; ++b) {
                 c3[b] = build_ctx(ws, eo, e_all + (long long)b * v, Bn[b].Boo, Bn[b].Bov, Bn[b].Bvv, o, vks[b],
                                   Bn[b].X, level, s, op.precision, df, smx);
+                c3[b]->mlp_w = op.mlp_weights;
+                c3[b]->graphs = op.sigma_graphs != 0;
                 int mm = 0;
                 for (int k : ks[b]) mm = std::max(mm, match[k]);
                 nr3[b] = g_dry ? nroots : std::min(nroots, mm + 1);
@@ -2162,21 +2251,18 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
                 j.c = c3[b];
                 j.nroots = nr3[b]; j.conv = conv; j.max_iter = op.max_iter; j.max_sub = op.max_subspace;
                 j.pmode = level >= 3 ? pm3 : pm2; j.prec = op.precision;
+                j.mlp = op.precond == 1 && level >= 3;
                 j.guess = Y2k[b]; j.nguess_in = nroots; j.vec_out = X3[b];
                 j.arena = &ws;
                 jp.push_back(&j);
             }
-            {
-                const size_t mj = ws.mark();
-                lockstep_run(jp, s, lockstep_chunk());
-                ws.release(mj);
-            }
+            run_jobs(jp);
             const size_t mx = ws.mark();
             for (int b = 0; b < nb; ++b) {
                 const DavResult& a3 = jobs[b].res;
                 const int vk = vks[b];
-                sig += jobs[b].sigma_builds;
-                sig3 += jobs[b].sigma_builds;
+                sig[b] += jobs[b].sigma_builds;
+                sig3[b] += jobs[b].sigma_builds;
                 out.all_conv = out.all_conv && a3.converged;
                 double* xk = take(ws, o + vk);
                 double* tmp = take(ws, (long long)o * vk * vk);
@@ -2204,13 +2290,15 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             for (int b = 0; b < nb; ++b) delete c3[b];
             ws.release(m3);
         }
-        for (int k = 0; k < nroots; ++k) {
-            out.rep[k].sigma_builds = k == 0 ? (int)sig : 0;
-            out.rep[k].sigma_builds_final = k == 0 ? (int)sig3 : 0;
-        }
+        // counted per basis, on the first root it serves (as one basis at a time does)
+        for (int b = 0; b < nb; ++b)
+            for (size_t j = 0; j < ks[b].size(); ++j) {
+                out.rep[ks[b][j]].sigma_builds = j == 0 ? (int)sig[b] : 0;
+                out.rep[ks[b][j]].sigma_builds_final = j == 0 ? (int)sig3[b] : 0;
+            }
     }
     // step 4 per basis: the roots it serves (root b for a state-specific basis, all for a shared one)
-    for (int b = 0; b < nb && !lock; ++b) {
+    for (int b = 0; b < nb && engine == 0; ++b) {
         const size_t mark = ws.mark();
         GemmScratch gscr(ws, GEMM_SCRATCH);
         std::vector<int> ks;
@@ -2766,7 +2854,7 @@ static adc3_opts resolve_opts(const adc3_opts* opts) {
     if (o.fno_mode != 0 && o.fno_mode != 1) fail(ADC3_EINVAL, "opts.fno_mode must be 0 (state-specific) or 1 (MP2)");
     if (!(o.fno_keep_frac >= 0.0 && o.fno_keep_frac <= 1.0)) fail(ADC3_EINVAL, "opts.fno_keep_frac must lie in [0, 1]");
     if (o.n_guess < 0 || (o.n_guess > 0 && !o.init_guess)) fail(ADC3_EINVAL, "opts.n_guess > 0 needs opts.init_guess");
-    if (o.lockstep < -1 || o.lockstep > 1) fail(ADC3_EINVAL, "opts.lockstep must be -1, 0 or 1");
+    if (o.lockstep < -1 || o.lockstep > 2) fail(ADC3_EINVAL, "opts.lockstep must be -1, 0, 1 or 2");
     return o;
 }
 

@@ -41,7 +41,7 @@ int main() {
     adc3_opts o;
     adc3_default_opts(&o);
     for (const Shape& sh : kShapes)
-        for (int lock = -1; lock < 2; ++lock)
+        for (int lock = -1; lock < 3; ++lock)
             for (int prec = 0; prec < 3; ++prec)
                 for (int mode = 0; mode < 2; ++mode) {
                     adc3_opts p = o;
@@ -75,7 +75,7 @@ int main() {
     for (int t = 0; t < 4; ++t) {
         sets.push_back(ragged(9 + t, t));
         adc3_opts p = o;
-        p.lockstep = t % 2;
+        p.lockstep = t % 3;
         ref.push_back(adc3_ea_solve_batched_workspace_bytes(sets[t].data(), (int)sets[t].size(), &p, 1 + t));
         if (ref[t] == 0) ++bad;
     }
@@ -84,7 +84,7 @@ int main() {
     for (int t = 0; t < 4; ++t)
         th.emplace_back([&, t] {
             adc3_opts p = o;
-            p.lockstep = t % 2;
+            p.lockstep = t % 3;
             for (int rep = 0; rep < 3; ++rep)
                 got[t] = adc3_ea_solve_batched_workspace_bytes(sets[t].data(), (int)sets[t].size(), &p, 1 + t);
         });

@@ -36,13 +36,13 @@ def test_default_opts(lib):
     assert not o.mlp_weights and o.sigma_graphs == 0 and o.ladder == 0
     assert o.sm_x == 1.0 and o.fno_mode == 0 and o.fno_keep_frac == 0.0
     assert not o.init_guess and o.n_guess == 0 and not o.vectors_out
-    assert o.lockstep == -1  # automatic: lockstep for two or more per-root bases, worker threads for batches
+    assert o.lockstep == -1  # automatic: per-root bases on threads of their own when two or more fit
 
 
 def test_option_validation(lib):
     """Out-of-range options are rejected by the workspace query (returns 0) before anything runs."""
     for field, bad in (("sm_x", 1.5), ("sm_x", -0.1), ("fno_mode", 2), ("fno_keep_frac", 1.2), ("n_guess", 3),
-                       ("lockstep", 2), ("lockstep", -2)):
+                       ("lockstep", 3), ("lockstep", -2)):
         o = adc.adc3_default_opts()
         setattr(o, field, bad)
         assert adc.adc3_ea_solve_workspace_bytes(4, 20, 60, 3, o) == 0, field
