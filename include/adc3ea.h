@@ -114,9 +114,10 @@ typedef struct {
                              stream; the host reads the flags once per chunk and sets the next block.
                              Batches: the instances in waves of nstreams.  Jacobi and exact-1p steps only
                              (precond 1 and 2 keep one solve at a time).
-                             2: each solve on a host thread and a stream of its own, with the one-at-a-time
-                             solver (the same iterations and roots as 0, the solves' kernels overlapping).
-                             Batches: worker threads, as 0.
+                             2: each basis's steps (its contexts' setup and its solves, with the
+                             one-at-a-time solver) on a host thread and a stream of its own: the same
+                             iterations and roots as 0, one basis's setup and another's Davidson
+                             overlapping on the GPU.  Batches: worker threads, as 0.
                              0: one solve at a time (batches: worker threads, one per stream).
                              -1 (default): 2 for the per-root bases of one solve when there are two or more
                              and their stored ladders take at most 96 GB together, else 0. */

@@ -1136,7 +1136,6 @@ struct LockJob {
     int nguess_in = 0;
     double* vec_out = nullptr;  // [nroots][N], nullable
     Arena* arena = nullptr;     // where the job's buffers are taken (jobs may share one)
-    bool mlp = false;           // the learned step (the thread engine only; the context holds the weights)
     // state
     hipStream_t s = nullptr;
     long long N = 0;
@@ -1641,82 +1640,6 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
     for (auto* j : jobs) j->s = nullptr;
 }
 
-// The jobs' Davidsons on the one-at-a-time solver, each on a host thread and a stream of its own, in
-// slices of the jobs' arena (sized by a dry run of the solver): the problems' kernels overlap on the GPU,
-// and each problem takes its host decisions at every iteration without waiting for the others.
-static void threads_run(std::vector<LockJob*>& jobs, hipStream_t caller) {
-    const int nj = (int)jobs.size();
-    std::vector<Arena> sub(nj);
-    for (int i = 0; i < nj; ++i) {
-        LockJob& j = *jobs[i];
-        size_t bytes = 0;
-        {
-            const bool was = g_dry;
-            g_dry = true;
-            Arena count;
-            // (the dry run's result, zero roots of the right count, stands for the job's in a planning run)
-            j.res = davidson_impl(j.c, count, j.nroots, j.conv, j.max_iter, j.max_sub, nullptr, nullptr, j.prec, j.mlp,
-                                  nullptr, j.guess, j.nguess_in, j.pmode);
-            g_dry = was;
-            bytes = (count.peak + GEMM_SCRATCH * sizeof(double) + 4096 + 255) / 256 * 256;
-        }
-        sub[i].base = j.arena->take<char>(bytes);
-        sub[i].cap = bytes;
-    }
-    if (g_dry || nj == 0) return;
-    struct Res {
-        std::vector<hipStream_t> st;
-        std::vector<hipEvent_t> ev;
-        hipEvent_t fork = nullptr;
-        ~Res() {
-            for (auto e : ev) (void)hipEventDestroy(e);
-            if (fork) (void)hipEventDestroy(fork);
-            for (auto x : st) (void)hipStreamDestroy(x);
-        }
-    } rs;
-    int dev = 0;
-    HIPCHK(hipGetDevice(&dev));
-    HIPCHK(hipEventCreateWithFlags(&rs.fork, hipEventDisableTiming));
-    HIPCHK(hipEventRecord(rs.fork, caller));
-    for (int i = 0; i < nj; ++i) {
-        hipStream_t x = nullptr;
-        HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-        rs.st.push_back(x);
-        hipEvent_t e = nullptr;
-        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        rs.ev.push_back(e);
-        HIPCHK(hipStreamWaitEvent(x, rs.fork, 0));
-    }
-    std::vector<std::exception_ptr> errs(nj);
-    auto run = [&](int i) {
-        try {
-            HIPCHK(hipSetDevice(dev));
-            LockJob& j = *jobs[i];
-            GemmScratch g(sub[i], GEMM_SCRATCH);
-            const long long before = j.c->sigma_count;
-            j.res = davidson_impl(j.c, sub[i], j.nroots, j.conv, j.max_iter, j.max_sub, j.vec_out, rs.st[i], j.prec,
-                                  j.mlp, nullptr, j.guess, j.nguess_in, j.pmode);
-            j.sigma_builds = j.c->sigma_count - before;
-            j.done = true;
-        } catch (...) {
-            errs[i] = std::current_exception();
-        }
-    };
-    {
-        std::vector<std::thread> th;
-        for (int i = 1; i < nj; ++i) th.emplace_back(run, i);
-        run(0);
-        for (auto& x : th) x.join();
-    }
-    for (int i = 0; i < nj; ++i) {
-        HIPCHK(hipEventRecord(rs.ev[i], rs.st[i]));
-        HIPCHK(hipStreamWaitEvent(caller, rs.ev[i], 0));
-    }
-    HIPCHK(hipStreamSynchronize(caller));
-    for (auto& e : errs)
-        if (e) std::rethrow_exception(e);
-}
-
 // ---------------------------------------------------------------------------
 // SS-FNO / NAF pipeline (Sec. "Computational Details", steps 2-4f)
 // ---------------------------------------------------------------------------
@@ -2113,11 +2036,12 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         }
         ws.release(mm);
     }
-    // step 4, all bases together: their truncated ADC(2) solves, then their ADC(3) solves, either in the
-    // lockstep block Davidson (opts.lockstep 1; not with the learned and Olsen steps) or each on a host
-    // thread and stream of its own (opts.lockstep 2, and the default -1 whenever there are two bases or
-    // more and their stored ladders, at the untruncated size, take at most the stored ladder's budget of
-    // 96 GB together); else one basis after the other.  Planning and the solve take the same decision.
+    // step 4 for all bases: one after the other (engine 0); or each basis's steps on a host thread and
+    // stream of its own (engine 2: opts.lockstep 2, and the default -1 whenever there are two bases or more
+    // and their stored ladders, at the untruncated size, take at most the stored ladder's budget of 96 GB
+    // together); or all bases' truncated ADC(2) solves in one lockstep block Davidson, then all their ADC(3)
+    // solves in another (engine 1: opts.lockstep 1; not with the learned and Olsen steps).  Planning and the
+    // solve take the same decision.
     const bool df_all = op.ladder == 2 || (op.ladder == 0 && ladder_df_auto(v));
     const double lock_ladder_bytes = (double)nb * 4.0 * (double)v * v * v * v;
     const bool together_auto = nb >= 2 && !df_all && lock_ladder_bytes <= 96e9;
@@ -2126,11 +2050,10 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
                                                                                    : 0;
     auto run_jobs = [&](std::vector<LockJob*>& jp) {
         const size_t mj = ws.mark();
-        if (engine == 1) lockstep_run(jp, s, lockstep_chunk());
-        else threads_run(jp, s);
+        lockstep_run(jp, s, lockstep_chunk());
         ws.release(mj);
     };
-    if (engine != 0) {
+    if (engine == 1) {
         GemmScratch gscr(ws, GEMM_SCRATCH);
         std::vector<Blocks> Bn(nb);
         std::vector<int> xks(nb, X);
@@ -2251,7 +2174,6 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
                 j.c = c3[b];
                 j.nroots = nr3[b]; j.conv = conv; j.max_iter = op.max_iter; j.max_sub = op.max_subspace;
                 j.pmode = level >= 3 ? pm3 : pm2; j.prec = op.precision;
-                j.mlp = op.precond == 1 && level >= 3;
                 j.guess = Y2k[b]; j.nguess_in = nroots; j.vec_out = X3[b];
                 j.arena = &ws;
                 jp.push_back(&j);
@@ -2297,10 +2219,12 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
                 out.rep[ks[b][j]].sigma_builds_final = j == 0 ? (int)sig3[b] : 0;
             }
     }
-    // step 4 per basis: the roots it serves (root b for a state-specific basis, all for a shared one)
-    for (int b = 0; b < nb && engine == 0; ++b) {
-        const size_t mark = ws.mark();
-        GemmScratch gscr(ws, GEMM_SCRATCH);
+    // step 4 for one basis once its blocks are formed: the roots it serves (root b for a state-specific
+    // basis, all for a shared one), its truncated ADC(2) and ADC(3) solves and eq 30, its buffers taken from
+    // `ar` and its work issued on `st`.  Returns whether both solves converged.
+    auto run_basis = [&](int b, const Blocks& Bn, int xk, Arena& ar, hipStream_t st) -> bool {
+        bool conv_b = true;
+        GemmScratch gscr(ar, GEMM_SCRATCH);
         std::vector<int> ks;
         if (shared)
             for (int k = 0; k < nroots; ++k) ks.push_back(k);
@@ -2308,14 +2232,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
             ks.push_back(b);
         const double* U = U_all + (long long)b * vv0;
         const double* enew = e_all + (long long)b * v;
-        const int vk = vks[b];                                        // 4c-4d
-        if (vk < 1) fail(ADC3_EINVAL, "SS-FNO threshold removes every virtual orbital");
-        Blocks Bt;
-        transform_blocks(B0, U, vk, Bt, ws, s);
-        Blocks Bn = Bt;
-        int xk = X;
-        if (naf > 0) xk = naf_blocks(Bt, naf, Bn, ws, s, vk == v ? &naf_cache : nullptr);  // 4e
-        VLOG("basis %d: kept %d virtuals, %d auxiliary functions", b, vk, xk);
+        const int vk = vks[b];
         const long long Nk = vk + (long long)o * vk * vk;
         if (nroots > Nk) fail(ADC3_EINVAL, "truncated space smaller than nroots");
         int sig = 0, sig3 = 0;
@@ -2323,44 +2240,44 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         // the canonical ADC(2) vectors carried into the truncated basis (r1 U, U^T z_i U): vector k is
         // the reference for root matching, all of them start the truncated ADC(2) solve, whose vectors
         // in turn start the truncated ADC(3) solve
-        double* carried = take(ws, (long long)nroots * Nk);
-        double* Y2k = take(ws, (long long)nroots * Nk);
+        double* carried = take(ar, (long long)nroots * Nk);
+        double* Y2k = take(ar, (long long)nroots * Nk);
         {
-            const size_t mt = ws.mark();
-            double* tmp = take(ws, (long long)o * v * vk);
+            const size_t mt = ar.mark();
+            double* tmp = take(ar, (long long)o * v * vk);
             for (int q = 0; q < nroots; ++q) {
                 const double* yq = Y2 + (long long)q * N0;
                 double* cq = carried + (long long)q * Nk;
-                gemm_rm(1, vk, v, 1.0, yq, v, false, U, vk, false, 0.0, cq, vk, s);
-                gemm_rm(o * v, vk, v, 1.0, yq + v, v, false, U, vk, false, 0.0, tmp, vk, s);
+                gemm_rm(1, vk, v, 1.0, yq, v, false, U, vk, false, 0.0, cq, vk, st);
+                gemm_rm(o * v, vk, v, 1.0, yq + v, v, false, U, vk, false, 0.0, tmp, vk, st);
                 Gemm g;
                 g.M = vk; g.N = vk; g.K = v;
                 g.A = U; g.sAm = 1; g.sAk = vk;
                 g.B = tmp; g.sBk = vk; g.sBn = 1; g.bB0 = (long long)v * vk;
                 g.C = cq + vk; g.sCm = vk; g.sCn = 1; g.bC0 = (long long)vk * vk;
                 g.nb0 = o;
-                gemm(g, s);
+                gemm(g, st);
             }
-            ws.release(mt);
+            ar.release(mt);
         }
         DavResult a2;
         {
-            double* ovl = take(ws, (long long)nroots * nroots);
-            double* part = take(ws, (long long)dots_partial_elems(nroots, nroots, Nk));
-            const size_t m2 = ws.mark();
-            Ctx* c2 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, s, op.precision);
+            double* ovl = take(ar, (long long)nroots * nroots);
+            double* part = take(ar, (long long)dots_partial_elems(nroots, nroots, Nk));
+            const size_t m2 = ar.mark();
+            Ctx* c2 = build_ctx(ar, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, 2, st, op.precision);
             c2->graphs = op.sigma_graphs != 0;
             if (m11Q && m11_pre[b]) {
-                k_copy(c2->m11_Q, m11Q + (long long)b * vv0, (long long)vk * vk, s);
-                k_copy(c2->m11_w, m11w + (long long)b * v, vk, s);
+                k_copy(c2->m11_Q, m11Q + (long long)b * vv0, (long long)vk * vk, st);
+                k_copy(c2->m11_w, m11w + (long long)b * v, vk, st);
                 c2->m11_eig = true;
             }
-            a2 = davidson_impl(c2, ws, nroots, conv, op.max_iter, op.max_subspace, Y2k, s, op.precision, false,
+            a2 = davidson_impl(c2, ar, nroots, conv, op.max_iter, op.max_subspace, Y2k, st, op.precision, false,
                                nullptr, carried, nroots, pm2);
             // overlaps of the truncated ADC(2) vectors with every carried canonical vector: ovl[k][q]
-            k_dots(carried, Nk, nroots, Y2k, Nk, nroots, Nk, ovl, nroots, part, s);
+            k_dots(carried, Nk, nroots, Y2k, Nk, nroots, Nk, ovl, nroots, part, st);
             std::vector<double> hov((size_t)nroots * nroots);
-            d2h(hov.data(), ovl, hov.size() * sizeof(double), s);
+            d2h(hov.data(), ovl, hov.size() * sizeof(double), st);
             for (int k : ks) {
                 match[k] = k;
                 if (!g_dry) {
@@ -2373,36 +2290,36 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
                 VLOG("root %d: truncated ADC(2) %d iterations, matched root %d (overlap %.4f)", k, a2.iters,
                      match[k], std::fabs(hov[(size_t)k * nroots + match[k]]));
             }
-            out.all_conv = out.all_conv && a2.converged;
+            conv_b = conv_b && a2.converged;
             sig += (int)c2->sigma_count;
             delete c2;
-            ws.release(m2);
+            ar.release(m2);
         }
         {
-            const size_t m3 = ws.mark();
-            Ctx* c3 = build_ctx(ws, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, s, op.precision, df, smx);
+            const size_t m3 = ar.mark();
+            Ctx* c3 = build_ctx(ar, eo, enew, Bn.Boo, Bn.Bov, Bn.Bvv, o, vk, Bn.X, level, st, op.precision, df, smx);
             c3->mlp_w = op.mlp_weights;
             c3->graphs = op.sigma_graphs != 0;
             // only the roots up to the highest matched one of this basis are needed
             int mmax = 0;
             for (int k : ks) mmax = std::max(mmax, match[k]);
             const int nr3 = std::min(nroots, mmax + 1);
-            double* X3 = take(ws, (long long)nr3 * Nk);
-            DavResult a3 = davidson_impl(c3, ws, nr3, conv, op.max_iter, op.max_subspace, X3, s, op.precision,
+            double* X3 = take(ar, (long long)nr3 * Nk);
+            DavResult a3 = davidson_impl(c3, ar, nr3, conv, op.max_iter, op.max_subspace, X3, st, op.precision,
                                          op.precond == 1, nullptr, Y2k, nroots, level >= 3 ? pm3 : pm2);
             {
                 // spectral amplitudes of the matched roots in this basis, virtual part carried back to the
                 // canonical virtuals through U (x_p = sum_a U[p][a] x~_a)
-                const size_t mx = ws.mark();
-                double* xk = take(ws, o + vk);
-                double* tmp = take(ws, (long long)o * vk * vk);
+                const size_t mx = ar.mark();
+                double* xk = take(ar, o + vk);
+                double* tmp = take(ar, (long long)o * vk * vk);
                 for (int k : ks) {
                     double* xo = xd + (long long)k * (o + v);
-                    spectral_amplitudes(c3, X3 + (long long)match[k] * Nk, xk, tmp, s);
-                    k_copy(xo, xk, o, s);
-                    gemm_rm(1, v, vk, 1.0, xk + o, vk, false, U, vk, true, 0.0, xo + o, v, s);
+                    spectral_amplitudes(c3, X3 + (long long)match[k] * Nk, xk, tmp, st);
+                    k_copy(xo, xk, o, st);
+                    gemm_rm(1, v, vk, 1.0, xk + o, vk, false, U, vk, true, 0.0, xo + o, v, st);
                 }
-                ws.release(mx);
+                ar.release(mx);
             }
             for (int k : ks) {
                 auto& R = out.rep[k];
@@ -2420,17 +2337,108 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
                 // each of the three eigenvalues lies within its residual norm of an eigenvalue of its matrix
                 R.err_bound = a3.rn[m] + (op.fno_correction ? r2.rn[k] + a2.rn[m] : 0.0);
             }
-            out.all_conv = out.all_conv && a3.converged;
+            conv_b = conv_b && a3.converged;
             sig += (int)c3->sigma_count;
             sig3 = (int)c3->sigma_count;
             delete c3;
-            ws.release(m3);
+            ar.release(m3);
         }
         for (size_t j = 0; j < ks.size(); ++j) {
             out.rep[ks[j]].sigma_builds = j == 0 ? sig : 0;
             out.rep[ks[j]].sigma_builds_final = j == 0 ? sig3 : 0;
         }
-        ws.release(mark);
+        return conv_b;
+    };
+    // 4c-4e for basis b: its blocks in the kept natural orbitals, then the NAF truncation (the NAF
+    // eigensolver's result is shared by the bases that keep every virtual)
+    auto prep_basis = [&](int b, Blocks& Bn) -> int {
+        const int vk = vks[b];
+        if (vk < 1) fail(ADC3_EINVAL, "SS-FNO threshold removes every virtual orbital");
+        GemmScratch gscr(ws, GEMM_SCRATCH);
+        Blocks Bt;
+        transform_blocks(B0, U_all + (long long)b * vv0, vk, Bt, ws, s);
+        Bn = Bt;
+        int xk = X;
+        if (naf > 0) xk = naf_blocks(Bt, naf, Bn, ws, s, vk == v ? &naf_cache : nullptr);
+        VLOG("basis %d: kept %d virtuals, %d auxiliary functions", b, vk, xk);
+        return xk;
+    };
+    if (engine == 0) {
+        for (int b = 0; b < nb; ++b) {
+            const size_t mark = ws.mark();
+            Blocks Bn;
+            const int xk = prep_basis(b, Bn);
+            const bool cb = run_basis(b, Bn, xk, ws, s);
+            out.all_conv = out.all_conv && cb;
+            ws.release(mark);
+        }
+    } else if (engine == 2) {
+        // every basis's blocks first, on the caller's stream; then each basis's solves on a host thread and a
+        // stream of its own, in a slice of the workspace sized by a dry run of the same steps, so that one
+        // basis's context setup overlaps the other bases' Davidsons
+        std::vector<Blocks> Bn(nb);
+        std::vector<int> xks(nb, X);
+        for (int b = 0; b < nb; ++b) xks[b] = prep_basis(b, Bn[b]);
+        std::vector<Arena> sub(nb);
+        for (int b = 0; b < nb; ++b) {
+            const bool was = g_dry;
+            g_dry = true;
+            Arena count;
+            run_basis(b, Bn[b], xks[b], count, nullptr);
+            g_dry = was;
+            const size_t bytes = (count.peak + 4096 + 255) / 256 * 256;
+            sub[b].base = ws.take<char>(bytes);
+            sub[b].cap = bytes;
+        }
+        if (!g_dry) {
+            struct Res {
+                std::vector<hipStream_t> st;
+                std::vector<hipEvent_t> ev;
+                hipEvent_t fork = nullptr;
+                ~Res() {
+                    for (auto e : ev) (void)hipEventDestroy(e);
+                    if (fork) (void)hipEventDestroy(fork);
+                    for (auto x : st) (void)hipStreamDestroy(x);
+                }
+            } rs;
+            int dev = 0;
+            HIPCHK(hipGetDevice(&dev));
+            HIPCHK(hipEventCreateWithFlags(&rs.fork, hipEventDisableTiming));
+            HIPCHK(hipEventRecord(rs.fork, s));
+            for (int b = 0; b < nb; ++b) {
+                hipStream_t x = nullptr;
+                HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+                rs.st.push_back(x);
+                hipEvent_t e = nullptr;
+                HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+                rs.ev.push_back(e);
+                HIPCHK(hipStreamWaitEvent(x, rs.fork, 0));
+            }
+            std::vector<char> cb(nb, 1);
+            std::vector<std::exception_ptr> errs(nb);
+            auto run = [&](int b) {
+                try {
+                    HIPCHK(hipSetDevice(dev));
+                    cb[b] = run_basis(b, Bn[b], xks[b], sub[b], rs.st[b]) ? 1 : 0;
+                } catch (...) {
+                    errs[b] = std::current_exception();
+                }
+            };
+            {
+                std::vector<std::thread> th;
+                for (int b = 1; b < nb; ++b) th.emplace_back(run, b);
+                run(0);
+                for (auto& x : th) x.join();
+            }
+            for (int b = 0; b < nb; ++b) {
+                HIPCHK(hipEventRecord(rs.ev[b], rs.st[b]));
+                HIPCHK(hipStreamWaitEvent(s, rs.ev[b], 0));
+            }
+            HIPCHK(hipStreamSynchronize(s));
+            for (auto& e : errs)
+                if (e) std::rethrow_exception(e);
+            for (int b = 0; b < nb; ++b) out.all_conv = out.all_conv && cb[b];
+        }
     }
     out.rep[0].sigma_builds += sig0;
     if (!g_dry) finish_amplitudes(xd, nroots, o + v, out.rep, op.dyson_out, s);
