@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 mixed-precision solves")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner study")
+    ap.add_argument("--no-large-form", action="store_true",
+                    help="skip the large workload's form: its assembled ladder at full shape in FP64 / FP32 / BF16, "
+                         "and a scaled-down instance solved in the three precisions against the oracle's golden")
     ap.add_argument("--learned-full", action="store_true",
                     help="also compare the learned preconditioner with Jacobi at o=30 v=400 X=1200 (251 GB)")
     ap.add_argument("--batched", type=int, default=64,
@@ -399,6 +402,47 @@ def large_mixed_study(adc, d, torch, np, scale, precs=(0, 1, 2), ref=None):
     for tag in ("fp32", "bf16"):
         if tag in out and "fp64" in out:
             out[tag]["speedup_vs_fp64"] = out["fp64"]["davidson_s"] / out[tag]["davidson_s"]
+    return out
+
+
+def large_workload_form(adc, d, torch, np):
+    """The large mixed-precision workload's path, within the default run's time: (1) its dominant sigma term,
+    the ladder assembled from the DF factor, at the full shape (v = 600, X = 1800, 200 rows) in FP64, FP32 and
+    BF16 operands (one untimed and one timed call each); (2) a scaled-down instance of the same form (o=16,
+    v=160, X=480, seed 2, B x 0.05, 5 canonical roots, the ladder assembled in every application) solved
+    with FP64, FP32 and BF16 sigma (reduced phases ending with the FP64 restart), each after one untimed
+    solve, against the FP64 oracle's stored roots (conv 1e-9)."""
+    import synth
+    out = {"ladder_full_shape": dfladder_only(adc, torch, 1)}
+    g = oracle_golden("large-like-o16v160x480_s0.05")
+    eo, ev, B = synth.make_instance(g["nocc"], g["nvir"], g["naux"], g["seed"], scale=g["scale"])
+    teo, tev, tB = d(eo), d(ev), d(B)
+    inst = {"nocc": g["nocc"], "nvir": g["nvir"], "naux": g["naux"], "seed": g["seed"], "scale": g["scale"],
+            "nroots": 5, "conv": 1e-7, "ladder": "assembled"}
+    ref = None
+    for prec, tag in ((0, "fp64"), (1, "fp32"), (2, "bf16")):
+        o = adc.adc3_default_opts()
+        o.ladder, o.precision = 2, prec
+        ws = torch.empty(adc.adc3_ea_solve_workspace_bytes(g["nocc"], g["nvir"], g["naux"], 5, o),
+                         dtype=torch.uint8, device="cuda")
+        adc.adc3_ea_solve(teo, tev, tB, 5, 0.0, 0.0, 1e-7, o, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        roots, reps, st = adc.adc3_ea_solve(teo, tev, tB, 5, 0.0, 0.0, 1e-7, o, workspace=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        inst[tag] = {"time_to_roots_s": dt, "status": st, "iterations": reps[0]["iters"],
+                     "iterations_reduced_precision": reps[0]["iters_lowp"] if prec else 0,
+                     "max_abs_root_diff_vs_oracle_Eh": vs_oracle(np, roots, g),
+                     "max_err_bound_Eh": float(max(r["err_bound"] for r in reps))}
+        if ref is None:
+            ref = dt
+        else:
+            inst[tag]["speedup_vs_fp64"] = ref / dt
+        print("large workload form: scaled instance %s %.3f s" % (tag, dt), file=sys.stderr, flush=True)
+        del ws
+        torch.cuda.empty_cache()
+    out["scaled_instance"] = inst
     return out
 
 
@@ -764,6 +808,14 @@ def main():
                                     ((0, "threads_cold_tuner"), (1, "lockstep"), (0, "threads")))
         except Exception as e:
             batched = {"error": str(e)}
+    large_form = None
+    if not a.no_large_form:
+        ws = None
+        torch.cuda.empty_cache()
+        try:
+            large_form = large_workload_form(adc, d, torch, np)
+        except Exception as e:
+            large_form = {"error": str(e)}
     large = None
     if a.large_mixed > 0:
         ws = None
@@ -841,6 +893,8 @@ def main():
         line["learned_full_size"] = learned_full
     if batched is not None:
         line["batched"] = batched
+    if large_form is not None:
+        line["large_workload_form"] = large_form
     if large is not None:
         line["large_mixed_precision"] = large
     if not a.no_cpu_baseline:
