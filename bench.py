@@ -583,6 +583,12 @@ def main():
                      dtype=torch.uint8, device="cuda")
     run = lambda: adc.adc3_ea_solve(teo, tev, tB, nroots, p["fno_thresh"], p["naf_thresh"], p["conv"],  # noqa: E731
                                     opts, workspace=ws)
+    # the ladder tuner settles its shapes in a first, untimed solve with the bases one after another, so that
+    # its trial launches are timed without the other bases' kernels running beside them
+    ot = adc.adc3_default_opts()
+    ot.lockstep = 0
+    adc.adc3_ea_solve(teo, tev, tB, nroots, p["fno_thresh"], p["naf_thresh"], p["conv"], ot, workspace=ws)
+    print("tuner settled (one basis at a time, untimed)", file=sys.stderr, flush=True)
     for w in range(a.warmup):
         roots, reps, st = run()
         print("warmup %d done: roots %s status %d" % (w, np.array2string(roots, precision=8), st),
@@ -642,8 +648,10 @@ def main():
                 wsm = torch.empty(adc.adc3_ea_solve_workspace_bytes(p["nocc"], p["nvir"], p["naux"], nroots, om),
                                   dtype=torch.uint8, device="cuda")
                 # one untimed solve first, as for the FP64 steps: the ladder tuner times its candidates
-                # on the first call of each shape
+                # on the first call of each shape, with the bases one after another
+                om.lockstep = 0
                 adc.adc3_ea_solve(teo, tev, tB, nroots, p["fno_thresh"], p["naf_thresh"], p["conv"], om, workspace=wsm)
+                om.lockstep = -1
                 torch.cuda.synchronize()
                 adc.adc3_profile_enable(True)
                 m0 = time.perf_counter()

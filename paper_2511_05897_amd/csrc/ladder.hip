@@ -782,8 +782,11 @@ void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long l
 // ---------------------------------------------------------------------------
 // Autotuner for the chunk count.  The best split depends on M (rows per tile), the
 // column count and the chip's load balance, so it is measured: on the first call for a
-// (rows, N, K) shape each candidate runs twice after a warm-up, timed with HIP events on
-// the caller's stream, and the fastest is kept for the process.  ADC3_TUNE_CACHE names a
+// (rows, N, K) shape each candidate (chunk count, and row tiling where that matters) runs once
+// untimed, then in three interleaved rounds timed launch by launch with HIP events on the
+// caller's stream; the candidate with the fastest single launch is kept for the process.  One
+// shape is measured at a time, other threads that reach it wait for the result, and taking each
+// candidate's best round keeps other streams' kernels from deciding it.  ADC3_TUNE_CACHE names a
 // text file that keeps the choices across processes (one line per shape and device
 // architecture); ADC3_LADDER_CHUNKS fixes the count and disables tuning.  Different
 // chunk counts sum in a different order, so the last bits of sigma can differ between
@@ -877,6 +880,7 @@ bool ladder_gemm_t32(int M, int N, int K, double alpha, const float* Zt, long lo
 
 namespace {
 std::mutex g_tune_mu;
+std::mutex g_tune_run_mu;  // held while a shape's trial launches run: one shape measured at a time
 std::map<std::string, int> g_tune;
 bool g_tune_loaded = false;
 
@@ -973,6 +977,14 @@ int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long 
     }
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone) return def;
+    // one shape measured at a time: host threads that reach the same shape together (the bases of a solve,
+    // the instances of a batch) wait for the first one's result instead of timing it again
+    std::unique_lock<std::mutex> run_lk(g_tune_run_mu);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return it->second;
+    }
     // prec 3 is the FP64 kernel with Z k-major, whose chunks have a minimum count
     const int nmin = prec == 3 ? ladder_t_min_chunks(K, ldz, ldg) : prec == 4 ? ladder_t32_min_chunks(K, ldz, ldg) : 1;
     std::vector<int> cand;
@@ -993,27 +1005,41 @@ int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long 
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
+    // every (row tiling, chunk count) once untimed, then three rounds over all of them, each launch timed on
+    // its own; a candidate's fastest round counts (kernels of other streams running beside a trial only
+    // ever add time, and interleaving spreads them over the candidates)
+    std::vector<std::pair<int, int>> trials;
+    for (int mt : rows)
+        for (int c : cand) trials.emplace_back(mt, c);
+    std::vector<float> tbest(trials.size(), 1e30f);
     int best = cand[0], best_rows = mt0;
-    float best_ms = 1e30f;
     try {
-        for (int mt : rows) {
-            t_trial_rows = mt;
-            for (int c : cand) {
-                ladder_run(prec, M, N, K, Z, ldz, G, ldg, C, ldc, c, partial, partial_elems, s);  // warm-up
+        for (const auto& t : trials) {
+            t_trial_rows = t.first;
+            ladder_run(prec, M, N, K, Z, ldz, G, ldg, C, ldc, t.second, partial, partial_elems, s);
+        }
+        for (int round = 0; round < 3; ++round)
+            for (size_t i = 0; i < trials.size(); ++i) {
+                t_trial_rows = trials[i].first;
                 HIPCHK(hipEventRecord(e0, s));
-                for (int rep = 0; rep < 2; ++rep)
-                    ladder_run(prec, M, N, K, Z, ldz, G, ldg, C, ldc, c, partial, partial_elems, s);
+                ladder_run(prec, M, N, K, Z, ldz, G, ldg, C, ldc, trials[i].second, partial, partial_elems, s);
                 HIPCHK(hipEventRecord(e1, s));
                 HIPCHK(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best_ms) { best_ms = ms; best = c; best_rows = mt; }
+                tbest[i] = std::min(tbest[i], ms);
             }
-        }
     } catch (...) {
         t_trial_rows = 0;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         throw;
     }
+    size_t ib = 0;
+    for (size_t i = 1; i < trials.size(); ++i)
+        if (tbest[i] < tbest[ib]) ib = i;
+    best_rows = trials[ib].first;
+    best = trials[ib].second;
     t_trial_rows = 0;
     HIPCHK(hipEventDestroy(e0));
     HIPCHK(hipEventDestroy(e1));
