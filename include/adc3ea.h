@@ -281,7 +281,9 @@ int adc3_ladder_apply_static(const double* Bvv_dev, const double* Z_dev, double*
 
 /* Symmetric eigensolver of the natural-orbital and natural-auxiliary-function steps (Sec.
  * "Frozen Natural Orbitals", eq 9 and the recanonicalisation of eqs 12-13; Sec. "Natural
- * Auxiliary Functions", eq 28): FP64 cyclic Jacobi.  A_dev[n][n] device, row-major, read only
+ * Auxiliary Functions", eq 28): FP64 cyclic Jacobi (n > 96: over blocks of 32 rows, each round's
+ * block-pair sub-matrices diagonalised in LDS and their orthogonal factors applied to A and V).
+ * A_dev[n][n] device, row-major, read only
  * (its symmetric part (A + A^T)/2 is diagonalised); w_dev[n] receives the eigenvalues in
  * ascending order, V_dev[n][n] the eigenvectors as columns (V[i][k] = component i of vector k),
  * each with its largest-magnitude component positive (first index on ties).  The workspace holds
@@ -295,8 +297,8 @@ int adc3_eigh(const double* A_dev, double* w_dev, double* V_dev, int n, void* wo
 /* The same eigensolver for nb independent matrices of one order n, as the solve uses it for the
  * natural orbitals and their recanonicalisation of all roots at once: A_dev[nb][n][n] device
  * (read only), w_dev[nb][n] (ascending per matrix), V_dev[nb][n][n] (columns, sign convention as
- * adc3_eigh).  Each matrix stops at its own convergence; the rounds of all matrices share one
- * launch.  Workspace: adc3_eigh_batched_workspace_bytes(n, nb).  1 <= n <= 4096,
+ * adc3_eigh).  Each matrix stops at its own convergence; the rounds of all matrices share their
+ * launches.  Workspace: adc3_eigh_batched_workspace_bytes(n, nb).  1 <= n <= 4096,
  * 1 <= nb <= 65535.  Synchronises the stream; ADC3_ENUMERIC if any matrix is non-finite. */
 size_t adc3_eigh_batched_workspace_bytes(int n, int nb);
 int adc3_eigh_batched(const double* A_dev, double* w_dev, double* V_dev, int n, int nb, void* workspace_dev,

@@ -1597,7 +1597,10 @@ static void lockstep_run(std::vector<LockJob*>& jobs_in, hipStream_t caller, int
         set_block(i);
     };
     std::atomic<bool> stop{false};
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
     auto run = [&](int i) {
+        HIPCHK(hipSetDevice(dev));  // the caller's device in every thread
         while (!jobs[i]->done && !stop.load()) advance(i);
     };
     std::vector<int> act;
@@ -3049,6 +3052,8 @@ static void batched_lockstep(const adc3_instance* inst, int ninst, const adc3_op
     }
     const std::vector<hipStream_t>& sls = slr.st;
     const std::vector<hipEvent_t>& sev = slr.ev;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
     for (size_t w = 0; w < nwave; ++w) {
         // the slots' streams start after everything on the caller's stream: the inputs, and the previous
         // wave's work on the same workspace slices
@@ -3065,6 +3070,10 @@ static void batched_lockstep(const adc3_instance* inst, int ninst, const adc3_op
         // of its own, so that the wave's setups overlap (an instance that truncates runs its whole pipeline
         // there); the wave's Davidsons then start together, ordered after every setup
         auto prepare = [&](int sl) {
+            if (hipSetDevice(dev) != hipSuccess) {
+                errs[sl] = std::make_exception_ptr(Error{ADC3_EHIP, "hipSetDevice failed in a slot thread"});
+                return;
+            }
             const int i = slot[sl][w];
             const adc3_instance& in = inst[i];
             hipStream_t ss = sls[sl];

@@ -269,11 +269,11 @@ void k_lincomb(double* Y, long long ldy, int nq, const double* X, long long ldx,
 // symmetric eigensolvers (Jacobi, FP64)
 // ---------------------------------------------------------------------------
 // A[n][n] (destroyed) -> w[n] ascending, V[n][n] columns eigenvectors (row-major V[i*n+k])
-void eig_small(double* A, int n, double* w, double* V, hipStream_t s);   // n <= 128, one workgroup
+void eig_small(double* A, int n, double* w, double* V, hipStream_t s);   // n <= 96, one workgroup
 void eig_large(double* A, int n, double* w, double* V, double* scratch, hipStream_t s);
 size_t eig_large_scratch(int n);
 // nb independent matrices of order n, contiguous A[nb][n][n] (destroyed), w[nb][n], V[nb][n][n] (unsorted, as
-// eig_large): one launch per round for the whole batch, each matrix stopping at its own convergence
+// eig_large): the launches of each round serve the whole batch, each matrix stopping at its own convergence
 void eig_batched(double* A, int n, int nb, double* w, double* V, double* scratch, hipStream_t s);
 size_t eig_batched_scratch(int n, int nb);
 // reorder eigenpairs descending (desc=1) or ascending and fix signs (largest |.| positive)

@@ -1,9 +1,12 @@
 // Symmetric eigensolvers in FP64: cyclic two-sided Jacobi with the round-robin
 // ("circle method") ordering, so that every round rotates n/2 disjoint index pairs
-// in parallel.  Used for the Rayleigh-Ritz subspace matrix (small, one workgroup,
-// LDS resident), the natural-orbital and recanonicalisation matrices and the
-// natural-auxiliary-function matrix (large, one launch per round, two buffers of A).
+// in parallel.  Order n <= 96 (the Rayleigh-Ritz subspace matrix): one workgroup, A and V in
+// LDS.  Larger orders (the natural-orbital, recanonicalisation, exact-1p-block and
+// natural-auxiliary-function matrices, one or a batch): the same ordering over blocks of 32
+// rows, each round diagonalising the block pairs' sub-matrices in LDS and applying their
+// orthogonal factors to A and V, two launches per round of block pairs.
 #include "internal.h"
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -31,25 +34,18 @@ __device__ inline void rot_of(double app, double aqq, double apq, double& c, dou
 constexpr int SMALL_MAX = 96;
 constexpr int SNT = 1024;
 
-__global__ __launch_bounds__(SNT) void jacobi_small_kernel(double* Ag, int n, double* w, double* Vg) {
-    extern __shared__ double sm[];
-    const int ld = n + 1;
-    double* A = sm;
-    double* V = sm + (size_t)n * ld;
+// Cyclic Jacobi on an n x n symmetric matrix held in LDS (row stride ld), one workgroup of SNT threads:
+// sweeps of n - 1 (n even) rounds of n/2 disjoint rotations, until the off-diagonal squared norm is at most
+// 1e-30 of the total (or max_sweeps).  V (same layout) accumulates the rotations on its columns.
+__device__ void jacobi_lds(double* A, double* V, int n, int ld, int max_sweeps) {
     __shared__ double cs[SMALL_MAX / 2 + 1], sn[SMALL_MAX / 2 + 1];
     __shared__ int pp[SMALL_MAX / 2 + 1], qq[SMALL_MAX / 2 + 1];
     __shared__ double red[SNT / 64];
     __shared__ double red2[SNT / 64];
     const int tid = threadIdx.x;
-    for (int t = tid; t < n * n; t += SNT) {
-        int i = t / n, j = t % n;
-        A[i * ld + j] = Ag[t];
-        V[i * ld + j] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
     const int np = n + (n & 1);
     const int npair = np / 2;
-    for (int sweep = 0; sweep < 60; ++sweep) {
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
         double off = 0.0, tot = 0.0;
         for (int t = tid; t < n * n; t += SNT) {
             int i = t / n, j = t % n;
@@ -122,123 +118,26 @@ __global__ __launch_bounds__(SNT) void jacobi_small_kernel(double* Ag, int n, do
             __syncthreads();
         }
     }
+}
+
+__global__ __launch_bounds__(SNT) void jacobi_small_kernel(double* Ag, int n, double* w, double* Vg) {
+    extern __shared__ double sm[];
+    const int ld = n + 1;
+    double* A = sm;
+    double* V = sm + (size_t)n * ld;
+    const int tid = threadIdx.x;
+    for (int t = tid; t < n * n; t += SNT) {
+        int i = t / n, j = t % n;
+        A[i * ld + j] = Ag[t];
+        V[i * ld + j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    jacobi_lds(A, V, n, ld, 60);
     for (int t = tid; t < n * n; t += SNT) {
         int i = t / n, j = t % n;
         Vg[t] = V[i * ld + j];
     }
     for (int i = tid; i < n; i += SNT) w[i] = A[i * ld + i];
-}
-
-// ---------------- large: global memory, one launch per round ----------------
-// One round in one launch: every workgroup forms all the round's rotations from Ain (which no
-// workgroup writes in this round) in LDS, then applies its share of the block updates into Aout.
-// Every element of A belongs to exactly one (row pair, column pair) block, so Aout is written in full;
-// V is updated in place (each (row, pair) element by one thread).
-__global__ void jacobi_round_kernel(const double* Ain, double* Aout, double* V, int n, int np, int r) {
-    extern __shared__ double csh[];  // [2 * npair]
-    const int npair = np / 2;
-    for (int k = threadIdx.x; k < npair; k += blockDim.x) {
-        int p, q;
-        pair_of(r, k, np, p, q);
-        double c = 1.0, s = 0.0;
-        if (q < n) rot_of(Ain[(long long)p * n + p], Ain[(long long)q * n + q], Ain[(long long)p * n + q], c, s);
-        csh[2 * k] = c;
-        csh[2 * k + 1] = s;
-    }
-    __syncthreads();
-    long long nblk = (long long)npair * npair;
-    long long nv = (long long)n * npair;
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nblk + nv;
-         t += (long long)gridDim.x * blockDim.x) {
-        if (t < nblk) {
-            int k1 = (int)(t / npair), k2 = (int)(t % npair);
-            int p1, q1, p2, q2;
-            pair_of(r, k1, np, p1, q1);
-            pair_of(r, k2, np, p2, q2);
-            double c1 = csh[2 * k1], s1 = csh[2 * k1 + 1], c2 = csh[2 * k2], s2 = csh[2 * k2 + 1];
-            bool v1 = q1 < n, v2 = q2 < n;
-            double a = Ain[(long long)p1 * n + p2];
-            double b = v2 ? Ain[(long long)p1 * n + q2] : 0.0;
-            double c = v1 ? Ain[(long long)q1 * n + p2] : 0.0;
-            double d = (v1 && v2) ? Ain[(long long)q1 * n + q2] : 0.0;
-            double ra = c1 * a - s1 * c, rb = c1 * b - s1 * d;
-            double rc = s1 * a + c1 * c, rd = s1 * b + c1 * d;
-            double na = c2 * ra - s2 * rb, nb = s2 * ra + c2 * rb;
-            double nc = c2 * rc - s2 * rd, nd = s2 * rc + c2 * rd;
-            Aout[(long long)p1 * n + p2] = na;
-            if (v2) Aout[(long long)p1 * n + q2] = nb;
-            if (v1) Aout[(long long)q1 * n + p2] = nc;
-            if (v1 && v2) Aout[(long long)q1 * n + q2] = nd;
-        } else {
-            long long u = t - nblk;
-            int k = (int)(u / n), i = (int)(u % n);
-            int p, q;
-            pair_of(r, k, np, p, q);
-            if (q >= n) continue;
-            double c = csh[2 * k], s = csh[2 * k + 1];
-            double vip = V[(long long)i * n + p], viq = V[(long long)i * n + q];
-            V[(long long)i * n + p] = c * vip - s * viq;
-            V[(long long)i * n + q] = s * vip + c * viq;
-        }
-    }
-}
-
-// Batched round: blockIdx.y picks the matrix (order n, contiguous [nb][n][n] buffers); matrices whose
-// flag is 0 (converged) are left as they are.
-__global__ void jacobi_round_batched_kernel(const double* Ain, double* Aout, double* Vb, int n, int np, int r,
-                                            const int* active) {
-    const int bm = blockIdx.y;
-    if (!active[bm]) return;
-    const long long nn = (long long)n * n;
-    const double* Ai = Ain + bm * nn;
-    double* Ao = Aout + bm * nn;
-    double* V = Vb + bm * nn;
-    extern __shared__ double csh[];  // [2 * npair]
-    const int npair = np / 2;
-    for (int k = threadIdx.x; k < npair; k += blockDim.x) {
-        int p, q;
-        pair_of(r, k, np, p, q);
-        double c = 1.0, s = 0.0;
-        if (q < n) rot_of(Ai[(long long)p * n + p], Ai[(long long)q * n + q], Ai[(long long)p * n + q], c, s);
-        csh[2 * k] = c;
-        csh[2 * k + 1] = s;
-    }
-    __syncthreads();
-    long long nblk = (long long)npair * npair;
-    long long nv = (long long)n * npair;
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nblk + nv;
-         t += (long long)gridDim.x * blockDim.x) {
-        if (t < nblk) {
-            int k1 = (int)(t / npair), k2 = (int)(t % npair);
-            int p1, q1, p2, q2;
-            pair_of(r, k1, np, p1, q1);
-            pair_of(r, k2, np, p2, q2);
-            double c1 = csh[2 * k1], s1 = csh[2 * k1 + 1], c2 = csh[2 * k2], s2 = csh[2 * k2 + 1];
-            bool v1 = q1 < n, v2 = q2 < n;
-            double a = Ai[(long long)p1 * n + p2];
-            double b = v2 ? Ai[(long long)p1 * n + q2] : 0.0;
-            double c = v1 ? Ai[(long long)q1 * n + p2] : 0.0;
-            double d = (v1 && v2) ? Ai[(long long)q1 * n + q2] : 0.0;
-            double ra = c1 * a - s1 * c, rb = c1 * b - s1 * d;
-            double rc = s1 * a + c1 * c, rd = s1 * b + c1 * d;
-            double na = c2 * ra - s2 * rb, nb = s2 * ra + c2 * rb;
-            double nc = c2 * rc - s2 * rd, nd = s2 * rc + c2 * rd;
-            Ao[(long long)p1 * n + p2] = na;
-            if (v2) Ao[(long long)p1 * n + q2] = nb;
-            if (v1) Ao[(long long)q1 * n + p2] = nc;
-            if (v1 && v2) Ao[(long long)q1 * n + q2] = nd;
-        } else {
-            long long u = t - nblk;
-            int k = (int)(u / n), i = (int)(u % n);
-            int p, q;
-            pair_of(r, k, np, p, q);
-            if (q >= n) continue;
-            double c = csh[2 * k], s = csh[2 * k + 1];
-            double vip = V[(long long)i * n + p], viq = V[(long long)i * n + q];
-            V[(long long)i * n + p] = c * vip - s * viq;
-            V[(long long)i * n + q] = s * vip + c * viq;
-        }
-    }
 }
 
 // Per matrix of the batch (one workgroup each): off-diagonal and total squared norms into nrm[2b..2b+1];
@@ -278,38 +177,10 @@ __global__ void diag_out_batched_kernel(const double* A, const double* A2, const
     w[(long long)bm * n + i] = Ab[(long long)i * n + i];
 }
 
-__global__ void offnorm_kernel(const double* A, int n, double* out) {
-    __shared__ double r1[16], r2[16];
-    double off = 0.0, tot = 0.0;
-    long long nn = (long long)n * n;
-    for (long long t = threadIdx.x; t < nn; t += blockDim.x) {
-        double a = A[t];
-        tot += a * a;
-        if (t / n != t % n) off += a * a;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        off += __shfl_down(off, o, 64);
-        tot += __shfl_down(tot, o, 64);
-    }
-    if ((threadIdx.x & 63) == 0) { r1[threadIdx.x >> 6] = off; r2[threadIdx.x >> 6] = tot; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double a = 0, b = 0;
-        for (int k = 0; k < (int)(blockDim.x >> 6); ++k) { a += r1[k]; b += r2[k]; }
-        out[0] = a;
-        out[1] = b;
-    }
-}
-
 __global__ void eye_kernel(double* V, int n) {
     long long nn = (long long)n * n;
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < nn; t += (long long)gridDim.x * blockDim.x)
         V[t] = (t / n == t % n) ? 1.0 : 0.0;
-}
-
-__global__ void diag_out_kernel(const double* A, int n, double* w) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) w[i] = A[(long long)i * n + i];
 }
 
 // ascending (desc=0) or descending (desc=1) order; ties by index; sign: largest |.| of
@@ -337,6 +208,146 @@ __global__ void sort_eig_kernel(double* w, double* V, int n, int desc, double* w
     for (int i = threadIdx.x; i < n; i += blockDim.x) w[i] = wtmp[i];
     for (long long t = threadIdx.x; t < (long long)n * n; t += blockDim.x) V[t] = Vtmp[t];
 }
+
+// ---------------- large: block Jacobi, two launches per round of block pairs ----------------
+// The matrix is cut into blocks of BJ rows (the last one shorter).  Every round pairs the blocks in the
+// same round-robin order as the scalar rounds (with a bye when their count is odd); bj_solve_kernel
+// diagonalises, for each pair, the symmetric sub-matrix on the pair's rows and columns (at most BSUB)
+// in LDS with the one-workgroup Jacobi, and writes its orthogonal factor Q_k; bj_apply_kernel then applies
+// every pair's factor at once, A <- P^T A P and V <- V P with P block-diagonal over the pairs' index sets,
+// each tile (pair p's rows, pair q's columns) of A, and each BSUB-row slab of V's pair-q columns, by one
+// workgroup.  Every element of A lies in exactly one tile, so A is updated in place.
+constexpr int BJ = 32, BSUB = 2 * BJ, BL = BSUB + 1;
+// Jacobi sweeps per sub-problem and round: the outer sweeps converge the whole matrix either way, and two
+// inner sweeps measured fastest (1, 2 and full inner convergence compared at n = 200 and 600, random and
+// density-like spectra, and in the SS-FNO solve)
+constexpr int BJ_INNER = 2;
+
+// the pair k of round r: first block's first row b0 and size m0, second block's b1 and m1 (m1 = 0 for the bye)
+__device__ inline void bj_pair(int r, int k, int npb, int nblk, int n, int& b0, int& m0, int& b1, int& m1) {
+    int I, J;
+    pair_of(r, k, npb, I, J);
+    b0 = I * BJ;
+    m0 = min(BJ, n - b0);
+    if (J < nblk) {
+        b1 = J * BJ;
+        m1 = min(BJ, n - b1);
+    } else {
+        b1 = 0;
+        m1 = 0;
+    }
+}
+__device__ inline int bj_row(int t, int b0, int m0, int b1) { return t < m0 ? b0 + t : b1 + (t - m0); }
+
+// grid (npb / 2, batch); Q [batch][npb / 2][BSUB][BSUB]
+__global__ __launch_bounds__(SNT) void bj_solve_kernel(const double* A, double* Q, int n, int nblk, int npb, int r,
+                                                       int sweeps, const int* active) {
+    const int bm = blockIdx.y;
+    if (active && !active[bm]) return;
+    const double* Ab = A + (long long)bm * n * n;
+    double* Qb = Q + ((long long)bm * (npb / 2) + blockIdx.x) * BSUB * BSUB;
+    int b0, m0, b1, m1;
+    bj_pair(r, blockIdx.x, npb, nblk, n, b0, m0, b1, m1);
+    const int ms = m0 + m1, ld = ms + 1;
+    extern __shared__ double sm[];
+    double* As = sm;
+    double* Vs = sm + (size_t)ms * ld;
+    for (int t = threadIdx.x; t < ms * ms; t += SNT) {
+        const int i = t / ms, j = t - (t / ms) * ms;
+        const long long gi = bj_row(i, b0, m0, b1), gj = bj_row(j, b0, m0, b1);
+        As[i * ld + j] = 0.5 * (Ab[gi * n + gj] + Ab[gj * n + gi]);
+        Vs[i * ld + j] = i == j ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    jacobi_lds(As, Vs, ms, ld, sweeps);
+    // one Newton-Schulz step, Q = V (3 I - V^T V) / 2, takes the factor's departure from orthogonality (the
+    // rounding of its many rotations) from e to about e^2, so that it does not add up over the rounds
+    // applied to the eigenvectors; G = V^T V goes where the sub-matrix was
+    double* G = As;
+    for (int t = threadIdx.x; t < ms * ms; t += SNT) {
+        const int i = t / ms, j = t - (t / ms) * ms;
+        double acc = 0.0;
+        for (int k = 0; k < ms; ++k) acc += Vs[k * ld + i] * Vs[k * ld + j];
+        G[i * ld + j] = acc;
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < ms * ms; t += SNT) {
+        const int i = t / ms, j = t - (t / ms) * ms;
+        double acc = 0.0;
+        for (int k = 0; k < ms; ++k) acc += Vs[i * ld + k] * G[k * ld + j];
+        Qb[i * BSUB + j] = 1.5 * Vs[i * ld + j] - 0.5 * acc;
+    }
+}
+
+// grid (npb / 2, npb / 2 + ceil(n / BSUB), batch): y < npb / 2 the A tile (pair y's rows, pair x's columns),
+// otherwise the V slab of rows BSUB (y - npb / 2) .. on pair x's columns
+__global__ __launch_bounds__(256) void bj_apply_kernel(double* A, double* V, const double* Q, int n, int nblk, int npb,
+                                                       int r, const int* active) {
+    const int bm = blockIdx.z;
+    if (active && !active[bm]) return;
+    const int npair = npb / 2;
+    const long long nn = (long long)n * n;
+    double* Ab = A + bm * nn;
+    double* Vb = V + bm * nn;
+    const double* Qb = Q + (long long)bm * npair * BSUB * BSUB;
+    extern __shared__ double sm[];
+    double* Qc = sm;               // column pair's factor [mc][BL]
+    double* X = sm + BSUB * BL;    // the tile or slab [rows][BL]
+    double* T = sm + 2 * BSUB * BL;
+    double* Qr = sm + 3 * BSUB * BL;
+    int c0, cm0, c1, cm1;
+    bj_pair(r, blockIdx.x, npb, nblk, n, c0, cm0, c1, cm1);
+    const int mc = cm0 + cm1;
+    const double* Qcg = Qb + (long long)blockIdx.x * BSUB * BSUB;
+    for (int t = threadIdx.x; t < mc * mc; t += 256) {
+        const int i = t / mc, j = t - (t / mc) * mc;
+        Qc[i * BL + j] = Qcg[i * BSUB + j];
+    }
+    if ((int)blockIdx.y < npair) {
+        int r0, rm0, r1, rm1;
+        bj_pair(r, blockIdx.y, npb, nblk, n, r0, rm0, r1, rm1);
+        const int mr = rm0 + rm1;
+        const double* Qrg = Qb + (long long)blockIdx.y * BSUB * BSUB;
+        for (int t = threadIdx.x; t < mr * mr; t += 256) {
+            const int i = t / mr, j = t - (t / mr) * mr;
+            Qr[i * BL + j] = Qrg[i * BSUB + j];
+        }
+        for (int t = threadIdx.x; t < mr * mc; t += 256) {
+            const int i = t / mc, j = t - (t / mc) * mc;
+            X[i * BL + j] = Ab[(long long)bj_row(i, r0, rm0, r1) * n + bj_row(j, c0, cm0, c1)];
+        }
+        __syncthreads();
+        // T = Qr^T X
+        for (int t = threadIdx.x; t < mr * mc; t += 256) {
+            const int i = t / mc, j = t - (t / mc) * mc;
+            double acc = 0.0;
+            for (int k = 0; k < mr; ++k) acc += Qr[k * BL + i] * X[k * BL + j];
+            T[i * BL + j] = acc;
+        }
+        __syncthreads();
+        // A tile = T Qc
+        for (int t = threadIdx.x; t < mr * mc; t += 256) {
+            const int i = t / mc, j = t - (t / mc) * mc;
+            double acc = 0.0;
+            for (int k = 0; k < mc; ++k) acc += T[i * BL + k] * Qc[k * BL + j];
+            Ab[(long long)bj_row(i, r0, rm0, r1) * n + bj_row(j, c0, cm0, c1)] = acc;
+        }
+    } else {
+        const int row0 = ((int)blockIdx.y - npair) * BSUB;
+        const int mr = min(BSUB, n - row0);
+        for (int t = threadIdx.x; t < mr * mc; t += 256) {
+            const int i = t / mc, j = t - (t / mc) * mc;
+            X[i * BL + j] = Vb[(long long)(row0 + i) * n + bj_row(j, c0, cm0, c1)];
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < mr * mc; t += 256) {
+            const int i = t / mc, j = t - (t / mc) * mc;
+            double acc = 0.0;
+            for (int k = 0; k < mc; ++k) acc += X[i * BL + k] * Qc[k * BL + j];
+            Vb[(long long)(row0 + i) * n + bj_row(j, c0, cm0, c1)] = acc;
+        }
+    }
+}
 }  // namespace
 
 void eig_small(double* A, int n, double* w, double* V, hipStream_t s) {
@@ -355,74 +366,43 @@ void eig_small(double* A, int n, double* w, double* V, hipStream_t s) {
     LAUNCHCHK();
 }
 
-// second copy of A (rounds alternate between the two) + norms
-size_t eig_large_scratch(int n) { return (size_t)n * n + 8; }
 
-void eig_large(double* A, int n, double* w, double* V, double* scratch, hipStream_t s) {
-    if (g_dry) return;
-    ProfScope prof(PROF_EIG, s, 0.0, 0.0);
-    if (n <= 0) return;
-    if (n <= SMALL_MAX) { eig_small(A, n, w, V, s); return; }
-    const int np = n + (n & 1);
-    double* A2 = scratch;                  // n*n doubles: the other buffer of the rounds
-    double* nrm = scratch + (long long)n * n;  // 2 doubles
-    hipLaunchKernelGGL(eye_kernel, dim3(256), dim3(256), 0, s, V, n);
-    LAUNCHCHK();
-    long long work = (long long)(np / 2) * (np / 2) + (long long)n * (np / 2);
-    unsigned gb = (unsigned)std::min<long long>((work + 255) / 256, 4096);
-    const size_t lds = (size_t)np * sizeof(double);  // 2 * (np/2) rotation coefficients
-    if (lds > 64 * 1024) fail(-1, "eig_large: n too large");
-    double* cur = A;
-    double* nxt = A2;
-    double hn[2];
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        hipLaunchKernelGGL(offnorm_kernel, dim3(1), dim3(1024), 0, s, cur, n, nrm);
-        LAUNCHCHK();
-        HIPCHK(hipMemcpyAsync(hn, nrm, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        if (!std::isfinite(hn[0]) || !std::isfinite(hn[1])) fail(-4, "eigensolver: non-finite matrix");
-        if (hn[0] <= 1e-30 * hn[1] || hn[0] == 0.0) break;
-        for (int r = 0; r < np - 1; ++r) {
-            hipLaunchKernelGGL(jacobi_round_kernel, dim3(gb), dim3(256), lds, s, cur, nxt, V, n, np, r);
-            std::swap(cur, nxt);
-        }
-        LAUNCHCHK();
-    }
-    hipLaunchKernelGGL(diag_out_kernel, dim3((n + 255) / 256), dim3(256), 0, s, cur, n, w);
-    LAUNCHCHK();
+namespace {
+// doubles of scratch the block solver takes for nb matrices of order n: the pairs' factors, norms, flags
+size_t block_scratch(int n, int nb) {
+    const long long nblk = (n + BJ - 1) / BJ, npair = (nblk + (nblk & 1)) / 2;
+    return (size_t)nb * npair * BSUB * BSUB + 4 * (size_t)nb + 8;
 }
 
-// second copies of the nb matrices, norms, flags
-size_t eig_batched_scratch(int n, int nb) { return (size_t)nb * n * n + 4 * (size_t)nb + 8; }
-
-void eig_batched(double* A, int n, int nb, double* w, double* V, double* scratch, hipStream_t s) {
-    if (g_dry) return;
-    ProfScope prof(PROF_EIG, s, 0.0, 0.0);
-    if (n <= 0 || nb <= 0) return;
+// nb symmetric matrices of order n > SMALL_MAX, [nb][n][n]: eigenvalues w [nb][n] (unsorted) and
+// eigenvectors V [nb][n][n] (columns), A overwritten; each matrix stops at its own convergence.
+void eig_block(double* A, int n, int nb, double* w, double* V, double* scratch, hipStream_t s) {
+    static const bool attr_set = [] {
+        HIPCHK(hipFuncSetAttribute((const void*)bj_solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(2 * BSUB * BL * sizeof(double))));
+        HIPCHK(hipFuncSetAttribute((const void*)bj_apply_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(4 * BSUB * BL * sizeof(double))));
+        return true;
+    }();
+    (void)attr_set;
     const long long nn = (long long)n * n;
-    if (n <= SMALL_MAX || nb == 1) {
-        for (int b = 0; b < nb; ++b) eig_large(A + b * nn, n, w + (long long)b * n, V + b * nn, scratch, s);
-        return;
-    }
-    const int np = n + (n & 1);
-    double* A2 = scratch;
-    double* nrm = scratch + nb * nn;                 // [nb][2]
-    int* active = (int*)(nrm + 2 * (long long)nb);   // [nb]
-    int* src = active + nb;                           // [nb]
-    std::vector<int> hact(nb, 1), hsrc(nb, 0);
+    const int nblk = (n + BJ - 1) / BJ, npb = nblk + (nblk & 1), npair = npb / 2;
+    double* Q = scratch;
+    double* nrm = Q + (long long)nb * npair * BSUB * BSUB;  // [nb][2]
+    int* active = (int*)(nrm + 2 * (long long)nb);           // [nb]
+    int* src = active + nb;                                  // [nb], zeros: the matrices stay in A
+    std::vector<int> hact(nb, 1), hzero(nb, 0);
     std::vector<double> hn(2 * (size_t)nb);
     HIPCHK(hipMemcpyAsync(active, hact.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(src, hzero.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
     for (int b = 0; b < nb; ++b) {
         hipLaunchKernelGGL(eye_kernel, dim3(256), dim3(256), 0, s, V + b * nn, n);
         LAUNCHCHK();
     }
-    long long work = (long long)(np / 2) * (np / 2) + (long long)n * (np / 2);
-    unsigned gb = (unsigned)std::min<long long>((work + 255) / 256, 4096);
-    const size_t lds = (size_t)np * sizeof(double);
-    if (lds > 64 * 1024) fail(-1, "eig_batched: n too large");
-    int parity = 0;  // 0: current matrices in A, 1: in A2
+    const dim3 gs(npair, nb), ga(npair, npair + (n + BSUB - 1) / BSUB, nb);
+    const size_t lds_s = 2 * (size_t)BSUB * BL * sizeof(double), lds_a = 4 * (size_t)BSUB * BL * sizeof(double);
     for (int sweep = 0; sweep < 60; ++sweep) {
-        hipLaunchKernelGGL(offnorm_batched_kernel, dim3(nb), dim3(1024), 0, s, parity ? A2 : A, n, nrm, active);
+        hipLaunchKernelGGL(offnorm_batched_kernel, dim3(nb), dim3(1024), 0, s, A, n, nrm, active);
         LAUNCHCHK();
         std::vector<int> now(nb);
         HIPCHK(hipMemcpyAsync(now.data(), active, nb * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -430,28 +410,48 @@ void eig_batched(double* A, int n, int nb, double* w, double* V, double* scratch
         HIPCHK(hipStreamSynchronize(s));
         int left = 0;
         for (int b = 0; b < nb; ++b) {
-            if (hact[b] && !now[b]) {
-                if (!std::isfinite(hn[2 * b]) || !std::isfinite(hn[2 * b + 1]))
-                    fail(-4, "eigensolver: non-finite matrix");
-                hsrc[b] = parity;  // converged here: its matrix stays in the current buffer
-            }
+            if (hact[b] && !now[b] && (!std::isfinite(hn[2 * b]) || !std::isfinite(hn[2 * b + 1])))
+                fail(-4, "eigensolver: non-finite matrix");
             hact[b] = now[b];
             left += now[b];
         }
         if (left == 0) break;
-        for (int r = 0; r < np - 1; ++r) {
-            hipLaunchKernelGGL(jacobi_round_batched_kernel, dim3(gb, nb), dim3(256), lds, s, parity ? A2 : A,
-                               parity ? A : A2, V, n, np, r, active);
-            parity ^= 1;
+        for (int r = 0; r < npb - 1; ++r) {
+            hipLaunchKernelGGL(bj_solve_kernel, gs, dim3(SNT), lds_s, s, A, Q, n, nblk, npb, r, BJ_INNER, active);
+            hipLaunchKernelGGL(bj_apply_kernel, ga, dim3(256), lds_a, s, A, V, Q, n, nblk, npb, r, active);
         }
         LAUNCHCHK();
     }
-    for (int b = 0; b < nb; ++b)
-        if (hact[b]) hsrc[b] = parity;  // not converged within the sweep limit: the last buffer
-    HIPCHK(hipMemcpyAsync(src, hsrc.data(), nb * sizeof(int), hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(diag_out_batched_kernel, dim3((n + 255) / 256, nb), dim3(256), 0, s, A, A2, src, n, w);
+    hipLaunchKernelGGL(diag_out_batched_kernel, dim3((n + 255) / 256, nb), dim3(256), 0, s, A, A, src, n, w);
     LAUNCHCHK();
     HIPCHK(hipStreamSynchronize(s));  // the host arrays of the copies above go out of scope here
+}
+}  // namespace
+
+// the block solver's factors, norms and flags
+size_t eig_large_scratch(int n) { return std::max((size_t)n * n + 8, block_scratch(n, 1)); }
+
+void eig_large(double* A, int n, double* w, double* V, double* scratch, hipStream_t s) {
+    if (g_dry) return;
+    ProfScope prof(PROF_EIG, s, 0.0, 0.0);
+    if (n <= 0) return;
+    if (n <= SMALL_MAX) { eig_small(A, n, w, V, s); return; }
+    eig_block(A, n, 1, w, V, scratch, s);
+}
+
+// the block solver's factors, norms and flags of the nb matrices
+size_t eig_batched_scratch(int n, int nb) { return std::max((size_t)nb * n * n + 4 * (size_t)nb + 8, block_scratch(n, nb)); }
+
+void eig_batched(double* A, int n, int nb, double* w, double* V, double* scratch, hipStream_t s) {
+    if (g_dry) return;
+    ProfScope prof(PROF_EIG, s, 0.0, 0.0);
+    if (n <= 0 || nb <= 0) return;
+    const long long nn = (long long)n * n;
+    if (n <= SMALL_MAX) {
+        for (int b = 0; b < nb; ++b) eig_small(A + b * nn, n, w + (long long)b * n, V + b * nn, s);
+        return;
+    }
+    eig_block(A, n, nb, w, V, scratch, s);
 }
 
 void k_sort_eig(double* w, double* V, int n, int desc, double* wtmp, double* Vtmp, hipStream_t s) {

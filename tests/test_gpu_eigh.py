@@ -1,6 +1,7 @@
 """The FP64 symmetric eigensolver of the natural-orbital and NAF steps (adc3_eigh) against
 numpy.linalg.eigh, at sizes that take each of its two forms: n <= 96 (one workgroup, A and V in
-LDS) and n > 96 (one launch per round, two buffers of A).  Spectra: random symmetric matrices, and
+LDS) and n > 96 (block Jacobi over 32-row blocks: even and odd block counts, a short last block, and
+n = 600, the natural-auxiliary-function order of the benchmark workload).  Spectra: random symmetric matrices, and
 density-matrix-like ones
 (Q diag(lambda) Q^T with lambda spread over 1 .. 1e-12, the occupation spectrum of eq 9).
 
@@ -16,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_2511_05897_amd as adc  # noqa: E402
 
-SIZES = [1, 2, 7, 96, 97, 150, 200, 333]
+SIZES = [1, 2, 7, 96, 97, 150, 200, 333, 600]
 
 
 def sign_fix(V):
