@@ -86,8 +86,9 @@ def test_lockstep_literal_workload_matches_golden():
                                         opts=_opts())
     assert st == adc.ADC3_OK
     assert [r["naux_kept"] for r in reps] == gold["naux_kept"]
-    tol = np.maximum(1e-8, 1e-11 * np.abs(np.array(gold["roots"])))
-    assert np.all(np.abs(roots - np.array(gold["roots"])) < tol + 2e-6)
+    # the bar of the one-at-a-time parity test (FP64 rounding at |omega| = 2.7e6)
+    tol = np.maximum(1e-8, 2e-13 * np.abs(np.array(gold["roots"])))
+    assert np.all(np.abs(roots - np.array(gold["roots"])) <= tol)
 
 
 def _ragged(n, seed0, scale):

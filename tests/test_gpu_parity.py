@@ -168,9 +168,10 @@ def test_solve_weak_correlation_full_size_fp64():
 def test_solve_literal_full_size_fp64():
     """Workload o=20, v=200, X=600, seed 1, literal scale, SS-FNO 10^-4.5, NAF 1e-2, 5 roots, conv 1e-6 (the
     benchmark's configuration): roots, uncorrected roots and kept sizes vs the stored FP64 oracle pipeline
-    (its Davidson also to 1e-6).  Both sides stop at residual norm 1e-6, so the roots agree to about that;
-    the bar is max(1e-8, 1e-11 |omega|) Eh, 2.7e-5 Eh at |omega| = 2.7e6, where the FP64 residual floor
-    of either side is about 1e-7."""
+    (its Davidson also to 1e-6).  Both sides stop at residual norm 1e-6, where the eigenvalue error is
+    about |r|^2 / gap, far below rounding; what is left is the FP64 rounding of the two pipelines at
+    |omega| = 2.7e6 (matrix elements up to ~1e6, sums over v^2 terms), measured at 5e-14 relative.  The
+    bar is max(1e-8, 2e-13 |omega|) Eh, 5.4e-7 Eh here."""
     import json
     import os
     gold = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
@@ -180,7 +181,8 @@ def test_solve_literal_full_size_fp64():
     assert st == adc.ADC3_OK
     assert [r["nvir_kept"] for r in reps] == gold["nvir_kept"]
     assert [r["naux_kept"] for r in reps] == gold["naux_kept"]
-    tol = np.maximum(1e-8, 1e-11 * np.abs(np.array(gold["roots"])))
+    tol = np.maximum(1e-8, 2e-13 * np.abs(np.array(gold["roots"])))
+    print("root differences vs the oracle", roots - np.array(gold["roots"]))
     assert np.all(np.abs(roots - np.array(gold["roots"])) <= tol)
     unc = np.array([r["omega_uncorr"] for r in reps])
     assert np.all(np.abs(unc - np.array(gold["omega_uncorr"])) <= tol)
