@@ -1926,6 +1926,7 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         }
         {
             const size_t mx = ws.mark();
+            GemmScratch gscr(ws, GEMM_SCRATCH);  // the amplitudes' long-K products split K across the chip
             double* xd = take(ws, (long long)nroots * (o + v));
             double* tmp = take(ws, (long long)o * v * v);
             for (int k = 0; k < nroots; ++k)
@@ -3064,6 +3065,7 @@ static void batched_lockstep(const adc3_instance* inst, int ninst, const adc3_op
         std::vector<Ctx*> ctx(nw, nullptr);
         std::vector<LockJob> jobs(nw);
         std::vector<double*> vecs(nw, nullptr);
+        std::vector<size_t> jmark(nw, 0);  // each slot's arena before the lockstep buffers
         std::vector<int> who(nw, -1);
         std::vector<LockJob*> jp;
         // each slot's instance is checked and its context built on the slot's own stream by a host thread
@@ -3107,6 +3109,7 @@ static void batched_lockstep(const adc3_instance* inst, int ninst, const adc3_op
                 ctx[sl] = build_ctx(ar[sl], in.eps_occ, in.eps_vir, B0.Boo, B0.Bov, B0.Bvv, in.nocc, in.nvir, in.naux,
                                     op.level, ss, op.precision, df, op.level >= 3 ? op.sm_x : 1.0);
                 vecs[sl] = take(ar[sl], (long long)in.nroots * N);
+                jmark[sl] = ar[sl].mark();
                 LockJob& j = jobs[sl];
                 j.c = ctx[sl];
                 j.nroots = in.nroots; j.conv = in.conv; j.max_iter = op.max_iter; j.max_sub = op.max_subspace;
@@ -3151,6 +3154,8 @@ static void batched_lockstep(const adc3_instance* inst, int ninst, const adc3_op
                     const DavResult& r = jobs[sl].res;
                     std::vector<adc3_root_report> rep(in.nroots, adc3_root_report{});
                     const int o = in.nocc, v = in.nvir;
+                    ar[sl].release(jmark[sl]);  // the Davidson's buffers (its vectors are in vecs)
+                    GemmScratch gscr(ar[sl], GEMM_SCRATCH);
                     double* xd = take(ar[sl], (long long)in.nroots * (o + v));
                     double* tmp = take(ar[sl], (long long)o * v * v);
                     for (int k = 0; k < in.nroots; ++k) {
