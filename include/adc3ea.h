@@ -344,6 +344,12 @@ int adc3_ea_spectral_amplitudes(adc3_ctx* ctx, const double* vecs_dev, int nvec,
  * NaN into one new sigma vector, once; that solve then returns ADC3_ENUMERIC.  0 disarms. */
 void adc3_debug_inject_nan(int iteration);
 
+/* Test hook of the multi-chunk paths of the k-major ladder kernel (the sigma ladder's minimum K-chunk
+ * count, and large setup contractions run as consecutive K ranges): lowers the byte limit of one
+ * chunk's operand span, 2^31 - 1 (32-bit offsets), to `bytes` (> 0) for every later call in the process;
+ * 0 restores it.  Results are the same up to summation order. */
+void adc3_debug_ladder_offset_limit(long long bytes);
+
 /* Test hook: dense M (N <= 20000) into M_dev[N][ldm] device. */
 int adc3_ea_dense_matrix(adc3_ctx* ctx, double* M_dev, int ldm, hipStream_t stream);
 

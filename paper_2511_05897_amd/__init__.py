@@ -28,7 +28,8 @@ EXPORTS = ["adc3_default_opts", "adc3_last_error", "adc3_ea_solve_workspace_byte
            "adc3_ea_setup_workspace_bytes_ex", "adc3_ea_setup_ex", "adc3_set_chunk_elems",
            "adc3_ladder_workspace_bytes", "adc3_ladder_apply", "adc3_eigh_workspace_bytes", "adc3_eigh",
            "adc3_eigh_batched_workspace_bytes", "adc3_eigh_batched", "adc3_ladder_apply_static",
-           "adc3_ea_davidson_guess", "adc3_ea_setup_sm", "adc3_debug_inject_nan", "adc3_ea_spectral_amplitudes"]
+           "adc3_ea_davidson_guess", "adc3_ea_setup_sm", "adc3_debug_inject_nan", "adc3_ea_spectral_amplitudes",
+           "adc3_debug_ladder_offset_limit"]
 
 # size of the static device scratch of adc3_ladder_apply_static (ADC3_STATIC_SCRATCH_BYTES)
 STATIC_SCRATCH_BYTES = 256 << 20
@@ -128,6 +129,8 @@ def load():
     lib.adc3_ea_spectral_amplitudes.restype = I
     lib.adc3_debug_inject_nan.argtypes = [I]
     lib.adc3_debug_inject_nan.restype = None
+    lib.adc3_debug_ladder_offset_limit.argtypes = [ctypes.c_longlong]
+    lib.adc3_debug_ladder_offset_limit.restype = None
     lib.adc3_ea_dense_matrix.argtypes = [P, P, I, P]
     lib.adc3_ea_dense_matrix.restype = I
     lib.adc3_ea_intermediate.argtypes = [P, I, P, ctypes.POINTER(LL), P]
@@ -469,6 +472,11 @@ adc3_ea_setup = Context
 def adc3_debug_inject_nan(iteration):
     """Arm the error-path hook: the next Davidson iteration >= iteration writes NaN into one sigma vector."""
     load().adc3_debug_inject_nan(int(iteration))
+
+
+def adc3_debug_ladder_offset_limit(nbytes):
+    """Test hook: byte limit of one k-major ladder chunk's operand span (0 restores 2^31 - 1)."""
+    load().adc3_debug_ladder_offset_limit(int(nbytes))
 
 
 def adc3_mlp_nparams():

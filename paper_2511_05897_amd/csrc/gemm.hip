@@ -252,9 +252,31 @@ static void gemm_impl(const Gemm& g, hipStream_t s, int tag, int kmin_split) {
     // large single GEMMs with A k-major and B, C row-major: the ladder kernel that copies both tiles
     // straight into LDS, when K fits one of its chunks
     if (sh == SH_128x128 && nb == 1 && g.sAm == 1 && g.sBn == 1 && g.sCn == 1 &&
-        ladder_t_supported(g.M, g.N, g.K, g.A, g.sAk, g.B, g.sBk) && ladder_t_min_chunks(g.K, g.sAk, g.sBk) == 1 &&
-        ladder_gemm_t(g.M, g.N, g.K, g.alpha, g.A, g.sAk, g.B, g.sBk, g.beta, g.C, g.sCm, 1, nullptr, 0, s, 2))
-        return;
+        ladder_t_supported(g.M, g.N, g.K, g.A, g.sAk, g.B, g.sBk)) {
+        const int nmin = ladder_t_min_chunks(g.K, g.sAk, g.sBk);
+        if (nmin == 1 &&
+            ladder_gemm_t(g.M, g.N, g.K, g.alpha, g.A, g.sAk, g.B, g.sBk, g.beta, g.C, g.sCm, 1, nullptr, 0, s, 2))
+            return;
+        if (nmin > 1) {
+            // K past the kernel's 32-bit offsets in one launch: consecutive K ranges of one chunk each (a
+            // multiple of 64 rows), accumulated into C in order
+            const long long kc = ((g.K + nmin - 1) / nmin + 63) / 64 * 64;
+            bool ok = true;
+            for (long long k0 = 0; k0 < g.K && ok; k0 += kc) {
+                const int kk = (int)std::min<long long>(kc, g.K - k0);
+                ok = ladder_t_supported(g.M, g.N, kk, g.A + k0 * g.sAk, g.sAk, g.B + k0 * g.sBk, g.sBk) &&
+                     ladder_t_min_chunks(kk, g.sAk, g.sBk) == 1;
+            }
+            if (ok) {
+                for (long long k0 = 0; k0 < g.K; k0 += kc) {
+                    const int kk = (int)std::min<long long>(kc, g.K - k0);
+                    ladder_gemm_t(g.M, g.N, kk, g.alpha, g.A + k0 * g.sAk, g.sAk, g.B + k0 * g.sBk, g.sBk,
+                                  k0 == 0 ? g.beta : 1.0, g.C, g.sCm, 1, nullptr, 0, s, 2);
+                }
+                return;
+            }
+        }
+    }
     // large single GEMMs with both operands contiguous along their tile rows: the ladder kernel's
     // tile (whole-M row blocks, 2 workgroups per CU, 16-byte loads) without splitting K
     if (sh == SH_128x128 && nb == 1 && g.sAk == 1 && g.sBn == 1 && g.sCn == 1 &&

@@ -28,6 +28,7 @@
 // accumulator element r holds D[l/16 + 4r][l%16].
 #include "internal.h"
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -795,10 +796,16 @@ void ladder_gemm(int M, int N, int K, double alpha, const double* Z, long long l
 // Chunks of the k-major kernel are addressed with 32-bit byte offsets: the smallest chunk count
 // whose chunks (a multiple of 64 rows each) stay below 2^31 bytes in both operands, or 0 when
 // not even 64 rows fit.
+// (adc3_debug_ladder_offset_limit lowers the byte limit for tests of the multi-chunk paths)
+static std::atomic<long long> g_offset_limit{0};
+static long long offset_limit() {
+    const long long l = g_offset_limit.load();
+    return l > 0 ? l : (1LL << 31) - 1;
+}
 int ladder_t_min_chunks(int K, long long ldz, long long ldg) {
     const long long ld = std::max(ldz, ldg);
     if (K <= 0 || ld <= 0) return 0;
-    const long long kcmax = ((1LL << 31) - 1) / (8 * ld) / 64 * 64;
+    const long long kcmax = offset_limit() / (8 * ld) / 64 * 64;
     if (kcmax < 64) return 0;
     int n = (int)std::max<long long>(1, (K + kcmax - 1) / kcmax);
     while (ladder_chunk_len(K, n) > kcmax) ++n;
@@ -1054,3 +1061,5 @@ int ladder_tuned_chunks(int prec, int M, int N, int K, const void* Z, long long 
 }
 
 }  // namespace adc3
+
+extern "C" void adc3_debug_ladder_offset_limit(long long bytes) { adc3::g_offset_limit.store(bytes > 0 ? bytes : 0); }

@@ -90,11 +90,12 @@ void ein2(Arena& ws, const char* spec, double alpha, const double* A, const int*
     if (M > 2147483647LL || N > 2147483647LL || K > 2147483647LL) fail(-1, "ein2: dimension too large");
     // A large contraction gets row-major B and output and a contiguous A (a permute of each is cheap
     // next to the GEMM), so that it runs on the ladder tiles: A k-major ([K..,M..], both tiles copied
-    // straight into LDS) when the whole product is one chunk of that kernel, else row-major
+    // straight into LDS; K in consecutive ranges when one launch's 32-bit offsets cannot span it), else
+    // row-major
     const bool big = 2.0 * (double)M * (double)N * (double)K >= 4e9;
-    const bool kmajor = big && M >= 128 && N >= 128 && ((M + 127) / 128) * ((N + 127) / 128) >= 512 && N % 2 == 0 &&
-                        ladder_t_min_chunks((int)K, M + (M & 1), N) == 1 &&
-                        (p.b != Kl + Nl || ((uintptr_t)B & 15) == 0);
+    const long long ldn = N + (N & 1);  // B's row stride on the k-major path: even, for 16-byte rows
+    const bool kmajor = big && M >= 128 && N >= 128 && ((M + 127) / 128) * ((N + 127) / 128) >= 512 &&
+                        ladder_t_min_chunks((int)K, M + (M & 1), ldn) >= 1;
     // A
     if (kmajor) {
         if (p.a == Kl + Ml && M % 2 == 0) { g.A = A; g.sAm = 1; g.sAk = M; }
@@ -118,7 +119,18 @@ void ein2(Arena& ws, const char* spec, double alpha, const double* A, const int*
         g.A = t; g.sAm = K; g.sAk = 1;
     }
     // B
-    if (p.b == Kl + Nl) { g.B = B; g.sBk = N; g.sBn = 1; }
+    if (kmajor && !(p.b == Kl + Nl && ldn == N && ((uintptr_t)B & 15) == 0)) {
+        // [K][N] with an even row stride
+        double* t = ws.take<double>(K * ldn);
+        if (ldn == N) {
+            permute_any(t, B, p.b, bdims, Kl + Nl, 1.0, 0.0, s);
+        } else {
+            double* u = ws.take<double>(K * N);
+            permute_any(u, B, p.b, bdims, Kl + Nl, 1.0, 0.0, s);
+            k_copy2d(t, ldn, u, N, K, N, 1.0, 0.0, s);
+        }
+        g.B = t; g.sBk = ldn; g.sBn = 1;
+    } else if (p.b == Kl + Nl) { g.B = B; g.sBk = N; g.sBn = 1; }
     else if (p.b == Nl + Kl && !big) { g.B = B; g.sBk = 1; g.sBn = K; }
     else {
         double* t = ws.take<double>(K * N);

@@ -243,17 +243,24 @@ def test_sigma_stored_ladder_row_tiles(o, v, X, nvec, chunks, monkeypatch):
 
 
 # Contractions of >= 4 GFLOP in the setup run on the ladder tiles: with A k-major (copied into LDS by
-# buffer loads) when the product has >= 512 tiles of 128 x 128, an even column count and fits one chunk
-# (o=10 v=120: the o^2 v^4 coupling terms are 1200 x 14400 x 1200 products), else with A row-major
-# (o=9 v=121: odd column counts).
-@pytest.mark.parametrize("o,v,X", [(10, 120, 150), (9, 121, 140)], ids=lambda c: str(c))
-def test_intermediates_large_contractions(o, v, X):
+# buffer loads) when the product has >= 512 tiles of 128 x 128 (o=10 v=120: the o^2 v^4 coupling terms are
+# 1200 x 14400 x 1200 products; o=9 v=121: odd row and column counts, copied with even strides), else with A
+# row-major (o=5 v=100: 500 x 10000 x 500, 316 tiles).  With the chunk byte limit lowered to 16 MB (test
+# hook) the o=10 v=120 products run as 10 consecutive K ranges, the path large instances take when an
+# operand spans more than 2 GB.
+@pytest.mark.parametrize("o,v,X,limit", [(10, 120, 150, 0), (9, 121, 140, 0), (5, 100, 120, 0),
+                                         (10, 120, 150, 16 << 20)], ids=lambda c: str(c))
+def test_intermediates_large_contractions(o, v, X, limit):
     eo, ev, B = synth.make_instance(o, v, X, 5, scale=0.3)
     P = Problem(eo, ev, B)
-    ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, nroots=0)
-    Uz = host(ctx.intermediate(1)).reshape(v, o, v, v)
-    M11 = host(ctx.intermediate(0)).reshape(v, v)
-    ctx.close()
+    adc.adc3_debug_ladder_offset_limit(limit)
+    try:
+        ctx = adc.Context(dev(eo), dev(ev), dev(B), 3, nroots=0)
+        Uz = host(ctx.intermediate(1)).reshape(v, o, v, v)
+        M11 = host(ctx.intermediate(0)).reshape(v, v)
+        ctx.close()
+    finally:
+        adc.adc3_debug_ladder_offset_limit(0)
     assert relerr(Uz, P.coupling_z(3)) < 1e-11
     assert relerr(M11, P.m11(3)) < 1e-11
 
