@@ -165,6 +165,99 @@ __global__ void splitk_reduce_kernel(const double* part, int nchunk, int M, int 
     }
 }
 
+// Skinny products with both operands contiguous along K and a long K (the 1p <- 2p1h coupling product
+// r2 U_z^T, M = vectors, N = virtuals, K = o v^2; Gram blocks of Davidson vectors):
+//   part[c][m][n] = sum over k in chunk c of A[m][k] B[n][k],   M <= 16, N <= 256.
+// No LDS: each wave loads its fragments straight from HBM.  One 16-k slab feeds four
+// 16x16x4 MFMAs; the K order inside a slab is permuted so that a lane's four k are adjacent
+// (k = k0 + 4q + j for lane group q = lane/16 at MFMA step j), which makes each lane's load
+// one contiguous 32-byte run (two 16-byte loads) when the rows are 16-byte aligned.  The
+// sum over k is the same set of products; only the order of the additions differs.  The four
+// waves of a workgroup share its K chunk and split the N tiles (tile t on wave t % 4), so the
+// U_z stream has no reduction inside the workgroup; the chunk partials are summed by
+// splitk_reduce in chunk order (deterministic).  Rows and ks past the ends read as zero.
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+template <bool VEC>
+__global__ __launch_bounds__(NT) void abt_skinny_kernel(const double* __restrict__ A, long long lda,
+                                                         const double* __restrict__ B, long long ldb, int M, int N,
+                                                         long long K, long long kc, double* __restrict__ part) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const long long klo = (long long)blockIdx.x * kc;
+    const long long khi = klo + kc < K ? klo + kc : K;
+    const int nt = (N + 15) / 16;
+    const bool arow = r < M;
+    const double* Ar = A + (arow ? (long long)r * lda : 0);
+    const double* Br[4];
+    bool brow[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int n = 16 * (wave + 4 * i) + r;
+        brow[i] = n < N;
+        Br[i] = B + (brow[i] ? (long long)n * ldb : 0);
+    }
+    d4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+    long long k0 = klo;
+    if (VEC) {
+        for (; k0 + 16 <= khi; k0 += 16) {
+            const long long ko = k0 + 4 * q;
+            d2 a0 = d2{0.0, 0.0}, a1 = d2{0.0, 0.0};
+            if (arow) {
+                a0 = *(const d2*)(Ar + ko);
+                a1 = *(const d2*)(Ar + ko + 2);
+            }
+            d2 b0[4], b1[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                b0[i] = d2{0.0, 0.0}; b1[i] = d2{0.0, 0.0};
+                if (wave + 4 * i < nt && brow[i]) {
+                    b0[i] = *(const d2*)(Br[i] + ko);
+                    b1[i] = *(const d2*)(Br[i] + ko + 2);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (wave + 4 * i >= nt) continue;  // uniform over the wave
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.x, b0[i].x, acc[i], 0, 0, 0);
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0.y, b0[i].y, acc[i], 0, 0, 0);
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.x, b1[i].x, acc[i], 0, 0, 0);
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1.y, b1[i].y, acc[i], 0, 0, 0);
+            }
+        }
+    }
+    // the rest (all of the chunk on unaligned rows): element loads, k = k0 + 4j + q
+    for (; k0 < khi; k0 += 16) {
+        double a[4], b[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long long k = k0 + 4 * j + q;
+            a[j] = (arow && k < khi) ? Ar[k] : 0.0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) b[i][j] = (wave + 4 * i < nt && brow[i] && k < khi) ? Br[i][k] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (wave + 4 * i >= nt) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[j], b[i][j], acc[i], 0, 0, 0);
+        }
+    }
+    double* P = part + (long long)blockIdx.x * M * N;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int n = 16 * (wave + 4 * i) + r;
+        if (n >= N) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int m = q + 4 * e;
+            if (m < M) P[(long long)m * N + n] = acc[i][e];
+        }
+    }
+}
+
 enum Shape { SH_64x64 = 0, SH_16x256 = 1, SH_128x80 = 2, SH_128x128 = 3, SH_16x64 = 4 };
 inline int tile_m(int sh) { return sh == SH_64x64 ? 64 : (sh == SH_16x256 || sh == SH_16x64) ? 16 : 128; }
 inline int tile_n(int sh) {
@@ -220,6 +313,34 @@ void splitk_reduce(const double* part, int nchunk, int M, int N, double alpha, d
                            sCn);
     }
     LAUNCHCHK();
+}
+
+long long abt_skinny_chunks(int M, int N, long long K, long long partial_elems) {
+    if (M < 1 || M > 16 || N < 1 || N > 256 || K < 256) return 0;
+    // about 1024 workgroups (one round at the kernel's occupancy: 4 per CU, 16 waves), each over a K chunk
+    // of at least 256.  At o=20 v=200 the coupling product takes 257 us (5.0 TB/s over U_z; 295 us on the
+    // LDS-staged split-K GEMM); requesting the next slab before the current slab's MFMAs (3 workgroups per
+    // CU, 768 of them) measured no faster there and slower on the Gram blocks (64 against 52 us).
+    long long nch = std::min<long long>(1024, K / 256);
+    nch = std::min<long long>(nch, partial_elems / ((long long)M * N));
+    return nch >= 2 ? nch : 0;
+}
+
+long long abt_skinny(int M, int N, long long K, const double* A, long long lda, const double* B, long long ldb,
+                     double* part, long long partial_elems, hipStream_t s) {
+    const long long want = abt_skinny_chunks(M, N, K, partial_elems);
+    if (want == 0) return 0;
+    const long long kc = ((K + want - 1) / want + 15) / 16 * 16;
+    const long long nch = (K + kc - 1) / kc;
+    const bool vec = ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && lda % 2 == 0 && ldb % 2 == 0;
+    if (vec)
+        hipLaunchKernelGGL((abt_skinny_kernel<true>), dim3((unsigned)nch), dim3(NT), 0, s, A, lda, B, ldb, M, N, K, kc,
+                           part);
+    else
+        hipLaunchKernelGGL((abt_skinny_kernel<false>), dim3((unsigned)nch), dim3(NT), 0, s, A, lda, B, ldb, M, N, K, kc,
+                           part);
+    LAUNCHCHK();
+    return nch;
 }
 
 thread_local double* g_gemm_scratch = nullptr;
@@ -283,6 +404,14 @@ static void gemm_impl(const Gemm& g, hipStream_t s, int tag, int kmin_split) {
         ladder_supported(g.M, g.N, g.K, g.A, g.sAm, g.B, g.sBk, g.C, g.sCm)) {
         ladder_gemm(g.M, g.N, g.K, g.alpha, g.A, g.sAm, g.B, g.sBk, g.beta, g.C, g.sCm, 1, nullptr, 0, s, 2);
         return;
+    }
+    // skinny products with both operands contiguous along a long K: the fragment-streaming kernel
+    if (nb == 1 && g.sAk == 1 && g.sBk == 1 && g.K >= kmin_split && g_gemm_scratch && g.M <= 16 && g.N <= 256) {
+        const long long nch = abt_skinny(g.M, g.N, g.K, g.A, g.sAm, g.B, g.sBn, g_gemm_scratch, g_gemm_scratch_n, s);
+        if (nch > 0) {
+            splitk_reduce(g_gemm_scratch, (int)nch, g.M, g.N, g.alpha, g.beta, g.C, g.sCm, g.sCn, s);
+            return;
+        }
     }
     const long long tiles = (long long)((g.N + tile_n(sh) - 1) / tile_n(sh)) * ((g.M + tile_m(sh) - 1) / tile_m(sh));
     const long long MN = (long long)g.M * g.N;

@@ -86,6 +86,11 @@ struct GemmLP {
 };
 void splitk_reduce(const double* part, int nchunk, int M, int N, double alpha, double beta, double* C,
                    long long sCm, long long sCn, hipStream_t s);
+// part[c][m][n] = sum over K chunk c of A[m][k] B[n][k] for M <= 16, N <= 256 rows contiguous along K (row
+// strides lda, ldb); returns the chunk count (0: nothing launched, shape or partial buffer unsuitable)
+long long abt_skinny_chunks(int M, int N, long long K, long long partial_elems);
+long long abt_skinny(int M, int N, long long K, const double* A, long long lda, const double* B, long long ldb,
+                     double* part, long long partial_elems, hipStream_t s);
 // sigma ladder (dedicated FP64 kernel): C = alpha Z G + beta C, K split into nchunk chunks
 // whose partial sums go to partial[nchunk][M][N] (nchunk 1: direct)
 bool ladder_supported(int M, int N, int K, const double* Z, long long ldz, const double* G, long long ldg,

@@ -171,6 +171,16 @@ void k_dots(const double* X, long long ldx, int np, const double* Y, long long l
             return;
         }
     }
+    // up to 16 x 256 products: the fragment-streaming skinny kernel (partials [chunk][M][N] as the GEMM's)
+    if (n > 0 && M <= 16 && N <= 256) {
+        const long long nch = abt_skinny(M, N, n, A, lda, B, ldb, partial, (long long)dots_partial_elems(np, nq, n), s);
+        if (nch > 0) {
+            hipLaunchKernelGGL(sum_partials_kernel, dim3((unsigned)MN), dim3(256), 0, s, partial, nch, M, N,
+                               swapped ? 1 : 0, G, ldg);
+            LAUNCHCHK();
+            return;
+        }
+    }
     const long long CH = chunk_of(n);
     long long nchunk = (n + CH - 1) / CH;
     if (nchunk == 0) {
