@@ -1045,6 +1045,10 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
             any_mlp = any_mlp || mlp_on[k];
         }
         if (any_mlp) k_fill((double*)mflag, (nn + 1) / 2, 0.0, s);
+        // the exact 1p-block steps go out together, up to 16 vectors per launch
+        Precond1p p1;
+        p1.R = R; p1.T = Tn; p1.N = N; p1.Q = c->m11_Q; p1.w = c->m11_w; p1.th = th; p1.v = c->v;
+        const bool p1_batch = c->v <= PRECOND_1P_VMAX;
         for (int j = 0; j < nn; ++j) {
             const int k = todo[j];
             if (mlp_on[k]) {
@@ -1053,11 +1057,20 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
                                  c->mlp_wb, Tn + (long long)j * N, mflag + j, s);
             } else if (block1p) {
                 // 1p block exactly: t1 = (M11 - theta)^-1 r1 through M11 = Q diag(w) Q^T; 2p1h diagonal
-                double* y = c->m11_tmp + (long long)c->v * c->v;
                 const int v = c->v;
-                gemm_rm(1, v, v, 1.0, R + (long long)k * N, v, false, c->m11_Q, v, false, 0.0, y, v, s);
-                k_div_shift(y, c->m11_w, th + k, v, s);
-                gemm_rm(1, v, v, 1.0, y, v, false, c->m11_Q, v, true, 0.0, Tn + (long long)j * N, v, s);
+                if (p1_batch) {
+                    p1.kidx[p1.nrow] = k;
+                    p1.tidx[p1.nrow] = j;
+                    if (++p1.nrow == 16) {
+                        k_precond_1p(p1, s);
+                        p1.nrow = 0;
+                    }
+                } else {
+                    double* y = c->m11_tmp + (long long)v * v;
+                    gemm_rm(1, v, v, 1.0, R + (long long)k * N, v, false, c->m11_Q, v, false, 0.0, y, v, s);
+                    k_div_shift(y, c->m11_w, th + k, v, s);
+                    gemm_rm(1, v, v, 1.0, y, v, false, c->m11_Q, v, true, 0.0, Tn + (long long)j * N, v, s);
+                }
                 k_precond(Tn + (long long)j * N + v, R + (long long)k * N + v, c->diag + v, th + k, 1, N - v, s);
             } else {
                 k_precond(Tn + (long long)j * N, R + (long long)k * N, c->diag, th + k, 1, N, s);
@@ -1071,6 +1084,7 @@ static DavResult davidson_impl(Ctx* c, Arena& ws, int nroots, double conv, int m
                 }
             }
         }
+        k_precond_1p(p1, s);
         if (any_mlp) {
             std::vector<unsigned int> hf(nn, 0);
             d2h(hf.data(), mflag, nn * sizeof(unsigned int), s);

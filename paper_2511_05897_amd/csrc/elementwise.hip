@@ -683,6 +683,54 @@ void k_div_shift(double* y, const double* lam, const double* th, int n, hipStrea
     LAUNCHCHK();
 }
 
+// The exact 1p-block step of up to 16 vectors in one launch, one workgroup per vector j:
+//   t1 = Q (diag(w) - theta_k)^-1 Q^T r1,   r1 = R[k][0:v], t1 -> T[tidx[j]][0:v],   k = kidx[j],
+// with M11 = Q diag(w) Q^T (Q[k][n]: component k of eigenvector n), the shift floored as div_shift_kernel
+// floors it.  Both products read Q from global memory (L2-resident, 8 v^2 bytes) with r1 and the scaled
+// coefficients in LDS; sums in a fixed order (deterministic).
+__global__ __launch_bounds__(1024) void precond_1p_kernel(Precond1p a) {
+    extern __shared__ double sh[];
+    const int j = blockIdx.x, k = a.kidx[j], v = a.v, tid = threadIdx.x;
+    const double* r = a.R + (long long)k * a.N;
+    double* t = a.T + (long long)a.tidx[j] * a.N;
+    double* rs = sh;          // r1, then the scaled coefficients
+    double* part = sh + v;    // [4][v] partial sums of Q^T r1 over k quarters
+    for (int i = tid; i < v; i += 1024) rs[i] = r[i];
+    __syncthreads();
+    const int g = tid >> 8, n0 = tid & 255;
+    const int kq = (v + 3) / 4, klo = g * kq, khi = min(v, klo + kq);
+    for (int n = n0; n < v; n += 256) {
+        double acc = 0.0;
+        for (int kk = klo; kk < khi; ++kk) acc += rs[kk] * a.Q[(long long)kk * v + n];
+        part[g * v + n] = acc;
+    }
+    __syncthreads();
+    const double th = a.th[k];
+    for (int n = tid; n < v; n += 1024) {
+        const double y = ((part[n] + part[v + n]) + part[2 * v + n]) + part[3 * v + n];
+        double den = a.w[n] - th;
+        if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+        rs[n] = y / den;
+    }
+    __syncthreads();
+    const int wave = tid >> 6, lane = tid & 63;
+    for (int m = wave; m < v; m += 16) {
+        double acc = 0.0;
+        for (int n = lane; n < v; n += 64) acc += a.Q[(long long)m * v + n] * rs[n];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if (lane == 0) t[m] = acc;
+    }
+}
+
+void k_precond_1p(const Precond1p& a, hipStream_t s) {
+    if (g_dry || a.nrow <= 0 || a.v <= 0) return;
+    if (a.nrow > 16) fail(-1, "precond_1p: more than 16 vectors in one launch");
+    const size_t lds = (size_t)5 * a.v * sizeof(double);
+    if (a.v > PRECOND_1P_VMAX) fail(-1, "precond_1p: nvir too large for the LDS");
+    hipLaunchKernelGGL(precond_1p_kernel, dim3((unsigned)a.nrow), dim3(1024), lds, s, a);
+    LAUNCHCHK();
+}
+
 // T -= (s[0]/s[1]) B  (s[1] == 0: T unchanged)
 __global__ void olsen_kernel(double* T, const double* B, const double* sc, long long n) {
     const double d = sc[1];

@@ -197,6 +197,17 @@ void k_residual(double* R, const double* AX, const double* X, const double* thet
 void k_precond(double* T, const double* R, const double* D, const double* theta, int nk, long long n, hipStream_t s);
 void k_olsen(double* T, const double* B, const double* sc, long long n, hipStream_t s);  // T -= (sc[0]/sc[1]) B
 void k_div_shift(double* y, const double* lam, const double* th, int n, hipStream_t s);  // y /= lam - th[0]
+// exact 1p-block preconditioner step of nrow <= 16 vectors:
+//   T[tidx[j]][0:v] = Q (diag(w) - th[kidx[j]])^-1 Q^T R[kidx[j]][0:v]   (rows of length N)
+// (shift floored at 1e-8 as k_div_shift); 5 v doubles of LDS, v <= PRECOND_1P_VMAX
+struct Precond1p {
+    const double* R = nullptr; double* T = nullptr; long long N = 0;
+    const double* Q = nullptr; const double* w = nullptr; const double* th = nullptr;
+    int v = 0, nrow = 0;
+    int kidx[16] = {}, tidx[16] = {};
+};
+constexpr int PRECOND_1P_VMAX = 1638;
+void k_precond_1p(const Precond1p& a, hipStream_t s);
 void k_scale_vec(double* x, long long n, const double* factor_dev, hipStream_t s);   // x *= factor[0]
 // row j of T[nn][n] *= 1/sqrt(G[j*ldg + j])  (rows with G <= 0 are zeroed)
 void k_rscale_rows(double* T, int nn, long long n, const double* G, int ldg, hipStream_t s);
