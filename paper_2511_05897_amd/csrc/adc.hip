@@ -530,16 +530,26 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
             h.C = ss + v; h.sCm = N; h.sCn = 1;
             gemm_lp(h, 1, s);
         } else {
-            gemm_rm(nv, v, (int)ovv, 1.0, rr + v, N, false, c->Uz, ovv, true, 1.0, ss, N, s);
-            // 2p1h: U_z^T r1, a stream over U_z [a][(i,b,c)]: on the k-major ladder kernel with r1 transposed
-            // ([a][n], a few KB), else as a GEMM
-            const long long ldr = (nv + 1) / 2 * 2;
-            double* r1t = take(ws, (long long)v * ldr);
-            const bool t = ovv <= 0x7fffffffLL && ladder_t_supported(nv, (int)ovv, v, r1t, ldr, c->Uz, ovv) &&
-                           ladder_t_min_chunks(v, ldr, ovv) == 1;
-            if (t) k_transpose(rr, N, nv, v, r1t, ldr, s);
-            if (!(t && ladder_gemm_t(nv, (int)ovv, v, 1.0, r1t, ldr, c->Uz, ovv, 0.0, ss + v, N, 1, nullptr, 0, s, 2)))
-                gemm_rm(nv, (int)ovv, v, 1.0, rr, N, false, c->Uz, ovv, false, 0.0, ss + v, N, s);
+            // both U_z products (1p: U_z z, 2p1h: U_z^T r1) in one stream over U_z when it fits the fused
+            // kernel (v <= 256, aligned rows), else one stream each
+            const long long pe1 = v <= 256 ? 768LL * nv * v : 0;
+            double* part1 = pe1 > 0 ? take(ws, pe1) : nullptr;
+            const long long nch =
+                (g_dry || pe1 == 0) ? 0 : couple_fused(nv, v, ovv, c->Uz, ovv, rr + v, N, rr, N, ss + v, N, part1, pe1, s);
+            if (nch > 0) {
+                splitk_reduce(part1, (int)nch, nv, v, 1.0, 1.0, ss, N, 1, s);
+            } else {
+                gemm_rm(nv, v, (int)ovv, 1.0, rr + v, N, false, c->Uz, ovv, true, 1.0, ss, N, s);
+                // 2p1h: U_z^T r1, a stream over U_z [a][(i,b,c)]: on the k-major ladder kernel with r1
+                // transposed ([a][n], a few KB), else as a GEMM
+                const long long ldr = (nv + 1) / 2 * 2;
+                double* r1t = take(ws, (long long)v * ldr);
+                const bool t = ovv <= 0x7fffffffLL && ladder_t_supported(nv, (int)ovv, v, r1t, ldr, c->Uz, ovv) &&
+                               ladder_t_min_chunks(v, ldr, ovv) == 1;
+                if (t) k_transpose(rr, N, nv, v, r1t, ldr, s);
+                if (!(t && ladder_gemm_t(nv, (int)ovv, v, 1.0, r1t, ldr, c->Uz, ovv, 0.0, ss + v, N, 1, nullptr, 0, s, 2)))
+                    gemm_rm(nv, (int)ovv, v, 1.0, rr, N, false, c->Uz, ovv, false, 0.0, ss + v, N, s);
+            }
         }
         k_k0_add(ss + v, rr + v, c->eo, c->ev, o, v, nv, N, s);
         if (c->level >= 3) {

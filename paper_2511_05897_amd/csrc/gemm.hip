@@ -258,6 +258,124 @@ __global__ __launch_bounds__(NT) void abt_skinny_kernel(const double* __restrict
     }
 }
 
+// Both 1p <-> 2p1h products of a sigma pass in one stream over U_z [a][k] (a < v <= 256 rows, k < K = o v^2):
+//   part1[c][m][a] = sum over k in chunk c of r2[m][k] U[a][k]      (1p side, summed over chunks afterwards)
+//   out2[m][k]     = sum_a r1[m][a] U[a][k]                          (2p1h side, written directly)
+// for m < M <= 16.  A workgroup takes one K chunk; each 16-k slab of U is loaded once, as the MFMA
+// fragments of the 1p product (waves split the 16-row tiles of a, as abt_skinny_kernel does), and
+// parked in LDS; the four waves then read the slab back in the transposed fragment layout (contraction
+// over a, MFMA steps of four a dealt out round-robin to the waves), the four partial 16 x 16 tiles are
+// summed in LDS in wave order and the slab's out2 columns written.  Rows and ks past the ends read as
+// zero.  Requires 16-byte aligned rows (even strides).
+__global__ __launch_bounds__(NT) void couple_fused_kernel(const double* __restrict__ U, long long ldu, int v,
+                                                          long long K, long long kc, const double* __restrict__ r2,
+                                                          long long ld2, const double* __restrict__ r1, long long ld1,
+                                                          int M, double* __restrict__ part1, double* __restrict__ out2,
+                                                          long long ldo) {
+    extern __shared__ double lds[];
+    double* Us = lds;                       // [v][17]: the slab, row a, 16 k (+1 pad)
+    double* Ps = lds + (long long)v * 17;   // [4][256]: the waves' out2 partial tiles [m][k]
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const long long klo = (long long)blockIdx.x * kc;
+    const long long khi = klo + kc < K ? klo + kc : K;
+    const int nt = (v + 15) / 16, nsteps = (v + 3) / 4;
+    const bool arow = r < M;
+    const double* Ar = r2 + (arow ? (long long)r * ld2 : 0);
+    const double* Br[4];
+    bool brow[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int a = 16 * (wave + 4 * i) + r;
+        brow[i] = a < v;
+        Br[i] = U + (brow[i] ? (long long)a * ldu : 0);
+    }
+    // r1 fragments of this wave's contraction steps s = wave + 4 i: lane (m = r, q) holds r1[m][4 s + q]
+    double f1[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int a = 4 * (wave + 4 * i) + q;
+        f1[i] = (arow && a < v) ? r1[(long long)r * ld1 + a] : 0.0;
+    }
+    d4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = d4{0.0, 0.0, 0.0, 0.0};
+    for (long long k0 = klo; k0 < khi; k0 += 16) {
+        const long long ko = k0 + 4 * q;
+        const bool full = k0 + 16 <= khi;
+        double a4[4], b4[4][4];
+        if (full) {
+            d2 x0 = d2{0.0, 0.0}, x1 = d2{0.0, 0.0};
+            if (arow) {
+                x0 = *(const d2*)(Ar + ko);
+                x1 = *(const d2*)(Ar + ko + 2);
+            }
+            a4[0] = x0.x; a4[1] = x0.y; a4[2] = x1.x; a4[3] = x1.y;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                d2 y0 = d2{0.0, 0.0}, y1 = d2{0.0, 0.0};
+                if (wave + 4 * i < nt && brow[i]) {
+                    y0 = *(const d2*)(Br[i] + ko);
+                    y1 = *(const d2*)(Br[i] + ko + 2);
+                }
+                b4[i][0] = y0.x; b4[i][1] = y0.y; b4[i][2] = y1.x; b4[i][3] = y1.y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const long long k = ko + j;
+                a4[j] = (arow && k < khi) ? Ar[k] : 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) b4[i][j] = (wave + 4 * i < nt && brow[i] && k < khi) ? Br[i][k] : 0.0;
+            }
+        }
+        // 1p product (k = ko + j at MFMA step j) and the slab into LDS
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if (wave + 4 * i >= nt) continue;  // uniform over the wave
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a4[j], b4[i][j], acc[i], 0, 0, 0);
+            if (brow[i]) {
+                double* u = Us + (long long)(16 * (wave + 4 * i) + r) * 17 + 4 * q;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) u[j] = b4[i][j];
+            }
+        }
+        __syncthreads();
+        // 2p1h product over a: D[m][k] += r1[m][a] U[a][k], lane (k = r, a = 4 s + q)
+        d4 d = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int st = wave + 4 * i;
+            if (st >= nsteps) break;  // uniform over the wave
+            const int a = 4 * st + q;
+            const double b = a < v ? Us[a * 17 + r] : 0.0;
+            d = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[i], b, d, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Ps[wave * 256 + (q + 4 * e) * 16 + r] = d[e];
+        __syncthreads();
+        {
+            const int m = tid >> 4, kk = tid & 15;
+            const long long k = k0 + kk;
+            if (m < M && k < khi)
+                out2[(long long)m * ldo + k] =
+                    ((Ps[m * 16 + kk] + Ps[256 + m * 16 + kk]) + Ps[512 + m * 16 + kk]) + Ps[768 + m * 16 + kk];
+        }
+    }
+    double* P = part1 + (long long)blockIdx.x * M * v;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int a = 16 * (wave + 4 * i) + r;
+        if (a >= v) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int m = q + 4 * e;
+            if (m < M) P[(long long)m * v + a] = acc[i][e];
+        }
+    }
+}
+
 enum Shape { SH_64x64 = 0, SH_16x256 = 1, SH_128x80 = 2, SH_128x128 = 3, SH_16x64 = 4 };
 inline int tile_m(int sh) { return sh == SH_64x64 ? 64 : (sh == SH_16x256 || sh == SH_16x64) ? 16 : 128; }
 inline int tile_n(int sh) {
@@ -339,6 +457,23 @@ long long abt_skinny(int M, int N, long long K, const double* A, long long lda, 
     else
         hipLaunchKernelGGL((abt_skinny_kernel<false>), dim3((unsigned)nch), dim3(NT), 0, s, A, lda, B, ldb, M, N, K, kc,
                            part);
+    LAUNCHCHK();
+    return nch;
+}
+
+long long couple_fused(int M, int v, long long K, const double* U, long long ldu, const double* r2, long long ld2,
+                       const double* r1, long long ld1, double* out2, long long ldo, double* part1,
+                       long long partial_elems, hipStream_t s) {
+    if (M < 1 || M > 16 || v < 1 || v > 256 || K < 256) return 0;
+    if ((uintptr_t)U % 16 || (uintptr_t)r2 % 16 || ldu % 2 || ld2 % 2) return 0;
+    long long want = std::min<long long>(768, K / 256);
+    want = std::min<long long>(want, partial_elems / ((long long)M * v));
+    if (want < 2) return 0;
+    const long long kc = ((K + want - 1) / want + 15) / 16 * 16;
+    const long long nch = (K + kc - 1) / kc;
+    const size_t lds = ((size_t)v * 17 + 4 * 256) * sizeof(double);
+    hipLaunchKernelGGL(couple_fused_kernel, dim3((unsigned)nch), dim3(NT), lds, s, U, ldu, v, K, kc, r2, ld2, r1, ld1,
+                       M, part1, out2, ldo);
     LAUNCHCHK();
     return nch;
 }

@@ -88,6 +88,12 @@ void splitk_reduce(const double* part, int nchunk, int M, int N, double alpha, d
                    long long sCm, long long sCn, hipStream_t s);
 // part[c][m][n] = sum over K chunk c of A[m][k] B[n][k] for M <= 16, N <= 256 rows contiguous along K (row
 // strides lda, ldb); returns the chunk count (0: nothing launched, shape or partial buffer unsuitable)
+// both U_z products of a sigma pass in one stream over U [v][K] (v <= 256, M <= 16, 16-byte aligned rows):
+// part1[c][m][a] = chunk c's share of sum_k r2[m][k] U[a][k] (sum with splitk_reduce over the returned chunk
+// count), out2[m][k] = sum_a r1[m][a] U[a][k]; returns 0 with nothing launched when the shape does not fit
+long long couple_fused(int M, int v, long long K, const double* U, long long ldu, const double* r2, long long ld2,
+                       const double* r1, long long ld1, double* out2, long long ldo, double* part1,
+                       long long partial_elems, hipStream_t s);
 long long abt_skinny_chunks(int M, int N, long long K, long long partial_elems);
 long long abt_skinny(int M, int N, long long K, const double* A, long long lda, const double* B, long long ldb,
                      double* part, long long partial_elems, hipStream_t s);

@@ -242,6 +242,25 @@ def test_sigma_stored_ladder_row_tiles(o, v, X, nvec, chunks, monkeypatch):
     assert relerr(s_gpu, P.sigma(r, 3)) < 1e-11
 
 
+# The 1p <-> 2p1h coupling products U_z z and U_z^T r1 of a sigma pass share one stream over U_z when the
+# virtual count is at most 256 and the rows of U_z and z are 16-byte aligned: o=5 v=42 has o v^2 = 8820,
+# not a multiple of 16, so the last K chunk ends in a partial slab; o=3 v=64 with 16 vectors fills every
+# fragment row; o=4 v=30 is one vector over 14 chunks; o=5 v=41 (odd o v^2, z rows not 16-byte aligned)
+# takes the two separate streams.
+@pytest.mark.parametrize("o,v,X,nvec", [(5, 42, 60, 7), (3, 64, 90, 16), (4, 30, 50, 1), (5, 41, 60, 5)],
+                         ids=lambda c: str(c))
+@pytest.mark.parametrize("level", [2, 3])
+def test_sigma_coupling_products(o, v, X, nvec, level):
+    eo, ev, B = synth.make_instance(o, v, X, 11, scale=0.3)
+    P = Problem(eo, ev, B)
+    ctx = adc.Context(dev(eo), dev(ev), dev(B), level, nroots=0)
+    r = np.random.default_rng(5).standard_normal((nvec, P.dim()))
+    print("coupling products o=%d v=%d nvec=%d level %d" % (o, v, nvec, level), flush=True)
+    s_gpu = host(ctx.sigma(dev(r)))
+    ctx.close()
+    assert relerr(s_gpu, P.sigma(r, level)) < 1e-11
+
+
 # Contractions of >= 4 GFLOP in the setup run on the ladder tiles: with A k-major (copied into LDS by
 # buffer loads) when the product has >= 512 tiles of 128 x 128 (o=10 v=120: the o^2 v^4 coupling terms are
 # 1200 x 14400 x 1200 products; o=9 v=121: odd row and column counts, copied with even strides), else with A
