@@ -267,7 +267,7 @@ __global__ __launch_bounds__(NT) void abt_skinny_kernel(const double* __restrict
 // over a, MFMA steps of four a dealt out round-robin to the waves), the four partial 16 x 16 tiles are
 // summed in LDS in wave order and the slab's out2 columns written.  Rows and ks past the ends read as
 // zero.  Requires 16-byte aligned rows (even strides).
-__global__ __launch_bounds__(NT) void couple_fused_kernel(const double* __restrict__ U, long long ldu, int v,
+__global__ __launch_bounds__(NT, 3) void couple_fused_kernel(const double* __restrict__ U, long long ldu, int v,
                                                           long long K, long long kc, const double* __restrict__ r2,
                                                           long long ld2, const double* __restrict__ r1, long long ld1,
                                                           int M, double* __restrict__ part1, double* __restrict__ out2,
@@ -342,18 +342,27 @@ __global__ __launch_bounds__(NT) void couple_fused_kernel(const double* __restri
             }
         }
         __syncthreads();
-        // 2p1h product over a: D[m][k] += r1[m][a] U[a][k], lane (k = r, a = 4 s + q)
-        d4 d = d4{0.0, 0.0, 0.0, 0.0};
+        // 2p1h product over a: D[m][k] += r1[m][a] U[a][k], lane (k = r, a = 4 s + q); the slab's fragments
+        // read eight steps at a time, two accumulators (even and odd steps) summed at the end
+        d4 d0 = d4{0.0, 0.0, 0.0, 0.0}, d1 = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int st = wave + 4 * i;
-            if (st >= nsteps) break;  // uniform over the wave
-            const int a = 4 * st + q;
-            const double b = a < v ? Us[a * 17 + r] : 0.0;
-            d = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[i], b, d, 0, 0, 0);
+        for (int h = 0; h < 16; h += 8) {
+            if (wave + 4 * h >= nsteps) break;  // uniform over the wave
+            double bb[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int st = wave + 4 * (h + i), a = 4 * st + q;
+                bb[i] = (st < nsteps && a < v) ? Us[a * 17 + r] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) {
+                if (wave + 4 * (h + i) < nsteps) d0 = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[h + i], bb[i], d0, 0, 0, 0);
+                if (wave + 4 * (h + i + 1) < nsteps)
+                    d1 = __builtin_amdgcn_mfma_f64_16x16x4f64(f1[h + i + 1], bb[i + 1], d1, 0, 0, 0);
+            }
         }
 #pragma unroll
-        for (int e = 0; e < 4; ++e) Ps[wave * 256 + (q + 4 * e) * 16 + r] = d[e];
+        for (int e = 0; e < 4; ++e) Ps[wave * 256 + (q + 4 * e) * 16 + r] = d0[e] + d1[e];
         __syncthreads();
         {
             const int m = tid >> 4, kk = tid & 15;
