@@ -2022,14 +2022,29 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         naf_cache.N = take(ws, (long long)X * X);
         naf_cache.w = take(ws, X);
     }
-    // the truncated ADC(2) solves precondition with the exact 1p block: the eigendecompositions of the
-    // bases' M11 solved as batches (bases with equal kept counts together) before the per-basis solves,
-    // where that pays and costs no second NAF eigensolver: kept count above the one-workgroup solver's
-    // size and the NAF result shared (nothing truncated) or not asked for
+    // step 4 for all bases: one after the other (engine 0); or each basis's steps on a host thread and
+    // stream of its own (engine 2: opts.lockstep 2, and the default -1 whenever there are two bases or more
+    // and their stored ladders, at the untruncated size, take at most the stored ladder's budget of 96 GB
+    // together); or all bases' truncated ADC(2) solves in one lockstep block Davidson, then all their ADC(3)
+    // solves in another (engine 1: opts.lockstep 1; not with the learned and Olsen steps).  Planning and the
+    // solve take the same decision.
+    const bool df_all = op.ladder == 2 || (op.ladder == 0 && ladder_df_auto(v));
+    const double lock_ladder_bytes = (double)nb * 4.0 * (double)v * v * v * v;
+    const bool together_auto = nb >= 2 && !df_all && lock_ladder_bytes <= 96e9;
+    const int engine = (op.lockstep == 1 && op.precond != 1 && op.precond != 2) ? 1
+                       : (op.lockstep == 2 || (op.lockstep < 0 && together_auto)) ? 2
+                                                                                   : 0;
+    // the truncated ADC(2) solves precondition with the exact 1p block: with the bases one after another,
+    // the eigendecompositions of the bases' M11 solved as batches (bases with equal kept counts together)
+    // before the per-basis solves, where that pays and costs no second NAF eigensolver: kept count above the
+    // one-workgroup solver's size and the NAF result shared (nothing truncated) or not asked for.  With each
+    // basis on a thread of its own (engine 2), each context solves its own M11 on its stream, beside the
+    // other bases' work, instead of in a batch (and a second pass over the blocks) before the threads start.
     double* m11Q = nullptr;
     double* m11w = nullptr;
     std::vector<char> m11_pre(nb, 0);
-    for (int b = 0; b < nb; ++b) m11_pre[b] = pm2 == 3 && vks[b] > 96 && (!(naf > 0) || vks[b] == v);
+    for (int b = 0; b < nb; ++b)
+        m11_pre[b] = engine != 2 && pm2 == 3 && vks[b] > 96 && (!(naf > 0) || vks[b] == v);
     if (std::count(m11_pre.begin(), m11_pre.end(), 1) >= 2) {
         m11Q = take(ws, (long long)nb * vv0);
         m11w = take(ws, (long long)nb * v);
@@ -2064,18 +2079,6 @@ static SolveOut solve_impl(Arena& ws, const double* eo, const double* ev, const 
         }
         ws.release(mm);
     }
-    // step 4 for all bases: one after the other (engine 0); or each basis's steps on a host thread and
-    // stream of its own (engine 2: opts.lockstep 2, and the default -1 whenever there are two bases or more
-    // and their stored ladders, at the untruncated size, take at most the stored ladder's budget of 96 GB
-    // together); or all bases' truncated ADC(2) solves in one lockstep block Davidson, then all their ADC(3)
-    // solves in another (engine 1: opts.lockstep 1; not with the learned and Olsen steps).  Planning and the
-    // solve take the same decision.
-    const bool df_all = op.ladder == 2 || (op.ladder == 0 && ladder_df_auto(v));
-    const double lock_ladder_bytes = (double)nb * 4.0 * (double)v * v * v * v;
-    const bool together_auto = nb >= 2 && !df_all && lock_ladder_bytes <= 96e9;
-    const int engine = (op.lockstep == 1 && op.precond != 1 && op.precond != 2) ? 1
-                       : (op.lockstep == 2 || (op.lockstep < 0 && together_auto)) ? 2
-                                                                                   : 0;
     auto run_jobs = [&](std::vector<LockJob*>& jp) {
         const size_t mj = ws.mark();
         lockstep_run(jp, s, lockstep_chunk());
