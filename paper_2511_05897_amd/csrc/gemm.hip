@@ -444,7 +444,7 @@ void splitk_reduce(const double* part, int nchunk, int M, int N, double alpha, d
 
 long long abt_skinny_chunks(int M, int N, long long K, long long partial_elems) {
     if (M < 1 || M > 16 || N < 1 || N > 256 || K < 256) return 0;
-    // about 1024 workgroups (one round at the kernel's occupancy: 4 per CU, 16 waves), each over a K chunk
+    // about 1024 workgroups (all resident at once at the kernel's occupancy: 4 per CU, 16 waves), each over a K chunk
     // of at least 256.  At o=20 v=200 the coupling product takes 257 us (5.0 TB/s over U_z; 295 us on the
     // LDS-staged split-K GEMM); requesting the next slab before the current slab's MFMAs (3 workgroups per
     // CU, 768 of them) measured no faster there and slower on the Gram blocks (64 against 52 us).
