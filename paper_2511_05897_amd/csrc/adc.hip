@@ -517,18 +517,29 @@ static void sigma_pass(Ctx* c, Arena& ws, const double* rr, double* ss, int nv, 
         // 1p: M11 r1 + U_z z
         gemm_rm(nv, v, v, 1.0, rr, N, false, c->M11, v, true, 0.0, ss, N, s);
         if (prec > 0) {
-            GemmLP g;
-            g.M = nv; g.N = v; g.K = (int)ovv;
-            g.A = rr + v; g.sAm = N; g.sAk = 1;
-            g.B = c->Uz32; g.sBk = 1; g.sBn = ovv;
-            g.C = ss; g.sCm = N; g.sCn = 1; g.beta = 1.0;
-            gemm_lp(g, 1, s);
-            GemmLP h;
-            h.M = nv; h.N = (int)ovv; h.K = v;
-            h.A = rr; h.sAm = N; h.sAk = 1;
-            h.B = c->Uz32; h.sBk = ovv; h.sBn = 1;
-            h.C = ss + v; h.sCm = N; h.sCn = 1;
-            gemm_lp(h, 1, s);
+            // the FP32 copy of U_z: both products in one stream over it when it fits the fused kernel (sums in
+            // FP64), else the two reduced-precision GEMMs (FP32 sums)
+            const long long pe1 = v <= 256 ? 768LL * nv * v : 0;
+            double* part1 = pe1 > 0 ? take(ws, pe1) : nullptr;
+            const long long nch = (g_dry || pe1 == 0)
+                                      ? 0
+                                      : couple_fused32(nv, v, ovv, c->Uz32, ovv, rr + v, N, rr, N, ss + v, N, part1, pe1, s);
+            if (nch > 0) {
+                splitk_reduce(part1, (int)nch, nv, v, 1.0, 1.0, ss, N, 1, s);
+            } else {
+                GemmLP g;
+                g.M = nv; g.N = v; g.K = (int)ovv;
+                g.A = rr + v; g.sAm = N; g.sAk = 1;
+                g.B = c->Uz32; g.sBk = 1; g.sBn = ovv;
+                g.C = ss; g.sCm = N; g.sCn = 1; g.beta = 1.0;
+                gemm_lp(g, 1, s);
+                GemmLP h;
+                h.M = nv; h.N = (int)ovv; h.K = v;
+                h.A = rr; h.sAm = N; h.sAk = 1;
+                h.B = c->Uz32; h.sBk = ovv; h.sBn = 1;
+                h.C = ss + v; h.sCm = N; h.sCn = 1;
+                gemm_lp(h, 1, s);
+            }
         } else {
             // both U_z products (1p: U_z z, 2p1h: U_z^T r1) in one stream over U_z when it fits the fused
             // kernel (v <= 256, aligned rows), else one stream each

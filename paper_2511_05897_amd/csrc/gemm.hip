@@ -20,6 +20,7 @@
 //   D     : D[row = l/16 + 4*r][col = l%16] in accumulator element r = 0..3
 #include "internal.h"
 #include <algorithm>
+#include <type_traits>
 
 namespace adc3 {
 
@@ -266,8 +267,10 @@ __global__ __launch_bounds__(NT) void abt_skinny_kernel(const double* __restrict
 // parked in LDS; the four waves then read the slab back in the transposed fragment layout (contraction
 // over a, MFMA steps of four a dealt out round-robin to the waves), the four partial 16 x 16 tiles are
 // summed in LDS in wave order and the slab's out2 columns written.  Rows and ks past the ends read as
-// zero.  Requires 16-byte aligned rows (even strides).
-__global__ __launch_bounds__(NT, 3) void couple_fused_kernel(const double* __restrict__ U, long long ldu, int v,
+// zero.  Requires 16-byte aligned rows (even strides).  U_z in FP32 (the reduced-precision sigma passes) is
+// widened to FP64 on load: the same fragments, and sums in FP64.
+template <typename TU>
+__global__ __launch_bounds__(NT, 3) void couple_fused_kernel(const TU* __restrict__ U, long long ldu, int v,
                                                           long long K, long long kc, const double* __restrict__ r2,
                                                           long long ld2, const double* __restrict__ r1, long long ld1,
                                                           int M, double* __restrict__ part1, double* __restrict__ out2,
@@ -282,7 +285,7 @@ __global__ __launch_bounds__(NT, 3) void couple_fused_kernel(const double* __res
     const int nt = (v + 15) / 16, nsteps = (v + 3) / 4;
     const bool arow = r < M;
     const double* Ar = r2 + (arow ? (long long)r * ld2 : 0);
-    const double* Br[4];
+    const TU* Br[4];
     bool brow[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -313,12 +316,19 @@ __global__ __launch_bounds__(NT, 3) void couple_fused_kernel(const double* __res
             a4[0] = x0.x; a4[1] = x0.y; a4[2] = x1.x; a4[3] = x1.y;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                d2 y0 = d2{0.0, 0.0}, y1 = d2{0.0, 0.0};
-                if (wave + 4 * i < nt && brow[i]) {
-                    y0 = *(const d2*)(Br[i] + ko);
-                    y1 = *(const d2*)(Br[i] + ko + 2);
+                if constexpr (std::is_same<TU, float>::value) {
+                    // FP32 U_z: one 16-byte load of four k, widened to FP64
+                    float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
+                    if (wave + 4 * i < nt && brow[i]) y = *(const float4*)(Br[i] + ko);
+                    b4[i][0] = y.x; b4[i][1] = y.y; b4[i][2] = y.z; b4[i][3] = y.w;
+                } else {
+                    d2 y0 = d2{0.0, 0.0}, y1 = d2{0.0, 0.0};
+                    if (wave + 4 * i < nt && brow[i]) {
+                        y0 = *(const d2*)(Br[i] + ko);
+                        y1 = *(const d2*)(Br[i] + ko + 2);
+                    }
+                    b4[i][0] = y0.x; b4[i][1] = y0.y; b4[i][2] = y1.x; b4[i][3] = y1.y;
                 }
-                b4[i][0] = y0.x; b4[i][1] = y0.y; b4[i][2] = y1.x; b4[i][3] = y1.y;
             }
         } else {
 #pragma unroll
@@ -470,21 +480,34 @@ long long abt_skinny(int M, int N, long long K, const double* A, long long lda, 
     return nch;
 }
 
-long long couple_fused(int M, int v, long long K, const double* U, long long ldu, const double* r2, long long ld2,
-                       const double* r1, long long ld1, double* out2, long long ldo, double* part1,
-                       long long partial_elems, hipStream_t s) {
+template <typename TU>
+static long long couple_fused_t(int M, int v, long long K, const TU* U, long long ldu, const double* r2, long long ld2,
+                                const double* r1, long long ld1, double* out2, long long ldo, double* part1,
+                                long long partial_elems, hipStream_t s) {
     if (M < 1 || M > 16 || v < 1 || v > 256 || K < 256) return 0;
-    if ((uintptr_t)U % 16 || (uintptr_t)r2 % 16 || ldu % 2 || ld2 % 2) return 0;
+    if ((uintptr_t)U % 16 || (uintptr_t)r2 % 16 || ldu % (16 / (long long)sizeof(TU)) || ld2 % 2) return 0;
     long long want = std::min<long long>(768, K / 256);
     want = std::min<long long>(want, partial_elems / ((long long)M * v));
     if (want < 2) return 0;
     const long long kc = ((K + want - 1) / want + 15) / 16 * 16;
     const long long nch = (K + kc - 1) / kc;
     const size_t lds = ((size_t)v * 17 + 4 * 256) * sizeof(double);
-    hipLaunchKernelGGL(couple_fused_kernel, dim3((unsigned)nch), dim3(NT), lds, s, U, ldu, v, K, kc, r2, ld2, r1, ld1,
-                       M, part1, out2, ldo);
+    hipLaunchKernelGGL(couple_fused_kernel<TU>, dim3((unsigned)nch), dim3(NT), lds, s, U, ldu, v, K, kc, r2, ld2, r1,
+                       ld1, M, part1, out2, ldo);
     LAUNCHCHK();
     return nch;
+}
+
+long long couple_fused(int M, int v, long long K, const double* U, long long ldu, const double* r2, long long ld2,
+                       const double* r1, long long ld1, double* out2, long long ldo, double* part1,
+                       long long partial_elems, hipStream_t s) {
+    return couple_fused_t(M, v, K, U, ldu, r2, ld2, r1, ld1, out2, ldo, part1, partial_elems, s);
+}
+
+long long couple_fused32(int M, int v, long long K, const float* U, long long ldu, const double* r2, long long ld2,
+                         const double* r1, long long ld1, double* out2, long long ldo, double* part1,
+                         long long partial_elems, hipStream_t s) {
+    return couple_fused_t(M, v, K, U, ldu, r2, ld2, r1, ld1, out2, ldo, part1, partial_elems, s);
 }
 
 thread_local double* g_gemm_scratch = nullptr;

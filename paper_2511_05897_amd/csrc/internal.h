@@ -94,6 +94,10 @@ void splitk_reduce(const double* part, int nchunk, int M, int N, double alpha, d
 long long couple_fused(int M, int v, long long K, const double* U, long long ldu, const double* r2, long long ld2,
                        const double* r1, long long ld1, double* out2, long long ldo, double* part1,
                        long long partial_elems, hipStream_t s);
+// the same with U_z in FP32 (widened to FP64 on load; ldu a multiple of 4)
+long long couple_fused32(int M, int v, long long K, const float* U, long long ldu, const double* r2, long long ld2,
+                         const double* r1, long long ld1, double* out2, long long ldo, double* part1,
+                         long long partial_elems, hipStream_t s);
 long long abt_skinny_chunks(int M, int N, long long K, long long partial_elems);
 long long abt_skinny(int M, int N, long long K, const double* A, long long lda, const double* B, long long ldb,
                      double* part, long long partial_elems, hipStream_t s);
